@@ -1,0 +1,260 @@
+"""FP64 oracle of the image prior phi(theta | Z): forward and exact backward.
+
+TEST INFRASTRUCTURE ONLY.  Plain, slow, obviously-correct NumPy; it shares no
+code with the GPU library and is imported only by the tests, the smoke check
+and the CPU baseline leg of the benchmark.
+
+The network is the paper's DIP image prior (Eq. (3); 3D convolutions,
+residual connections and LayerNorm, Sec. III-D) in the plain residual U-Net
+reading used throughout this project:
+
+  stem   : a = relu(LN(conv3(Z)))
+  enc_0  : ResBlock(C -> C) on a
+  enc_l  : ResBlock(c_{l-1} -> c_l) on avgpool2(enc_{l-1}),  l = 1 .. L-1
+  dec_l  : ResBlock(3 c_l -> c_l) on concat[up2(dec_{l+1}), enc_l],
+           l = L-2 .. 0, with dec_{L-1} = enc_{L-1}
+  tail   : y = conv1(dec_0) (C -> 1); the image is mask * y
+
+  ResBlock(x): h1 = conv3(x); a1 = relu(LN1(h1)); h2 = conv3(a1);
+               out = relu(LN2(h2) + skip(x)), skip = 1x1x1 conv if the channel
+               count changes, identity otherwise.
+
+Conventions: arrays are channel-first [C, n, n, n] in (z, y, x) order; conv3
+is a 3x3x3 cross-correlation with zero padding 1; LN normalises over all of
+(C, z, y, x) with the biased variance, eps = 1e-5 inside the square root, and
+a per-channel affine (gamma, beta); avgpool2 averages 2x2x2 blocks; up2
+repeats every voxel into a 2x2x2 block (nearest neighbour); relu'(0) = 0.
+"""
+import numpy as np
+
+LN_EPS = 1e-5
+
+
+# ----------------------------------------------------------------------------
+# parameter unpacking (own copy of the flat layout: modules stem, enc_0..,
+# dec_{L-2}..dec_0, tail; per conv W[Cout][Cin][k][k][k] then b; per norm
+# gamma then beta; ResBlock order conv1, norm1, conv2, norm2, proj)
+# ----------------------------------------------------------------------------
+
+def _block_shapes(cin, cout):
+    shapes = [("conv1.w", (cout, cin, 3, 3, 3)), ("conv1.b", (cout,)),
+              ("norm1.g", (cout,)), ("norm1.beta", (cout,)),
+              ("conv2.w", (cout, cout, 3, 3, 3)), ("conv2.b", (cout,)),
+              ("norm2.g", (cout,)), ("norm2.beta", (cout,))]
+    if cin != cout:
+        shapes += [("proj.w", (cout, cin, 1, 1, 1)), ("proj.b", (cout,))]
+    return shapes
+
+
+def module_list(levels, base_ch):
+    """[(module name, [(param name, shape)])] in flat order."""
+    ch = [base_ch * 2 ** l for l in range(levels)]
+    mods = [("stem", [("conv.w", (base_ch, 1, 3, 3, 3)), ("conv.b", (base_ch,)),
+                      ("norm.g", (base_ch,)), ("norm.beta", (base_ch,))])]
+    mods.append(("enc0", _block_shapes(ch[0], ch[0])))
+    for l in range(1, levels):
+        mods.append(("enc%d" % l, _block_shapes(ch[l - 1], ch[l])))
+    for l in range(levels - 2, -1, -1):
+        mods.append(("dec%d" % l, _block_shapes(ch[l + 1] + ch[l], ch[l])))
+    mods.append(("tail", [("w", (1, base_ch, 1, 1, 1)), ("b", (1,))]))
+    return mods
+
+
+def n_params(levels, base_ch):
+    return sum(int(np.prod(s)) for _, ps in module_list(levels, base_ch) for _, s in ps)
+
+
+def unpack(theta, levels, base_ch):
+    """Flat theta -> {module: {param: view}} (views into theta)."""
+    out, off = {}, 0
+    for mod, ps in module_list(levels, base_ch):
+        d = {}
+        for name, shape in ps:
+            k = int(np.prod(shape))
+            d[name] = theta[off:off + k].reshape(shape)
+            off += k
+        out[mod] = d
+    assert off == theta.size, (off, theta.size)
+    return out
+
+
+# ----------------------------------------------------------------------------
+# layers (forward and backward)
+# ----------------------------------------------------------------------------
+
+def conv3d(x, w, b):
+    """out[co] = b[co] + sum_{ci, dz, dy, dx} w[co, ci, dz, dy, dx] *
+    x[ci, z+dz-1, y+dy-1, x+dx-1] (zeros outside); w is k x k x k, k in {1, 3}."""
+    cin, n = x.shape[0], x.shape[1]
+    k = w.shape[2]
+    p = k // 2
+    xp = np.pad(x, ((0, 0), (p, p), (p, p), (p, p)))
+    out = np.zeros((w.shape[0], n ** 3))
+    for dz in range(k):
+        for dy in range(k):
+            for dx in range(k):
+                win = xp[:, dz:dz + n, dy:dy + n, dx:dx + n].reshape(cin, -1)
+                out += w[:, :, dz, dy, dx] @ win
+    out += b[:, None]
+    return out.reshape(w.shape[0], n, n, n)
+
+
+def conv3d_backward(x, w, gout, need_gx=True):
+    """Gradients of conv3d w.r.t. x, w and b given gout = dL/dout."""
+    cin, n = x.shape[0], x.shape[1]
+    cout, k = w.shape[0], w.shape[2]
+    p = k // 2
+    xp = np.pad(x, ((0, 0), (p, p), (p, p), (p, p)))
+    g2 = gout.reshape(cout, -1)
+    gw = np.zeros_like(w)
+    gxp = np.zeros_like(xp) if need_gx else None
+    for dz in range(k):
+        for dy in range(k):
+            for dx in range(k):
+                win = xp[:, dz:dz + n, dy:dy + n, dx:dx + n].reshape(cin, -1)
+                gw[:, :, dz, dy, dx] = g2 @ win.T
+                if need_gx:
+                    gxp[:, dz:dz + n, dy:dy + n, dx:dx + n] += \
+                        (w[:, :, dz, dy, dx].T @ g2).reshape(cin, n, n, n)
+    gb = g2.sum(axis=1)
+    gx = gxp[:, p:p + n, p:p + n, p:p + n] if need_gx else None
+    return gx, gw, gb
+
+
+def layer_norm(h, g, beta, eps=LN_EPS):
+    mu = h.mean()
+    var = ((h - mu) ** 2).mean()
+    rstd = 1.0 / np.sqrt(var + eps)
+    xhat = (h - mu) * rstd
+    return g[:, None, None, None] * xhat + beta[:, None, None, None], (xhat, rstd)
+
+
+def layer_norm_backward(gout, g, cache):
+    xhat, rstd = cache
+    gg = (gout * xhat).sum(axis=(1, 2, 3))
+    gbeta = gout.sum(axis=(1, 2, 3))
+    gxhat = gout * g[:, None, None, None]
+    gh = rstd * (gxhat - gxhat.mean() - xhat * (gxhat * xhat).mean())
+    return gh, gg, gbeta
+
+
+def relu(x):
+    return np.maximum(x, 0.0)
+
+
+def relu_backward(gout, y):
+    return gout * (y > 0.0)
+
+
+def avgpool2(x):
+    c, n = x.shape[0], x.shape[1]
+    m = n // 2
+    return x.reshape(c, m, 2, m, 2, m, 2).mean(axis=(2, 4, 6))
+
+
+def avgpool2_backward(gout):
+    return np.repeat(np.repeat(np.repeat(gout, 2, 1), 2, 2), 2, 3) / 8.0
+
+
+def up2(x):
+    return np.repeat(np.repeat(np.repeat(x, 2, 1), 2, 2), 2, 3)
+
+
+def up2_backward(gout):
+    c, n = gout.shape[0], gout.shape[1]
+    m = n // 2
+    return gout.reshape(c, m, 2, m, 2, m, 2).sum(axis=(2, 4, 6))
+
+
+# ----------------------------------------------------------------------------
+# blocks and the whole network
+# ----------------------------------------------------------------------------
+
+def resblock_forward(x, P):
+    h1 = conv3d(x, P["conv1.w"], P["conv1.b"])
+    n1, c1 = layer_norm(h1, P["norm1.g"], P["norm1.beta"])
+    a1 = relu(n1)
+    h2 = conv3d(a1, P["conv2.w"], P["conv2.b"])
+    n2, c2 = layer_norm(h2, P["norm2.g"], P["norm2.beta"])
+    s = conv3d(x, P["proj.w"], P["proj.b"]) if "proj.w" in P else x
+    y = relu(n2 + s)
+    return y, dict(x=x, a1=a1, c1=c1, c2=c2, y=y)
+
+
+def resblock_backward(gy, P, cache):
+    G = {}
+    gz = relu_backward(gy, cache["y"])
+    gh2, G["norm2.g"], G["norm2.beta"] = layer_norm_backward(gz, P["norm2.g"], cache["c2"])
+    ga1, G["conv2.w"], G["conv2.b"] = conv3d_backward(cache["a1"], P["conv2.w"], gh2)
+    gn1 = relu_backward(ga1, cache["a1"])
+    gh1, G["norm1.g"], G["norm1.beta"] = layer_norm_backward(gn1, P["norm1.g"], cache["c1"])
+    gx, G["conv1.w"], G["conv1.b"] = conv3d_backward(cache["x"], P["conv1.w"], gh1)
+    if "proj.w" in P:
+        gxs, G["proj.w"], G["proj.b"] = conv3d_backward(cache["x"], P["proj.w"], gz)
+        gx = gx + gxs
+    else:
+        gx = gx + gz
+    return gx, G
+
+
+def forward(theta, Z, n, levels, base_ch):
+    """phi(theta | Z) before masking, as an (n, n, n) array, plus the cache."""
+    P = unpack(theta, levels, base_ch)
+    z = Z.reshape(1, n, n, n)
+    hs = conv3d(z, P["stem"]["conv.w"], P["stem"]["conv.b"])
+    ns, cs = layer_norm(hs, P["stem"]["norm.g"], P["stem"]["norm.beta"])
+    a = relu(ns)
+    cache = dict(z=z, stem=(a, cs))
+    enc = []
+    x = a
+    for l in range(levels):
+        if l > 0:
+            x = avgpool2(enc[-1])
+        y, cache["enc%d" % l] = resblock_forward(x, P["enc%d" % l])
+        enc.append(y)
+    d = enc[-1]
+    for l in range(levels - 2, -1, -1):
+        x = np.concatenate([up2(d), enc[l]], axis=0)
+        d, cache["dec%d" % l] = resblock_forward(x, P["dec%d" % l])
+    out = conv3d(d, P["tail"]["w"], P["tail"]["b"])
+    cache["d0"] = d
+    return out[0], cache
+
+
+def backward(gout, theta, cache, n, levels, base_ch):
+    """d(loss)/d(theta) as a flat array, given gout = d(loss)/d(phi) (n, n, n)."""
+    P = unpack(theta, levels, base_ch)
+    grad = np.zeros(theta.size, dtype=np.float64)
+    Gv = unpack(grad, levels, base_ch)
+    go = gout.reshape(1, n, n, n)
+    gd, gtw, gtb = conv3d_backward(cache["d0"], P["tail"]["w"], go)
+    Gv["tail"]["w"][...] = gtw
+    Gv["tail"]["b"][...] = gtb
+    # decoder, from dec_0 up to dec_{L-2}; gd is d(loss)/d(dec_l output)
+    genc = [np.zeros(1)] * levels
+    for l in range(0, levels - 1):
+        gx, G = resblock_backward(gd, P["dec%d" % l], cache["dec%d" % l])
+        for k, v in G.items():
+            Gv["dec%d" % l][k][...] = v
+        c_up = base_ch * 2 ** (l + 1)
+        gd = up2_backward(gx[:c_up])          # to dec_{l+1} (or enc_{L-1})
+        genc[l] = gx[c_up:]                    # skip contribution to enc_l
+    # encoder, from the bottleneck down; gd is d(loss)/d(enc_{L-1} output)
+    genc[levels - 1] = gd
+    gy = genc[levels - 1]
+    for l in range(levels - 1, -1, -1):
+        gx, G = resblock_backward(gy, P["enc%d" % l], cache["enc%d" % l])
+        for k, v in G.items():
+            Gv["enc%d" % l][k][...] = v
+        if l > 0:
+            gy = genc[l - 1] + avgpool2_backward(gx)
+        else:
+            ga = gx
+    a, cs = cache["stem"]
+    gn = relu_backward(ga, a)
+    gh, Gv["stem"]["norm.g"][...], Gv["stem"]["norm.beta"][...] = \
+        layer_norm_backward(gn, P["stem"]["norm.g"], cs)
+    _, gw, gb = conv3d_backward(cache["z"], P["stem"]["conv.w"], gh, need_gx=False)
+    Gv["stem"]["conv.w"][...] = gw
+    Gv["stem"]["conv.b"][...] = gb
+    return grad
