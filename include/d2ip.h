@@ -1,0 +1,165 @@
+/*
+ * d2ip.h - C-ABI of the MI355X (gfx950) library for the per-frame fitting
+ * iteration of D2IP, "Deep Dynamic Image Prior for 3D Time-sequence
+ * Pulmonary Impedance Imaging" (arXiv 2507.14046).
+ *
+ * The library fits the parameters theta of a 3D residual U-Net image prior
+ * phi(theta | Z) to one frame of boundary-voltage differences:
+ *
+ *   image        d_sigma = mask * phi(theta | Z)                Eq. (3)
+ *   prediction   p = J d_sigma                                  Eq. (1)
+ *   data loss    L = (1/M) sum_m (p_m - dv_m)^2                 Eq. (4), l2 data term
+ *   update       Adam on theta                                  Sec. III-A
+ *
+ * and carries theta from frame to frame (Temporal Parameter Propagation,
+ * Eq. (9)): d2ip_set_frame replaces dv and leaves theta untouched.  The image
+ * of a frame is read after its last update (Eq. (5)).
+ *
+ * Network (plain residual U-Net reading of Sec. III-D), with L levels and C
+ * base channels, level l having C*2^l channels on an (n/2^l)^3 grid:
+ *   stem conv3(1->C)+LN+ReLU; encoder ResBlocks at every level joined by 2x2x2
+ *   average pooling; decoder ResBlocks(3c_l -> c_l) on [nearest-up x2, skip];
+ *   tail conv1(C->1); ResBlock(a->b) = conv3, LN, ReLU, conv3, LN, + skip
+ *   (1x1x1 conv if a != b), ReLU.  LN normalises each instance over all
+ *   channels and voxels (eps 1e-5, biased variance) with a per-channel affine.
+ *
+ * Conventions for every entry point
+ *  - Status: every function returns a d2ip_status; 0 is success.  On failure
+ *    d2ip_last_error() describes the cause and the context keeps its previous
+ *    valid state.  No C++ exception crosses the ABI.
+ *  - Memory: the caller owns every buffer it passes.  `on_device` = 0 means a
+ *    host pointer: the call copies and returns when the copy is complete.
+ *    `on_device` = 1 means a device pointer in the same HIP device (e.g. a
+ *    torch tensor's data_ptr()): the work is enqueued on the context stream and
+ *    the caller keeps the buffer alive until that stream has passed the point.
+ *  - Workspace: all device memory the library uses lives in one
+ *    caller-allocated workspace (size from d2ip_workspace_bytes, 256-byte
+ *    aligned) that the context borrows for its lifetime.  The library itself
+ *    allocates no device memory.
+ *  - Layouts: voxel index q = (z*n + y)*n + x (x fastest) for Z, mask and
+ *    images; J is M x n^3 row-major FP32 with columns in that order.
+ *    theta uses the flat order: stem, enc_0..enc_{L-1}, dec_{L-2}..dec_0,
+ *    tail; inside a module conv W[Cout][Cin][kz][ky][kx] then b, norm gamma
+ *    then beta, ResBlock order conv1, norm1, conv2, norm2, proj.
+ *  - Threads: a context is not thread-safe; distinct contexts are independent.
+ */
+#ifndef D2IP_H
+#define D2IP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct d2ip_ctx d2ip_ctx;
+
+typedef enum {
+  D2IP_OK = 0,
+  D2IP_EINVAL = -1,     /* bad argument (NULL, shape, range)                 */
+  D2IP_ENOMEM = -2,     /* workspace too small                               */
+  D2IP_EHIP = -3,       /* a HIP runtime call failed                         */
+  D2IP_ESTATE = -4,     /* call out of order (e.g. run before set_geometry)  */
+  D2IP_ENONFINITE = -5  /* a non-finite loss was produced                    */
+} d2ip_status;
+
+/* Operand precision of the convolutions; accumulation is always FP32 and the
+ * J products, LayerNorm, loss and Adam are FP32 (loss reduced in FP64). */
+typedef enum { D2IP_PLAIN_FP32 = 0, D2IP_BF16_CONV = 1 } d2ip_precision;
+
+/* d2ip_create flags */
+#define D2IP_FLAG_GRAPH 1u /* capture one iteration in a hipGraph, replay it */
+
+/* A measurement geometry: grid edge n (n^3 voxels) and M measurements. */
+typedef struct {
+  int n;
+  int M;
+} d2ip_geometry_desc;
+
+/* One fitted instance (one sequence): its geometry index, levels L (2..5) and
+ * base channels C (8, 16 or 32); n must be divisible by 2^(L-1) with
+ * n / 2^(L-1) >= 2, and C * 2^(L-1) <= 256. */
+typedef struct {
+  int geometry;
+  int levels;
+  int base_ch;
+} d2ip_instance_desc;
+
+/* Adam hyper-parameters (defaults lr 1e-3, beta1 0.9, beta2 0.999, eps 1e-8). */
+typedef struct {
+  float lr, beta1, beta2, eps;
+} d2ip_adam_cfg;
+
+/* Text of the last error on this thread ("" if none); valid until the next call. */
+const char* d2ip_last_error(void);
+
+/* Number of parameters of a network with `levels` levels and `base_ch` base
+ * channels.  Host only; needs no GPU. */
+d2ip_status d2ip_param_count(int levels, int base_ch, size_t* out);
+
+/* Workspace bytes needed by d2ip_create with the same arguments.  Host only. */
+d2ip_status d2ip_workspace_bytes(const d2ip_geometry_desc* geos, int n_geo,
+                                 const d2ip_instance_desc* insts, int n_inst, int precision,
+                                 unsigned flags, size_t* out);
+
+/* Create a context over `workspace` (device memory, >= d2ip_workspace_bytes)
+ * that enqueues on `hip_stream` (a hipStream_t; NULL = default stream).
+ * All instances start with theta = 0, Adam state zero and no frame. */
+d2ip_status d2ip_create(const d2ip_geometry_desc* geos, int n_geo, const d2ip_instance_desc* insts,
+                        int n_inst, int precision, unsigned flags, void* workspace, size_t bytes,
+                        void* hip_stream, d2ip_ctx** out);
+
+/* Release host resources (waits for the stream).  The workspace is not freed. */
+d2ip_status d2ip_destroy(d2ip_ctx* ctx);
+
+/* Sensitivity matrix of geometry `geo` (Eq. (1)): J is M x n^3 FP32 row-major,
+ * mask n^3 bytes (non-zero = voxel inside the imaging region).  J is
+ * compacted to the mask's voxels on the device; masked columns of J are
+ * ignored and masked image voxels are 0. */
+d2ip_status d2ip_set_geometry(d2ip_ctx* ctx, int geo, const float* J, const uint8_t* mask,
+                              int on_device);
+
+/* theta of instance `inst` (n = d2ip_param_count floats, flat order). */
+d2ip_status d2ip_set_params(d2ip_ctx* ctx, int inst, const float* theta, size_t n, int on_device);
+d2ip_status d2ip_get_params(d2ip_ctx* ctx, int inst, float* theta, size_t n, int on_device);
+
+/* Fixed noise input Z of instance `inst` (Eq. (3)): n^3 FP32. */
+d2ip_status d2ip_set_noise_input(d2ip_ctx* ctx, int inst, const float* z, int on_device);
+
+/* Voltage differences dv of the current frame of `inst` (M FP32).  theta is
+ * not touched (Temporal Parameter Propagation, Eq. (9)). */
+d2ip_status d2ip_set_frame(d2ip_ctx* ctx, int inst, const float* dv, int on_device);
+
+/* Adam hyper-parameters for all instances. */
+d2ip_status d2ip_set_adam(d2ip_ctx* ctx, const d2ip_adam_cfg* cfg);
+
+/* Zero the Adam moments and step counter of `inst` (call between frames to
+ * restart the optimiser while theta carries over). */
+d2ip_status d2ip_reset_optimizer(d2ip_ctx* ctx, int inst);
+
+/* Full optimiser state of `inst`: theta_m_v = [theta | m | v] (3 * P FP32),
+ * t = Adam step count.  Restoring a saved state resumes bit-exactly. */
+d2ip_status d2ip_get_state(d2ip_ctx* ctx, int inst, float* theta_m_v, int64_t* t, int on_device);
+d2ip_status d2ip_set_state(d2ip_ctx* ctx, int inst, const float* theta_m_v, int64_t t,
+                           int on_device);
+
+/* Run k iterations of every instance (forward, J d_sigma, loss, J^T, backward,
+ * Adam).  Asynchronous unless `last_loss` (n_inst doubles, may be NULL) is
+ * given: then it synchronises and stores, per instance, the data loss of the
+ * last iteration (evaluated before its update), and returns D2IP_ENONFINITE
+ * if any loss was not finite. */
+d2ip_status d2ip_run(d2ip_ctx* ctx, int k, double* last_loss);
+
+/* Gradient dL/dtheta of the data loss computed by the last iteration of
+ * `inst` (before that iteration's Adam update), flat order, n = P floats. */
+d2ip_status d2ip_get_grad(d2ip_ctx* ctx, int inst, float* grad, size_t n, int on_device);
+
+/* Image of `inst` at its current theta: mask * phi(theta | Z), n^3 FP32 (Eq. (5)). */
+d2ip_status d2ip_read_image(d2ip_ctx* ctx, int inst, float* sigma, int on_device);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* D2IP_H */

@@ -1,0 +1,88 @@
+"""ctypes declarations of libd2ip.so (the C-ABI in include/d2ip.h).
+
+There is no fallback: if the shared library is missing or fails to load this
+module raises, so nothing can silently run elsewhere.
+"""
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libd2ip.so")
+
+OK, EINVAL, ENOMEM, EHIP, ESTATE, ENONFINITE = 0, -1, -2, -3, -4, -5
+STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "ESTATE", -5: "ENONFINITE"}
+PLAIN_FP32, BF16_CONV = 0, 1
+FLAG_GRAPH = 1
+
+
+class GeometryDesc(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int), ("M", ctypes.c_int)]
+
+
+class InstanceDesc(ctypes.Structure):
+    _fields_ = [("geometry", ctypes.c_int), ("levels", ctypes.c_int), ("base_ch", ctypes.c_int)]
+
+
+class AdamCfg(ctypes.Structure):
+    _fields_ = [("lr", ctypes.c_float), ("beta1", ctypes.c_float), ("beta2", ctypes.c_float),
+                ("eps", ctypes.c_float)]
+
+
+class D2ipError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("%s (%d): %s" % (STATUS_NAMES.get(status, "?"), status, msg))
+        self.status = status
+
+
+_c_size_p = ctypes.POINTER(ctypes.c_size_t)
+_vp = ctypes.c_void_p
+_i = ctypes.c_int
+
+# name -> argument types (all return int status, except d2ip_last_error)
+SIGNATURES = {
+    "d2ip_param_count": [_i, _i, _c_size_p],
+    "d2ip_workspace_bytes": [ctypes.POINTER(GeometryDesc), _i, ctypes.POINTER(InstanceDesc), _i, _i,
+                             ctypes.c_uint, _c_size_p],
+    "d2ip_create": [ctypes.POINTER(GeometryDesc), _i, ctypes.POINTER(InstanceDesc), _i, _i,
+                    ctypes.c_uint, _vp, ctypes.c_size_t, _vp, ctypes.POINTER(_vp)],
+    "d2ip_destroy": [_vp],
+    "d2ip_set_geometry": [_vp, _i, _vp, _vp, _i],
+    "d2ip_set_params": [_vp, _i, _vp, ctypes.c_size_t, _i],
+    "d2ip_get_params": [_vp, _i, _vp, ctypes.c_size_t, _i],
+    "d2ip_get_grad": [_vp, _i, _vp, ctypes.c_size_t, _i],
+    "d2ip_set_noise_input": [_vp, _i, _vp, _i],
+    "d2ip_set_frame": [_vp, _i, _vp, _i],
+    "d2ip_set_adam": [_vp, ctypes.POINTER(AdamCfg)],
+    "d2ip_reset_optimizer": [_vp, _i],
+    "d2ip_get_state": [_vp, _i, _vp, ctypes.POINTER(ctypes.c_int64), _i],
+    "d2ip_set_state": [_vp, _i, _vp, ctypes.c_int64, _i],
+    "d2ip_run": [_vp, _i, ctypes.POINTER(ctypes.c_double)],
+    "d2ip_read_image": [_vp, _i, _vp, _i],
+}
+
+_lib = None
+
+
+def load():
+    """Load libd2ip.so once; raises if it is not built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libd2ip.so is not built (run `python -m paper_2507_14046_amd.build` "
+                          "or __graft_entry__.build()); there is no fallback path")
+    lib = ctypes.CDLL(LIB_PATH)
+    lib.d2ip_last_error.restype = ctypes.c_char_p
+    lib.d2ip_last_error.argtypes = []
+    for name, args in SIGNATURES.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def check(status):
+    if status != OK:
+        raise D2ipError(status, load().d2ip_last_error().decode())
+    return status

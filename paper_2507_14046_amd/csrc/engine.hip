@@ -1,0 +1,908 @@
+// Context, workspace plan, per-iteration launch schedule and the C-ABI of the
+// D2IP fitting library.  One context holds geometries (compacted J, mask) and
+// instances (network parameters, Adam state, activations); every launch goes
+// to the context's stream, and with D2IP_FLAG_GRAPH one iteration of all
+// instances is captured once into a hipGraph and replayed.
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "d2ip.h"
+#include "kernels.h"
+
+using namespace d2ip;
+
+namespace {
+
+thread_local std::string g_err;
+
+d2ip_status fail(d2ip_status s, const std::string& m) {
+  g_err = m;
+  return s;
+}
+
+#define HIPCHK(expr)                                                                 \
+  do {                                                                               \
+    hipError_t e_ = (expr);                                                          \
+    if (e_ != hipSuccess)                                                            \
+      return fail(D2IP_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_));     \
+  } while (0)
+
+constexpr float kLnEps = 1e-5f;
+
+struct Carver {
+  char* base = nullptr;
+  size_t off = 0;
+  template <class T>
+  T* take(size_t count) {
+    off = (off + 255) & ~size_t(255);
+    T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+    off += count * sizeof(T);
+    return p;
+  }
+};
+
+struct Conv {
+  int th_w = -1, th_b = -1;
+  int cin_real = 0, cin = 0, cout = 0, taps = 0;
+  long long wf = 0, wd = 0;
+  bool dgrad = false;
+};
+
+struct Norm {
+  int th_g = -1, th_b = -1;
+};
+
+struct Block {
+  bool enc = true;
+  int level = 0, n = 0, cin = 0, cout = 0;
+  bool proj = false;
+  Conv c1, c2, pj;
+  Norm n1, n2;
+  float *x = nullptr, *h1 = nullptr, *h2 = nullptr, *s = nullptr, *y = nullptr;
+  const float* pool_src = nullptr;  // encoder l >= 1: output of encoder l-1
+  const float* up_src = nullptr;    // decoder: output of the level below
+  const float* skip_src = nullptr;  // decoder: output of encoder l
+  LnStat *st1 = nullptr, *st2 = nullptr;
+  LnBwd *cb1 = nullptr, *cb2 = nullptr;
+};
+
+struct Level {
+  int n = 0, c = 0;
+  size_t V = 0;
+  float *gy = nullptr, *gz = nullptr, *gh = nullptr, *ga = nullptr, *gx = nullptr,
+        *genc = nullptr;
+};
+
+struct Geometry {
+  int n = 0, M = 0;
+  size_t Q = 0;
+  int qa = 0, qa_pad = 0, qa_cap = 0;
+  float* Jc = nullptr;
+  int* idx = nullptr;
+  int* inv = nullptr;
+  float* mask = nullptr;
+  bool set = false;
+};
+
+struct Instance {
+  int geo = 0, L = 0, C = 0, n = 0;
+  size_t V0 = 0, P = 0;
+  int tile = TILE_2x4x16;
+  float *theta = nullptr, *grad = nullptr, *m = nullptr, *v = nullptr;
+  float* wf32 = nullptr;
+  uint16_t* wbf16 = nullptr;
+  long long wtotal = 0;
+  std::vector<ConvPack> packs;
+  ConvPack* packs_dev = nullptr;
+  int max_pack = 0;
+  float* zpad = nullptr;
+  Conv stem;
+  Norm stem_n;
+  float *hs = nullptr, *as = nullptr;
+  LnStat* sts = nullptr;
+  LnBwd* cbs = nullptr;
+  std::vector<Block> blocks;
+  int tail_w = -1, tail_b = -1;
+  float *sigma = nullptr, *dv = nullptr;
+  IterState* it = nullptr;
+  std::vector<Level> lv;
+  double* stat_part = nullptr;
+  double* lnb_part = nullptr;
+  float *ppart = nullptr, *gp = nullptr, *tpart = nullptr;
+  double* tail_part = nullptr;
+  bool has_frame = false, has_z = false;
+};
+
+int tile_for(int n) { return n % 16 == 0 ? TILE_2x4x16 : TILE_2x8x8; }
+
+}  // namespace
+
+struct d2ip_ctx {
+  int precision = D2IP_PLAIN_FP32;
+  unsigned flags = 0;
+  hipStream_t stream = nullptr;
+  std::vector<Geometry> geos;
+  std::vector<Instance> insts;
+  float* wg_part = nullptr;
+  float* wg_partb = nullptr;
+  float lr = 1e-3f, b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  size_t bytes = 0;
+};
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// plan: parameter layout, packing table and workspace carve
+// ---------------------------------------------------------------------------
+
+d2ip_status check_desc(const d2ip_geometry_desc* geos, int n_geo, const d2ip_instance_desc* insts,
+                       int n_inst, int precision) {
+  if (!geos || n_geo <= 0 || !insts || n_inst <= 0) return fail(D2IP_EINVAL, "empty geometry or instance list");
+  if (precision != D2IP_PLAIN_FP32 && precision != D2IP_BF16_CONV)
+    return fail(D2IP_EINVAL, "unknown precision");
+  for (int g = 0; g < n_geo; ++g) {
+    if (geos[g].n < 4 || geos[g].n > 256 || geos[g].M <= 0 || geos[g].M > 65536)
+      return fail(D2IP_EINVAL, "geometry " + std::to_string(g) + ": n must be in [4, 256], M in [1, 65536]");
+  }
+  for (int i = 0; i < n_inst; ++i) {
+    const d2ip_instance_desc& d = insts[i];
+    if (d.geometry < 0 || d.geometry >= n_geo)
+      return fail(D2IP_EINVAL, "instance " + std::to_string(i) + ": bad geometry index");
+    if (d.levels < 2 || d.levels > 5)
+      return fail(D2IP_EINVAL, "instance " + std::to_string(i) + ": levels must be 2..5");
+    if (d.base_ch != 8 && d.base_ch != 16 && d.base_ch != 32)
+      return fail(D2IP_EINVAL, "instance " + std::to_string(i) + ": base_ch must be 8, 16 or 32");
+    if (d.base_ch << (d.levels - 1) > 256)
+      return fail(D2IP_EINVAL, "instance " + std::to_string(i) + ": base_ch * 2^(levels-1) > 256");
+    const int n = geos[d.geometry].n, f = 1 << (d.levels - 1);
+    if (n % f != 0 || n / f < 2)
+      return fail(D2IP_EINVAL, "instance " + std::to_string(i) + ": grid not divisible by 2^(levels-1)");
+  }
+  return D2IP_OK;
+}
+
+// Parameter offsets of one network in the flat order.
+struct LayoutBuilder {
+  int off = 0;
+  Conv conv(int cout, int cin, int k) {
+    Conv c;
+    c.th_w = off;
+    off += cout * cin * k * k * k;
+    c.th_b = off;
+    off += cout;
+    c.cout = cout;
+    c.cin_real = cin;
+    c.cin = (cin + 7) / 8 * 8;
+    c.taps = k * k * k;
+    c.dgrad = true;
+    return c;
+  }
+  Norm norm(int c) {
+    Norm nm;
+    nm.th_g = off;
+    off += c;
+    nm.th_b = off;
+    off += c;
+    return nm;
+  }
+};
+
+void make_block(LayoutBuilder& lb, Block& b, int cin, int cout) {
+  b.cin = cin;
+  b.cout = cout;
+  b.c1 = lb.conv(cout, cin, 3);
+  b.n1 = lb.norm(cout);
+  b.c2 = lb.conv(cout, cout, 3);
+  b.n2 = lb.norm(cout);
+  b.proj = cin != cout;
+  if (b.proj) b.pj = lb.conv(cout, cin, 1);
+}
+
+size_t layout(Instance& I) {
+  LayoutBuilder lb;
+  const int C = I.C, L = I.L;
+  I.stem = lb.conv(C, 1, 3);
+  I.stem.dgrad = false;
+  I.stem_n = lb.norm(C);
+  I.blocks.clear();
+  for (int l = 0; l < L; ++l) {
+    Block b;
+    b.enc = true;
+    b.level = l;
+    b.n = I.n >> l;
+    make_block(lb, b, l == 0 ? C : (C << (l - 1)), C << l);
+    I.blocks.push_back(b);
+  }
+  for (int l = L - 2; l >= 0; --l) {
+    Block b;
+    b.enc = false;
+    b.level = l;
+    b.n = I.n >> l;
+    make_block(lb, b, (C << (l + 1)) + (C << l), C << l);
+    I.blocks.push_back(b);
+  }
+  Conv t = lb.conv(1, C, 1);
+  I.tail_w = t.th_w;
+  I.tail_b = t.th_b;
+  return (size_t)lb.off;
+}
+
+void add_pack(Instance& I, Conv& c) {
+  c.wf = I.wtotal;
+  I.wtotal += (long long)c.cout * c.taps * c.cin;
+  if (c.dgrad) {
+    c.wd = I.wtotal;
+    I.wtotal += (long long)c.cin_real * c.taps * c.cout;
+  }
+  ConvPack p;
+  p.th_off = c.th_w;
+  p.cout = c.cout;
+  p.cin_real = c.cin_real;
+  p.cin = c.cin;
+  p.taps = c.taps;
+  p.need_dgrad = c.dgrad ? 1 : 0;
+  p.wf_off = c.wf;
+  p.wd_off = c.wd;
+  I.packs.push_back(p);
+  const int e = c.cout * c.cin_real * c.taps;
+  if (e > I.max_pack) I.max_pack = e;
+}
+
+ConvFwd fwd_args(const Instance& I, int prec, const Conv& c, int n, const float* x, int cin_stride,
+                 float* y) {
+  ConvFwd a;
+  std::memset(&a, 0, sizeof(a));
+  a.x = x;
+  a.n = n;
+  a.cin = c.cin;
+  a.cin_stride = cin_stride;
+  a.w = prec == PREC_BF16 ? (const void*)(I.wbf16 + c.wf) : (const void*)(I.wf32 + c.wf);
+  a.w_rows = c.cout;
+  a.cout = c.cout;
+  a.y = y;
+  a.taps = c.taps;
+  a.prologue = PRO_NONE;
+  a.prec = prec;
+  a.tile = tile_for(n);
+  return a;
+}
+
+ConvFwd dgrad_args(const Instance& I, int prec, const Conv& c, int n, const float* g, float* y) {
+  ConvFwd a;
+  std::memset(&a, 0, sizeof(a));
+  a.x = g;
+  a.n = n;
+  a.cin = c.cout;
+  a.cin_stride = c.cout;
+  a.w = prec == PREC_BF16 ? (const void*)(I.wbf16 + c.wd) : (const void*)(I.wf32 + c.wd);
+  a.w_rows = c.cin_real;
+  a.cout = c.cin_real;
+  a.y = y;
+  a.taps = c.taps;
+  a.prologue = PRO_NONE;
+  a.prec = prec;
+  a.tile = tile_for(n);
+  return a;
+}
+
+// Carve the workspace (base == nullptr: only count bytes).
+void plan(d2ip_ctx& X, const d2ip_geometry_desc* gd, int n_geo, const d2ip_instance_desc* id,
+          int n_inst, Carver& cv) {
+  X.geos.assign(n_geo, Geometry());
+  for (int g = 0; g < n_geo; ++g) {
+    Geometry& G = X.geos[g];
+    G.n = gd[g].n;
+    G.M = gd[g].M;
+    G.Q = (size_t)G.n * G.n * G.n;
+    G.qa_cap = (int)((G.Q + 63) / 64 * 64);
+    G.Jc = cv.take<float>((size_t)G.M * G.qa_cap);
+    G.idx = cv.take<int>(G.qa_cap);
+    G.inv = cv.take<int>(G.Q);
+    G.mask = cv.take<float>(G.Q);
+  }
+  X.insts.assign(n_inst, Instance());
+  size_t wg_max = 0, wgb_max = 0;
+  for (int i = 0; i < n_inst; ++i) {
+    Instance& I = X.insts[i];
+    I.geo = id[i].geometry;
+    I.L = id[i].levels;
+    I.C = id[i].base_ch;
+    const Geometry& G = X.geos[I.geo];
+    I.n = G.n;
+    I.V0 = G.Q;
+    I.tile = tile_for(I.n);
+    I.P = layout(I);
+    I.packs.clear();
+    I.wtotal = 0;
+    I.max_pack = 0;
+    add_pack(I, I.stem);
+    for (Block& b : I.blocks) {
+      add_pack(I, b.c1);
+      add_pack(I, b.c2);
+      if (b.proj) add_pack(I, b.pj);
+    }
+    I.theta = cv.take<float>(I.P);
+    I.grad = cv.take<float>(I.P);
+    I.m = cv.take<float>(I.P);
+    I.v = cv.take<float>(I.P);
+    if (X.precision == D2IP_BF16_CONV)
+      I.wbf16 = cv.take<uint16_t>(I.wtotal);
+    else
+      I.wf32 = cv.take<float>(I.wtotal);
+    I.packs_dev = cv.take<ConvPack>(I.packs.size());
+    const size_t V0 = I.V0;
+    const int C = I.C;
+    I.zpad = cv.take<float>(V0 * 8);
+    I.hs = cv.take<float>(V0 * C);
+    I.as = cv.take<float>(V0 * C);
+    I.sts = cv.take<LnStat>(1);
+    I.cbs = cv.take<LnBwd>(1);
+    int max_conv_blocks = 0;
+    size_t max_lnb = 0;
+    auto note_conv = [&](const Conv& c, int n) {
+      ConvFwd a;
+      std::memset(&a, 0, sizeof(a));
+      a.n = n;
+      a.cout = c.cout;
+      a.tile = tile_for(n);
+      max_conv_blocks = std::max(max_conv_blocks, conv_fwd_blocks(a));
+      if (c.dgrad) {
+        a.cout = c.cin_real;
+        max_conv_blocks = std::max(max_conv_blocks, conv_fwd_blocks(a));
+      }
+      wg_max = std::max(wg_max, conv_wgrad_part_floats(n, c.cin, c.cout, c.taps, tile_for(n)));
+      wgb_max = std::max(wgb_max, (size_t)conv_wgrad_splits(n, c.cin, c.cout, tile_for(n)) *
+                                      ((c.cout + 15) / 16 * 16));
+    };
+    note_conv(I.stem, I.n);
+    max_lnb = std::max(max_lnb, (size_t)ln_bwd_blocks(V0, C) * C);
+    I.lv.assign(I.L, Level());
+    for (int l = 0; l < I.L; ++l) {
+      Level& Lv = I.lv[l];
+      Lv.n = I.n >> l;
+      Lv.c = C << l;
+      Lv.V = (size_t)Lv.n * Lv.n * Lv.n;
+      Lv.gy = cv.take<float>(Lv.V * Lv.c);
+      Lv.gz = cv.take<float>(Lv.V * Lv.c);
+      Lv.gh = cv.take<float>(Lv.V * Lv.c);
+      Lv.ga = cv.take<float>(Lv.V * Lv.c);
+      Lv.gx = cv.take<float>(Lv.V * Lv.c * 3);
+      Lv.genc = cv.take<float>(Lv.V * Lv.c);
+      max_lnb = std::max(max_lnb, (size_t)ln_bwd_blocks(Lv.V, Lv.c) * Lv.c);
+    }
+    const int L = I.L;
+    for (size_t k = 0; k < I.blocks.size(); ++k) {
+      Block& b = I.blocks[k];
+      const size_t V = (size_t)b.n * b.n * b.n;
+      if (b.enc) {
+        if (b.level == 0) {
+          b.x = I.as;
+        } else {
+          b.x = cv.take<float>(V * b.cin);
+          b.pool_src = I.blocks[b.level - 1].y;
+        }
+      } else {
+        b.x = cv.take<float>(V * b.cin);
+      }
+      b.h1 = cv.take<float>(V * b.cout);
+      b.h2 = cv.take<float>(V * b.cout);
+      b.y = cv.take<float>(V * b.cout);
+      if (b.proj) b.s = cv.take<float>(V * b.cout);
+      b.st1 = cv.take<LnStat>(1);
+      b.st2 = cv.take<LnStat>(1);
+      b.cb1 = cv.take<LnBwd>(1);
+      b.cb2 = cv.take<LnBwd>(1);
+      note_conv(b.c1, b.n);
+      note_conv(b.c2, b.n);
+      if (b.proj) note_conv(b.pj, b.n);
+      if (b.enc && b.level > 0) b.pool_src = I.blocks[b.level - 1].y;
+    }
+    // decoder sources (after every block has its output buffer)
+    for (size_t k = L; k < I.blocks.size(); ++k) {
+      Block& b = I.blocks[k];
+      b.up_src = (b.level == L - 2) ? I.blocks[L - 1].y : I.blocks[k - 1].y;
+      b.skip_src = I.blocks[b.level].y;
+    }
+    I.sigma = cv.take<float>(V0);
+    I.dv = cv.take<float>(G.M);
+    I.it = cv.take<IterState>(1);
+    I.stat_part = cv.take<double>(2 * (size_t)max_conv_blocks);
+    I.lnb_part = cv.take<double>(2 * max_lnb);
+    I.ppart = cv.take<float>((size_t)jvec_qblocks(G.qa_cap) * G.M);
+    I.gp = cv.take<float>(G.M);
+    I.tpart = cv.take<float>((size_t)jt_mblocks(G.M) * G.qa_cap);
+    I.tail_part = cv.take<double>((size_t)tail_bwd_blocks(V0, C) * (C + 1));
+  }
+  X.wg_part = cv.take<float>(wg_max);
+  X.wg_partb = cv.take<float>(wgb_max);
+}
+
+// ---------------------------------------------------------------------------
+// launch schedule
+// ---------------------------------------------------------------------------
+
+void conv_fwd_stats(d2ip_ctx& X, Instance& I, ConvFwd a, LnStat* st) {
+  a.stat_part = I.stat_part;
+  conv_fwd(a, X.stream);
+  ln_finalize(I.stat_part, conv_fwd_blocks(a), (double)a.n * a.n * a.n * a.cout, kLnEps, st,
+              X.stream);
+}
+
+void wgrad(d2ip_ctx& X, Instance& I, const Conv& c, int n, const float* x, int cin_stride,
+           const float* g, int pro, const LnStat* st, const float* lg, const float* lb) {
+  ConvWgrad a;
+  std::memset(&a, 0, sizeof(a));
+  a.x = x;
+  a.n = n;
+  a.cin = c.cin;
+  a.cin_stride = cin_stride;
+  a.g = g;
+  a.cout = c.cout;
+  a.taps = c.taps;
+  a.prologue = pro;
+  a.ln = st;
+  a.ln_g = lg;
+  a.ln_b = lb;
+  a.part = X.wg_part;
+  a.partb = X.wg_partb;
+  a.tile = tile_for(n);
+  a.splits = conv_wgrad_splits(n, c.cin, c.cout, a.tile);
+  a.prec = X.precision == D2IP_BF16_CONV ? PREC_BF16 : PREC_F32;
+  conv_wgrad(a, X.stream);
+  wgrad_reduce(X.wg_part, X.wg_partb, a.splits, c.cout, c.taps, c.cin, c.cin_real,
+               I.grad + c.th_w, I.grad + c.th_b, X.stream);
+}
+
+void enqueue_forward(d2ip_ctx& X, Instance& I) {
+  const int prec = X.precision == D2IP_BF16_CONV ? PREC_BF16 : PREC_F32;
+  const Geometry& G = X.geos[I.geo];
+  hipStream_t s = X.stream;
+  float* th = I.theta;
+  {
+    ConvFwd a = fwd_args(I, prec, I.stem, I.n, I.zpad, 8, I.hs);
+    a.bias = th + I.stem.th_b;
+    conv_fwd_stats(X, I, a, I.sts);
+    ln_apply(I.hs, I.sts, th + I.stem_n.th_g, th + I.stem_n.th_b, nullptr, I.as, I.V0, I.C, s);
+  }
+  for (Block& b : I.blocks) {
+    const size_t V = (size_t)b.n * b.n * b.n;
+    if (b.enc && b.level > 0) avgpool2(b.pool_src, b.n * 2, b.cin, b.x, s);
+    if (!b.enc) up_concat(b.up_src, b.cout * 2, b.skip_src, b.cout, b.n, b.x, s);
+    ConvFwd a1 = fwd_args(I, prec, b.c1, b.n, b.x, b.cin, b.h1);
+    a1.bias = th + b.c1.th_b;
+    conv_fwd_stats(X, I, a1, b.st1);
+    ConvFwd a2 = fwd_args(I, prec, b.c2, b.n, b.h1, b.cout, b.h2);
+    a2.bias = th + b.c2.th_b;
+    a2.prologue = PRO_LN_RELU;
+    a2.ln = b.st1;
+    a2.ln_g = th + b.n1.th_g;
+    a2.ln_b = th + b.n1.th_b;
+    conv_fwd_stats(X, I, a2, b.st2);
+    if (b.proj) {
+      ConvFwd ap = fwd_args(I, prec, b.pj, b.n, b.x, b.cin, b.s);
+      ap.bias = th + b.pj.th_b;
+      conv_fwd(ap, s);
+    }
+    ln_apply(b.h2, b.st2, th + b.n2.th_g, th + b.n2.th_b, b.proj ? b.s : b.x, b.y, V, b.cout, s);
+  }
+  tail_fwd(I.blocks.back().y, I.C, th + I.tail_w, th + I.tail_b, G.mask, I.V0, I.sigma, s);
+}
+
+void enqueue_iteration(d2ip_ctx& X, Instance& I) {
+  const int prec = X.precision == D2IP_BF16_CONV ? PREC_BF16 : PREC_F32;
+  const Geometry& G = X.geos[I.geo];
+  hipStream_t s = X.stream;
+  float* th = I.theta;
+  float* gr = I.grad;
+  enqueue_forward(X, I);
+  // measurement operator, data term and its gradient w.r.t. the image
+  jvec(G.Jc, G.M, G.qa_pad, G.idx, I.sigma, I.ppart, s);
+  data_loss(I.ppart, jvec_qblocks(G.qa_pad), I.dv, G.M, I.gp, I.it, X.b1, X.b2, s);
+  jtvec(G.Jc, G.M, G.qa_pad, I.gp, I.tpart, s);
+  const Block& d0 = I.blocks.back();
+  tail_bwd(I.tpart, jt_mblocks(G.M), G.qa_pad, G.inv, d0.y, I.C, th + I.tail_w, I.V0,
+           I.lv[0].gy, I.tail_part, s);
+  reduce_cols(I.tail_part, tail_bwd_blocks(I.V0, I.C), I.C + 1, gr + I.tail_w, s);
+  // network backward, decoder first
+  const int L = I.L;
+  for (int k = (int)I.blocks.size() - 1; k >= 0; --k) {
+    Block& b = I.blocks[k];
+    Level& Lv = I.lv[b.level];
+    const size_t V = (size_t)b.n * b.n * b.n;
+    const double cnt = (double)V * b.cout;
+    ln_bwd_sums(Lv.gy, LNMASK_Y, b.y, nullptr, nullptr, b.h2, b.st2, Lv.gz, I.lnb_part, V, b.cout,
+                s);
+    ln_bwd_finalize(I.lnb_part, ln_bwd_blocks(V, b.cout), b.cout, cnt, th + b.n2.th_g,
+                    gr + b.n2.th_g, gr + b.n2.th_b, b.cb2, s);
+    ln_bwd_apply(Lv.gz, b.h2, b.st2, th + b.n2.th_g, b.cb2, Lv.gh, V, b.cout, s);
+    wgrad(X, I, b.c2, b.n, b.h1, b.cout, Lv.gh, PRO_LN_RELU, b.st1, th + b.n1.th_g,
+          th + b.n1.th_b);
+    conv_fwd(dgrad_args(I, prec, b.c2, b.n, Lv.gh, Lv.ga), s);
+    ln_bwd_sums(Lv.ga, LNMASK_LN, nullptr, th + b.n1.th_g, th + b.n1.th_b, b.h1, b.st1, Lv.ga,
+                I.lnb_part, V, b.cout, s);
+    ln_bwd_finalize(I.lnb_part, ln_bwd_blocks(V, b.cout), b.cout, cnt, th + b.n1.th_g,
+                    gr + b.n1.th_g, gr + b.n1.th_b, b.cb1, s);
+    ln_bwd_apply(Lv.ga, b.h1, b.st1, th + b.n1.th_g, b.cb1, Lv.gh, V, b.cout, s);
+    wgrad(X, I, b.c1, b.n, b.x, b.cin, Lv.gh, PRO_NONE, nullptr, nullptr, nullptr);
+    {
+      ConvFwd a = dgrad_args(I, prec, b.c1, b.n, Lv.gh, Lv.gx);
+      if (!b.proj) a.add = Lv.gz;
+      conv_fwd(a, s);
+    }
+    if (b.proj) {
+      wgrad(X, I, b.pj, b.n, b.x, b.cin, Lv.gz, PRO_NONE, nullptr, nullptr, nullptr);
+      ConvFwd a = dgrad_args(I, prec, b.pj, b.n, Lv.gz, Lv.gx);
+      a.accumulate = 1;
+      conv_fwd(a, s);
+    }
+    if (!b.enc) {
+      up_concat_bwd(Lv.gx, b.cout * 2, b.cout, b.n, I.lv[b.level + 1].gy, Lv.genc, s);
+    } else if (b.level > 0) {
+      Level& Lp = I.lv[b.level - 1];
+      pool_bwd_add(Lv.gx, Lp.genc, Lp.n, Lp.c, Lp.gy, s);
+    }
+    (void)L;
+  }
+  // stem
+  {
+    Level& L0 = I.lv[0];
+    const double cnt = (double)I.V0 * I.C;
+    ln_bwd_sums(L0.gx, LNMASK_Y, I.as, nullptr, nullptr, I.hs, I.sts, L0.gz, I.lnb_part, I.V0,
+                I.C, s);
+    ln_bwd_finalize(I.lnb_part, ln_bwd_blocks(I.V0, I.C), I.C, cnt, th + I.stem_n.th_g,
+                    gr + I.stem_n.th_g, gr + I.stem_n.th_b, I.cbs, s);
+    ln_bwd_apply(L0.gz, I.hs, I.sts, th + I.stem_n.th_g, I.cbs, L0.gh, I.V0, I.C, s);
+    wgrad(X, I, I.stem, I.n, I.zpad, 8, L0.gh, PRO_NONE, nullptr, nullptr, nullptr);
+  }
+  adam(th, gr, I.m, I.v, I.P, X.lr, X.b1, X.b2, X.eps, I.it, s);
+  pack_weights(I.packs_dev, (int)I.packs.size(), I.max_pack, th, I.wf32, I.wbf16, s);
+}
+
+d2ip_status check_inst(d2ip_ctx* X, int inst) {
+  if (!X) return fail(D2IP_EINVAL, "null context");
+  if (inst < 0 || inst >= (int)X->insts.size()) return fail(D2IP_EINVAL, "bad instance index");
+  return D2IP_OK;
+}
+
+hipMemcpyKind kind_to_dev(int on_device) {
+  return on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+}
+hipMemcpyKind kind_from_dev(int on_device) {
+  return on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+}
+
+d2ip_status copy_in(d2ip_ctx* X, void* dst, const void* src, size_t bytes, int on_device) {
+  HIPCHK(hipMemcpyAsync(dst, src, bytes, kind_to_dev(on_device), X->stream));
+  if (!on_device) HIPCHK(hipStreamSynchronize(X->stream));
+  return D2IP_OK;
+}
+
+d2ip_status copy_out(d2ip_ctx* X, void* dst, const void* src, size_t bytes, int on_device) {
+  HIPCHK(hipMemcpyAsync(dst, src, bytes, kind_from_dev(on_device), X->stream));
+  if (!on_device) HIPCHK(hipStreamSynchronize(X->stream));
+  return D2IP_OK;
+}
+
+d2ip_status repack(d2ip_ctx* X, Instance& I) {
+  pack_weights(I.packs_dev, (int)I.packs.size(), I.max_pack, I.theta, I.wf32, I.wbf16, X->stream);
+  HIPCHK(hipGetLastError());
+  return D2IP_OK;
+}
+
+void drop_graph(d2ip_ctx* X) {
+  if (X->gexec) hipGraphExecDestroy(X->gexec);
+  if (X->graph) hipGraphDestroy(X->graph);
+  X->gexec = nullptr;
+  X->graph = nullptr;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C-ABI
+// ---------------------------------------------------------------------------
+
+extern "C" {
+
+const char* d2ip_last_error(void) { return g_err.c_str(); }
+
+d2ip_status d2ip_param_count(int levels, int base_ch, size_t* out) {
+  if (!out) return fail(D2IP_EINVAL, "null output");
+  if (levels < 2 || levels > 5 || base_ch <= 0 || base_ch > 256)
+    return fail(D2IP_EINVAL, "levels must be 2..5 and base_ch in 1..256");
+  Instance I;
+  I.L = levels;
+  I.C = base_ch;
+  *out = layout(I);
+  return D2IP_OK;
+}
+
+d2ip_status d2ip_workspace_bytes(const d2ip_geometry_desc* geos, int n_geo,
+                                 const d2ip_instance_desc* insts, int n_inst, int precision,
+                                 unsigned flags, size_t* out) {
+  if (!out) return fail(D2IP_EINVAL, "null output");
+  d2ip_status st = check_desc(geos, n_geo, insts, n_inst, precision);
+  if (st != D2IP_OK) return st;
+  d2ip_ctx X;
+  X.precision = precision;
+  X.flags = flags;
+  Carver cv;
+  plan(X, geos, n_geo, insts, n_inst, cv);
+  *out = (cv.off + 255) & ~size_t(255);
+  return D2IP_OK;
+}
+
+d2ip_status d2ip_create(const d2ip_geometry_desc* geos, int n_geo, const d2ip_instance_desc* insts,
+                        int n_inst, int precision, unsigned flags, void* workspace, size_t bytes,
+                        void* hip_stream, d2ip_ctx** out) {
+  if (!out) return fail(D2IP_EINVAL, "null output");
+  *out = nullptr;
+  size_t need = 0;
+  d2ip_status st = d2ip_workspace_bytes(geos, n_geo, insts, n_inst, precision, flags, &need);
+  if (st != D2IP_OK) return st;
+  if (!workspace) return fail(D2IP_EINVAL, "null workspace");
+  if (((uintptr_t)workspace & 255) != 0) return fail(D2IP_EINVAL, "workspace not 256-byte aligned");
+  if (bytes < need)
+    return fail(D2IP_ENOMEM, "workspace too small: need " + std::to_string(need) + " bytes, got " +
+                                 std::to_string(bytes));
+  d2ip_ctx* X = new d2ip_ctx();
+  X->precision = precision;
+  X->flags = flags;
+  X->stream = reinterpret_cast<hipStream_t>(hip_stream);
+  X->bytes = bytes;
+  Carver cv;
+  cv.base = reinterpret_cast<char*>(workspace);
+  plan(*X, geos, n_geo, insts, n_inst, cv);
+  auto cleanup = [&](d2ip_status s) {
+    delete X;
+    return s;
+  };
+  // zero everything once: padding of packed weights and J, state, counters
+  hipError_t e = hipMemsetAsync(workspace, 0, need, X->stream);
+  if (e == hipSuccess) {
+    for (Instance& I : X->insts) {
+      e = hipMemcpyAsync(I.packs_dev, I.packs.data(), I.packs.size() * sizeof(ConvPack),
+                         hipMemcpyHostToDevice, X->stream);
+      if (e != hipSuccess) break;
+    }
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(X->stream);
+  if (e != hipSuccess)
+    return cleanup(fail(D2IP_EHIP, std::string("workspace init: ") + hipGetErrorString(e)));
+  *out = X;
+  return D2IP_OK;
+}
+
+d2ip_status d2ip_destroy(d2ip_ctx* X) {
+  if (!X) return D2IP_OK;
+  hipStreamSynchronize(X->stream);
+  drop_graph(X);
+  delete X;
+  return D2IP_OK;
+}
+
+d2ip_status d2ip_set_geometry(d2ip_ctx* X, int geo, const float* J, const uint8_t* mask,
+                              int on_device) {
+  if (!X) return fail(D2IP_EINVAL, "null context");
+  if (geo < 0 || geo >= (int)X->geos.size()) return fail(D2IP_EINVAL, "bad geometry index");
+  if (!J || !mask) return fail(D2IP_EINVAL, "null J or mask");
+  Geometry& G = X->geos[geo];
+  std::vector<uint8_t> hm(G.Q);
+  if (on_device) {
+    HIPCHK(hipMemcpyAsync(hm.data(), mask, G.Q, hipMemcpyDeviceToHost, X->stream));
+    HIPCHK(hipStreamSynchronize(X->stream));
+  } else {
+    std::memcpy(hm.data(), mask, G.Q);
+  }
+  std::vector<int> idx;
+  std::vector<int> inv(G.Q, -1);
+  std::vector<float> maskf(G.Q, 0.f);
+  for (size_t q = 0; q < G.Q; ++q)
+    if (hm[q]) {
+      inv[q] = (int)idx.size();
+      idx.push_back((int)q);
+      maskf[q] = 1.f;
+    }
+  if (idx.empty()) return fail(D2IP_EINVAL, "mask selects no voxel");
+  const int qa = (int)idx.size();
+  const int qa_pad = (qa + 63) / 64 * 64;
+  std::vector<int> idxp(qa_pad, idx[0]);
+  std::copy(idx.begin(), idx.end(), idxp.begin());
+  HIPCHK(hipMemcpyAsync(G.idx, idxp.data(), qa_pad * sizeof(int), hipMemcpyHostToDevice, X->stream));
+  HIPCHK(hipMemcpyAsync(G.inv, inv.data(), G.Q * sizeof(int), hipMemcpyHostToDevice, X->stream));
+  HIPCHK(hipMemcpyAsync(G.mask, maskf.data(), G.Q * sizeof(float), hipMemcpyHostToDevice, X->stream));
+  if (on_device) {
+    gather_columns(J, G.M, (int)G.Q, G.idx, qa, qa_pad, G.Jc, X->stream);
+    HIPCHK(hipGetLastError());
+  } else {
+    std::vector<float> jc((size_t)G.M * qa_pad, 0.f);
+    for (int m = 0; m < G.M; ++m) {
+      const float* row = J + (size_t)m * G.Q;
+      float* dst = jc.data() + (size_t)m * qa_pad;
+      for (int q = 0; q < qa; ++q) dst[q] = row[idx[q]];
+    }
+    HIPCHK(hipMemcpyAsync(G.Jc, jc.data(), jc.size() * sizeof(float), hipMemcpyHostToDevice,
+                          X->stream));
+  }
+  HIPCHK(hipStreamSynchronize(X->stream));
+  G.qa = qa;
+  G.qa_pad = qa_pad;
+  G.set = true;
+  drop_graph(X);
+  return D2IP_OK;
+}
+
+d2ip_status d2ip_set_params(d2ip_ctx* X, int inst, const float* theta, size_t n, int on_device) {
+  d2ip_status st = check_inst(X, inst);
+  if (st != D2IP_OK) return st;
+  Instance& I = X->insts[inst];
+  if (!theta || n != I.P)
+    return fail(D2IP_EINVAL, "theta must hold " + std::to_string(I.P) + " floats");
+  st = copy_in(X, I.theta, theta, n * sizeof(float), on_device);
+  if (st != D2IP_OK) return st;
+  return repack(X, I);
+}
+
+d2ip_status d2ip_get_params(d2ip_ctx* X, int inst, float* theta, size_t n, int on_device) {
+  d2ip_status st = check_inst(X, inst);
+  if (st != D2IP_OK) return st;
+  Instance& I = X->insts[inst];
+  if (!theta || n != I.P)
+    return fail(D2IP_EINVAL, "theta must hold " + std::to_string(I.P) + " floats");
+  return copy_out(X, theta, I.theta, n * sizeof(float), on_device);
+}
+
+d2ip_status d2ip_get_grad(d2ip_ctx* X, int inst, float* grad, size_t n, int on_device) {
+  d2ip_status st = check_inst(X, inst);
+  if (st != D2IP_OK) return st;
+  Instance& I = X->insts[inst];
+  if (!grad || n != I.P)
+    return fail(D2IP_EINVAL, "grad must hold " + std::to_string(I.P) + " floats");
+  return copy_out(X, grad, I.grad, n * sizeof(float), on_device);
+}
+
+d2ip_status d2ip_set_noise_input(d2ip_ctx* X, int inst, const float* z, int on_device) {
+  d2ip_status st = check_inst(X, inst);
+  if (st != D2IP_OK) return st;
+  if (!z) return fail(D2IP_EINVAL, "null Z");
+  Instance& I = X->insts[inst];
+  // stage Z in the sigma buffer, then spread it into the padded input
+  st = copy_in(X, I.sigma, z, I.V0 * sizeof(float), on_device);
+  if (st != D2IP_OK) return st;
+  pad_input(I.sigma, I.V0, I.zpad, X->stream);
+  HIPCHK(hipGetLastError());
+  I.has_z = true;
+  return D2IP_OK;
+}
+
+d2ip_status d2ip_set_frame(d2ip_ctx* X, int inst, const float* dv, int on_device) {
+  d2ip_status st = check_inst(X, inst);
+  if (st != D2IP_OK) return st;
+  if (!dv) return fail(D2IP_EINVAL, "null dv");
+  Instance& I = X->insts[inst];
+  const int M = X->geos[I.geo].M;
+  if (!on_device) {
+    for (int m = 0; m < M; ++m)
+      if (!std::isfinite(dv[m])) return fail(D2IP_ENONFINITE, "dv holds a non-finite value");
+  }
+  st = copy_in(X, I.dv, dv, M * sizeof(float), on_device);
+  if (st != D2IP_OK) return st;
+  I.has_frame = true;
+  return D2IP_OK;
+}
+
+d2ip_status d2ip_set_adam(d2ip_ctx* X, const d2ip_adam_cfg* cfg) {
+  if (!X || !cfg) return fail(D2IP_EINVAL, "null argument");
+  if (!(cfg->lr > 0.f) || !(cfg->beta1 >= 0.f && cfg->beta1 < 1.f) ||
+      !(cfg->beta2 >= 0.f && cfg->beta2 < 1.f) || !(cfg->eps > 0.f))
+    return fail(D2IP_EINVAL, "Adam needs lr > 0, 0 <= beta < 1, eps > 0");
+  X->lr = cfg->lr;
+  X->b1 = cfg->beta1;
+  X->b2 = cfg->beta2;
+  X->eps = cfg->eps;
+  drop_graph(X);
+  return D2IP_OK;
+}
+
+d2ip_status d2ip_reset_optimizer(d2ip_ctx* X, int inst) {
+  d2ip_status st = check_inst(X, inst);
+  if (st != D2IP_OK) return st;
+  Instance& I = X->insts[inst];
+  HIPCHK(hipMemsetAsync(I.m, 0, I.P * sizeof(float), X->stream));
+  HIPCHK(hipMemsetAsync(I.v, 0, I.P * sizeof(float), X->stream));
+  HIPCHK(hipMemsetAsync(&I.it->t, 0, sizeof(int), X->stream));
+  return D2IP_OK;
+}
+
+d2ip_status d2ip_get_state(d2ip_ctx* X, int inst, float* tmv, int64_t* t, int on_device) {
+  d2ip_status st = check_inst(X, inst);
+  if (st != D2IP_OK) return st;
+  if (!tmv || !t) return fail(D2IP_EINVAL, "null argument");
+  Instance& I = X->insts[inst];
+  const size_t b = I.P * sizeof(float);
+  const hipMemcpyKind k = kind_from_dev(on_device);
+  HIPCHK(hipMemcpyAsync(tmv, I.theta, b, k, X->stream));
+  HIPCHK(hipMemcpyAsync(tmv + I.P, I.m, b, k, X->stream));
+  HIPCHK(hipMemcpyAsync(tmv + 2 * I.P, I.v, b, k, X->stream));
+  int tt = 0;
+  HIPCHK(hipMemcpyAsync(&tt, &I.it->t, sizeof(int), hipMemcpyDeviceToHost, X->stream));
+  HIPCHK(hipStreamSynchronize(X->stream));
+  *t = tt;
+  return D2IP_OK;
+}
+
+d2ip_status d2ip_set_state(d2ip_ctx* X, int inst, const float* tmv, int64_t t, int on_device) {
+  d2ip_status st = check_inst(X, inst);
+  if (st != D2IP_OK) return st;
+  if (!tmv || t < 0 || t > (int64_t)1 << 30) return fail(D2IP_EINVAL, "bad state");
+  Instance& I = X->insts[inst];
+  const size_t b = I.P * sizeof(float);
+  const hipMemcpyKind k = kind_to_dev(on_device);
+  int tt = (int)t;
+  HIPCHK(hipMemcpyAsync(I.theta, tmv, b, k, X->stream));
+  HIPCHK(hipMemcpyAsync(I.m, tmv + I.P, b, k, X->stream));
+  HIPCHK(hipMemcpyAsync(I.v, tmv + 2 * I.P, b, k, X->stream));
+  HIPCHK(hipMemcpyAsync(&I.it->t, &tt, sizeof(int), hipMemcpyHostToDevice, X->stream));
+  HIPCHK(hipStreamSynchronize(X->stream));
+  return repack(X, I);
+}
+
+d2ip_status d2ip_run(d2ip_ctx* X, int k, double* last_loss) {
+  if (!X) return fail(D2IP_EINVAL, "null context");
+  if (k < 0) return fail(D2IP_EINVAL, "k must be >= 0");
+  for (size_t i = 0; i < X->insts.size(); ++i) {
+    const Instance& I = X->insts[i];
+    if (!X->geos[I.geo].set)
+      return fail(D2IP_ESTATE, "geometry " + std::to_string(I.geo) + " not set");
+    if (!I.has_z) return fail(D2IP_ESTATE, "instance " + std::to_string(i) + ": noise input not set");
+    if (!I.has_frame) return fail(D2IP_ESTATE, "instance " + std::to_string(i) + ": frame not set");
+  }
+  if (k > 0) {
+    if (X->flags & D2IP_FLAG_GRAPH) {
+      if (!X->gexec) {
+        HIPCHK(hipStreamBeginCapture(X->stream, hipStreamCaptureModeThreadLocal));
+        for (Instance& I : X->insts) enqueue_iteration(*X, I);
+        hipGraph_t g = nullptr;
+        hipError_t e = hipStreamEndCapture(X->stream, &g);
+        if (e != hipSuccess) return fail(D2IP_EHIP, std::string("graph capture: ") + hipGetErrorString(e));
+        X->graph = g;
+        HIPCHK(hipGraphInstantiate(&X->gexec, X->graph, nullptr, nullptr, 0));
+      }
+      for (int i = 0; i < k; ++i) HIPCHK(hipGraphLaunch(X->gexec, X->stream));
+    } else {
+      for (int i = 0; i < k; ++i)
+        for (Instance& I : X->insts) enqueue_iteration(*X, I);
+      HIPCHK(hipGetLastError());
+    }
+  }
+  if (last_loss) {
+    bool bad = false;
+    for (size_t i = 0; i < X->insts.size(); ++i) {
+      IterState h;
+      HIPCHK(hipMemcpyAsync(&h, X->insts[i].it, sizeof(h), hipMemcpyDeviceToHost, X->stream));
+      HIPCHK(hipStreamSynchronize(X->stream));
+      last_loss[i] = h.loss;
+      if (h.nonfinite) bad = true;
+    }
+    if (bad) return fail(D2IP_ENONFINITE, "a non-finite loss was produced");
+  }
+  return D2IP_OK;
+}
+
+d2ip_status d2ip_read_image(d2ip_ctx* X, int inst, float* sigma, int on_device) {
+  d2ip_status st = check_inst(X, inst);
+  if (st != D2IP_OK) return st;
+  if (!sigma) return fail(D2IP_EINVAL, "null output");
+  Instance& I = X->insts[inst];
+  if (!X->geos[I.geo].set) return fail(D2IP_ESTATE, "geometry not set");
+  if (!I.has_z) return fail(D2IP_ESTATE, "noise input not set");
+  enqueue_forward(*X, I);
+  HIPCHK(hipGetLastError());
+  return copy_out(X, sigma, I.sigma, I.V0 * sizeof(float), on_device);
+}
+
+}  // extern "C"

@@ -1,0 +1,280 @@
+// Linearised measurement operator (Eq. (1)), the data term of the loss
+// (Eq. (4), mean-squared form), the output head and the fused Adam update.
+//
+// J is stored compacted to the voxels of the imaging region (M x qa_pad,
+// row-major, zero-padded columns): the products J sigma and J^T g each stream
+// it once from HBM with 16-byte loads; sums over column or row blocks land in
+// partial buffers that a second pass reduces in a fixed order.
+#include "kernels.h"
+
+namespace d2ip {
+namespace {
+
+__global__ void k_gather_columns(const float* __restrict__ J, int M, int Q,
+                                 const int* __restrict__ idx, int qa, int qa_pad,
+                                 float* __restrict__ Jc) {
+  const size_t total = (size_t)M * qa_pad;
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < total;
+       i += (size_t)gridDim.x * blockDim.x) {
+    const int q = (int)(i % qa_pad);
+    const size_t m = i / qa_pad;
+    Jc[i] = q < qa ? J[m * Q + idx[q]] : 0.f;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_jvec(const float* __restrict__ Jc, int M, int qa_pad,
+                                              const int* __restrict__ idx,
+                                              const float* __restrict__ sigma,
+                                              float* __restrict__ ppart) {
+  __shared__ __align__(16) float sv[kJvecCols];
+  const int q0 = blockIdx.x * kJvecCols;
+  const int qn = min(kJvecCols, qa_pad - q0);
+  for (int q = threadIdx.x; q < kJvecCols; q += 256) sv[q] = q < qn ? sigma[idx[q0 + q]] : 0.f;
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int r = wave; r < kJvecRows; r += 4) {
+    const int m = blockIdx.y * kJvecRows + r;
+    if (m >= M) break;
+    const float* row = Jc + (size_t)m * qa_pad + q0;
+    float acc = 0.f;
+    for (int j = lane * 4; j < qn; j += 256) {
+      const float4 jv = *reinterpret_cast<const float4*>(row + j);
+      const float4 s = *reinterpret_cast<const float4*>(sv + j);
+      acc += jv.x * s.x + jv.y * s.y + jv.z * s.z + jv.w * s.w;
+    }
+    acc = wave_sum(acc);
+    if (lane == 0) ppart[(size_t)blockIdx.x * M + m] = acc;
+  }
+}
+
+__global__ void k_data_loss(const float* __restrict__ ppart, int nqb, const float* __restrict__ dv,
+                            int M, float* __restrict__ gp, IterState* it, float beta1,
+                            float beta2) {
+  __shared__ double sh[16];
+  double s = 0.0;
+  const float scale = 2.f / (float)M;
+  for (int m = threadIdx.x; m < M; m += blockDim.x) {
+    float p = 0.f;
+    for (int k = 0; k < nqb; ++k) p += ppart[(size_t)k * M + m];
+    const float r = p - dv[m];
+    gp[m] = scale * r;
+    s += (double)r * r;
+  }
+  s = block_sum(s, sh);
+  if (threadIdx.x == 0) {
+    const double L = s / M;
+    it->loss = L;
+    if (!isfinite(L)) it->nonfinite = 1;
+    const int t = it->t + 1;
+    it->t = t;
+    it->bc1 = (float)(1.0 - pow((double)beta1, (double)t));
+    it->bc2 = (float)(1.0 - pow((double)beta2, (double)t));
+  }
+}
+
+__global__ __launch_bounds__(256) void k_jtvec(const float* __restrict__ Jc, int M, int qa_pad,
+                                               const float* __restrict__ gp,
+                                               float* __restrict__ tpart) {
+  __shared__ float gs[kJtRows];
+  const int m0 = blockIdx.y * kJtRows;
+  const int mn = min(kJtRows, M - m0);
+  if (threadIdx.x < kJtRows) gs[threadIdx.x] = threadIdx.x < mn ? gp[m0 + threadIdx.x] : 0.f;
+  __syncthreads();
+  const int q = (blockIdx.x * 256 + threadIdx.x) * 4;
+  if (q >= qa_pad) return;
+  float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+  const float* base = Jc + (size_t)m0 * qa_pad + q;
+#pragma unroll 8
+  for (int r = 0; r < mn; ++r) {
+    const float4 jv = *reinterpret_cast<const float4*>(base + (size_t)r * qa_pad);
+    const float g = gs[r];
+    acc.x += jv.x * g;
+    acc.y += jv.y * g;
+    acc.z += jv.z * g;
+    acc.w += jv.w * g;
+  }
+  *reinterpret_cast<float4*>(tpart + (size_t)blockIdx.y * qa_pad + q) = acc;
+}
+
+__global__ void k_tail_fwd(const float* __restrict__ d0, int C, const float* __restrict__ w,
+                           const float* __restrict__ b, const float* __restrict__ mask, size_t V,
+                           float* __restrict__ sigma) {
+  for (size_t v = blockIdx.x * (size_t)blockDim.x + threadIdx.x; v < V;
+       v += (size_t)gridDim.x * blockDim.x) {
+    const float4* row = reinterpret_cast<const float4*>(d0 + v * C);
+    float acc = b[0];
+    for (int c4 = 0; c4 < C / 4; ++c4) {
+      const float4 x = row[c4];
+      acc += w[4 * c4] * x.x + w[4 * c4 + 1] * x.y + w[4 * c4 + 2] * x.z + w[4 * c4 + 3] * x.w;
+    }
+    sigma[v] = mask[v] * acc;
+  }
+}
+
+constexpr int kTailVoxels = 256;
+
+__global__ __launch_bounds__(256) void k_tail_bwd(const float* __restrict__ tpart, int nmb,
+                                                  int qa_pad, const int* __restrict__ inv,
+                                                  const float* __restrict__ d0, int C,
+                                                  const float* __restrict__ w, size_t V,
+                                                  float* __restrict__ gd0,
+                                                  double* __restrict__ part) {
+  __shared__ float gsv[kTailVoxels];
+  __shared__ double sh[256];
+  const int tid = threadIdx.x;
+  const size_t v0 = (size_t)blockIdx.x * kTailVoxels;
+  {
+    const size_t v = v0 + tid;
+    float g = 0.f;
+    if (v < V) {
+      const int q = inv[v];
+      if (q >= 0)
+        for (int k = 0; k < nmb; ++k) g += tpart[(size_t)k * qa_pad + q];
+    }
+    gsv[tid] = g;
+  }
+  __syncthreads();
+  // channel-major sweep: thread (c, r0) covers voxels r0, r0 + 256/C, ...
+  const int c = tid % C, r0 = tid / C, rpi = 256 / C;
+  const float wc = w[c];
+  double s = 0.0;
+  for (int r = r0; r < kTailVoxels; r += rpi) {
+    const size_t v = v0 + r;
+    if (v >= V) break;
+    const float g = gsv[r];
+    gd0[v * C + c] = g * wc;
+    s += (double)g * d0[v * C + c];
+  }
+  sh[tid] = s;
+  __syncthreads();
+  const size_t pb = (size_t)blockIdx.x * (C + 1);
+  if (tid < C) {
+    double a = 0.0;
+    for (int k = tid; k < 256; k += C) a += sh[k];
+    part[pb + tid] = a;
+  }
+  __syncthreads();
+  sh[tid] = gsv[tid];
+  __syncthreads();
+  if (tid == 0) {
+    double a = 0.0;
+    for (int k = 0; k < kTailVoxels; ++k) a += sh[k];
+    part[pb + C] = a;
+  }
+}
+
+__global__ void k_reduce_cols(const double* __restrict__ part, int nparts, int K,
+                              float* __restrict__ dst) {
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < K; k += gridDim.x * blockDim.x) {
+    double s = 0.0;
+    for (int i = 0; i < nparts; ++i) s += part[(size_t)i * K + k];
+    dst[k] = (float)s;
+  }
+}
+
+__global__ void k_adam(float* __restrict__ theta, const float* __restrict__ g,
+                       float* __restrict__ m, float* __restrict__ v, size_t P, float lr,
+                       float beta1, float beta2, float eps, const IterState* __restrict__ it) {
+  const float bc1 = it->bc1, bc2 = it->bc2;
+  const float step = lr / bc1;
+  const float rs2 = 1.f / sqrtf(bc2);
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < P;
+       i += (size_t)gridDim.x * blockDim.x) {
+    const float gi = g[i];
+    const float mi = beta1 * m[i] + (1.f - beta1) * gi;
+    const float vi = beta2 * v[i] + (1.f - beta2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    theta[i] -= step * mi / (sqrtf(vi) * rs2 + eps);
+  }
+}
+
+__global__ void k_pack_weights(const ConvPack* __restrict__ packs, const float* __restrict__ theta,
+                               float* __restrict__ wf32, uint16_t* __restrict__ wbf16) {
+  const ConvPack pk = packs[blockIdx.y];
+  const int per_co = pk.cin_real * pk.taps;
+  const int total = pk.cout * per_co;
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < total; e += gridDim.x * blockDim.x) {
+    const int co = e / per_co;
+    const int rem = e - co * per_co;
+    const int ci = rem / pk.taps;
+    const int tap = rem - ci * pk.taps;
+    const float val = theta[pk.th_off + e];
+    const long long fi = pk.wf_off + ((long long)co * pk.taps + tap) * pk.cin + ci;
+    if (wf32) wf32[fi] = val;
+    if (wbf16) wbf16[fi] = f2bf(val);
+    if (pk.need_dgrad) {
+      const long long di =
+          pk.wd_off + ((long long)ci * pk.taps + (pk.taps - 1 - tap)) * pk.cout + co;
+      if (wf32) wf32[di] = val;
+      if (wbf16) wbf16[di] = f2bf(val);
+    }
+  }
+}
+
+inline int grid_for(size_t work) {
+  size_t b = (work + 255) / 256;
+  if (b > 8192) b = 8192;
+  if (b < 1) b = 1;
+  return (int)b;
+}
+
+}  // namespace
+
+void gather_columns(const float* J, int M, int Q, const int* idx, int qa, int qa_pad, float* Jc,
+                    hipStream_t s) {
+  hipLaunchKernelGGL(k_gather_columns, dim3(grid_for((size_t)M * qa_pad)), dim3(256), 0, s, J, M,
+                     Q, idx, qa, qa_pad, Jc);
+}
+
+void jvec(const float* Jc, int M, int qa_pad, const int* idx, const float* sigma, float* ppart,
+          hipStream_t s) {
+  dim3 grid(jvec_qblocks(qa_pad), (M + kJvecRows - 1) / kJvecRows);
+  hipLaunchKernelGGL(k_jvec, grid, dim3(256), 0, s, Jc, M, qa_pad, idx, sigma, ppart);
+}
+
+void data_loss(const float* ppart, int nqb, const float* dv, int M, float* gp, IterState* it,
+               float beta1, float beta2, hipStream_t s) {
+  hipLaunchKernelGGL(k_data_loss, dim3(1), dim3(256), 0, s, ppart, nqb, dv, M, gp, it, beta1,
+                     beta2);
+}
+
+void jtvec(const float* Jc, int M, int qa_pad, const float* gp, float* tpart, hipStream_t s) {
+  dim3 grid((qa_pad / 4 + 255) / 256, jt_mblocks(M));
+  hipLaunchKernelGGL(k_jtvec, grid, dim3(256), 0, s, Jc, M, qa_pad, gp, tpart);
+}
+
+void tail_fwd(const float* d0, int C, const float* w, const float* b, const float* mask, size_t V,
+              float* sigma, hipStream_t s) {
+  hipLaunchKernelGGL(k_tail_fwd, dim3(grid_for(V)), dim3(256), 0, s, d0, C, w, b, mask, V, sigma);
+}
+
+int tail_bwd_blocks(size_t V, int C) {
+  (void)C;
+  return (int)((V + kTailVoxels - 1) / kTailVoxels);
+}
+
+void tail_bwd(const float* tpart, int nmb, int qa_pad, const int* inv, const float* d0, int C,
+              const float* w, size_t V, float* gd0, double* part, hipStream_t s) {
+  hipLaunchKernelGGL(k_tail_bwd, dim3(tail_bwd_blocks(V, C)), dim3(256), 0, s, tpart, nmb, qa_pad,
+                     inv, d0, C, w, V, gd0, part);
+}
+
+void reduce_cols(const double* part, int nparts, int K, float* dst, hipStream_t s) {
+  hipLaunchKernelGGL(k_reduce_cols, dim3((K + 255) / 256), dim3(256), 0, s, part, nparts, K, dst);
+}
+
+void adam(float* theta, const float* g, float* m, float* v, size_t P, float lr, float beta1,
+          float beta2, float eps, const IterState* it, hipStream_t s) {
+  hipLaunchKernelGGL(k_adam, dim3(grid_for(P)), dim3(256), 0, s, theta, g, m, v, P, lr, beta1,
+                     beta2, eps, it);
+}
+
+void pack_weights(const ConvPack* packs, int npacks, int max_elems, const float* theta,
+                  float* wf32, uint16_t* wbf16, hipStream_t s) {
+  dim3 grid((max_elems + 255) / 256, npacks);
+  if (grid.x > 1024) grid.x = 1024;
+  hipLaunchKernelGGL(k_pack_weights, grid, dim3(256), 0, s, packs, theta, wf32, wbf16);
+}
+
+}  // namespace d2ip

@@ -1,0 +1,84 @@
+"""Write oracle trajectories used as stored expected values by the GPU tests.
+
+Calls only the FP64 oracle and the seeded input generator.  For a problem it
+stores the recorded losses, the image at checkpoint iterations, and the
+SHA-256 of the FP32 inputs so a test can detect a generator drift on another
+machine.  With --floor it also runs the oracle from theta_0 moved by one FP32
+ulp per entry (random direction) and stores those images: the distance
+between the two trajectories is the sensitivity floor that FP32 rounding
+alone can cause.
+
+    python tests/golden/make_golden.py c1 --iters 500 --floor
+"""
+import argparse
+import hashlib
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
+
+import tseit_synth as ts  # noqa: E402
+from oracle import fit  # noqa: E402
+
+
+def sha(a):
+    return hashlib.sha256(np.ascontiguousarray(a).tobytes()).hexdigest()
+
+
+def ulp_perturb(theta, seed=12345):
+    r = np.random.default_rng(seed)
+    to = np.where(r.random(theta.size) < 0.5, np.inf, -np.inf).astype(np.float32)
+    return np.nextafter(theta.astype(np.float32), to).astype(np.float32)
+
+
+def trajectory(pr, theta0, dv, iters, lr, checkpoints, log=None):
+    st = fit.State(theta0)
+    losses, images = [], {}
+    done = 0
+    t0 = time.time()
+    for c in sorted(checkpoints):
+        losses += fit.run(pr, st, dv, c - done, lr)
+        done = c
+        images[c] = pr.image(st.theta)
+        if log:
+            log("iter %d loss %.6e  (%.0f s)" % (c, losses[-1], time.time() - t0))
+    return np.array(losses), images
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("config", choices=["c0", "c1"])
+    ap.add_argument("--iters", type=int, default=None)
+    ap.add_argument("--floor", action="store_true")
+    ap.add_argument("--out", default=None)
+    a = ap.parse_args()
+    cfg = ts.CONFIGS[a.config]
+    iters = a.iters or cfg["iters"]
+    cps = sorted({c for c in (1, 5, 10, 20, 50, 100, 200, 300, 500, 1000) if c <= iters} | {iters})
+    p = ts.make_problem(cfg["n"], cfg["rings"], cfg["levels"], cfg["base_ch"], cfg["seed"])
+    pr = fit.Problem(p["J"], p["mask"], p["Z"], cfg["n"], cfg["levels"], cfg["base_ch"])
+
+    def log(m):
+        print(m, flush=True)
+
+    out = dict(config=a.config, iters=iters, lr=cfg["lr"], checkpoints=np.array(cps),
+               sha_J=sha(p["J"]), sha_Z=sha(p["Z"]), sha_theta0=sha(p["theta0"]),
+               sha_dv=sha(p["dv"]))
+    losses, imgs = trajectory(pr, p["theta0"], p["dv"][0], iters, cfg["lr"], cps, log)
+    out["losses"] = losses
+    out["images"] = np.stack([imgs[c] for c in cps])
+    if a.floor:
+        fl, fimgs = trajectory(pr, ulp_perturb(p["theta0"]), p["dv"][0], iters, cfg["lr"], cps, log)
+        out["floor_losses"] = fl
+        out["floor_images"] = np.stack([fimgs[c] for c in cps])
+    path = a.out or os.path.join(HERE, "oracle_%s_%d.npz" % (a.config, iters))
+    np.savez_compressed(path, **out)
+    log("wrote " + path)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,86 @@
+"""Host-side checks of the C-ABI library: it loads, exports every function the
+header declares, and its host-only entry points validate their arguments.
+No compute call is made (no GPU needed)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import tseit_synth as ts
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "d2ip.h")
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_2507_14046_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.skip("libd2ip.so not built")
+    _lib.load()
+    return _lib
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(d2ip_[a-z_]+)\s*\(", src)))
+
+
+def test_every_declared_symbol_is_exported(L):
+    lib = ctypes.CDLL(L.LIB_PATH)
+    names = declared_functions()
+    assert len(names) >= 17
+    for name in names:
+        assert hasattr(lib, name), name
+    # and the binding declares a signature for each compute entry point
+    for name in names:
+        if name != "d2ip_last_error":
+            assert name in L.SIGNATURES, name
+
+
+@pytest.mark.parametrize("L_,C", [(2, 8), (3, 16), (4, 32), (3, 8), (2, 16), (5, 16)])
+def test_param_count_matches_generator(L, L_, C):
+    from paper_2507_14046_amd import param_count
+    assert param_count(L_, C) == ts.param_count(L_, C)
+
+
+def test_workspace_bytes_and_validation(L):
+    from paper_2507_14046_amd import workspace_bytes, D2ipError
+    b1 = workspace_bytes([(32, 928)], [(0, 3, 16)])
+    b2 = workspace_bytes([(32, 928)], [(0, 3, 16), (0, 3, 16)])
+    assert b1 > 121 * 2 ** 20          # at least the J buffer
+    assert b2 > b1
+    assert b1 % 256 == 0
+    assert workspace_bytes([(32, 928)], [(0, 3, 16)], precision="bf16") > 0
+    bad = [
+        ([(32, 928)], [(0, 1, 16)]),      # levels < 2
+        ([(32, 928)], [(0, 3, 12)]),      # base_ch not 8/16/32
+        ([(30, 928)], [(0, 3, 16)]),      # 30 not divisible by 4
+        ([(32, 928)], [(1, 3, 16)]),      # bad geometry index
+        ([(32, 0)], [(0, 3, 16)]),        # M = 0
+        ([(8, 10)], [(0, 3, 16)]),        # coarsest level 2^3 -> 2 ok? 8/4 = 2 -> fine
+    ]
+    for geos, insts in bad[:-1]:
+        with pytest.raises(D2ipError) as e:
+            workspace_bytes(geos, insts)
+        assert e.value.status == L.EINVAL
+        assert len(L.load().d2ip_last_error()) > 0
+    assert workspace_bytes(*bad[-1]) > 0
+    with pytest.raises(ValueError):
+        workspace_bytes([(32, 928)], [(0, 3, 16)], precision="fp8")
+
+
+def test_null_pointer_errors(L):
+    lib = L.load()
+    assert lib.d2ip_param_count(3, 16, None) == L.EINVAL
+    assert lib.d2ip_run(None, 1, None) == L.EINVAL
+    assert lib.d2ip_read_image(None, 0, None, 0) == L.EINVAL
+    assert lib.d2ip_destroy(None) == L.OK
+    out = ctypes.c_void_p()
+    g = (L.GeometryDesc * 1)(L.GeometryDesc(16, 208))
+    i = (L.InstanceDesc * 1)(L.InstanceDesc(0, 2, 8))
+    # null workspace
+    assert lib.d2ip_create(g, 1, i, 1, 0, 0, None, 0, None, ctypes.byref(out)) == L.EINVAL
+    assert b"workspace" in lib.d2ip_last_error()
