@@ -64,9 +64,15 @@ typedef enum {
   D2IP_ENONFINITE = -5  /* a non-finite loss was produced                    */
 } d2ip_status;
 
-/* Operand precision of the convolutions; accumulation is always FP32 and the
- * J products, LayerNorm, loss and Adam are FP32 (loss reduced in FP64). */
-typedef enum { D2IP_PLAIN_FP32 = 0, D2IP_BF16_CONV = 1 } d2ip_precision;
+/* Operand precision of the convolutions (forward, input gradient and weight
+ * gradient); accumulation is always FP32, and the J products, LayerNorm, loss
+ * and Adam are FP32 (the loss reduced in FP64).
+ *   D2IP_PLAIN_FP32   FP32 operands (FP32 matrix-core instructions)
+ *   D2IP_BF16_CONV    operands rounded to bfloat16 (one BF16 MFMA per product)
+ *   D2IP_BF16X3_CONV  each FP32 operand split into bf16 hi + bf16 lo; products
+ *                     hi*hi + hi*lo + lo*hi on three BF16 MFMAs (relative
+ *                     product error near 2^-16) */
+typedef enum { D2IP_PLAIN_FP32 = 0, D2IP_BF16_CONV = 1, D2IP_BF16X3_CONV = 2 } d2ip_precision;
 
 /* d2ip_create flags */
 #define D2IP_FLAG_GRAPH 1u /* capture one iteration in a hipGraph, replay it */
@@ -154,6 +160,25 @@ d2ip_status d2ip_run(d2ip_ctx* ctx, int k, double* last_loss);
 /* Gradient dL/dtheta of the data loss computed by the last iteration of
  * `inst` (before that iteration's Adam update), flat order, n = P floats. */
 d2ip_status d2ip_get_grad(d2ip_ctx* ctx, int inst, float* grad, size_t n, int on_device);
+
+/* Kernels d2ip_time_kernel can time in isolation. */
+typedef enum {
+  D2IP_KERNEL_JVEC = 0,        /* p = J d_sigma (streams J once)                  */
+  D2IP_KERNEL_JTVEC = 1,       /* J^T g (streams J once)                          */
+  D2IP_KERNEL_ADAM = 2,        /* fused Adam over all parameters (updates state!) */
+  D2IP_KERNEL_CONV_FWD = 3,    /* forward of conv1 of block `block`               */
+  D2IP_KERNEL_CONV_DGRAD = 4,  /* input gradient of that conv                     */
+  D2IP_KERNEL_CONV_WGRAD = 5   /* weight gradient of that conv (+ its reduction)  */
+} d2ip_kernel;
+
+/* Benchmark helper: launch kernel `which` of instance `inst` `reps` times on
+ * the context stream (after one untimed launch) and store the mean duration
+ * per launch in ms, measured with HIP events.  `block` indexes the ResBlocks
+ * in flat order (enc_0.., dec_{L-2}..dec_0) for the conv kernels.  Must
+ * follow at least one d2ip_run (buffers hold that iteration's data).  The
+ * Adam variant advances theta and the moments. */
+d2ip_status d2ip_time_kernel(d2ip_ctx* ctx, int inst, int which, int block, int reps,
+                             double* avg_ms);
 
 /* Image of `inst` at its current theta: mask * phi(theta | Z), n^3 FP32 (Eq. (5)). */
 d2ip_status d2ip_read_image(d2ip_ctx* ctx, int inst, float* sigma, int on_device);

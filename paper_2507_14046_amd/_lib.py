@@ -11,8 +11,9 @@ LIB_PATH = os.path.join(_HERE, "libd2ip.so")
 
 OK, EINVAL, ENOMEM, EHIP, ESTATE, ENONFINITE = 0, -1, -2, -3, -4, -5
 STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "ESTATE", -5: "ENONFINITE"}
-PLAIN_FP32, BF16_CONV = 0, 1
+PLAIN_FP32, BF16_CONV, BF16X3_CONV = 0, 1, 2
 FLAG_GRAPH = 1
+KERNEL_JVEC, KERNEL_JTVEC, KERNEL_ADAM, KERNEL_CONV_FWD, KERNEL_CONV_DGRAD, KERNEL_CONV_WGRAD = range(6)
 
 
 class GeometryDesc(ctypes.Structure):
@@ -58,6 +59,7 @@ SIGNATURES = {
     "d2ip_set_state": [_vp, _i, _vp, ctypes.c_int64, _i],
     "d2ip_run": [_vp, _i, ctypes.POINTER(ctypes.c_double)],
     "d2ip_read_image": [_vp, _i, _vp, _i],
+    "d2ip_time_kernel": [_vp, _i, _i, _i, _i, ctypes.POINTER(ctypes.c_double)],
 }
 
 _lib = None

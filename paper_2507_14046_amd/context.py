@@ -39,7 +39,9 @@ def _prec(p):
         return L.PLAIN_FP32
     if p in ("bf16", L.BF16_CONV):
         return L.BF16_CONV
-    raise ValueError("precision must be 'fp32' or 'bf16'")
+    if p in ("bf16x3", L.BF16X3_CONV):
+        return L.BF16X3_CONV
+    raise ValueError("precision must be 'fp32', 'bf16' or 'bf16x3'")
 
 
 def _is_torch(x):
@@ -174,6 +176,12 @@ class Context:
         img = np.empty(n ** 3, dtype=np.float32)
         L.check(self._lib.d2ip_read_image(self._ctx, inst, img.ctypes.data_as(ctypes.c_void_p), 0))
         return img
+
+    def time_kernel(self, inst, which, block=0, reps=20):
+        """Mean ms per launch of one kernel (see d2ip_time_kernel)."""
+        ms = ctypes.c_double()
+        L.check(self._lib.d2ip_time_kernel(self._ctx, inst, which, block, reps, ctypes.byref(ms)))
+        return ms.value
 
     # -- convenience ----------------------------------------------------------
     def load_problem(self, inst, prob, frame=0, set_geometry=True):

@@ -1,390 +1,9 @@
-// 3D convolutions of the image prior (3x3x3 and 1x1x1, zero padding) as
-// implicit GEMMs on the gfx950 matrix cores.
-//
-// Forward / input-gradient kernel: the GEMM rows are output voxels of a
-// TZ x TY x TX spatial tile, the columns are output channels, the reduction
-// runs over (tap, input channel).  Each block stages the input halo of its tile
-// for a chunk of CK channels in LDS (applying the LayerNorm+ReLU of the
-// producing layer on the fly when asked), then every wave issues 16x16 MFMAs:
-// v_mfma_f32_16x16x4_f32 (FP32 operands) or v_mfma_f32_16x16x32_bf16 (BF16
-// operands, rounded to nearest even while staging); accumulation is FP32.
-// The epilogue adds bias / residual, stores, and emits per-block (sum, sumsq)
-// partials in FP64 for the following whole-volume LayerNorm.
-//
-// Weight-gradient kernel: rows are output channels, columns (tap, channel),
-// the reduction runs over voxels; blocks split the voxel range and write
-// partial sums that a second kernel reduces in a fixed order (deterministic).
-#include <type_traits>
-
-#include "kernels.h"
+// Conv entry points: mode dispatch, launch-shape helpers and the deterministic
+// reduction of weight-gradient partials.
+#include "conv_impl.h"
 
 namespace d2ip {
 namespace {
-
-template <int TILE>
-struct TileDims;
-template <>
-struct TileDims<TILE_2x4x16> {
-  static constexpr int Z = 2, Y = 4, X = 16;
-};
-template <>
-struct TileDims<TILE_2x8x8> {
-  static constexpr int Z = 2, Y = 8, X = 8;
-};
-
-__device__ __forceinline__ float ln_relu(float h, float mean, float rstd, float g, float b) {
-  float v = g * ((h - mean) * rstd) + b;
-  return v > 0.f ? v : 0.f;
-}
-
-template <bool BF>
-struct Frag;
-template <>
-struct Frag<false> {
-  using T = float;
-};
-template <>
-struct Frag<true> {
-  using T = bf16x8;
-};
-
-__device__ __forceinline__ f32x4 mfma(float a, float b, f32x4 c) {
-  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
-}
-__device__ __forceinline__ f32x4 mfma(bf16x8 a, bf16x8 b, f32x4 c) {
-  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
-}
-
-// Stage a (HZ x HY x HX) halo of CK channels starting at ci0 into LDS.
-template <bool BF, int CK, int HZ, int HY, int HX, int CKP, int PRO>
-__device__ __forceinline__ void stage_halo(typename std::conditional<BF, uint16_t, float>::type* hal,
-                                           const float* __restrict__ x, int n, int cin_stride,
-                                           int ci0, int z0, int y0, int x0, int R,
-                                           const LnStat* ln, const float* lng, const float* lnb) {
-  constexpr int Q = CK / 4;
-  constexpr int HP = HZ * HY * HX;
-  float mean = 0.f, rstd = 1.f;
-  if (PRO == PRO_LN_RELU) {
-    mean = ln->mean;
-    rstd = ln->rstd;
-  }
-  for (int p = threadIdx.x; p < HP * Q; p += 256) {
-    const int pos = p / Q, q = p - pos * Q;
-    const int hx = pos % HX, hy = (pos / HX) % HY, hz = pos / (HX * HY);
-    const int gz = z0 + hz - R, gy = y0 + hy - R, gx = x0 + hx - R;
-    float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-    if (gz >= 0 && gz < n && gy >= 0 && gy < n && gx >= 0 && gx < n) {
-      const int c = ci0 + 4 * q;
-      v = *reinterpret_cast<const float4*>(x + (size_t)((gz * n + gy) * n + gx) * cin_stride + c);
-      if (PRO == PRO_LN_RELU) {
-        v.x = ln_relu(v.x, mean, rstd, lng[c + 0], lnb[c + 0]);
-        v.y = ln_relu(v.y, mean, rstd, lng[c + 1], lnb[c + 1]);
-        v.z = ln_relu(v.z, mean, rstd, lng[c + 2], lnb[c + 2]);
-        v.w = ln_relu(v.w, mean, rstd, lng[c + 3], lnb[c + 3]);
-      }
-    }
-    if constexpr (BF) {
-      uint2 pk;
-      pk.x = (uint32_t)f2bf(v.x) | ((uint32_t)f2bf(v.y) << 16);
-      pk.y = (uint32_t)f2bf(v.z) | ((uint32_t)f2bf(v.w) << 16);
-      *reinterpret_cast<uint2*>(hal + pos * CKP + 4 * q) = pk;
-    } else {
-      float* d = hal + pos * CKP + 4 * q;
-      d[0] = v.x;
-      d[1] = v.y;
-      d[2] = v.z;
-      d[3] = v.w;
-    }
-  }
-}
-
-__device__ __forceinline__ int tap_offset(int tap, int HY, int HX) {
-  const int dz = tap / 9, dy = (tap / 3) % 3, dx = tap % 3;
-  return (dz * HY + dy) * HX + dx;
-}
-
-template <bool BF, int TAPS, int CK, int TILE, int BN, int PRO>
-__global__ __launch_bounds__(256) void k_conv_fwd(ConvFwd a) {
-  using TD = TileDims<TILE>;
-  constexpr int TZ = TD::Z, TY = TD::Y, TX = TD::X;
-  constexpr int R = TAPS == 27 ? 1 : 0;
-  constexpr int HZ = TZ + 2 * R, HY = TY + 2 * R, HX = TX + 2 * R, HP = HZ * HY * HX;
-  constexpr int KPL = BF ? 8 : 1;
-  constexpr int KSTEP = 4 * KPL;
-  constexpr int NSTEP = (TAPS * CK + KSTEP - 1) / KSTEP;
-  constexpr bool KEXACT = (TAPS * CK) % KSTEP == 0;
-  constexpr int CKP = BF ? CK + 8 : CK + 1;
-  using ST = typename std::conditional<BF, uint16_t, float>::type;
-  using FT = typename Frag<BF>::T;
-  constexpr int BM = TZ * TY * TX, MT = BM / 16, MTW = MT / 4, NT = BN / 16;
-  static_assert(MT % 4 == 0, "tile must hold a multiple of 64 voxels");
-  __shared__ __align__(16) ST hal[HP * CKP];
-  __shared__ double red[8];
-
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int l16 = lane & 15, g = lane >> 4;
-  const int n = a.n;
-  const int ntx = (n + TX - 1) / TX, nty = (n + TY - 1) / TY;
-  int b = blockIdx.x;
-  const int x0 = (b % ntx) * TX;
-  b /= ntx;
-  const int y0 = (b % nty) * TY;
-  b /= nty;
-  const int z0 = b * TZ;
-  const int co0 = blockIdx.y * BN;
-
-  f32x4 acc[MTW][NT];
-#pragma unroll
-  for (int i = 0; i < MTW; ++i)
-#pragma unroll
-    for (int j = 0; j < NT; ++j) acc[i][j] = (f32x4){0.f, 0.f, 0.f, 0.f};
-
-  int apos[MTW];
-#pragma unroll
-  for (int mt = 0; mt < MTW; ++mt) {
-    const int li = (wave * MTW + mt) * 16 + l16;
-    const int tz = li / (TY * TX), ty = (li / TX) % TY, tx = li % TX;
-    apos[mt] = (tz * HY + ty) * HX + tx;
-  }
-
-  const ST* __restrict__ W = reinterpret_cast<const ST*>(a.w);
-  for (int ci0 = 0; ci0 < a.cin; ci0 += CK) {
-    stage_halo<BF, CK, HZ, HY, HX, CKP, PRO>(hal, a.x, n, a.cin_stride, ci0, z0, y0, x0, R, a.ln,
-                                             a.ln_g, a.ln_b);
-    __syncthreads();
-#pragma unroll 2
-    for (int step = 0; step < NSTEP; ++step) {
-      const int kl = step * KSTEP + g * KPL;
-      const int tap = kl / CK, c = kl - tap * CK;
-      const bool kv = KEXACT || tap < TAPS;
-      const int toff = TAPS == 27 ? tap_offset(tap, HY, HX) : 0;
-      FT A[MTW], B[NT];
-#pragma unroll
-      for (int mt = 0; mt < MTW; ++mt) {
-        if constexpr (BF) {
-          u32x4 v = {0u, 0u, 0u, 0u};
-          if (kv) v = *reinterpret_cast<const u32x4*>(hal + (apos[mt] + toff) * CKP + c);
-          A[mt] = __builtin_bit_cast(bf16x8, v);
-        } else {
-          A[mt] = kv ? hal[(apos[mt] + toff) * CKP + c] : 0.f;
-        }
-      }
-#pragma unroll
-      for (int nt = 0; nt < NT; ++nt) {
-        const int co = co0 + nt * 16 + l16;
-        const bool ok = kv && co < a.w_rows;
-        const size_t wi = ((size_t)co * TAPS + tap) * a.cin + ci0 + c;
-        if constexpr (BF) {
-          u32x4 v = {0u, 0u, 0u, 0u};
-          if (ok) v = *reinterpret_cast<const u32x4*>(W + wi);
-          B[nt] = __builtin_bit_cast(bf16x8, v);
-        } else {
-          B[nt] = ok ? W[wi] : 0.f;
-        }
-      }
-#pragma unroll
-      for (int mt = 0; mt < MTW; ++mt)
-#pragma unroll
-        for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = mfma(A[mt], B[nt], acc[mt][nt]);
-    }
-    __syncthreads();
-  }
-
-  double s1 = 0.0, s2 = 0.0;
-#pragma unroll
-  for (int mt = 0; mt < MTW; ++mt) {
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int li = (wave * MTW + mt) * 16 + 4 * g + r;
-      const int tz = li / (TY * TX), ty = (li / TX) % TY, tx = li % TX;
-      const int gz = z0 + tz, gy = y0 + ty, gx = x0 + tx;
-      if (gz >= n || gy >= n || gx >= n) continue;
-      const size_t vox = (size_t)(gz * n + gy) * n + gx;
-#pragma unroll
-      for (int nt = 0; nt < NT; ++nt) {
-        const int co = co0 + nt * 16 + l16;
-        if (co >= a.cout) continue;
-        const size_t o = vox * a.cout + co;
-        float v = acc[mt][nt][r];
-        if (a.bias) v += a.bias[co];
-        if (a.add) v += a.add[o];
-        if (a.accumulate) v += a.y[o];
-        a.y[o] = v;
-        s1 += v;
-        s2 += (double)v * v;
-      }
-    }
-  }
-  if (a.stat_part) {
-    s1 = block_sum(s1, red);
-    s2 = block_sum(s2, red);
-    if (tid == 0) {
-      const size_t pb = (size_t)blockIdx.y * gridDim.x + blockIdx.x;
-      a.stat_part[2 * pb] = s1;
-      a.stat_part[2 * pb + 1] = s2;
-    }
-  }
-}
-
-template <bool BF, int TAPS, int CK, int TILE, int PRO>
-__global__ __launch_bounds__(256) void k_conv_wgrad(ConvWgrad a) {
-  using TD = TileDims<TILE>;
-  constexpr int TZ = TD::Z, TY = TD::Y, TX = TD::X;
-  constexpr int R = TAPS == 27 ? 1 : 0;
-  constexpr int HZ = TZ + 2 * R, HY = TY + 2 * R, HX = TX + 2 * R;
-  constexpr int HP = HZ * HY * HX;
-  constexpr int KPL = BF ? 8 : 1;
-  constexpr int KSTEP = 4 * KPL;
-  constexpr int CKP = BF ? CK + 8 : CK + 1;
-  constexpr int BM = TZ * TY * TX;
-  constexpr int NTOT = TAPS * CK;
-  constexpr int NT = (NTOT + 15) / 16;
-  constexpr int NTW = (NT + 3) / 4;
-  constexpr int GP = BF ? BM + 8 : 17;  // g tile row pitch
-  using ST = typename std::conditional<BF, uint16_t, float>::type;
-  using FT = typename Frag<BF>::T;
-  __shared__ __align__(16) ST hal[HP * CKP];
-  // BF16: gs[co][voxel]; FP32: gs[voxel][co]
-  __shared__ __align__(16) ST gs[BF ? 16 * GP : BM * GP];
-  __shared__ float bred[256];
-
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int l16 = lane & 15, g = lane >> 4;
-  const int n = a.n;
-  const int ntx = (n + TX - 1) / TX, nty = (n + TY - 1) / TY, ntz = (n + TZ - 1) / TZ;
-  const int ntiles = ntx * nty * ntz;
-  const int ci0 = blockIdx.y * CK;
-  const int co0 = blockIdx.z * 16;
-  const bool do_bias = a.partb != nullptr && blockIdx.y == 0;
-
-  f32x4 acc[NTW];
-#pragma unroll
-  for (int j = 0; j < NTW; ++j) acc[j] = (f32x4){0.f, 0.f, 0.f, 0.f};
-  float bacc = 0.f;
-
-  for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
-    int b = t;
-    const int x0 = (b % ntx) * TX;
-    b /= ntx;
-    const int y0 = (b % nty) * TY;
-    b /= nty;
-    const int z0 = b * TZ;
-    stage_halo<BF, CK, HZ, HY, HX, CKP, PRO>(hal, a.x, n, a.cin_stride, ci0, z0, y0, x0, R, a.ln,
-                                             a.ln_g, a.ln_b);
-    // g tile: BM voxels x 16 output channels (zero outside the grid / cout)
-    for (int p = tid; p < BM * 4; p += 256) {
-      const int v = p >> 2, q = p & 3;
-      const int tz = v / (TY * TX), ty = (v / TX) % TY, tx = v % TX;
-      const int gz = z0 + tz, gy = y0 + ty, gx = x0 + tx;
-      const int co = co0 + 4 * q;
-      float4 val = make_float4(0.f, 0.f, 0.f, 0.f);
-      if (gz < n && gy < n && gx < n && co < a.cout)
-        val = *reinterpret_cast<const float4*>(a.g + ((size_t)(gz * n + gy) * n + gx) * a.cout + co);
-      if constexpr (BF) {
-        gs[(4 * q + 0) * GP + v] = f2bf(val.x);
-        gs[(4 * q + 1) * GP + v] = f2bf(val.y);
-        gs[(4 * q + 2) * GP + v] = f2bf(val.z);
-        gs[(4 * q + 3) * GP + v] = f2bf(val.w);
-      } else {
-        float* d = gs + v * GP + 4 * q;
-        d[0] = val.x;
-        d[1] = val.y;
-        d[2] = val.z;
-        d[3] = val.w;
-      }
-    }
-    __syncthreads();
-    // bias partial in FP32 from the unrounded gradient
-    if (do_bias) {
-      const int co = tid & 15;
-      if (co0 + co < a.cout) {
-        for (int v = tid >> 4; v < BM; v += 16) {
-          const int tz = v / (TY * TX), ty = (v / TX) % TY, tx = v % TX;
-          const int gz = z0 + tz, gy = y0 + ty, gx = x0 + tx;
-          if (gz < n && gy < n && gx < n)
-            bacc += a.g[((size_t)(gz * n + gy) * n + gx) * a.cout + co0 + co];
-        }
-      }
-    }
-#pragma unroll 2
-    for (int ks = 0; ks < BM / KSTEP; ++ks) {
-      FT A;
-      FT B[NTW];
-      if constexpr (BF) {
-        const int v0 = ks * KSTEP + g * KPL;
-        A = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u32x4*>(gs + l16 * GP + v0));
-#pragma unroll
-        for (int j = 0; j < NTW; ++j) {
-          const int nn = (wave + 4 * j) * 16 + l16;
-          uint16_t e[8];
-          if (nn < NTOT) {
-            const int tap = nn / CK, c = nn - tap * CK;
-            const int toff = TAPS == 27 ? tap_offset(tap, HY, HX) : 0;
-#pragma unroll
-            for (int q = 0; q < 8; ++q) {
-              const int v = v0 + q;
-              const int tz = v / (TY * TX), ty = (v / TX) % TY, tx = v % TX;
-              e[q] = hal[((tz * HY + ty) * HX + tx + toff) * CKP + c];
-            }
-          } else {
-#pragma unroll
-            for (int q = 0; q < 8; ++q) e[q] = 0;
-          }
-          u32x4 pk;
-          pk.x = (uint32_t)e[0] | ((uint32_t)e[1] << 16);
-          pk.y = (uint32_t)e[2] | ((uint32_t)e[3] << 16);
-          pk.z = (uint32_t)e[4] | ((uint32_t)e[5] << 16);
-          pk.w = (uint32_t)e[6] | ((uint32_t)e[7] << 16);
-          B[j] = __builtin_bit_cast(bf16x8, pk);
-        }
-      } else {
-        const int v = ks * KSTEP + g;
-        A = gs[v * GP + l16];
-        const int tz = v / (TY * TX), ty = (v / TX) % TY, tx = v % TX;
-        const int vp = (tz * HY + ty) * HX + tx;
-#pragma unroll
-        for (int j = 0; j < NTW; ++j) {
-          const int nn = (wave + 4 * j) * 16 + l16;
-          float e = 0.f;
-          if (nn < NTOT) {
-            const int tap = nn / CK, c = nn - tap * CK;
-            const int toff = TAPS == 27 ? tap_offset(tap, HY, HX) : 0;
-            e = hal[(vp + toff) * CKP + c];
-          }
-          B[j] = e;
-        }
-      }
-#pragma unroll
-      for (int j = 0; j < NTW; ++j) acc[j] = mfma(A, B[j], acc[j]);
-    }
-    __syncthreads();
-  }
-
-  const int cout16 = (a.cout + 15) & ~15;
-  float* part = a.part + (size_t)blockIdx.x * cout16 * TAPS * a.cin;
-#pragma unroll
-  for (int j = 0; j < NTW; ++j) {
-    const int nt = wave + 4 * j;
-    if (nt >= NT) continue;
-    const int nn = nt * 16 + l16;
-    if (nn >= NTOT) continue;
-    const int tap = nn / CK, c = nn - tap * CK;
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int co = co0 + 4 * g + r;
-      if (co < a.cout) part[((size_t)co * TAPS + tap) * a.cin + ci0 + c] = acc[j][r];
-    }
-  }
-  if (do_bias) {
-    bred[tid] = bacc;
-    __syncthreads();
-    if (tid < 16) {
-      float s = 0.f;
-      for (int k = tid; k < 256; k += 16) s += bred[k];
-      if (co0 + tid < a.cout) a.partb[(size_t)blockIdx.x * cout16 + co0 + tid] = s;
-    }
-  }
-}
 
 __global__ void k_wgrad_reduce(const float* __restrict__ part, const float* __restrict__ partb,
                                int splits, int cout, int taps, int cin, int cin_real, float* gw,
@@ -411,124 +30,24 @@ __global__ void k_wgrad_reduce(const float* __restrict__ part, const float* __re
   }
 }
 
-// ---------------------------------------------------------------------------
-// dispatch
-// ---------------------------------------------------------------------------
-
-inline void tile_dims(int tile, int& tz, int& ty, int& tx) {
-  if (tile == TILE_2x4x16) {
-    tz = 2; ty = 4; tx = 16;
-  } else {
-    tz = 2; ty = 8; tx = 8;
-  }
-}
-
-inline int spatial_tiles(int n, int tile) {
-  int tz, ty, tx;
-  tile_dims(tile, tz, ty, tx);
-  return ((n + tx - 1) / tx) * ((n + ty - 1) / ty) * ((n + tz - 1) / tz);
-}
-
-inline int pick_ck(int cin) {
-  if (cin % 32 == 0) return 32;
-  if (cin % 16 == 0) return 16;
-  return 8;
-}
-
-inline int pick_bn(int cout) {
-  if (cout <= 16) return 16;
-  if (cout <= 32) return 32;
-  return 64;
-}
-
-template <bool BF, int TAPS, int CK, int TILE, int BN, int PRO>
-void launch_fwd(const ConvFwd& a, hipStream_t s) {
-  dim3 grid(spatial_tiles(a.n, TILE), (a.cout + BN - 1) / BN);
-  hipLaunchKernelGGL((k_conv_fwd<BF, TAPS, CK, TILE, BN, PRO>), grid, dim3(256), 0, s, a);
-}
-
-template <bool BF, int TAPS, int CK, int TILE, int BN>
-void fwd_pro(const ConvFwd& a, hipStream_t s) {
-  if (a.prologue == PRO_LN_RELU && TAPS == 27)
-    launch_fwd<BF, TAPS, CK, TILE, BN, PRO_LN_RELU>(a, s);
-  else
-    launch_fwd<BF, TAPS, CK, TILE, BN, PRO_NONE>(a, s);
-}
-
-template <bool BF, int TAPS, int CK, int TILE>
-void fwd_bn(const ConvFwd& a, hipStream_t s) {
-  switch (pick_bn(a.cout)) {
-    case 16: fwd_pro<BF, TAPS, CK, TILE, 16>(a, s); break;
-    case 32: fwd_pro<BF, TAPS, CK, TILE, 32>(a, s); break;
-    default: fwd_pro<BF, TAPS, CK, TILE, 64>(a, s); break;
-  }
-}
-
-template <bool BF, int TAPS, int CK>
-void fwd_tile(const ConvFwd& a, hipStream_t s) {
-  if (a.tile == TILE_2x4x16)
-    fwd_bn<BF, TAPS, CK, TILE_2x4x16>(a, s);
-  else
-    fwd_bn<BF, TAPS, CK, TILE_2x8x8>(a, s);
-}
-
-template <bool BF, int TAPS>
-void fwd_ck(const ConvFwd& a, hipStream_t s) {
-  switch (pick_ck(a.cin)) {
-    case 32: fwd_tile<BF, TAPS, 32>(a, s); break;
-    case 16: fwd_tile<BF, TAPS, 16>(a, s); break;
-    default: fwd_tile<BF, TAPS, 8>(a, s); break;
-  }
-}
-
-template <bool BF, int TAPS, int CK, int TILE, int PRO>
-void launch_wg(const ConvWgrad& a, hipStream_t s) {
-  dim3 grid(a.splits, a.cin / CK, (a.cout + 15) / 16);
-  hipLaunchKernelGGL((k_conv_wgrad<BF, TAPS, CK, TILE, PRO>), grid, dim3(256), 0, s, a);
-}
-
-template <bool BF, int TAPS, int CK, int TILE>
-void wg_pro(const ConvWgrad& a, hipStream_t s) {
-  if (a.prologue == PRO_LN_RELU && TAPS == 27)
-    launch_wg<BF, TAPS, CK, TILE, PRO_LN_RELU>(a, s);
-  else
-    launch_wg<BF, TAPS, CK, TILE, PRO_NONE>(a, s);
-}
-
-template <bool BF, int TAPS, int CK>
-void wg_tile(const ConvWgrad& a, hipStream_t s) {
-  if (a.tile == TILE_2x4x16)
-    wg_pro<BF, TAPS, CK, TILE_2x4x16>(a, s);
-  else
-    wg_pro<BF, TAPS, CK, TILE_2x8x8>(a, s);
-}
-
-template <bool BF, int TAPS>
-void wg_ck(const ConvWgrad& a, hipStream_t s) {
-  switch (pick_ck(a.cin)) {
-    case 32: wg_tile<BF, TAPS, 32>(a, s); break;
-    case 16: wg_tile<BF, TAPS, 16>(a, s); break;
-    default: wg_tile<BF, TAPS, 8>(a, s); break;
-  }
-}
-
 }  // namespace
 
 int conv_fwd_blocks(const ConvFwd& a) {
-  return spatial_tiles(a.n, a.tile) * ((a.cout + pick_bn(a.cout) - 1) / pick_bn(a.cout));
+  const int bn = conv_detail::pick_bn(a.cout);
+  return conv_detail::spatial_tiles(a.n, a.tile) * ((a.cout + bn - 1) / bn);
 }
 
 void conv_fwd(const ConvFwd& a, hipStream_t s) {
-  if (a.prec == PREC_BF16) {
-    if (a.taps == 27) fwd_ck<true, 27>(a, s); else fwd_ck<true, 1>(a, s);
-  } else {
-    if (a.taps == 27) fwd_ck<false, 27>(a, s); else fwd_ck<false, 1>(a, s);
+  switch (a.prec) {
+    case PREC_BF16: conv_fwd_bf16(a, s); break;
+    case PREC_BF16X3: conv_fwd_bf16x3(a, s); break;
+    default: conv_fwd_f32(a, s); break;
   }
 }
 
 int conv_wgrad_splits(int n, int cin, int cout, int tile) {
-  const int per = (cin / pick_ck(cin)) * ((cout + 15) / 16);
-  const int tiles = spatial_tiles(n, tile);
+  const int per = (cin / conv_detail::pick_ck(cin)) * ((cout + 15) / 16);
+  const int tiles = conv_detail::spatial_tiles(n, tile);
   int s = (1024 + per - 1) / per;
   if (s > tiles) s = tiles;
   if (s < 1) s = 1;
@@ -541,10 +60,10 @@ size_t conv_wgrad_part_floats(int n, int cin, int cout, int taps, int tile) {
 }
 
 void conv_wgrad(const ConvWgrad& a, hipStream_t s) {
-  if (a.prec == PREC_BF16) {
-    if (a.taps == 27) wg_ck<true, 27>(a, s); else wg_ck<true, 1>(a, s);
-  } else {
-    if (a.taps == 27) wg_ck<false, 27>(a, s); else wg_ck<false, 1>(a, s);
+  switch (a.prec) {
+    case PREC_BF16: conv_wgrad_bf16(a, s); break;
+    case PREC_BF16X3: conv_wgrad_bf16x3(a, s); break;
+    default: conv_wgrad_f32(a, s); break;
   }
 }
 

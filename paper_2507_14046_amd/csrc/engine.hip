@@ -117,6 +117,12 @@ struct Instance {
 
 int tile_for(int n) { return n % 16 == 0 ? TILE_2x4x16 : TILE_2x8x8; }
 
+int conv_prec(int precision) {
+  if (precision == D2IP_BF16_CONV) return PREC_BF16;
+  if (precision == D2IP_BF16X3_CONV) return PREC_BF16X3;
+  return PREC_F32;
+}
+
 }  // namespace
 
 struct d2ip_ctx {
@@ -130,6 +136,7 @@ struct d2ip_ctx {
   float lr = 1e-3f, b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
+  hipStream_t cap = nullptr;  // capture stream (the caller's may be the legacy default stream)
   size_t bytes = 0;
 };
 
@@ -142,7 +149,8 @@ namespace {
 d2ip_status check_desc(const d2ip_geometry_desc* geos, int n_geo, const d2ip_instance_desc* insts,
                        int n_inst, int precision) {
   if (!geos || n_geo <= 0 || !insts || n_inst <= 0) return fail(D2IP_EINVAL, "empty geometry or instance list");
-  if (precision != D2IP_PLAIN_FP32 && precision != D2IP_BF16_CONV)
+  if (precision != D2IP_PLAIN_FP32 && precision != D2IP_BF16_CONV &&
+      precision != D2IP_BF16X3_CONV)
     return fail(D2IP_EINVAL, "unknown precision");
   for (int g = 0; g < n_geo; ++g) {
     if (geos[g].n < 4 || geos[g].n > 256 || geos[g].M <= 0 || geos[g].M > 65536)
@@ -260,7 +268,8 @@ ConvFwd fwd_args(const Instance& I, int prec, const Conv& c, int n, const float*
   a.n = n;
   a.cin = c.cin;
   a.cin_stride = cin_stride;
-  a.w = prec == PREC_BF16 ? (const void*)(I.wbf16 + c.wf) : (const void*)(I.wf32 + c.wf);
+  a.w = prec != PREC_F32 ? (const void*)(I.wbf16 + c.wf) : (const void*)(I.wf32 + c.wf);
+  a.w_lo_off = prec == PREC_BF16X3 ? I.wtotal : 0;
   a.w_rows = c.cout;
   a.cout = c.cout;
   a.y = y;
@@ -278,7 +287,8 @@ ConvFwd dgrad_args(const Instance& I, int prec, const Conv& c, int n, const floa
   a.n = n;
   a.cin = c.cout;
   a.cin_stride = c.cout;
-  a.w = prec == PREC_BF16 ? (const void*)(I.wbf16 + c.wd) : (const void*)(I.wf32 + c.wd);
+  a.w = prec != PREC_F32 ? (const void*)(I.wbf16 + c.wd) : (const void*)(I.wf32 + c.wd);
+  a.w_lo_off = prec == PREC_BF16X3 ? I.wtotal : 0;
   a.w_rows = c.cin_real;
   a.cout = c.cin_real;
   a.y = y;
@@ -331,6 +341,8 @@ void plan(d2ip_ctx& X, const d2ip_geometry_desc* gd, int n_geo, const d2ip_insta
     I.v = cv.take<float>(I.P);
     if (X.precision == D2IP_BF16_CONV)
       I.wbf16 = cv.take<uint16_t>(I.wtotal);
+    else if (X.precision == D2IP_BF16X3_CONV)
+      I.wbf16 = cv.take<uint16_t>(2 * I.wtotal);  // hi parts, then lo parts
     else
       I.wf32 = cv.take<float>(I.wtotal);
     I.packs_dev = cv.take<ConvPack>(I.packs.size());
@@ -451,14 +463,14 @@ void wgrad(d2ip_ctx& X, Instance& I, const Conv& c, int n, const float* x, int c
   a.partb = X.wg_partb;
   a.tile = tile_for(n);
   a.splits = conv_wgrad_splits(n, c.cin, c.cout, a.tile);
-  a.prec = X.precision == D2IP_BF16_CONV ? PREC_BF16 : PREC_F32;
+  a.prec = conv_prec(X.precision);
   conv_wgrad(a, X.stream);
   wgrad_reduce(X.wg_part, X.wg_partb, a.splits, c.cout, c.taps, c.cin, c.cin_real,
                I.grad + c.th_w, I.grad + c.th_b, X.stream);
 }
 
 void enqueue_forward(d2ip_ctx& X, Instance& I) {
-  const int prec = X.precision == D2IP_BF16_CONV ? PREC_BF16 : PREC_F32;
+  const int prec = conv_prec(X.precision);
   const Geometry& G = X.geos[I.geo];
   hipStream_t s = X.stream;
   float* th = I.theta;
@@ -493,7 +505,7 @@ void enqueue_forward(d2ip_ctx& X, Instance& I) {
 }
 
 void enqueue_iteration(d2ip_ctx& X, Instance& I) {
-  const int prec = X.precision == D2IP_BF16_CONV ? PREC_BF16 : PREC_F32;
+  const int prec = conv_prec(X.precision);
   const Geometry& G = X.geos[I.geo];
   hipStream_t s = X.stream;
   float* th = I.theta;
@@ -559,7 +571,8 @@ void enqueue_iteration(d2ip_ctx& X, Instance& I) {
     wgrad(X, I, I.stem, I.n, I.zpad, 8, L0.gh, PRO_NONE, nullptr, nullptr, nullptr);
   }
   adam(th, gr, I.m, I.v, I.P, X.lr, X.b1, X.b2, X.eps, I.it, s);
-  pack_weights(I.packs_dev, (int)I.packs.size(), I.max_pack, th, I.wf32, I.wbf16, s);
+  pack_weights(I.packs_dev, (int)I.packs.size(), I.max_pack, th, I.wf32, I.wbf16,
+               X.precision == D2IP_BF16X3_CONV ? I.wtotal : 0, s);
 }
 
 d2ip_status check_inst(d2ip_ctx* X, int inst) {
@@ -588,7 +601,8 @@ d2ip_status copy_out(d2ip_ctx* X, void* dst, const void* src, size_t bytes, int 
 }
 
 d2ip_status repack(d2ip_ctx* X, Instance& I) {
-  pack_weights(I.packs_dev, (int)I.packs.size(), I.max_pack, I.theta, I.wf32, I.wbf16, X->stream);
+  pack_weights(I.packs_dev, (int)I.packs.size(), I.max_pack, I.theta, I.wf32, I.wbf16,
+               X->precision == D2IP_BF16X3_CONV ? I.wtotal : 0, X->stream);
   HIPCHK(hipGetLastError());
   return D2IP_OK;
 }
@@ -671,6 +685,8 @@ d2ip_status d2ip_create(const d2ip_geometry_desc* geos, int n_geo, const d2ip_in
     }
   }
   if (e == hipSuccess) e = hipStreamSynchronize(X->stream);
+  if (e == hipSuccess && (flags & D2IP_FLAG_GRAPH))
+    e = hipStreamCreateWithFlags(&X->cap, hipStreamNonBlocking);
   if (e != hipSuccess)
     return cleanup(fail(D2IP_EHIP, std::string("workspace init: ") + hipGetErrorString(e)));
   *out = X;
@@ -681,6 +697,7 @@ d2ip_status d2ip_destroy(d2ip_ctx* X) {
   if (!X) return D2IP_OK;
   hipStreamSynchronize(X->stream);
   drop_graph(X);
+  if (X->cap) hipStreamDestroy(X->cap);
   delete X;
   return D2IP_OK;
 }
@@ -864,10 +881,17 @@ d2ip_status d2ip_run(d2ip_ctx* X, int k, double* last_loss) {
   if (k > 0) {
     if (X->flags & D2IP_FLAG_GRAPH) {
       if (!X->gexec) {
-        HIPCHK(hipStreamBeginCapture(X->stream, hipStreamCaptureModeThreadLocal));
-        for (Instance& I : X->insts) enqueue_iteration(*X, I);
+        // record one iteration of every instance on the capture stream; the
+        // graph is then launched on the caller's stream
+        hipStream_t user = X->stream;
+        X->stream = X->cap;
+        hipError_t e = hipStreamBeginCapture(X->cap, hipStreamCaptureModeThreadLocal);
         hipGraph_t g = nullptr;
-        hipError_t e = hipStreamEndCapture(X->stream, &g);
+        if (e == hipSuccess) {
+          for (Instance& I : X->insts) enqueue_iteration(*X, I);
+          e = hipStreamEndCapture(X->cap, &g);
+        }
+        X->stream = user;
         if (e != hipSuccess) return fail(D2IP_EHIP, std::string("graph capture: ") + hipGetErrorString(e));
         X->graph = g;
         HIPCHK(hipGraphInstantiate(&X->gexec, X->graph, nullptr, nullptr, 0));
@@ -890,6 +914,67 @@ d2ip_status d2ip_run(d2ip_ctx* X, int k, double* last_loss) {
     }
     if (bad) return fail(D2IP_ENONFINITE, "a non-finite loss was produced");
   }
+  return D2IP_OK;
+}
+
+d2ip_status d2ip_time_kernel(d2ip_ctx* X, int inst, int which, int block, int reps,
+                             double* avg_ms) {
+  d2ip_status st = check_inst(X, inst);
+  if (st != D2IP_OK) return st;
+  if (!avg_ms || reps <= 0) return fail(D2IP_EINVAL, "need reps > 0 and an output");
+  Instance& I = X->insts[inst];
+  const Geometry& G = X->geos[I.geo];
+  if (!G.set || !I.has_frame || !I.has_z) return fail(D2IP_ESTATE, "instance not ready");
+  const int prec = conv_prec(X->precision);
+  hipStream_t s = X->stream;
+  Block* b = nullptr;
+  if (which >= D2IP_KERNEL_CONV_FWD) {
+    if (block < 0 || block >= (int)I.blocks.size()) return fail(D2IP_EINVAL, "bad block index");
+    b = &I.blocks[block];
+  }
+  Level* Lv = b ? &I.lv[b->level] : nullptr;
+  auto launch = [&]() {
+    switch (which) {
+      case D2IP_KERNEL_JVEC:
+        jvec(G.Jc, G.M, G.qa_pad, G.idx, I.sigma, I.ppart, s);
+        break;
+      case D2IP_KERNEL_JTVEC:
+        jtvec(G.Jc, G.M, G.qa_pad, I.gp, I.tpart, s);
+        break;
+      case D2IP_KERNEL_ADAM:
+        adam(I.theta, I.grad, I.m, I.v, I.P, X->lr, X->b1, X->b2, X->eps, I.it, s);
+        break;
+      case D2IP_KERNEL_CONV_FWD: {
+        ConvFwd a = fwd_args(I, prec, b->c1, b->n, b->x, b->cin, b->h1);
+        a.bias = I.theta + b->c1.th_b;
+        a.stat_part = I.stat_part;
+        conv_fwd(a, s);
+        break;
+      }
+      case D2IP_KERNEL_CONV_DGRAD:
+        conv_fwd(dgrad_args(I, prec, b->c1, b->n, Lv->gh, Lv->gx), s);
+        break;
+      default:
+        wgrad(*X, I, b->c1, b->n, b->x, b->cin, Lv->gh, PRO_NONE, nullptr, nullptr, nullptr);
+        break;
+    }
+  };
+  if (which < D2IP_KERNEL_JVEC || which > D2IP_KERNEL_CONV_WGRAD)
+    return fail(D2IP_EINVAL, "unknown kernel id");
+  launch();
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  HIPCHK(hipEventRecord(e0, s));
+  for (int r = 0; r < reps; ++r) launch();
+  HIPCHK(hipEventRecord(e1, s));
+  HIPCHK(hipEventSynchronize(e1));
+  float ms = 0.f;
+  HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  HIPCHK(hipGetLastError());
+  *avg_ms = (double)ms / reps;
   return D2IP_OK;
 }
 

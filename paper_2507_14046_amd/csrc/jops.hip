@@ -189,8 +189,15 @@ __global__ void k_adam(float* __restrict__ theta, const float* __restrict__ g,
   }
 }
 
+__device__ __forceinline__ void put_bf(uint16_t* w, long long i, long long lo_off, float val) {
+  const uint16_t hi = f2bf(val);
+  w[i] = hi;
+  if (lo_off) w[lo_off + i] = f2bf(val - bf2f(hi));
+}
+
 __global__ void k_pack_weights(const ConvPack* __restrict__ packs, const float* __restrict__ theta,
-                               float* __restrict__ wf32, uint16_t* __restrict__ wbf16) {
+                               float* __restrict__ wf32, uint16_t* __restrict__ wbf16,
+                               long long lo_off) {
   const ConvPack pk = packs[blockIdx.y];
   const int per_co = pk.cin_real * pk.taps;
   const int total = pk.cout * per_co;
@@ -202,12 +209,12 @@ __global__ void k_pack_weights(const ConvPack* __restrict__ packs, const float* 
     const float val = theta[pk.th_off + e];
     const long long fi = pk.wf_off + ((long long)co * pk.taps + tap) * pk.cin + ci;
     if (wf32) wf32[fi] = val;
-    if (wbf16) wbf16[fi] = f2bf(val);
+    if (wbf16) put_bf(wbf16, fi, lo_off, val);
     if (pk.need_dgrad) {
       const long long di =
           pk.wd_off + ((long long)ci * pk.taps + (pk.taps - 1 - tap)) * pk.cout + co;
       if (wf32) wf32[di] = val;
-      if (wbf16) wbf16[di] = f2bf(val);
+      if (wbf16) put_bf(wbf16, di, lo_off, val);
     }
   }
 }
@@ -271,10 +278,10 @@ void adam(float* theta, const float* g, float* m, float* v, size_t P, float lr, 
 }
 
 void pack_weights(const ConvPack* packs, int npacks, int max_elems, const float* theta,
-                  float* wf32, uint16_t* wbf16, hipStream_t s) {
+                  float* wf32, uint16_t* wbf16, long long lo_off, hipStream_t s) {
   dim3 grid((max_elems + 255) / 256, npacks);
   if (grid.x > 1024) grid.x = 1024;
-  hipLaunchKernelGGL(k_pack_weights, grid, dim3(256), 0, s, packs, theta, wf32, wbf16);
+  hipLaunchKernelGGL(k_pack_weights, grid, dim3(256), 0, s, packs, theta, wf32, wbf16, lo_off);
 }
 
 }  // namespace d2ip

@@ -12,7 +12,7 @@ namespace d2ip {
 enum Prologue { PRO_NONE = 0, PRO_LN_RELU = 1 };
 
 // Operand precision of the conv MFMAs (accumulation is always FP32).
-enum ConvPrec { PREC_F32 = 0, PREC_BF16 = 1 };
+enum ConvPrec { PREC_F32 = 0, PREC_BF16 = 1, PREC_BF16X3 = 2 };
 
 // Spatial output tile of a conv block (TZ x TY x TX voxels).
 enum TileCfg { TILE_2x4x16 = 0, TILE_2x8x8 = 1, TILE_COUNT = 2 };
@@ -25,6 +25,7 @@ struct ConvFwd {
   const float* x;        // [n^3][cin_stride], fp32
   int n, cin, cin_stride;  // cin: multiple of 8, channels read
   const void* w;         // packed weights [w_rows][taps][cin], fp32 or bf16
+  long long w_lo_off;    // PREC_BF16X3: elements from w to its lo-part copy
   int w_rows;            // rows present in w (>= cout)
   const float* bias;     // [cout] or null
   const float* add;      // [n^3][cout] residual added in the epilogue, or null
@@ -141,7 +142,9 @@ void tail_bwd(const float* tpart, int nmb, int qa_pad, const int* inv, const flo
 void reduce_cols(const double* part, int nparts, int K, float* dst, hipStream_t s);
 void adam(float* theta, const float* g, float* m, float* v, size_t P, float lr, float beta1,
           float beta2, float eps, const IterState* it, hipStream_t s);
+// Packed conv weights from theta; with lo_off > 0 the bf16 lo parts
+// (bf16(w - bf16(w))) are written lo_off elements after the hi parts.
 void pack_weights(const ConvPack* packs, int npacks, int max_elems, const float* theta,
-                  float* wf32, uint16_t* wbf16, hipStream_t s);
+                  float* wf32, uint16_t* wbf16, long long lo_off, hipStream_t s);
 
 }  // namespace d2ip

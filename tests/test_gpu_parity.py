@@ -23,8 +23,11 @@ CASES = {
     "n16_L3_C16_M928": (16, 2, 3, 16, 3),
 }
 
-TOL_IMG = {"fp32": 1e-5, "bf16": 2e-2}
-TOL_GRAD = {"fp32": 2e-4, "bf16": 5e-2}
+# pure BF16 operands: errors are recorded, bounds only catch gross failures
+TOL_IMG = {"fp32": 1e-5, "bf16x3": 2e-5, "bf16": 2e-2}
+TOL_GRAD = {"fp32": 2e-4, "bf16x3": 5e-4, "bf16": 0.3}
+TOL_TRAJ = {"fp32": 2e-5, "bf16x3": 2e-4, "bf16": 0.5}
+PRECS = ["fp32", "bf16x3", "bf16"]
 
 
 @pytest.fixture(scope="module")
@@ -32,7 +35,7 @@ def probs():
     return {k: problem(*v) for k, v in CASES.items()}
 
 
-@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+@pytest.mark.parametrize("prec", PRECS)
 @pytest.mark.parametrize("case", list(CASES))
 def test_forward_image(lib, probs, case, prec):
     p = probs[case]
@@ -45,7 +48,7 @@ def test_forward_image(lib, probs, case, prec):
     assert e < TOL_IMG[prec]
 
 
-@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+@pytest.mark.parametrize("prec", PRECS)
 @pytest.mark.parametrize("case", list(CASES))
 def test_one_iteration_loss_and_gradient(lib, probs, case, prec):
     p = probs[case]
@@ -63,7 +66,7 @@ def test_one_iteration_loss_and_gradient(lib, probs, case, prec):
     assert worst[1] < 5 * TOL_GRAD[prec], per
 
 
-@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+@pytest.mark.parametrize("prec", PRECS)
 def test_trajectory_50_iterations_16cubed(lib, probs, prec):
     p = probs["n16_L2_C8"]
     ctx = make_ctx(lib, [p], prec)
@@ -76,7 +79,7 @@ def test_trajectory_50_iterations_16cubed(lib, probs, prec):
     e = rel(img, ref)
     lrel = float(np.max(np.abs(np.array(losses) - lref) / np.array(lref)))
     record("trajectory50_n16", prec=prec, image_rel=e, loss_max_rel=lrel)
-    assert e < (2e-5 if prec == "fp32" else 2e-3)
+    assert e < TOL_TRAJ[prec]
 
 
 def test_tpp_two_frames_matches_oracle(lib):
@@ -95,7 +98,7 @@ def test_tpp_two_frames_matches_oracle(lib):
     assert e0 < 1e-5 and e1 < 1e-5
 
 
-@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+@pytest.mark.parametrize("prec", PRECS)
 def test_graph_replay_matches_eager(lib, probs, prec):
     p = probs["n24_L3_C8"]
     a = make_ctx(lib, [p], prec, graph=False)
@@ -191,7 +194,7 @@ def test_full_size_32cubed_one_iteration(lib):
     oracle after one iteration."""
     c = ts.CONFIGS["c1"]
     p = problem(c["n"], c["rings"], c["levels"], c["base_ch"], c["seed"])
-    for prec in ("fp32", "bf16"):
+    for prec in PRECS:
         ctx = make_ctx(lib, [p], prec, graph=True)
         loss = ctx.run(1)[0]
         g = ctx.get_grad(0)
@@ -203,3 +206,4 @@ def test_full_size_32cubed_one_iteration(lib):
         record("full32_one_iteration", prec=prec, loss_rel=abs(loss - L0) / L0,
                grad_rel=rel(g, gref), worst=max(per.values()))
         assert rel(g, gref) < TOL_GRAD[prec]
+        ctx.close()
