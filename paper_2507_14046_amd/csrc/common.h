@@ -43,6 +43,8 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
   return r;
 }
 
+constexpr float kLnEps = 1e-5f;  // LayerNorm epsilon (inside the square root)
+
 // Normalisation statistics of one LayerNorm: mean and 1/sqrt(var + eps).
 struct LnStat {
   float mean, rstd;
@@ -52,3 +54,89 @@ struct LnStat {
 struct LnBwd {
   float A, B;
 };
+
+// Per-block FP64 partial pairs written by the producer of a LayerNorm input
+// (sum, sum of squares) or of its backward ((sum_c gamma_c sum gz),
+// (sum_c gamma_c sum gz*xhat)); every consumer block reduces them itself.
+struct PairRef {
+  const double* part;  // [nparts][2]
+  int nparts;
+  double count;        // elements normalised together
+};
+
+// Block-wide sum of `n` (a, b) pairs in a fixed order; the same value in all
+// threads.  Contains barriers: every thread of the block must call it.
+__device__ __forceinline__ void block_pair_sum(const double* part, int n, double& s1, double& s2) {
+  __shared__ double sh[2][16];
+  double a = 0.0, b = 0.0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    a += part[2 * i];
+    b += part[2 * i + 1];
+  }
+  a = wave_sum(a);
+  b = wave_sum(b);
+  const int w = threadIdx.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) {
+    sh[0][w] = a;
+    sh[1][w] = b;
+  }
+  __syncthreads();
+  s1 = 0.0;
+  s2 = 0.0;
+  for (int i = 0; i < (int)(blockDim.x >> 6); ++i) {
+    s1 += sh[0][i];
+    s2 += sh[1][i];
+  }
+}
+
+__device__ __forceinline__ LnStat stat_of(const PairRef& r) {
+  double s1, s2;
+  block_pair_sum(r.part, r.nparts, s1, s2);
+  const double mean = s1 / r.count;
+  double var = s2 / r.count - mean * mean;
+  if (var < 0.0) var = 0.0;
+  LnStat st;
+  st.mean = (float)mean;
+  st.rstd = (float)(1.0 / sqrt(var + (double)kLnEps));
+  return st;
+}
+
+__device__ __forceinline__ LnBwd coef_of(const PairRef& r) {
+  double s1, s2;
+  block_pair_sum(r.part, r.nparts, s1, s2);
+  LnBwd c;
+  c.A = (float)(s1 / r.count);
+  c.B = (float)(s2 / r.count);
+  return c;
+}
+
+// "Last block finalises": called by every thread of a block after the block
+// stored its partial results.  Returns true (uniform over the block) in the
+// block that arrives last among `nblocks` arrivals on `counter`; that block
+// resets the counter to zero, so the next launch (or graph replay) finds it
+// zeroed.  No block ever waits on another.
+__device__ __forceinline__ bool arrive_last(int* counter, int nblocks) {
+  __shared__ int s_last;
+  // release this block's partials at device scope (L2 write-back only; a
+  // seq_cst fence would also invalidate this XCD's L2 for every block)
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int prev = atomicAdd(counter, 1);
+    s_last = prev == nblocks - 1;
+    if (s_last) atomicExch(counter, 0);
+  }
+  __syncthreads();
+  const bool last = s_last != 0;
+  if (last) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");  // see the other blocks' partials
+  return last;
+}
+
+// Device-coherent loads of data other blocks of the same launch wrote.
+__device__ __forceinline__ float load_dev(const float* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ double load_dev(const double* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}

@@ -1,40 +1,65 @@
-// Conv entry points: mode dispatch, launch-shape helpers and the deterministic
-// reduction of weight-gradient partials.
+// Conv entry points: mode dispatch, launch-shape helpers and the batched,
+// deterministic reduction of all weight-gradient partials of an iteration.
 #include "conv_impl.h"
 
 namespace d2ip {
 namespace {
 
-__global__ void k_wgrad_reduce(const float* __restrict__ part, const float* __restrict__ partb,
-                               int splits, int cout, int taps, int cin, int cin_real, float* gw,
-                               float* gb) {
-  const int cout16 = (cout + 15) & ~15;
-  const size_t per = (size_t)cout16 * taps * cin;
-  const size_t total = (size_t)cout * taps * cin;
-  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < total;
-       i += (size_t)gridDim.x * blockDim.x) {
-    const int ci = (int)(i % cin);
-    const int tap = (int)((i / cin) % taps);
-    const int co = (int)(i / ((size_t)cin * taps));
-    if (ci >= cin_real) continue;
-    float s = 0.f;
-    for (int k = 0; k < splits; ++k) s += part[k * per + i];
-    gw[((size_t)co * cin_real + ci) * taps + tap] = s;
+// One block row per conv segment.  A block owns 64 consecutive partial
+// elements (layout [co][tap][ci]); its 4 thread groups sum interleaved split
+// subsets, combined in group order, so the sum order is fixed.
+__global__ void k_grad_reduce(const GradSeg* __restrict__ segs, const float* __restrict__ part,
+                              const float* __restrict__ partb, const double* __restrict__ dpart,
+                              float* __restrict__ grad) {
+  __shared__ float sh[4][64];
+  const GradSeg sg = segs[blockIdx.y];
+  if (sg.kind == 1) {
+    // column sums of double partials [splits][cout]
+    const double* D = dpart + sg.part_off;
+    for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < sg.cout; k += gridDim.x * blockDim.x) {
+      double acc = 0.0;
+      for (int i = 0; i < sg.splits; ++i) acc += D[(long long)i * sg.cout + k];
+      grad[sg.th_w + k] = (float)acc;
+    }
+    return;
   }
-  if (gb && blockIdx.x == 0) {
-    for (int co = threadIdx.x; co < cout; co += blockDim.x) {
-      float s = 0.f;
-      for (int k = 0; k < splits; ++k) s += partb[(size_t)k * cout16 + co];
-      gb[co] = s;
+  const int cout16 = (sg.cout + 15) & ~15;
+  const long long per = (long long)cout16 * sg.taps * sg.cin;
+  const int total = sg.cout * sg.taps * sg.cin;
+  const float* P = part + sg.part_off;
+  const int j = threadIdx.x & 63, q = threadIdx.x >> 6;
+  for (int base = blockIdx.x * 64; base < total; base += gridDim.x * 64) {
+    const int f = base + j;
+    float acc = 0.f;
+    if (f < total)
+      for (int k = q; k < sg.splits; k += 4) acc += P[k * per + f];
+    sh[q][j] = acc;
+    __syncthreads();
+    if (q == 0 && f < total) {
+      const float v = ((sh[0][j] + sh[1][j]) + sh[2][j]) + sh[3][j];
+      const int ci = f % sg.cin;
+      const int tap = (f / sg.cin) % sg.taps;
+      const int co = f / (sg.cin * sg.taps);
+      if (ci < sg.cin_real) grad[sg.th_w + ((long long)co * sg.cin_real + ci) * sg.taps + tap] = v;
+    }
+    __syncthreads();
+  }
+  if (blockIdx.x == 0) {
+    const float* PB = partb + sg.partb_off;
+    for (int co = threadIdx.x; co < sg.cout; co += blockDim.x) {
+      float acc = 0.f;
+      for (int k = 0; k < sg.splits; ++k) acc += PB[(long long)k * cout16 + co];
+      grad[sg.th_b + co] = acc;
     }
   }
 }
 
 }  // namespace
 
+int conv_tiles(int n, int tile) { return conv_detail::spatial_tiles(n, tile); }
+
 int conv_fwd_blocks(const ConvFwd& a) {
-  const int bn = conv_detail::pick_bn(a.cout);
-  return conv_detail::spatial_tiles(a.n, a.tile) * ((a.cout + bn - 1) / bn);
+  return conv_detail::spatial_tiles(a.n, a.tile) * ((a.cout + a.bn - 1) / a.bn);
 }
 
 void conv_fwd(const ConvFwd& a, hipStream_t s) {
@@ -45,18 +70,8 @@ void conv_fwd(const ConvFwd& a, hipStream_t s) {
   }
 }
 
-int conv_wgrad_splits(int n, int cin, int cout, int tile) {
-  const int per = (cin / conv_detail::pick_ck(cin)) * ((cout + 15) / 16);
-  const int tiles = conv_detail::spatial_tiles(n, tile);
-  int s = (1024 + per - 1) / per;
-  if (s > tiles) s = tiles;
-  if (s < 1) s = 1;
-  return s;
-}
-
-size_t conv_wgrad_part_floats(int n, int cin, int cout, int taps, int tile) {
-  const int s = conv_wgrad_splits(n, cin, cout, tile);
-  return (size_t)s * ((cout + 15) & ~15) * taps * cin;
+int conv_wgrad_groups(int taps, int ck) {
+  return (taps * ck + conv_detail::kWgCols - 1) / conv_detail::kWgCols;
 }
 
 void conv_wgrad(const ConvWgrad& a, hipStream_t s) {
@@ -67,14 +82,17 @@ void conv_wgrad(const ConvWgrad& a, hipStream_t s) {
   }
 }
 
-void wgrad_reduce(const float* part, const float* partb, int splits, int cout, int taps, int cin,
-                  int cin_real, float* gw, float* gb, hipStream_t s) {
-  const size_t total = (size_t)cout * taps * cin;
-  int blocks = (int)((total + 255) / 256);
-  if (blocks > 2048) blocks = 2048;
-  if (blocks < 1) blocks = 1;
-  hipLaunchKernelGGL(k_wgrad_reduce, dim3(blocks), dim3(256), 0, s, part, partb, splits, cout,
-                     taps, cin, cin_real, gw, gb);
+size_t conv_fwd_lds_bytes(int tile, int taps, int bn, int ck, int prec) {
+  return conv_detail::fwd_lds_bytes(tile, taps, bn, ck, prec);
+}
+
+void grad_reduce(const GradSeg* segs, int nsegs, int max_elems, const float* part,
+                 const float* partb, const double* dpart, float* grad, hipStream_t s) {
+  int bx = (max_elems + 63) / 64;
+  if (bx > 1024) bx = 1024;
+  if (bx < 1) bx = 1;
+  hipLaunchKernelGGL(k_grad_reduce, dim3(bx, nsegs), dim3(256), 0, s, segs, part, partb, dpart,
+                     grad);
 }
 
 }  // namespace d2ip

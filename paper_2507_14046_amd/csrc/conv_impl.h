@@ -1,19 +1,22 @@
 // 3D convolutions of the image prior (3x3x3 and 1x1x1, zero padding) as
 // implicit GEMMs on the gfx950 matrix cores.
 //
-// Forward / input-gradient kernel: the GEMM rows are output voxels of a
-// TZ x TY x TX spatial tile, the columns are output channels, the reduction
-// runs over (tap, input channel).  Each block stages the input halo of its tile
-// for a chunk of CK channels in LDS (applying the LayerNorm+ReLU of the
-// producing layer on the fly when asked), then every wave issues 16x16 MFMAs:
-// v_mfma_f32_16x16x4_f32 (FP32 operands) or v_mfma_f32_16x16x32_bf16 (BF16
-// operands, rounded to nearest even while staging); accumulation is FP32.
-// The epilogue adds bias / residual, stores, and emits per-block (sum, sumsq)
-// partials in FP64 for the following whole-volume LayerNorm.
+// Forward / input-gradient kernel: GEMM rows are the output voxels of a
+// TZ x TY x TX spatial tile, columns are output channels (BN per block), the
+// reduction runs over (tap, input channel).  Each block stages the input halo
+// of its tile for a chunk of CK channels in LDS, applying the producer's
+// pending transform on the fly (LayerNorm+ReLU, or the LayerNorm backward),
+// then each wave issues 16x16 MFMAs: v_mfma_f32_16x16x4_f32 (FP32 operands)
+// or v_mfma_f32_16x16x32_bf16 (BF16 operands); accumulation is FP32.  Coarse
+// grids split the channel chunks over blocks (split-K); the last block of
+// each output tile sums the partials in a fixed order.  The epilogue adds
+// bias / residual, stores, and emits per-tile FP64 (sum, sumsq) partials; the
+// last tile turns them into the LayerNorm statistics of the output.
 //
-// Weight-gradient kernel: rows are output channels, columns (tap, channel),
-// the reduction runs over voxels; blocks split the voxel range and write
-// partial sums that a second kernel reduces in a fixed order (deterministic).
+// Weight-gradient kernel: rows are output channels (16 per block), columns
+// (tap, channel) in groups of 128 per block, the reduction runs over voxels;
+// blocks split the voxel range and write partial sums that one batched
+// kernel per iteration reduces in a fixed order (deterministic).
 //
 // Operand modes: PREC_F32 (one FP32 MFMA per k-step), PREC_BF16 (operands
 // rounded to bf16, one MFMA), PREC_BF16X3 (each operand x split into
@@ -28,6 +31,9 @@
 namespace d2ip {
 namespace conv_detail {
 
+constexpr int kCkMax = 32;       // largest channel chunk staged at once
+constexpr int kWgNtw = 2;        // weight-gradient N tiles per wave
+constexpr int kWgCols = 4 * kWgNtw * 16;  // columns per weight-gradient block
 
 template <int TILE>
 struct TileDims;
@@ -36,8 +42,12 @@ struct TileDims<TILE_2x4x16> {
   static constexpr int Z = 2, Y = 4, X = 16;
 };
 template <>
-struct TileDims<TILE_2x8x8> {
-  static constexpr int Z = 2, Y = 8, X = 8;
+struct TileDims<TILE_1x4x16> {
+  static constexpr int Z = 1, Y = 4, X = 16;
+};
+template <>
+struct TileDims<TILE_1x8x8> {
+  static constexpr int Z = 1, Y = 8, X = 8;
 };
 
 template <int MODE>
@@ -46,13 +56,38 @@ struct Mode {
   static constexpr bool SPLIT = MODE == PREC_BF16X3;  // hi + lo parts
   static constexpr int KPL = BF ? 8 : 1;              // k per lane per MFMA
   static constexpr int KSTEP = 4 * KPL;               // k per MFMA
+  static constexpr int PAD = BF ? 8 : 1;              // LDS row padding (elements)
   using ST = typename std::conditional<BF, uint16_t, float>::type;  // LDS element
   using FT = typename std::conditional<BF, bf16x8, float>::type;    // MFMA operand
 };
 
-__device__ __forceinline__ float ln_relu(float h, float mean, float rstd, float g, float b) {
-  float v = g * ((h - mean) * rstd) + b;
-  return v > 0.f ? v : 0.f;
+// LDS row pitch (elements) of the forward weight slab: FP32 pitches are
+// 2 mod 32 words so the 16 rows x 4 k of a fragment hit distinct banks; BF16
+// pitches keep 16-byte alignment.
+__host__ __device__ inline int fwd_wrow(int taps, int ck, bool bf) {
+  const int base = taps * ck;
+  if (bf) return base + 8;
+  return base + ((2 - base % 32) + 32) % 32;
+}
+
+__host__ inline size_t fwd_lds_bytes(int tile, int taps, int bn, int ck, int mode) {
+  int tz, ty, tx;
+  if (tile == TILE_2x4x16) {
+    tz = 2; ty = 4; tx = 16;
+  } else if (tile == TILE_1x4x16) {
+    tz = 1; ty = 4; tx = 16;
+  } else {
+    tz = 1; ty = 8; tx = 8;
+  }
+  const int r = taps == 27 ? 1 : 0;
+  const size_t hp = (size_t)(tz + 2 * r) * (ty + 2 * r) * (tx + 2 * r);
+  const bool bf = mode != PREC_F32;
+  const int parts = mode == PREC_BF16X3 ? 2 : 1;
+  const size_t el = bf ? 2 : 4;
+  const size_t ckp = ck + (bf ? 8 : 1);
+  const size_t stage = parts * el * (hp * ckp + (size_t)bn * fwd_wrow(taps, ck, bf));
+  const size_t xch = (size_t)4 * (tz * ty * tx / 16) * (bn / 16) * 64 * 16;  // 4 waves x tiles
+  return stage > xch ? stage : xch;
 }
 
 __device__ __forceinline__ f32x4 mfma(float a, float b, f32x4 c) {
@@ -72,55 +107,89 @@ __device__ __forceinline__ uint32_t pack2(uint16_t a, uint16_t b) {
   return (uint32_t)a | ((uint32_t)b << 16);
 }
 
-// Stage a (HZ x HY x HX) halo of CK channels starting at ci0 into LDS
-// (rows of CKP elements); the LayerNorm+ReLU prologue is applied to in-grid
-// voxels, out-of-grid voxels are the conv's zero padding.
-template <int MODE, int CK, int HZ, int HY, int HX, int CKP, int PRO>
-__device__ __forceinline__ void stage_halo(typename Mode<MODE>::ST* hal,
-                                           typename Mode<MODE>::ST* hal_lo,
-                                           const float* __restrict__ x, int n, int cin_stride,
-                                           int ci0, int z0, int y0, int x0, int R,
-                                           const LnStat* ln, const float* lng, const float* lnb) {
-  constexpr int Q = CK / 4;
-  constexpr int HP = HZ * HY * HX;
-  float mean = 0.f, rstd = 1.f;
+// Four consecutive channels c..c+3 of the operand at element offset i, with
+// the source's prologue applied.
+template <int PRO>
+__device__ __forceinline__ float4 load_src4(const ConvSrc& s, size_t i, int c, float mean,
+                                            float rstd, float A, float B) {
+  float4 v = *reinterpret_cast<const float4*>(s.x + i);
   if (PRO == PRO_LN_RELU) {
-    mean = ln->mean;
-    rstd = ln->rstd;
+    v.x = fmaxf(s.gamma[c + 0] * ((v.x - mean) * rstd) + s.beta[c + 0], 0.f);
+    v.y = fmaxf(s.gamma[c + 1] * ((v.y - mean) * rstd) + s.beta[c + 1], 0.f);
+    v.z = fmaxf(s.gamma[c + 2] * ((v.z - mean) * rstd) + s.beta[c + 2], 0.f);
+    v.w = fmaxf(s.gamma[c + 3] * ((v.w - mean) * rstd) + s.beta[c + 3], 0.f);
+  } else if (PRO == PRO_LN_BWD) {
+    const float4 h = *reinterpret_cast<const float4*>(s.h + i);
+    v.x = rstd * (s.gamma[c + 0] * v.x - A - ((h.x - mean) * rstd) * B);
+    v.y = rstd * (s.gamma[c + 1] * v.y - A - ((h.y - mean) * rstd) * B);
+    v.z = rstd * (s.gamma[c + 2] * v.z - A - ((h.z - mean) * rstd) * B);
+    v.w = rstd * (s.gamma[c + 3] * v.w - A - ((h.w - mean) * rstd) * B);
   }
+  return v;
+}
+
+// Prologue constants of a source, reduced from the producers' partials by
+// the whole block (call from every thread).
+template <int PRO>
+__device__ __forceinline__ void src_consts(const ConvSrc& s, float& mean, float& rstd, float& A,
+                                           float& B) {
+  mean = 0.f;
+  rstd = 1.f;
+  A = 0.f;
+  B = 0.f;
+  if (PRO != PRO_NONE) {
+    const LnStat st = stat_of(s.st);
+    mean = st.mean;
+    rstd = st.rstd;
+  }
+  if (PRO == PRO_LN_BWD) {
+    const LnBwd c = coef_of(s.bw);
+    A = c.A;
+    B = c.B;
+  }
+}
+
+// Store four values at LDS element offset o (and the lo parts in split mode).
+template <int MODE>
+__device__ __forceinline__ void put4(typename Mode<MODE>::ST* hi, typename Mode<MODE>::ST* lo,
+                                     int o, float4 v) {
+  if constexpr (Mode<MODE>::SPLIT) {
+    uint16_t h0, h1, h2, h3, l0, l1, l2, l3;
+    split_bf(v.x, h0, l0);
+    split_bf(v.y, h1, l1);
+    split_bf(v.z, h2, l2);
+    split_bf(v.w, h3, l3);
+    *reinterpret_cast<uint2*>(hi + o) = make_uint2(pack2(h0, h1), pack2(h2, h3));
+    *reinterpret_cast<uint2*>(lo + o) = make_uint2(pack2(l0, l1), pack2(l2, l3));
+  } else if constexpr (Mode<MODE>::BF) {
+    *reinterpret_cast<uint2*>(hi + o) =
+        make_uint2(pack2(f2bf(v.x), f2bf(v.y)), pack2(f2bf(v.z), f2bf(v.w)));
+  } else {
+    hi[o + 0] = v.x;
+    hi[o + 1] = v.y;
+    hi[o + 2] = v.z;
+    hi[o + 3] = v.w;
+  }
+}
+
+// Stage a (HZ x HY x HX) halo of ck channels starting at ci0 into LDS rows of
+// ckp elements; out-of-grid voxels are the conv's zero padding.
+template <int MODE, int HZ, int HY, int HX, int PRO>
+__device__ __forceinline__ void stage_halo(typename Mode<MODE>::ST* hal,
+                                           typename Mode<MODE>::ST* hal_lo, const ConvSrc& s,
+                                           int n, int ck, int ckp, int ci0, int z0, int y0, int x0,
+                                           int R, float mean, float rstd, float A, float B) {
+  const int Q = ck >> 2;
+  constexpr int HP = HZ * HY * HX;
   for (int p = threadIdx.x; p < HP * Q; p += 256) {
     const int pos = p / Q, q = p - pos * Q;
     const int hx = pos % HX, hy = (pos / HX) % HY, hz = pos / (HX * HY);
     const int gz = z0 + hz - R, gy = y0 + hy - R, gx = x0 + hx - R;
     float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-    if (gz >= 0 && gz < n && gy >= 0 && gy < n && gx >= 0 && gx < n) {
-      const int c = ci0 + 4 * q;
-      v = *reinterpret_cast<const float4*>(x + (size_t)((gz * n + gy) * n + gx) * cin_stride + c);
-      if (PRO == PRO_LN_RELU) {
-        v.x = ln_relu(v.x, mean, rstd, lng[c + 0], lnb[c + 0]);
-        v.y = ln_relu(v.y, mean, rstd, lng[c + 1], lnb[c + 1]);
-        v.z = ln_relu(v.z, mean, rstd, lng[c + 2], lnb[c + 2]);
-        v.w = ln_relu(v.w, mean, rstd, lng[c + 3], lnb[c + 3]);
-      }
-    }
-    const int o = pos * CKP + 4 * q;
-    if constexpr (Mode<MODE>::SPLIT) {
-      uint16_t h0, h1, h2, h3, l0, l1, l2, l3;
-      split_bf(v.x, h0, l0);
-      split_bf(v.y, h1, l1);
-      split_bf(v.z, h2, l2);
-      split_bf(v.w, h3, l3);
-      *reinterpret_cast<uint2*>(hal + o) = make_uint2(pack2(h0, h1), pack2(h2, h3));
-      *reinterpret_cast<uint2*>(hal_lo + o) = make_uint2(pack2(l0, l1), pack2(l2, l3));
-    } else if constexpr (Mode<MODE>::BF) {
-      *reinterpret_cast<uint2*>(hal + o) =
-          make_uint2(pack2(f2bf(v.x), f2bf(v.y)), pack2(f2bf(v.z), f2bf(v.w)));
-    } else {
-      hal[o + 0] = v.x;
-      hal[o + 1] = v.y;
-      hal[o + 2] = v.z;
-      hal[o + 3] = v.w;
-    }
+    const int c = ci0 + 4 * q;
+    if (gz >= 0 && gz < n && gy >= 0 && gy < n && gx >= 0 && gx < n)
+      v = load_src4<PRO>(s, (size_t)((gz * n + gy) * n + gx) * s.stride + c, c, mean, rstd, A, B);
+    put4<MODE>(hal, hal_lo, pos * ckp + 4 * q, v);
   }
 }
 
@@ -130,8 +199,7 @@ __device__ __forceinline__ int tap_offset(int tap, int HY, int HX) {
 }
 
 template <int MODE>
-__device__ __forceinline__ typename Mode<MODE>::FT lds_frag(const typename Mode<MODE>::ST* p,
-                                                            bool ok) {
+__device__ __forceinline__ typename Mode<MODE>::FT frag(const typename Mode<MODE>::ST* p, bool ok) {
   if constexpr (Mode<MODE>::BF) {
     u32x4 v = {0u, 0u, 0u, 0u};
     if (ok) v = *reinterpret_cast<const u32x4*>(p);
@@ -141,19 +209,7 @@ __device__ __forceinline__ typename Mode<MODE>::FT lds_frag(const typename Mode<
   }
 }
 
-template <int MODE>
-__device__ __forceinline__ typename Mode<MODE>::FT glb_frag(const typename Mode<MODE>::ST* p,
-                                                            bool ok) {
-  if constexpr (Mode<MODE>::BF) {
-    u32x4 v = {0u, 0u, 0u, 0u};
-    if (ok) v = *reinterpret_cast<const u32x4*>(p);
-    return __builtin_bit_cast(bf16x8, v);
-  } else {
-    return ok ? *p : 0.f;
-  }
-}
-
-template <int MODE, int TAPS, int CK, int TILE, int BN, int PRO>
+template <int MODE, int TAPS, int TILE, int BN, int PRO>
 __global__ __launch_bounds__(256) void k_conv_fwd(ConvFwd a) {
   using MD = Mode<MODE>;
   using ST = typename MD::ST;
@@ -163,18 +219,23 @@ __global__ __launch_bounds__(256) void k_conv_fwd(ConvFwd a) {
   constexpr int R = TAPS == 27 ? 1 : 0;
   constexpr int HZ = TZ + 2 * R, HY = TY + 2 * R, HX = TX + 2 * R, HP = HZ * HY * HX;
   constexpr int KPL = MD::KPL, KSTEP = MD::KSTEP;
-  constexpr int NSTEP = (TAPS * CK + KSTEP - 1) / KSTEP;
-  constexpr bool KEXACT = (TAPS * CK) % KSTEP == 0;
-  constexpr int CKP = MD::BF ? CK + 8 : CK + 1;
-  constexpr int BM = TZ * TY * TX, MT = BM / 16, MTW = MT / 4, NT = BN / 16;
-  static_assert(MT % 4 == 0, "tile must hold a multiple of 64 voxels");
-  __shared__ __align__(16) ST hal[HP * CKP];
-  __shared__ __align__(16) ST hal_lo[MD::SPLIT ? HP * CKP : 8];
+  constexpr int BM = TZ * TY * TX, MT = BM / 16, NT = BN / 16;
+  static_assert(MT * NT <= 16, "accumulator tile too large");
+  extern __shared__ __align__(16) unsigned char smem[];
   __shared__ double red[8];
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int l16 = lane & 15, g = lane >> 4;
   const int n = a.n;
+  const int ck = a.ck, ckp = ck + MD::PAD;
+  const int ck_shift = __builtin_ctz(ck);
+  // LDS: halo [HP][ckp] (+ lo parts), weight slab [BN][wrp] (+ lo parts); the
+  // same space holds the cross-wave accumulator exchange after the K loop
+  const int wrp = fwd_wrow(TAPS, ck, MD::BF);
+  ST* hal = reinterpret_cast<ST*>(smem);
+  ST* hal_lo = hal + (MD::SPLIT ? HP * ckp : 0);
+  ST* wsm = hal + (MD::SPLIT ? 2 : 1) * HP * ckp;
+  ST* wsm_lo = wsm + (MD::SPLIT ? BN * wrp : 0);
   const int ntx = (n + TX - 1) / TX, nty = (n + TY - 1) / TY;
   int b = blockIdx.x;
   const int x0 = (b % ntx) * TX;
@@ -184,50 +245,85 @@ __global__ __launch_bounds__(256) void k_conv_fwd(ConvFwd a) {
   const int z0 = b * TZ;
   const int co0 = blockIdx.y * BN;
 
-  f32x4 acc[MTW][NT];
+  // every wave accumulates all MT x NT tiles over every 4th k-step
+  f32x4 acc[MT][NT];
 #pragma unroll
-  for (int i = 0; i < MTW; ++i)
+  for (int i = 0; i < MT; ++i)
 #pragma unroll
     for (int j = 0; j < NT; ++j) acc[i][j] = (f32x4){0.f, 0.f, 0.f, 0.f};
 
-  int apos[MTW];
+  int apos[MT];
 #pragma unroll
-  for (int mt = 0; mt < MTW; ++mt) {
-    const int li = (wave * MTW + mt) * 16 + l16;
+  for (int mt = 0; mt < MT; ++mt) {
+    const int li = mt * 16 + l16;
     const int tz = li / (TY * TX), ty = (li / TX) % TY, tx = li % TX;
     apos[mt] = (tz * HY + ty) * HX + tx;
   }
 
   const ST* __restrict__ W = reinterpret_cast<const ST*>(a.w);
   const ST* __restrict__ Wlo = W + a.w_lo_off;
-  for (int ci0 = 0; ci0 < a.cin; ci0 += CK) {
-    stage_halo<MODE, CK, HZ, HY, HX, CKP, PRO>(hal, hal_lo, a.x, n, a.cin_stride, ci0, z0, y0, x0,
-                                               R, a.ln, a.ln_g, a.ln_b);
+  const int nchunks = a.cin >> ck_shift;
+  const int cps = nchunks / (int)gridDim.z;
+  const int nstep = (TAPS * ck + KSTEP - 1) / KSTEP;
+  float pmean, prstd, pA, pB;
+  src_consts<PRO>(a.src, pmean, prstd, pA, pB);
+  for (int ch = blockIdx.z * cps; ch < (int)(blockIdx.z + 1) * cps; ++ch) {
+    const int ci0 = ch << ck_shift;
+    stage_halo<MODE, HZ, HY, HX, PRO>(hal, hal_lo, a.src, n, ck, ckp, ci0, z0, y0, x0, R, pmean,
+                                      prstd, pA, pB);
+    // weight slab of this chunk: rows co0.., for every tap ck channels
+    {
+      constexpr int EV = MD::BF ? 8 : 4;  // elements per 16-byte vector
+      const int vpr = ck / EV;            // vectors per (row, tap)
+      const int nv = BN * TAPS * vpr;
+      for (int p = tid; p < nv; p += 256) {
+        const int r = p / (TAPS * vpr);
+        const int rem = p - r * TAPS * vpr;
+        const int tap = rem / vpr, q = rem - tap * vpr;
+        const int co = co0 + r;
+        const int o = r * wrp + tap * ck + q * EV;
+        u32x4 v = {0u, 0u, 0u, 0u}, vl = {0u, 0u, 0u, 0u};
+        if (co < a.w_rows) {
+          const size_t wi = ((size_t)co * TAPS + tap) * a.cin + ci0 + q * EV;
+          v = *reinterpret_cast<const u32x4*>(W + wi);
+          if constexpr (MD::SPLIT) vl = *reinterpret_cast<const u32x4*>(Wlo + wi);
+        }
+        if constexpr (MD::BF) {
+          *reinterpret_cast<u32x4*>(wsm + o) = v;
+          if constexpr (MD::SPLIT) *reinterpret_cast<u32x4*>(wsm_lo + o) = vl;
+        } else {
+          // FP32 rows are padded to an even pitch: 4-byte stores
+          ST* d = wsm + o;
+          d[0] = __uint_as_float(v.x);
+          d[1] = __uint_as_float(v.y);
+          d[2] = __uint_as_float(v.z);
+          d[3] = __uint_as_float(v.w);
+        }
+      }
+    }
     __syncthreads();
 #pragma unroll 2
-    for (int step = 0; step < NSTEP; ++step) {
+    for (int step = wave; step < nstep; step += 4) {
       const int kl = step * KSTEP + g * KPL;
-      const int tap = kl / CK, c = kl - tap * CK;
-      const bool kv = KEXACT || tap < TAPS;
+      const int tap = kl >> ck_shift, c = kl & (ck - 1);
+      const bool kv = tap < TAPS;
       const int toff = TAPS == 27 ? tap_offset(tap, HY, HX) : 0;
-      FT A[MTW], B[NT];
-      FT Al[MD::SPLIT ? MTW : 1], Bl[MD::SPLIT ? NT : 1];
+      FT A[MT], B[NT];
+      FT Al[MD::SPLIT ? MT : 1], Bl[MD::SPLIT ? NT : 1];
 #pragma unroll
-      for (int mt = 0; mt < MTW; ++mt) {
-        const int o = (apos[mt] + toff) * CKP + c;
-        A[mt] = lds_frag<MODE>(hal + o, kv);
-        if constexpr (MD::SPLIT) Al[mt] = lds_frag<MODE>(hal_lo + o, kv);
+      for (int mt = 0; mt < MT; ++mt) {
+        const int o = (apos[mt] + toff) * ckp + c;
+        A[mt] = frag<MODE>(hal + o, kv);
+        if constexpr (MD::SPLIT) Al[mt] = frag<MODE>(hal_lo + o, kv);
       }
 #pragma unroll
       for (int nt = 0; nt < NT; ++nt) {
-        const int co = co0 + nt * 16 + l16;
-        const bool ok = kv && co < a.w_rows;
-        const size_t wi = ((size_t)co * TAPS + tap) * a.cin + ci0 + c;
-        B[nt] = glb_frag<MODE>(W + wi, ok);
-        if constexpr (MD::SPLIT) Bl[nt] = glb_frag<MODE>(Wlo + wi, ok);
+        const int o = (nt * 16 + l16) * wrp + tap * ck + c;
+        B[nt] = frag<MODE>(wsm + o, kv);
+        if constexpr (MD::SPLIT) Bl[nt] = frag<MODE>(wsm_lo + o, kv);
       }
 #pragma unroll
-      for (int mt = 0; mt < MTW; ++mt)
+      for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
         for (int nt = 0; nt < NT; ++nt) {
           if constexpr (MD::SPLIT) {
@@ -240,43 +336,104 @@ __global__ __launch_bounds__(256) void k_conv_fwd(ConvFwd a) {
     __syncthreads();
   }
 
+  // cross-wave exchange: wave w finishes tiles t = w, w + 4, ... by adding the
+  // four waves' accumulators in wave order
+  f32x4* xch = reinterpret_cast<f32x4*>(smem);
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) xch[((wave * MT + mt) * NT + nt) * 64 + lane] = acc[mt][nt];
+  __syncthreads();
+  constexpr int NTILE = MT * NT;
+  constexpr int TPW = (NTILE + 3) / 4;  // tiles per wave
+  f32x4 fin[TPW];
+#pragma unroll
+  for (int j = 0; j < TPW; ++j) {
+    const int t = wave + 4 * j;
+    f32x4 v = (f32x4){0.f, 0.f, 0.f, 0.f};
+    if (t < NTILE) {
+#pragma unroll
+      for (int w = 0; w < 4; ++w) v += xch[(w * NTILE + t) * 64 + lane];
+    }
+    fin[j] = v;
+  }
+
+  const int tile_id = blockIdx.y * gridDim.x + blockIdx.x;
+  const size_t V = (size_t)n * n * n;
+  if (gridDim.z > 1) {
+    // split-K: publish this block's partial tile; the last block of the tile
+    // sums all partials in split order and continues with the epilogue
+    float* kp = a.kpart + (size_t)blockIdx.z * V * a.cout;
+#pragma unroll
+    for (int j = 0; j < TPW; ++j) {
+      const int t = wave + 4 * j;
+      if (t >= NTILE) continue;
+      const int mt = t / NT, nt = t - mt * NT;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int li = mt * 16 + 4 * g + r;
+        const int tz = li / (TY * TX), ty = (li / TX) % TY, tx = li % TX;
+        const int gz = z0 + tz, gy = y0 + ty, gx = x0 + tx;
+        const int co = co0 + nt * 16 + l16;
+        if (gz >= n || gy >= n || gx >= n || co >= a.cout) continue;
+        kp[((size_t)(gz * n + gy) * n + gx) * a.cout + co] = fin[j][r];
+      }
+    }
+    if (!arrive_last(a.counters + tile_id, gridDim.z)) return;
+#pragma unroll
+    for (int j = 0; j < TPW; ++j) {
+      const int t = wave + 4 * j;
+      if (t >= NTILE) continue;
+      const int mt = t / NT, nt = t - mt * NT;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int li = mt * 16 + 4 * g + r;
+        const int tz = li / (TY * TX), ty = (li / TX) % TY, tx = li % TX;
+        const int gz = z0 + tz, gy = y0 + ty, gx = x0 + tx;
+        const int co = co0 + nt * 16 + l16;
+        if (gz >= n || gy >= n || gx >= n || co >= a.cout) continue;
+        const size_t o = ((size_t)(gz * n + gy) * n + gx) * a.cout + co;
+        float sum = 0.f;
+        for (int k = 0; k < (int)gridDim.z; ++k) sum += load_dev(a.kpart + (size_t)k * V * a.cout + o);
+        fin[j][r] = sum;
+      }
+    }
+  }
+
   double s1 = 0.0, s2 = 0.0;
 #pragma unroll
-  for (int mt = 0; mt < MTW; ++mt) {
+  for (int j = 0; j < TPW; ++j) {
+    const int t = wave + 4 * j;
+    if (t >= NTILE) continue;
+    const int mt = t / NT, nt = t - mt * NT;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int li = (wave * MTW + mt) * 16 + 4 * g + r;
+      const int li = mt * 16 + 4 * g + r;
       const int tz = li / (TY * TX), ty = (li / TX) % TY, tx = li % TX;
       const int gz = z0 + tz, gy = y0 + ty, gx = x0 + tx;
-      if (gz >= n || gy >= n || gx >= n) continue;
-      const size_t vox = (size_t)(gz * n + gy) * n + gx;
-#pragma unroll
-      for (int nt = 0; nt < NT; ++nt) {
-        const int co = co0 + nt * 16 + l16;
-        if (co >= a.cout) continue;
-        const size_t o = vox * a.cout + co;
-        float v = acc[mt][nt][r];
-        if (a.bias) v += a.bias[co];
-        if (a.add) v += a.add[o];
-        if (a.accumulate) v += a.y[o];
-        a.y[o] = v;
-        s1 += v;
-        s2 += (double)v * v;
-      }
+      const int co = co0 + nt * 16 + l16;
+      if (gz >= n || gy >= n || gx >= n || co >= a.cout) continue;
+      const size_t o = ((size_t)(gz * n + gy) * n + gx) * a.cout + co;
+      float v = fin[j][r];
+      if (a.bias) v += a.bias[co];
+      if (a.add) v += a.add[o];
+      if (a.accumulate) v += a.y[o];
+      a.y[o] = v;
+      s1 += v;
+      s2 += (double)v * v;
     }
   }
   if (a.stat_part) {
     s1 = block_sum(s1, red);
     s2 = block_sum(s2, red);
     if (tid == 0) {
-      const size_t pb = (size_t)blockIdx.y * gridDim.x + blockIdx.x;
-      a.stat_part[2 * pb] = s1;
-      a.stat_part[2 * pb + 1] = s2;
+      a.stat_part[2 * tile_id] = s1;
+      a.stat_part[2 * tile_id + 1] = s2;
     }
   }
 }
 
-template <int MODE, int TAPS, int CK, int TILE, int PRO>
+template <int MODE, int TAPS, int TILE, int PRO, int GPRO>
 __global__ __launch_bounds__(256) void k_conv_wgrad(ConvWgrad a) {
   using MD = Mode<MODE>;
   using ST = typename MD::ST;
@@ -287,33 +444,47 @@ __global__ __launch_bounds__(256) void k_conv_wgrad(ConvWgrad a) {
   constexpr int HZ = TZ + 2 * R, HY = TY + 2 * R, HX = TX + 2 * R;
   constexpr int HP = HZ * HY * HX;
   constexpr int KPL = MD::KPL, KSTEP = MD::KSTEP;
-  constexpr int CKP = MD::BF ? CK + 8 : CK + 1;
   constexpr int BM = TZ * TY * TX;
-  constexpr int NTOT = TAPS * CK;
-  constexpr int NT = (NTOT + 15) / 16;
-  constexpr int NTW = (NT + 3) / 4;
   constexpr int GP = MD::BF ? BM + 8 : 17;  // g tile row pitch
   constexpr int GSZ = MD::BF ? 16 * GP : BM * GP;
-  __shared__ __align__(16) ST hal[HP * CKP];
-  __shared__ __align__(16) ST hal_lo[MD::SPLIT ? HP * CKP : 8];
+  __shared__ __align__(16) ST hal[HP * (kCkMax + MD::PAD)];
+  __shared__ __align__(16) ST hal_lo[MD::SPLIT ? HP * (kCkMax + MD::PAD) : 8];
   // BF16: gs[co][voxel]; FP32: gs[voxel][co]
   __shared__ __align__(16) ST gs[GSZ];
   __shared__ __align__(16) ST gs_lo[MD::SPLIT ? GSZ : 8];
-  __shared__ float bred[256];
+  __shared__ float4 bred[256];
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int l16 = lane & 15, g = lane >> 4;
   const int n = a.n;
+  const int ck = a.ck, ckp = ck + MD::PAD;
+  const int ck_shift = __builtin_ctz(ck);
+  const int ntot = TAPS * ck;
+  const int ngroups = (ntot + kWgCols - 1) / kWgCols;
+  const int chunk = blockIdx.y / ngroups, grp = blockIdx.y - chunk * ngroups;
   const int ntx = (n + TX - 1) / TX, nty = (n + TY - 1) / TY, ntz = (n + TZ - 1) / TZ;
   const int ntiles = ntx * nty * ntz;
-  const int ci0 = blockIdx.y * CK;
+  const int ci0 = chunk << ck_shift;
   const int co0 = blockIdx.z * 16;
-  const bool do_bias = a.partb != nullptr && blockIdx.y == 0;
+  const bool do_bias = blockIdx.y == 0;
 
-  f32x4 acc[NTW];
+  float gmean, grstd, gA, gB;
+  src_consts<GPRO>(a.gsrc, gmean, grstd, gA, gB);
+  float xmean, xrstd, xA, xB;
+  src_consts<PRO>(a.src, xmean, xrstd, xA, xB);
+
+  f32x4 acc[kWgNtw];
 #pragma unroll
-  for (int j = 0; j < NTW; ++j) acc[j] = (f32x4){0.f, 0.f, 0.f, 0.f};
-  float bacc = 0.f;
+  for (int j = 0; j < kWgNtw; ++j) acc[j] = (f32x4){0.f, 0.f, 0.f, 0.f};
+  float4 bacc = make_float4(0.f, 0.f, 0.f, 0.f);
+  // columns of this wave: nn = (grp*4*kWgNtw + wave*kWgNtw + j)*16 + l16
+  int ncol[kWgNtw], ctap[kWgNtw], cc[kWgNtw];
+#pragma unroll
+  for (int j = 0; j < kWgNtw; ++j) {
+    ncol[j] = ((grp * 4 + wave) * kWgNtw + j) * 16 + l16;
+    ctap[j] = ncol[j] >> ck_shift;
+    cc[j] = ncol[j] & (ck - 1);
+  }
 
   for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
     int b = t;
@@ -322,8 +493,8 @@ __global__ __launch_bounds__(256) void k_conv_wgrad(ConvWgrad a) {
     const int y0 = (b % nty) * TY;
     b /= nty;
     const int z0 = b * TZ;
-    stage_halo<MODE, CK, HZ, HY, HX, CKP, PRO>(hal, hal_lo, a.x, n, a.cin_stride, ci0, z0, y0, x0,
-                                               R, a.ln, a.ln_g, a.ln_b);
+    stage_halo<MODE, HZ, HY, HX, PRO>(hal, hal_lo, a.src, n, ck, ckp, ci0, z0, y0, x0, R, xmean,
+                                      xrstd, xA, xB);
     // g tile: BM voxels x 16 output channels (zero outside the grid / cout)
     for (int p = tid; p < BM * 4; p += 256) {
       const int v = p >> 2, q = p & 3;
@@ -332,7 +503,12 @@ __global__ __launch_bounds__(256) void k_conv_wgrad(ConvWgrad a) {
       const int co = co0 + 4 * q;
       float4 val = make_float4(0.f, 0.f, 0.f, 0.f);
       if (gz < n && gy < n && gx < n && co < a.cout)
-        val = *reinterpret_cast<const float4*>(a.g + ((size_t)(gz * n + gy) * n + gx) * a.cout + co);
+        val = load_src4<GPRO>(a.gsrc, ((size_t)(gz * n + gy) * n + gx) * a.cout + co, co, gmean,
+                              grstd, gA, gB);
+      bacc.x += val.x;
+      bacc.y += val.y;
+      bacc.z += val.z;
+      bacc.w += val.w;
       if constexpr (MD::BF) {
         const float e[4] = {val.x, val.y, val.z, val.w};
 #pragma unroll
@@ -355,39 +531,25 @@ __global__ __launch_bounds__(256) void k_conv_wgrad(ConvWgrad a) {
       }
     }
     __syncthreads();
-    // bias partial in FP32 from the unrounded gradient
-    if (do_bias) {
-      const int co = tid & 15;
-      if (co0 + co < a.cout) {
-        for (int v = tid >> 4; v < BM; v += 16) {
-          const int tz = v / (TY * TX), ty = (v / TX) % TY, tx = v % TX;
-          const int gz = z0 + tz, gy = y0 + ty, gx = x0 + tx;
-          if (gz < n && gy < n && gx < n)
-            bacc += a.g[((size_t)(gz * n + gy) * n + gx) * a.cout + co0 + co];
-        }
-      }
-    }
 #pragma unroll 2
     for (int ks = 0; ks < BM / KSTEP; ++ks) {
       FT A, Al;
-      FT B[NTW], Bl[MD::SPLIT ? NTW : 1];
+      FT B[kWgNtw], Bl[MD::SPLIT ? kWgNtw : 1];
       if constexpr (MD::BF) {
         const int v0 = ks * KSTEP + g * KPL;
         A = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u32x4*>(gs + l16 * GP + v0));
         if constexpr (MD::SPLIT)
           Al = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u32x4*>(gs_lo + l16 * GP + v0));
 #pragma unroll
-        for (int j = 0; j < NTW; ++j) {
-          const int nn = (wave + 4 * j) * 16 + l16;
+        for (int j = 0; j < kWgNtw; ++j) {
           uint16_t e[8], el[8];
-          if (nn < NTOT) {
-            const int tap = nn / CK, c = nn - tap * CK;
-            const int toff = TAPS == 27 ? tap_offset(tap, HY, HX) : 0;
+          if (ncol[j] < ntot) {
+            const int toff = TAPS == 27 ? tap_offset(ctap[j], HY, HX) : 0;
 #pragma unroll
             for (int q = 0; q < 8; ++q) {
               const int v = v0 + q;
               const int tz = v / (TY * TX), ty = (v / TX) % TY, tx = v % TX;
-              const int o = ((tz * HY + ty) * HX + tx + toff) * CKP + c;
+              const int o = ((tz * HY + ty) * HX + tx + toff) * ckp + cc[j];
               e[q] = hal[o];
               if constexpr (MD::SPLIT) el[q] = hal_lo[o];
             }
@@ -412,19 +574,17 @@ __global__ __launch_bounds__(256) void k_conv_wgrad(ConvWgrad a) {
         const int tz = v / (TY * TX), ty = (v / TX) % TY, tx = v % TX;
         const int vp = (tz * HY + ty) * HX + tx;
 #pragma unroll
-        for (int j = 0; j < NTW; ++j) {
-          const int nn = (wave + 4 * j) * 16 + l16;
+        for (int j = 0; j < kWgNtw; ++j) {
           float e = 0.f;
-          if (nn < NTOT) {
-            const int tap = nn / CK, c = nn - tap * CK;
-            const int toff = TAPS == 27 ? tap_offset(tap, HY, HX) : 0;
-            e = hal[(vp + toff) * CKP + c];
+          if (ncol[j] < ntot) {
+            const int toff = TAPS == 27 ? tap_offset(ctap[j], HY, HX) : 0;
+            e = hal[(vp + toff) * ckp + cc[j]];
           }
           B[j] = e;
         }
       }
 #pragma unroll
-      for (int j = 0; j < NTW; ++j) {
+      for (int j = 0; j < kWgNtw; ++j) {
         if constexpr (MD::SPLIT) {
           acc[j] = mfma(Al, B[j], acc[j]);
           acc[j] = mfma(A, Bl[j], acc[j]);
@@ -438,24 +598,25 @@ __global__ __launch_bounds__(256) void k_conv_wgrad(ConvWgrad a) {
   const int cout16 = (a.cout + 15) & ~15;
   float* part = a.part + (size_t)blockIdx.x * cout16 * TAPS * a.cin;
 #pragma unroll
-  for (int j = 0; j < NTW; ++j) {
-    const int nt = wave + 4 * j;
-    if (nt >= NT) continue;
-    const int nn = nt * 16 + l16;
-    if (nn >= NTOT) continue;
-    const int tap = nn / CK, c = nn - tap * CK;
+  for (int j = 0; j < kWgNtw; ++j) {
+    if (ncol[j] >= ntot) continue;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int co = co0 + 4 * g + r;
-      if (co < a.cout) part[((size_t)co * TAPS + tap) * a.cin + ci0 + c] = acc[j][r];
+      if (co < a.cout) part[((size_t)co * TAPS + ctap[j]) * a.cin + ci0 + cc[j]] = acc[j][r];
     }
   }
   if (do_bias) {
+    // threads with equal tid & 3 staged the same four channels
     bred[tid] = bacc;
     __syncthreads();
     if (tid < 16) {
+      const int q = tid >> 2, e = tid & 3;
       float s = 0.f;
-      for (int k = tid; k < 256; k += 16) s += bred[k];
+      for (int k = q; k < 256; k += 4) {
+        const float4 v = bred[k];
+        s += e == 0 ? v.x : e == 1 ? v.y : e == 2 ? v.z : v.w;
+      }
       if (co0 + tid < a.cout) a.partb[(size_t)blockIdx.x * cout16 + co0 + tid] = s;
     }
   }
@@ -468,8 +629,10 @@ __global__ __launch_bounds__(256) void k_conv_wgrad(ConvWgrad a) {
 inline void tile_dims(int tile, int& tz, int& ty, int& tx) {
   if (tile == TILE_2x4x16) {
     tz = 2; ty = 4; tx = 16;
+  } else if (tile == TILE_1x4x16) {
+    tz = 1; ty = 4; tx = 16;
   } else {
-    tz = 2; ty = 8; tx = 8;
+    tz = 1; ty = 8; tx = 8;
   }
 }
 
@@ -479,97 +642,78 @@ inline int spatial_tiles(int n, int tile) {
   return ((n + tx - 1) / tx) * ((n + ty - 1) / ty) * ((n + tz - 1) / tz);
 }
 
-inline int pick_ck(int cin) {
-  if (cin % 32 == 0) return 32;
-  if (cin % 16 == 0) return 16;
-  return 8;
-}
-
-inline int pick_bn(int cout) {
-  if (cout <= 16) return 16;
-  if (cout <= 32) return 32;
-  return 64;
-}
-
-template <int MODE, int TAPS, int CK, int TILE, int BN, int PRO>
+template <int MODE, int TAPS, int TILE, int BN, int PRO>
 void launch_fwd(const ConvFwd& a, hipStream_t s) {
-  dim3 grid(spatial_tiles(a.n, TILE), (a.cout + BN - 1) / BN);
-  hipLaunchKernelGGL((k_conv_fwd<MODE, TAPS, CK, TILE, BN, PRO>), grid, dim3(256), 0, s, a);
+  dim3 grid(spatial_tiles(a.n, TILE), (a.cout + BN - 1) / BN, a.ksplit);
+  const size_t lds = fwd_lds_bytes(TILE, TAPS, BN, a.ck, MODE);
+  hipLaunchKernelGGL((k_conv_fwd<MODE, TAPS, TILE, BN, PRO>), grid, dim3(256), lds, s, a);
 }
 
-template <int MODE, int TAPS, int CK, int TILE, int BN>
+template <int MODE, int TAPS, int TILE, int BN>
 void fwd_pro(const ConvFwd& a, hipStream_t s) {
-  if (a.prologue == PRO_LN_RELU && TAPS == 27)
-    launch_fwd<MODE, TAPS, CK, TILE, BN, PRO_LN_RELU>(a, s);
-  else
-    launch_fwd<MODE, TAPS, CK, TILE, BN, PRO_NONE>(a, s);
+  if constexpr (TAPS == 27) {
+    if (a.src.prologue == PRO_LN_RELU) return launch_fwd<MODE, TAPS, TILE, BN, PRO_LN_RELU>(a, s);
+    if (a.src.prologue == PRO_LN_BWD) return launch_fwd<MODE, TAPS, TILE, BN, PRO_LN_BWD>(a, s);
+  }
+  launch_fwd<MODE, TAPS, TILE, BN, PRO_NONE>(a, s);
 }
 
-template <int MODE, int TAPS, int CK, int TILE>
+// The 128-voxel tile holds at most 32 output channels per block (16
+// accumulator tiles per wave); the engine never asks it for 64.
+template <int MODE, int TAPS, int TILE>
 void fwd_bn(const ConvFwd& a, hipStream_t s) {
-  switch (pick_bn(a.cout)) {
-    case 16: fwd_pro<MODE, TAPS, CK, TILE, 16>(a, s); break;
-    case 32: fwd_pro<MODE, TAPS, CK, TILE, 32>(a, s); break;
-    default: fwd_pro<MODE, TAPS, CK, TILE, 64>(a, s); break;
+  switch (a.bn) {
+    case 16: fwd_pro<MODE, TAPS, TILE, 16>(a, s); break;
+    case 32: fwd_pro<MODE, TAPS, TILE, 32>(a, s); break;
+    default:
+      if constexpr (TILE != TILE_2x4x16) fwd_pro<MODE, TAPS, TILE, 64>(a, s);
+      break;
   }
 }
 
-template <int MODE, int TAPS, int CK>
+template <int MODE, int TAPS>
 void fwd_tile(const ConvFwd& a, hipStream_t s) {
-  if (a.tile == TILE_2x4x16)
-    fwd_bn<MODE, TAPS, CK, TILE_2x4x16>(a, s);
-  else
-    fwd_bn<MODE, TAPS, CK, TILE_2x8x8>(a, s);
-}
-
-template <int MODE, int TAPS>
-void fwd_ck(const ConvFwd& a, hipStream_t s) {
-  switch (pick_ck(a.cin)) {
-    case 32: fwd_tile<MODE, TAPS, 32>(a, s); break;
-    case 16: fwd_tile<MODE, TAPS, 16>(a, s); break;
-    default: fwd_tile<MODE, TAPS, 8>(a, s); break;
+  switch (a.tile) {
+    case TILE_2x4x16: fwd_bn<MODE, TAPS, TILE_2x4x16>(a, s); break;
+    case TILE_1x4x16: fwd_bn<MODE, TAPS, TILE_1x4x16>(a, s); break;
+    default: fwd_bn<MODE, TAPS, TILE_1x8x8>(a, s); break;
   }
 }
 
-template <int MODE, int TAPS, int CK, int TILE, int PRO>
+template <int MODE, int TAPS, int TILE, int PRO, int GPRO>
 void launch_wg(const ConvWgrad& a, hipStream_t s) {
-  dim3 grid(a.splits, a.cin / CK, (a.cout + 15) / 16);
-  hipLaunchKernelGGL((k_conv_wgrad<MODE, TAPS, CK, TILE, PRO>), grid, dim3(256), 0, s, a);
+  dim3 grid(a.splits, (a.cin / a.ck) * conv_wgrad_groups(a.taps, a.ck), (a.cout + 15) / 16);
+  hipLaunchKernelGGL((k_conv_wgrad<MODE, TAPS, TILE, PRO, GPRO>), grid, dim3(256), 0, s, a);
 }
 
-template <int MODE, int TAPS, int CK, int TILE>
+template <int MODE, int TAPS, int TILE>
 void wg_pro(const ConvWgrad& a, hipStream_t s) {
-  if (a.prologue == PRO_LN_RELU && TAPS == 27)
-    launch_wg<MODE, TAPS, CK, TILE, PRO_LN_RELU>(a, s);
-  else
-    launch_wg<MODE, TAPS, CK, TILE, PRO_NONE>(a, s);
-}
-
-template <int MODE, int TAPS, int CK>
-void wg_tile(const ConvWgrad& a, hipStream_t s) {
-  if (a.tile == TILE_2x4x16)
-    wg_pro<MODE, TAPS, CK, TILE_2x4x16>(a, s);
-  else
-    wg_pro<MODE, TAPS, CK, TILE_2x8x8>(a, s);
+  if constexpr (TAPS == 27) {
+    const bool xr = a.src.prologue == PRO_LN_RELU, gb = a.gsrc.prologue == PRO_LN_BWD;
+    if (xr && gb) return launch_wg<MODE, TAPS, TILE, PRO_LN_RELU, PRO_LN_BWD>(a, s);
+    if (xr) return launch_wg<MODE, TAPS, TILE, PRO_LN_RELU, PRO_NONE>(a, s);
+    if (gb) return launch_wg<MODE, TAPS, TILE, PRO_NONE, PRO_LN_BWD>(a, s);
+  }
+  launch_wg<MODE, TAPS, TILE, PRO_NONE, PRO_NONE>(a, s);
 }
 
 template <int MODE, int TAPS>
-void wg_ck(const ConvWgrad& a, hipStream_t s) {
-  switch (pick_ck(a.cin)) {
-    case 32: wg_tile<MODE, TAPS, 32>(a, s); break;
-    case 16: wg_tile<MODE, TAPS, 16>(a, s); break;
-    default: wg_tile<MODE, TAPS, 8>(a, s); break;
+void wg_tile(const ConvWgrad& a, hipStream_t s) {
+  switch (a.tile) {
+    case TILE_2x4x16: wg_pro<MODE, TAPS, TILE_2x4x16>(a, s); break;
+    case TILE_1x4x16: wg_pro<MODE, TAPS, TILE_1x4x16>(a, s); break;
+    default: wg_pro<MODE, TAPS, TILE_1x8x8>(a, s); break;
   }
 }
 
 template <int MODE>
 void conv_fwd_mode(const ConvFwd& a, hipStream_t s) {
-  if (a.taps == 27) fwd_ck<MODE, 27>(a, s); else fwd_ck<MODE, 1>(a, s);
+  if (a.taps == 27) fwd_tile<MODE, 27>(a, s); else fwd_tile<MODE, 1>(a, s);
 }
 
 template <int MODE>
 void conv_wgrad_mode(const ConvWgrad& a, hipStream_t s) {
-  if (a.taps == 27) wg_ck<MODE, 27>(a, s); else wg_ck<MODE, 1>(a, s);
+  if (a.taps == 27) wg_tile<MODE, 27>(a, s); else wg_tile<MODE, 1>(a, s);
 }
 
 }  // namespace conv_detail

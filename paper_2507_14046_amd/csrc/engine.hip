@@ -29,7 +29,6 @@ d2ip_status fail(d2ip_status s, const std::string& m) {
       return fail(D2IP_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_));     \
   } while (0)
 
-constexpr float kLnEps = 1e-5f;
 
 struct Carver {
   char* base = nullptr;
@@ -43,11 +42,20 @@ struct Carver {
   }
 };
 
+// Launch shape of one conv role (forward or input gradient).
+struct Shape {
+  int tile = TILE_2x4x16, bn = 16, ck = 8, ksplit = 1;
+};
+
 struct Conv {
   int th_w = -1, th_b = -1;
   int cin_real = 0, cin = 0, cout = 0, taps = 0;
   long long wf = 0, wd = 0;
   bool dgrad = false;
+  int n = 0;
+  Shape fwd, bwd;          // forward / input-gradient launch shapes
+  int wg_tile = 0, wg_ck = 8, wg_splits = 1;
+  long long wg_off = 0, wgb_off = 0;  // partial regions of the weight gradient
 };
 
 struct Norm {
@@ -61,18 +69,18 @@ struct Block {
   Conv c1, c2, pj;
   Norm n1, n2;
   float *x = nullptr, *h1 = nullptr, *h2 = nullptr, *s = nullptr, *y = nullptr;
-  const float* pool_src = nullptr;  // encoder l >= 1: output of encoder l-1
+  float* pool_out = nullptr;        // encoder l < L-1: input of encoder l+1
   const float* up_src = nullptr;    // decoder: output of the level below
   const float* skip_src = nullptr;  // decoder: output of encoder l
-  LnStat *st1 = nullptr, *st2 = nullptr;
-  LnBwd *cb1 = nullptr, *cb2 = nullptr;
+  PairRef st1{}, st2{};         // forward statistics partials of h1, h2
+  PairRef cb1{}, cb2{};         // LayerNorm-backward coefficient partials
+  double *lnc1 = nullptr, *lnc2 = nullptr;  // per-channel dgamma/dbeta partials
 };
 
 struct Level {
   int n = 0, c = 0;
   size_t V = 0;
-  float *gy = nullptr, *gz = nullptr, *gh = nullptr, *ga = nullptr, *gx = nullptr,
-        *genc = nullptr;
+  float *gy = nullptr, *gz = nullptr, *ga = nullptr, *gx = nullptr, *genc = nullptr;
 };
 
 struct Geometry {
@@ -89,7 +97,6 @@ struct Geometry {
 struct Instance {
   int geo = 0, L = 0, C = 0, n = 0;
   size_t V0 = 0, P = 0;
-  int tile = TILE_2x4x16;
   float *theta = nullptr, *grad = nullptr, *m = nullptr, *v = nullptr;
   float* wf32 = nullptr;
   uint16_t* wbf16 = nullptr;
@@ -97,25 +104,29 @@ struct Instance {
   std::vector<ConvPack> packs;
   ConvPack* packs_dev = nullptr;
   int max_pack = 0;
+  std::vector<GradSeg> segs;
+  GradSeg* segs_dev = nullptr;
+  int max_seg = 0;
+  float *wg_part = nullptr, *wg_partb = nullptr;
+  long long wg_total = 0, wgb_total = 0;
   float* zpad = nullptr;
   Conv stem;
   Norm stem_n;
   float *hs = nullptr, *as = nullptr;
-  LnStat* sts = nullptr;
-  LnBwd* cbs = nullptr;
+  PairRef sts{}, cbs{};
+  double* lncs = nullptr;
   std::vector<Block> blocks;
   int tail_w = -1, tail_b = -1;
   float *sigma = nullptr, *dv = nullptr;
   IterState* it = nullptr;
   std::vector<Level> lv;
-  double* stat_part = nullptr;
-  double* lnb_part = nullptr;
-  float *ppart = nullptr, *gp = nullptr, *tpart = nullptr;
+  double* dpart = nullptr;   // FP64 partial arena (statistics, LN and head gradients)
+  long long dtotal = 0;
+  float *ppart = nullptr, *tpart = nullptr;
   double* tail_part = nullptr;
+  double* rsum = nullptr;
   bool has_frame = false, has_z = false;
 };
-
-int tile_for(int n) { return n % 16 == 0 ? TILE_2x4x16 : TILE_2x8x8; }
 
 int conv_prec(int precision) {
   if (precision == D2IP_BF16_CONV) return PREC_BF16;
@@ -123,38 +134,59 @@ int conv_prec(int precision) {
   return PREC_F32;
 }
 
-}  // namespace
+int pick_tile(int n) {
+  if (n % 16 == 0) return n >= 32 ? TILE_2x4x16 : TILE_1x4x16;
+  return TILE_1x8x8;
+}
 
-struct d2ip_ctx {
-  int precision = D2IP_PLAIN_FP32;
-  unsigned flags = 0;
-  hipStream_t stream = nullptr;
-  std::vector<Geometry> geos;
-  std::vector<Instance> insts;
-  float* wg_part = nullptr;
-  float* wg_partb = nullptr;
-  float lr = 1e-3f, b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t gexec = nullptr;
-  hipStream_t cap = nullptr;  // capture stream (the caller's may be the legacy default stream)
-  size_t bytes = 0;
-};
+int largest_ck(int cin) { return cin % 32 == 0 ? 32 : cin % 16 == 0 ? 16 : 8; }
 
-namespace {
+constexpr int kTargetBlocks = 256;
+constexpr size_t kLdsBudget = 64 * 1024;
 
-// ---------------------------------------------------------------------------
-// plan: parameter layout, packing table and workspace carve
-// ---------------------------------------------------------------------------
+// Enough blocks to cover the chip: narrow N tiles and channel split-K on
+// coarse grids, wide N tiles and whole-channel chunks on fine ones; the halo
+// plus weight slab must fit the LDS budget (two blocks per CU).
+Shape choose_shape(int n, int cin, int cout, int taps, int prec) {
+  Shape s;
+  s.tile = pick_tile(n);
+  s.bn = cout <= 16 ? 16 : cout <= 32 ? 32 : 64;
+  if (s.tile == TILE_2x4x16 && s.bn > 32) s.bn = 32;  // <= 16 accumulator tiles per wave
+  const int tiles = conv_tiles(n, s.tile);
+  auto blocks = [&](int bn) { return tiles * ((cout + bn - 1) / bn); };
+  if (blocks(s.bn) < kTargetBlocks) s.bn = 16;
+  s.ck = largest_ck(cin);
+  while (conv_fwd_lds_bytes(s.tile, taps, s.bn, s.ck, prec) > kLdsBudget) {
+    if (s.ck > 8)
+      s.ck >>= 1;
+    else if (s.bn > 16)
+      s.bn >>= 1;
+    else
+      break;
+  }
+  const int base = blocks(s.bn);
+  if (base < kTargetBlocks) {
+    const int want = (kTargetBlocks + base - 1) / base;
+    while (s.ck > 8 && cin / s.ck < want) s.ck >>= 1;
+    const int nch = cin / s.ck;
+    int ks = std::min(want, nch);
+    while (nch % ks != 0) --ks;
+    s.ksplit = ks;
+  }
+  return s;
+}
 
 d2ip_status check_desc(const d2ip_geometry_desc* geos, int n_geo, const d2ip_instance_desc* insts,
                        int n_inst, int precision) {
-  if (!geos || n_geo <= 0 || !insts || n_inst <= 0) return fail(D2IP_EINVAL, "empty geometry or instance list");
+  if (!geos || n_geo <= 0 || !insts || n_inst <= 0)
+    return fail(D2IP_EINVAL, "empty geometry or instance list");
   if (precision != D2IP_PLAIN_FP32 && precision != D2IP_BF16_CONV &&
       precision != D2IP_BF16X3_CONV)
     return fail(D2IP_EINVAL, "unknown precision");
   for (int g = 0; g < n_geo; ++g) {
     if (geos[g].n < 4 || geos[g].n > 256 || geos[g].M <= 0 || geos[g].M > 65536)
-      return fail(D2IP_EINVAL, "geometry " + std::to_string(g) + ": n must be in [4, 256], M in [1, 65536]");
+      return fail(D2IP_EINVAL,
+                  "geometry " + std::to_string(g) + ": n must be in [4, 256], M in [1, 65536]");
   }
   for (int i = 0; i < n_inst; ++i) {
     const d2ip_instance_desc& d = insts[i];
@@ -168,7 +200,8 @@ d2ip_status check_desc(const d2ip_geometry_desc* geos, int n_geo, const d2ip_ins
       return fail(D2IP_EINVAL, "instance " + std::to_string(i) + ": base_ch * 2^(levels-1) > 256");
     const int n = geos[d.geometry].n, f = 1 << (d.levels - 1);
     if (n % f != 0 || n / f < 2)
-      return fail(D2IP_EINVAL, "instance " + std::to_string(i) + ": grid not divisible by 2^(levels-1)");
+      return fail(D2IP_EINVAL,
+                  "instance " + std::to_string(i) + ": grid not divisible by 2^(levels-1)");
   }
   return D2IP_OK;
 }
@@ -176,7 +209,7 @@ d2ip_status check_desc(const d2ip_geometry_desc* geos, int n_geo, const d2ip_ins
 // Parameter offsets of one network in the flat order.
 struct LayoutBuilder {
   int off = 0;
-  Conv conv(int cout, int cin, int k) {
+  Conv conv(int cout, int cin, int k, int n) {
     Conv c;
     c.th_w = off;
     off += cout * cin * k * k * k;
@@ -187,6 +220,7 @@ struct LayoutBuilder {
     c.cin = (cin + 7) / 8 * 8;
     c.taps = k * k * k;
     c.dgrad = true;
+    c.n = n;
     return c;
   }
   Norm norm(int c) {
@@ -202,18 +236,18 @@ struct LayoutBuilder {
 void make_block(LayoutBuilder& lb, Block& b, int cin, int cout) {
   b.cin = cin;
   b.cout = cout;
-  b.c1 = lb.conv(cout, cin, 3);
+  b.c1 = lb.conv(cout, cin, 3, b.n);
   b.n1 = lb.norm(cout);
-  b.c2 = lb.conv(cout, cout, 3);
+  b.c2 = lb.conv(cout, cout, 3, b.n);
   b.n2 = lb.norm(cout);
   b.proj = cin != cout;
-  if (b.proj) b.pj = lb.conv(cout, cin, 1);
+  if (b.proj) b.pj = lb.conv(cout, cin, 1, b.n);
 }
 
 size_t layout(Instance& I) {
   LayoutBuilder lb;
   const int C = I.C, L = I.L;
-  I.stem = lb.conv(C, 1, 3);
+  I.stem = lb.conv(C, 1, 3, I.n);
   I.stem.dgrad = false;
   I.stem_n = lb.norm(C);
   I.blocks.clear();
@@ -233,13 +267,14 @@ size_t layout(Instance& I) {
     make_block(lb, b, (C << (l + 1)) + (C << l), C << l);
     I.blocks.push_back(b);
   }
-  Conv t = lb.conv(1, C, 1);
+  Conv t = lb.conv(1, C, 1, I.n);
   I.tail_w = t.th_w;
   I.tail_b = t.th_b;
   return (size_t)lb.off;
 }
 
-void add_pack(Instance& I, Conv& c) {
+// Launch shapes, packing table and weight-gradient partial regions of a conv.
+void add_conv(Instance& I, Conv& c, int prec, size_t& kpart_max, int& tiles_max) {
   c.wf = I.wtotal;
   I.wtotal += (long long)c.cout * c.taps * c.cin;
   if (c.dgrad) {
@@ -256,48 +291,62 @@ void add_pack(Instance& I, Conv& c) {
   p.wf_off = c.wf;
   p.wd_off = c.wd;
   I.packs.push_back(p);
-  const int e = c.cout * c.cin_real * c.taps;
-  if (e > I.max_pack) I.max_pack = e;
+  I.max_pack = std::max(I.max_pack, c.cout * c.cin_real * c.taps);
+
+  const size_t V = (size_t)c.n * c.n * c.n;
+  c.fwd = choose_shape(c.n, c.cin, c.cout, c.taps, prec);
+  tiles_max = std::max(tiles_max, conv_tiles(c.n, c.fwd.tile) * ((c.cout + c.fwd.bn - 1) / c.fwd.bn));
+  if (c.fwd.ksplit > 1) kpart_max = std::max(kpart_max, (size_t)c.fwd.ksplit * V * c.cout);
+  if (c.dgrad) {
+    c.bwd = choose_shape(c.n, c.cout, c.cin_real, c.taps, prec);
+    tiles_max = std::max(tiles_max,
+                         conv_tiles(c.n, c.bwd.tile) * ((c.cin_real + c.bwd.bn - 1) / c.bwd.bn));
+    if (c.bwd.ksplit > 1) kpart_max = std::max(kpart_max, (size_t)c.bwd.ksplit * V * c.cin_real);
+  }
+  // weight gradient: voxel splits sized so that about 512 blocks run
+  c.wg_tile = pick_tile(c.n);
+  c.wg_ck = largest_ck(c.cin);
+  const int cout16 = (c.cout + 15) / 16 * 16;
+  const int per = (c.cin / c.wg_ck) * conv_wgrad_groups(c.taps, c.wg_ck) * (cout16 / 16);
+  const int tiles = conv_tiles(c.n, c.wg_tile);
+  c.wg_splits = std::max(1, std::min(std::min(tiles, 64), (512 + per - 1) / per));
+  c.wg_off = I.wg_total;
+  I.wg_total += (long long)c.wg_splits * cout16 * c.taps * c.cin;
+  c.wgb_off = I.wgb_total;
+  I.wgb_total += (long long)c.wg_splits * cout16;
+  GradSeg sg;
+  sg.kind = 0;
+  sg.part_off = c.wg_off;
+  sg.partb_off = c.wgb_off;
+  sg.splits = c.wg_splits;
+  sg.cout = c.cout;
+  sg.taps = c.taps;
+  sg.cin = c.cin;
+  sg.cin_real = c.cin_real;
+  sg.th_w = c.th_w;
+  sg.th_b = c.th_b;
+  I.segs.push_back(sg);
+  I.max_seg = std::max(I.max_seg, c.cout * c.cin_real * c.taps);
 }
 
-ConvFwd fwd_args(const Instance& I, int prec, const Conv& c, int n, const float* x, int cin_stride,
-                 float* y) {
-  ConvFwd a;
-  std::memset(&a, 0, sizeof(a));
-  a.x = x;
-  a.n = n;
-  a.cin = c.cin;
-  a.cin_stride = cin_stride;
-  a.w = prec != PREC_F32 ? (const void*)(I.wbf16 + c.wf) : (const void*)(I.wf32 + c.wf);
-  a.w_lo_off = prec == PREC_BF16X3 ? I.wtotal : 0;
-  a.w_rows = c.cout;
-  a.cout = c.cout;
-  a.y = y;
-  a.taps = c.taps;
-  a.prologue = PRO_NONE;
-  a.prec = prec;
-  a.tile = tile_for(n);
-  return a;
-}
+}  // namespace
 
-ConvFwd dgrad_args(const Instance& I, int prec, const Conv& c, int n, const float* g, float* y) {
-  ConvFwd a;
-  std::memset(&a, 0, sizeof(a));
-  a.x = g;
-  a.n = n;
-  a.cin = c.cout;
-  a.cin_stride = c.cout;
-  a.w = prec != PREC_F32 ? (const void*)(I.wbf16 + c.wd) : (const void*)(I.wf32 + c.wd);
-  a.w_lo_off = prec == PREC_BF16X3 ? I.wtotal : 0;
-  a.w_rows = c.cin_real;
-  a.cout = c.cin_real;
-  a.y = y;
-  a.taps = c.taps;
-  a.prologue = PRO_NONE;
-  a.prec = prec;
-  a.tile = tile_for(n);
-  return a;
-}
+struct d2ip_ctx {
+  int precision = D2IP_PLAIN_FP32;
+  unsigned flags = 0;
+  hipStream_t stream = nullptr;
+  std::vector<Geometry> geos;
+  std::vector<Instance> insts;
+  float* kpart = nullptr;   // split-K partial outputs (shared, sequential use)
+  int* counters = nullptr;  // zeroed arrival counters (shared, sequential use)
+  float lr = 1e-3f, b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  hipStream_t cap = nullptr;  // capture stream (the caller's may be the legacy default stream)
+  size_t bytes = 0;
+};
+
+namespace {
 
 // Carve the workspace (base == nullptr: only count bytes).
 void plan(d2ip_ctx& X, const d2ip_geometry_desc* gd, int n_geo, const d2ip_instance_desc* id,
@@ -315,7 +364,9 @@ void plan(d2ip_ctx& X, const d2ip_geometry_desc* gd, int n_geo, const d2ip_insta
     G.mask = cv.take<float>(G.Q);
   }
   X.insts.assign(n_inst, Instance());
-  size_t wg_max = 0, wgb_max = 0;
+  size_t kpart_max = 0;
+  int tiles_max = 1;
+  const int prec = conv_prec(X.precision);
   for (int i = 0; i < n_inst; ++i) {
     Instance& I = X.insts[i];
     I.geo = id[i].geometry;
@@ -324,17 +375,65 @@ void plan(d2ip_ctx& X, const d2ip_geometry_desc* gd, int n_geo, const d2ip_insta
     const Geometry& G = X.geos[I.geo];
     I.n = G.n;
     I.V0 = G.Q;
-    I.tile = tile_for(I.n);
     I.P = layout(I);
     I.packs.clear();
+    I.segs.clear();
     I.wtotal = 0;
     I.max_pack = 0;
-    add_pack(I, I.stem);
+    I.wg_total = 0;
+    I.wgb_total = 0;
+    add_conv(I, I.stem, prec, kpart_max, tiles_max);
     for (Block& b : I.blocks) {
-      add_pack(I, b.c1);
-      add_pack(I, b.c2);
-      if (b.proj) add_pack(I, b.pj);
+      add_conv(I, b.c1, prec, kpart_max, tiles_max);
+      add_conv(I, b.c2, prec, kpart_max, tiles_max);
+      if (b.proj) add_conv(I, b.pj, prec, kpart_max, tiles_max);
     }
+    // FP64 partial arena: statistics of every LayerNorm input, LayerNorm
+    // backward partials, head gradient and residual sums (offsets in doubles)
+    auto dtake = [&](size_t nd) {
+      const long long o = I.dtotal;
+      I.dtotal += (long long)((nd + 31) / 32 * 32);
+      return o;
+    };
+    auto fwd_tiles = [](const Conv& c) {
+      return conv_tiles(c.n, c.fwd.tile) * ((c.cout + c.fwd.bn - 1) / c.fwd.bn);
+    };
+    auto ln_seg = [&](long long off, int nblk, int C2, int th_g) {
+      GradSeg sg;
+      std::memset(&sg, 0, sizeof(sg));
+      sg.kind = 1;
+      sg.part_off = off;
+      sg.splits = nblk;
+      sg.cout = C2;
+      sg.th_w = th_g;
+      I.segs.push_back(sg);
+      I.max_seg = std::max(I.max_seg, C2);
+    };
+    const size_t V0 = I.V0;
+    const int C = I.C;
+    const int nb0 = ln_bwd_blocks(V0, C);
+    const long long o_sts = dtake(2 * (size_t)fwd_tiles(I.stem));
+    const long long o_cbs = dtake(2 * (size_t)nb0);
+    const long long o_lncs = dtake((size_t)nb0 * 2 * C);
+    ln_seg(o_lncs, nb0, 2 * C, I.stem_n.th_g);
+    std::vector<long long> o_st1, o_st2, o_cb1, o_cb2, o_lnc1, o_lnc2;
+    for (Block& b : I.blocks) {
+      const size_t V = (size_t)b.n * b.n * b.n;
+      const int nb = ln_bwd_blocks(V, b.cout);
+      o_st1.push_back(dtake(2 * (size_t)fwd_tiles(b.c1)));
+      o_st2.push_back(dtake(2 * (size_t)fwd_tiles(b.c2)));
+      o_cb1.push_back(dtake(2 * (size_t)nb));
+      o_cb2.push_back(dtake(2 * (size_t)nb));
+      o_lnc1.push_back(dtake((size_t)nb * 2 * b.cout));
+      o_lnc2.push_back(dtake((size_t)nb * 2 * b.cout));
+      ln_seg(o_lnc1.back(), nb, 2 * b.cout, b.n1.th_g);
+      ln_seg(o_lnc2.back(), nb, 2 * b.cout, b.n2.th_g);
+    }
+    const int ntb = tail_bwd_blocks(V0, C);
+    const long long o_tail = dtake((size_t)ntb * (C + 1));
+    ln_seg(o_tail, ntb, C + 1, I.tail_w);
+    const long long o_rsum = dtake(jt_mblocks(G.M));
+
     I.theta = cv.take<float>(I.P);
     I.grad = cv.take<float>(I.P);
     I.m = cv.take<float>(I.P);
@@ -346,32 +445,17 @@ void plan(d2ip_ctx& X, const d2ip_geometry_desc* gd, int n_geo, const d2ip_insta
     else
       I.wf32 = cv.take<float>(I.wtotal);
     I.packs_dev = cv.take<ConvPack>(I.packs.size());
-    const size_t V0 = I.V0;
-    const int C = I.C;
+    I.segs_dev = cv.take<GradSeg>(I.segs.size());
+    I.wg_part = cv.take<float>(I.wg_total);
+    I.wg_partb = cv.take<float>(I.wgb_total);
+    I.dpart = cv.take<double>(I.dtotal);
+    auto dp = [&](long long off) { return I.dpart ? I.dpart + off : nullptr; };
     I.zpad = cv.take<float>(V0 * 8);
     I.hs = cv.take<float>(V0 * C);
     I.as = cv.take<float>(V0 * C);
-    I.sts = cv.take<LnStat>(1);
-    I.cbs = cv.take<LnBwd>(1);
-    int max_conv_blocks = 0;
-    size_t max_lnb = 0;
-    auto note_conv = [&](const Conv& c, int n) {
-      ConvFwd a;
-      std::memset(&a, 0, sizeof(a));
-      a.n = n;
-      a.cout = c.cout;
-      a.tile = tile_for(n);
-      max_conv_blocks = std::max(max_conv_blocks, conv_fwd_blocks(a));
-      if (c.dgrad) {
-        a.cout = c.cin_real;
-        max_conv_blocks = std::max(max_conv_blocks, conv_fwd_blocks(a));
-      }
-      wg_max = std::max(wg_max, conv_wgrad_part_floats(n, c.cin, c.cout, c.taps, tile_for(n)));
-      wgb_max = std::max(wgb_max, (size_t)conv_wgrad_splits(n, c.cin, c.cout, tile_for(n)) *
-                                      ((c.cout + 15) / 16 * 16));
-    };
-    note_conv(I.stem, I.n);
-    max_lnb = std::max(max_lnb, (size_t)ln_bwd_blocks(V0, C) * C);
+    I.sts = PairRef{dp(o_sts), fwd_tiles(I.stem), (double)V0 * C};
+    I.cbs = PairRef{dp(o_cbs), nb0, (double)V0 * C};
+    I.lncs = dp(o_lncs);
     I.lv.assign(I.L, Level());
     for (int l = 0; l < I.L; ++l) {
       Level& Lv = I.lv[l];
@@ -380,40 +464,34 @@ void plan(d2ip_ctx& X, const d2ip_geometry_desc* gd, int n_geo, const d2ip_insta
       Lv.V = (size_t)Lv.n * Lv.n * Lv.n;
       Lv.gy = cv.take<float>(Lv.V * Lv.c);
       Lv.gz = cv.take<float>(Lv.V * Lv.c);
-      Lv.gh = cv.take<float>(Lv.V * Lv.c);
       Lv.ga = cv.take<float>(Lv.V * Lv.c);
       Lv.gx = cv.take<float>(Lv.V * Lv.c * 3);
       Lv.genc = cv.take<float>(Lv.V * Lv.c);
-      max_lnb = std::max(max_lnb, (size_t)ln_bwd_blocks(Lv.V, Lv.c) * Lv.c);
     }
     const int L = I.L;
     for (size_t k = 0; k < I.blocks.size(); ++k) {
       Block& b = I.blocks[k];
       const size_t V = (size_t)b.n * b.n * b.n;
-      if (b.enc) {
-        if (b.level == 0) {
-          b.x = I.as;
-        } else {
-          b.x = cv.take<float>(V * b.cin);
-          b.pool_src = I.blocks[b.level - 1].y;
-        }
-      } else {
+      if (b.enc && b.level == 0)
+        b.x = I.as;
+      else if (b.enc)
+        b.x = I.blocks[b.level - 1].pool_out;
+      else
         b.x = cv.take<float>(V * b.cin);
-      }
       b.h1 = cv.take<float>(V * b.cout);
       b.h2 = cv.take<float>(V * b.cout);
       b.y = cv.take<float>(V * b.cout);
       if (b.proj) b.s = cv.take<float>(V * b.cout);
-      b.st1 = cv.take<LnStat>(1);
-      b.st2 = cv.take<LnStat>(1);
-      b.cb1 = cv.take<LnBwd>(1);
-      b.cb2 = cv.take<LnBwd>(1);
-      note_conv(b.c1, b.n);
-      note_conv(b.c2, b.n);
-      if (b.proj) note_conv(b.pj, b.n);
-      if (b.enc && b.level > 0) b.pool_src = I.blocks[b.level - 1].y;
+      if (b.enc && b.level < L - 1) b.pool_out = cv.take<float>(V / 8 * b.cout);
+      const int nb = ln_bwd_blocks(V, b.cout);
+      const double cnt = (double)V * b.cout;
+      b.st1 = PairRef{dp(o_st1[k]), fwd_tiles(b.c1), cnt};
+      b.st2 = PairRef{dp(o_st2[k]), fwd_tiles(b.c2), cnt};
+      b.cb1 = PairRef{dp(o_cb1[k]), nb, cnt};
+      b.cb2 = PairRef{dp(o_cb2[k]), nb, cnt};
+      b.lnc1 = dp(o_lnc1[k]);
+      b.lnc2 = dp(o_lnc2[k]);
     }
-    // decoder sources (after every block has its output buffer)
     for (size_t k = L; k < I.blocks.size(); ++k) {
       Block& b = I.blocks[k];
       b.up_src = (b.level == L - 2) ? I.blocks[L - 1].y : I.blocks[k - 1].y;
@@ -422,132 +500,183 @@ void plan(d2ip_ctx& X, const d2ip_geometry_desc* gd, int n_geo, const d2ip_insta
     I.sigma = cv.take<float>(V0);
     I.dv = cv.take<float>(G.M);
     I.it = cv.take<IterState>(1);
-    I.stat_part = cv.take<double>(2 * (size_t)max_conv_blocks);
-    I.lnb_part = cv.take<double>(2 * max_lnb);
     I.ppart = cv.take<float>((size_t)jvec_qblocks(G.qa_cap) * G.M);
-    I.gp = cv.take<float>(G.M);
     I.tpart = cv.take<float>((size_t)jt_mblocks(G.M) * G.qa_cap);
-    I.tail_part = cv.take<double>((size_t)tail_bwd_blocks(V0, C) * (C + 1));
+    I.tail_part = dp(o_tail);
+    I.rsum = dp(o_rsum);
   }
-  X.wg_part = cv.take<float>(wg_max);
-  X.wg_partb = cv.take<float>(wgb_max);
+  X.kpart = cv.take<float>(std::max<size_t>(kpart_max, 1));
+  X.counters = cv.take<int>((size_t)tiles_max + 64);
 }
 
 // ---------------------------------------------------------------------------
 // launch schedule
 // ---------------------------------------------------------------------------
 
-void conv_fwd_stats(d2ip_ctx& X, Instance& I, ConvFwd a, LnStat* st) {
-  a.stat_part = I.stat_part;
-  conv_fwd(a, X.stream);
-  ln_finalize(I.stat_part, conv_fwd_blocks(a), (double)a.n * a.n * a.n * a.cout, kLnEps, st,
-              X.stream);
+ConvSrc src_plain(const float* x, int stride) {
+  ConvSrc s;
+  std::memset(&s, 0, sizeof(s));
+  s.x = x;
+  s.stride = stride;
+  s.prologue = PRO_NONE;
+  return s;
 }
 
-void wgrad(d2ip_ctx& X, Instance& I, const Conv& c, int n, const float* x, int cin_stride,
-           const float* g, int pro, const LnStat* st, const float* lg, const float* lb) {
+ConvSrc src_ln_relu(const float* h, int stride, const PairRef& st, const float* g,
+                    const float* b) {
+  ConvSrc s = src_plain(h, stride);
+  s.prologue = PRO_LN_RELU;
+  s.st = st;
+  s.gamma = g;
+  s.beta = b;
+  return s;
+}
+
+ConvSrc src_ln_bwd(const float* gz, const float* h, int stride, const PairRef& st,
+                   const float* g, const PairRef& cb) {
+  ConvSrc s = src_plain(gz, stride);
+  s.prologue = PRO_LN_BWD;
+  s.h = h;
+  s.st = st;
+  s.gamma = g;
+  s.bw = cb;
+  return s;
+}
+
+// Forward conv: y = conv(src) + bias, with LayerNorm statistics into `st`.
+ConvFwd fwd_args(const d2ip_ctx& X, const Instance& I, const Conv& c, ConvSrc src, float* y,
+                 const PairRef* st) {
+  const int prec = conv_prec(X.precision);
+  ConvFwd a;
+  std::memset(&a, 0, sizeof(a));
+  a.src = src;
+  a.n = c.n;
+  a.cin = c.cin;
+  a.w = prec != PREC_F32 ? (const void*)(I.wbf16 + c.wf) : (const void*)(I.wf32 + c.wf);
+  a.w_lo_off = prec == PREC_BF16X3 ? I.wtotal : 0;
+  a.w_rows = c.cout;
+  a.bias = I.theta + c.th_b;
+  a.cout = c.cout;
+  a.y = y;
+  a.taps = c.taps;
+  a.stat_part = st ? const_cast<double*>(st->part) : nullptr;
+  a.prec = prec;
+  a.tile = c.fwd.tile;
+  a.bn = c.fwd.bn;
+  a.ck = c.fwd.ck;
+  a.ksplit = c.fwd.ksplit;
+  a.kpart = X.kpart;
+  a.counters = X.counters;
+  return a;
+}
+
+// Input gradient: y (+)= conv^T(src) (+ add).
+ConvFwd dgrad_args(const d2ip_ctx& X, const Instance& I, const Conv& c, ConvSrc src, float* y) {
+  const int prec = conv_prec(X.precision);
+  ConvFwd a;
+  std::memset(&a, 0, sizeof(a));
+  a.src = src;
+  a.n = c.n;
+  a.cin = c.cout;
+  a.w = prec != PREC_F32 ? (const void*)(I.wbf16 + c.wd) : (const void*)(I.wf32 + c.wd);
+  a.w_lo_off = prec == PREC_BF16X3 ? I.wtotal : 0;
+  a.w_rows = c.cin_real;
+  a.cout = c.cin_real;
+  a.y = y;
+  a.taps = c.taps;
+  a.prec = prec;
+  a.tile = c.bwd.tile;
+  a.bn = c.bwd.bn;
+  a.ck = c.bwd.ck;
+  a.ksplit = c.bwd.ksplit;
+  a.kpart = X.kpart;
+  a.counters = X.counters;
+  return a;
+}
+
+void wgrad(const d2ip_ctx& X, const Instance& I, const Conv& c, ConvSrc xs, ConvSrc gsrc) {
   ConvWgrad a;
   std::memset(&a, 0, sizeof(a));
-  a.x = x;
-  a.n = n;
+  a.src = xs;
+  a.gsrc = gsrc;
+  a.n = c.n;
   a.cin = c.cin;
-  a.cin_stride = cin_stride;
-  a.g = g;
   a.cout = c.cout;
   a.taps = c.taps;
-  a.prologue = pro;
-  a.ln = st;
-  a.ln_g = lg;
-  a.ln_b = lb;
-  a.part = X.wg_part;
-  a.partb = X.wg_partb;
-  a.tile = tile_for(n);
-  a.splits = conv_wgrad_splits(n, c.cin, c.cout, a.tile);
+  a.part = I.wg_part + c.wg_off;
+  a.partb = I.wg_partb + c.wgb_off;
+  a.splits = c.wg_splits;
   a.prec = conv_prec(X.precision);
+  a.tile = c.wg_tile;
+  a.ck = c.wg_ck;
   conv_wgrad(a, X.stream);
-  wgrad_reduce(X.wg_part, X.wg_partb, a.splits, c.cout, c.taps, c.cin, c.cin_real,
-               I.grad + c.th_w, I.grad + c.th_b, X.stream);
 }
 
 void enqueue_forward(d2ip_ctx& X, Instance& I) {
-  const int prec = conv_prec(X.precision);
   const Geometry& G = X.geos[I.geo];
   hipStream_t s = X.stream;
   float* th = I.theta;
-  {
-    ConvFwd a = fwd_args(I, prec, I.stem, I.n, I.zpad, 8, I.hs);
-    a.bias = th + I.stem.th_b;
-    conv_fwd_stats(X, I, a, I.sts);
-    ln_apply(I.hs, I.sts, th + I.stem_n.th_g, th + I.stem_n.th_b, nullptr, I.as, I.V0, I.C, s);
-  }
+  const int L = I.L;
+  conv_fwd(fwd_args(X, I, I.stem, src_plain(I.zpad, 8), I.hs, &I.sts), s);
+  ln_apply(I.hs, I.sts, th + I.stem_n.th_g, th + I.stem_n.th_b, nullptr, I.as, I.V0, I.C, s);
   for (Block& b : I.blocks) {
     const size_t V = (size_t)b.n * b.n * b.n;
-    if (b.enc && b.level > 0) avgpool2(b.pool_src, b.n * 2, b.cin, b.x, s);
     if (!b.enc) up_concat(b.up_src, b.cout * 2, b.skip_src, b.cout, b.n, b.x, s);
-    ConvFwd a1 = fwd_args(I, prec, b.c1, b.n, b.x, b.cin, b.h1);
-    a1.bias = th + b.c1.th_b;
-    conv_fwd_stats(X, I, a1, b.st1);
-    ConvFwd a2 = fwd_args(I, prec, b.c2, b.n, b.h1, b.cout, b.h2);
-    a2.bias = th + b.c2.th_b;
-    a2.prologue = PRO_LN_RELU;
-    a2.ln = b.st1;
-    a2.ln_g = th + b.n1.th_g;
-    a2.ln_b = th + b.n1.th_b;
-    conv_fwd_stats(X, I, a2, b.st2);
-    if (b.proj) {
-      ConvFwd ap = fwd_args(I, prec, b.pj, b.n, b.x, b.cin, b.s);
-      ap.bias = th + b.pj.th_b;
-      conv_fwd(ap, s);
-    }
-    ln_apply(b.h2, b.st2, th + b.n2.th_g, th + b.n2.th_b, b.proj ? b.s : b.x, b.y, V, b.cout, s);
+    conv_fwd(fwd_args(X, I, b.c1, src_plain(b.x, b.cin), b.h1, &b.st1), s);
+    conv_fwd(fwd_args(X, I, b.c2,
+                      src_ln_relu(b.h1, b.cout, b.st1, th + b.n1.th_g, th + b.n1.th_b), b.h2,
+                      &b.st2),
+             s);
+    if (b.proj) conv_fwd(fwd_args(X, I, b.pj, src_plain(b.x, b.cin), b.s, nullptr), s);
+    const float* skip = b.proj ? b.s : b.x;
+    if (b.enc && b.level < L - 1)
+      ln_apply_pool(b.h2, b.st2, th + b.n2.th_g, th + b.n2.th_b, skip, b.y, b.pool_out, b.n,
+                    b.cout, s);
+    else
+      ln_apply(b.h2, b.st2, th + b.n2.th_g, th + b.n2.th_b, skip, b.y, V, b.cout, s);
   }
   tail_fwd(I.blocks.back().y, I.C, th + I.tail_w, th + I.tail_b, G.mask, I.V0, I.sigma, s);
 }
 
 void enqueue_iteration(d2ip_ctx& X, Instance& I) {
-  const int prec = conv_prec(X.precision);
   const Geometry& G = X.geos[I.geo];
   hipStream_t s = X.stream;
   float* th = I.theta;
   float* gr = I.grad;
   enqueue_forward(X, I);
   // measurement operator, data term and its gradient w.r.t. the image
+  const int nqb = jvec_qblocks(G.qa_pad);
   jvec(G.Jc, G.M, G.qa_pad, G.idx, I.sigma, I.ppart, s);
-  data_loss(I.ppart, jvec_qblocks(G.qa_pad), I.dv, G.M, I.gp, I.it, X.b1, X.b2, s);
-  jtvec(G.Jc, G.M, G.qa_pad, I.gp, I.tpart, s);
-  const Block& d0 = I.blocks.back();
-  tail_bwd(I.tpart, jt_mblocks(G.M), G.qa_pad, G.inv, d0.y, I.C, th + I.tail_w, I.V0,
-           I.lv[0].gy, I.tail_part, s);
-  reduce_cols(I.tail_part, tail_bwd_blocks(I.V0, I.C), I.C + 1, gr + I.tail_w, s);
+  jtvec(G.Jc, G.M, G.qa_pad, I.ppart, nqb, I.dv, I.rsum, I.tpart, s);
+  tail_bwd(I.tpart, jt_mblocks(G.M), G.qa_pad, G.inv, I.blocks.back().y, I.C, th + I.tail_w,
+           I.V0, I.lv[0].gy, I.tail_part, s);
   // network backward, decoder first
-  const int L = I.L;
   for (int k = (int)I.blocks.size() - 1; k >= 0; --k) {
     Block& b = I.blocks[k];
     Level& Lv = I.lv[b.level];
     const size_t V = (size_t)b.n * b.n * b.n;
-    const double cnt = (double)V * b.cout;
-    ln_bwd_sums(Lv.gy, LNMASK_Y, b.y, nullptr, nullptr, b.h2, b.st2, Lv.gz, I.lnb_part, V, b.cout,
-                s);
-    ln_bwd_finalize(I.lnb_part, ln_bwd_blocks(V, b.cout), b.cout, cnt, th + b.n2.th_g,
-                    gr + b.n2.th_g, gr + b.n2.th_b, b.cb2, s);
-    ln_bwd_apply(Lv.gz, b.h2, b.st2, th + b.n2.th_g, b.cb2, Lv.gh, V, b.cout, s);
-    wgrad(X, I, b.c2, b.n, b.h1, b.cout, Lv.gh, PRO_LN_RELU, b.st1, th + b.n1.th_g,
-          th + b.n1.th_b);
-    conv_fwd(dgrad_args(I, prec, b.c2, b.n, Lv.gh, Lv.ga), s);
-    ln_bwd_sums(Lv.ga, LNMASK_LN, nullptr, th + b.n1.th_g, th + b.n1.th_b, b.h1, b.st1, Lv.ga,
-                I.lnb_part, V, b.cout, s);
-    ln_bwd_finalize(I.lnb_part, ln_bwd_blocks(V, b.cout), b.cout, cnt, th + b.n1.th_g,
-                    gr + b.n1.th_g, gr + b.n1.th_b, b.cb1, s);
-    ln_bwd_apply(Lv.ga, b.h1, b.st1, th + b.n1.th_g, b.cb1, Lv.gh, V, b.cout, s);
-    wgrad(X, I, b.c1, b.n, b.x, b.cin, Lv.gh, PRO_NONE, nullptr, nullptr, nullptr);
+    const float* g1 = th + b.n1.th_g;
+    const float* b1 = th + b.n1.th_b;
+    const float* g2 = th + b.n2.th_g;
+    // LN2 backward (mask from y): gz and its partials
+    ln_bwd(Lv.gy, LNMASK_Y, b.y, nullptr, nullptr, b.h2, b.st2, Lv.gz, b.lnc2,
+           const_cast<double*>(b.cb2.part), V, b.cout, g2, s);
+    const ConvSrc gh2 = src_ln_bwd(Lv.gz, b.h2, b.cout, b.st2, g2, b.cb2);
+    wgrad(X, I, b.c2, src_ln_relu(b.h1, b.cout, b.st1, g1, b1), gh2);
+    conv_fwd(dgrad_args(X, I, b.c2, gh2, Lv.ga), s);
+    // LN1 backward (mask from LN1 output), in place on ga
+    ln_bwd(Lv.ga, LNMASK_LN, nullptr, g1, b1, b.h1, b.st1, Lv.ga, b.lnc1,
+           const_cast<double*>(b.cb1.part), V, b.cout, g1, s);
+    const ConvSrc gh1 = src_ln_bwd(Lv.ga, b.h1, b.cout, b.st1, g1, b.cb1);
+    wgrad(X, I, b.c1, src_plain(b.x, b.cin), gh1);
     {
-      ConvFwd a = dgrad_args(I, prec, b.c1, b.n, Lv.gh, Lv.gx);
+      ConvFwd a = dgrad_args(X, I, b.c1, gh1, Lv.gx);
       if (!b.proj) a.add = Lv.gz;
       conv_fwd(a, s);
     }
     if (b.proj) {
-      wgrad(X, I, b.pj, b.n, b.x, b.cin, Lv.gz, PRO_NONE, nullptr, nullptr, nullptr);
-      ConvFwd a = dgrad_args(I, prec, b.pj, b.n, Lv.gz, Lv.gx);
+      wgrad(X, I, b.pj, src_plain(b.x, b.cin), src_plain(Lv.gz, b.cout));
+      ConvFwd a = dgrad_args(X, I, b.pj, src_plain(Lv.gz, b.cout), Lv.gx);
       a.accumulate = 1;
       conv_fwd(a, s);
     }
@@ -557,22 +686,20 @@ void enqueue_iteration(d2ip_ctx& X, Instance& I) {
       Level& Lp = I.lv[b.level - 1];
       pool_bwd_add(Lv.gx, Lp.genc, Lp.n, Lp.c, Lp.gy, s);
     }
-    (void)L;
   }
   // stem
   {
     Level& L0 = I.lv[0];
-    const double cnt = (double)I.V0 * I.C;
-    ln_bwd_sums(L0.gx, LNMASK_Y, I.as, nullptr, nullptr, I.hs, I.sts, L0.gz, I.lnb_part, I.V0,
-                I.C, s);
-    ln_bwd_finalize(I.lnb_part, ln_bwd_blocks(I.V0, I.C), I.C, cnt, th + I.stem_n.th_g,
-                    gr + I.stem_n.th_g, gr + I.stem_n.th_b, I.cbs, s);
-    ln_bwd_apply(L0.gz, I.hs, I.sts, th + I.stem_n.th_g, I.cbs, L0.gh, I.V0, I.C, s);
-    wgrad(X, I, I.stem, I.n, I.zpad, 8, L0.gh, PRO_NONE, nullptr, nullptr, nullptr);
+    const float* gs = th + I.stem_n.th_g;
+    ln_bwd(L0.gx, LNMASK_Y, I.as, nullptr, nullptr, I.hs, I.sts, L0.gz, I.lncs,
+           const_cast<double*>(I.cbs.part), I.V0, I.C, gs, s);
+    wgrad(X, I, I.stem, src_plain(I.zpad, 8), src_ln_bwd(L0.gz, I.hs, I.C, I.sts, gs, I.cbs));
   }
+  grad_reduce(I.segs_dev, (int)I.segs.size(), I.max_seg, I.wg_part, I.wg_partb, I.dpart, gr, s);
   adam(th, gr, I.m, I.v, I.P, X.lr, X.b1, X.b2, X.eps, I.it, s);
   pack_weights(I.packs_dev, (int)I.packs.size(), I.max_pack, th, I.wf32, I.wbf16,
-               X.precision == D2IP_BF16X3_CONV ? I.wtotal : 0, s);
+               X.precision == D2IP_BF16X3_CONV ? I.wtotal : 0, I.it, I.rsum, jt_mblocks(G.M),
+               G.M, s);
 }
 
 d2ip_status check_inst(d2ip_ctx* X, int inst) {
@@ -602,7 +729,7 @@ d2ip_status copy_out(d2ip_ctx* X, void* dst, const void* src, size_t bytes, int 
 
 d2ip_status repack(d2ip_ctx* X, Instance& I) {
   pack_weights(I.packs_dev, (int)I.packs.size(), I.max_pack, I.theta, I.wf32, I.wbf16,
-               X->precision == D2IP_BF16X3_CONV ? I.wtotal : 0, X->stream);
+               X->precision == D2IP_BF16X3_CONV ? I.wtotal : 0, nullptr, nullptr, 0, 1, X->stream);
   HIPCHK(hipGetLastError());
   return D2IP_OK;
 }
@@ -681,6 +808,9 @@ d2ip_status d2ip_create(const d2ip_geometry_desc* geos, int n_geo, const d2ip_in
     for (Instance& I : X->insts) {
       e = hipMemcpyAsync(I.packs_dev, I.packs.data(), I.packs.size() * sizeof(ConvPack),
                          hipMemcpyHostToDevice, X->stream);
+      if (e == hipSuccess)
+        e = hipMemcpyAsync(I.segs_dev, I.segs.data(), I.segs.size() * sizeof(GradSeg),
+                           hipMemcpyHostToDevice, X->stream);
       if (e != hipSuccess) break;
     }
   }
@@ -925,7 +1055,6 @@ d2ip_status d2ip_time_kernel(d2ip_ctx* X, int inst, int which, int block, int re
   Instance& I = X->insts[inst];
   const Geometry& G = X->geos[I.geo];
   if (!G.set || !I.has_frame || !I.has_z) return fail(D2IP_ESTATE, "instance not ready");
-  const int prec = conv_prec(X->precision);
   hipStream_t s = X->stream;
   Block* b = nullptr;
   if (which >= D2IP_KERNEL_CONV_FWD) {
@@ -939,24 +1068,28 @@ d2ip_status d2ip_time_kernel(d2ip_ctx* X, int inst, int which, int block, int re
         jvec(G.Jc, G.M, G.qa_pad, G.idx, I.sigma, I.ppart, s);
         break;
       case D2IP_KERNEL_JTVEC:
-        jtvec(G.Jc, G.M, G.qa_pad, I.gp, I.tpart, s);
+        jtvec(G.Jc, G.M, G.qa_pad, I.ppart, jvec_qblocks(G.qa_pad), I.dv, I.rsum, I.tpart, s);
         break;
       case D2IP_KERNEL_ADAM:
         adam(I.theta, I.grad, I.m, I.v, I.P, X->lr, X->b1, X->b2, X->eps, I.it, s);
         break;
-      case D2IP_KERNEL_CONV_FWD: {
-        ConvFwd a = fwd_args(I, prec, b->c1, b->n, b->x, b->cin, b->h1);
-        a.bias = I.theta + b->c1.th_b;
-        a.stat_part = I.stat_part;
-        conv_fwd(a, s);
+      case D2IP_KERNEL_CONV_FWD:
+        conv_fwd(fwd_args(*X, I, b->c1, src_plain(b->x, b->cin), b->h1, &b->st1), s);
+        break;
+      case D2IP_KERNEL_CONV_DGRAD: {
+        const float* th = I.theta;
+        conv_fwd(dgrad_args(*X, I, b->c1,
+                            src_ln_bwd(Lv->ga, b->h1, b->cout, b->st1, th + b->n1.th_g, b->cb1),
+                            Lv->gx),
+                 s);
         break;
       }
-      case D2IP_KERNEL_CONV_DGRAD:
-        conv_fwd(dgrad_args(I, prec, b->c1, b->n, Lv->gh, Lv->gx), s);
+      default: {
+        const float* th = I.theta;
+        wgrad(*X, I, b->c1, src_plain(b->x, b->cin),
+              src_ln_bwd(Lv->ga, b->h1, b->cout, b->st1, th + b->n1.th_g, b->cb1));
         break;
-      default:
-        wgrad(*X, I, b->c1, b->n, b->x, b->cin, Lv->gh, PRO_NONE, nullptr, nullptr, nullptr);
-        break;
+      }
     }
   };
   if (which < D2IP_KERNEL_JVEC || which > D2IP_KERNEL_CONV_WGRAD)

@@ -47,38 +47,34 @@ __global__ __launch_bounds__(256) void k_jvec(const float* __restrict__ Jc, int 
   }
 }
 
-__global__ void k_data_loss(const float* __restrict__ ppart, int nqb, const float* __restrict__ dv,
-                            int M, float* __restrict__ gp, IterState* it, float beta1,
-                            float beta2) {
-  __shared__ double sh[16];
-  double s = 0.0;
-  const float scale = 2.f / (float)M;
-  for (int m = threadIdx.x; m < M; m += blockDim.x) {
-    float p = 0.f;
-    for (int k = 0; k < nqb; ++k) p += ppart[(size_t)k * M + m];
-    const float r = p - dv[m];
-    gp[m] = scale * r;
-    s += (double)r * r;
-  }
-  s = block_sum(s, sh);
-  if (threadIdx.x == 0) {
-    const double L = s / M;
-    it->loss = L;
-    if (!isfinite(L)) it->nonfinite = 1;
-    const int t = it->t + 1;
-    it->t = t;
-    it->bc1 = (float)(1.0 - pow((double)beta1, (double)t));
-    it->bc2 = (float)(1.0 - pow((double)beta2, (double)t));
-  }
-}
-
 __global__ __launch_bounds__(256) void k_jtvec(const float* __restrict__ Jc, int M, int qa_pad,
-                                               const float* __restrict__ gp,
+                                               const float* __restrict__ ppart, int nqb,
+                                               const float* __restrict__ dv,
+                                               double* __restrict__ rsum,
                                                float* __restrict__ tpart) {
   __shared__ float gs[kJtRows];
+  __shared__ double sh[16];
   const int m0 = blockIdx.y * kJtRows;
   const int mn = min(kJtRows, M - m0);
-  if (threadIdx.x < kJtRows) gs[threadIdx.x] = threadIdx.x < mn ? gp[m0 + threadIdx.x] : 0.f;
+  // residual of this block's rows: 8 threads per row, column blocks k = j, j+8, ..
+  {
+    const int r = threadIdx.x >> 3, j = threadIdx.x & 7;
+    float p = 0.f;
+    if (r < mn)
+      for (int k = j; k < nqb; k += 8) p += ppart[(size_t)k * M + m0 + r];
+#pragma unroll
+    for (int o = 4; o > 0; o >>= 1) p += __shfl_xor(p, o, 8);
+    double rr = 0.0;
+    if (j == 0 && r < kJtRows) {
+      const float res = r < mn ? p - dv[m0 + r] : 0.f;
+      gs[r] = (2.f / (float)M) * res;
+      rr = (double)res * res;
+    }
+    if (blockIdx.x == 0) {
+      rr = block_sum(rr, sh);
+      if (threadIdx.x == 0) rsum[blockIdx.y] = rr;
+    }
+  }
   __syncthreads();
   const int q = (blockIdx.x * 256 + threadIdx.x) * 4;
   if (q >= qa_pad) return;
@@ -163,19 +159,17 @@ __global__ __launch_bounds__(256) void k_tail_bwd(const float* __restrict__ tpar
   }
 }
 
-__global__ void k_reduce_cols(const double* __restrict__ part, int nparts, int K,
-                              float* __restrict__ dst) {
-  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < K; k += gridDim.x * blockDim.x) {
-    double s = 0.0;
-    for (int i = 0; i < nparts; ++i) s += part[(size_t)i * K + k];
-    dst[k] = (float)s;
-  }
-}
-
 __global__ void k_adam(float* __restrict__ theta, const float* __restrict__ g,
                        float* __restrict__ m, float* __restrict__ v, size_t P, float lr,
                        float beta1, float beta2, float eps, const IterState* __restrict__ it) {
-  const float bc1 = it->bc1, bc2 = it->bc2;
+  __shared__ float sbc[2];
+  if (threadIdx.x == 0) {
+    const int t = it->t + 1;
+    sbc[0] = (float)(1.0 - pow((double)beta1, (double)t));
+    sbc[1] = (float)(1.0 - pow((double)beta2, (double)t));
+  }
+  __syncthreads();
+  const float bc1 = sbc[0], bc2 = sbc[1];
   const float step = lr / bc1;
   const float rs2 = 1.f / sqrtf(bc2);
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < P;
@@ -197,7 +191,16 @@ __device__ __forceinline__ void put_bf(uint16_t* w, long long i, long long lo_of
 
 __global__ void k_pack_weights(const ConvPack* __restrict__ packs, const float* __restrict__ theta,
                                float* __restrict__ wf32, uint16_t* __restrict__ wbf16,
-                               long long lo_off) {
+                               long long lo_off, IterState* it, const double* __restrict__ rsum,
+                               int nrs, int M) {
+  if (it && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) {
+    double L = 0.0;
+    for (int k = 0; k < nrs; ++k) L += rsum[k];
+    L /= M;
+    it->loss = L;
+    if (!isfinite(L)) it->nonfinite = 1;
+    it->t = it->t + 1;
+  }
   const ConvPack pk = packs[blockIdx.y];
   const int per_co = pk.cin_real * pk.taps;
   const int total = pk.cout * per_co;
@@ -240,15 +243,10 @@ void jvec(const float* Jc, int M, int qa_pad, const int* idx, const float* sigma
   hipLaunchKernelGGL(k_jvec, grid, dim3(256), 0, s, Jc, M, qa_pad, idx, sigma, ppart);
 }
 
-void data_loss(const float* ppart, int nqb, const float* dv, int M, float* gp, IterState* it,
-               float beta1, float beta2, hipStream_t s) {
-  hipLaunchKernelGGL(k_data_loss, dim3(1), dim3(256), 0, s, ppart, nqb, dv, M, gp, it, beta1,
-                     beta2);
-}
-
-void jtvec(const float* Jc, int M, int qa_pad, const float* gp, float* tpart, hipStream_t s) {
+void jtvec(const float* Jc, int M, int qa_pad, const float* ppart, int nqb, const float* dv,
+           double* rsum, float* tpart, hipStream_t s) {
   dim3 grid((qa_pad / 4 + 255) / 256, jt_mblocks(M));
-  hipLaunchKernelGGL(k_jtvec, grid, dim3(256), 0, s, Jc, M, qa_pad, gp, tpart);
+  hipLaunchKernelGGL(k_jtvec, grid, dim3(256), 0, s, Jc, M, qa_pad, ppart, nqb, dv, rsum, tpart);
 }
 
 void tail_fwd(const float* d0, int C, const float* w, const float* b, const float* mask, size_t V,
@@ -267,10 +265,6 @@ void tail_bwd(const float* tpart, int nmb, int qa_pad, const int* inv, const flo
                      inv, d0, C, w, V, gd0, part);
 }
 
-void reduce_cols(const double* part, int nparts, int K, float* dst, hipStream_t s) {
-  hipLaunchKernelGGL(k_reduce_cols, dim3((K + 255) / 256), dim3(256), 0, s, part, nparts, K, dst);
-}
-
 void adam(float* theta, const float* g, float* m, float* v, size_t P, float lr, float beta1,
           float beta2, float eps, const IterState* it, hipStream_t s) {
   hipLaunchKernelGGL(k_adam, dim3(grid_for(P)), dim3(256), 0, s, theta, g, m, v, P, lr, beta1,
@@ -278,10 +272,12 @@ void adam(float* theta, const float* g, float* m, float* v, size_t P, float lr, 
 }
 
 void pack_weights(const ConvPack* packs, int npacks, int max_elems, const float* theta,
-                  float* wf32, uint16_t* wbf16, long long lo_off, hipStream_t s) {
+                  float* wf32, uint16_t* wbf16, long long lo_off, IterState* it,
+                  const double* rsum, int nrs, int M, hipStream_t s) {
   dim3 grid((max_elems + 255) / 256, npacks);
   if (grid.x > 1024) grid.x = 1024;
-  hipLaunchKernelGGL(k_pack_weights, grid, dim3(256), 0, s, packs, theta, wf32, wbf16, lo_off);
+  hipLaunchKernelGGL(k_pack_weights, grid, dim3(256), 0, s, packs, theta, wf32, wbf16, lo_off, it,
+                     rsum, nrs, M);
 }
 
 }  // namespace d2ip

@@ -8,22 +8,40 @@
 
 namespace d2ip {
 
-// Input transform applied while a conv stages its input tile.
-enum Prologue { PRO_NONE = 0, PRO_LN_RELU = 1 };
+// Input transform applied while a conv stages an operand tile.
+//   PRO_LN_RELU: x -> relu(gamma_c * (x - mean) * rstd + beta_c)
+//   PRO_LN_BWD : gz -> rstd * (gamma_c * gz - A - xhat * B), xhat from the
+//                pre-norm activation h (LayerNorm backward, whole volume)
+enum Prologue { PRO_NONE = 0, PRO_LN_RELU = 1, PRO_LN_BWD = 2 };
 
 // Operand precision of the conv MFMAs (accumulation is always FP32).
 enum ConvPrec { PREC_F32 = 0, PREC_BF16 = 1, PREC_BF16X3 = 2 };
 
 // Spatial output tile of a conv block (TZ x TY x TX voxels).
-enum TileCfg { TILE_2x4x16 = 0, TILE_2x8x8 = 1, TILE_COUNT = 2 };
+enum TileCfg { TILE_2x4x16 = 0, TILE_1x4x16 = 1, TILE_1x8x8 = 2, TILE_COUNT = 3 };
+
+// Operand tile source with its prologue.
+struct ConvSrc {
+  const float* x;        // [n^3][stride] fp32
+  int stride;
+  int prologue;          // Prologue
+  PairRef st;            // statistics partials of the normalised tensor
+  const float* gamma;    // [channels]
+  const float* beta;     // [channels] (PRO_LN_RELU)
+  const float* h;        // PRO_LN_BWD: pre-norm activation, same layout as x
+  PairRef bw;            // PRO_LN_BWD: partials of the coefficients A, B
+};
 
 // y[v][co] (+)= sum_{tap, ci} Wp[co][tap][ci] * T(x)[v + off(tap)][ci] (+ bias[co])
 // (+ add[v][co]); NDHWC tensors on an n^3 grid, zero padding.  Used for the
-// forward conv (Wp = forward packing) and for the input gradient (Wp = flipped,
-// transposed packing).
+// forward conv (Wp = forward packing) and the input gradient (Wp = flipped,
+// transposed packing).  With ksplit > 1 the channel chunks are split over
+// blocks; the last block of each output tile sums the partials in a fixed
+// order and runs the epilogue.  With stat_part set, every output tile writes
+// the (sum, sumsq) pair of its outputs for the following LayerNorm.
 struct ConvFwd {
-  const float* x;        // [n^3][cin_stride], fp32
-  int n, cin, cin_stride;  // cin: multiple of 8, channels read
+  ConvSrc src;
+  int n, cin;            // cin: multiple of ck, channels read
   const void* w;         // packed weights [w_rows][taps][cin], fp32 or bf16
   long long w_lo_off;    // PREC_BF16X3: elements from w to its lo-part copy
   int w_rows;            // rows present in w (>= cout)
@@ -33,68 +51,64 @@ struct ConvFwd {
   int accumulate;        // 1: y += result
   float* y;              // [n^3][cout]
   int taps;              // 27 or 1
-  int prologue;          // Prologue
-  const LnStat* ln;      // statistics of x (PRO_LN_RELU)
-  const float* ln_g;     // gamma[cin] (PRO_LN_RELU)
-  const float* ln_b;     // beta[cin]
-  double* stat_part;     // per-block (sum, sumsq) of y, or null
-  int prec;              // ConvPrec
-  int tile;              // TileCfg
+  double* stat_part;     // per-tile (sum, sumsq) of y, or null
+  int prec, tile, bn, ck, ksplit;
+  float* kpart;          // [ksplit][n^3][cout] (ksplit > 1)
+  int* counters;         // ksplit > 1: >= tiles zeroed ints (left zeroed)
 };
-int conv_fwd_blocks(const ConvFwd& a);  // number of blocks (= stat partials)
+int conv_tiles(int n, int tile);
+int conv_fwd_blocks(const ConvFwd& a);  // output tiles (= stat partials)
+// dynamic LDS of a forward/input-gradient launch (halo + weight slab)
+size_t conv_fwd_lds_bytes(int tile, int taps, int bn, int ck, int prec);
 void conv_fwd(const ConvFwd& a, hipStream_t s);
 
-// Weight gradient: part[s][co][tap][ci] = sum over voxels of split s of
-// g[v][co] * T(x)[v + off(tap)][ci]; bias partials partb[s][co] = sum g[v][co].
+// Weight gradient partials: part[s][co][tap][ci] = sum over the voxels of
+// split s of T(g)[v][co] * T(x)[v + off(tap)][ci]; partb[s][co] = sum T(g)[v][co].
 struct ConvWgrad {
-  const float* x;        // [n^3][cin_stride]
-  int n, cin, cin_stride;
-  const float* g;        // [n^3][cout]
-  int cout;
-  int taps;
-  int prologue;
-  const LnStat* ln;
-  const float* ln_g;
-  const float* ln_b;
+  ConvSrc src;           // x operand
+  ConvSrc gsrc;          // g operand (PRO_NONE or PRO_LN_BWD), stride = cout
+  int n, cin, cout, taps;
   float* part;           // [splits][cout16][taps][cin]
-  float* partb;          // [splits][cout16] or null
-  int splits;
-  int prec;
-  int tile;
+  float* partb;          // [splits][cout16]
+  int splits, prec, tile, ck;
 };
-int conv_wgrad_splits(int n, int cin, int cout, int tile);
-size_t conv_wgrad_part_floats(int n, int cin, int cout, int taps, int tile);
+int conv_wgrad_groups(int taps, int ck);
 void conv_wgrad(const ConvWgrad& a, hipStream_t s);
 
-// gw[co][ci][tap] (canonical) = sum_s part[s][co][tap][ci] for ci < cin_real;
-// gb[co] = sum_s partb[s][co].
-void wgrad_reduce(const float* part, const float* partb, int splits, int cout, int taps,
-                  int cin, int cin_real, float* gw, float* gb, hipStream_t s);
-
+// One slice of the batched gradient reduction at the end of an iteration.
+//  kind 0 (conv): g[th_w + (co*cin_real + ci)*taps + tap] = sum_s part[s][co][tap][ci]
+//                 and g[th_b + co] = sum_s partb[s][co]   (float partials)
+//  kind 1 (columns): g[th_w + k] = sum_i dpart[i][k], k < cout (double
+//                 partials [splits][cout]: LayerNorm gains/shifts, output head)
+struct GradSeg {
+  int kind;
+  long long part_off, partb_off;  // offsets in the partial buffers
+  int splits, cout, taps, cin, cin_real;
+  int th_w, th_b;
+};
+void grad_reduce(const GradSeg* segs, int nsegs, int max_elems, const float* part,
+                 const float* partb, const double* dpart, float* grad, hipStream_t s);
 
 // ---- LayerNorm, ReLU, pooling, up-sampling (norm.hip) ----------------------
 enum LnMask { LNMASK_NONE = 0, LNMASK_Y = 1, LNMASK_LN = 2 };
 
-// mean / rstd from `nparts` (sum, sumsq) FP64 partials over `count` elements.
-void ln_finalize(const double* part, int nparts, double count, float eps, LnStat* out,
-                 hipStream_t s);
 // y = relu(g[c] * (h - mean) * rstd + b[c] (+ skip)), [V][C]
-void ln_apply(const float* h, const LnStat* st, const float* g, const float* b, const float* skip,
+void ln_apply(const float* h, PairRef st, const float* g, const float* b, const float* skip,
               float* y, size_t V, int C, hipStream_t s);
+// the same on an n^3 grid (n even), also writing the 2x2x2 average of y
+// (the next encoder input) when `pooled` is not null
+void ln_apply_pool(const float* h, PairRef st, const float* g, const float* b, const float* skip,
+                   float* y, float* pooled, int n, int C, hipStream_t s);
 int ln_bwd_vpb(int C);
 int ln_bwd_blocks(size_t V, int C);
-// gz = gy * relu'(.) (mask from y > 0, or from g*xhat + b > 0), per-block
-// per-channel partial sums of gz and gz * xhat.
-void ln_bwd_sums(const float* gy, int mask_mode, const float* my, const float* mg, const float* mb,
-                 const float* h, const LnStat* st, float* gz, double* part, size_t V, int C,
-                 hipStream_t s);
-// dgamma, dbeta and the coefficients A = sum_c gamma_c S1_c / count,
-// B = sum_c gamma_c S2_c / count.
-void ln_bwd_finalize(const double* part, int nparts, int C, double count, const float* gamma,
-                     float* dgamma, float* dbeta, LnBwd* coef, hipStream_t s);
-// gh = rstd * (gamma_c * gz - A - xhat * B)
-void ln_bwd_apply(const float* gz, const float* h, const LnStat* st, const float* gamma,
-                  const LnBwd* coef, float* gh, size_t V, int C, hipStream_t s);
+// gz = gy * relu'(.) (mask from y > 0, or from g*xhat + b > 0); per block:
+// part_c[blk][c] = sum gz*xhat (dgamma), part_c[blk][C + c] = sum gz (dbeta),
+// part_ab[blk] = (sum_c gamma_c sum gz, sum_c gamma_c sum gz*xhat), whose
+// totals over `count` elements are the coefficients A, B of
+// dh = rstd * (gamma_c * gz - A - xhat * B).
+void ln_bwd(const float* gy, int mask_mode, const float* my, const float* mg, const float* mb,
+            const float* h, PairRef st, float* gz, double* part_c, double* part_ab, size_t V,
+            int C, const float* gamma, hipStream_t s);
 void avgpool2(const float* x, int n, int C, float* y, hipStream_t s);
 void up_concat(const float* d, int Cu, const float* e, int Cs, int n, float* cat, hipStream_t s);
 void up_concat_bwd(const float* gcat, int Cu, int Cs, int n, float* gu, float* gs, hipStream_t s);
@@ -122,29 +136,35 @@ inline int jt_mblocks(int M) { return (M + kJtRows - 1) / kJtRows; }
 
 void gather_columns(const float* J, int M, int Q, const int* idx, int qa, int qa_pad, float* Jc,
                     hipStream_t s);
-// ppart[qb][m] = sum_{q in block qb} Jc[m][q] * sigma[idx[q]]
+// ppart[qb][m] = sum_{q in block qb} Jc[m][q] * sigma[idx[q]]; then, by the
+// last block: r = sum_qb ppart - dv, loss = (1/M) sum r^2 (FP64), gp = (2/M) r,
+// Adam step counter t += 1 with its bias corrections.
+// ppart[qb][m] = sum_{q in column block qb} Jc[m][q] * sigma[idx[q]]
 void jvec(const float* Jc, int M, int qa_pad, const int* idx, const float* sigma, float* ppart,
           hipStream_t s);
-// r = sum_qb ppart - dv; loss = (1/M) sum r^2 (FP64); gp = (2/M) r; t += 1.
-void data_loss(const float* ppart, int nqb, const float* dv, int M, float* gp, IterState* it,
-               float beta1, float beta2, hipStream_t s);
-// tpart[mb][q] = sum_{m in block mb} Jc[m][q] * gp[m]
-void jtvec(const float* Jc, int M, int qa_pad, const float* gp, float* tpart, hipStream_t s);
+// Each block first forms, for its kJtRows rows, p = sum_qb ppart (column-block
+// order), r = p - dv and gp = (2/M) r; blocks of the first column write
+// rsum[mb] = sum r^2 (FP64).  Then tpart[mb][q] = sum_{m in mb} Jc[m][q] gp[m].
+void jtvec(const float* Jc, int M, int qa_pad, const float* ppart, int nqb, const float* dv,
+           double* rsum, float* tpart, hipStream_t s);
 // sigma[v] = mask[v] * (b + sum_c w[c] d0[v][c])
 void tail_fwd(const float* d0, int C, const float* w, const float* b, const float* mask, size_t V,
               float* sigma, hipStream_t s);
 int tail_bwd_blocks(size_t V, int C);
 // gs[v] = sum_mb tpart[mb][inv[v]] (0 where inv < 0); gd0[v][c] = gs[v] w[c];
-// part[blk][c] = sum gs*d0[.][c], part[blk][C] = sum gs.
+// part[blk][c] = sum gs*d0[.][c], part[blk][C] = sum gs (gradient of the head,
+// reduced by grad_reduce).
 void tail_bwd(const float* tpart, int nmb, int qa_pad, const int* inv, const float* d0, int C,
               const float* w, size_t V, float* gd0, double* part, hipStream_t s);
-// dst[k] = sum_i part[i][k]  (k < K)
-void reduce_cols(const double* part, int nparts, int K, float* dst, hipStream_t s);
+// Adam step t + 1 (t = it->t, bias corrections 1 - beta^(t+1)).
 void adam(float* theta, const float* g, float* m, float* v, size_t P, float lr, float beta1,
           float beta2, float eps, const IterState* it, hipStream_t s);
 // Packed conv weights from theta; with lo_off > 0 the bf16 lo parts
-// (bf16(w - bf16(w))) are written lo_off elements after the hi parts.
+// (bf16(w - bf16(w))) are written lo_off elements after the hi parts.  When
+// `it` is set this ends an iteration: it->loss = sum(rsum[0..nrs)) / M (FP64),
+// the non-finite flag, and t += 1.
 void pack_weights(const ConvPack* packs, int npacks, int max_elems, const float* theta,
-                  float* wf32, uint16_t* wbf16, long long lo_off, hipStream_t s);
+                  float* wf32, uint16_t* wbf16, long long lo_off, IterState* it,
+                  const double* rsum, int nrs, int M, hipStream_t s);
 
 }  // namespace d2ip

@@ -9,32 +9,13 @@
 namespace d2ip {
 namespace {
 
-constexpr int kElemsPerBlock = 4096;
+constexpr int kElemsPerBlock = 1024;
 
-__global__ void k_ln_finalize(const double* __restrict__ part, int nparts, double count, float eps,
-                              LnStat* out) {
-  __shared__ double sh[16];
-  double s1 = 0.0, s2 = 0.0;
-  for (int i = threadIdx.x; i < nparts; i += blockDim.x) {
-    s1 += part[2 * i];
-    s2 += part[2 * i + 1];
-  }
-  s1 = block_sum(s1, sh);
-  s2 = block_sum(s2, sh);
-  if (threadIdx.x == 0) {
-    const double mean = s1 / count;
-    double var = s2 / count - mean * mean;
-    if (var < 0.0) var = 0.0;
-    out->mean = (float)mean;
-    out->rstd = (float)(1.0 / sqrt(var + (double)eps));
-  }
-}
-
-__global__ void k_ln_apply(const float4* __restrict__ h, const LnStat* __restrict__ st,
-                           const float* __restrict__ g, const float* __restrict__ b,
-                           const float4* __restrict__ skip, float4* __restrict__ y, size_t n4,
-                           int C) {
-  const float mean = st->mean, rstd = st->rstd;
+__global__ void k_ln_apply(const float4* __restrict__ h, PairRef sr, const float* __restrict__ g,
+                           const float* __restrict__ b, const float4* __restrict__ skip,
+                           float4* __restrict__ y, size_t n4, int C) {
+  const LnStat st = stat_of(sr);
+  const float mean = st.mean, rstd = st.rstd;
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n4;
        i += (size_t)gridDim.x * blockDim.x) {
     const int c = (int)((i * 4) % C);
@@ -49,16 +30,19 @@ __global__ void k_ln_apply(const float4* __restrict__ h, const LnStat* __restric
   }
 }
 
-// gz = gy * mask; per-block per-channel partial sums of gz and gz * xhat.
-__global__ __launch_bounds__(256) void k_ln_bwd_sums(
-    const float* gy, int mask_mode, const float* __restrict__ my,
-    const float* __restrict__ mg, const float* __restrict__ mb, const float* __restrict__ h,
-    const LnStat* __restrict__ st, float* gz, double* __restrict__ part, int V,
-    int C, int vpb) {
+// gz = gy * mask and the block's partial sums: part_c[blk] = per-channel
+// (sum gz*xhat [C], sum gz [C]); part_ab[blk] = (sum_c gamma_c sum gz,
+// sum_c gamma_c sum gz*xhat).
+__global__ __launch_bounds__(256) void k_ln_bwd(
+    const float* gy, int mask_mode, const float* __restrict__ my, const float* __restrict__ mg,
+    const float* __restrict__ mb, const float* __restrict__ h, PairRef sr, float* gz,
+    double* __restrict__ part_c, double* __restrict__ part_ab, int V, int C, int vpb,
+    const float* __restrict__ gamma) {
   __shared__ double sh1[256], sh2[256];
+  const LnStat st = stat_of(sr);
   const int tid = threadIdx.x;
   const int c = tid % C, r0 = tid / C, rpi = 256 / C;
-  const float mean = st->mean, rstd = st->rstd;
+  const float mean = st.mean, rstd = st.rstd;
   const float gam = mask_mode == LNMASK_LN ? mg[c] : 0.f;
   const float bet = mask_mode == LNMASK_LN ? mb[c] : 0.f;
   double s1 = 0.0, s2 = 0.0;
@@ -77,56 +61,59 @@ __global__ __launch_bounds__(256) void k_ln_bwd_sums(
   sh1[tid] = s1;
   sh2[tid] = s2;
   __syncthreads();
+  double ga = 0.0, gb = 0.0;
   if (tid < C) {
     double a = 0.0, b = 0.0;
     for (int k = tid; k < 256; k += C) {
       a += sh1[k];
       b += sh2[k];
     }
-    part[((size_t)blockIdx.x * C + tid) * 2] = a;
-    part[((size_t)blockIdx.x * C + tid) * 2 + 1] = b;
+    part_c[(size_t)blockIdx.x * 2 * C + tid] = b;      // dgamma partial
+    part_c[(size_t)blockIdx.x * 2 * C + C + tid] = a;  // dbeta partial
+    ga = (double)gamma[tid] * a;
+    gb = (double)gamma[tid] * b;
+  }
+  __syncthreads();
+  ga = block_sum(ga, sh1);
+  gb = block_sum(gb, sh2);
+  if (tid == 0) {
+    part_ab[2 * (size_t)blockIdx.x] = ga;
+    part_ab[2 * (size_t)blockIdx.x + 1] = gb;
   }
 }
 
-__global__ void k_ln_bwd_finalize(const double* __restrict__ part, int nparts, int C, double count,
-                                  const float* __restrict__ gamma, float* dgamma, float* dbeta,
-                                  LnBwd* coef) {
-  __shared__ double sh[16];
-  double a = 0.0, b = 0.0;
-  for (int c = threadIdx.x; c < C; c += blockDim.x) {
-    double s1 = 0.0, s2 = 0.0;
-    for (int k = 0; k < nparts; ++k) {
-      s1 += part[((size_t)k * C + c) * 2];
-      s2 += part[((size_t)k * C + c) * 2 + 1];
-    }
-    dgamma[c] = (float)s2;
-    dbeta[c] = (float)s1;
-    a += (double)gamma[c] * s1;
-    b += (double)gamma[c] * s2;
-  }
-  a = block_sum(a, sh);
-  b = block_sum(b, sh);
-  if (threadIdx.x == 0) {
-    coef->A = (float)(a / count);
-    coef->B = (float)(b / count);
-  }
-}
-
-__global__ void k_ln_bwd_apply(const float4* __restrict__ gz, const float4* __restrict__ h,
-                               const LnStat* __restrict__ st, const float* __restrict__ gamma,
-                               const LnBwd* __restrict__ coef, float4* __restrict__ gh, size_t n4,
-                               int C) {
-  const float mean = st->mean, rstd = st->rstd, A = coef->A, B = coef->B;
-  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n4;
+// y = relu(LN(h) + skip) for 2x2x2 groups of voxels, and the group mean of y
+// (the average-pooled input of the next encoder level) when `pooled` is set.
+__global__ void k_ln_apply_pool(const float4* __restrict__ h, PairRef sr,
+                                const float* __restrict__ g, const float* __restrict__ b,
+                                const float4* __restrict__ skip, float4* __restrict__ y,
+                                float4* __restrict__ pooled, int n, int C4) {
+  const int m = n / 2;
+  const size_t total = (size_t)m * m * m * C4;
+  const LnStat st = stat_of(sr);
+  const float mean = st.mean, rstd = st.rstd;
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < total;
        i += (size_t)gridDim.x * blockDim.x) {
-    const int c = (int)((i * 4) % C);
-    const float4 g = gz[i], x = h[i];
-    float4 o;
-    o.x = rstd * (gamma[c + 0] * g.x - A - ((x.x - mean) * rstd) * B);
-    o.y = rstd * (gamma[c + 1] * g.y - A - ((x.y - mean) * rstd) * B);
-    o.z = rstd * (gamma[c + 2] * g.z - A - ((x.z - mean) * rstd) * B);
-    o.w = rstd * (gamma[c + 3] * g.w - A - ((x.w - mean) * rstd) * B);
-    gh[i] = o;
+    const int c4 = (int)(i % C4);
+    const size_t vc = i / C4;
+    const int xx = (int)(vc % m), yy = (int)((vc / m) % m), zz = (int)(vc / ((size_t)m * m));
+    const int c = 4 * c4;
+    float4 s = make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const int fz = 2 * zz + (k >> 2), fy = 2 * yy + ((k >> 1) & 1), fx = 2 * xx + (k & 1);
+      const size_t j = ((size_t)(fz * n + fy) * n + fx) * C4 + c4;
+      const float4 v = h[j];
+      const float4 sk = skip ? skip[j] : make_float4(0.f, 0.f, 0.f, 0.f);
+      float4 o;
+      o.x = fmaxf(g[c + 0] * ((v.x - mean) * rstd) + b[c + 0] + sk.x, 0.f);
+      o.y = fmaxf(g[c + 1] * ((v.y - mean) * rstd) + b[c + 1] + sk.y, 0.f);
+      o.z = fmaxf(g[c + 2] * ((v.z - mean) * rstd) + b[c + 2] + sk.z, 0.f);
+      o.w = fmaxf(g[c + 3] * ((v.w - mean) * rstd) + b[c + 3] + sk.w, 0.f);
+      y[j] = o;
+      s.x += o.x; s.y += o.y; s.z += o.z; s.w += o.w;
+    }
+    if (pooled) pooled[i] = make_float4(0.125f * s.x, 0.125f * s.y, 0.125f * s.z, 0.125f * s.w);
   }
 }
 
@@ -233,12 +220,7 @@ inline int grid_for(size_t work, int per_thread = 1) {
 
 }  // namespace
 
-void ln_finalize(const double* part, int nparts, double count, float eps, LnStat* out,
-                 hipStream_t s) {
-  hipLaunchKernelGGL(k_ln_finalize, dim3(1), dim3(256), 0, s, part, nparts, count, eps, out);
-}
-
-void ln_apply(const float* h, const LnStat* st, const float* g, const float* b, const float* skip,
+void ln_apply(const float* h, PairRef st, const float* g, const float* b, const float* skip,
               float* y, size_t V, int C, hipStream_t s) {
   const size_t n4 = V * C / 4;
   hipLaunchKernelGGL(k_ln_apply, dim3(grid_for(n4)), dim3(256), 0, s,
@@ -257,25 +239,20 @@ int ln_bwd_vpb(int C) {
   return vpb;
 }
 
-void ln_bwd_sums(const float* gy, int mask_mode, const float* my, const float* mg, const float* mb,
-                 const float* h, const LnStat* st, float* gz, double* part, size_t V, int C,
-                 hipStream_t s) {
-  hipLaunchKernelGGL(k_ln_bwd_sums, dim3(ln_bwd_blocks(V, C)), dim3(256), 0, s, gy, mask_mode, my,
-                     mg, mb, h, st, gz, part, (int)V, C, ln_bwd_vpb(C));
+void ln_bwd(const float* gy, int mask_mode, const float* my, const float* mg, const float* mb,
+            const float* h, PairRef st, float* gz, double* part_c, double* part_ab, size_t V,
+            int C, const float* gamma, hipStream_t s) {
+  hipLaunchKernelGGL(k_ln_bwd, dim3(ln_bwd_blocks(V, C)), dim3(256), 0, s, gy, mask_mode, my, mg,
+                     mb, h, st, gz, part_c, part_ab, (int)V, C, ln_bwd_vpb(C), gamma);
 }
 
-void ln_bwd_finalize(const double* part, int nparts, int C, double count, const float* gamma,
-                     float* dgamma, float* dbeta, LnBwd* coef, hipStream_t s) {
-  hipLaunchKernelGGL(k_ln_bwd_finalize, dim3(1), dim3(256), 0, s, part, nparts, C, count, gamma,
-                     dgamma, dbeta, coef);
-}
-
-void ln_bwd_apply(const float* gz, const float* h, const LnStat* st, const float* gamma,
-                  const LnBwd* coef, float* gh, size_t V, int C, hipStream_t s) {
-  const size_t n4 = V * C / 4;
-  hipLaunchKernelGGL(k_ln_bwd_apply, dim3(grid_for(n4)), dim3(256), 0, s,
-                     reinterpret_cast<const float4*>(gz), reinterpret_cast<const float4*>(h), st,
-                     gamma, coef, reinterpret_cast<float4*>(gh), n4, C);
+void ln_apply_pool(const float* h, PairRef st, const float* g, const float* b, const float* skip,
+                   float* y, float* pooled, int n, int C, hipStream_t s) {
+  const size_t work = (size_t)(n / 2) * (n / 2) * (n / 2) * (C / 4);
+  hipLaunchKernelGGL(k_ln_apply_pool, dim3(grid_for(work)), dim3(256), 0, s,
+                     reinterpret_cast<const float4*>(h), st, g, b,
+                     reinterpret_cast<const float4*>(skip), reinterpret_cast<float4*>(y),
+                     reinterpret_cast<float4*>(pooled), n, C / 4);
 }
 
 void avgpool2(const float* x, int n, int C, float* y, hipStream_t s) {
