@@ -14,12 +14,24 @@ __global__ void k_grad_reduce(const GradSeg* __restrict__ segs, const float* __r
   __shared__ float sh[4][64];
   const GradSeg sg = segs[blockIdx.y];
   if (sg.kind == 1) {
-    // column sums of double partials [splits][cout]
+    // column sums of double partials [splits][cout]: 8 columns per pass, 32
+    // row groups (rows g, g + 32, ...) combined in group order
+    __shared__ double shd[32][8];
     const double* D = dpart + sg.part_off;
-    for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < sg.cout; k += gridDim.x * blockDim.x) {
+    const int col = threadIdx.x & 7, rg = threadIdx.x >> 3;
+    for (int k0 = blockIdx.x * 8; k0 < sg.cout; k0 += gridDim.x * 8) {
+      const int k = k0 + col;
       double acc = 0.0;
-      for (int i = 0; i < sg.splits; ++i) acc += D[(long long)i * sg.cout + k];
-      grad[sg.th_w + k] = (float)acc;
+      if (k < sg.cout)
+        for (int i = rg; i < sg.splits; i += 32) acc += D[(long long)i * sg.cout + k];
+      shd[rg][col] = acc;
+      __syncthreads();
+      if (rg == 0 && k < sg.cout) {
+        double t = 0.0;
+        for (int q = 0; q < 32; ++q) t += shd[q][col];
+        grad[sg.th_w + k] = (float)t;
+      }
+      __syncthreads();
     }
     return;
   }
@@ -84,6 +96,10 @@ void conv_wgrad(const ConvWgrad& a, hipStream_t s) {
 
 size_t conv_fwd_lds_bytes(int tile, int taps, int bn, int ck, int prec) {
   return conv_detail::fwd_lds_bytes(tile, taps, bn, ck, prec);
+}
+
+size_t conv_wgrad_lds_bytes(int tile, int taps, int ck, int prec) {
+  return conv_detail::wg_lds_bytes(tile, taps, ck, prec);
 }
 
 void grad_reduce(const GradSeg* segs, int nsegs, int max_elems, const float* part,

@@ -32,8 +32,8 @@ namespace d2ip {
 namespace conv_detail {
 
 constexpr int kCkMax = 32;       // largest channel chunk staged at once
-constexpr int kWgNtw = 2;        // weight-gradient N tiles per wave
-constexpr int kWgCols = 4 * kWgNtw * 16;  // columns per weight-gradient block
+constexpr int kWgNg = 8;         // weight-gradient column tiles per block (every wave)
+constexpr int kWgCols = kWgNg * 16;  // columns per weight-gradient block
 
 template <int TILE>
 struct TileDims;
@@ -433,6 +433,35 @@ __global__ __launch_bounds__(256) void k_conv_fwd(ConvFwd a) {
   }
 }
 
+// Weight-gradient LDS (dynamic): halo, g tile and the cross-wave exchange.
+//  FP32: halo [HP][ck+1] floats, g tile [BM][17] floats.
+//  BF16: halo channel-major in three copies shifted by dx = 0, 1, 2 so that
+//        8 consecutive voxels of a row are one aligned 16-byte read:
+//        [3][ck][HZ*HY*TX + 8] (hi, then lo parts), g tile [16][BM + 8].
+__host__ __device__ inline size_t wg_lds_bytes(int tile, int taps, int ck, int mode) {
+  int tz, ty, tx;
+  if (tile == TILE_2x4x16) {
+    tz = 2; ty = 4; tx = 16;
+  } else if (tile == TILE_1x4x16) {
+    tz = 1; ty = 4; tx = 16;
+  } else {
+    tz = 1; ty = 8; tx = 8;
+  }
+  const int r = taps == 27 ? 1 : 0;
+  const size_t bm = (size_t)tz * ty * tx;
+  size_t stage;
+  if (mode == PREC_F32) {
+    const size_t hp = (size_t)(tz + 2 * r) * (ty + 2 * r) * (tx + 2 * r);
+    stage = 4 * (hp * (ck + 1) + bm * 17);
+  } else {
+    const int parts = mode == PREC_BF16X3 ? 2 : 1;
+    const size_t plane = (size_t)(tz + 2 * r) * (ty + 2 * r) * tx + 8;
+    stage = parts * 2 * ((taps == 27 ? 3 : 1) * ck * plane + 16 * (bm + 8));
+  }
+  const size_t xch = (size_t)4 * kWgNg * 64 * 16;
+  return stage > xch ? stage : xch;
+}
+
 template <int MODE, int TAPS, int TILE, int PRO, int GPRO>
 __global__ __launch_bounds__(256) void k_conv_wgrad(ConvWgrad a) {
   using MD = Mode<MODE>;
@@ -445,20 +474,20 @@ __global__ __launch_bounds__(256) void k_conv_wgrad(ConvWgrad a) {
   constexpr int HP = HZ * HY * HX;
   constexpr int KPL = MD::KPL, KSTEP = MD::KSTEP;
   constexpr int BM = TZ * TY * TX;
-  constexpr int GP = MD::BF ? BM + 8 : 17;  // g tile row pitch
+  constexpr int NSTEP = BM / KSTEP;
+  constexpr int NCOPY = TAPS == 27 ? 3 : 1;       // BF16: dx-shifted halo copies
+  constexpr int PLANE = HZ * HY * TX + 8;          // BF16: elements per (copy, channel)
+  constexpr int GP = MD::BF ? BM + 8 : 17;         // g tile row pitch
   constexpr int GSZ = MD::BF ? 16 * GP : BM * GP;
-  __shared__ __align__(16) ST hal[HP * (kCkMax + MD::PAD)];
-  __shared__ __align__(16) ST hal_lo[MD::SPLIT ? HP * (kCkMax + MD::PAD) : 8];
-  // BF16: gs[co][voxel]; FP32: gs[voxel][co]
-  __shared__ __align__(16) ST gs[GSZ];
-  __shared__ __align__(16) ST gs_lo[MD::SPLIT ? GSZ : 8];
+  extern __shared__ __align__(16) unsigned char smem[];
   __shared__ float4 bred[256];
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int l16 = lane & 15, g = lane >> 4;
   const int n = a.n;
-  const int ck = a.ck, ckp = ck + MD::PAD;
+  const int ck = a.ck;
   const int ck_shift = __builtin_ctz(ck);
+  const int ckp = ck + 1;                          // FP32 halo row pitch
   const int ntot = TAPS * ck;
   const int ngroups = (ntot + kWgCols - 1) / kWgCols;
   const int chunk = blockIdx.y / ngroups, grp = blockIdx.y - chunk * ngroups;
@@ -468,23 +497,40 @@ __global__ __launch_bounds__(256) void k_conv_wgrad(ConvWgrad a) {
   const int co0 = blockIdx.z * 16;
   const bool do_bias = blockIdx.y == 0;
 
+  // LDS carve
+  ST* hal = reinterpret_cast<ST*>(smem);
+  const int hal_sz = MD::BF ? NCOPY * ck * PLANE : HP * ckp;
+  ST* hal_lo = hal + (MD::SPLIT ? hal_sz : 0);
+  ST* gs = hal + (MD::SPLIT ? 2 : 1) * hal_sz;
+  ST* gs_lo = gs + (MD::SPLIT ? GSZ : 0);
+
   float gmean, grstd, gA, gB;
   src_consts<GPRO>(a.gsrc, gmean, grstd, gA, gB);
   float xmean, xrstd, xA, xB;
   src_consts<PRO>(a.src, xmean, xrstd, xA, xB);
 
-  f32x4 acc[kWgNtw];
+  // this block's columns (tap, channel), shared by all waves
+  f32x4 acc[kWgNg];
 #pragma unroll
-  for (int j = 0; j < kWgNtw; ++j) acc[j] = (f32x4){0.f, 0.f, 0.f, 0.f};
-  float4 bacc = make_float4(0.f, 0.f, 0.f, 0.f);
-  // columns of this wave: nn = (grp*4*kWgNtw + wave*kWgNtw + j)*16 + l16
-  int ncol[kWgNtw], ctap[kWgNtw], cc[kWgNtw];
+  for (int j = 0; j < kWgNg; ++j) acc[j] = (f32x4){0.f, 0.f, 0.f, 0.f};
+  int ctap[kWgNg], cc[kWgNg], coff[kWgNg];
+  bool cval[kWgNg];
 #pragma unroll
-  for (int j = 0; j < kWgNtw; ++j) {
-    ncol[j] = ((grp * 4 + wave) * kWgNtw + j) * 16 + l16;
-    ctap[j] = ncol[j] >> ck_shift;
-    cc[j] = ncol[j] & (ck - 1);
+  for (int j = 0; j < kWgNg; ++j) {
+    const int nn = (grp * kWgNg + j) * 16 + l16;
+    cval[j] = nn < ntot;
+    ctap[j] = cval[j] ? nn >> ck_shift : 0;
+    cc[j] = nn & (ck - 1);
+    if constexpr (MD::BF) {
+      // copy dx, channel c, plane offset of (dz, dy)
+      const int dz = TAPS == 27 ? ctap[j] / 9 : 0, dy = TAPS == 27 ? (ctap[j] / 3) % 3 : 0;
+      const int dx = TAPS == 27 ? ctap[j] % 3 : 0;
+      coff[j] = (dx * ck + cc[j]) * PLANE + (dz * HY + dy) * TX;
+    } else {
+      coff[j] = (TAPS == 27 ? tap_offset(ctap[j], HY, HX) : 0) * ckp + cc[j];
+    }
   }
+  float4 bacc = make_float4(0.f, 0.f, 0.f, 0.f);
 
   for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
     int b = t;
@@ -493,9 +539,49 @@ __global__ __launch_bounds__(256) void k_conv_wgrad(ConvWgrad a) {
     const int y0 = (b % nty) * TY;
     b /= nty;
     const int z0 = b * TZ;
-    stage_halo<MODE, HZ, HY, HX, PRO>(hal, hal_lo, a.src, n, ck, ckp, ci0, z0, y0, x0, R, xmean,
-                                      xrstd, xA, xB);
-    // g tile: BM voxels x 16 output channels (zero outside the grid / cout)
+    // ---- halo of ck channels
+    {
+      const int Q = ck >> 2;
+      for (int p = tid; p < HP * Q; p += 256) {
+        const int pos = p / Q, q = p - pos * Q;
+        const int hx = pos % HX, hy = (pos / HX) % HY, hz = pos / (HX * HY);
+        const int gz = z0 + hz - R, gy = y0 + hy - R, gx = x0 + hx - R;
+        float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+        const int c = ci0 + 4 * q;
+        if (gz >= 0 && gz < n && gy >= 0 && gy < n && gx >= 0 && gx < n)
+          v = load_src4<PRO>(a.src, (size_t)((gz * n + gy) * n + gx) * a.src.stride + c, c, xmean,
+                             xrstd, xA, xB);
+        if constexpr (MD::BF) {
+          // scatter into the dx copies that contain column hx
+          const float e[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+          for (int dx = 0; dx < NCOPY; ++dx) {
+            const int tx = hx - dx;
+            if (tx < 0 || tx >= TX) continue;
+            const int base = (hz * HY + hy) * TX + tx;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+              const int o = (dx * ck + 4 * q + k) * PLANE + base;
+              if constexpr (MD::SPLIT) {
+                uint16_t hi, lo;
+                split_bf(e[k], hi, lo);
+                hal[o] = hi;
+                hal_lo[o] = lo;
+              } else {
+                hal[o] = f2bf(e[k]);
+              }
+            }
+          }
+        } else {
+          float* d = hal + pos * ckp + 4 * q;
+          d[0] = v.x;
+          d[1] = v.y;
+          d[2] = v.z;
+          d[3] = v.w;
+        }
+      }
+    }
+    // ---- g tile: BM voxels x 16 output channels (zero outside the grid / cout)
     for (int p = tid; p < BM * 4; p += 256) {
       const int v = p >> 2, q = p & 3;
       const int tz = v / (TY * TX), ty = (v / TX) % TY, tx = v % TX;
@@ -531,60 +617,33 @@ __global__ __launch_bounds__(256) void k_conv_wgrad(ConvWgrad a) {
       }
     }
     __syncthreads();
+    // ---- every wave: all column tiles, voxel k-steps ks = wave, wave + 4, ...
 #pragma unroll 2
-    for (int ks = 0; ks < BM / KSTEP; ++ks) {
+    for (int ks = wave; ks < NSTEP; ks += 4) {
       FT A, Al;
-      FT B[kWgNtw], Bl[MD::SPLIT ? kWgNtw : 1];
+      FT B[kWgNg], Bl[MD::SPLIT ? kWgNg : 1];
       if constexpr (MD::BF) {
-        const int v0 = ks * KSTEP + g * KPL;
+        const int v0 = ks * KSTEP + g * KPL;  // 8 consecutive voxels of one row
         A = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u32x4*>(gs + l16 * GP + v0));
         if constexpr (MD::SPLIT)
           Al = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u32x4*>(gs_lo + l16 * GP + v0));
+        const int tz = v0 / (TY * TX), ty = (v0 / TX) % TY, tx = v0 % TX;
+        const int vb = (tz * HY + ty) * TX + tx;
 #pragma unroll
-        for (int j = 0; j < kWgNtw; ++j) {
-          uint16_t e[8], el[8];
-          if (ncol[j] < ntot) {
-            const int toff = TAPS == 27 ? tap_offset(ctap[j], HY, HX) : 0;
-#pragma unroll
-            for (int q = 0; q < 8; ++q) {
-              const int v = v0 + q;
-              const int tz = v / (TY * TX), ty = (v / TX) % TY, tx = v % TX;
-              const int o = ((tz * HY + ty) * HX + tx + toff) * ckp + cc[j];
-              e[q] = hal[o];
-              if constexpr (MD::SPLIT) el[q] = hal_lo[o];
-            }
-          } else {
-#pragma unroll
-            for (int q = 0; q < 8; ++q) {
-              e[q] = 0;
-              el[q] = 0;
-            }
-          }
-          u32x4 pk = {pack2(e[0], e[1]), pack2(e[2], e[3]), pack2(e[4], e[5]), pack2(e[6], e[7])};
-          B[j] = __builtin_bit_cast(bf16x8, pk);
-          if constexpr (MD::SPLIT) {
-            u32x4 pl = {pack2(el[0], el[1]), pack2(el[2], el[3]), pack2(el[4], el[5]),
-                        pack2(el[6], el[7])};
-            Bl[j] = __builtin_bit_cast(bf16x8, pl);
-          }
+        for (int j = 0; j < kWgNg; ++j) {
+          B[j] = frag<MODE>(hal + coff[j] + vb, cval[j]);
+          if constexpr (MD::SPLIT) Bl[j] = frag<MODE>(hal_lo + coff[j] + vb, cval[j]);
         }
       } else {
         const int v = ks * KSTEP + g;
         A = gs[v * GP + l16];
         const int tz = v / (TY * TX), ty = (v / TX) % TY, tx = v % TX;
-        const int vp = (tz * HY + ty) * HX + tx;
+        const int vp = ((tz * HY + ty) * HX + tx) * ckp;
 #pragma unroll
-        for (int j = 0; j < kWgNtw; ++j) {
-          float e = 0.f;
-          if (ncol[j] < ntot) {
-            const int toff = TAPS == 27 ? tap_offset(ctap[j], HY, HX) : 0;
-            e = hal[(vp + toff) * ckp + cc[j]];
-          }
-          B[j] = e;
-        }
+        for (int j = 0; j < kWgNg; ++j) B[j] = cval[j] ? hal[vp + coff[j]] : 0.f;
       }
 #pragma unroll
-      for (int j = 0; j < kWgNtw; ++j) {
+      for (int j = 0; j < kWgNg; ++j) {
         if constexpr (MD::SPLIT) {
           acc[j] = mfma(Al, B[j], acc[j]);
           acc[j] = mfma(A, Bl[j], acc[j]);
@@ -595,15 +654,26 @@ __global__ __launch_bounds__(256) void k_conv_wgrad(ConvWgrad a) {
     __syncthreads();
   }
 
+  // ---- cross-wave exchange (fixed wave order), then this block's partials
+  f32x4* xch = reinterpret_cast<f32x4*>(smem);
+#pragma unroll
+  for (int j = 0; j < kWgNg; ++j) xch[(wave * kWgNg + j) * 64 + lane] = acc[j];
+  __syncthreads();
   const int cout16 = (a.cout + 15) & ~15;
   float* part = a.part + (size_t)blockIdx.x * cout16 * TAPS * a.cin;
 #pragma unroll
-  for (int j = 0; j < kWgNtw; ++j) {
-    if (ncol[j] >= ntot) continue;
+  for (int jj = 0; jj < kWgNg / 4; ++jj) {
+    const int j = wave + 4 * jj;
+    f32x4 v = (f32x4){0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int w = 0; w < 4; ++w) v += xch[(w * kWgNg + j) * 64 + lane];
+    const int nn = (grp * kWgNg + j) * 16 + l16;
+    if (nn >= ntot) continue;
+    const int tap = nn >> ck_shift, c = nn & (ck - 1);
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int co = co0 + 4 * g + r;
-      if (co < a.cout) part[((size_t)co * TAPS + ctap[j]) * a.cin + ci0 + cc[j]] = acc[j][r];
+      if (co < a.cout) part[((size_t)co * TAPS + tap) * a.cin + ci0 + c] = v[r];
     }
   }
   if (do_bias) {
@@ -683,7 +753,8 @@ void fwd_tile(const ConvFwd& a, hipStream_t s) {
 template <int MODE, int TAPS, int TILE, int PRO, int GPRO>
 void launch_wg(const ConvWgrad& a, hipStream_t s) {
   dim3 grid(a.splits, (a.cin / a.ck) * conv_wgrad_groups(a.taps, a.ck), (a.cout + 15) / 16);
-  hipLaunchKernelGGL((k_conv_wgrad<MODE, TAPS, TILE, PRO, GPRO>), grid, dim3(256), 0, s, a);
+  const size_t lds = wg_lds_bytes(TILE, TAPS, a.ck, MODE);
+  hipLaunchKernelGGL((k_conv_wgrad<MODE, TAPS, TILE, PRO, GPRO>), grid, dim3(256), lds, s, a);
 }
 
 template <int MODE, int TAPS, int TILE>

@@ -72,6 +72,7 @@ struct Block {
   float* pool_out = nullptr;        // encoder l < L-1: input of encoder l+1
   const float* up_src = nullptr;    // decoder: output of the level below
   const float* skip_src = nullptr;  // decoder: output of encoder l
+  float *gz = nullptr, *ga = nullptr;  // this block's LayerNorm-backward gradients
   PairRef st1{}, st2{};         // forward statistics partials of h1, h2
   PairRef cb1{}, cb2{};         // LayerNorm-backward coefficient partials
   double *lnc1 = nullptr, *lnc2 = nullptr;  // per-channel dgamma/dbeta partials
@@ -142,7 +143,7 @@ int pick_tile(int n) {
 int largest_ck(int cin) { return cin % 32 == 0 ? 32 : cin % 16 == 0 ? 16 : 8; }
 
 constexpr int kTargetBlocks = 256;
-constexpr size_t kLdsBudget = 64 * 1024;
+constexpr size_t kLdsBudget = 60 * 1024;  // dynamic LDS per block (static use stays small)
 
 // Enough blocks to cover the chip: narrow N tiles and channel split-K on
 // coarse grids, wide N tiles and whole-channel chunks on fine ones; the halo
@@ -295,6 +296,9 @@ void add_conv(Instance& I, Conv& c, int prec, size_t& kpart_max, int& tiles_max)
 
   const size_t V = (size_t)c.n * c.n * c.n;
   c.fwd = choose_shape(c.n, c.cin, c.cout, c.taps, prec);
+  // 1x1 projections run forward on the side stream, concurrently with split-K
+  // convs of the main stream: they must not share the split-K scratch
+  if (c.taps == 1) c.fwd.ksplit = 1;
   tiles_max = std::max(tiles_max, conv_tiles(c.n, c.fwd.tile) * ((c.cout + c.fwd.bn - 1) / c.fwd.bn));
   if (c.fwd.ksplit > 1) kpart_max = std::max(kpart_max, (size_t)c.fwd.ksplit * V * c.cout);
   if (c.dgrad) {
@@ -306,6 +310,8 @@ void add_conv(Instance& I, Conv& c, int prec, size_t& kpart_max, int& tiles_max)
   // weight gradient: voxel splits sized so that about 512 blocks run
   c.wg_tile = pick_tile(c.n);
   c.wg_ck = largest_ck(c.cin);
+  while (c.wg_ck > 8 && conv_wgrad_lds_bytes(c.wg_tile, c.taps, c.wg_ck, prec) > kLdsBudget)
+    c.wg_ck >>= 1;
   const int cout16 = (c.cout + 15) / 16 * 16;
   const int per = (c.cin / c.wg_ck) * conv_wgrad_groups(c.taps, c.wg_ck) * (cout16 / 16);
   const int tiles = conv_tiles(c.n, c.wg_tile);
@@ -343,6 +349,8 @@ struct d2ip_ctx {
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
   hipStream_t cap = nullptr;  // capture stream (the caller's may be the legacy default stream)
+  hipStream_t side = nullptr;  // branch for work off the critical path (weight gradients)
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   size_t bytes = 0;
 };
 
@@ -483,6 +491,8 @@ void plan(d2ip_ctx& X, const d2ip_geometry_desc* gd, int n_geo, const d2ip_insta
       b.y = cv.take<float>(V * b.cout);
       if (b.proj) b.s = cv.take<float>(V * b.cout);
       if (b.enc && b.level < L - 1) b.pool_out = cv.take<float>(V / 8 * b.cout);
+      b.gz = cv.take<float>(V * b.cout);
+      b.ga = cv.take<float>(V * b.cout);
       const int nb = ln_bwd_blocks(V, b.cout);
       const double cnt = (double)V * b.cout;
       b.st1 = PairRef{dp(o_st1[k]), fwd_tiles(b.c1), cnt};
@@ -594,7 +604,8 @@ ConvFwd dgrad_args(const d2ip_ctx& X, const Instance& I, const Conv& c, ConvSrc 
   return a;
 }
 
-void wgrad(const d2ip_ctx& X, const Instance& I, const Conv& c, ConvSrc xs, ConvSrc gsrc) {
+void wgrad(const d2ip_ctx& X, const Instance& I, const Conv& c, ConvSrc xs, ConvSrc gsrc,
+           hipStream_t stream) {
   ConvWgrad a;
   std::memset(&a, 0, sizeof(a));
   a.src = xs;
@@ -609,7 +620,17 @@ void wgrad(const d2ip_ctx& X, const Instance& I, const Conv& c, ConvSrc xs, Conv
   a.prec = conv_prec(X.precision);
   a.tile = c.wg_tile;
   a.ck = c.wg_ck;
-  conv_wgrad(a, X.stream);
+  conv_wgrad(a, stream);
+}
+
+// Fork the side stream off the main stream at this point / join it back.
+void fork(d2ip_ctx& X) {
+  hipEventRecord(X.ev_fork, X.stream);
+  hipStreamWaitEvent(X.side, X.ev_fork, 0);
+}
+void join(d2ip_ctx& X) {
+  hipEventRecord(X.ev_join, X.side);
+  hipStreamWaitEvent(X.stream, X.ev_join, 0);
 }
 
 void enqueue_forward(d2ip_ctx& X, Instance& I) {
@@ -622,12 +643,17 @@ void enqueue_forward(d2ip_ctx& X, Instance& I) {
   for (Block& b : I.blocks) {
     const size_t V = (size_t)b.n * b.n * b.n;
     if (!b.enc) up_concat(b.up_src, b.cout * 2, b.skip_src, b.cout, b.n, b.x, s);
+    if (b.proj) {
+      // the 1x1 projection only needs x: overlap it with conv1 / conv2
+      fork(X);
+      conv_fwd(fwd_args(X, I, b.pj, src_plain(b.x, b.cin), b.s, nullptr), X.side);
+    }
     conv_fwd(fwd_args(X, I, b.c1, src_plain(b.x, b.cin), b.h1, &b.st1), s);
     conv_fwd(fwd_args(X, I, b.c2,
                       src_ln_relu(b.h1, b.cout, b.st1, th + b.n1.th_g, th + b.n1.th_b), b.h2,
                       &b.st2),
              s);
-    if (b.proj) conv_fwd(fwd_args(X, I, b.pj, src_plain(b.x, b.cin), b.s, nullptr), s);
+    if (b.proj) join(X);
     const float* skip = b.proj ? b.s : b.x;
     if (b.enc && b.level < L - 1)
       ln_apply_pool(b.h2, b.st2, th + b.n2.th_g, th + b.n2.th_b, skip, b.y, b.pool_out, b.n,
@@ -650,7 +676,9 @@ void enqueue_iteration(d2ip_ctx& X, Instance& I) {
   jtvec(G.Jc, G.M, G.qa_pad, I.ppart, nqb, I.dv, I.rsum, I.tpart, s);
   tail_bwd(I.tpart, jt_mblocks(G.M), G.qa_pad, G.inv, I.blocks.back().y, I.C, th + I.tail_w,
            I.V0, I.lv[0].gy, I.tail_part, s);
-  // network backward, decoder first
+  // network backward, decoder first.  Weight gradients only feed the batched
+  // reduction at the end: they run on the side stream, overlapping the
+  // input-gradient chain, and join before the reduction.
   for (int k = (int)I.blocks.size() - 1; k >= 0; --k) {
     Block& b = I.blocks[k];
     Level& Lv = I.lv[b.level];
@@ -659,24 +687,26 @@ void enqueue_iteration(d2ip_ctx& X, Instance& I) {
     const float* b1 = th + b.n1.th_b;
     const float* g2 = th + b.n2.th_g;
     // LN2 backward (mask from y): gz and its partials
-    ln_bwd(Lv.gy, LNMASK_Y, b.y, nullptr, nullptr, b.h2, b.st2, Lv.gz, b.lnc2,
+    ln_bwd(Lv.gy, LNMASK_Y, b.y, nullptr, nullptr, b.h2, b.st2, b.gz, b.lnc2,
            const_cast<double*>(b.cb2.part), V, b.cout, g2, s);
-    const ConvSrc gh2 = src_ln_bwd(Lv.gz, b.h2, b.cout, b.st2, g2, b.cb2);
-    wgrad(X, I, b.c2, src_ln_relu(b.h1, b.cout, b.st1, g1, b1), gh2);
-    conv_fwd(dgrad_args(X, I, b.c2, gh2, Lv.ga), s);
+    const ConvSrc gh2 = src_ln_bwd(b.gz, b.h2, b.cout, b.st2, g2, b.cb2);
+    fork(X);
+    wgrad(X, I, b.c2, src_ln_relu(b.h1, b.cout, b.st1, g1, b1), gh2, X.side);
+    if (b.proj) wgrad(X, I, b.pj, src_plain(b.x, b.cin), src_plain(b.gz, b.cout), X.side);
+    conv_fwd(dgrad_args(X, I, b.c2, gh2, b.ga), s);
     // LN1 backward (mask from LN1 output), in place on ga
-    ln_bwd(Lv.ga, LNMASK_LN, nullptr, g1, b1, b.h1, b.st1, Lv.ga, b.lnc1,
+    ln_bwd(b.ga, LNMASK_LN, nullptr, g1, b1, b.h1, b.st1, b.ga, b.lnc1,
            const_cast<double*>(b.cb1.part), V, b.cout, g1, s);
-    const ConvSrc gh1 = src_ln_bwd(Lv.ga, b.h1, b.cout, b.st1, g1, b.cb1);
-    wgrad(X, I, b.c1, src_plain(b.x, b.cin), gh1);
+    const ConvSrc gh1 = src_ln_bwd(b.ga, b.h1, b.cout, b.st1, g1, b.cb1);
+    fork(X);
+    wgrad(X, I, b.c1, src_plain(b.x, b.cin), gh1, X.side);
     {
       ConvFwd a = dgrad_args(X, I, b.c1, gh1, Lv.gx);
-      if (!b.proj) a.add = Lv.gz;
+      if (!b.proj) a.add = b.gz;
       conv_fwd(a, s);
     }
     if (b.proj) {
-      wgrad(X, I, b.pj, src_plain(b.x, b.cin), src_plain(Lv.gz, b.cout));
-      ConvFwd a = dgrad_args(X, I, b.pj, src_plain(Lv.gz, b.cout), Lv.gx);
+      ConvFwd a = dgrad_args(X, I, b.pj, src_plain(b.gz, b.cout), Lv.gx);
       a.accumulate = 1;
       conv_fwd(a, s);
     }
@@ -693,8 +723,11 @@ void enqueue_iteration(d2ip_ctx& X, Instance& I) {
     const float* gs = th + I.stem_n.th_g;
     ln_bwd(L0.gx, LNMASK_Y, I.as, nullptr, nullptr, I.hs, I.sts, L0.gz, I.lncs,
            const_cast<double*>(I.cbs.part), I.V0, I.C, gs, s);
-    wgrad(X, I, I.stem, src_plain(I.zpad, 8), src_ln_bwd(L0.gz, I.hs, I.C, I.sts, gs, I.cbs));
+    fork(X);
+    wgrad(X, I, I.stem, src_plain(I.zpad, 8), src_ln_bwd(L0.gz, I.hs, I.C, I.sts, gs, I.cbs),
+          X.side);
   }
+  join(X);
   grad_reduce(I.segs_dev, (int)I.segs.size(), I.max_seg, I.wg_part, I.wg_partb, I.dpart, gr, s);
   adam(th, gr, I.m, I.v, I.P, X.lr, X.b1, X.b2, X.eps, I.it, s);
   pack_weights(I.packs_dev, (int)I.packs.size(), I.max_pack, th, I.wf32, I.wbf16,
@@ -799,6 +832,10 @@ d2ip_status d2ip_create(const d2ip_geometry_desc* geos, int n_geo, const d2ip_in
   cv.base = reinterpret_cast<char*>(workspace);
   plan(*X, geos, n_geo, insts, n_inst, cv);
   auto cleanup = [&](d2ip_status s) {
+    if (X->ev_join) hipEventDestroy(X->ev_join);
+    if (X->ev_fork) hipEventDestroy(X->ev_fork);
+    if (X->side) hipStreamDestroy(X->side);
+    if (X->cap) hipStreamDestroy(X->cap);
     delete X;
     return s;
   };
@@ -817,6 +854,9 @@ d2ip_status d2ip_create(const d2ip_geometry_desc* geos, int n_geo, const d2ip_in
   if (e == hipSuccess) e = hipStreamSynchronize(X->stream);
   if (e == hipSuccess && (flags & D2IP_FLAG_GRAPH))
     e = hipStreamCreateWithFlags(&X->cap, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&X->side, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&X->ev_fork, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&X->ev_join, hipEventDisableTiming);
   if (e != hipSuccess)
     return cleanup(fail(D2IP_EHIP, std::string("workspace init: ") + hipGetErrorString(e)));
   *out = X;
@@ -827,6 +867,10 @@ d2ip_status d2ip_destroy(d2ip_ctx* X) {
   if (!X) return D2IP_OK;
   hipStreamSynchronize(X->stream);
   drop_graph(X);
+  if (X->side) hipStreamSynchronize(X->side);
+  if (X->ev_join) hipEventDestroy(X->ev_join);
+  if (X->ev_fork) hipEventDestroy(X->ev_fork);
+  if (X->side) hipStreamDestroy(X->side);
   if (X->cap) hipStreamDestroy(X->cap);
   delete X;
   return D2IP_OK;
@@ -1079,7 +1123,7 @@ d2ip_status d2ip_time_kernel(d2ip_ctx* X, int inst, int which, int block, int re
       case D2IP_KERNEL_CONV_DGRAD: {
         const float* th = I.theta;
         conv_fwd(dgrad_args(*X, I, b->c1,
-                            src_ln_bwd(Lv->ga, b->h1, b->cout, b->st1, th + b->n1.th_g, b->cb1),
+                            src_ln_bwd(b->ga, b->h1, b->cout, b->st1, th + b->n1.th_g, b->cb1),
                             Lv->gx),
                  s);
         break;
@@ -1087,7 +1131,7 @@ d2ip_status d2ip_time_kernel(d2ip_ctx* X, int inst, int which, int block, int re
       default: {
         const float* th = I.theta;
         wgrad(*X, I, b->c1, src_plain(b->x, b->cin),
-              src_ln_bwd(Lv->ga, b->h1, b->cout, b->st1, th + b->n1.th_g, b->cb1));
+              src_ln_bwd(b->ga, b->h1, b->cout, b->st1, th + b->n1.th_g, b->cb1), s);
         break;
       }
     }

@@ -73,6 +73,7 @@ struct ConvWgrad {
   int splits, prec, tile, ck;
 };
 int conv_wgrad_groups(int taps, int ck);
+size_t conv_wgrad_lds_bytes(int tile, int taps, int ck, int prec);
 void conv_wgrad(const ConvWgrad& a, hipStream_t s);
 
 // One slice of the batched gradient reduction at the end of an iteration.
