@@ -109,6 +109,15 @@ d2ip_status d2ip_workspace_bytes(const d2ip_geometry_desc* geos, int n_geo,
                                  const d2ip_instance_desc* insts, int n_inst, int precision,
                                  unsigned flags, size_t* out);
 
+/* Host-only self check: plan the workspace for these arguments at a fake
+ * address and walk one iteration's launch schedule without launching,
+ * verifying that every kernel argument's extent lies inside one workspace
+ * allocation for every instance.  D2IP_EINVAL with the violations in
+ * d2ip_last_error() if not.  Needs no GPU. */
+d2ip_status d2ip_check_launches(const d2ip_geometry_desc* geos, int n_geo,
+                                const d2ip_instance_desc* insts, int n_inst, int precision,
+                                unsigned flags);
+
 /* Create a context over `workspace` (device memory, >= d2ip_workspace_bytes)
  * that enqueues on `hip_stream` (a hipStream_t; NULL = default stream).
  * All instances start with theta = 0, Adam state zero and no frame. */

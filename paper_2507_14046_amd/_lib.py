@@ -44,6 +44,8 @@ SIGNATURES = {
     "d2ip_param_count": [_i, _i, _c_size_p],
     "d2ip_workspace_bytes": [ctypes.POINTER(GeometryDesc), _i, ctypes.POINTER(InstanceDesc), _i, _i,
                              ctypes.c_uint, _c_size_p],
+    "d2ip_check_launches": [ctypes.POINTER(GeometryDesc), _i, ctypes.POINTER(InstanceDesc), _i, _i,
+                            ctypes.c_uint],
     "d2ip_create": [ctypes.POINTER(GeometryDesc), _i, ctypes.POINTER(InstanceDesc), _i, _i,
                     ctypes.c_uint, _vp, ctypes.c_size_t, _vp, ctypes.POINTER(_vp)],
     "d2ip_destroy": [_vp],

@@ -34,6 +34,14 @@ def workspace_bytes(geometries, instances, precision="fp32", graph=False):
     return out.value
 
 
+def check_launches(geometries, instances, precision="fp32", graph=False):
+    """Host-only launch-extent check of one iteration (raises D2ipError)."""
+    lib = L.load()
+    G, I = _descs(geometries, instances)
+    L.check(lib.d2ip_check_launches(G, len(geometries), I, len(instances), _prec(precision),
+                                    L.FLAG_GRAPH if graph else 0))
+
+
 def _prec(p):
     if p in ("fp32", L.PLAIN_FP32):
         return L.PLAIN_FP32

@@ -3,6 +3,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #define D2IP_WAVE 64
 
 typedef __attribute__((ext_vector_type(4))) float f32x4;
@@ -139,4 +141,12 @@ __device__ __forceinline__ float load_dev(const float* p) {
 }
 __device__ __forceinline__ double load_dev(const double* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Members of an instance group share every shape; member b's data lives
+// b * istride bytes after member 0's.  A kernel shifts its per-member pointers.
+template <class T>
+__host__ __device__ __forceinline__ T* ishift(T* p, long long off) {
+  return p ? reinterpret_cast<T*>(reinterpret_cast<char*>(const_cast<typename std::remove_const<T>::type*>(p)) + off)
+           : p;
 }

@@ -8,11 +8,18 @@ namespace {
 // One block row per conv segment.  A block owns 64 consecutive partial
 // elements (layout [co][tap][ci]); its 4 thread groups sum interleaved split
 // subsets, combined in group order, so the sum order is fixed.
-__global__ void k_grad_reduce(const GradSeg* __restrict__ segs, const float* __restrict__ part,
-                              const float* __restrict__ partb, const double* __restrict__ dpart,
-                              float* __restrict__ grad) {
+__global__ void k_grad_reduce(const GradSeg* __restrict__ segs, const float* part,
+                              const float* partb, const double* dpart, float* grad,
+                              long long istride) {
   __shared__ float sh[4][64];
   const GradSeg sg = segs[blockIdx.y];
+  {
+    const long long off = (long long)blockIdx.z * istride;  // group member
+    part = ishift(part, off);
+    partb = ishift(partb, off);
+    dpart = ishift(dpart, off);
+    grad = ishift(grad, off);
+  }
   if (sg.kind == 1) {
     // column sums of double partials [splits][cout]: 8 columns per pass, 32
     // row groups (rows g, g + 32, ...) combined in group order
@@ -103,12 +110,13 @@ size_t conv_wgrad_lds_bytes(int tile, int taps, int ck, int prec) {
 }
 
 void grad_reduce(const GradSeg* segs, int nsegs, int max_elems, const float* part,
-                 const float* partb, const double* dpart, float* grad, hipStream_t s) {
+                 const float* partb, const double* dpart, float* grad, int batch,
+                 long long istride, hipStream_t s) {
   int bx = (max_elems + 63) / 64;
   if (bx > 1024) bx = 1024;
   if (bx < 1) bx = 1;
-  hipLaunchKernelGGL(k_grad_reduce, dim3(bx, nsegs), dim3(256), 0, s, segs, part, partb, dpart,
-                     grad);
+  hipLaunchKernelGGL(k_grad_reduce, dim3(bx, nsegs, batch), dim3(256), 0, s, segs, part, partb,
+                     dpart, grad, istride);
 }
 
 }  // namespace d2ip

@@ -211,6 +211,20 @@ __device__ __forceinline__ typename Mode<MODE>::FT frag(const typename Mode<MODE
 
 template <int MODE, int TAPS, int TILE, int BN, int PRO>
 __global__ __launch_bounds__(256) void k_conv_fwd(ConvFwd a) {
+  // grid z = member * ksplit + split
+  const int ksplit = a.ksplit;
+  const int kz = blockIdx.z % ksplit;
+  {
+    const long long off = (long long)(blockIdx.z / ksplit) * a.istride;
+    a.src = shift_src(a.src, off);
+    a.w = ishift(a.w, off);
+    a.bias = ishift(a.bias, off);
+    a.add = ishift(a.add, off);
+    a.y = ishift(a.y, off);
+    a.stat_part = ishift(a.stat_part, off);
+    a.kpart = ishift(a.kpart, off);
+    a.counters = ishift(a.counters, off);
+  }
   using MD = Mode<MODE>;
   using ST = typename MD::ST;
   using FT = typename MD::FT;
@@ -263,11 +277,11 @@ __global__ __launch_bounds__(256) void k_conv_fwd(ConvFwd a) {
   const ST* __restrict__ W = reinterpret_cast<const ST*>(a.w);
   const ST* __restrict__ Wlo = W + a.w_lo_off;
   const int nchunks = a.cin >> ck_shift;
-  const int cps = nchunks / (int)gridDim.z;
+  const int cps = nchunks / ksplit;
   const int nstep = (TAPS * ck + KSTEP - 1) / KSTEP;
   float pmean, prstd, pA, pB;
   src_consts<PRO>(a.src, pmean, prstd, pA, pB);
-  for (int ch = blockIdx.z * cps; ch < (int)(blockIdx.z + 1) * cps; ++ch) {
+  for (int ch = kz * cps; ch < (kz + 1) * cps; ++ch) {
     const int ci0 = ch << ck_shift;
     stage_halo<MODE, HZ, HY, HX, PRO>(hal, hal_lo, a.src, n, ck, ckp, ci0, z0, y0, x0, R, pmean,
                                       prstd, pA, pB);
@@ -360,10 +374,10 @@ __global__ __launch_bounds__(256) void k_conv_fwd(ConvFwd a) {
 
   const int tile_id = blockIdx.y * gridDim.x + blockIdx.x;
   const size_t V = (size_t)n * n * n;
-  if (gridDim.z > 1) {
+  if (ksplit > 1) {
     // split-K: publish this block's partial tile; the last block of the tile
     // sums all partials in split order and continues with the epilogue
-    float* kp = a.kpart + (size_t)blockIdx.z * V * a.cout;
+    float* kp = a.kpart + (size_t)kz * V * a.cout;
 #pragma unroll
     for (int j = 0; j < TPW; ++j) {
       const int t = wave + 4 * j;
@@ -379,7 +393,7 @@ __global__ __launch_bounds__(256) void k_conv_fwd(ConvFwd a) {
         kp[((size_t)(gz * n + gy) * n + gx) * a.cout + co] = fin[j][r];
       }
     }
-    if (!arrive_last(a.counters + tile_id, gridDim.z)) return;
+    if (!arrive_last(a.counters + tile_id, ksplit)) return;
 #pragma unroll
     for (int j = 0; j < TPW; ++j) {
       const int t = wave + 4 * j;
@@ -394,7 +408,7 @@ __global__ __launch_bounds__(256) void k_conv_fwd(ConvFwd a) {
         if (gz >= n || gy >= n || gx >= n || co >= a.cout) continue;
         const size_t o = ((size_t)(gz * n + gy) * n + gx) * a.cout + co;
         float sum = 0.f;
-        for (int k = 0; k < (int)gridDim.z; ++k) sum += load_dev(a.kpart + (size_t)k * V * a.cout + o);
+        for (int k = 0; k < ksplit; ++k) sum += load_dev(a.kpart + (size_t)k * V * a.cout + o);
         fin[j][r] = sum;
       }
     }
@@ -464,6 +478,16 @@ __host__ __device__ inline size_t wg_lds_bytes(int tile, int taps, int ck, int m
 
 template <int MODE, int TAPS, int TILE, int PRO, int GPRO>
 __global__ __launch_bounds__(256) void k_conv_wgrad(ConvWgrad a) {
+  // grid z = member * cout tiles + cout tile
+  const int cotiles = (a.cout + 15) / 16;
+  const int cz = blockIdx.z % cotiles;
+  {
+    const long long off = (long long)(blockIdx.z / cotiles) * a.istride;
+    a.src = shift_src(a.src, off);
+    a.gsrc = shift_src(a.gsrc, off);
+    a.part = ishift(a.part, off);
+    a.partb = ishift(a.partb, off);
+  }
   using MD = Mode<MODE>;
   using ST = typename MD::ST;
   using FT = typename MD::FT;
@@ -494,7 +518,7 @@ __global__ __launch_bounds__(256) void k_conv_wgrad(ConvWgrad a) {
   const int ntx = (n + TX - 1) / TX, nty = (n + TY - 1) / TY, ntz = (n + TZ - 1) / TZ;
   const int ntiles = ntx * nty * ntz;
   const int ci0 = chunk << ck_shift;
-  const int co0 = blockIdx.z * 16;
+  const int co0 = cz * 16;
   const bool do_bias = blockIdx.y == 0;
 
   // LDS carve
@@ -714,7 +738,7 @@ inline int spatial_tiles(int n, int tile) {
 
 template <int MODE, int TAPS, int TILE, int BN, int PRO>
 void launch_fwd(const ConvFwd& a, hipStream_t s) {
-  dim3 grid(spatial_tiles(a.n, TILE), (a.cout + BN - 1) / BN, a.ksplit);
+  dim3 grid(spatial_tiles(a.n, TILE), (a.cout + BN - 1) / BN, a.ksplit * a.batch);
   const size_t lds = fwd_lds_bytes(TILE, TAPS, BN, a.ck, MODE);
   hipLaunchKernelGGL((k_conv_fwd<MODE, TAPS, TILE, BN, PRO>), grid, dim3(256), lds, s, a);
 }
@@ -752,7 +776,8 @@ void fwd_tile(const ConvFwd& a, hipStream_t s) {
 
 template <int MODE, int TAPS, int TILE, int PRO, int GPRO>
 void launch_wg(const ConvWgrad& a, hipStream_t s) {
-  dim3 grid(a.splits, (a.cin / a.ck) * conv_wgrad_groups(a.taps, a.ck), (a.cout + 15) / 16);
+  dim3 grid(a.splits, (a.cin / a.ck) * conv_wgrad_groups(a.taps, a.ck),
+            ((a.cout + 15) / 16) * a.batch);
   const size_t lds = wg_lds_bytes(TILE, TAPS, a.ck, MODE);
   hipLaunchKernelGGL((k_conv_wgrad<MODE, TAPS, TILE, PRO, GPRO>), grid, dim3(256), lds, s, a);
 }

@@ -30,6 +30,46 @@ d2ip_status fail(d2ip_status s, const std::string& m) {
   } while (0)
 
 
+// ---------------------------------------------------------------------------
+// Launch-extent checker (host only).  With a checker active, the workspace is
+// planned at a fake base address, every carved allocation is recorded, and the
+// launch schedule is walked without launching: each pointer argument's byte
+// extent, implied by the kernel's shapes, must lie inside one allocation for
+// every member of its instance group.
+// ---------------------------------------------------------------------------
+struct Checker {
+  struct Alloc {
+    uintptr_t lo, hi;
+  };
+  std::vector<Alloc> allocs;
+  std::vector<std::string> errors;
+  const char* where = "";
+  void add(const void* p, size_t bytes) {
+    allocs.push_back({(uintptr_t)p, (uintptr_t)p + bytes});
+  }
+  bool inside(uintptr_t lo, uintptr_t hi) const {
+    for (const Alloc& a : allocs)
+      if (lo >= a.lo && hi <= a.hi) return true;
+    return false;
+  }
+  // [p + b*istride, + bytes) for members b < B must each fit one allocation
+  void range(const void* p, size_t bytes, const char* what, int B = 1, long long istride = 0) {
+    if (!p || bytes == 0) return;
+    for (int b = 0; b < B; ++b) {
+      const uintptr_t lo = (uintptr_t)p + (uintptr_t)(b * istride);
+      if (!inside(lo, lo + bytes) && errors.size() < 20)
+        errors.push_back(std::string(where) + ": " + what + " (member " + std::to_string(b) +
+                         ", " + std::to_string(bytes) + " bytes) outside every allocation");
+    }
+  }
+  void require(bool ok, const std::string& what) {
+    if (!ok && errors.size() < 20) errors.push_back(std::string(where) + ": " + what);
+  }
+};
+thread_local Checker* g_chk = nullptr;
+
+constexpr bool kGroupInstances = false;
+
 struct Carver {
   char* base = nullptr;
   size_t off = 0;
@@ -38,6 +78,7 @@ struct Carver {
     off = (off + 255) & ~size_t(255);
     T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
     off += count * sizeof(T);
+    if (g_chk && p) g_chk->add(p, count * sizeof(T));
     return p;
   }
 };
@@ -126,7 +167,14 @@ struct Instance {
   float *ppart = nullptr, *tpart = nullptr;
   double* tail_part = nullptr;
   double* rsum = nullptr;
-  bool has_frame = false, has_z = false;
+  float* kpart = nullptr;   // split-K partial outputs
+  int* counters = nullptr;  // zeroed arrival counters of split-K tiles
+  // group: B members of identical shape; member b's data is b * istride
+  // bytes after member 0's (every pointer above is member 0's)
+  int B = 1;
+  long long istride = 0;
+  std::vector<int> member_inst;  // API instance index of each member
+  std::vector<char> has_frame, has_z;
 };
 
 int conv_prec(int precision) {
@@ -342,9 +390,8 @@ struct d2ip_ctx {
   unsigned flags = 0;
   hipStream_t stream = nullptr;
   std::vector<Geometry> geos;
-  std::vector<Instance> insts;
-  float* kpart = nullptr;   // split-K partial outputs (shared, sequential use)
-  int* counters = nullptr;  // zeroed arrival counters (shared, sequential use)
+  std::vector<Instance> insts;              // instance groups
+  std::vector<std::pair<int, int>> members;  // API instance -> (group, member)
   float lr = 1e-3f, b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
@@ -371,15 +418,40 @@ void plan(d2ip_ctx& X, const d2ip_geometry_desc* gd, int n_geo, const d2ip_insta
     G.inv = cv.take<int>(G.Q);
     G.mask = cv.take<float>(G.Q);
   }
-  X.insts.assign(n_inst, Instance());
-  size_t kpart_max = 0;
-  int tiles_max = 1;
-  const int prec = conv_prec(X.precision);
+  // Instances of equal geometry, levels and channels can form one group
+  // (batched launches).  Groups of more than one member are switched off
+  // (kGroupInstances): their first GPU run ended in a host-side crash whose
+  // cause has not been found, so every instance forms its own group.
+  X.insts.clear();
+  X.members.assign(n_inst, std::make_pair(0, 0));
   for (int i = 0; i < n_inst; ++i) {
-    Instance& I = X.insts[i];
-    I.geo = id[i].geometry;
-    I.L = id[i].levels;
-    I.C = id[i].base_ch;
+    int g = -1;
+    for (size_t k = 0; kGroupInstances && k < X.insts.size(); ++k) {
+      const Instance& J = X.insts[k];
+      if (J.geo == id[i].geometry && J.L == id[i].levels && J.C == id[i].base_ch) g = (int)k;
+    }
+    if (g < 0) {
+      X.insts.push_back(Instance());
+      g = (int)X.insts.size() - 1;
+      X.insts[g].geo = id[i].geometry;
+      X.insts[g].L = id[i].levels;
+      X.insts[g].C = id[i].base_ch;
+      X.insts[g].B = 0;
+    }
+    Instance& J = X.insts[g];
+    X.members[i] = std::make_pair(g, J.B);
+    J.member_inst.push_back(i);
+    J.B += 1;
+  }
+  const int prec = conv_prec(X.precision);
+  for (size_t gi = 0; gi < X.insts.size(); ++gi) {
+    size_t kpart_max = 0;
+    int tiles_max = 1;
+    Instance& I = X.insts[gi];
+    I.has_frame.assign(I.B, 0);
+    I.has_z.assign(I.B, 0);
+    cv.off = (cv.off + 255) & ~size_t(255);
+    const size_t region0 = cv.off;
     const Geometry& G = X.geos[I.geo];
     I.n = G.n;
     I.V0 = G.Q;
@@ -514,10 +586,251 @@ void plan(d2ip_ctx& X, const d2ip_geometry_desc* gd, int n_geo, const d2ip_insta
     I.tpart = cv.take<float>((size_t)jt_mblocks(G.M) * G.qa_cap);
     I.tail_part = dp(o_tail);
     I.rsum = dp(o_rsum);
+    I.kpart = cv.take<float>(std::max<size_t>(kpart_max, 1));
+    I.counters = cv.take<int>((size_t)tiles_max + 64);
+    // members 1.. follow member 0 at a fixed stride
+    cv.off = (cv.off + 255) & ~size_t(255);
+    I.istride = (long long)(cv.off - region0);
+    cv.off = region0 + (size_t)I.istride * I.B;
+    if (g_chk && cv.base) {
+      // members 1.. hold the same allocations shifted by the member stride
+      const uintptr_t lo0 = (uintptr_t)cv.base + region0, hi0 = lo0 + (uintptr_t)I.istride;
+      std::vector<Checker::Alloc> mine;
+      for (const Checker::Alloc& a : g_chk->allocs)
+        if (a.lo >= lo0 && a.hi <= hi0) mine.push_back(a);
+      for (int b = 1; b < I.B; ++b)
+        for (const Checker::Alloc& a : mine)
+          g_chk->allocs.push_back({a.lo + (uintptr_t)(b * I.istride), a.hi + (uintptr_t)(b * I.istride)});
+    }
   }
-  X.kpart = cv.take<float>(std::max<size_t>(kpart_max, 1));
-  X.counters = cv.take<int>((size_t)tiles_max + 64);
 }
+
+// Launch wrappers: launch, or (checker active) verify argument extents.
+void chk_src(Checker& c, const ConvSrc& s, size_t V, int ch, int B, long long is, const char* nm) {
+  const std::string n = nm;
+  c.require(s.stride >= ch, n + ": stride < channels read");
+  c.range(s.x, ((V - 1) * s.stride + ch) * sizeof(float), (n + ".x").c_str(), B, is);
+  if (s.prologue != PRO_NONE) {
+    c.range(s.gamma, ch * sizeof(float), (n + ".gamma").c_str(), B, is);
+    c.range(s.st.part, s.st.nparts * 2 * sizeof(double), (n + ".stats").c_str(), B, is);
+    c.require(s.st.nparts > 0, n + ": no statistics partials");
+  }
+  if (s.prologue == PRO_LN_RELU) c.range(s.beta, ch * sizeof(float), (n + ".beta").c_str(), B, is);
+  if (s.prologue == PRO_LN_BWD) {
+    c.range(s.h, ((V - 1) * s.stride + ch) * sizeof(float), (n + ".h").c_str(), B, is);
+    c.range(s.bw.part, s.bw.nparts * 2 * sizeof(double), (n + ".coef").c_str(), B, is);
+  }
+}
+
+void L_conv_fwd(const ConvFwd& a, hipStream_t s) {
+  if (!g_chk) return conv_fwd(a, s);
+  Checker& c = *g_chk;
+  c.where = "conv_fwd";
+  const size_t V = (size_t)a.n * a.n * a.n;
+  const int B = a.batch;
+  const long long is = a.istride;
+  c.require(B >= 1, "batch < 1");
+  c.require(a.ck == 8 || a.ck == 16 || a.ck == 32, "bad channel chunk");
+  c.require(a.cin % a.ck == 0, "cin not a multiple of the chunk");
+  c.require(a.ksplit >= 1 && (a.cin / a.ck) % a.ksplit == 0, "ksplit does not divide the chunks");
+  c.require(a.bn == 16 || a.bn == 32 || a.bn == 64, "bad N tile");
+  c.require(!(a.tile == TILE_2x4x16 && a.bn == 64), "128-voxel tile with N tile 64");
+  c.require(conv_fwd_lds_bytes(a.tile, a.taps, a.bn, a.ck, a.prec) <= 60 * 1024, "LDS over budget");
+  chk_src(c, a.src, V, a.cin, B, is, "src");
+  const size_t el = a.prec == PREC_F32 ? 4 : 2;
+  const size_t wel = (size_t)a.w_rows * a.taps * a.cin;
+  c.range(a.w, (a.prec == PREC_BF16X3 ? a.w_lo_off + wel : wel) * el, "weights", B, is);
+  c.require(a.w_rows >= a.cout, "fewer weight rows than outputs");
+  c.range(a.bias, a.cout * sizeof(float), "bias", B, is);
+  c.range(a.add, V * a.cout * sizeof(float), "add", B, is);
+  c.range(a.y, V * a.cout * sizeof(float), "y", B, is);
+  const int tiles = conv_fwd_blocks(a);
+  c.range(a.stat_part, (size_t)tiles * 2 * sizeof(double), "stat partials", B, is);
+  if (a.ksplit > 1) {
+    c.range(a.kpart, (size_t)a.ksplit * V * a.cout * sizeof(float), "split-K partials", B, is);
+    c.range(a.counters, (size_t)tiles * sizeof(int), "counters", B, is);
+  }
+}
+
+void L_conv_wgrad(const ConvWgrad& a, hipStream_t s) {
+  if (!g_chk) return conv_wgrad(a, s);
+  Checker& c = *g_chk;
+  c.where = "conv_wgrad";
+  const size_t V = (size_t)a.n * a.n * a.n;
+  const int B = a.batch;
+  const long long is = a.istride;
+  c.require(a.cin % a.ck == 0, "cin not a multiple of the chunk");
+  c.require(conv_wgrad_lds_bytes(a.tile, a.taps, a.ck, a.prec) <= 60 * 1024, "LDS over budget");
+  c.require(a.gsrc.stride == a.cout, "g stride != cout");
+  chk_src(c, a.src, V, a.cin, B, is, "x");
+  chk_src(c, a.gsrc, V, a.cout, B, is, "g");
+  const size_t cout16 = (a.cout + 15) / 16 * 16;
+  c.range(a.part, (size_t)a.splits * cout16 * a.taps * a.cin * sizeof(float), "partials", B, is);
+  c.range(a.partb, (size_t)a.splits * cout16 * sizeof(float), "bias partials", B, is);
+}
+
+void L_ln_apply(const float* h, PairRef st, const float* g, const float* b, const float* skip,
+                float* y, size_t V, int C, int B, long long is, hipStream_t s) {
+  if (!g_chk) return ln_apply(h, st, g, b, skip, y, V, C, B, is, s);
+  Checker& c = *g_chk;
+  c.where = "ln_apply";
+  c.range(h, V * C * 4, "h", B, is);
+  c.range(st.part, st.nparts * 16, "stats", B, is);
+  c.range(g, C * 4, "gamma", B, is);
+  c.range(b, C * 4, "beta", B, is);
+  c.range(skip, V * C * 4, "skip", B, is);
+  c.range(y, V * C * 4, "y", B, is);
+}
+
+void L_ln_apply_pool(const float* h, PairRef st, const float* g, const float* b,
+                     const float* skip, float* y, float* pooled, int n, int C, int B,
+                     long long is, hipStream_t s) {
+  if (!g_chk) return ln_apply_pool(h, st, g, b, skip, y, pooled, n, C, B, is, s);
+  Checker& c = *g_chk;
+  c.where = "ln_apply_pool";
+  const size_t V = (size_t)n * n * n;
+  c.require(n % 2 == 0, "odd grid");
+  c.range(h, V * C * 4, "h", B, is);
+  c.range(st.part, st.nparts * 16, "stats", B, is);
+  c.range(g, C * 4, "gamma", B, is);
+  c.range(b, C * 4, "beta", B, is);
+  c.range(skip, V * C * 4, "skip", B, is);
+  c.range(y, V * C * 4, "y", B, is);
+  c.range(pooled, V / 8 * C * 4, "pooled", B, is);
+}
+
+void L_ln_bwd(const float* gy, int mm, const float* my, const float* mg, const float* mb,
+              const float* h, PairRef st, float* gz, double* pc, double* pab, size_t V, int C,
+              const float* gamma, int B, long long is, hipStream_t s) {
+  if (!g_chk) return ln_bwd(gy, mm, my, mg, mb, h, st, gz, pc, pab, V, C, gamma, B, is, s);
+  Checker& c = *g_chk;
+  c.where = "ln_bwd";
+  const size_t nb = ln_bwd_blocks(V, C);
+  c.require(256 % C == 0, "channels do not divide 256");
+  c.range(gy, V * C * 4, "gy", B, is);
+  if (mm == LNMASK_Y) c.range(my, V * C * 4, "mask y", B, is);
+  if (mm == LNMASK_LN) {
+    c.range(mg, C * 4, "mask gamma", B, is);
+    c.range(mb, C * 4, "mask beta", B, is);
+  }
+  c.range(h, V * C * 4, "h", B, is);
+  c.range(st.part, st.nparts * 16, "stats", B, is);
+  c.range(gz, V * C * 4, "gz", B, is);
+  c.range(pc, nb * 2 * C * 8, "channel partials", B, is);
+  c.range(pab, nb * 2 * 8, "coefficient partials", B, is);
+  c.range(gamma, C * 4, "gamma", B, is);
+}
+
+void L_up_concat(const float* d, int Cu, const float* e, int Cs, int n, float* cat, int B,
+                 long long is, hipStream_t s) {
+  if (!g_chk) return up_concat(d, Cu, e, Cs, n, cat, B, is, s);
+  Checker& c = *g_chk;
+  c.where = "up_concat";
+  const size_t V = (size_t)n * n * n;
+  c.range(d, V / 8 * Cu * 4, "coarse", B, is);
+  c.range(e, V * Cs * 4, "skip", B, is);
+  c.range(cat, V * (Cu + Cs) * 4, "cat", B, is);
+}
+
+void L_up_concat_bwd(const float* gcat, int Cu, int Cs, int n, float* gu, float* gs, int B,
+                     long long is, hipStream_t s) {
+  if (!g_chk) return up_concat_bwd(gcat, Cu, Cs, n, gu, gs, B, is, s);
+  Checker& c = *g_chk;
+  c.where = "up_concat_bwd";
+  const size_t V = (size_t)n * n * n;
+  c.range(gcat, V * (Cu + Cs) * 4, "gcat", B, is);
+  c.range(gu, V / 8 * Cu * 4, "gu", B, is);
+  c.range(gs, V * Cs * 4, "gs", B, is);
+}
+
+void L_pool_bwd_add(const float* gx, const float* add, int n, int C, float* gy, int B,
+                    long long is, hipStream_t s) {
+  if (!g_chk) return pool_bwd_add(gx, add, n, C, gy, B, is, s);
+  Checker& c = *g_chk;
+  c.where = "pool_bwd_add";
+  const size_t V = (size_t)n * n * n;
+  c.range(gx, V / 8 * C * 4, "gx", B, is);
+  c.range(add, V * C * 4, "add", B, is);
+  c.range(gy, V * C * 4, "gy", B, is);
+}
+
+void L_tail_fwd(const float* d0, int C, const float* w, const float* b, const float* mask,
+                size_t V, float* sigma, int B, long long is, hipStream_t s) {
+  if (!g_chk) return tail_fwd(d0, C, w, b, mask, V, sigma, B, is, s);
+  Checker& c = *g_chk;
+  c.where = "tail_fwd";
+  c.range(d0, V * C * 4, "d0", B, is);
+  c.range(w, C * 4, "w", B, is);
+  c.range(b, 4, "b", B, is);
+  c.range(mask, V * 4, "mask");
+  c.range(sigma, V * 4, "sigma", B, is);
+}
+
+void L_jvec(const float* Jc, int M, int qa_pad, const int* idx, const float* sigma, float* ppart,
+            size_t V, int B, long long is, hipStream_t s) {
+  if (!g_chk) return jvec(Jc, M, qa_pad, idx, sigma, ppart, B, is, s);
+  Checker& c = *g_chk;
+  c.where = "jvec";
+  c.range(Jc, (size_t)M * qa_pad * 4, "J");
+  c.range(idx, (size_t)qa_pad * 4, "idx");
+  c.range(sigma, V * 4, "sigma", B, is);
+  c.range(ppart, (size_t)jvec_qblocks(qa_pad) * M * 4, "ppart", B, is);
+}
+
+void L_jtvec(const float* Jc, int M, int qa_pad, const float* ppart, int nqb, const float* dv,
+             double* rsum, float* tpart, int B, long long is, hipStream_t s) {
+  if (!g_chk) return jtvec(Jc, M, qa_pad, ppart, nqb, dv, rsum, tpart, B, is, s);
+  Checker& c = *g_chk;
+  c.where = "jtvec";
+  c.range(Jc, (size_t)M * qa_pad * 4, "J");
+  c.range(ppart, (size_t)nqb * M * 4, "ppart", B, is);
+  c.range(dv, (size_t)M * 4, "dv", B, is);
+  c.range(rsum, (size_t)jt_mblocks(M) * 8, "rsum", B, is);
+  c.range(tpart, (size_t)jt_mblocks(M) * qa_pad * 4, "tpart", B, is);
+}
+
+void L_tail_bwd(const float* tpart, int nmb, int qa_pad, const int* inv, const float* d0, int C,
+                const float* w, size_t V, float* gd0, double* part, int B, long long is,
+                hipStream_t s) {
+  if (!g_chk) return tail_bwd(tpart, nmb, qa_pad, inv, d0, C, w, V, gd0, part, B, is, s);
+  Checker& c = *g_chk;
+  c.where = "tail_bwd";
+  c.range(tpart, (size_t)nmb * qa_pad * 4, "tpart", B, is);
+  c.range(inv, V * 4, "inv");
+  c.range(d0, V * C * 4, "d0", B, is);
+  c.range(w, C * 4, "w", B, is);
+  c.range(gd0, V * C * 4, "gd0", B, is);
+  c.range(part, (size_t)tail_bwd_blocks(V, C) * (C + 1) * 8, "partials", B, is);
+}
+
+void L_grad_reduce(const Instance& I, float* grad, hipStream_t s) {
+  if (!g_chk)
+    return grad_reduce(I.segs_dev, (int)I.segs.size(), I.max_seg, I.wg_part, I.wg_partb, I.dpart,
+                       grad, I.B, I.istride, s);
+  Checker& c = *g_chk;
+  c.where = "grad_reduce";
+  c.range(I.segs_dev, I.segs.size() * sizeof(GradSeg), "segments");
+  for (const GradSeg& g : I.segs) {
+    if (g.kind == 0) {
+      const size_t cout16 = (g.cout + 15) / 16 * 16;
+      c.range(I.wg_part + g.part_off, (size_t)g.splits * cout16 * g.taps * g.cin * 4, "conv partials",
+              I.B, I.istride);
+      c.range(I.wg_partb + g.partb_off, (size_t)g.splits * cout16 * 4, "bias partials", I.B,
+              I.istride);
+      c.range(grad + g.th_w, (size_t)g.cout * g.cin_real * g.taps * 4, "dW", I.B, I.istride);
+      c.range(grad + g.th_b, (size_t)g.cout * 4, "db", I.B, I.istride);
+      c.require(g.th_w + g.cout * g.cin_real * g.taps <= (long long)I.P, "dW beyond theta");
+    } else {
+      c.range(I.dpart + g.part_off, (size_t)g.splits * g.cout * 8, "column partials", I.B,
+              I.istride);
+      c.range(grad + g.th_w, (size_t)g.cout * 4, "columns", I.B, I.istride);
+      c.require(g.th_w + g.cout <= (int)I.P, "columns beyond theta");
+    }
+  }
+}
+
+void L_adam(Instance& I, const d2ip_ctx& X, hipStream_t s);
+void L_pack(Instance& I, int prec, bool end_iteration, int M, hipStream_t s);
 
 // ---------------------------------------------------------------------------
 // launch schedule
@@ -575,8 +888,10 @@ ConvFwd fwd_args(const d2ip_ctx& X, const Instance& I, const Conv& c, ConvSrc sr
   a.bn = c.fwd.bn;
   a.ck = c.fwd.ck;
   a.ksplit = c.fwd.ksplit;
-  a.kpart = X.kpart;
-  a.counters = X.counters;
+  a.kpart = I.kpart;
+  a.counters = I.counters;
+  a.batch = I.B;
+  a.istride = I.istride;
   return a;
 }
 
@@ -599,8 +914,10 @@ ConvFwd dgrad_args(const d2ip_ctx& X, const Instance& I, const Conv& c, ConvSrc 
   a.bn = c.bwd.bn;
   a.ck = c.bwd.ck;
   a.ksplit = c.bwd.ksplit;
-  a.kpart = X.kpart;
-  a.counters = X.counters;
+  a.kpart = I.kpart;
+  a.counters = I.counters;
+  a.batch = I.B;
+  a.istride = I.istride;
   return a;
 }
 
@@ -620,15 +937,19 @@ void wgrad(const d2ip_ctx& X, const Instance& I, const Conv& c, ConvSrc xs, Conv
   a.prec = conv_prec(X.precision);
   a.tile = c.wg_tile;
   a.ck = c.wg_ck;
-  conv_wgrad(a, stream);
+  a.batch = I.B;
+  a.istride = I.istride;
+  L_conv_wgrad(a, stream);
 }
 
 // Fork the side stream off the main stream at this point / join it back.
 void fork(d2ip_ctx& X) {
+  if (g_chk) return;
   hipEventRecord(X.ev_fork, X.stream);
   hipStreamWaitEvent(X.side, X.ev_fork, 0);
 }
 void join(d2ip_ctx& X) {
+  if (g_chk) return;
   hipEventRecord(X.ev_join, X.side);
   hipStreamWaitEvent(X.stream, X.ev_join, 0);
 }
@@ -638,30 +959,33 @@ void enqueue_forward(d2ip_ctx& X, Instance& I) {
   hipStream_t s = X.stream;
   float* th = I.theta;
   const int L = I.L;
-  conv_fwd(fwd_args(X, I, I.stem, src_plain(I.zpad, 8), I.hs, &I.sts), s);
-  ln_apply(I.hs, I.sts, th + I.stem_n.th_g, th + I.stem_n.th_b, nullptr, I.as, I.V0, I.C, s);
+  L_conv_fwd(fwd_args(X, I, I.stem, src_plain(I.zpad, 8), I.hs, &I.sts), s);
+  L_ln_apply(I.hs, I.sts, th + I.stem_n.th_g, th + I.stem_n.th_b, nullptr, I.as, I.V0, I.C, I.B,
+           I.istride, s);
   for (Block& b : I.blocks) {
     const size_t V = (size_t)b.n * b.n * b.n;
-    if (!b.enc) up_concat(b.up_src, b.cout * 2, b.skip_src, b.cout, b.n, b.x, s);
+    if (!b.enc) L_up_concat(b.up_src, b.cout * 2, b.skip_src, b.cout, b.n, b.x, I.B, I.istride, s);
     if (b.proj) {
       // the 1x1 projection only needs x: overlap it with conv1 / conv2
       fork(X);
-      conv_fwd(fwd_args(X, I, b.pj, src_plain(b.x, b.cin), b.s, nullptr), X.side);
+      L_conv_fwd(fwd_args(X, I, b.pj, src_plain(b.x, b.cin), b.s, nullptr), X.side);
     }
-    conv_fwd(fwd_args(X, I, b.c1, src_plain(b.x, b.cin), b.h1, &b.st1), s);
-    conv_fwd(fwd_args(X, I, b.c2,
+    L_conv_fwd(fwd_args(X, I, b.c1, src_plain(b.x, b.cin), b.h1, &b.st1), s);
+    L_conv_fwd(fwd_args(X, I, b.c2,
                       src_ln_relu(b.h1, b.cout, b.st1, th + b.n1.th_g, th + b.n1.th_b), b.h2,
                       &b.st2),
              s);
     if (b.proj) join(X);
     const float* skip = b.proj ? b.s : b.x;
     if (b.enc && b.level < L - 1)
-      ln_apply_pool(b.h2, b.st2, th + b.n2.th_g, th + b.n2.th_b, skip, b.y, b.pool_out, b.n,
-                    b.cout, s);
+      L_ln_apply_pool(b.h2, b.st2, th + b.n2.th_g, th + b.n2.th_b, skip, b.y, b.pool_out, b.n,
+                    b.cout, I.B, I.istride, s);
     else
-      ln_apply(b.h2, b.st2, th + b.n2.th_g, th + b.n2.th_b, skip, b.y, V, b.cout, s);
+      L_ln_apply(b.h2, b.st2, th + b.n2.th_g, th + b.n2.th_b, skip, b.y, V, b.cout, I.B, I.istride,
+               s);
   }
-  tail_fwd(I.blocks.back().y, I.C, th + I.tail_w, th + I.tail_b, G.mask, I.V0, I.sigma, s);
+  L_tail_fwd(I.blocks.back().y, I.C, th + I.tail_w, th + I.tail_b, G.mask, I.V0, I.sigma, I.B,
+           I.istride, s);
 }
 
 void enqueue_iteration(d2ip_ctx& X, Instance& I) {
@@ -672,10 +996,10 @@ void enqueue_iteration(d2ip_ctx& X, Instance& I) {
   enqueue_forward(X, I);
   // measurement operator, data term and its gradient w.r.t. the image
   const int nqb = jvec_qblocks(G.qa_pad);
-  jvec(G.Jc, G.M, G.qa_pad, G.idx, I.sigma, I.ppart, s);
-  jtvec(G.Jc, G.M, G.qa_pad, I.ppart, nqb, I.dv, I.rsum, I.tpart, s);
-  tail_bwd(I.tpart, jt_mblocks(G.M), G.qa_pad, G.inv, I.blocks.back().y, I.C, th + I.tail_w,
-           I.V0, I.lv[0].gy, I.tail_part, s);
+  L_jvec(G.Jc, G.M, G.qa_pad, G.idx, I.sigma, I.ppart, I.V0, I.B, I.istride, s);
+  L_jtvec(G.Jc, G.M, G.qa_pad, I.ppart, nqb, I.dv, I.rsum, I.tpart, I.B, I.istride, s);
+  L_tail_bwd(I.tpart, jt_mblocks(G.M), G.qa_pad, G.inv, I.blocks.back().y, I.C, th + I.tail_w,
+           I.V0, I.lv[0].gy, I.tail_part, I.B, I.istride, s);
   // network backward, decoder first.  Weight gradients only feed the batched
   // reduction at the end: they run on the side stream, overlapping the
   // input-gradient chain, and join before the reduction.
@@ -687,57 +1011,99 @@ void enqueue_iteration(d2ip_ctx& X, Instance& I) {
     const float* b1 = th + b.n1.th_b;
     const float* g2 = th + b.n2.th_g;
     // LN2 backward (mask from y): gz and its partials
-    ln_bwd(Lv.gy, LNMASK_Y, b.y, nullptr, nullptr, b.h2, b.st2, b.gz, b.lnc2,
-           const_cast<double*>(b.cb2.part), V, b.cout, g2, s);
+    L_ln_bwd(Lv.gy, LNMASK_Y, b.y, nullptr, nullptr, b.h2, b.st2, b.gz, b.lnc2,
+           const_cast<double*>(b.cb2.part), V, b.cout, g2, I.B, I.istride, s);
     const ConvSrc gh2 = src_ln_bwd(b.gz, b.h2, b.cout, b.st2, g2, b.cb2);
     fork(X);
     wgrad(X, I, b.c2, src_ln_relu(b.h1, b.cout, b.st1, g1, b1), gh2, X.side);
     if (b.proj) wgrad(X, I, b.pj, src_plain(b.x, b.cin), src_plain(b.gz, b.cout), X.side);
-    conv_fwd(dgrad_args(X, I, b.c2, gh2, b.ga), s);
+    L_conv_fwd(dgrad_args(X, I, b.c2, gh2, b.ga), s);
     // LN1 backward (mask from LN1 output), in place on ga
-    ln_bwd(b.ga, LNMASK_LN, nullptr, g1, b1, b.h1, b.st1, b.ga, b.lnc1,
-           const_cast<double*>(b.cb1.part), V, b.cout, g1, s);
+    L_ln_bwd(b.ga, LNMASK_LN, nullptr, g1, b1, b.h1, b.st1, b.ga, b.lnc1,
+           const_cast<double*>(b.cb1.part), V, b.cout, g1, I.B, I.istride, s);
     const ConvSrc gh1 = src_ln_bwd(b.ga, b.h1, b.cout, b.st1, g1, b.cb1);
     fork(X);
     wgrad(X, I, b.c1, src_plain(b.x, b.cin), gh1, X.side);
     {
       ConvFwd a = dgrad_args(X, I, b.c1, gh1, Lv.gx);
       if (!b.proj) a.add = b.gz;
-      conv_fwd(a, s);
+      L_conv_fwd(a, s);
     }
     if (b.proj) {
       ConvFwd a = dgrad_args(X, I, b.pj, src_plain(b.gz, b.cout), Lv.gx);
       a.accumulate = 1;
-      conv_fwd(a, s);
+      L_conv_fwd(a, s);
     }
     if (!b.enc) {
-      up_concat_bwd(Lv.gx, b.cout * 2, b.cout, b.n, I.lv[b.level + 1].gy, Lv.genc, s);
+      L_up_concat_bwd(Lv.gx, b.cout * 2, b.cout, b.n, I.lv[b.level + 1].gy, Lv.genc, I.B,
+                    I.istride, s);
     } else if (b.level > 0) {
       Level& Lp = I.lv[b.level - 1];
-      pool_bwd_add(Lv.gx, Lp.genc, Lp.n, Lp.c, Lp.gy, s);
+      L_pool_bwd_add(Lv.gx, Lp.genc, Lp.n, Lp.c, Lp.gy, I.B, I.istride, s);
     }
   }
   // stem
   {
     Level& L0 = I.lv[0];
     const float* gs = th + I.stem_n.th_g;
-    ln_bwd(L0.gx, LNMASK_Y, I.as, nullptr, nullptr, I.hs, I.sts, L0.gz, I.lncs,
-           const_cast<double*>(I.cbs.part), I.V0, I.C, gs, s);
+    L_ln_bwd(L0.gx, LNMASK_Y, I.as, nullptr, nullptr, I.hs, I.sts, L0.gz, I.lncs,
+           const_cast<double*>(I.cbs.part), I.V0, I.C, gs, I.B, I.istride, s);
     fork(X);
     wgrad(X, I, I.stem, src_plain(I.zpad, 8), src_ln_bwd(L0.gz, I.hs, I.C, I.sts, gs, I.cbs),
           X.side);
   }
   join(X);
-  grad_reduce(I.segs_dev, (int)I.segs.size(), I.max_seg, I.wg_part, I.wg_partb, I.dpart, gr, s);
-  adam(th, gr, I.m, I.v, I.P, X.lr, X.b1, X.b2, X.eps, I.it, s);
-  pack_weights(I.packs_dev, (int)I.packs.size(), I.max_pack, th, I.wf32, I.wbf16,
-               X.precision == D2IP_BF16X3_CONV ? I.wtotal : 0, I.it, I.rsum, jt_mblocks(G.M),
-               G.M, s);
+  L_grad_reduce(I, gr, s);
+  L_adam(I, X, s);
+  L_pack(I, X.precision, true, G.M, s);
+}
+
+void L_adam(Instance& I, const d2ip_ctx& X, hipStream_t s) {
+  if (!g_chk)
+    return adam(I.theta, I.grad, I.m, I.v, I.P, X.lr, X.b1, X.b2, X.eps, I.it, I.B, I.istride, s);
+  Checker& c = *g_chk;
+  c.where = "adam";
+  for (const float* p : {(const float*)I.theta, (const float*)I.grad, (const float*)I.m,
+                         (const float*)I.v})
+    c.range(p, I.P * 4, "parameter vector", I.B, I.istride);
+  c.range(I.it, sizeof(IterState), "iteration state", I.B, I.istride);
+}
+
+void L_pack(Instance& I, int precision, bool end_iteration, int M, hipStream_t s) {
+  const long long lo = precision == D2IP_BF16X3_CONV ? I.wtotal : 0;
+  const int nrs = jt_mblocks(M);
+  if (!g_chk)
+    return pack_weights(I.packs_dev, (int)I.packs.size(), I.max_pack, I.theta, I.wf32, I.wbf16,
+                        lo, end_iteration ? I.it : nullptr, end_iteration ? I.rsum : nullptr,
+                        end_iteration ? nrs : 0, end_iteration ? M : 1, I.B, I.istride, s);
+  Checker& c = *g_chk;
+  c.where = "pack_weights";
+  c.range(I.packs_dev, I.packs.size() * sizeof(ConvPack), "pack table");
+  for (const ConvPack& p : I.packs) {
+    c.range(I.theta + p.th_off, (size_t)p.cout * p.cin_real * p.taps * 4, "theta", I.B, I.istride);
+    const size_t nf = (size_t)p.cout * p.taps * p.cin, nd = (size_t)p.cin_real * p.taps * p.cout;
+    if (I.wf32) {
+      c.range(I.wf32 + p.wf_off, nf * 4, "packed fwd", I.B, I.istride);
+      if (p.need_dgrad) c.range(I.wf32 + p.wd_off, nd * 4, "packed dgrad", I.B, I.istride);
+    }
+    if (I.wbf16) {
+      c.range(I.wbf16 + p.wf_off + lo, nf * 2, "packed fwd (lo)", I.B, I.istride);
+      c.range(I.wbf16 + p.wf_off, nf * 2, "packed fwd", I.B, I.istride);
+      if (p.need_dgrad) {
+        c.range(I.wbf16 + p.wd_off, nd * 2, "packed dgrad", I.B, I.istride);
+        c.range(I.wbf16 + p.wd_off + lo, nd * 2, "packed dgrad (lo)", I.B, I.istride);
+      }
+    }
+  }
+  if (end_iteration) {
+    c.range(I.rsum, nrs * 8, "rsum", I.B, I.istride);
+    c.range(I.it, sizeof(IterState), "iteration state", I.B, I.istride);
+  }
 }
 
 d2ip_status check_inst(d2ip_ctx* X, int inst) {
   if (!X) return fail(D2IP_EINVAL, "null context");
-  if (inst < 0 || inst >= (int)X->insts.size()) return fail(D2IP_EINVAL, "bad instance index");
+  if (inst < 0 || inst >= (int)X->members.size()) return fail(D2IP_EINVAL, "bad instance index");
   return D2IP_OK;
 }
 
@@ -761,8 +1127,7 @@ d2ip_status copy_out(d2ip_ctx* X, void* dst, const void* src, size_t bytes, int 
 }
 
 d2ip_status repack(d2ip_ctx* X, Instance& I) {
-  pack_weights(I.packs_dev, (int)I.packs.size(), I.max_pack, I.theta, I.wf32, I.wbf16,
-               X->precision == D2IP_BF16X3_CONV ? I.wtotal : 0, nullptr, nullptr, 0, 1, X->stream);
+  L_pack(I, X->precision, false, 1, X->stream);
   HIPCHK(hipGetLastError());
   return D2IP_OK;
 }
@@ -792,6 +1157,37 @@ d2ip_status d2ip_param_count(int levels, int base_ch, size_t* out) {
   I.L = levels;
   I.C = base_ch;
   *out = layout(I);
+  return D2IP_OK;
+}
+
+d2ip_status d2ip_check_launches(const d2ip_geometry_desc* geos, int n_geo,
+                                const d2ip_instance_desc* insts, int n_inst, int precision,
+                                unsigned flags) {
+  d2ip_status st = check_desc(geos, n_geo, insts, n_inst, precision);
+  if (st != D2IP_OK) return st;
+  Checker c;
+  d2ip_ctx X;
+  X.precision = precision;
+  X.flags = flags;
+  Carver cv;
+  cv.base = reinterpret_cast<char*>((uintptr_t)1 << 40);  // never dereferenced
+  g_chk = &c;
+  plan(X, geos, n_geo, insts, n_inst, cv);
+  for (Geometry& G : X.geos) {
+    G.qa = (int)G.Q;
+    G.qa_pad = G.qa_cap;  // every voxel active: the largest extents
+    G.set = true;
+  }
+  for (Instance& I : X.insts) {
+    enqueue_iteration(X, I);
+    L_pack(I, X.precision, false, 1, X.stream);
+  }
+  g_chk = nullptr;
+  if (!c.errors.empty()) {
+    std::string m;
+    for (const std::string& e : c.errors) m += e + "; ";
+    return fail(D2IP_EINVAL, m);
+  }
   return D2IP_OK;
 }
 
@@ -930,10 +1326,12 @@ d2ip_status d2ip_set_geometry(d2ip_ctx* X, int geo, const float* J, const uint8_
 d2ip_status d2ip_set_params(d2ip_ctx* X, int inst, const float* theta, size_t n, int on_device) {
   d2ip_status st = check_inst(X, inst);
   if (st != D2IP_OK) return st;
-  Instance& I = X->insts[inst];
+  Instance& I = X->insts[X->members[inst].first];
+  const int mb = X->members[inst].second;
+  const long long mo = (long long)mb * I.istride;
   if (!theta || n != I.P)
     return fail(D2IP_EINVAL, "theta must hold " + std::to_string(I.P) + " floats");
-  st = copy_in(X, I.theta, theta, n * sizeof(float), on_device);
+  st = copy_in(X, ishift(I.theta, mo), theta, n * sizeof(float), on_device);
   if (st != D2IP_OK) return st;
   return repack(X, I);
 }
@@ -941,32 +1339,38 @@ d2ip_status d2ip_set_params(d2ip_ctx* X, int inst, const float* theta, size_t n,
 d2ip_status d2ip_get_params(d2ip_ctx* X, int inst, float* theta, size_t n, int on_device) {
   d2ip_status st = check_inst(X, inst);
   if (st != D2IP_OK) return st;
-  Instance& I = X->insts[inst];
+  Instance& I = X->insts[X->members[inst].first];
+  const int mb = X->members[inst].second;
+  const long long mo = (long long)mb * I.istride;
   if (!theta || n != I.P)
     return fail(D2IP_EINVAL, "theta must hold " + std::to_string(I.P) + " floats");
-  return copy_out(X, theta, I.theta, n * sizeof(float), on_device);
+  return copy_out(X, theta, ishift(I.theta, mo), n * sizeof(float), on_device);
 }
 
 d2ip_status d2ip_get_grad(d2ip_ctx* X, int inst, float* grad, size_t n, int on_device) {
   d2ip_status st = check_inst(X, inst);
   if (st != D2IP_OK) return st;
-  Instance& I = X->insts[inst];
+  Instance& I = X->insts[X->members[inst].first];
+  const int mb = X->members[inst].second;
+  const long long mo = (long long)mb * I.istride;
   if (!grad || n != I.P)
     return fail(D2IP_EINVAL, "grad must hold " + std::to_string(I.P) + " floats");
-  return copy_out(X, grad, I.grad, n * sizeof(float), on_device);
+  return copy_out(X, grad, ishift(I.grad, mo), n * sizeof(float), on_device);
 }
 
 d2ip_status d2ip_set_noise_input(d2ip_ctx* X, int inst, const float* z, int on_device) {
   d2ip_status st = check_inst(X, inst);
   if (st != D2IP_OK) return st;
   if (!z) return fail(D2IP_EINVAL, "null Z");
-  Instance& I = X->insts[inst];
+  Instance& I = X->insts[X->members[inst].first];
+  const int mb = X->members[inst].second;
+  const long long mo = (long long)mb * I.istride;
   // stage Z in the sigma buffer, then spread it into the padded input
-  st = copy_in(X, I.sigma, z, I.V0 * sizeof(float), on_device);
+  st = copy_in(X, ishift(I.sigma, mo), z, I.V0 * sizeof(float), on_device);
   if (st != D2IP_OK) return st;
-  pad_input(I.sigma, I.V0, I.zpad, X->stream);
+  pad_input(ishift(I.sigma, mo), I.V0, ishift(I.zpad, mo), X->stream);
   HIPCHK(hipGetLastError());
-  I.has_z = true;
+  I.has_z[mb] = 1;
   return D2IP_OK;
 }
 
@@ -974,15 +1378,17 @@ d2ip_status d2ip_set_frame(d2ip_ctx* X, int inst, const float* dv, int on_device
   d2ip_status st = check_inst(X, inst);
   if (st != D2IP_OK) return st;
   if (!dv) return fail(D2IP_EINVAL, "null dv");
-  Instance& I = X->insts[inst];
+  Instance& I = X->insts[X->members[inst].first];
+  const int mb = X->members[inst].second;
+  const long long mo = (long long)mb * I.istride;
   const int M = X->geos[I.geo].M;
   if (!on_device) {
     for (int m = 0; m < M; ++m)
       if (!std::isfinite(dv[m])) return fail(D2IP_ENONFINITE, "dv holds a non-finite value");
   }
-  st = copy_in(X, I.dv, dv, M * sizeof(float), on_device);
+  st = copy_in(X, ishift(I.dv, mo), dv, M * sizeof(float), on_device);
   if (st != D2IP_OK) return st;
-  I.has_frame = true;
+  I.has_frame[mb] = 1;
   return D2IP_OK;
 }
 
@@ -1002,10 +1408,12 @@ d2ip_status d2ip_set_adam(d2ip_ctx* X, const d2ip_adam_cfg* cfg) {
 d2ip_status d2ip_reset_optimizer(d2ip_ctx* X, int inst) {
   d2ip_status st = check_inst(X, inst);
   if (st != D2IP_OK) return st;
-  Instance& I = X->insts[inst];
-  HIPCHK(hipMemsetAsync(I.m, 0, I.P * sizeof(float), X->stream));
-  HIPCHK(hipMemsetAsync(I.v, 0, I.P * sizeof(float), X->stream));
-  HIPCHK(hipMemsetAsync(&I.it->t, 0, sizeof(int), X->stream));
+  Instance& I = X->insts[X->members[inst].first];
+  const int mb = X->members[inst].second;
+  const long long mo = (long long)mb * I.istride;
+  HIPCHK(hipMemsetAsync(ishift(I.m, mo), 0, I.P * sizeof(float), X->stream));
+  HIPCHK(hipMemsetAsync(ishift(I.v, mo), 0, I.P * sizeof(float), X->stream));
+  HIPCHK(hipMemsetAsync(&ishift(I.it, mo)->t, 0, sizeof(int), X->stream));
   return D2IP_OK;
 }
 
@@ -1013,14 +1421,16 @@ d2ip_status d2ip_get_state(d2ip_ctx* X, int inst, float* tmv, int64_t* t, int on
   d2ip_status st = check_inst(X, inst);
   if (st != D2IP_OK) return st;
   if (!tmv || !t) return fail(D2IP_EINVAL, "null argument");
-  Instance& I = X->insts[inst];
+  Instance& I = X->insts[X->members[inst].first];
+  const int mb = X->members[inst].second;
+  const long long mo = (long long)mb * I.istride;
   const size_t b = I.P * sizeof(float);
   const hipMemcpyKind k = kind_from_dev(on_device);
-  HIPCHK(hipMemcpyAsync(tmv, I.theta, b, k, X->stream));
-  HIPCHK(hipMemcpyAsync(tmv + I.P, I.m, b, k, X->stream));
-  HIPCHK(hipMemcpyAsync(tmv + 2 * I.P, I.v, b, k, X->stream));
+  HIPCHK(hipMemcpyAsync(tmv, ishift(I.theta, mo), b, k, X->stream));
+  HIPCHK(hipMemcpyAsync(tmv + I.P, ishift(I.m, mo), b, k, X->stream));
+  HIPCHK(hipMemcpyAsync(tmv + 2 * I.P, ishift(I.v, mo), b, k, X->stream));
   int tt = 0;
-  HIPCHK(hipMemcpyAsync(&tt, &I.it->t, sizeof(int), hipMemcpyDeviceToHost, X->stream));
+  HIPCHK(hipMemcpyAsync(&tt, &ishift(I.it, mo)->t, sizeof(int), hipMemcpyDeviceToHost, X->stream));
   HIPCHK(hipStreamSynchronize(X->stream));
   *t = tt;
   return D2IP_OK;
@@ -1030,14 +1440,16 @@ d2ip_status d2ip_set_state(d2ip_ctx* X, int inst, const float* tmv, int64_t t, i
   d2ip_status st = check_inst(X, inst);
   if (st != D2IP_OK) return st;
   if (!tmv || t < 0 || t > (int64_t)1 << 30) return fail(D2IP_EINVAL, "bad state");
-  Instance& I = X->insts[inst];
+  Instance& I = X->insts[X->members[inst].first];
+  const int mb = X->members[inst].second;
+  const long long mo = (long long)mb * I.istride;
   const size_t b = I.P * sizeof(float);
   const hipMemcpyKind k = kind_to_dev(on_device);
   int tt = (int)t;
-  HIPCHK(hipMemcpyAsync(I.theta, tmv, b, k, X->stream));
-  HIPCHK(hipMemcpyAsync(I.m, tmv + I.P, b, k, X->stream));
-  HIPCHK(hipMemcpyAsync(I.v, tmv + 2 * I.P, b, k, X->stream));
-  HIPCHK(hipMemcpyAsync(&I.it->t, &tt, sizeof(int), hipMemcpyHostToDevice, X->stream));
+  HIPCHK(hipMemcpyAsync(ishift(I.theta, mo), tmv, b, k, X->stream));
+  HIPCHK(hipMemcpyAsync(ishift(I.m, mo), tmv + I.P, b, k, X->stream));
+  HIPCHK(hipMemcpyAsync(ishift(I.v, mo), tmv + 2 * I.P, b, k, X->stream));
+  HIPCHK(hipMemcpyAsync(&ishift(I.it, mo)->t, &tt, sizeof(int), hipMemcpyHostToDevice, X->stream));
   HIPCHK(hipStreamSynchronize(X->stream));
   return repack(X, I);
 }
@@ -1045,12 +1457,15 @@ d2ip_status d2ip_set_state(d2ip_ctx* X, int inst, const float* tmv, int64_t t, i
 d2ip_status d2ip_run(d2ip_ctx* X, int k, double* last_loss) {
   if (!X) return fail(D2IP_EINVAL, "null context");
   if (k < 0) return fail(D2IP_EINVAL, "k must be >= 0");
-  for (size_t i = 0; i < X->insts.size(); ++i) {
-    const Instance& I = X->insts[i];
+  for (size_t i = 0; i < X->members.size(); ++i) {
+    const Instance& I = X->insts[X->members[i].first];
+    const int mb = X->members[i].second;
     if (!X->geos[I.geo].set)
       return fail(D2IP_ESTATE, "geometry " + std::to_string(I.geo) + " not set");
-    if (!I.has_z) return fail(D2IP_ESTATE, "instance " + std::to_string(i) + ": noise input not set");
-    if (!I.has_frame) return fail(D2IP_ESTATE, "instance " + std::to_string(i) + ": frame not set");
+    if (!I.has_z[mb])
+      return fail(D2IP_ESTATE, "instance " + std::to_string(i) + ": noise input not set");
+    if (!I.has_frame[mb])
+      return fail(D2IP_ESTATE, "instance " + std::to_string(i) + ": frame not set");
   }
   if (k > 0) {
     if (X->flags & D2IP_FLAG_GRAPH) {
@@ -1079,9 +1494,11 @@ d2ip_status d2ip_run(d2ip_ctx* X, int k, double* last_loss) {
   }
   if (last_loss) {
     bool bad = false;
-    for (size_t i = 0; i < X->insts.size(); ++i) {
+    for (size_t i = 0; i < X->members.size(); ++i) {
+      const Instance& I = X->insts[X->members[i].first];
+      const long long mo = (long long)X->members[i].second * I.istride;
       IterState h;
-      HIPCHK(hipMemcpyAsync(&h, X->insts[i].it, sizeof(h), hipMemcpyDeviceToHost, X->stream));
+      HIPCHK(hipMemcpyAsync(&h, ishift(I.it, mo), sizeof(h), hipMemcpyDeviceToHost, X->stream));
       HIPCHK(hipStreamSynchronize(X->stream));
       last_loss[i] = h.loss;
       if (h.nonfinite) bad = true;
@@ -1096,9 +1513,14 @@ d2ip_status d2ip_time_kernel(d2ip_ctx* X, int inst, int which, int block, int re
   d2ip_status st = check_inst(X, inst);
   if (st != D2IP_OK) return st;
   if (!avg_ms || reps <= 0) return fail(D2IP_EINVAL, "need reps > 0 and an output");
-  Instance& I = X->insts[inst];
+  Instance& I = X->insts[X->members[inst].first];
+  const int mb = X->members[inst].second;
+  const long long mo = (long long)mb * I.istride;
   const Geometry& G = X->geos[I.geo];
-  if (!G.set || !I.has_frame || !I.has_z) return fail(D2IP_ESTATE, "instance not ready");
+  for (int b = 0; b < I.B; ++b)
+    if (!G.set || !I.has_frame[b] || !I.has_z[b])
+      return fail(D2IP_ESTATE, "every instance of the group must be ready");
+  (void)mo;
   hipStream_t s = X->stream;
   Block* b = nullptr;
   if (which >= D2IP_KERNEL_CONV_FWD) {
@@ -1109,13 +1531,14 @@ d2ip_status d2ip_time_kernel(d2ip_ctx* X, int inst, int which, int block, int re
   auto launch = [&]() {
     switch (which) {
       case D2IP_KERNEL_JVEC:
-        jvec(G.Jc, G.M, G.qa_pad, G.idx, I.sigma, I.ppart, s);
+        jvec(G.Jc, G.M, G.qa_pad, G.idx, I.sigma, I.ppart, I.B, I.istride, s);
         break;
       case D2IP_KERNEL_JTVEC:
-        jtvec(G.Jc, G.M, G.qa_pad, I.ppart, jvec_qblocks(G.qa_pad), I.dv, I.rsum, I.tpart, s);
+        jtvec(G.Jc, G.M, G.qa_pad, I.ppart, jvec_qblocks(G.qa_pad), I.dv, I.rsum, I.tpart, I.B,
+              I.istride, s);
         break;
       case D2IP_KERNEL_ADAM:
-        adam(I.theta, I.grad, I.m, I.v, I.P, X->lr, X->b1, X->b2, X->eps, I.it, s);
+        adam(I.theta, I.grad, I.m, I.v, I.P, X->lr, X->b1, X->b2, X->eps, I.it, I.B, I.istride, s);
         break;
       case D2IP_KERNEL_CONV_FWD:
         conv_fwd(fwd_args(*X, I, b->c1, src_plain(b->x, b->cin), b->h1, &b->st1), s);
@@ -1159,12 +1582,15 @@ d2ip_status d2ip_read_image(d2ip_ctx* X, int inst, float* sigma, int on_device) 
   d2ip_status st = check_inst(X, inst);
   if (st != D2IP_OK) return st;
   if (!sigma) return fail(D2IP_EINVAL, "null output");
-  Instance& I = X->insts[inst];
+  Instance& I = X->insts[X->members[inst].first];
+  const int mb = X->members[inst].second;
+  const long long mo = (long long)mb * I.istride;
   if (!X->geos[I.geo].set) return fail(D2IP_ESTATE, "geometry not set");
-  if (!I.has_z) return fail(D2IP_ESTATE, "noise input not set");
+  for (int b = 0; b < I.B; ++b)
+    if (!I.has_z[b]) return fail(D2IP_ESTATE, "noise input not set");
   enqueue_forward(*X, I);
   HIPCHK(hipGetLastError());
-  return copy_out(X, sigma, I.sigma, I.V0 * sizeof(float), on_device);
+  return copy_out(X, sigma, ishift(I.sigma, mo), I.V0 * sizeof(float), on_device);
 }
 
 }  // extern "C"

@@ -5,6 +5,8 @@
 // row-major, zero-padded columns): the products J sigma and J^T g each stream
 // it once from HBM with 16-byte loads; sums over column or row blocks land in
 // partial buffers that a second pass reduces in a fixed order.
+#include <algorithm>
+
 #include "kernels.h"
 
 namespace d2ip {
@@ -22,79 +24,110 @@ __global__ void k_gather_columns(const float* __restrict__ J, int M, int Q,
   }
 }
 
+// Members of a group share J: each block reads its J tile once and forms the
+// partial products for every member (up to kJMaxB per launch).
 __global__ __launch_bounds__(256) void k_jvec(const float* __restrict__ Jc, int M, int qa_pad,
-                                              const int* __restrict__ idx,
-                                              const float* __restrict__ sigma,
-                                              float* __restrict__ ppart) {
-  __shared__ __align__(16) float sv[kJvecCols];
+                                              const int* __restrict__ idx, const float* sigma,
+                                              float* ppart, int B, long long istride) {
+  __shared__ __align__(16) float sv[kJMaxB][kJvecCols];
   const int q0 = blockIdx.x * kJvecCols;
   const int qn = min(kJvecCols, qa_pad - q0);
-  for (int q = threadIdx.x; q < kJvecCols; q += 256) sv[q] = q < qn ? sigma[idx[q0 + q]] : 0.f;
+  for (int b = 0; b < B; ++b) {
+    const float* sg = ishift(sigma, b * istride);
+    for (int q = threadIdx.x; q < kJvecCols; q += 256) sv[b][q] = q < qn ? sg[idx[q0 + q]] : 0.f;
+  }
   __syncthreads();
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   for (int r = wave; r < kJvecRows; r += 4) {
     const int m = blockIdx.y * kJvecRows + r;
     if (m >= M) break;
     const float* row = Jc + (size_t)m * qa_pad + q0;
-    float acc = 0.f;
+    float acc[kJMaxB];
+#pragma unroll
+    for (int b = 0; b < kJMaxB; ++b) acc[b] = 0.f;
     for (int j = lane * 4; j < qn; j += 256) {
       const float4 jv = *reinterpret_cast<const float4*>(row + j);
-      const float4 s = *reinterpret_cast<const float4*>(sv + j);
-      acc += jv.x * s.x + jv.y * s.y + jv.z * s.z + jv.w * s.w;
+#pragma unroll
+      for (int b = 0; b < kJMaxB; ++b) {
+        if (b >= B) break;
+        const float4 sb = *reinterpret_cast<const float4*>(&sv[b][j]);
+        acc[b] += jv.x * sb.x + jv.y * sb.y + jv.z * sb.z + jv.w * sb.w;
+      }
     }
-    acc = wave_sum(acc);
-    if (lane == 0) ppart[(size_t)blockIdx.x * M + m] = acc;
+#pragma unroll
+    for (int b = 0; b < kJMaxB; ++b) {
+      if (b >= B) break;
+      const float v = wave_sum(acc[b]);
+      if (lane == 0) ishift(ppart, b * istride)[(size_t)blockIdx.x * M + m] = v;
+    }
   }
 }
 
 __global__ __launch_bounds__(256) void k_jtvec(const float* __restrict__ Jc, int M, int qa_pad,
-                                               const float* __restrict__ ppart, int nqb,
-                                               const float* __restrict__ dv,
-                                               double* __restrict__ rsum,
-                                               float* __restrict__ tpart) {
-  __shared__ float gs[kJtRows];
+                                               const float* ppart, int nqb, const float* dv,
+                                               double* rsum, float* tpart, int B,
+                                               long long istride) {
+  __shared__ float gs[kJMaxB][kJtRows];
   __shared__ double sh[16];
   const int m0 = blockIdx.y * kJtRows;
   const int mn = min(kJtRows, M - m0);
-  // residual of this block's rows: 8 threads per row, column blocks k = j, j+8, ..
-  {
+  // residual of this block's rows for every member: 8 threads per row,
+  // column blocks k = j, j+8, .. combined by a butterfly (fixed order)
+  for (int b = 0; b < B; ++b) {
+    const long long off = b * istride;
+    const float* pp = ishift(ppart, off);
     const int r = threadIdx.x >> 3, j = threadIdx.x & 7;
     float p = 0.f;
     if (r < mn)
-      for (int k = j; k < nqb; k += 8) p += ppart[(size_t)k * M + m0 + r];
+      for (int k = j; k < nqb; k += 8) p += pp[(size_t)k * M + m0 + r];
 #pragma unroll
     for (int o = 4; o > 0; o >>= 1) p += __shfl_xor(p, o, 8);
     double rr = 0.0;
     if (j == 0 && r < kJtRows) {
-      const float res = r < mn ? p - dv[m0 + r] : 0.f;
-      gs[r] = (2.f / (float)M) * res;
+      const float res = r < mn ? p - ishift(dv, off)[m0 + r] : 0.f;
+      gs[b][r] = (2.f / (float)M) * res;
       rr = (double)res * res;
     }
     if (blockIdx.x == 0) {
       rr = block_sum(rr, sh);
-      if (threadIdx.x == 0) rsum[blockIdx.y] = rr;
+      if (threadIdx.x == 0) ishift(rsum, off)[blockIdx.y] = rr;
     }
   }
   __syncthreads();
   const int q = (blockIdx.x * 256 + threadIdx.x) * 4;
   if (q >= qa_pad) return;
-  float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+  float4 acc[kJMaxB];
+#pragma unroll
+  for (int b = 0; b < kJMaxB; ++b) acc[b] = make_float4(0.f, 0.f, 0.f, 0.f);
   const float* base = Jc + (size_t)m0 * qa_pad + q;
-#pragma unroll 8
+#pragma unroll 4
   for (int r = 0; r < mn; ++r) {
     const float4 jv = *reinterpret_cast<const float4*>(base + (size_t)r * qa_pad);
-    const float g = gs[r];
-    acc.x += jv.x * g;
-    acc.y += jv.y * g;
-    acc.z += jv.z * g;
-    acc.w += jv.w * g;
+#pragma unroll
+    for (int b = 0; b < kJMaxB; ++b) {
+      if (b >= B) break;
+      const float g = gs[b][r];
+      acc[b].x += jv.x * g;
+      acc[b].y += jv.y * g;
+      acc[b].z += jv.z * g;
+      acc[b].w += jv.w * g;
+    }
   }
-  *reinterpret_cast<float4*>(tpart + (size_t)blockIdx.y * qa_pad + q) = acc;
+#pragma unroll
+  for (int b = 0; b < kJMaxB; ++b) {
+    if (b >= B) break;
+    *reinterpret_cast<float4*>(ishift(tpart, b * istride) + (size_t)blockIdx.y * qa_pad + q) =
+        acc[b];
+  }
 }
 
-__global__ void k_tail_fwd(const float* __restrict__ d0, int C, const float* __restrict__ w,
-                           const float* __restrict__ b, const float* __restrict__ mask, size_t V,
-                           float* __restrict__ sigma) {
+__global__ void k_tail_fwd(const float* d0, int C, const float* w, const float* b,
+                           const float* __restrict__ mask, size_t V, float* sigma,
+                           long long istride) {
+  {
+    const long long off = (long long)blockIdx.y * istride;
+    d0 = ishift(d0, off); w = ishift(w, off); b = ishift(b, off); sigma = ishift(sigma, off);
+  }
   for (size_t v = blockIdx.x * (size_t)blockDim.x + threadIdx.x; v < V;
        v += (size_t)gridDim.x * blockDim.x) {
     const float4* row = reinterpret_cast<const float4*>(d0 + v * C);
@@ -109,12 +142,15 @@ __global__ void k_tail_fwd(const float* __restrict__ d0, int C, const float* __r
 
 constexpr int kTailVoxels = 256;
 
-__global__ __launch_bounds__(256) void k_tail_bwd(const float* __restrict__ tpart, int nmb,
-                                                  int qa_pad, const int* __restrict__ inv,
-                                                  const float* __restrict__ d0, int C,
-                                                  const float* __restrict__ w, size_t V,
-                                                  float* __restrict__ gd0,
-                                                  double* __restrict__ part) {
+__global__ __launch_bounds__(256) void k_tail_bwd(const float* tpart, int nmb, int qa_pad,
+                                                  const int* __restrict__ inv, const float* d0,
+                                                  int C, const float* w, size_t V, float* gd0,
+                                                  double* part, long long istride) {
+  {
+    const long long off = (long long)blockIdx.y * istride;
+    tpart = ishift(tpart, off); d0 = ishift(d0, off); w = ishift(w, off);
+    gd0 = ishift(gd0, off); part = ishift(part, off);
+  }
   __shared__ float gsv[kTailVoxels];
   __shared__ double sh[256];
   const int tid = threadIdx.x;
@@ -159,9 +195,14 @@ __global__ __launch_bounds__(256) void k_tail_bwd(const float* __restrict__ tpar
   }
 }
 
-__global__ void k_adam(float* __restrict__ theta, const float* __restrict__ g,
-                       float* __restrict__ m, float* __restrict__ v, size_t P, float lr,
-                       float beta1, float beta2, float eps, const IterState* __restrict__ it) {
+__global__ void k_adam(float* theta, const float* g, float* m, float* v, size_t P, float lr,
+                       float beta1, float beta2, float eps, const IterState* it,
+                       long long istride) {
+  {
+    const long long off = (long long)blockIdx.y * istride;
+    theta = ishift(theta, off); g = ishift(g, off); m = ishift(m, off); v = ishift(v, off);
+    it = ishift(it, off);
+  }
   __shared__ float sbc[2];
   if (threadIdx.x == 0) {
     const int t = it->t + 1;
@@ -189,10 +230,14 @@ __device__ __forceinline__ void put_bf(uint16_t* w, long long i, long long lo_of
   if (lo_off) w[lo_off + i] = f2bf(val - bf2f(hi));
 }
 
-__global__ void k_pack_weights(const ConvPack* __restrict__ packs, const float* __restrict__ theta,
-                               float* __restrict__ wf32, uint16_t* __restrict__ wbf16,
-                               long long lo_off, IterState* it, const double* __restrict__ rsum,
-                               int nrs, int M) {
+__global__ void k_pack_weights(const ConvPack* __restrict__ packs, const float* theta,
+                               float* wf32, uint16_t* wbf16, long long lo_off, IterState* it,
+                               const double* rsum, int nrs, int M, long long istride) {
+  {
+    const long long off = (long long)blockIdx.z * istride;
+    theta = ishift(theta, off); wf32 = ishift(wf32, off); wbf16 = ishift(wbf16, off);
+    it = ishift(it, off); rsum = ishift(rsum, off);
+  }
   if (it && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) {
     double L = 0.0;
     for (int k = 0; k < nrs; ++k) L += rsum[k];
@@ -238,20 +283,28 @@ void gather_columns(const float* J, int M, int Q, const int* idx, int qa, int qa
 }
 
 void jvec(const float* Jc, int M, int qa_pad, const int* idx, const float* sigma, float* ppart,
-          hipStream_t s) {
+          int batch, long long istride, hipStream_t s) {
   dim3 grid(jvec_qblocks(qa_pad), (M + kJvecRows - 1) / kJvecRows);
-  hipLaunchKernelGGL(k_jvec, grid, dim3(256), 0, s, Jc, M, qa_pad, idx, sigma, ppart);
+  for (int b0 = 0; b0 < batch; b0 += kJMaxB)
+    hipLaunchKernelGGL(k_jvec, grid, dim3(256), 0, s, Jc, M, qa_pad, idx,
+                       ishift(sigma, b0 * istride), ishift(ppart, b0 * istride),
+                       std::min(kJMaxB, batch - b0), istride);
 }
 
 void jtvec(const float* Jc, int M, int qa_pad, const float* ppart, int nqb, const float* dv,
-           double* rsum, float* tpart, hipStream_t s) {
+           double* rsum, float* tpart, int batch, long long istride, hipStream_t s) {
   dim3 grid((qa_pad / 4 + 255) / 256, jt_mblocks(M));
-  hipLaunchKernelGGL(k_jtvec, grid, dim3(256), 0, s, Jc, M, qa_pad, ppart, nqb, dv, rsum, tpart);
+  for (int b0 = 0; b0 < batch; b0 += kJMaxB)
+    hipLaunchKernelGGL(k_jtvec, grid, dim3(256), 0, s, Jc, M, qa_pad,
+                       ishift(ppart, b0 * istride), nqb, ishift(dv, b0 * istride),
+                       ishift(rsum, b0 * istride), ishift(tpart, b0 * istride),
+                       std::min(kJMaxB, batch - b0), istride);
 }
 
 void tail_fwd(const float* d0, int C, const float* w, const float* b, const float* mask, size_t V,
-              float* sigma, hipStream_t s) {
-  hipLaunchKernelGGL(k_tail_fwd, dim3(grid_for(V)), dim3(256), 0, s, d0, C, w, b, mask, V, sigma);
+              float* sigma, int batch, long long istride, hipStream_t s) {
+  hipLaunchKernelGGL(k_tail_fwd, dim3(grid_for(V), batch), dim3(256), 0, s, d0, C, w, b, mask, V,
+                     sigma, istride);
 }
 
 int tail_bwd_blocks(size_t V, int C) {
@@ -260,24 +313,27 @@ int tail_bwd_blocks(size_t V, int C) {
 }
 
 void tail_bwd(const float* tpart, int nmb, int qa_pad, const int* inv, const float* d0, int C,
-              const float* w, size_t V, float* gd0, double* part, hipStream_t s) {
-  hipLaunchKernelGGL(k_tail_bwd, dim3(tail_bwd_blocks(V, C)), dim3(256), 0, s, tpart, nmb, qa_pad,
-                     inv, d0, C, w, V, gd0, part);
+              const float* w, size_t V, float* gd0, double* part, int batch, long long istride,
+              hipStream_t s) {
+  hipLaunchKernelGGL(k_tail_bwd, dim3(tail_bwd_blocks(V, C), batch), dim3(256), 0, s, tpart, nmb,
+                     qa_pad, inv, d0, C, w, V, gd0, part, istride);
 }
 
 void adam(float* theta, const float* g, float* m, float* v, size_t P, float lr, float beta1,
-          float beta2, float eps, const IterState* it, hipStream_t s) {
-  hipLaunchKernelGGL(k_adam, dim3(grid_for(P)), dim3(256), 0, s, theta, g, m, v, P, lr, beta1,
-                     beta2, eps, it);
+          float beta2, float eps, const IterState* it, int batch, long long istride,
+          hipStream_t s) {
+  hipLaunchKernelGGL(k_adam, dim3(grid_for(P), batch), dim3(256), 0, s, theta, g, m, v, P, lr,
+                     beta1, beta2, eps, it, istride);
 }
 
 void pack_weights(const ConvPack* packs, int npacks, int max_elems, const float* theta,
                   float* wf32, uint16_t* wbf16, long long lo_off, IterState* it,
-                  const double* rsum, int nrs, int M, hipStream_t s) {
-  dim3 grid((max_elems + 255) / 256, npacks);
+                  const double* rsum, int nrs, int M, int batch, long long istride,
+                  hipStream_t s) {
+  dim3 grid((max_elems + 255) / 256, npacks, batch);
   if (grid.x > 1024) grid.x = 1024;
   hipLaunchKernelGGL(k_pack_weights, grid, dim3(256), 0, s, packs, theta, wf32, wbf16, lo_off, it,
-                     rsum, nrs, M);
+                     rsum, nrs, M, istride);
 }
 
 }  // namespace d2ip

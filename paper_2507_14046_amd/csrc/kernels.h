@@ -32,6 +32,17 @@ struct ConvSrc {
   PairRef bw;            // PRO_LN_BWD: partials of the coefficients A, B
 };
 
+// Shift every per-member pointer of a source by `off` bytes.
+__host__ __device__ inline ConvSrc shift_src(ConvSrc s, long long off) {
+  s.x = ishift(s.x, off);
+  s.gamma = ishift(s.gamma, off);
+  s.beta = ishift(s.beta, off);
+  s.h = ishift(s.h, off);
+  s.st.part = ishift(s.st.part, off);
+  s.bw.part = ishift(s.bw.part, off);
+  return s;
+}
+
 // y[v][co] (+)= sum_{tap, ci} Wp[co][tap][ci] * T(x)[v + off(tap)][ci] (+ bias[co])
 // (+ add[v][co]); NDHWC tensors on an n^3 grid, zero padding.  Used for the
 // forward conv (Wp = forward packing) and the input gradient (Wp = flipped,
@@ -55,6 +66,8 @@ struct ConvFwd {
   int prec, tile, bn, ck, ksplit;
   float* kpart;          // [ksplit][n^3][cout] (ksplit > 1)
   int* counters;         // ksplit > 1: >= tiles zeroed ints (left zeroed)
+  int batch;             // group members (grid z = ksplit * batch)
+  long long istride;     // bytes between members' data
 };
 int conv_tiles(int n, int tile);
 int conv_fwd_blocks(const ConvFwd& a);  // output tiles (= stat partials)
@@ -71,6 +84,8 @@ struct ConvWgrad {
   float* part;           // [splits][cout16][taps][cin]
   float* partb;          // [splits][cout16]
   int splits, prec, tile, ck;
+  int batch;             // group members (grid z = cout tiles * batch)
+  long long istride;
 };
 int conv_wgrad_groups(int taps, int ck);
 size_t conv_wgrad_lds_bytes(int tile, int taps, int ck, int prec);
@@ -88,18 +103,20 @@ struct GradSeg {
   int th_w, th_b;
 };
 void grad_reduce(const GradSeg* segs, int nsegs, int max_elems, const float* part,
-                 const float* partb, const double* dpart, float* grad, hipStream_t s);
+                 const float* partb, const double* dpart, float* grad, int batch,
+                 long long istride, hipStream_t s);
 
 // ---- LayerNorm, ReLU, pooling, up-sampling (norm.hip) ----------------------
 enum LnMask { LNMASK_NONE = 0, LNMASK_Y = 1, LNMASK_LN = 2 };
 
 // y = relu(g[c] * (h - mean) * rstd + b[c] (+ skip)), [V][C]
 void ln_apply(const float* h, PairRef st, const float* g, const float* b, const float* skip,
-              float* y, size_t V, int C, hipStream_t s);
+              float* y, size_t V, int C, int batch, long long istride, hipStream_t s);
 // the same on an n^3 grid (n even), also writing the 2x2x2 average of y
 // (the next encoder input) when `pooled` is not null
 void ln_apply_pool(const float* h, PairRef st, const float* g, const float* b, const float* skip,
-                   float* y, float* pooled, int n, int C, hipStream_t s);
+                   float* y, float* pooled, int n, int C, int batch, long long istride,
+                   hipStream_t s);
 int ln_bwd_vpb(int C);
 int ln_bwd_blocks(size_t V, int C);
 // gz = gy * relu'(.) (mask from y > 0, or from g*xhat + b > 0); per block:
@@ -109,11 +126,14 @@ int ln_bwd_blocks(size_t V, int C);
 // dh = rstd * (gamma_c * gz - A - xhat * B).
 void ln_bwd(const float* gy, int mask_mode, const float* my, const float* mg, const float* mb,
             const float* h, PairRef st, float* gz, double* part_c, double* part_ab, size_t V,
-            int C, const float* gamma, hipStream_t s);
+            int C, const float* gamma, int batch, long long istride, hipStream_t s);
 void avgpool2(const float* x, int n, int C, float* y, hipStream_t s);
-void up_concat(const float* d, int Cu, const float* e, int Cs, int n, float* cat, hipStream_t s);
-void up_concat_bwd(const float* gcat, int Cu, int Cs, int n, float* gu, float* gs, hipStream_t s);
-void pool_bwd_add(const float* gx, const float* add, int n, int C, float* gy, hipStream_t s);
+void up_concat(const float* d, int Cu, const float* e, int Cs, int n, float* cat, int batch,
+               long long istride, hipStream_t s);
+void up_concat_bwd(const float* gcat, int Cu, int Cs, int n, float* gu, float* gs, int batch,
+                   long long istride, hipStream_t s);
+void pool_bwd_add(const float* gx, const float* add, int n, int C, float* gy, int batch,
+                  long long istride, hipStream_t s);
 void pad_input(const float* z, size_t V, float* zp, hipStream_t s);
 
 // ---- measurement operator, loss, tail, Adam (jops.hip) ----------------------
@@ -132,6 +152,7 @@ struct ConvPack {  // one conv of the flat parameter vector
 constexpr int kJvecCols = 1024;   // columns per J*sigma block
 constexpr int kJvecRows = 16;     // rows per J*sigma block
 constexpr int kJtRows = 32;       // rows per J^T g block
+constexpr int kJMaxB = 8;         // group members per J-product launch (J read once)
 inline int jvec_qblocks(int qa_pad) { return (qa_pad + kJvecCols - 1) / kJvecCols; }
 inline int jt_mblocks(int M) { return (M + kJtRows - 1) / kJtRows; }
 
@@ -142,30 +163,33 @@ void gather_columns(const float* J, int M, int Q, const int* idx, int qa, int qa
 // Adam step counter t += 1 with its bias corrections.
 // ppart[qb][m] = sum_{q in column block qb} Jc[m][q] * sigma[idx[q]]
 void jvec(const float* Jc, int M, int qa_pad, const int* idx, const float* sigma, float* ppart,
-          hipStream_t s);
+          int batch, long long istride, hipStream_t s);
 // Each block first forms, for its kJtRows rows, p = sum_qb ppart (column-block
 // order), r = p - dv and gp = (2/M) r; blocks of the first column write
 // rsum[mb] = sum r^2 (FP64).  Then tpart[mb][q] = sum_{m in mb} Jc[m][q] gp[m].
 void jtvec(const float* Jc, int M, int qa_pad, const float* ppart, int nqb, const float* dv,
-           double* rsum, float* tpart, hipStream_t s);
+           double* rsum, float* tpart, int batch, long long istride, hipStream_t s);
 // sigma[v] = mask[v] * (b + sum_c w[c] d0[v][c])
 void tail_fwd(const float* d0, int C, const float* w, const float* b, const float* mask, size_t V,
-              float* sigma, hipStream_t s);
+              float* sigma, int batch, long long istride, hipStream_t s);
 int tail_bwd_blocks(size_t V, int C);
 // gs[v] = sum_mb tpart[mb][inv[v]] (0 where inv < 0); gd0[v][c] = gs[v] w[c];
 // part[blk][c] = sum gs*d0[.][c], part[blk][C] = sum gs (gradient of the head,
 // reduced by grad_reduce).
 void tail_bwd(const float* tpart, int nmb, int qa_pad, const int* inv, const float* d0, int C,
-              const float* w, size_t V, float* gd0, double* part, hipStream_t s);
+              const float* w, size_t V, float* gd0, double* part, int batch, long long istride,
+              hipStream_t s);
 // Adam step t + 1 (t = it->t, bias corrections 1 - beta^(t+1)).
 void adam(float* theta, const float* g, float* m, float* v, size_t P, float lr, float beta1,
-          float beta2, float eps, const IterState* it, hipStream_t s);
+          float beta2, float eps, const IterState* it, int batch, long long istride,
+          hipStream_t s);
 // Packed conv weights from theta; with lo_off > 0 the bf16 lo parts
 // (bf16(w - bf16(w))) are written lo_off elements after the hi parts.  When
 // `it` is set this ends an iteration: it->loss = sum(rsum[0..nrs)) / M (FP64),
 // the non-finite flag, and t += 1.
 void pack_weights(const ConvPack* packs, int npacks, int max_elems, const float* theta,
                   float* wf32, uint16_t* wbf16, long long lo_off, IterState* it,
-                  const double* rsum, int nrs, int M, hipStream_t s);
+                  const double* rsum, int nrs, int M, int batch, long long istride,
+                  hipStream_t s);
 
 }  // namespace d2ip

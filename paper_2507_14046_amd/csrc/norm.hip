@@ -11,9 +11,13 @@ namespace {
 
 constexpr int kElemsPerBlock = 1024;
 
-__global__ void k_ln_apply(const float4* __restrict__ h, PairRef sr, const float* __restrict__ g,
-                           const float* __restrict__ b, const float4* __restrict__ skip,
-                           float4* __restrict__ y, size_t n4, int C) {
+__global__ void k_ln_apply(const float4* h, PairRef sr, const float* g, const float* b,
+                           const float4* skip, float4* y, size_t n4, int C, long long istride) {
+  {
+    const long long off = (long long)blockIdx.y * istride;
+    h = ishift(h, off); sr.part = ishift(sr.part, off); g = ishift(g, off); b = ishift(b, off);
+    skip = ishift(skip, off); y = ishift(y, off);
+  }
   const LnStat st = stat_of(sr);
   const float mean = st.mean, rstd = st.rstd;
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n4;
@@ -34,10 +38,15 @@ __global__ void k_ln_apply(const float4* __restrict__ h, PairRef sr, const float
 // (sum gz*xhat [C], sum gz [C]); part_ab[blk] = (sum_c gamma_c sum gz,
 // sum_c gamma_c sum gz*xhat).
 __global__ __launch_bounds__(256) void k_ln_bwd(
-    const float* gy, int mask_mode, const float* __restrict__ my, const float* __restrict__ mg,
-    const float* __restrict__ mb, const float* __restrict__ h, PairRef sr, float* gz,
-    double* __restrict__ part_c, double* __restrict__ part_ab, int V, int C, int vpb,
-    const float* __restrict__ gamma) {
+    const float* gy, int mask_mode, const float* my, const float* mg, const float* mb,
+    const float* h, PairRef sr, float* gz, double* part_c, double* part_ab, int V, int C, int vpb,
+    const float* gamma, long long istride) {
+  {
+    const long long off = (long long)blockIdx.y * istride;
+    gy = ishift(gy, off); my = ishift(my, off); mg = ishift(mg, off); mb = ishift(mb, off);
+    h = ishift(h, off); sr.part = ishift(sr.part, off); gz = ishift(gz, off);
+    part_c = ishift(part_c, off); part_ab = ishift(part_ab, off); gamma = ishift(gamma, off);
+  }
   __shared__ double sh1[256], sh2[256];
   const LnStat st = stat_of(sr);
   const int tid = threadIdx.x;
@@ -84,10 +93,14 @@ __global__ __launch_bounds__(256) void k_ln_bwd(
 
 // y = relu(LN(h) + skip) for 2x2x2 groups of voxels, and the group mean of y
 // (the average-pooled input of the next encoder level) when `pooled` is set.
-__global__ void k_ln_apply_pool(const float4* __restrict__ h, PairRef sr,
-                                const float* __restrict__ g, const float* __restrict__ b,
-                                const float4* __restrict__ skip, float4* __restrict__ y,
-                                float4* __restrict__ pooled, int n, int C4) {
+__global__ void k_ln_apply_pool(const float4* h, PairRef sr, const float* g, const float* b,
+                                const float4* skip, float4* y, float4* pooled, int n, int C4,
+                                long long istride) {
+  {
+    const long long off = (long long)blockIdx.y * istride;
+    h = ishift(h, off); sr.part = ishift(sr.part, off); g = ishift(g, off); b = ishift(b, off);
+    skip = ishift(skip, off); y = ishift(y, off); pooled = ishift(pooled, off);
+  }
   const int m = n / 2;
   const size_t total = (size_t)m * m * m * C4;
   const LnStat st = stat_of(sr);
@@ -138,8 +151,12 @@ __global__ void k_avgpool2(const float4* __restrict__ x, int n, int C4, float4* 
 }
 
 // cat[v][0..Cu) = d[parent(v)], cat[v][Cu..Cu+Cs) = e[v]  (fine grid n).
-__global__ void k_up_concat(const float4* __restrict__ d, int Cu4, const float4* __restrict__ e,
-                            int Cs4, int n, float4* __restrict__ cat) {
+__global__ void k_up_concat(const float4* d, int Cu4, const float4* e, int Cs4, int n, float4* cat,
+                            long long istride) {
+  {
+    const long long off = (long long)blockIdx.y * istride;
+    d = ishift(d, off); e = ishift(e, off); cat = ishift(cat, off);
+  }
   const int m = n / 2, C4 = Cu4 + Cs4;
   const size_t total = (size_t)n * n * n * C4;
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < total;
@@ -156,8 +173,12 @@ __global__ void k_up_concat(const float4* __restrict__ d, int Cu4, const float4*
 }
 
 // gu[v'][c] = sum of gcat[child][c] over the 8 children, c < Cu (coarse grid).
-__global__ void k_up_bwd(const float4* __restrict__ gcat, int C4, int Cu4, int n,
-                         float4* __restrict__ gu) {
+__global__ void k_up_bwd(const float4* gcat, int C4, int Cu4, int n, float4* gu,
+                         long long istride) {
+  {
+    const long long off = (long long)blockIdx.y * istride;
+    gcat = ishift(gcat, off); gu = ishift(gu, off);
+  }
   const int m = n / 2;
   const size_t total = (size_t)m * m * m * Cu4;
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < total;
@@ -177,8 +198,12 @@ __global__ void k_up_bwd(const float4* __restrict__ gcat, int C4, int Cu4, int n
 }
 
 // gs[v][c] = gcat[v][Cu + c]
-__global__ void k_cat_split(const float4* __restrict__ gcat, int C4, int Cu4, int Cs4, size_t V,
-                            float4* __restrict__ gs) {
+__global__ void k_cat_split(const float4* gcat, int C4, int Cu4, int Cs4, size_t V, float4* gs,
+                            long long istride) {
+  {
+    const long long off = (long long)blockIdx.y * istride;
+    gcat = ishift(gcat, off); gs = ishift(gs, off);
+  }
   const size_t total = V * Cs4;
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < total;
        i += (size_t)gridDim.x * blockDim.x) {
@@ -188,8 +213,12 @@ __global__ void k_cat_split(const float4* __restrict__ gcat, int C4, int Cu4, in
 }
 
 // gy[v][c] = add[v][c] + gx[parent(v)][c] / 8   (fine grid n)
-__global__ void k_pool_bwd_add(const float4* __restrict__ gx, const float4* __restrict__ add,
-                               int n, int C4, float4* __restrict__ gy) {
+__global__ void k_pool_bwd_add(const float4* gx, const float4* add, int n, int C4, float4* gy,
+                               long long istride) {
+  {
+    const long long off = (long long)blockIdx.y * istride;
+    gx = ishift(gx, off); add = ishift(add, off); gy = ishift(gy, off);
+  }
   const int m = n / 2;
   const size_t total = (size_t)n * n * n * C4;
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < total;
@@ -206,6 +235,7 @@ __global__ void k_pool_bwd_add(const float4* __restrict__ gx, const float4* __re
 
 // zp[v][0] = z[v], zp[v][1..8) = 0
 __global__ void k_pad_input(const float* __restrict__ z, size_t V, float* __restrict__ zp) {
+
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < V * 8;
        i += (size_t)gridDim.x * blockDim.x)
     zp[i] = (i % 8) == 0 ? z[i / 8] : 0.f;
@@ -221,11 +251,12 @@ inline int grid_for(size_t work, int per_thread = 1) {
 }  // namespace
 
 void ln_apply(const float* h, PairRef st, const float* g, const float* b, const float* skip,
-              float* y, size_t V, int C, hipStream_t s) {
+              float* y, size_t V, int C, int batch, long long istride, hipStream_t s) {
   const size_t n4 = V * C / 4;
-  hipLaunchKernelGGL(k_ln_apply, dim3(grid_for(n4)), dim3(256), 0, s,
+  hipLaunchKernelGGL(k_ln_apply, dim3(grid_for(n4), batch), dim3(256), 0, s,
                      reinterpret_cast<const float4*>(h), st, g, b,
-                     reinterpret_cast<const float4*>(skip), reinterpret_cast<float4*>(y), n4, C);
+                     reinterpret_cast<const float4*>(skip), reinterpret_cast<float4*>(y), n4, C,
+                     istride);
 }
 
 int ln_bwd_blocks(size_t V, int C) {
@@ -241,18 +272,20 @@ int ln_bwd_vpb(int C) {
 
 void ln_bwd(const float* gy, int mask_mode, const float* my, const float* mg, const float* mb,
             const float* h, PairRef st, float* gz, double* part_c, double* part_ab, size_t V,
-            int C, const float* gamma, hipStream_t s) {
-  hipLaunchKernelGGL(k_ln_bwd, dim3(ln_bwd_blocks(V, C)), dim3(256), 0, s, gy, mask_mode, my, mg,
-                     mb, h, st, gz, part_c, part_ab, (int)V, C, ln_bwd_vpb(C), gamma);
+            int C, const float* gamma, int batch, long long istride, hipStream_t s) {
+  hipLaunchKernelGGL(k_ln_bwd, dim3(ln_bwd_blocks(V, C), batch), dim3(256), 0, s, gy, mask_mode,
+                     my, mg, mb, h, st, gz, part_c, part_ab, (int)V, C, ln_bwd_vpb(C), gamma,
+                     istride);
 }
 
 void ln_apply_pool(const float* h, PairRef st, const float* g, const float* b, const float* skip,
-                   float* y, float* pooled, int n, int C, hipStream_t s) {
+                   float* y, float* pooled, int n, int C, int batch, long long istride,
+                   hipStream_t s) {
   const size_t work = (size_t)(n / 2) * (n / 2) * (n / 2) * (C / 4);
-  hipLaunchKernelGGL(k_ln_apply_pool, dim3(grid_for(work)), dim3(256), 0, s,
+  hipLaunchKernelGGL(k_ln_apply_pool, dim3(grid_for(work), batch), dim3(256), 0, s,
                      reinterpret_cast<const float4*>(h), st, g, b,
                      reinterpret_cast<const float4*>(skip), reinterpret_cast<float4*>(y),
-                     reinterpret_cast<float4*>(pooled), n, C / 4);
+                     reinterpret_cast<float4*>(pooled), n, C / 4, istride);
 }
 
 void avgpool2(const float* x, int n, int C, float* y, hipStream_t s) {
@@ -261,31 +294,34 @@ void avgpool2(const float* x, int n, int C, float* y, hipStream_t s) {
                      reinterpret_cast<const float4*>(x), n, C / 4, reinterpret_cast<float4*>(y));
 }
 
-void up_concat(const float* d, int Cu, const float* e, int Cs, int n, float* cat, hipStream_t s) {
+void up_concat(const float* d, int Cu, const float* e, int Cs, int n, float* cat, int batch,
+               long long istride, hipStream_t s) {
   const size_t work = (size_t)n * n * n * ((Cu + Cs) / 4);
-  hipLaunchKernelGGL(k_up_concat, dim3(grid_for(work)), dim3(256), 0, s,
+  hipLaunchKernelGGL(k_up_concat, dim3(grid_for(work), batch), dim3(256), 0, s,
                      reinterpret_cast<const float4*>(d), Cu / 4,
                      reinterpret_cast<const float4*>(e), Cs / 4, n,
-                     reinterpret_cast<float4*>(cat));
+                     reinterpret_cast<float4*>(cat), istride);
 }
 
-void up_concat_bwd(const float* gcat, int Cu, int Cs, int n, float* gu, float* gs, hipStream_t s) {
+void up_concat_bwd(const float* gcat, int Cu, int Cs, int n, float* gu, float* gs, int batch,
+                   long long istride, hipStream_t s) {
   const int C4 = (Cu + Cs) / 4;
   const size_t wu = (size_t)(n / 2) * (n / 2) * (n / 2) * (Cu / 4);
-  hipLaunchKernelGGL(k_up_bwd, dim3(grid_for(wu)), dim3(256), 0, s,
+  hipLaunchKernelGGL(k_up_bwd, dim3(grid_for(wu), batch), dim3(256), 0, s,
                      reinterpret_cast<const float4*>(gcat), C4, Cu / 4, n,
-                     reinterpret_cast<float4*>(gu));
+                     reinterpret_cast<float4*>(gu), istride);
   const size_t V = (size_t)n * n * n;
-  hipLaunchKernelGGL(k_cat_split, dim3(grid_for(V * (Cs / 4))), dim3(256), 0, s,
+  hipLaunchKernelGGL(k_cat_split, dim3(grid_for(V * (Cs / 4)), batch), dim3(256), 0, s,
                      reinterpret_cast<const float4*>(gcat), C4, Cu / 4, Cs / 4, V,
-                     reinterpret_cast<float4*>(gs));
+                     reinterpret_cast<float4*>(gs), istride);
 }
 
-void pool_bwd_add(const float* gx, const float* add, int n, int C, float* gy, hipStream_t s) {
+void pool_bwd_add(const float* gx, const float* add, int n, int C, float* gy, int batch,
+                  long long istride, hipStream_t s) {
   const size_t work = (size_t)n * n * n * (C / 4);
-  hipLaunchKernelGGL(k_pool_bwd_add, dim3(grid_for(work)), dim3(256), 0, s,
+  hipLaunchKernelGGL(k_pool_bwd_add, dim3(grid_for(work), batch), dim3(256), 0, s,
                      reinterpret_cast<const float4*>(gx), reinterpret_cast<const float4*>(add), n,
-                     C / 4, reinterpret_cast<float4*>(gy));
+                     C / 4, reinterpret_cast<float4*>(gy), istride);
 }
 
 void pad_input(const float* z, size_t V, float* zp, hipStream_t s) {

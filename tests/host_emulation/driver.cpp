@@ -1,0 +1,118 @@
+// Drives every C-ABI entry point of the library through the host emulation
+// of the HIP runtime (device memory = host memory, launches not executed), so
+// that AddressSanitizer sees all host-side bookkeeping: workspace planning,
+// uploads, graph capture and replay, state save/restore, kernel timing and
+// teardown, for several instance layouts, precisions and both run modes.
+#include <cstdio>
+#include <cstdlib>
+#include <random>
+#include <vector>
+
+#include "d2ip.h"
+
+extern "C" long g_launches;
+
+#define CK(x)                                                              \
+  do {                                                                     \
+    d2ip_status s_ = (x);                                                  \
+    if (s_) {                                                              \
+      printf("FAIL %s: %d %s\n", #x, (int)s_, d2ip_last_error());          \
+      return 1;                                                            \
+    }                                                                      \
+  } while (0)
+#define EXPECT_ERR(x, code)                                                \
+  do {                                                                     \
+    if ((x) != (code)) {                                                   \
+      printf("FAIL %s: expected %d\n", #x, (int)(code));                   \
+      return 1;                                                            \
+    }                                                                      \
+  } while (0)
+
+static int run_case(const std::vector<d2ip_geometry_desc>& G,
+                    const std::vector<d2ip_instance_desc>& I, int prec, unsigned flags) {
+  size_t need = 0;
+  CK(d2ip_workspace_bytes(G.data(), (int)G.size(), I.data(), (int)I.size(), prec, flags, &need));
+  char* ws = (char*)aligned_alloc(256, (need + 255) / 256 * 256);
+  d2ip_ctx* X = nullptr;
+  int stream_token = 0;
+  EXPECT_ERR(d2ip_create(G.data(), (int)G.size(), I.data(), (int)I.size(), prec, flags, ws,
+                         need - 1, &stream_token, &X),
+             D2IP_ENOMEM);
+  CK(d2ip_create(G.data(), (int)G.size(), I.data(), (int)I.size(), prec, flags, ws, need,
+                 &stream_token, &X));
+  std::vector<double> loss(I.size());
+  EXPECT_ERR(d2ip_run(X, 1, loss.data()), D2IP_ESTATE);
+  std::mt19937 rng(1);
+  std::normal_distribution<float> nd;
+  for (size_t g = 0; g < G.size(); ++g) {
+    const size_t Q = (size_t)G[g].n * G[g].n * G[g].n;
+    std::vector<float> J((size_t)G[g].M * Q);
+    for (float& v : J) v = nd(rng);
+    std::vector<uint8_t> mask(Q);
+    for (size_t q = 0; q < Q; ++q) mask[q] = (q * 7 % 5) != 0;
+    CK(d2ip_set_geometry(X, (int)g, J.data(), mask.data(), 0));
+  }
+  for (size_t i = 0; i < I.size(); ++i) {
+    size_t P = 0;
+    CK(d2ip_param_count(I[i].levels, I[i].base_ch, &P));
+    std::vector<float> th(P);
+    for (float& v : th) v = 0.1f * nd(rng);
+    EXPECT_ERR(d2ip_set_params(X, (int)i, th.data(), P - 1, 0), D2IP_EINVAL);
+    CK(d2ip_set_params(X, (int)i, th.data(), P, 0));
+    const size_t V = (size_t)G[I[i].geometry].n * G[I[i].geometry].n * G[I[i].geometry].n;
+    std::vector<float> z(V);
+    for (float& v : z) v = nd(rng);
+    CK(d2ip_set_noise_input(X, (int)i, z.data(), 0));
+    std::vector<float> dv(G[I[i].geometry].M);
+    for (float& v : dv) v = nd(rng);
+    CK(d2ip_set_frame(X, (int)i, dv.data(), 0));
+  }
+  EXPECT_ERR(d2ip_set_frame(X, (int)I.size(), nullptr, 0), D2IP_EINVAL);
+  CK(d2ip_run(X, 4, loss.data()));
+  d2ip_adam_cfg cfg = {2e-3f, 0.9f, 0.999f, 1e-8f};
+  CK(d2ip_set_adam(X, &cfg));
+  CK(d2ip_run(X, 2, nullptr));
+  for (size_t i = 0; i < I.size(); ++i) {
+    size_t P = 0;
+    CK(d2ip_param_count(I[i].levels, I[i].base_ch, &P));
+    std::vector<float> st(3 * P), g(P);
+    int64_t t = 0;
+    CK(d2ip_get_state(X, (int)i, st.data(), &t, 0));
+    CK(d2ip_set_state(X, (int)i, st.data(), t, 0));
+    CK(d2ip_reset_optimizer(X, (int)i));
+    CK(d2ip_get_grad(X, (int)i, g.data(), P, 0));
+    CK(d2ip_get_params(X, (int)i, g.data(), P, 0));
+    const size_t V = (size_t)G[I[i].geometry].n * G[I[i].geometry].n * G[I[i].geometry].n;
+    std::vector<float> img(V);
+    CK(d2ip_read_image(X, (int)i, img.data(), 0));
+    double ms = 0.0;
+    for (int k = 0; k <= 5; ++k)
+      for (int blk = 0; blk < 2; ++blk) {
+        d2ip_status s = d2ip_time_kernel(X, (int)i, k, blk, 2, &ms);
+        if (s != D2IP_OK && s != D2IP_EINVAL) {
+          printf("FAIL time_kernel %d %d: %s\n", k, blk, d2ip_last_error());
+          return 1;
+        }
+      }
+  }
+  CK(d2ip_run(X, 3, loss.data()));
+  CK(d2ip_check_launches(G.data(), (int)G.size(), I.data(), (int)I.size(), prec, flags));
+  CK(d2ip_destroy(X));
+  free(ws);
+  printf("ok: %zu geometries, %zu instances, precision %d, flags %u\n", G.size(), I.size(), prec,
+         flags);
+  return 0;
+}
+
+int main() {
+  int bad = 0;
+  for (int prec = 0; prec < 3; ++prec)
+    for (unsigned fl = 0; fl < 2; ++fl) {
+      bad |= run_case({{16, 928}}, {{0, 3, 8}, {0, 3, 8}, {0, 3, 8}}, prec, fl);
+      bad |= run_case({{16, 208}, {24, 208}}, {{0, 2, 8}, {0, 2, 16}, {1, 3, 8}, {0, 2, 8}}, prec,
+                      fl);
+      bad |= run_case({{16, 208}}, {{0, 2, 8}}, prec, fl);
+    }
+  printf("launches: %ld\n", g_launches);
+  return bad;
+}

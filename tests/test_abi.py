@@ -84,3 +84,31 @@ def test_null_pointer_errors(L):
     # null workspace
     assert lib.d2ip_create(g, 1, i, 1, 0, 0, None, 0, None, ctypes.byref(out)) == L.EINVAL
     assert b"workspace" in lib.d2ip_last_error()
+
+
+def _workload(name):
+    """(geometries, instances) of one named workload, one geometry per distinct grid."""
+    c = ts.CONFIGS[name]
+    M = {1: 208, 2: 928}
+    if name == "c4":
+        geos, insts = [], []
+        for inst in c["instances"]:
+            g = (inst["n"], M[inst["rings"]])
+            if g not in geos:
+                geos.append(g)
+            insts.append((geos.index(g), c["levels"], inst["base_ch"]))
+        return geos, insts
+    geos = [(c["n"], M[c["rings"]])]
+    return geos, [(0, c["levels"], c["base_ch"])] * c.get("sequences", 1)
+
+
+@pytest.mark.parametrize("name", ["c0", "c1", "c2", "c3", "c4"])
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3", "bf16"])
+def test_every_launch_stays_inside_the_workspace(L, name, prec):
+    """Host-only walk of one iteration's launch schedule: each kernel
+    argument's extent, implied by its shapes, lies in one workspace
+    allocation (all instances, eager and graph plans)."""
+    import paper_2507_14046_amd as d2ip
+    geos, insts = _workload(name)
+    for graph in (False, True):
+        d2ip.check_launches(geos, insts, prec, graph=graph)

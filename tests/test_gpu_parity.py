@@ -211,3 +211,51 @@ def test_full_size_32cubed_one_iteration(lib):
                grad_rel=rel(g, gref), worst=max(per.values()))
         assert rel(g, gref) < TOL_GRAD[prec]
         ctx.close()
+
+
+@pytest.mark.skip(reason="instance groups (batched launches) are switched off: their first GPU run crashed the host process (SIGSEGV in d2ip_run) and the cause is not yet shown")
+def test_group_of_instances_matches_each_alone(lib):
+    """Instances sharing geometry, levels and channels run as one group
+    (batched launches, J read once for all members); each member must match
+    the same instance run alone, bit for bit, across a frame switch."""
+    probs = [problem(16, 2, 3, 8, s, frames=2, breathing=True) for s in (21, 22, 23)]
+    grp = lib.Context([(16, 928)], [(0, 3, 8)] * 3, graph=True)
+    grp.set_geometry(0, probs[0]["J"], probs[0]["mask"])
+    for i, p in enumerate(probs):
+        grp.load_problem(i, p, set_geometry=False)
+    l_grp = grp.run(4)
+    for i, p in enumerate(probs):
+        grp.set_frame(i, p["dv"][1])
+        grp.reset_optimizer(i)
+    l_grp2 = grp.run(3)
+    for i, p in enumerate(probs):
+        one = make_ctx(lib, [p], graph=True)
+        assert one.run(4)[0] == l_grp[i]
+        one.set_frame(0, p["dv"][1])
+        one.reset_optimizer(0)
+        assert one.run(3)[0] == l_grp2[i]
+        np.testing.assert_array_equal(one.get_params(0), grp.get_params(i))
+        np.testing.assert_array_equal(one.read_image(0), grp.read_image(i))
+
+
+@pytest.mark.skip(reason="instance groups (batched launches) are switched off: their first GPU run crashed the host process (SIGSEGV in d2ip_run) and the cause is not yet shown")
+def test_mixed_groups_and_shared_geometry(lib):
+    """Two groups on one geometry (different channel counts) plus a group on
+    another geometry, as in the uneven batch; compared with the oracle."""
+    pa = problem(16, 1, 2, 8, 31)
+    pb = problem(16, 1, 2, 16, 32)
+    pc = problem(24, 1, 3, 8, 33)
+    ctx = lib.Context([(16, 208), (24, 208)], [(0, 2, 8), (0, 2, 16), (1, 3, 8), (0, 2, 8)])
+    ctx.set_geometry(0, pa["J"], pa["mask"])
+    ctx.set_geometry(1, pc["J"], pc["mask"])
+    pd = problem(16, 1, 2, 8, 34)
+    for i, p in enumerate([pa, pb, pc, pd]):
+        ctx.load_problem(i, p, set_geometry=False)
+    ctx.run(3)
+    for i, p in enumerate([pa, pb, pc, pd]):
+        pr = oracle_problem(p)
+        st = fit.State(p["theta0"])
+        fit.run(pr, st, p["dv"][0], 3, 1e-3)
+        e = rel(ctx.read_image(i), pr.image(st.theta))
+        record("mixed_groups", instance=i, image_rel=e)
+        assert e < 1e-5
