@@ -87,7 +87,21 @@ __host__ inline size_t fwd_lds_bytes(int tile, int taps, int bn, int ck, int mod
   const size_t ckp = ck + (bf ? 8 : 1);
   const size_t stage = parts * el * (hp * ckp + (size_t)bn * fwd_wrow(taps, ck, bf));
   const size_t xch = (size_t)4 * (tz * ty * tx / 16) * (bn / 16) * 64 * 16;  // 4 waves x tiles
-  return stage > xch ? stage : xch;
+  const int kstep = bf ? 32 : 4;
+  const size_t ktab = (size_t)4 * 4 * ((taps * ck + kstep - 1) / kstep);  // k-offset table
+  return (((stage > xch ? stage : xch) + 15) & ~(size_t)15) + ktab;
+}
+
+// Offset (in LDS elements) of the k-offset table of the forward kernel.
+__host__ __device__ inline int fwd_ktab_offset_bytes(int hp, int bn, int ck, int taps, int mode,
+                                                     int mt, int nt) {
+  const bool bf = mode != PREC_F32;
+  const int parts = mode == PREC_BF16X3 ? 2 : 1;
+  const int el = bf ? 2 : 4;
+  const int ckp = ck + (bf ? 8 : 1);
+  const int stage = parts * el * (hp * ckp + bn * fwd_wrow(taps, ck, bf));
+  const int xch = 4 * mt * nt * 64 * 16;
+  return ((stage > xch ? stage : xch) + 15) & ~15;
 }
 
 __device__ __forceinline__ f32x4 mfma(float a, float b, f32x4 c) {
@@ -105,27 +119,6 @@ __device__ __forceinline__ void split_bf(float x, uint16_t& hi, uint16_t& lo) {
 
 __device__ __forceinline__ uint32_t pack2(uint16_t a, uint16_t b) {
   return (uint32_t)a | ((uint32_t)b << 16);
-}
-
-// Four consecutive channels c..c+3 of the operand at element offset i, with
-// the source's prologue applied.
-template <int PRO>
-__device__ __forceinline__ float4 load_src4(const ConvSrc& s, size_t i, int c, float mean,
-                                            float rstd, float A, float B) {
-  float4 v = *reinterpret_cast<const float4*>(s.x + i);
-  if (PRO == PRO_LN_RELU) {
-    v.x = fmaxf(s.gamma[c + 0] * ((v.x - mean) * rstd) + s.beta[c + 0], 0.f);
-    v.y = fmaxf(s.gamma[c + 1] * ((v.y - mean) * rstd) + s.beta[c + 1], 0.f);
-    v.z = fmaxf(s.gamma[c + 2] * ((v.z - mean) * rstd) + s.beta[c + 2], 0.f);
-    v.w = fmaxf(s.gamma[c + 3] * ((v.w - mean) * rstd) + s.beta[c + 3], 0.f);
-  } else if (PRO == PRO_LN_BWD) {
-    const float4 h = *reinterpret_cast<const float4*>(s.h + i);
-    v.x = rstd * (s.gamma[c + 0] * v.x - A - ((h.x - mean) * rstd) * B);
-    v.y = rstd * (s.gamma[c + 1] * v.y - A - ((h.y - mean) * rstd) * B);
-    v.z = rstd * (s.gamma[c + 2] * v.z - A - ((h.z - mean) * rstd) * B);
-    v.w = rstd * (s.gamma[c + 3] * v.w - A - ((h.w - mean) * rstd) * B);
-  }
-  return v;
 }
 
 // Prologue constants of a source, reduced from the producers' partials by
@@ -172,24 +165,118 @@ __device__ __forceinline__ void put4(typename Mode<MODE>::ST* hi, typename Mode<
   }
 }
 
-// Stage a (HZ x HY x HX) halo of ck channels starting at ci0 into LDS rows of
-// ckp elements; out-of-grid voxels are the conv's zero padding.
-template <int MODE, int HZ, int HY, int HX, int PRO>
-__device__ __forceinline__ void stage_halo(typename Mode<MODE>::ST* hal,
-                                           typename Mode<MODE>::ST* hal_lo, const ConvSrc& s,
-                                           int n, int ck, int ckp, int ci0, int z0, int y0, int x0,
-                                           int R, float mean, float rstd, float A, float B) {
-  const int Q = ck >> 2;
+// Staging goes through registers in two phases: every global load of a
+// pass is issued first (all in flight together, and across chunks or tiles
+// while the previous one is being computed), then the values are
+// transformed and written to LDS.  Element k of a thread's pass is
+// p = k * 256 + tid; with Q = ck / 4 channel quads per voxel (Q divides 256)
+// a thread always handles the same quad, tid % Q.
+template <int NB, int PRO>
+struct Quads {
+  float4 v[NB];
+  float4 h[PRO == PRO_LN_BWD ? NB : 1];  // LayerNorm-backward input
+  unsigned in;                           // bit k: element k lies inside the grid
+};
+
+// Element k's LayerNorm-backward input (zero for other prologues).
+template <int NB, int PRO>
+__device__ __forceinline__ float4 quad_h(const Quads<NB, PRO>& r, int k) {
+  if constexpr (PRO == PRO_LN_BWD) return r.h[k];
+  return make_float4(0.f, 0.f, 0.f, 0.f);
+}
+
+// Channel constants of a source prologue for the channels c..c+3.
+struct ChanConsts {
+  float4 g, b;
+};
+
+template <int PRO>
+__device__ __forceinline__ ChanConsts chan_consts(const ConvSrc& s, int c) {
+  ChanConsts k;
+  k.g = make_float4(1.f, 1.f, 1.f, 1.f);
+  k.b = make_float4(0.f, 0.f, 0.f, 0.f);
+  if (PRO != PRO_NONE) k.g = make_float4(s.gamma[c], s.gamma[c + 1], s.gamma[c + 2], s.gamma[c + 3]);
+  if (PRO == PRO_LN_RELU) k.b = make_float4(s.beta[c], s.beta[c + 1], s.beta[c + 2], s.beta[c + 3]);
+  return k;
+}
+
+// The source's pending transform on four channels (inside the grid only: the
+// conv's zero padding stays zero).
+template <int PRO>
+__device__ __forceinline__ float4 apply_pro(float4 v, float4 h, const ChanConsts& k, float mean,
+                                            float rstd, float A, float B) {
+  if (PRO == PRO_LN_RELU) {
+    v.x = fmaxf(k.g.x * ((v.x - mean) * rstd) + k.b.x, 0.f);
+    v.y = fmaxf(k.g.y * ((v.y - mean) * rstd) + k.b.y, 0.f);
+    v.z = fmaxf(k.g.z * ((v.z - mean) * rstd) + k.b.z, 0.f);
+    v.w = fmaxf(k.g.w * ((v.w - mean) * rstd) + k.b.w, 0.f);
+  } else if (PRO == PRO_LN_BWD) {
+    v.x = rstd * (k.g.x * v.x - A - ((h.x - mean) * rstd) * B);
+    v.y = rstd * (k.g.y * v.y - A - ((h.y - mean) * rstd) * B);
+    v.z = rstd * (k.g.z * v.z - A - ((h.z - mean) * rstd) * B);
+    v.w = rstd * (k.g.w * v.w - A - ((h.w - mean) * rstd) * B);
+  }
+  return v;
+}
+
+// Number of staging elements per thread for a halo of HP voxels at the
+// largest channel chunk.
+template <int HP>
+constexpr int halo_nb() {
+  return (HP * (kCkMax / 4) + 255) / 256;
+}
+
+// Issue the loads of a (HZ x HY x HX) halo of ck = 4 << qs channels starting
+// at ci0, anchored at (z0, y0, x0) - R.
+template <int NB, int PRO, int HZ, int HY, int HX>
+__device__ __forceinline__ void halo_load(Quads<NB, PRO>& r, const ConvSrc& s, int n, int qs,
+                                          int ci0, int z0, int y0, int x0, int R) {
   constexpr int HP = HZ * HY * HX;
-  for (int p = threadIdx.x; p < HP * Q; p += 256) {
-    const int pos = p / Q, q = p - pos * Q;
+  const int total = HP << qs;
+  const int c = ci0 + 4 * (threadIdx.x & ((1 << qs) - 1));
+  r.in = 0u;
+#pragma unroll
+  for (int k = 0; k < NB; ++k) {
+    r.v[k] = make_float4(0.f, 0.f, 0.f, 0.f);
+    if constexpr (PRO == PRO_LN_BWD) r.h[k] = r.v[k];
+    if (k * 256 >= total) continue;  // uniform: dead for smaller chunks
+    const int p = k * 256 + threadIdx.x;
+    const int pos = p >> qs;
     const int hx = pos % HX, hy = (pos / HX) % HY, hz = pos / (HX * HY);
     const int gz = z0 + hz - R, gy = y0 + hy - R, gx = x0 + hx - R;
-    float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-    const int c = ci0 + 4 * q;
-    if (gz >= 0 && gz < n && gy >= 0 && gy < n && gx >= 0 && gx < n)
-      v = load_src4<PRO>(s, (size_t)((gz * n + gy) * n + gx) * s.stride + c, c, mean, rstd, A, B);
-    put4<MODE>(hal, hal_lo, pos * ckp + 4 * q, v);
+    const bool ok = p < total && gz >= 0 && gz < n && gy >= 0 && gy < n && gx >= 0 && gx < n;
+    float4 v = make_float4(0.f, 0.f, 0.f, 0.f), h = v;
+    if (ok) {
+      const size_t i = (size_t)((gz * n + gy) * n + gx) * s.stride + c;
+      v = *reinterpret_cast<const float4*>(s.x + i);
+      if (PRO == PRO_LN_BWD) h = *reinterpret_cast<const float4*>(s.h + i);
+    }
+    r.v[k] = v;
+    if constexpr (PRO == PRO_LN_BWD) r.h[k] = h;
+    r.in |= (ok ? 1u : 0u) << k;
+  }
+}
+
+// Write a loaded halo to LDS rows of ckp elements (forward layout
+// [voxel][channel]).
+template <int MODE, int NB, int PRO, int HP>
+__device__ __forceinline__ void halo_store(typename Mode<MODE>::ST* hal,
+                                           typename Mode<MODE>::ST* hal_lo,
+                                           const Quads<NB, PRO>& r, int qs, int ckp,
+                                           const ChanConsts& kc, float mean, float rstd, float A,
+                                           float B) {
+  const int total = HP << qs;
+  const int q = threadIdx.x & ((1 << qs) - 1);
+#pragma unroll
+  for (int k = 0; k < NB; ++k) {
+    if (k * 256 >= total) break;  // uniform
+    const int p = k * 256 + threadIdx.x;
+    if (p < total) {
+      float4 v = r.v[k];
+      if (PRO != PRO_NONE && ((r.in >> k) & 1u))
+        v = apply_pro<PRO>(v, quad_h(r, k), kc, mean, rstd, A, B);
+      put4<MODE>(hal, hal_lo, (p >> qs) * ckp + 4 * q, v);
+    }
   }
 }
 
@@ -198,14 +285,21 @@ __device__ __forceinline__ int tap_offset(int tap, int HY, int HX) {
   return (dz * HY + dy) * HX + dx;
 }
 
+// MFMA operand fragment at p (always an in-bounds LDS address), zeroed
+// where ok is false; a select, not a branch.
 template <int MODE>
 __device__ __forceinline__ typename Mode<MODE>::FT frag(const typename Mode<MODE>::ST* p, bool ok) {
   if constexpr (Mode<MODE>::BF) {
-    u32x4 v = {0u, 0u, 0u, 0u};
-    if (ok) v = *reinterpret_cast<const u32x4*>(p);
+    u32x4 v = *reinterpret_cast<const u32x4*>(p);
+    const unsigned m = ok ? 0xffffffffu : 0u;
+    v.x &= m;
+    v.y &= m;
+    v.z &= m;
+    v.w &= m;
     return __builtin_bit_cast(bf16x8, v);
   } else {
-    return ok ? *p : 0.f;
+    const float v = *p;
+    return ok ? v : 0.f;
   }
 }
 
@@ -266,75 +360,120 @@ __global__ __launch_bounds__(256) void k_conv_fwd(ConvFwd a) {
 #pragma unroll
     for (int j = 0; j < NT; ++j) acc[i][j] = (f32x4){0.f, 0.f, 0.f, 0.f};
 
-  int apos[MT];
+  // LDS offsets of this lane's A rows (halo voxels) and B rows (weight rows)
+  int abase[MT], bbase[NT];
 #pragma unroll
   for (int mt = 0; mt < MT; ++mt) {
     const int li = mt * 16 + l16;
     const int tz = li / (TY * TX), ty = (li / TX) % TY, tx = li % TX;
-    apos[mt] = (tz * HY + ty) * HX + tx;
+    abase[mt] = ((tz * HY + ty) * HX + tx) * ckp;
+  }
+#pragma unroll
+  for (int nt = 0; nt < NT; ++nt) bbase[nt] = (nt * 16 + l16) * wrp;
+  // k-offset table: for k-step s and lane group gg, the halo offset of its
+  // (tap, channel) in the low 16 bits and the weight-slab column in the high
+  // 16 bits; k beyond the taps points at the zeroed pad column of every
+  // weight row (only BF16 steps overrun)
+  const int nstep = (TAPS * ck + KSTEP - 1) / KSTEP;
+  uint32_t* ktab = reinterpret_cast<uint32_t*>(
+      smem + fwd_ktab_offset_bytes(HP, BN, ck, TAPS, MODE, MT, NT));
+  for (int e = tid; e < nstep * 4; e += 256) {
+    const int kl = (e >> 2) * KSTEP + (e & 3) * KPL;
+    const int tap = kl >> ck_shift, c = kl & (ck - 1);
+    uint32_t hoff = 0, woff = TAPS * ck;
+    if (tap < TAPS) {
+      hoff = (TAPS == 27 ? tap_offset(tap, HY, HX) : 0) * ckp + c;
+      woff = tap * ck + c;
+    }
+    ktab[e] = hoff | (woff << 16);
+  }
+  if constexpr (MD::BF) {
+    // zero pad columns [TAPS * ck, wrp) of every weight row (hi and lo)
+    const int padw = wrp - TAPS * ck;
+    for (int e = tid; e < BN * padw; e += 256) {
+      const int r = e / padw, j = e - r * padw;
+      wsm[r * wrp + TAPS * ck + j] = 0;
+      if constexpr (MD::SPLIT) wsm_lo[r * wrp + TAPS * ck + j] = 0;
+    }
   }
 
   const ST* __restrict__ W = reinterpret_cast<const ST*>(a.w);
   const ST* __restrict__ Wlo = W + a.w_lo_off;
   const int nchunks = a.cin >> ck_shift;
   const int cps = nchunks / ksplit;
-  const int nstep = (TAPS * ck + KSTEP - 1) / KSTEP;
+  const int qs = ck_shift - 2;
+  constexpr int NBH = halo_nb<HP>();
+  Quads<NBH, PRO> hq;
+  // first chunk's halo in flight while the prologue statistics are reduced
+  halo_load<NBH, PRO, HZ, HY, HX>(hq, a.src, n, qs, (kz * cps) << ck_shift, z0, y0, x0, R);
   float pmean, prstd, pA, pB;
   src_consts<PRO>(a.src, pmean, prstd, pA, pB);
   for (int ch = kz * cps; ch < (kz + 1) * cps; ++ch) {
     const int ci0 = ch << ck_shift;
-    stage_halo<MODE, HZ, HY, HX, PRO>(hal, hal_lo, a.src, n, ck, ckp, ci0, z0, y0, x0, R, pmean,
-                                      prstd, pA, pB);
+    const ChanConsts kc = chan_consts<PRO>(a.src, ci0 + 4 * (tid & ((1 << qs) - 1)));
+    halo_store<MODE, NBH, PRO, HP>(hal, hal_lo, hq, qs, ckp, kc, pmean, prstd, pA, pB);
     // weight slab of this chunk: rows co0.., for every tap ck channels
     {
       constexpr int EV = MD::BF ? 8 : 4;  // elements per 16-byte vector
-      const int vpr = ck / EV;            // vectors per (row, tap)
-      const int nv = BN * TAPS * vpr;
-      for (int p = tid; p < nv; p += 256) {
-        const int r = p / (TAPS * vpr);
-        const int rem = p - r * TAPS * vpr;
-        const int tap = rem / vpr, q = rem - tap * vpr;
-        const int co = co0 + r;
-        const int o = r * wrp + tap * ck + q * EV;
-        u32x4 v = {0u, 0u, 0u, 0u}, vl = {0u, 0u, 0u, 0u};
-        if (co < a.w_rows) {
-          const size_t wi = ((size_t)co * TAPS + tap) * a.cin + ci0 + q * EV;
-          v = *reinterpret_cast<const u32x4*>(W + wi);
-          if constexpr (MD::SPLIT) vl = *reinterpret_cast<const u32x4*>(Wlo + wi);
+      constexpr int NBW = 8;              // loads in flight per thread
+      const int vs = ck_shift - (MD::BF ? 3 : 2);  // log2(vectors per (row, tap))
+      const int nv = (BN * TAPS) << vs;
+      for (int p0 = 0; p0 < nv; p0 += 256 * NBW) {
+        u32x4 v[NBW], vl[MD::SPLIT ? NBW : 1];
+#pragma unroll
+        for (int k = 0; k < NBW; ++k) {
+          const int p = p0 + k * 256 + tid;
+          const int rt = p >> vs, q = p & ((1 << vs) - 1);
+          const int r = rt / TAPS, tap = rt - r * TAPS;
+          const int co = co0 + r;
+          v[k] = (u32x4){0u, 0u, 0u, 0u};
+          if constexpr (MD::SPLIT) vl[k] = (u32x4){0u, 0u, 0u, 0u};
+          if (p < nv && co < a.w_rows) {
+            const size_t wi = ((size_t)co * TAPS + tap) * a.cin + ci0 + q * EV;
+            v[k] = *reinterpret_cast<const u32x4*>(W + wi);
+            if constexpr (MD::SPLIT) vl[k] = *reinterpret_cast<const u32x4*>(Wlo + wi);
+          }
         }
-        if constexpr (MD::BF) {
-          *reinterpret_cast<u32x4*>(wsm + o) = v;
-          if constexpr (MD::SPLIT) *reinterpret_cast<u32x4*>(wsm_lo + o) = vl;
-        } else {
-          // FP32 rows are padded to an even pitch: 4-byte stores
-          ST* d = wsm + o;
-          d[0] = __uint_as_float(v.x);
-          d[1] = __uint_as_float(v.y);
-          d[2] = __uint_as_float(v.z);
-          d[3] = __uint_as_float(v.w);
+#pragma unroll
+        for (int k = 0; k < NBW; ++k) {
+          const int p = p0 + k * 256 + tid;
+          if (p >= nv) continue;
+          const int rt = p >> vs, q = p & ((1 << vs) - 1);
+          const int r = rt / TAPS, tap = rt - r * TAPS;
+          const int o = r * wrp + tap * ck + q * EV;
+          if constexpr (MD::BF) {
+            *reinterpret_cast<u32x4*>(wsm + o) = v[k];
+            if constexpr (MD::SPLIT) *reinterpret_cast<u32x4*>(wsm_lo + o) = vl[k];
+          } else {
+            // FP32 rows are padded to an even pitch: 4-byte stores
+            ST* d = wsm + o;
+            d[0] = __uint_as_float(v[k].x);
+            d[1] = __uint_as_float(v[k].y);
+            d[2] = __uint_as_float(v[k].z);
+            d[3] = __uint_as_float(v[k].w);
+          }
         }
       }
     }
     __syncthreads();
+    // next chunk's halo loads run under this chunk's MFMAs
+    if (ch + 1 < (kz + 1) * cps)
+      halo_load<NBH, PRO, HZ, HY, HX>(hq, a.src, n, qs, (ch + 1) << ck_shift, z0, y0, x0, R);
 #pragma unroll 2
     for (int step = wave; step < nstep; step += 4) {
-      const int kl = step * KSTEP + g * KPL;
-      const int tap = kl >> ck_shift, c = kl & (ck - 1);
-      const bool kv = tap < TAPS;
-      const int toff = TAPS == 27 ? tap_offset(tap, HY, HX) : 0;
+      const uint32_t ko = ktab[step * 4 + g];
+      const int hoff = ko & 0xffffu, woff = ko >> 16;
       FT A[MT], B[NT];
       FT Al[MD::SPLIT ? MT : 1], Bl[MD::SPLIT ? NT : 1];
 #pragma unroll
       for (int mt = 0; mt < MT; ++mt) {
-        const int o = (apos[mt] + toff) * ckp + c;
-        A[mt] = frag<MODE>(hal + o, kv);
-        if constexpr (MD::SPLIT) Al[mt] = frag<MODE>(hal_lo + o, kv);
+        A[mt] = frag<MODE>(hal + abase[mt] + hoff, true);
+        if constexpr (MD::SPLIT) Al[mt] = frag<MODE>(hal_lo + abase[mt] + hoff, true);
       }
 #pragma unroll
       for (int nt = 0; nt < NT; ++nt) {
-        const int o = (nt * 16 + l16) * wrp + tap * ck + c;
-        B[nt] = frag<MODE>(wsm + o, kv);
-        if constexpr (MD::SPLIT) Bl[nt] = frag<MODE>(wsm_lo + o, kv);
+        B[nt] = frag<MODE>(wsm + bbase[nt] + woff, true);
+        if constexpr (MD::SPLIT) Bl[nt] = frag<MODE>(wsm_lo + bbase[nt] + woff, true);
       }
 #pragma unroll
       for (int mt = 0; mt < MT; ++mt)
@@ -528,11 +667,6 @@ __global__ __launch_bounds__(256) void k_conv_wgrad(ConvWgrad a) {
   ST* gs = hal + (MD::SPLIT ? 2 : 1) * hal_sz;
   ST* gs_lo = gs + (MD::SPLIT ? GSZ : 0);
 
-  float gmean, grstd, gA, gB;
-  src_consts<GPRO>(a.gsrc, gmean, grstd, gA, gB);
-  float xmean, xrstd, xA, xB;
-  src_consts<PRO>(a.src, xmean, xrstd, xA, xB);
-
   // this block's columns (tap, channel), shared by all waves
   f32x4 acc[kWgNg];
 #pragma unroll
@@ -556,27 +690,71 @@ __global__ __launch_bounds__(256) void k_conv_wgrad(ConvWgrad a) {
   }
   float4 bacc = make_float4(0.f, 0.f, 0.f, 0.f);
 
-  for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+  // staging of a voxel tile (halo of ck input channels, g tile of 16 output
+  // channels) goes through registers: the next tile's loads are issued before
+  // the current tile's MFMAs
+  constexpr int NBH = halo_nb<HP>();
+  constexpr int NBG = (BM * 4 + 255) / 256;
+  const int qs = ck_shift - 2;
+  const int gco = co0 + 4 * (tid & 3);  // output channels of this thread's g quads
+  Quads<NBH, PRO> hq;
+  Quads<NBG, GPRO> gq;
+  auto issue = [&](int t) {
     int b = t;
     const int x0 = (b % ntx) * TX;
     b /= ntx;
     const int y0 = (b % nty) * TY;
     b /= nty;
     const int z0 = b * TZ;
+    halo_load<NBH, PRO, HZ, HY, HX>(hq, a.src, n, qs, ci0, z0, y0, x0, R);
+    gq.in = 0u;
+#pragma unroll
+    for (int k = 0; k < NBG; ++k) {
+      const int p = k * 256 + tid;
+      const int v = p >> 2;
+      const int tz = v / (TY * TX), ty = (v / TX) % TY, tx = v % TX;
+      const int gz = z0 + tz, gy = y0 + ty, gx = x0 + tx;
+      const bool ok = p < BM * 4 && gz < n && gy < n && gx < n && gco < a.cout;
+      float4 val = make_float4(0.f, 0.f, 0.f, 0.f), h = val;
+      if (ok) {
+        const size_t i = ((size_t)(gz * n + gy) * n + gx) * a.cout + gco;
+        val = *reinterpret_cast<const float4*>(a.gsrc.x + i);
+        if (GPRO == PRO_LN_BWD) h = *reinterpret_cast<const float4*>(a.gsrc.h + i);
+      }
+      gq.v[k] = val;
+      if constexpr (GPRO == PRO_LN_BWD) gq.h[k] = h;
+      gq.in |= (ok ? 1u : 0u) << k;
+    }
+  };
+  if ((int)blockIdx.x < ntiles) issue(blockIdx.x);
+
+  float gmean, grstd, gA, gB;
+  src_consts<GPRO>(a.gsrc, gmean, grstd, gA, gB);
+  float xmean, xrstd, xA, xB;
+  src_consts<PRO>(a.src, xmean, xrstd, xA, xB);
+  const ChanConsts xk = chan_consts<PRO>(a.src, ci0 + 4 * (tid & ((1 << qs) - 1)));
+  ChanConsts gk;
+  gk.g = make_float4(1.f, 1.f, 1.f, 1.f);
+  gk.b = make_float4(0.f, 0.f, 0.f, 0.f);
+  if (gco < a.cout) gk = chan_consts<GPRO>(a.gsrc, gco);
+
+  for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
     // ---- halo of ck channels
     {
-      const int Q = ck >> 2;
-      for (int p = tid; p < HP * Q; p += 256) {
-        const int pos = p / Q, q = p - pos * Q;
-        const int hx = pos % HX, hy = (pos / HX) % HY, hz = pos / (HX * HY);
-        const int gz = z0 + hz - R, gy = y0 + hy - R, gx = x0 + hx - R;
-        float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-        const int c = ci0 + 4 * q;
-        if (gz >= 0 && gz < n && gy >= 0 && gy < n && gx >= 0 && gx < n)
-          v = load_src4<PRO>(a.src, (size_t)((gz * n + gy) * n + gx) * a.src.stride + c, c, xmean,
-                             xrstd, xA, xB);
+      const int total = HP << qs;
+      const int q = tid & ((1 << qs) - 1);
+#pragma unroll
+      for (int k = 0; k < NBH; ++k) {
+        if (k * 256 >= total) break;  // uniform
+        const int p = k * 256 + tid;
+        if (p >= total) continue;
+        const int pos = p >> qs;
+        float4 v = hq.v[k];
+        if (PRO != PRO_NONE && ((hq.in >> k) & 1u))
+          v = apply_pro<PRO>(v, quad_h(hq, k), xk, xmean, xrstd, xA, xB);
         if constexpr (MD::BF) {
           // scatter into the dx copies that contain column hx
+          const int hx = pos % HX, hy = (pos / HX) % HY, hz = pos / (HX * HY);
           const float e[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
           for (int dx = 0; dx < NCOPY; ++dx) {
@@ -584,15 +762,15 @@ __global__ __launch_bounds__(256) void k_conv_wgrad(ConvWgrad a) {
             if (tx < 0 || tx >= TX) continue;
             const int base = (hz * HY + hy) * TX + tx;
 #pragma unroll
-            for (int k = 0; k < 4; ++k) {
-              const int o = (dx * ck + 4 * q + k) * PLANE + base;
+            for (int e4 = 0; e4 < 4; ++e4) {
+              const int o = (dx * ck + 4 * q + e4) * PLANE + base;
               if constexpr (MD::SPLIT) {
                 uint16_t hi, lo;
-                split_bf(e[k], hi, lo);
+                split_bf(e[e4], hi, lo);
                 hal[o] = hi;
                 hal_lo[o] = lo;
               } else {
-                hal[o] = f2bf(e[k]);
+                hal[o] = f2bf(e[e4]);
               }
             }
           }
@@ -606,15 +784,14 @@ __global__ __launch_bounds__(256) void k_conv_wgrad(ConvWgrad a) {
       }
     }
     // ---- g tile: BM voxels x 16 output channels (zero outside the grid / cout)
-    for (int p = tid; p < BM * 4; p += 256) {
+#pragma unroll
+    for (int k = 0; k < NBG; ++k) {
+      const int p = k * 256 + tid;
+      if (p >= BM * 4) continue;
       const int v = p >> 2, q = p & 3;
-      const int tz = v / (TY * TX), ty = (v / TX) % TY, tx = v % TX;
-      const int gz = z0 + tz, gy = y0 + ty, gx = x0 + tx;
-      const int co = co0 + 4 * q;
-      float4 val = make_float4(0.f, 0.f, 0.f, 0.f);
-      if (gz < n && gy < n && gx < n && co < a.cout)
-        val = load_src4<GPRO>(a.gsrc, ((size_t)(gz * n + gy) * n + gx) * a.cout + co, co, gmean,
-                              grstd, gA, gB);
+      float4 val = gq.v[k];
+      if (GPRO != PRO_NONE && ((gq.in >> k) & 1u))
+        val = apply_pro<GPRO>(val, quad_h(gq, k), gk, gmean, grstd, gA, gB);
       bacc.x += val.x;
       bacc.y += val.y;
       bacc.z += val.z;
@@ -622,14 +799,14 @@ __global__ __launch_bounds__(256) void k_conv_wgrad(ConvWgrad a) {
       if constexpr (MD::BF) {
         const float e[4] = {val.x, val.y, val.z, val.w};
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
+        for (int e4 = 0; e4 < 4; ++e4) {
           if constexpr (MD::SPLIT) {
             uint16_t h, l;
-            split_bf(e[k], h, l);
-            gs[(4 * q + k) * GP + v] = h;
-            gs_lo[(4 * q + k) * GP + v] = l;
+            split_bf(e[e4], h, l);
+            gs[(4 * q + e4) * GP + v] = h;
+            gs_lo[(4 * q + e4) * GP + v] = l;
           } else {
-            gs[(4 * q + k) * GP + v] = f2bf(e[k]);
+            gs[(4 * q + e4) * GP + v] = f2bf(e[e4]);
           }
         }
       } else {
@@ -641,6 +818,7 @@ __global__ __launch_bounds__(256) void k_conv_wgrad(ConvWgrad a) {
       }
     }
     __syncthreads();
+    if (t + (int)gridDim.x < ntiles) issue(t + gridDim.x);
     // ---- every wave: all column tiles, voxel k-steps ks = wave, wave + 4, ...
 #pragma unroll 2
     for (int ks = wave; ks < NSTEP; ks += 4) {
@@ -664,7 +842,7 @@ __global__ __launch_bounds__(256) void k_conv_wgrad(ConvWgrad a) {
         const int tz = v / (TY * TX), ty = (v / TX) % TY, tx = v % TX;
         const int vp = ((tz * HY + ty) * HX + tx) * ckp;
 #pragma unroll
-        for (int j = 0; j < kWgNg; ++j) B[j] = cval[j] ? hal[vp + coff[j]] : 0.f;
+        for (int j = 0; j < kWgNg; ++j) B[j] = frag<MODE>(hal + vp + coff[j], cval[j]);
       }
 #pragma unroll
       for (int j = 0; j < kWgNg; ++j) {
