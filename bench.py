@@ -6,11 +6,17 @@ loss, J^T, network backward, Adam) over the 32^3 / 928-measurement / 3-level /
 500-iteration fit, so the image after the timed region is compared with the
 stored FP64 oracle image at iteration 500: each precision form is reported
 with its image error, and `value` is the fastest form whose error is within
-its bound (FP32 1e-5, BF16 forms 2e-3).
+its bound (FP32 1e-5, BF16 forms 2e-3).  Each form runs with autotuned conv
+launch shapes inside one captured hipGraph; "plain" is FP32 with the
+heuristic shapes and eager launches.
+
+The other workloads are reported under "configs": 16^3 (50 iterations), 64^3,
+eight 32^3 sequences fitted frame after frame (frames/s) and sixteen uneven
+instances.
 
     python bench.py [--steps 480] [--warmup 20] [--gpus 1]
 
-Prints one JSON line on stdout.
+Prints one JSON line on stdout; progress goes to stderr.
 """
 import argparse
 import json
@@ -28,6 +34,7 @@ HBM_PEAK_GBS = 8000.0
 PEAK_TFLOPS = {"fp32": 157.3, "bf16": 2500.0, "bf16x3": 2500.0}
 ERR_BOUND = {"fp32": 1e-5, "bf16x3": 2e-3, "bf16": 2e-3}
 DTYPE = {"fp32": "f32", "bf16": "bf16", "bf16x3": "bf16x3"}
+M_OF_RINGS = {1: 208, 2: 928}
 
 
 def log(*a):
@@ -37,10 +44,16 @@ def log(*a):
 def golden_image(cfg_name, iters):
     path = os.path.join(ROOT, "tests", "golden", "oracle_%s_%d.npz" % (cfg_name, iters))
     if not os.path.exists(path):
-        return None, None
+        return None
     z = np.load(path)
     cps = list(z["checkpoints"])
-    return z, (z["images"][cps.index(iters)] if iters in cps else None)
+    return z["images"][cps.index(iters)] if iters in cps else None
+
+
+def rel_err(img, ref):
+    if ref is None:
+        return None
+    return float(np.linalg.norm(img - ref) / np.linalg.norm(ref))
 
 
 def conv_flops(n, cin, cout, taps):
@@ -57,12 +70,18 @@ def block_convs(levels, C, n):
     return out
 
 
-def time_form(d2ip, p, cfg, prec, steps, warmup, torch):
-    ctx = d2ip.Context([(cfg["n"], p["J"].shape[0])], [(0, cfg["levels"], cfg["base_ch"])],
-                       precision=prec, graph=True)
-    ctx.load_problem(0, p)
-    ctx.set_adam(lr=cfg["lr"])
-    ctx.run(warmup)
+def tuned(d2ip, at, geos, insts, prec, cache):
+    """Tuning table for this workload and precision (tuned once per run)."""
+    key = (tuple(geos), tuple(insts), prec)
+    if key not in cache:
+        t0 = time.time()
+        cache[key] = at.tune(geos, insts, prec, reps=10)
+        log("  tuned %d conv passes for %s in %.1f s" % (len(cache[key]), prec, time.time() - t0))
+    return cache[key]
+
+
+def timed_run(ctx, steps, torch):
+    """ms of `steps` iterations of every instance (HIP events on the context stream)."""
     torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
@@ -70,10 +89,20 @@ def time_form(d2ip, p, cfg, prec, steps, warmup, torch):
     ctx.run(steps, sync=False)
     e1.record(ctx.stream)
     torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1)
+    return e0.elapsed_time(e1)
+
+
+def single_form(d2ip, at, p, cfg, prec, steps, warmup, torch, graph=True, tune=True, cache=None):
+    geos = [(cfg["n"], p["J"].shape[0])]
+    insts = [(0, cfg["levels"], cfg["base_ch"])]
+    at.set_tuning(tuned(d2ip, at, geos, insts, prec, cache) if tune else [])
+    ctx = d2ip.Context(geos, insts, precision=prec, graph=graph)
+    ctx.load_problem(0, p)
+    ctx.set_adam(lr=cfg["lr"])
+    ctx.run(warmup)
+    ms = timed_run(ctx, steps, torch)
     loss = float(ctx.run(0)[0])
-    img = ctx.read_image(0)
-    return ctx, ms, loss, img
+    return ctx, ms, loss, ctx.read_image(0)
 
 
 def kernel_table(d2ip, ctx, p, cfg, prec):
@@ -126,6 +155,91 @@ def cpu_baseline(p, cfg, budget_s):
                        % (k, dt))
 
 
+def config0(d2ip, at, ts, prec, torch, cache):
+    cfg = ts.CONFIGS["c0"]
+    p = ts.make_problem(cfg["n"], cfg["rings"], cfg["levels"], cfg["base_ch"], cfg["seed"])
+    ctx, ms, loss, img = single_form(d2ip, at, p, cfg, prec, cfg["iters"], 0, torch, cache=cache)
+    ctx.close()
+    return dict(workload=cfg["desc"], form=prec, it_per_s=cfg["iters"] / (ms * 1e-3),
+                image_rel_err=rel_err(img, golden_image("c0", cfg["iters"])))
+
+
+def config2(d2ip, at, ts, prec, torch, cache, steps=40):
+    cfg = ts.CONFIGS["c2"]
+    p = ts.make_problem(cfg["n"], cfg["rings"], cfg["levels"], cfg["base_ch"], cfg["seed"])
+    ctx, ms, loss, img = single_form(d2ip, at, p, cfg, prec, steps, 3, torch, cache=cache)
+    ctx.close()
+    return dict(workload=cfg["desc"], form=prec, it_per_s=steps / (ms * 1e-3), timed_iters=steps,
+                final_loss=loss, image_rel_err=None,
+                note="no stored FP64 oracle trajectory at this size")
+
+
+def config3(d2ip, at, ts, prec, torch, cache, frames=3):
+    """Eight sequences fitted together, frame after frame (TPP): steady-state
+    frames/s over `frames` frames of 50 iterations after a 500-iteration first
+    frame, and the full 100-frame schedule's rate derived from it."""
+    cfg = ts.CONFIGS["c3"]
+    seqs = [ts.make_problem(cfg["n"], cfg["rings"], cfg["levels"], cfg["base_ch"], s,
+                            frames=frames + 1, breathing=True) for s in cfg["seeds"]]
+    M = seqs[0]["J"].shape[0]
+    geos = [(cfg["n"], M)]
+    insts = [(0, cfg["levels"], cfg["base_ch"])] * len(seqs)
+    at.set_tuning(tuned(d2ip, at, geos, [insts[0]], prec, cache))
+    ctx = d2ip.Context(geos, insts, precision=prec, graph=True)
+    ctx.set_geometry(0, seqs[0]["J"], seqs[0]["mask"])
+    for i, p in enumerate(seqs):
+        ctx.load_problem(i, p, set_geometry=False)
+    ctx.set_adam(lr=cfg["lr"])
+    t_first = timed_run(ctx, cfg["iters"], torch)
+    t_later = 0.0
+    for f in range(1, frames + 1):
+        for i, p in enumerate(seqs):
+            ctx.set_frame(i, p["dv"][f])
+            ctx.reset_optimizer(i)
+        t_later += timed_run(ctx, cfg["later_iters"], torch)
+    ctx.close()
+    S = len(seqs)
+    per_frame_ms = t_later / frames
+    total_ms = t_first + (cfg["frames"] - 1) * per_frame_ms
+    return dict(workload=cfg["desc"], form=prec, sequences=S,
+                frames_per_s_steady=S / (per_frame_ms * 1e-3),
+                frames_per_s_schedule=S * cfg["frames"] / (total_ms * 1e-3),
+                first_frame_ms=t_first, later_frame_ms=per_frame_ms,
+                sample="first frame (500 its) + %d frames of 50 its, 8 sequences; the full "
+                       "100-frame rate extrapolates the measured per-frame time" % frames)
+
+
+def config4(d2ip, at, ts, prec, torch, cache, iters=20):
+    cfg = ts.CONFIGS["c4"]
+    geos, insts, probs = [], [], []
+    for it in cfg["instances"]:
+        p = ts.make_problem(it["n"], it["rings"], cfg["levels"], it["base_ch"], it["seed"])
+        g = (it["n"], M_OF_RINGS[it["rings"]])
+        if g not in geos:
+            geos.append(g)
+        insts.append((geos.index(g), cfg["levels"], it["base_ch"]))
+        probs.append(p)
+    table = {}
+    for k in {tuple(i) for i in insts}:
+        for e in tuned(d2ip, at, [geos[k[0]]], [(0, k[1], k[2])], prec, cache):
+            table[tuple(e[f] for f in at.FIELDS)] = e
+    at.set_tuning(list(table.values()))
+    ctx = d2ip.Context(geos, insts, precision=prec, graph=True)
+    done = set()
+    for i, p in enumerate(probs):
+        ctx.load_problem(i, p, set_geometry=insts[i][0] not in done)
+        done.add(insts[i][0])
+    ctx.set_adam(lr=cfg["lr"])
+    ctx.run(2)
+    ms = timed_run(ctx, iters, torch)
+    ctx.close()
+    return dict(workload=cfg["desc"], form=prec, instances=len(insts),
+                batched_it_per_s=iters / (ms * 1e-3),
+                instance_it_per_s=len(insts) * iters / (ms * 1e-3),
+                schedule_s=cfg["iters"] * ms / iters * 1e-3,
+                sample="%d batched iterations timed after 2 warm-up iterations" % iters)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -135,6 +249,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-kernels", action="store_true")
+    ap.add_argument("--no-configs", action="store_true")
     a = ap.parse_args()
     if a.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -143,19 +258,19 @@ def main():
 
     import torch
     import paper_2507_14046_amd as d2ip
+    from paper_2507_14046_amd import autotune as at
     import tseit_synth as ts
 
     cfg = ts.CONFIGS["c1"]
     p = ts.make_problem(cfg["n"], cfg["rings"], cfg["levels"], cfg["base_ch"], cfg["seed"])
     total = a.warmup + a.steps
-    gz, gimg = golden_image("c1", total)
-    forms = {}
-    ctxs = {}
+    gimg = golden_image("c1", total)
+    cache = {}
+    forms, ctxs = {}, {}
     for prec in a.forms.split(","):
-        ctx, ms, loss, img = time_form(d2ip, p, cfg, prec, a.steps, a.warmup, torch)
-        err = None
-        if gimg is not None:
-            err = float(np.linalg.norm(img - gimg) / np.linalg.norm(gimg))
+        ctx, ms, loss, img = single_form(d2ip, at, p, cfg, prec, a.steps, a.warmup, torch,
+                                         cache=cache)
+        err = rel_err(img, gimg)
         forms[prec] = dict(it_per_s=a.steps / (ms * 1e-3), ms_per_step=ms / a.steps,
                            final_loss=loss, image_rel_err_vs_fp64_oracle=err,
                            error_bound=ERR_BOUND[prec],
@@ -163,14 +278,22 @@ def main():
         ctxs[prec] = ctx
         log("form %-7s %9.1f it/s  %.4f ms/it  loss %.4e  image err %s" %
             (prec, forms[prec]["it_per_s"], ms / a.steps, loss, err))
+    ctx, ms, loss, img = single_form(d2ip, at, p, cfg, "fp32", a.steps, a.warmup, torch,
+                                     graph=False, tune=False, cache=cache)
+    plain = dict(it_per_s=a.steps / (ms * 1e-3), ms_per_step=ms / a.steps, final_loss=loss,
+                 image_rel_err_vs_fp64_oracle=rel_err(img, gimg),
+                 note="FP32, heuristic launch shapes, eager launches (no graph)")
+    ctx.close()
+    log("plain fp32     %9.1f it/s" % plain["it_per_s"])
     ok = [f for f in forms if forms[f]["within_bound"]]
-    chosen = max(ok, key=lambda f: forms[f]["it_per_s"]) if ok else "fp32"
-    if chosen not in forms:
-        chosen = list(forms)[0]
+    chosen = max(ok, key=lambda f: forms[f]["it_per_s"]) if ok else (
+        "fp32" if "fp32" in forms else list(forms)[0])
     res = forms[chosen]
 
     roof = None
     if not a.no_kernels:
+        at.set_tuning(tuned(d2ip, at, [(cfg["n"], p["J"].shape[0])],
+                            [(0, cfg["levels"], cfg["base_ch"])], chosen, cache))
         rows = kernel_table(d2ip, ctxs[chosen], p, cfg, chosen)
         for r in rows:
             log("  %-40s %8.4f ms  %9.2f %s  (%.1f%% of %s peak)" %
@@ -181,6 +304,18 @@ def main():
                     ms_per_launch=dom["ms"],
                     kernels={r["kernel"]: dict(ms=r["ms"], achieved=r["achieved"],
                                                unit=r["unit"], frac=r["frac"]) for r in rows})
+    for c in ctxs.values():
+        c.close()
+    configs = {}
+    if not a.no_configs:
+        for name, fn in (("c0", config0), ("c2", config2), ("c3", config3), ("c4", config4)):
+            configs[name] = {}
+            for prec in ("fp32", "bf16"):
+                t0 = time.time()
+                configs[name][prec] = fn(d2ip, at, ts, prec, torch, cache)
+                log("%s %-5s %s (%.0f s)" % (name, prec, json.dumps(configs[name][prec]),
+                                             time.time() - t0))
+        at.set_tuning([])
     cpu = None if a.no_cpu else cpu_baseline(p, cfg, a.cpu_seconds)
     out = {
         "metric": METRIC,
@@ -198,10 +333,13 @@ def main():
         "config": {"workload": "32^3 voxels, 928 measurements (2 rings x 16 electrodes), "
                                "3-level residual U-Net with 16 base channels, 1 frame, "
                                "Adam lr 1e-3, %d iterations" % total,
-                   "form": chosen, "graph": True, "instances": 1},
+                   "form": chosen, "graph": True, "autotuned": True, "instances": 1},
         "image_rel_err": res["image_rel_err_vs_fp64_oracle"],
+        "speedup_vs_plain_fp32": res["it_per_s"] / plain["it_per_s"],
         "frames_per_s_tpp50": res["it_per_s"] / 50.0,
         "forms": forms,
+        "plain_fp32": plain,
+        "configs": configs,
         "roofline": roof,
         "cpu_baseline": cpu,
     }

@@ -192,6 +192,64 @@ d2ip_status d2ip_time_kernel(d2ip_ctx* ctx, int inst, int which, int block, int 
 /* Image of `inst` at its current theta: mask * phi(theta | Z), n^3 FP32 (Eq. (5)). */
 d2ip_status d2ip_read_image(d2ip_ctx* ctx, int inst, float* sigma, int on_device);
 
+/* ---- launch shapes of the convolutions (for autotuning) ----------------
+ * Every 3x3x3 / 1x1x1 convolution of the network (Eq. (3): the prior phi is
+ * built from them) runs three passes: 0 forward, 1 input gradient, 2 weight
+ * gradient.  A pass's launch shape trades parallelism against per-block
+ * work; the plan picks one by a heuristic unless the tuning table holds an
+ * entry for that pass. */
+typedef struct {
+  int tile;  /* voxel tile per block: 0 = 2x4x16, 1 = 1x4x16, 2 = 1x8x8 (z x y x x) */
+  int bn;    /* passes 0/1: output channels per block, 16, 32 or 64 (not 64 with tile 0) */
+  int ck;    /* input channels staged per step: 8, 16 or 32, dividing the pass's input */
+  int split; /* passes 0/1: blocks sharing the channel chunks (split-K; divides
+                the chunk count; 1 for forward 1x1 convs); pass 2: voxel
+                splits, 1..min(64, voxel tiles) */
+} d2ip_conv_shape;
+
+/* One pass of one convolution and its shape.  The convolution is named by
+ * its forward channels: grid n^3, cin inputs (8 for the padded 1-channel
+ * stem), cout outputs, taps 27 or 1.  `prologue` is the operand transform the
+ * pass fuses into its staging: passes 0/1: 0 none, 1 LayerNorm + ReLU of the
+ * input (pass 0), 2 LayerNorm backward of the incoming gradient (pass 1);
+ * pass 2: 3 * (input transform: 0 or 1) + (gradient transform: 0 or 2).
+ * `precision` is a d2ip_precision. */
+typedef struct {
+  int n, cin, cout, taps;
+  int pass;
+  int prologue;
+  int precision;
+  d2ip_conv_shape shape;
+} d2ip_tuning_entry;
+
+/* Replace the process-wide tuning table with `count` entries (0 clears it).
+ * Plans made afterwards (d2ip_workspace_bytes, d2ip_create,
+ * d2ip_check_launches, d2ip_plan_convs) use an entry's shape for every pass
+ * that matches all its key fields.  Every entry is validated first; on
+ * D2IP_EINVAL (the reason in d2ip_last_error) the table is unchanged.  Not
+ * thread-safe with concurrent planning.  Host only. */
+d2ip_status d2ip_set_tuning(const d2ip_tuning_entry* table, int count);
+
+/* The passes of every convolution of instance `inst` of the plan for these
+ * arguments, in schedule order, with the shapes the plan chose.  Writes at
+ * most `cap` entries to `out` (may be NULL with cap 0) and the total to
+ * *count.  Host only. */
+d2ip_status d2ip_plan_convs(const d2ip_geometry_desc* geos, int n_geo,
+                            const d2ip_instance_desc* insts, int n_inst, int precision,
+                            unsigned flags, int inst, d2ip_tuning_entry* out, int cap,
+                            int* count);
+
+/* Device workspace bytes d2ip_time_conv needs for entry `e`.  Host only. */
+d2ip_status d2ip_time_conv_bytes(const d2ip_tuning_entry* e, size_t* out);
+
+/* Time one pass of one convolution with the shape in `e`, in isolation, on
+ * zero-filled operands carved from the caller's device `workspace` (256-byte
+ * aligned, at least d2ip_time_conv_bytes): one untimed launch, then `reps`
+ * launches on `hip_stream` between HIP events; the mean ms per launch goes to
+ * *avg_ms.  The weight-gradient pass times its partial-sum kernel only. */
+d2ip_status d2ip_time_conv(const d2ip_tuning_entry* e, void* workspace, size_t bytes,
+                           void* hip_stream, int reps, double* avg_ms);
+
 #ifdef __cplusplus
 }
 #endif

@@ -29,6 +29,17 @@ class AdamCfg(ctypes.Structure):
                 ("eps", ctypes.c_float)]
 
 
+class ConvShape(ctypes.Structure):
+    _fields_ = [("tile", ctypes.c_int), ("bn", ctypes.c_int), ("ck", ctypes.c_int),
+                ("split", ctypes.c_int)]
+
+
+class TuningEntry(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int), ("cin", ctypes.c_int), ("cout", ctypes.c_int),
+                ("taps", ctypes.c_int), ("pass_", ctypes.c_int), ("prologue", ctypes.c_int),
+                ("precision", ctypes.c_int), ("shape", ConvShape)]
+
+
 class D2ipError(RuntimeError):
     def __init__(self, status, msg):
         super().__init__("%s (%d): %s" % (STATUS_NAMES.get(status, "?"), status, msg))
@@ -62,6 +73,13 @@ SIGNATURES = {
     "d2ip_run": [_vp, _i, ctypes.POINTER(ctypes.c_double)],
     "d2ip_read_image": [_vp, _i, _vp, _i],
     "d2ip_time_kernel": [_vp, _i, _i, _i, _i, ctypes.POINTER(ctypes.c_double)],
+    "d2ip_set_tuning": [ctypes.POINTER(TuningEntry), _i],
+    "d2ip_plan_convs": [ctypes.POINTER(GeometryDesc), _i, ctypes.POINTER(InstanceDesc), _i, _i,
+                        ctypes.c_uint, _i, ctypes.POINTER(TuningEntry), _i,
+                        ctypes.POINTER(ctypes.c_int)],
+    "d2ip_time_conv_bytes": [ctypes.POINTER(TuningEntry), _c_size_p],
+    "d2ip_time_conv": [ctypes.POINTER(TuningEntry), _vp, ctypes.c_size_t, _vp, _i,
+                       ctypes.POINTER(ctypes.c_double)],
 }
 
 _lib = None

@@ -95,6 +95,7 @@ struct Conv {
   bool dgrad = false;
   int n = 0;
   Shape fwd, bwd;          // forward / input-gradient launch shapes
+  int pro_fwd = PRO_NONE, pro_bwd = PRO_NONE, pro_wg = 0;  // fused operand transforms
   int wg_tile = 0, wg_ck = 8, wg_splits = 1;
   long long wg_off = 0, wgb_off = 0;  // partial regions of the weight gradient
 };
@@ -322,8 +323,66 @@ size_t layout(Instance& I) {
   return (size_t)lb.off;
 }
 
+// Process-wide table of tuned launch shapes, consulted by every later plan.
+std::vector<d2ip_tuning_entry> g_tuning;
+
+// Whether `e` describes a launch the kernels support; the reason if not.
+bool shape_ok(const d2ip_tuning_entry& e, std::string* why) {
+  auto no = [&](const char* m) {
+    if (why) *why = m;
+    return false;
+  };
+  const d2ip_conv_shape& sh = e.shape;
+  if (e.n < 1 || e.n > 256) return no("n must be in [1, 256]");
+  if (e.taps != 27 && e.taps != 1) return no("taps must be 27 or 1");
+  if (e.cin < 8 || e.cout < 1 || e.cin > 1024 || e.cout > 1024) return no("bad channel counts");
+  if (e.precision < D2IP_PLAIN_FP32 || e.precision > D2IP_BF16X3_CONV) return no("bad precision");
+  if (sh.tile < TILE_2x4x16 || sh.tile > TILE_1x8x8) return no("tile must be 0, 1 or 2");
+  if (sh.ck != 8 && sh.ck != 16 && sh.ck != 32) return no("ck must be 8, 16 or 32");
+  const int prec = conv_prec(e.precision);
+  if (e.pass == 0 || e.pass == 1) {
+    const int kin = e.pass == 0 ? e.cin : e.cout;
+    if (kin % sh.ck != 0) return no("ck must divide the pass's input channels");
+    if (sh.bn != 16 && sh.bn != 32 && sh.bn != 64) return no("bn must be 16, 32 or 64");
+    if (sh.tile == TILE_2x4x16 && sh.bn == 64) return no("the 2x4x16 tile takes bn <= 32");
+    if (sh.split < 1 || (kin / sh.ck) % sh.split != 0)
+      return no("split must divide the number of channel chunks");
+    if (e.pass == 0 && e.taps == 1 && sh.split != 1)
+      return no("1x1 forward convs run on the side stream without split-K");
+    const bool pro_ok = e.pass == 0 ? (e.prologue == PRO_NONE || e.prologue == PRO_LN_RELU)
+                                    : (e.prologue == PRO_NONE || e.prologue == PRO_LN_BWD);
+    if (!pro_ok || (e.taps == 1 && e.prologue != PRO_NONE)) return no("bad prologue");
+    if (conv_fwd_lds_bytes(sh.tile, e.taps, sh.bn, sh.ck, prec) > kLdsBudget)
+      return no("LDS over budget");
+    return true;
+  }
+  if (e.pass == 2) {
+    if (e.cin % sh.ck != 0) return no("ck must divide the input channels");
+    if (sh.split < 1 || sh.split > 64 || sh.split > conv_tiles(e.n, sh.tile))
+      return no("split must be in [1, min(64, voxel tiles)]");
+    const int xp = e.prologue / 3, gp = e.prologue % 3;
+    if (e.prologue < 0 || xp > PRO_LN_RELU || (gp != PRO_NONE && gp != PRO_LN_BWD) ||
+        (e.taps == 1 && e.prologue != 0))
+      return no("bad prologue");
+    if (conv_wgrad_lds_bytes(sh.tile, e.taps, sh.ck, prec) > kLdsBudget)
+      return no("LDS over budget");
+    return true;
+  }
+  return no("pass must be 0, 1 or 2");
+}
+
+const d2ip_tuning_entry* find_tuned(int n, int cin, int cout, int taps, int pass, int pro,
+                                    int precision) {
+  for (const d2ip_tuning_entry& e : g_tuning)
+    if (e.n == n && e.cin == cin && e.cout == cout && e.taps == taps && e.pass == pass &&
+        e.prologue == pro && e.precision == precision)
+      return &e;
+  return nullptr;
+}
+
 // Launch shapes, packing table and weight-gradient partial regions of a conv.
-void add_conv(Instance& I, Conv& c, int prec, size_t& kpart_max, int& tiles_max) {
+void add_conv(Instance& I, Conv& c, int precision, size_t& kpart_max, int& tiles_max) {
+  const int prec = conv_prec(precision);
   c.wf = I.wtotal;
   I.wtotal += (long long)c.cout * c.taps * c.cin;
   if (c.dgrad) {
@@ -347,10 +406,23 @@ void add_conv(Instance& I, Conv& c, int prec, size_t& kpart_max, int& tiles_max)
   // 1x1 projections run forward on the side stream, concurrently with split-K
   // convs of the main stream: they must not share the split-K scratch
   if (c.taps == 1) c.fwd.ksplit = 1;
+  if (const d2ip_tuning_entry* t = find_tuned(c.n, c.cin, c.cout, c.taps, 0, c.pro_fwd, precision)) {
+    c.fwd.tile = t->shape.tile;
+    c.fwd.bn = t->shape.bn;
+    c.fwd.ck = t->shape.ck;
+    c.fwd.ksplit = t->shape.split;
+  }
   tiles_max = std::max(tiles_max, conv_tiles(c.n, c.fwd.tile) * ((c.cout + c.fwd.bn - 1) / c.fwd.bn));
   if (c.fwd.ksplit > 1) kpart_max = std::max(kpart_max, (size_t)c.fwd.ksplit * V * c.cout);
   if (c.dgrad) {
     c.bwd = choose_shape(c.n, c.cout, c.cin_real, c.taps, prec);
+    if (const d2ip_tuning_entry* t =
+            find_tuned(c.n, c.cin, c.cout, c.taps, 1, c.pro_bwd, precision)) {
+      c.bwd.tile = t->shape.tile;
+      c.bwd.bn = t->shape.bn;
+      c.bwd.ck = t->shape.ck;
+      c.bwd.ksplit = t->shape.split;
+    }
     tiles_max = std::max(tiles_max,
                          conv_tiles(c.n, c.bwd.tile) * ((c.cin_real + c.bwd.bn - 1) / c.bwd.bn));
     if (c.bwd.ksplit > 1) kpart_max = std::max(kpart_max, (size_t)c.bwd.ksplit * V * c.cin_real);
@@ -364,6 +436,11 @@ void add_conv(Instance& I, Conv& c, int prec, size_t& kpart_max, int& tiles_max)
   const int per = (c.cin / c.wg_ck) * conv_wgrad_groups(c.taps, c.wg_ck) * (cout16 / 16);
   const int tiles = conv_tiles(c.n, c.wg_tile);
   c.wg_splits = std::max(1, std::min(std::min(tiles, 64), (512 + per - 1) / per));
+  if (const d2ip_tuning_entry* t = find_tuned(c.n, c.cin, c.cout, c.taps, 2, c.pro_wg, precision)) {
+    c.wg_tile = t->shape.tile;
+    c.wg_ck = t->shape.ck;
+    c.wg_splits = t->shape.split;
+  }
   c.wg_off = I.wg_total;
   I.wg_total += (long long)c.wg_splits * cout16 * c.taps * c.cin;
   c.wgb_off = I.wgb_total;
@@ -462,11 +539,19 @@ void plan(d2ip_ctx& X, const d2ip_geometry_desc* gd, int n_geo, const d2ip_insta
     I.max_pack = 0;
     I.wg_total = 0;
     I.wgb_total = 0;
-    add_conv(I, I.stem, prec, kpart_max, tiles_max);
+    // operand transforms fused into each pass (fixed by the schedule)
+    I.stem.pro_wg = PRO_LN_BWD;
     for (Block& b : I.blocks) {
-      add_conv(I, b.c1, prec, kpart_max, tiles_max);
-      add_conv(I, b.c2, prec, kpart_max, tiles_max);
-      if (b.proj) add_conv(I, b.pj, prec, kpart_max, tiles_max);
+      b.c2.pro_fwd = PRO_LN_RELU;
+      b.c1.pro_bwd = b.c2.pro_bwd = PRO_LN_BWD;
+      b.c1.pro_wg = PRO_LN_BWD;
+      b.c2.pro_wg = 3 * PRO_LN_RELU + PRO_LN_BWD;
+    }
+    add_conv(I, I.stem, X.precision, kpart_max, tiles_max);
+    for (Block& b : I.blocks) {
+      add_conv(I, b.c1, X.precision, kpart_max, tiles_max);
+      add_conv(I, b.c2, X.precision, kpart_max, tiles_max);
+      if (b.proj) add_conv(I, b.pj, X.precision, kpart_max, tiles_max);
     }
     // FP64 partial arena: statistics of every LayerNorm input, LayerNorm
     // backward partials, head gradient and residual sums (offsets in doubles)
@@ -1132,6 +1217,43 @@ d2ip_status repack(d2ip_ctx* X, Instance& I) {
   return D2IP_OK;
 }
 
+// Operand buffers of one standalone conv pass (d2ip_time_conv).
+struct TimeConvBufs {
+  float *x = nullptr, *h = nullptr, *g = nullptr, *y = nullptr, *gamma = nullptr, *beta = nullptr;
+  float *bias = nullptr, *kpart = nullptr, *part = nullptr, *partb = nullptr;
+  void* w = nullptr;
+  double *st = nullptr, *stat = nullptr;
+  int* counters = nullptr;
+};
+
+void carve_time_conv(const d2ip_tuning_entry& e, Carver& cv, TimeConvBufs& b) {
+  const size_t V = (size_t)e.n * e.n * e.n;
+  const int kin = e.pass == 1 ? e.cout : e.cin, kout = e.pass == 1 ? e.cin : e.cout;
+  const int cmax = std::max(e.cin, e.cout);
+  b.x = cv.take<float>(V * kin);
+  b.h = cv.take<float>(V * cmax);
+  b.g = cv.take<float>(V * e.cout);
+  b.y = cv.take<float>(V * kout);
+  b.gamma = cv.take<float>(cmax);
+  b.beta = cv.take<float>(cmax);
+  b.bias = cv.take<float>(kout);
+  b.st = cv.take<double>(2);
+  const int prec = conv_prec(e.precision);
+  const size_t wel = (size_t)kout * e.taps * kin;
+  if (prec == PREC_F32)
+    b.w = cv.take<float>(wel);
+  else
+    b.w = cv.take<uint16_t>((prec == PREC_BF16X3 ? 2 : 1) * wel);
+  const int tiles = conv_tiles(e.n, e.shape.tile) * ((kout + std::max(e.shape.bn, 16) - 1) /
+                                                     std::max(e.shape.bn, 16));
+  b.stat = cv.take<double>(2 * (size_t)tiles);
+  b.counters = cv.take<int>((size_t)tiles + 64);
+  b.kpart = cv.take<float>(std::max<size_t>(1, (size_t)e.shape.split * V * kout));
+  const size_t cout16 = (e.cout + 15) / 16 * 16;
+  b.part = cv.take<float>((size_t)e.shape.split * cout16 * e.taps * e.cin);
+  b.partb = cv.take<float>((size_t)e.shape.split * cout16);
+}
+
 void drop_graph(d2ip_ctx* X) {
   if (X->gexec) hipGraphExecDestroy(X->gexec);
   if (X->graph) hipGraphDestroy(X->graph);
@@ -1188,6 +1310,157 @@ d2ip_status d2ip_check_launches(const d2ip_geometry_desc* geos, int n_geo,
     for (const std::string& e : c.errors) m += e + "; ";
     return fail(D2IP_EINVAL, m);
   }
+  return D2IP_OK;
+}
+
+d2ip_status d2ip_set_tuning(const d2ip_tuning_entry* table, int count) {
+  if (count < 0 || (count > 0 && !table)) return fail(D2IP_EINVAL, "bad tuning table");
+  for (int i = 0; i < count; ++i) {
+    std::string why;
+    if (!shape_ok(table[i], &why))
+      return fail(D2IP_EINVAL, "tuning entry " + std::to_string(i) + ": " + why);
+  }
+  g_tuning.assign(table, table + count);
+  return D2IP_OK;
+}
+
+d2ip_status d2ip_plan_convs(const d2ip_geometry_desc* geos, int n_geo,
+                            const d2ip_instance_desc* insts, int n_inst, int precision,
+                            unsigned flags, int inst, d2ip_tuning_entry* out, int cap,
+                            int* count) {
+  d2ip_status st = check_desc(geos, n_geo, insts, n_inst, precision);
+  if (st != D2IP_OK) return st;
+  if (!count || cap < 0 || (cap > 0 && !out)) return fail(D2IP_EINVAL, "bad output");
+  if (inst < 0 || inst >= n_inst) return fail(D2IP_EINVAL, "bad instance index");
+  d2ip_ctx X;
+  X.precision = precision;
+  X.flags = flags;
+  Carver cv;
+  plan(X, geos, n_geo, insts, n_inst, cv);
+  const Instance& I = X.insts[X.members[inst].first];
+  std::vector<d2ip_tuning_entry> v;
+  auto put = [&](const Conv& c) {
+    d2ip_tuning_entry e;
+    e.n = c.n;
+    e.cin = c.cin;
+    e.cout = c.cout;
+    e.taps = c.taps;
+    e.precision = precision;
+    e.pass = 0;
+    e.prologue = c.pro_fwd;
+    e.shape = d2ip_conv_shape{c.fwd.tile, c.fwd.bn, c.fwd.ck, c.fwd.ksplit};
+    v.push_back(e);
+    if (c.dgrad) {
+      e.pass = 1;
+      e.prologue = c.pro_bwd;
+      e.shape = d2ip_conv_shape{c.bwd.tile, c.bwd.bn, c.bwd.ck, c.bwd.ksplit};
+      v.push_back(e);
+    }
+    e.pass = 2;
+    e.prologue = c.pro_wg;
+    e.shape = d2ip_conv_shape{c.wg_tile, 0, c.wg_ck, c.wg_splits};
+    v.push_back(e);
+  };
+  put(I.stem);
+  for (const Block& b : I.blocks) {
+    put(b.c1);
+    put(b.c2);
+    if (b.proj) put(b.pj);
+  }
+  *count = (int)v.size();
+  for (int i = 0; i < cap && i < (int)v.size(); ++i) out[i] = v[i];
+  return D2IP_OK;
+}
+
+d2ip_status d2ip_time_conv_bytes(const d2ip_tuning_entry* e, size_t* out) {
+  if (!e || !out) return fail(D2IP_EINVAL, "null argument");
+  std::string why;
+  if (!shape_ok(*e, &why)) return fail(D2IP_EINVAL, why);
+  Carver cv;
+  TimeConvBufs b;
+  carve_time_conv(*e, cv, b);
+  *out = cv.off + 256;
+  return D2IP_OK;
+}
+
+d2ip_status d2ip_time_conv(const d2ip_tuning_entry* e, void* workspace, size_t bytes,
+                           void* hip_stream, int reps, double* avg_ms) {
+  if (!e || !workspace || !avg_ms || reps <= 0) return fail(D2IP_EINVAL, "bad argument");
+  if (((uintptr_t)workspace & 255) != 0) return fail(D2IP_EINVAL, "workspace not 256-byte aligned");
+  size_t need = 0;
+  d2ip_status st = d2ip_time_conv_bytes(e, &need);
+  if (st != D2IP_OK) return st;
+  if (bytes < need) return fail(D2IP_ENOMEM, "workspace too small: need " + std::to_string(need));
+  hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
+  Carver cv;
+  cv.base = reinterpret_cast<char*>(workspace);
+  TimeConvBufs b;
+  carve_time_conv(*e, cv, b);
+  HIPCHK(hipMemsetAsync(workspace, 0, cv.off, s));
+  const int prec = conv_prec(e->precision);
+  const int n = e->n;
+  const double cnt = (double)n * n * n;
+  auto launch = [&]() {
+    if (e->pass == 2) {
+      ConvWgrad a;
+      std::memset(&a, 0, sizeof(a));
+      a.src = ConvSrc{b.x, e->cin, e->prologue / 3, PairRef{b.st, 1, cnt * e->cin}, b.gamma,
+                      b.beta, nullptr, PairRef{}};
+      a.gsrc = ConvSrc{b.g, e->cout, e->prologue % 3, PairRef{b.st, 1, cnt * e->cout}, b.gamma,
+                       nullptr, b.h, PairRef{b.st, 1, cnt * e->cout}};
+      a.n = n;
+      a.cin = e->cin;
+      a.cout = e->cout;
+      a.taps = e->taps;
+      a.part = b.part;
+      a.partb = b.partb;
+      a.splits = e->shape.split;
+      a.prec = prec;
+      a.tile = e->shape.tile;
+      a.ck = e->shape.ck;
+      a.batch = 1;
+      conv_wgrad(a, s);
+    } else {
+      const int kin = e->pass == 0 ? e->cin : e->cout, kout = e->pass == 0 ? e->cout : e->cin;
+      ConvFwd a;
+      std::memset(&a, 0, sizeof(a));
+      a.src = ConvSrc{b.x, kin, e->prologue, PairRef{b.st, 1, cnt * kin}, b.gamma, b.beta, b.h,
+                      PairRef{b.st, 1, cnt * kin}};
+      a.n = n;
+      a.cin = kin;
+      a.w = b.w;
+      a.w_lo_off = prec == PREC_BF16X3 ? (long long)kout * e->taps * kin : 0;
+      a.w_rows = kout;
+      a.bias = e->pass == 0 ? b.bias : nullptr;
+      a.cout = kout;
+      a.y = b.y;
+      a.taps = e->taps;
+      a.stat_part = e->pass == 0 ? b.stat : nullptr;
+      a.prec = prec;
+      a.tile = e->shape.tile;
+      a.bn = e->shape.bn;
+      a.ck = e->shape.ck;
+      a.ksplit = e->shape.split;
+      a.kpart = b.kpart;
+      a.counters = b.counters;
+      a.batch = 1;
+      conv_fwd(a, s);
+    }
+  };
+  launch();
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  HIPCHK(hipEventRecord(e0, s));
+  for (int r = 0; r < reps; ++r) launch();
+  HIPCHK(hipEventRecord(e1, s));
+  HIPCHK(hipEventSynchronize(e1));
+  float ms = 0.f;
+  HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  HIPCHK(hipGetLastError());
+  *avg_ms = (double)ms / reps;
   return D2IP_OK;
 }
 

@@ -104,8 +104,36 @@ static int run_case(const std::vector<d2ip_geometry_desc>& G,
   return 0;
 }
 
+// Standalone pass timing and the tuning table over every pass of one plan.
+static int tuning_case() {
+  const d2ip_geometry_desc G[1] = {{16, 208}};
+  const d2ip_instance_desc I[1] = {{0, 3, 8}};
+  int count = 0;
+  CK(d2ip_plan_convs(G, 1, I, 1, D2IP_BF16X3_CONV, 0, 0, nullptr, 0, &count));
+  std::vector<d2ip_tuning_entry> e(count);
+  CK(d2ip_plan_convs(G, 1, I, 1, D2IP_BF16X3_CONV, 0, 0, e.data(), count, &count));
+  for (const d2ip_tuning_entry& t : e) {
+    size_t need = 0;
+    CK(d2ip_time_conv_bytes(&t, &need));
+    char* ws = (char*)aligned_alloc(256, (need + 255) / 256 * 256);
+    double ms = 0.0;
+    int token = 0;
+    EXPECT_ERR(d2ip_time_conv(&t, ws, need - 1, &token, 2, &ms), D2IP_ENOMEM);
+    CK(d2ip_time_conv(&t, ws, need, &token, 2, &ms));
+    free(ws);
+  }
+  CK(d2ip_set_tuning(e.data(), count));
+  d2ip_tuning_entry bad = e[0];
+  bad.shape.ck = 12;
+  EXPECT_ERR(d2ip_set_tuning(&bad, 1), D2IP_EINVAL);
+  CK(d2ip_check_launches(G, 1, I, 1, D2IP_BF16X3_CONV, 1));
+  CK(d2ip_set_tuning(nullptr, 0));
+  printf("ok: tuning, %d passes\n", count);
+  return 0;
+}
+
 int main() {
-  int bad = 0;
+  int bad = tuning_case();
   for (int prec = 0; prec < 3; ++prec)
     for (unsigned fl = 0; fl < 2; ++fl) {
       bad |= run_case({{16, 928}}, {{0, 3, 8}, {0, 3, 8}, {0, 3, 8}}, prec, fl);

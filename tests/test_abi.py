@@ -112,3 +112,50 @@ def test_every_launch_stays_inside_the_workspace(L, name, prec):
     geos, insts = _workload(name)
     for graph in (False, True):
         d2ip.check_launches(geos, insts, prec, graph=graph)
+
+
+def _shape_tables(geos, insts, k):
+    """The k-th table of non-heuristic shapes (same choice as the GPU test)."""
+    from paper_2507_14046_amd import autotune as at
+    at.set_tuning([])
+    passes = at.plan_convs(geos, insts)
+    table, seen = [], set()
+    for j, e in enumerate(passes):
+        cands = [c for c in at.candidates(e) if c != e["shape"]]
+        key = (e["n"], e["cin"], e["cout"], e["taps"], e["pass"], e["prologue"])
+        if cands and key not in seen:
+            seen.add(key)
+            table.append(dict(e, shape=cands[(7 * k + 3 * j) % len(cands)]))
+    return table
+
+
+@pytest.mark.parametrize("geo,inst", [((16, 208), (0, 2, 8)), ((24, 928), (0, 3, 8)),
+                                      ((32, 928), (0, 3, 16))])
+def test_tuning_tables_plan_and_stay_in_bounds(L, geo, inst):
+    from paper_2507_14046_amd import autotune as at
+    import paper_2507_14046_amd as d2ip
+    try:
+        for k in range(3):
+            table = _shape_tables([geo], [inst], k)
+            at.set_tuning(table)
+            got = {(e["n"], e["cin"], e["cout"], e["taps"], e["pass"], e["prologue"]): e["shape"]
+                   for e in at.plan_convs([geo], [inst])}
+            for e in table:
+                key = (e["n"], e["cin"], e["cout"], e["taps"], e["pass"], e["prologue"])
+                assert got[key] == e["shape"]
+            for prec in ("fp32", "bf16x3", "bf16"):
+                d2ip.check_launches([geo], [inst], prec, graph=True)
+    finally:
+        at.set_tuning([])
+
+
+def test_tuning_entry_validation(L):
+    from paper_2507_14046_amd import autotune as at
+    e = at.plan_convs([(32, 928)], [(0, 3, 16)])[2]
+    bad = [dict(tile=0, bn=64, ck=16, split=1), dict(tile=3, bn=16, ck=16, split=1),
+           dict(tile=1, bn=16, ck=12, split=1), dict(tile=1, bn=16, ck=16, split=3),
+           dict(tile=0, bn=32, ck=16, split=1)]  # the last is over the LDS budget
+    for sh in bad:
+        with pytest.raises(Exception):
+            at.set_tuning([dict(e, shape=sh)])
+    assert at.plan_convs([(32, 928)], [(0, 3, 16)])[2]["shape"] == e["shape"]

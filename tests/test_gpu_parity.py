@@ -259,3 +259,58 @@ def test_mixed_groups_and_shared_geometry(lib):
         e = rel(ctx.read_image(i), pr.image(st.theta))
         record("mixed_groups", instance=i, image_rel=e)
         assert e < 1e-5
+
+
+@pytest.mark.parametrize("case", ["n16_L2_C8", "n24_L3_C8"])
+def test_every_launch_shape_family_matches_oracle(lib, probs, case):
+    """Tuned launch shapes (tiles, channel tiles, chunks, split-K, voxel
+    splits) other than the heuristic's give the same gradient: three tables,
+    each choosing for every conv pass a different valid shape."""
+    from paper_2507_14046_amd import autotune as at
+    p = probs[case]
+    geos, insts = [(p["n"], p["J"].shape[0])], [(0, p["levels"], p["base_ch"])]
+    pr = oracle_problem(p)
+    _, gref, _ = pr.loss_and_grad(p["theta0"].astype(np.float64), p["dv"][0].astype(np.float64))
+    passes = at.plan_convs(geos, insts)
+    try:
+        for k in range(3):
+            table, seen = [], set()
+            for j, e in enumerate(passes):
+                cands = [c for c in at.candidates(e) if c != e["shape"]]
+                key = (e["n"], e["cin"], e["cout"], e["taps"], e["pass"], e["prologue"])
+                if cands and key not in seen:
+                    seen.add(key)
+                    table.append(dict(e, shape=cands[(7 * k + 3 * j) % len(cands)]))
+            at.set_tuning(table)
+            lib.check_launches(geos, insts)
+            ctx = make_ctx(lib, [p])
+            ctx.run(1)
+            g = ctx.get_grad(0)
+            record("tuned_shapes", case=case, table=k, grad_rel=rel(g, gref))
+            assert rel(g, gref) < TOL_GRAD["fp32"], (k, rel(g, gref))
+            ctx.close()
+    finally:
+        at.set_tuning([])
+
+
+def test_standalone_conv_timing(lib):
+    from paper_2507_14046_amd import autotune as at
+    passes = at.plan_convs([(16, 208)], [(0, 2, 8)])
+    for e in passes[:6]:
+        ms = at.time_pass(e, e["shape"], reps=3)
+        assert 0.0 < ms < 50.0
+
+
+@pytest.mark.parametrize("graph", [False, True])
+def test_instances_sharing_a_geometry_match_separate(lib, graph):
+    """Two instances on one geometry (each its own launch sequence) give
+    bitwise the results of each run alone."""
+    pa, pb = problem(16, 1, 2, 8, 41), problem(16, 1, 2, 8, 42)
+    both = make_ctx(lib, [pa, pb], graph=graph, shared_geometry=True)
+    l_both = both.run(3)
+    for i, p in enumerate([pa, pb]):
+        one = make_ctx(lib, [p], graph=graph)
+        assert one.run(3)[0] == l_both[i]
+        np.testing.assert_array_equal(one.get_params(0), both.get_params(i))
+        one.close()
+    both.close()

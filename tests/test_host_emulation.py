@@ -48,4 +48,4 @@ def test_host_logic_under_address_sanitizer(tmp_path):
     env = dict(os.environ, ASAN_OPTIONS="detect_leaks=1:abort_on_error=0")
     r = subprocess.run([exe], capture_output=True, text=True, env=env, timeout=600)
     assert r.returncode == 0, (r.stdout[-3000:], r.stderr[-5000:])
-    assert r.stdout.count("ok:") == 18
+    assert r.stdout.count("ok:") == 19
