@@ -250,6 +250,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-kernels", action="store_true")
     ap.add_argument("--no-configs", action="store_true")
+    ap.add_argument("--traffic-probe", type=int, default=0,
+                    help="MiB copied 3 times after the kernel table (counter calibration)")
     a = ap.parse_args()
     if a.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -304,6 +306,14 @@ def main():
                     ms_per_launch=dom["ms"],
                     kernels={r["kernel"]: dict(ms=r["ms"], achieved=r["achieved"],
                                                unit=r["unit"], frac=r["frac"]) for r in rows})
+    if a.traffic_probe > 0:
+        # plain device copies of known size: the scale of the HBM byte counters
+        src = torch.ones(a.traffic_probe << 18, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log("traffic probe: 3 copies of %d MiB" % a.traffic_probe)
     for c in ctxs.values():
         c.close()
     configs = {}
