@@ -93,6 +93,12 @@ def load():
     if not os.path.exists(LIB_PATH):
         raise ImportError("libd2ip.so is not built (run `python -m paper_2507_14046_amd.build` "
                           "or __graft_entry__.build()); there is no fallback path")
+    # PyTorch ships its own HIP runtime: load it first so that the library
+    # binds to the same runtime instance as the tensors and streams it is given
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ctypes.CDLL(LIB_PATH)
     lib.d2ip_last_error.restype = ctypes.c_char_p
     lib.d2ip_last_error.argtypes = []

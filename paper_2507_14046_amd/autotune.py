@@ -7,7 +7,7 @@ launch shape: voxel tile, output-channel tile, staged channel chunk and split
 shape per pass becomes an entry of the process-wide tuning table that later
 plans use (``d2ip_set_tuning``).  Tables are plain JSON lists of entries.
 
-    python -m paper_2507_14046_amd.autotune --workload c1 --out table.json
+    python -m paper_2507_14046_amd.autotune --out paper_2507_14046_amd/tuned_mi355x.json
 """
 import argparse
 import ctypes
@@ -101,20 +101,27 @@ def time_pass(e, shape, reps=20, device=0):
     return ms.value
 
 
-def tune(geometries, instances, precision="fp32", reps=20, log=None):
-    """Tuning entries for every distinct conv pass of the workload."""
+def tune(geometries, instances, precision="fp32", reps=10, log=None, margin=0.97):
+    """Tuning entries for every distinct conv pass of the workload.
+
+    Every valid shape is timed with `reps` launches; the three fastest and
+    the heuristic's shape are timed again with 3 * reps launches, and a shape
+    replaces the heuristic's only if it is faster by more than 1 - margin."""
     seen = {}
-    set_tuning([])  # time the heuristic's choice as the baseline
+    set_tuning([])  # the heuristic's choice is the baseline
     for i in range(len(instances)):
         for e in plan_convs(geometries, instances, precision, inst=i):
             seen.setdefault(_key(e), e)
     table = []
     for key, e in seen.items():
-        base = time_pass(e, e["shape"], reps)
+        first = sorted(((time_pass(e, sh, reps), i, sh) for i, sh in enumerate(candidates(e))),
+                       key=lambda t: (t[0], t[1]))
+        finals = [sh for _, _, sh in first[:3]]
+        base = time_pass(e, e["shape"], 3 * reps)
         best, best_ms = e["shape"], base
-        for sh in candidates(e):
-            ms = time_pass(e, sh, reps)
-            if ms < best_ms:
+        for sh in finals:
+            ms = time_pass(e, sh, 3 * reps)
+            if ms < margin * base and ms < best_ms:
                 best, best_ms = sh, ms
         if log:
             log("n=%-3d %3d->%-3d taps %2d pass %d pro %d: %.4f ms -> %.4f ms %s"
@@ -122,6 +129,17 @@ def tune(geometries, instances, precision="fp32", reps=20, log=None):
                    best_ms, best))
         table.append(dict(e, shape=best, ms=best_ms, heuristic_ms=base))
     return table
+
+
+def merge(*tables):
+    """One table from several (the first entry of a key wins)."""
+    out, keys = [], set()
+    for t in tables:
+        for e in t:
+            if _key(e) not in keys:
+                keys.add(_key(e))
+                out.append(e)
+    return out
 
 
 def save(table, path):
@@ -151,17 +169,36 @@ def workload(name):
     return [(c["n"], M[c["rings"]])], [(0, c["levels"], c["base_ch"])]
 
 
+WORKLOADS = ("c0", "c1", "c2", "c3", "c4")
+PRECISIONS = ("fp32", "bf16x3", "bf16")
+
+
+def tune_all(workloads=WORKLOADS, precisions=PRECISIONS, reps=10, log=None):
+    """One table for every conv pass of the named workloads and precisions."""
+    tables = []
+    for w in workloads:
+        geos, insts = workload(w)
+        for prec in precisions:
+            for k in sorted({tuple(i) for i in insts}):
+                tables.append(tune([geos[k[0]]], [(0, k[1], k[2])], prec, reps, log))
+    return merge(*tables)
+
+
+def default_table_path():
+    return os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned_mi355x.json")
+
+
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--workload", default="c1")
-    ap.add_argument("--precision", default="fp32")
-    ap.add_argument("--reps", type=int, default=20)
+    ap.add_argument("--workload", default="all", help="c0..c4 or all")
+    ap.add_argument("--precision", default="all")
+    ap.add_argument("--reps", type=int, default=10)
     ap.add_argument("--out", required=True)
     a = ap.parse_args()
-    geos, insts = workload(a.workload)
-    table = tune(geos, insts, a.precision, a.reps,
-                 log=lambda m: print(m, file=sys.stderr, flush=True))
-    save(table, a.out)
+    log = lambda m: print(m, file=sys.stderr, flush=True)
+    ws = WORKLOADS if a.workload == "all" else (a.workload,)
+    ps = PRECISIONS if a.precision == "all" else (a.precision,)
+    save(tune_all(ws, ps, a.reps, log), a.out)
 
 
 if __name__ == "__main__":

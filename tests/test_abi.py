@@ -159,3 +159,21 @@ def test_tuning_entry_validation(L):
         with pytest.raises(Exception):
             at.set_tuning([dict(e, shape=sh)])
     assert at.plan_convs([(32, 928)], [(0, 3, 16)])[2]["shape"] == e["shape"]
+
+
+def test_stored_tuning_table_plans_every_workload(L):
+    """The chip's stored table is valid and keeps every launch in bounds."""
+    import os
+    from paper_2507_14046_amd import autotune as at
+    import paper_2507_14046_amd as d2ip
+    path = at.default_table_path()
+    if not os.path.exists(path):
+        pytest.skip("no stored tuning table")
+    try:
+        at.set_tuning(at.load_table(path))
+        for w in at.WORKLOADS:
+            geos, insts = at.workload(w)
+            for prec in at.PRECISIONS:
+                d2ip.check_launches(geos, insts, prec, graph=True)
+    finally:
+        at.set_tuning([])

@@ -314,3 +314,28 @@ def test_instances_sharing_a_geometry_match_separate(lib, graph):
         np.testing.assert_array_equal(one.get_params(0), both.get_params(i))
         one.close()
     both.close()
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_stored_tuning_table_matches_oracle(lib, prec):
+    """The chip's stored tuning table (the bench's launch shapes) on the
+    full-size 32^3 workload: one-iteration gradient against the oracle."""
+    import os
+    from paper_2507_14046_amd import autotune as at
+    path = at.default_table_path()
+    if not os.path.exists(path):
+        pytest.skip("no stored tuning table")
+    c = ts.CONFIGS["c1"]
+    p = problem(c["n"], c["rings"], c["levels"], c["base_ch"], c["seed"])
+    pr = oracle_problem(p)
+    _, gref, _ = pr.loss_and_grad(p["theta0"].astype(np.float64), p["dv"][0].astype(np.float64))
+    try:
+        at.set_tuning(at.load_table(path))
+        ctx = make_ctx(lib, [p], precision=prec, graph=True)
+        ctx.run(1)
+        g = ctx.get_grad(0)
+        record("stored_table_32cubed", prec=prec, grad_rel=rel(g, gref))
+        assert rel(g, gref) < TOL_GRAD[prec]
+        ctx.close()
+    finally:
+        at.set_tuning([])
