@@ -250,6 +250,69 @@ d2ip_status d2ip_time_conv_bytes(const d2ip_tuning_entry* e, size_t* out);
 d2ip_status d2ip_time_conv(const d2ip_tuning_entry* e, void* workspace, size_t bytes,
                            void* hip_stream, int reps, double* avg_ms);
 
+/* ---- standalone operators --------------------------------------------
+ * The building blocks of the prior (Sec. III-D, Eq. (3)) and of the data term
+ * (Eqs. (1), (4)) on caller buffers, for composing the network in a framework
+ * with its own autograd.  They run the fitting iteration's kernels.  All
+ * tensors are device pointers to FP32 (BF16 forms round the conv operands
+ * internally); activations are channels-last: x[v][c] with v = (z*n + y)*n + x
+ * over an n^3 grid.  Each call enqueues on `hip_stream` and returns; buffers
+ * must stay alive until the stream passes that point.  `workspace` (device,
+ * 256-byte aligned, at least the matching *_bytes) is scratch owned by the
+ * caller; one workspace must not be used by two calls in flight at once.
+ * These calls upload small tables with hipMemcpyAsync and clear counters with
+ * hipMemsetAsync: they are not meant for stream capture. */
+
+/* Workspace bytes of d2ip_op_conv3d_forward / _backward.  cin and cout
+ * multiples of 8 in [8, 1024], taps 27 (3x3x3, zero padding) or 1. */
+d2ip_status d2ip_op_conv3d_bytes(int n, int cin, int cout, int taps, int precision, size_t* out);
+
+/* y[v][co] = b[co] + sum_{tap, ci} w[co][ci][tap] x[v + offset(tap)][ci]
+ * (cross-correlation, zero padding; w in the canonical [cout][cin][kz][ky][kx]
+ * order, b may be NULL). */
+d2ip_status d2ip_op_conv3d_forward(const float* x, const float* w, const float* b, float* y, int n,
+                                   int cin, int cout, int taps, int precision, void* workspace,
+                                   size_t bytes, void* hip_stream);
+
+/* Gradients of that convolution given gy = dL/dy: gx = dL/dx (input
+ * gradient: the flipped, transposed convolution), gw = dL/dw (canonical
+ * order) and gb = dL/db; any of the three outputs may be NULL.  Sums over
+ * voxels are reduced in a fixed order (deterministic). */
+d2ip_status d2ip_op_conv3d_backward(const float* x, const float* w, const float* gy, float* gx,
+                                    float* gw, float* gb, int n, int cin, int cout, int taps,
+                                    int precision, void* workspace, size_t bytes,
+                                    void* hip_stream);
+
+/* Workspace bytes of the LayerNorm + ReLU operators (C a power of two in
+ * [4, 256]). */
+d2ip_status d2ip_op_ln_relu_bytes(int n, int C, size_t* out);
+
+/* y = relu(gamma_c * (x - mean) / sqrt(var + 1e-5) + beta_c + skip), with
+ * mean and (biased) variance over all n^3 x C values of x; skip may be NULL. */
+d2ip_status d2ip_op_ln_relu_forward(const float* x, const float* gamma, const float* beta,
+                                    const float* skip, float* y, int n, int C, void* workspace,
+                                    size_t bytes, void* hip_stream);
+
+/* Backward of d2ip_op_ln_relu_forward given its input x, output y and
+ * gy = dL/dy: gx = dL/dx, gskip = dL/dskip (the ReLU-masked gy) and
+ * dgamma_dbeta = [dL/dgamma (C), dL/dbeta (C)]; outputs may be NULL. */
+d2ip_status d2ip_op_ln_relu_backward(const float* x, const float* y, const float* gamma,
+                                     const float* gy, float* gx, float* gskip,
+                                     float* dgamma_dbeta, int n, int C, void* workspace,
+                                     size_t bytes, void* hip_stream);
+
+/* p = J sigma for a dense row-major M x Q J (Eq. (1)); Q a multiple of 4. */
+d2ip_status d2ip_op_j_forward(const float* J, const float* sigma, float* p, int M, int Q,
+                              void* hip_stream);
+
+/* Workspace bytes of d2ip_op_jt. */
+d2ip_status d2ip_op_jt_bytes(int M, int Q, size_t* out);
+
+/* out = J^T g (Q values), the adjoint of d2ip_op_j_forward, summed over rows
+ * in a fixed order. */
+d2ip_status d2ip_op_jt(const float* J, const float* g, float* out, int M, int Q, void* workspace,
+                       size_t bytes, void* hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

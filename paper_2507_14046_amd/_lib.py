@@ -80,6 +80,18 @@ SIGNATURES = {
     "d2ip_time_conv_bytes": [ctypes.POINTER(TuningEntry), _c_size_p],
     "d2ip_time_conv": [ctypes.POINTER(TuningEntry), _vp, ctypes.c_size_t, _vp, _i,
                        ctypes.POINTER(ctypes.c_double)],
+    # standalone operators
+    "d2ip_op_conv3d_bytes": [_i, _i, _i, _i, _i, _c_size_p],
+    "d2ip_op_conv3d_forward": [_vp, _vp, _vp, _vp, _i, _i, _i, _i, _i, _vp, ctypes.c_size_t, _vp],
+    "d2ip_op_conv3d_backward": [_vp, _vp, _vp, _vp, _vp, _vp, _i, _i, _i, _i, _i, _vp,
+                                ctypes.c_size_t, _vp],
+    "d2ip_op_ln_relu_bytes": [_i, _i, _c_size_p],
+    "d2ip_op_ln_relu_forward": [_vp, _vp, _vp, _vp, _vp, _i, _i, _vp, ctypes.c_size_t, _vp],
+    "d2ip_op_ln_relu_backward": [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _i, _i, _vp, ctypes.c_size_t,
+                                 _vp],
+    "d2ip_op_j_forward": [_vp, _vp, _vp, _i, _i, _vp],
+    "d2ip_op_jt_bytes": [_i, _i, _c_size_p],
+    "d2ip_op_jt": [_vp, _vp, _vp, _i, _i, _vp, ctypes.c_size_t, _vp],
 }
 
 _lib = None

@@ -435,7 +435,7 @@ void add_conv(Instance& I, Conv& c, int precision, size_t& kpart_max, int& tiles
   const int cout16 = (c.cout + 15) / 16 * 16;
   const int per = (c.cin / c.wg_ck) * conv_wgrad_groups(c.taps, c.wg_ck) * (cout16 / 16);
   const int tiles = conv_tiles(c.n, c.wg_tile);
-  c.wg_splits = std::max(1, std::min(std::min(tiles, 64), (512 + per - 1) / per));
+  c.wg_splits = std::max(1, std::min(std::min(tiles, 64), (512 + per - 1) / per));  // ~512 blocks
   if (const d2ip_tuning_entry* t = find_tuned(c.n, c.cin, c.cout, c.taps, 2, c.pro_wg, precision)) {
     c.wg_tile = t->shape.tile;
     c.wg_ck = t->shape.ck;
@@ -461,6 +461,29 @@ void add_conv(Instance& I, Conv& c, int precision, size_t& kpart_max, int& tiles
 }
 
 }  // namespace
+
+namespace d2ip {
+d2ip_status api_fail(d2ip_status s, const std::string& m) { return fail(s, m); }
+
+void default_conv_shape(int n, int cin, int cout, int taps, int prec, int* tile, int* bn, int* ck,
+                        int* ksplit) {
+  const Shape sh = choose_shape(n, cin, cout, taps, prec);
+  *tile = sh.tile;
+  *bn = sh.bn;
+  *ck = sh.ck;
+  *ksplit = sh.ksplit;
+}
+
+int default_wgrad_splits(int n, int cin, int cout, int taps, int tile, int ck) {
+  const int cout16 = (cout + 15) / 16 * 16;
+  const int per = (cin / ck) * conv_wgrad_groups(taps, ck) * (cout16 / 16);
+  const int tiles = conv_tiles(n, tile);
+  return std::max(1, std::min(std::min(tiles, 64), (512 + per - 1) / per));
+}
+
+int default_tile(int n) { return pick_tile(n); }
+int default_ck(int cin) { return largest_ck(cin); }
+}  // namespace d2ip
 
 struct d2ip_ctx {
   int precision = D2IP_PLAIN_FP32;

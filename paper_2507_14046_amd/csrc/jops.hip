@@ -267,6 +267,57 @@ __global__ void k_pack_weights(const ConvPack* __restrict__ packs, const float* 
   }
 }
 
+// Dense J products of the standalone operators (J is M x Q row-major FP32,
+// Q a multiple of 4).  p[m] = sum_q J[m][q] sigma[q]: one block per row,
+// fixed-order block reduction.
+__global__ __launch_bounds__(256) void k_jv_dense(const float* J, int M, int Q, const float* sig,
+                                                  float* p) {
+  __shared__ double sh[8];
+  const float4* r = reinterpret_cast<const float4*>(J + (size_t)blockIdx.x * Q);
+  const float4* s4 = reinterpret_cast<const float4*>(sig);
+  float acc = 0.f;
+  for (int q = threadIdx.x; q < Q / 4; q += 256) {
+    const float4 a = r[q], b = s4[q];
+    acc += a.x * b.x + a.y * b.y + a.z * b.z + a.w * b.w;
+  }
+  const double t = block_sum((double)acc, sh);
+  if (threadIdx.x == 0) p[blockIdx.x] = (float)t;
+}
+
+// part[rs][q] = sum over rows m = rs, rs + RS, ... of J[m][q] g[m] (4 columns
+// per thread, rows in order); k_jt_sum adds the RS slices in order.
+constexpr int kJtSlices = 8;
+__global__ __launch_bounds__(256) void k_jt_dense(const float* J, int M, int Q, const float* g,
+                                                  float* part) {
+  const int q4 = blockIdx.x * 256 + threadIdx.x;
+  if (q4 * 4 >= Q) return;
+  const int rs = blockIdx.y;
+  float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+  for (int m = rs; m < M; m += kJtSlices) {
+    const float4 j = reinterpret_cast<const float4*>(J + (size_t)m * Q)[q4];
+    const float gm = g[m];
+    acc.x += j.x * gm;
+    acc.y += j.y * gm;
+    acc.z += j.z * gm;
+    acc.w += j.w * gm;
+  }
+  reinterpret_cast<float4*>(part + (size_t)rs * Q)[q4] = acc;
+}
+
+__global__ void k_jt_sum(const float* part, int Q, float* out) {
+  const int q4 = blockIdx.x * 256 + threadIdx.x;
+  if (q4 * 4 >= Q) return;
+  float4 acc = reinterpret_cast<const float4*>(part)[q4];
+  for (int rs = 1; rs < kJtSlices; ++rs) {
+    const float4 v = reinterpret_cast<const float4*>(part + (size_t)rs * Q)[q4];
+    acc.x += v.x;
+    acc.y += v.y;
+    acc.z += v.z;
+    acc.w += v.w;
+  }
+  reinterpret_cast<float4*>(out)[q4] = acc;
+}
+
 inline int grid_for(size_t work) {
   size_t b = (work + 255) / 256;
   if (b > 8192) b = 8192;
@@ -334,6 +385,19 @@ void pack_weights(const ConvPack* packs, int npacks, int max_elems, const float*
   if (grid.x > 1024) grid.x = 1024;
   hipLaunchKernelGGL(k_pack_weights, grid, dim3(256), 0, s, packs, theta, wf32, wbf16, lo_off, it,
                      rsum, nrs, M, istride);
+}
+
+void jv_dense(const float* J, int M, int Q, const float* sigma, float* p, hipStream_t s) {
+  hipLaunchKernelGGL(k_jv_dense, dim3(M), dim3(256), 0, s, J, M, Q, sigma, p);
+}
+
+size_t jt_dense_scratch(int Q) { return (size_t)kJtSlices * Q; }
+
+void jt_dense(const float* J, int M, int Q, const float* g, float* part, float* out,
+              hipStream_t s) {
+  const int bx = (Q / 4 + 255) / 256;
+  hipLaunchKernelGGL(k_jt_dense, dim3(bx, kJtSlices), dim3(256), 0, s, J, M, Q, g, part);
+  hipLaunchKernelGGL(k_jt_sum, dim3(bx), dim3(256), 0, s, part, Q, out);
 }
 
 }  // namespace d2ip

@@ -192,4 +192,21 @@ void pack_weights(const ConvPack* packs, int npacks, int max_elems, const float*
                   const double* rsum, int nrs, int M, int batch, long long istride,
                   hipStream_t s);
 
+// ---- standalone operators (op-level C-ABI) ----
+int block_stats_blocks(size_t n);
+// part[b] = (sum, sum of squares) of a contiguous range of x (FP64).
+void block_stats(const float* x, size_t n, double* part, hipStream_t s);
+// gx = rstd * (gamma_c * gz - A - xhat * B) (LayerNorm input gradient).
+void ln_dx(const float* gz, const float* h, PairRef st, PairRef bw, const float* gamma, float* gx,
+           size_t V, int C, hipStream_t s);
+// p = J sigma and out = J^T g for a dense row-major M x Q J (Q % 4 == 0).
+void jv_dense(const float* J, int M, int Q, const float* sigma, float* p, hipStream_t s);
+size_t jt_dense_scratch(int Q);  // floats of `part`
+void jt_dense(const float* J, int M, int Q, const float* g, float* part, float* out,
+              hipStream_t s);
+// The launch shape the plan's heuristic picks for a forward / input-gradient
+// pass with `cin` inputs and `cout` outputs (precision: PREC_*).
+void default_conv_shape(int n, int cin, int cout, int taps, int prec, int* tile, int* bn, int* ck,
+                        int* ksplit);
+
 }  // namespace d2ip

@@ -248,6 +248,46 @@ inline int grid_for(size_t work, int per_thread = 1) {
   return (int)b;
 }
 
+// Per-block FP64 (sum, sum of squares) partials of x[0..n): block b covers a
+// contiguous range, so the partials (and any fixed-order sum of them) are
+// run-to-run identical.  The statistics a standalone LayerNorm needs.
+__global__ __launch_bounds__(256) void k_block_stats(const float* x, size_t n, size_t per,
+                                                     double* part) {
+  __shared__ double sh[8];
+  const size_t lo = blockIdx.x * per, hi = min(n, lo + per);
+  double s1 = 0.0, s2 = 0.0;
+  for (size_t i = lo + threadIdx.x; i < hi; i += 256) {
+    const double v = x[i];
+    s1 += v;
+    s2 += v * v;
+  }
+  s1 = block_sum(s1, sh);
+  s2 = block_sum(s2, sh);
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = s1;
+    part[2 * blockIdx.x + 1] = s2;
+  }
+}
+
+// LayerNorm input gradient: gx = rstd * (gamma_c * gz - A - xhat * B), with
+// the statistics of h and the coefficients (A, B) reduced from partials.
+__global__ void k_ln_dx(const float4* gz, const float4* h, PairRef st, PairRef bw,
+                        const float* gamma, float4* gx, size_t n4, int C) {
+  const LnStat s = stat_of(st);
+  const LnBwd k = coef_of(bw);
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n4;
+       i += (size_t)gridDim.x * blockDim.x) {
+    const int c = (int)((i * 4) % C);
+    const float4 g = gz[i], x = h[i];
+    float4 o;
+    o.x = s.rstd * (gamma[c + 0] * g.x - k.A - ((x.x - s.mean) * s.rstd) * k.B);
+    o.y = s.rstd * (gamma[c + 1] * g.y - k.A - ((x.y - s.mean) * s.rstd) * k.B);
+    o.z = s.rstd * (gamma[c + 2] * g.z - k.A - ((x.z - s.mean) * s.rstd) * k.B);
+    o.w = s.rstd * (gamma[c + 3] * g.w - k.A - ((x.w - s.mean) * s.rstd) * k.B);
+    gx[i] = o;
+  }
+}
+
 }  // namespace
 
 void ln_apply(const float* h, PairRef st, const float* g, const float* b, const float* skip,
@@ -326,6 +366,26 @@ void pool_bwd_add(const float* gx, const float* add, int n, int C, float* gy, in
 
 void pad_input(const float* z, size_t V, float* zp, hipStream_t s) {
   hipLaunchKernelGGL(k_pad_input, dim3(grid_for(V * 8)), dim3(256), 0, s, z, V, zp);
+}
+
+int block_stats_blocks(size_t n) {
+  size_t b = (n + 8191) / 8192;
+  if (b > 1024) b = 1024;
+  return (int)(b < 1 ? 1 : b);
+}
+
+void block_stats(const float* x, size_t n, double* part, hipStream_t s) {
+  const int nb = block_stats_blocks(n);
+  const size_t per = (n + nb - 1) / nb;
+  hipLaunchKernelGGL(k_block_stats, dim3(nb), dim3(256), 0, s, x, n, per, part);
+}
+
+void ln_dx(const float* gz, const float* h, PairRef st, PairRef bw, const float* gamma, float* gx,
+           size_t V, int C, hipStream_t s) {
+  const size_t n4 = V * C / 4;
+  hipLaunchKernelGGL(k_ln_dx, dim3(grid_for(n4)), dim3(256), 0, s,
+                     reinterpret_cast<const float4*>(gz), reinterpret_cast<const float4*>(h), st,
+                     bw, gamma, reinterpret_cast<float4*>(gx), n4, C);
 }
 
 }  // namespace d2ip

@@ -1,0 +1,390 @@
+// Standalone operators of the C-ABI: one convolution (forward, input and
+// weight gradients), LayerNorm + ReLU (forward and backward) and the dense J
+// products, on caller buffers and the caller's stream.  They run the same
+// kernels as the fitting iteration and let a framework compose the network
+// with its own autograd.
+#include <algorithm>
+#include <cstring>
+#include <string>
+
+#include "d2ip.h"
+#include "kernels.h"
+
+namespace d2ip {
+d2ip_status api_fail(d2ip_status s, const std::string& m);
+int default_wgrad_splits(int n, int cin, int cout, int taps, int tile, int ck);
+int default_tile(int n);
+int default_ck(int cin);
+}  // namespace d2ip
+
+using namespace d2ip;
+
+namespace {
+
+#define OPCHK(expr)                                                                      \
+  do {                                                                                   \
+    hipError_t e_ = (expr);                                                              \
+    if (e_ != hipSuccess)                                                                \
+      return api_fail(D2IP_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_));    \
+  } while (0)
+
+// Carves 256-byte aligned pieces off a workspace (sizes only when base is null).
+struct Piece {
+  char* base = nullptr;
+  size_t off = 0;
+  template <class T>
+  T* take(size_t count) {
+    off = (off + 255) & ~size_t(255);
+    T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+    off += count * sizeof(T);
+    return p;
+  }
+};
+
+int prec_of(int precision) {
+  return precision == D2IP_BF16_CONV ? PREC_BF16 : precision == D2IP_BF16X3_CONV ? PREC_BF16X3
+                                                                                 : PREC_F32;
+}
+
+// Launch shapes and scratch of one convolution.
+struct ConvOp {
+  int n = 0, cin = 0, cout = 0, taps = 0, prec = PREC_F32;
+  size_t V = 0;
+  int f_tile, f_bn, f_ck, f_split;  // forward
+  int d_tile, d_bn, d_ck, d_split;  // input gradient
+  int w_tile, w_ck, w_split;        // weight gradient
+  ConvPack* pack = nullptr;
+  GradSeg* seg = nullptr;
+  float* wf32 = nullptr;
+  uint16_t* wbf16 = nullptr;
+  long long wtotal = 0;
+  float *kpart = nullptr, *part = nullptr, *partb = nullptr, *grad = nullptr;
+  int* counters = nullptr;
+};
+
+d2ip_status conv_check(int n, int cin, int cout, int taps, int precision) {
+  if (n < 1 || n > 256) return api_fail(D2IP_EINVAL, "n must be in [1, 256]");
+  if (taps != 27 && taps != 1) return api_fail(D2IP_EINVAL, "taps must be 27 or 1");
+  if (cin < 8 || cout < 8 || cin % 8 || cout % 8 || cin > 1024 || cout > 1024)
+    return api_fail(D2IP_EINVAL, "cin and cout must be multiples of 8 in [8, 1024]");
+  if (precision < D2IP_PLAIN_FP32 || precision > D2IP_BF16X3_CONV)
+    return api_fail(D2IP_EINVAL, "unknown precision");
+  return D2IP_OK;
+}
+
+void conv_plan(ConvOp& c, int n, int cin, int cout, int taps, int precision, Piece& w) {
+  c.n = n;
+  c.cin = cin;
+  c.cout = cout;
+  c.taps = taps;
+  c.prec = prec_of(precision);
+  c.V = (size_t)n * n * n;
+  default_conv_shape(n, cin, cout, taps, c.prec, &c.f_tile, &c.f_bn, &c.f_ck, &c.f_split);
+  default_conv_shape(n, cout, cin, taps, c.prec, &c.d_tile, &c.d_bn, &c.d_ck, &c.d_split);
+  c.w_tile = default_tile(n);
+  c.w_ck = default_ck(cin);
+  while (c.w_ck > 8 && conv_wgrad_lds_bytes(c.w_tile, taps, c.w_ck, c.prec) > 60 * 1024)
+    c.w_ck >>= 1;
+  c.w_split = default_wgrad_splits(n, cin, cout, taps, c.w_tile, c.w_ck);
+  const size_t wel = (size_t)cout * taps * cin;
+  c.wtotal = (long long)(2 * wel);  // forward packing, then input-gradient packing
+  c.pack = w.take<ConvPack>(1);
+  c.seg = w.take<GradSeg>(1);
+  if (c.prec == PREC_F32)
+    c.wf32 = w.take<float>(c.wtotal);
+  else
+    c.wbf16 = w.take<uint16_t>((c.prec == PREC_BF16X3 ? 2 : 1) * c.wtotal);
+  const size_t kp = std::max((size_t)c.f_split * c.V * cout, (size_t)c.d_split * c.V * cin);
+  c.kpart = w.take<float>(std::max<size_t>(1, kp));
+  const int tf = conv_tiles(n, c.f_tile) * ((cout + c.f_bn - 1) / c.f_bn);
+  const int td = conv_tiles(n, c.d_tile) * ((cin + c.d_bn - 1) / c.d_bn);
+  c.counters = w.take<int>((size_t)std::max(tf, td) + 64);
+  const size_t cout16 = (cout + 15) / 16 * 16;
+  c.part = w.take<float>((size_t)c.w_split * cout16 * taps * cin);
+  c.partb = w.take<float>((size_t)c.w_split * cout16);
+  c.grad = w.take<float>(wel + cout);
+}
+
+ConvPack make_pack(const ConvOp& c) {
+  ConvPack p;
+  std::memset(&p, 0, sizeof(p));
+  p.th_off = 0;
+  p.cout = c.cout;
+  p.cin_real = c.cin;
+  p.cin = c.cin;
+  p.taps = c.taps;
+  p.need_dgrad = 1;
+  p.wf_off = 0;
+  p.wd_off = (long long)c.cout * c.taps * c.cin;
+  return p;
+}
+
+// Upload the packing table (and zero the split-K counters) once per call and
+// pack w into the forward and input-gradient layouts.
+d2ip_status conv_prepare(ConvOp& c, const float* w, hipStream_t s) {
+  const ConvPack p = make_pack(c);
+  OPCHK(hipMemcpyAsync(c.pack, &p, sizeof(p), hipMemcpyHostToDevice, s));
+  const int tf = conv_tiles(c.n, c.f_tile) * ((c.cout + c.f_bn - 1) / c.f_bn);
+  const int td = conv_tiles(c.n, c.d_tile) * ((c.cin + c.d_bn - 1) / c.d_bn);
+  OPCHK(hipMemsetAsync(c.counters, 0, ((size_t)std::max(tf, td) + 64) * sizeof(int), s));
+  pack_weights(c.pack, 1, c.cout * c.cin * c.taps, w, c.wf32, c.wbf16,
+               c.prec == PREC_BF16X3 ? c.wtotal : 0, nullptr, nullptr, 0, 1, 1, 0, s);
+  return D2IP_OK;
+}
+
+ConvSrc plain(const float* x, int stride) {
+  ConvSrc s;
+  std::memset(&s, 0, sizeof(s));
+  s.x = x;
+  s.stride = stride;
+  s.prologue = PRO_NONE;
+  return s;
+}
+
+ConvFwd fwd_of(const ConvOp& c, bool dgrad, const float* src, const float* bias, float* y) {
+  ConvFwd a;
+  std::memset(&a, 0, sizeof(a));
+  const int kin = dgrad ? c.cout : c.cin, kout = dgrad ? c.cin : c.cout;
+  const long long off = dgrad ? (long long)c.cout * c.taps * c.cin : 0;
+  a.src = plain(src, kin);
+  a.n = c.n;
+  a.cin = kin;
+  a.w = c.prec == PREC_F32 ? (const void*)(c.wf32 + off) : (const void*)(c.wbf16 + off);
+  a.w_lo_off = c.prec == PREC_BF16X3 ? c.wtotal : 0;
+  a.w_rows = kout;
+  a.bias = bias;
+  a.cout = kout;
+  a.y = y;
+  a.taps = c.taps;
+  a.prec = c.prec;
+  a.tile = dgrad ? c.d_tile : c.f_tile;
+  a.bn = dgrad ? c.d_bn : c.f_bn;
+  a.ck = dgrad ? c.d_ck : c.f_ck;
+  a.ksplit = dgrad ? c.d_split : c.f_split;
+  a.kpart = c.kpart;
+  a.counters = c.counters;
+  a.batch = 1;
+  return a;
+}
+
+d2ip_status ws_check(void* ws, size_t bytes, size_t need) {
+  if (!ws) return api_fail(D2IP_EINVAL, "null workspace");
+  if (((uintptr_t)ws & 255) != 0) return api_fail(D2IP_EINVAL, "workspace not 256-byte aligned");
+  if (bytes < need)
+    return api_fail(D2IP_ENOMEM, "workspace too small: need " + std::to_string(need) + " bytes");
+  return D2IP_OK;
+}
+
+d2ip_status ln_check(int n, int C) {
+  if (n < 1 || n > 256) return api_fail(D2IP_EINVAL, "n must be in [1, 256]");
+  if (C < 4 || C > 256 || 256 % C != 0)
+    return api_fail(D2IP_EINVAL, "C must be a power of two in [4, 256]");
+  return D2IP_OK;
+}
+
+struct LnOp {
+  double *st = nullptr, *part_c = nullptr, *part_ab = nullptr;
+  float* gz = nullptr;
+  GradSeg* seg = nullptr;
+  int nst = 0, nb = 0;
+};
+
+void ln_plan(LnOp& l, int n, int C, Piece& w) {
+  const size_t V = (size_t)n * n * n;
+  l.nst = block_stats_blocks(V * C);
+  l.nb = ln_bwd_blocks(V, C);
+  l.st = w.take<double>(2 * (size_t)l.nst);
+  l.part_c = w.take<double>((size_t)l.nb * 2 * C);
+  l.part_ab = w.take<double>(2 * (size_t)l.nb);
+  l.gz = w.take<float>(V * C);
+  l.seg = w.take<GradSeg>(1);
+}
+
+}  // namespace
+
+extern "C" {
+
+d2ip_status d2ip_op_conv3d_bytes(int n, int cin, int cout, int taps, int precision, size_t* out) {
+  if (!out) return api_fail(D2IP_EINVAL, "null output");
+  d2ip_status st = conv_check(n, cin, cout, taps, precision);
+  if (st != D2IP_OK) return st;
+  Piece w;
+  ConvOp c;
+  conv_plan(c, n, cin, cout, taps, precision, w);
+  *out = w.off + 256;
+  return D2IP_OK;
+}
+
+d2ip_status d2ip_op_conv3d_forward(const float* x, const float* w, const float* b, float* y, int n,
+                                   int cin, int cout, int taps, int precision, void* workspace,
+                                   size_t bytes, void* hip_stream) {
+  d2ip_status st = conv_check(n, cin, cout, taps, precision);
+  if (st != D2IP_OK) return st;
+  if (!x || !w || !y) return api_fail(D2IP_EINVAL, "null x, w or y");
+  size_t need = 0;
+  d2ip_op_conv3d_bytes(n, cin, cout, taps, precision, &need);
+  if ((st = ws_check(workspace, bytes, need)) != D2IP_OK) return st;
+  hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
+  Piece pc;
+  pc.base = reinterpret_cast<char*>(workspace);
+  ConvOp c;
+  conv_plan(c, n, cin, cout, taps, precision, pc);
+  if ((st = conv_prepare(c, w, s)) != D2IP_OK) return st;
+  conv_fwd(fwd_of(c, false, x, b, y), s);
+  OPCHK(hipGetLastError());
+  return D2IP_OK;
+}
+
+d2ip_status d2ip_op_conv3d_backward(const float* x, const float* w, const float* gy, float* gx,
+                                    float* gw, float* gb, int n, int cin, int cout, int taps,
+                                    int precision, void* workspace, size_t bytes,
+                                    void* hip_stream) {
+  d2ip_status st = conv_check(n, cin, cout, taps, precision);
+  if (st != D2IP_OK) return st;
+  if (!x || !w || !gy) return api_fail(D2IP_EINVAL, "null x, w or gy");
+  size_t need = 0;
+  d2ip_op_conv3d_bytes(n, cin, cout, taps, precision, &need);
+  if ((st = ws_check(workspace, bytes, need)) != D2IP_OK) return st;
+  hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
+  Piece pc;
+  pc.base = reinterpret_cast<char*>(workspace);
+  ConvOp c;
+  conv_plan(c, n, cin, cout, taps, precision, pc);
+  if ((st = conv_prepare(c, w, s)) != D2IP_OK) return st;
+  if (gx) conv_fwd(fwd_of(c, true, gy, nullptr, gx), s);
+  if (gw || gb) {
+    ConvWgrad a;
+    std::memset(&a, 0, sizeof(a));
+    a.src = plain(x, cin);
+    a.gsrc = plain(gy, cout);
+    a.n = n;
+    a.cin = cin;
+    a.cout = cout;
+    a.taps = taps;
+    a.part = c.part;
+    a.partb = c.partb;
+    a.splits = c.w_split;
+    a.prec = c.prec;
+    a.tile = c.w_tile;
+    a.ck = c.w_ck;
+    a.batch = 1;
+    conv_wgrad(a, s);
+    GradSeg g;
+    std::memset(&g, 0, sizeof(g));
+    g.kind = 0;
+    g.splits = c.w_split;
+    g.cout = cout;
+    g.taps = taps;
+    g.cin = cin;
+    g.cin_real = cin;
+    g.th_w = 0;
+    g.th_b = cout * cin * taps;
+    OPCHK(hipMemcpyAsync(c.seg, &g, sizeof(g), hipMemcpyHostToDevice, s));
+    grad_reduce(c.seg, 1, cout * cin * taps, c.part, c.partb, nullptr, c.grad, 1, 0, s);
+    const size_t wel = (size_t)cout * cin * taps;
+    if (gw) OPCHK(hipMemcpyAsync(gw, c.grad, wel * 4, hipMemcpyDeviceToDevice, s));
+    if (gb) OPCHK(hipMemcpyAsync(gb, c.grad + wel, (size_t)cout * 4, hipMemcpyDeviceToDevice, s));
+  }
+  OPCHK(hipGetLastError());
+  return D2IP_OK;
+}
+
+d2ip_status d2ip_op_ln_relu_bytes(int n, int C, size_t* out) {
+  if (!out) return api_fail(D2IP_EINVAL, "null output");
+  d2ip_status st = ln_check(n, C);
+  if (st != D2IP_OK) return st;
+  Piece w;
+  LnOp l;
+  ln_plan(l, n, C, w);
+  *out = w.off + 256;
+  return D2IP_OK;
+}
+
+d2ip_status d2ip_op_ln_relu_forward(const float* x, const float* gamma, const float* beta,
+                                    const float* skip, float* y, int n, int C, void* workspace,
+                                    size_t bytes, void* hip_stream) {
+  d2ip_status st = ln_check(n, C);
+  if (st != D2IP_OK) return st;
+  if (!x || !gamma || !beta || !y) return api_fail(D2IP_EINVAL, "null x, gamma, beta or y");
+  size_t need = 0;
+  d2ip_op_ln_relu_bytes(n, C, &need);
+  if ((st = ws_check(workspace, bytes, need)) != D2IP_OK) return st;
+  hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
+  Piece pc;
+  pc.base = reinterpret_cast<char*>(workspace);
+  LnOp l;
+  ln_plan(l, n, C, pc);
+  const size_t V = (size_t)n * n * n;
+  block_stats(x, V * C, l.st, s);
+  ln_apply(x, PairRef{l.st, l.nst, (double)V * C}, gamma, beta, skip, y, V, C, 1, 0, s);
+  OPCHK(hipGetLastError());
+  return D2IP_OK;
+}
+
+d2ip_status d2ip_op_ln_relu_backward(const float* x, const float* y, const float* gamma,
+                                     const float* gy, float* gx, float* gskip,
+                                     float* dgamma_dbeta, int n, int C, void* workspace,
+                                     size_t bytes, void* hip_stream) {
+  d2ip_status st = ln_check(n, C);
+  if (st != D2IP_OK) return st;
+  if (!x || !y || !gamma || !gy) return api_fail(D2IP_EINVAL, "null x, y, gamma or gy");
+  size_t need = 0;
+  d2ip_op_ln_relu_bytes(n, C, &need);
+  if ((st = ws_check(workspace, bytes, need)) != D2IP_OK) return st;
+  hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
+  Piece pc;
+  pc.base = reinterpret_cast<char*>(workspace);
+  LnOp l;
+  ln_plan(l, n, C, pc);
+  const size_t V = (size_t)n * n * n;
+  const PairRef stat{l.st, l.nst, (double)V * C};
+  block_stats(x, V * C, l.st, s);
+  float* gz = gskip ? gskip : l.gz;
+  ln_bwd(gy, LNMASK_Y, y, nullptr, nullptr, x, stat, gz, l.part_c, l.part_ab, V, C, gamma, 1, 0,
+         s);
+  if (gx) ln_dx(gz, x, stat, PairRef{l.part_ab, l.nb, (double)V * C}, gamma, gx, V, C, s);
+  if (dgamma_dbeta) {
+    GradSeg g;
+    std::memset(&g, 0, sizeof(g));
+    g.kind = 1;
+    g.part_off = 0;
+    g.splits = l.nb;
+    g.cout = 2 * C;
+    g.th_w = 0;
+    OPCHK(hipMemcpyAsync(l.seg, &g, sizeof(g), hipMemcpyHostToDevice, s));
+    grad_reduce(l.seg, 1, 2 * C, nullptr, nullptr, l.part_c, dgamma_dbeta, 1, 0, s);
+  }
+  OPCHK(hipGetLastError());
+  return D2IP_OK;
+}
+
+d2ip_status d2ip_op_j_forward(const float* J, const float* sigma, float* p, int M, int Q,
+                              void* hip_stream) {
+  if (!J || !sigma || !p) return api_fail(D2IP_EINVAL, "null J, sigma or p");
+  if (M < 1 || Q < 4 || Q % 4 != 0) return api_fail(D2IP_EINVAL, "need M >= 1 and Q % 4 == 0");
+  jv_dense(J, M, Q, sigma, p, reinterpret_cast<hipStream_t>(hip_stream));
+  OPCHK(hipGetLastError());
+  return D2IP_OK;
+}
+
+d2ip_status d2ip_op_jt_bytes(int M, int Q, size_t* out) {
+  if (!out) return api_fail(D2IP_EINVAL, "null output");
+  if (M < 1 || Q < 4 || Q % 4 != 0) return api_fail(D2IP_EINVAL, "need M >= 1 and Q % 4 == 0");
+  *out = jt_dense_scratch(Q) * sizeof(float) + 256;
+  return D2IP_OK;
+}
+
+d2ip_status d2ip_op_jt(const float* J, const float* g, float* out, int M, int Q, void* workspace,
+                       size_t bytes, void* hip_stream) {
+  if (!J || !g || !out) return api_fail(D2IP_EINVAL, "null J, g or out");
+  size_t need = 0;
+  d2ip_status st = d2ip_op_jt_bytes(M, Q, &need);
+  if (st != D2IP_OK) return st;
+  if ((st = ws_check(workspace, bytes, need)) != D2IP_OK) return st;
+  jt_dense(J, M, Q, g, reinterpret_cast<float*>(workspace), out,
+           reinterpret_cast<hipStream_t>(hip_stream));
+  OPCHK(hipGetLastError());
+  return D2IP_OK;
+}
+
+}  // extern "C"

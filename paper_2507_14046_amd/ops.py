@@ -1,0 +1,302 @@
+"""PyTorch autograd operators over the library's standalone kernels.
+
+``Conv3dFn``, ``LayerNormReLUFn`` and ``MeasureFn`` wrap the op-level C-ABI
+(include/d2ip.h): their forward and backward passes are the library's HIP
+kernels (implicit-GEMM convolutions with the input and weight gradients, the
+whole-volume LayerNorm + ReLU and its backward, J sigma and J^T g).  ``DIPNet``
+composes the prior of Eq. (3) from them; pooling, up-sampling, channel
+concatenation and the 1x1x1 output head are plain tensor operations of the
+model around the operators.  With ``recompute=True`` every ResBlock's
+activations are dropped after the forward and recomputed during the backward
+(``torch.utils.checkpoint``), trading one more forward for activation memory.
+
+Activations are channels-last 2-D tensors [n^3, C] (voxel v = (z*n + y)*n + x).
+"""
+import ctypes
+
+import numpy as np
+
+from . import _lib as L
+
+_PREC = {"fp32": L.PLAIN_FP32, "bf16": L.BF16_CONV, "bf16x3": L.BF16X3_CONV}
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _p(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _stream(t):
+    return ctypes.c_void_p(_torch().cuda.current_stream(t.device).cuda_stream)
+
+
+def _workspace(fn, *args, device):
+    torch = _torch()
+    nb = ctypes.c_size_t()
+    L.check(fn(*args, ctypes.byref(nb)))
+    return torch.empty(nb.value, dtype=torch.uint8, device=device), nb.value
+
+
+def _grid_n(V):
+    n = round(V ** (1.0 / 3.0))
+    if n ** 3 != V:
+        raise ValueError("activations must hold n^3 voxels")
+    return n
+
+
+class Conv3dFn:
+    """y = conv3d(x, w, b): x [n^3, cin], w [cout, cin, k, k, k] (k 3 or 1), b [cout]."""
+
+    @staticmethod
+    def apply(x, w, b, precision="fp32"):
+        return _conv_fn().apply(x, w, b, precision)
+
+
+class LayerNormReLUFn:
+    """y = relu(LayerNorm(x) * gamma + beta + skip) over all n^3 x C values."""
+
+    @staticmethod
+    def apply(x, gamma, beta, skip=None):
+        return _ln_fn().apply(x, gamma, beta, skip)
+
+
+class MeasureFn:
+    """p = J sigma (J dense [M, Q]); its backward is g_sigma = J^T g_p."""
+
+    @staticmethod
+    def apply(sigma, J):
+        return _measure_fn().apply(sigma, J)
+
+
+_FNS = {}
+
+
+def _conv_fn():
+    if "conv" in _FNS:
+        return _FNS["conv"]
+    torch = _torch()
+
+    class _Conv(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, x, w, b, precision):
+            lib = L.load()
+            x, w = x.contiguous(), w.contiguous()
+            b = b.contiguous() if b is not None else None
+            V, cin = x.shape
+            cout, taps = w.shape[0], w[0, 0].numel()
+            n = _grid_n(V)
+            prec = _PREC[precision]
+            ws, nb = _workspace(lib.d2ip_op_conv3d_bytes, n, cin, cout, taps, prec,
+                                device=x.device)
+            y = torch.empty(V, cout, dtype=torch.float32, device=x.device)
+            L.check(lib.d2ip_op_conv3d_forward(_p(x), _p(w), _p(b), _p(y), n, cin, cout, taps,
+                                               prec, _p(ws), nb, _stream(x)))
+            ctx.save_for_backward(x, w)
+            ctx.meta = (n, cin, cout, taps, prec, b is not None)
+            return y
+
+        @staticmethod
+        def backward(ctx, gy):
+            lib = L.load()
+            x, w = ctx.saved_tensors
+            n, cin, cout, taps, prec, has_b = ctx.meta
+            gy = gy.contiguous()
+            need_x, need_w, need_b = ctx.needs_input_grad[:3]
+            gx = torch.empty_like(x) if need_x else None
+            gw = torch.empty_like(w) if need_w else None
+            gb = torch.empty(cout, dtype=torch.float32, device=x.device) if (need_b and has_b) \
+                else None
+            ws, nb = _workspace(lib.d2ip_op_conv3d_bytes, n, cin, cout, taps, prec,
+                                device=x.device)
+            L.check(lib.d2ip_op_conv3d_backward(_p(x), _p(w), _p(gy), _p(gx), _p(gw), _p(gb), n,
+                                                cin, cout, taps, prec, _p(ws), nb, _stream(x)))
+            return gx, gw, gb, None
+
+    _FNS["conv"] = _Conv
+    return _Conv
+
+
+def _ln_fn():
+    if "ln" in _FNS:
+        return _FNS["ln"]
+    torch = _torch()
+
+    class _LN(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, x, gamma, beta, skip):
+            lib = L.load()
+            x = x.contiguous()
+            skip = skip.contiguous() if skip is not None else None
+            V, C = x.shape
+            n = _grid_n(V)
+            ws, nb = _workspace(lib.d2ip_op_ln_relu_bytes, n, C, device=x.device)
+            y = torch.empty_like(x)
+            L.check(lib.d2ip_op_ln_relu_forward(_p(x), _p(gamma.contiguous()),
+                                                _p(beta.contiguous()), _p(skip), _p(y), n, C,
+                                                _p(ws), nb, _stream(x)))
+            ctx.save_for_backward(x, y, gamma)
+            ctx.meta = (n, C, skip is not None)
+            return y
+
+        @staticmethod
+        def backward(ctx, gy):
+            lib = L.load()
+            x, y, gamma = ctx.saved_tensors
+            n, C, has_skip = ctx.meta
+            gy = gy.contiguous()
+            gx = torch.empty_like(x) if ctx.needs_input_grad[0] else None
+            gskip = torch.empty_like(x) if (has_skip and ctx.needs_input_grad[3]) else None
+            need_gb = ctx.needs_input_grad[1] or ctx.needs_input_grad[2]
+            ggb = torch.empty(2 * C, dtype=torch.float32, device=x.device) if need_gb else None
+            ws, nb = _workspace(lib.d2ip_op_ln_relu_bytes, n, C, device=x.device)
+            L.check(lib.d2ip_op_ln_relu_backward(_p(x), _p(y), _p(gamma.contiguous()), _p(gy),
+                                                 _p(gx), _p(gskip), _p(ggb), n, C, _p(ws), nb,
+                                                 _stream(x)))
+            gg = ggb[:C] if need_gb else None
+            gbeta = ggb[C:] if need_gb else None
+            return gx, gg, gbeta, gskip
+
+    _FNS["ln"] = _LN
+    return _LN
+
+
+def _measure_fn():
+    if "j" in _FNS:
+        return _FNS["j"]
+    torch = _torch()
+
+    class _J(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, sigma, J):
+            lib = L.load()
+            sigma, J = sigma.contiguous(), J.contiguous()
+            M, Q = J.shape
+            p = torch.empty(M, dtype=torch.float32, device=J.device)
+            L.check(lib.d2ip_op_j_forward(_p(J), _p(sigma), _p(p), M, Q, _stream(J)))
+            ctx.save_for_backward(J)
+            return p
+
+        @staticmethod
+        def backward(ctx, gp):
+            lib = L.load()
+            (J,) = ctx.saved_tensors
+            M, Q = J.shape
+            out = torch.empty(Q, dtype=torch.float32, device=J.device)
+            ws, nb = _workspace(lib.d2ip_op_jt_bytes, M, Q, device=J.device)
+            L.check(lib.d2ip_op_jt(_p(J), _p(gp.contiguous()), _p(out), M, Q, _p(ws), nb,
+                                   _stream(J)))
+            return out, None
+
+    _FNS["j"] = _J
+    return _J
+
+
+# ----------------------------------------------------------------------------
+# the prior of Eq. (3) composed from the operators
+# ----------------------------------------------------------------------------
+
+def param_shapes(levels, base_ch):
+    """(name, shape) of every parameter tensor in the canonical flat order:
+    stem, encoder ResBlocks 0..L-1, decoder ResBlocks L-2..0, head; in a
+    module each conv's W [Cout][Cin][k][k][k] then b, each norm gamma then
+    beta, in the order conv1, norm1, conv2, norm2, projection."""
+    C = base_ch
+    ch = [C << l for l in range(levels)]
+    out = [("stem.w", (C, 1, 3, 3, 3)), ("stem.b", (C,)), ("stem.g", (C,)), ("stem.beta", (C,))]
+
+    def block(name, a, b):
+        s = [(name + ".w1", (b, a, 3, 3, 3)), (name + ".b1", (b,)), (name + ".g1", (b,)),
+             (name + ".beta1", (b,)), (name + ".w2", (b, b, 3, 3, 3)), (name + ".b2", (b,)),
+             (name + ".g2", (b,)), (name + ".beta2", (b,))]
+        if a != b:
+            s += [(name + ".wp", (b, a, 1, 1, 1)), (name + ".bp", (b,))]
+        return s
+
+    out += block("enc0", C, C)
+    for l in range(1, levels):
+        out += block("enc%d" % l, ch[l - 1], ch[l])
+    for l in range(levels - 2, -1, -1):
+        out += block("dec%d" % l, ch[l + 1] + ch[l], ch[l])
+    out += [("head.w", (1, C, 1, 1, 1)), ("head.b", (1,))]
+    return out
+
+
+def _pool(x, n):
+    m = n // 2
+    return x.view(m, 2, m, 2, m, 2, x.shape[1]).mean(dim=(1, 3, 5)).reshape(m ** 3, x.shape[1])
+
+
+def _up(x, m):
+    c = x.shape[1]
+    v = x.view(m, 1, m, 1, m, 1, c).expand(m, 2, m, 2, m, 2, c)
+    return v.reshape(8 * m ** 3, c)
+
+
+class DIPNet:
+    """sigma = mask * phi(theta | Z) built from the operators; theta is one
+    flat tensor in the canonical order (gradients flow to it through views)."""
+
+    def __init__(self, n, levels, base_ch, precision="fp32", recompute=False):
+        self.n, self.L, self.C = n, levels, base_ch
+        self.precision = precision
+        self.recompute = recompute
+        self.shapes = param_shapes(levels, base_ch)
+        self.size = int(sum(np.prod(s) for _, s in self.shapes))
+
+    def views(self, theta):
+        out, off = {}, 0
+        for name, shape in self.shapes:
+            k = int(np.prod(shape))
+            out[name] = theta[off:off + k].view(*shape)
+            off += k
+        return out
+
+    def _block(self, P, name, x, n):
+        prec = self.precision
+        h1 = Conv3dFn.apply(x, P[name + ".w1"], P[name + ".b1"], prec)
+        a1 = LayerNormReLUFn.apply(h1, P[name + ".g1"], P[name + ".beta1"])
+        h2 = Conv3dFn.apply(a1, P[name + ".w2"], P[name + ".b2"], prec)
+        s = Conv3dFn.apply(x, P[name + ".wp"], P[name + ".bp"], prec) if name + ".wp" in P else x
+        return LayerNormReLUFn.apply(h2, P[name + ".g2"], P[name + ".beta2"], s)
+
+    def _run_block(self, P, name, x, n):
+        if not self.recompute:
+            return self._block(P, name, x, n)
+        from torch.utils.checkpoint import checkpoint
+        return checkpoint(lambda t: self._block(P, name, t, n), x, use_reentrant=False)
+
+    def forward(self, theta, Z, mask):
+        """theta [P], Z [n^3] noise input, mask [n^3] (0/1) -> sigma [n^3]."""
+        torch = _torch()
+        P = self.views(theta)
+        n, L = self.n, self.L
+        # the 1-channel stem input is padded to 8 channels (zero weights)
+        z8 = torch.zeros(n ** 3, 8, dtype=torch.float32, device=Z.device)
+        z8[:, 0] = Z
+        w8 = torch.cat([P["stem.w"], torch.zeros(self.C, 7, 3, 3, 3, dtype=theta.dtype,
+                                                 device=theta.device)], dim=1)
+        h = Conv3dFn.apply(z8, w8, P["stem.b"], self.precision)
+        x = LayerNormReLUFn.apply(h, P["stem.g"], P["stem.beta"])
+        skips = []
+        for l in range(L):
+            nl = n >> l
+            if l > 0:
+                x = _pool(x, nl * 2)
+            x = self._run_block(P, "enc%d" % l, x, nl)
+            skips.append(x)
+        for l in range(L - 2, -1, -1):
+            nl = n >> l
+            x = torch.cat([_up(x, nl // 2), skips[l]], dim=1)
+            x = self._run_block(P, "dec%d" % l, x, nl)
+        out = x @ P["head.w"].view(1, self.C).t() + P["head.b"]
+        return out.view(-1) * mask
+
+    def loss(self, theta, Z, mask, J, dv):
+        """(1/M) sum (J sigma - dv)^2, with J sigma and J^T on the library's kernels."""
+        sigma = self.forward(theta, Z, mask)
+        r = MeasureFn.apply(sigma, J) - dv
+        return (r * r).sum() / J.shape[0]

@@ -132,8 +132,49 @@ static int tuning_case() {
   return 0;
 }
 
+// The standalone operators on host-emulated buffers.
+static int ops_case() {
+  const int n = 8, cin = 16, cout = 24, C = 16, M = 40, Q = n * n * n;
+  std::vector<float> x((size_t)Q * 32, 0.f), y((size_t)Q * 32), w((size_t)cout * cin * 27),
+      b(cout), g((size_t)Q * 32), gx((size_t)Q * 32), gw(w.size()), gb(cout), gam(C, 1.f),
+      bet(C), gs((size_t)Q * C), ggb(2 * C), J((size_t)M * Q), p(M), out(Q);
+  int token = 0;
+  for (int taps : {27, 1})
+    for (int prec = 0; prec < 3; ++prec) {
+      size_t need = 0;
+      CK(d2ip_op_conv3d_bytes(n, cin, cout, taps, prec, &need));
+      char* ws = (char*)aligned_alloc(256, (need + 255) / 256 * 256);
+      std::vector<float> wt((size_t)cout * cin * taps);
+      CK(d2ip_op_conv3d_forward(x.data(), wt.data(), b.data(), y.data(), n, cin, cout, taps, prec,
+                                ws, need, &token));
+      CK(d2ip_op_conv3d_backward(x.data(), wt.data(), g.data(), gx.data(), gw.data(), gb.data(), n,
+                                 cin, cout, taps, prec, ws, need, &token));
+      EXPECT_ERR(d2ip_op_conv3d_forward(x.data(), wt.data(), b.data(), y.data(), n, cin, cout,
+                                        taps, prec, ws, need - 1, &token),
+                 D2IP_ENOMEM);
+      free(ws);
+    }
+  size_t need = 0;
+  EXPECT_ERR(d2ip_op_conv3d_bytes(n, 12, cout, 27, 0, &need), D2IP_EINVAL);
+  CK(d2ip_op_ln_relu_bytes(n, C, &need));
+  char* ws = (char*)aligned_alloc(256, (need + 255) / 256 * 256);
+  CK(d2ip_op_ln_relu_forward(x.data(), gam.data(), bet.data(), nullptr, y.data(), n, C, ws, need,
+                             &token));
+  CK(d2ip_op_ln_relu_backward(x.data(), y.data(), gam.data(), g.data(), gx.data(), gs.data(),
+                              ggb.data(), n, C, ws, need, &token));
+  free(ws);
+  EXPECT_ERR(d2ip_op_ln_relu_bytes(n, 12, &need), D2IP_EINVAL);
+  CK(d2ip_op_j_forward(J.data(), x.data(), p.data(), M, Q, &token));
+  CK(d2ip_op_jt_bytes(M, Q, &need));
+  ws = (char*)aligned_alloc(256, (need + 255) / 256 * 256);
+  CK(d2ip_op_jt(J.data(), p.data(), out.data(), M, Q, ws, need, &token));
+  free(ws);
+  printf("ok: standalone operators\n");
+  return 0;
+}
+
 int main() {
-  int bad = tuning_case();
+  int bad = tuning_case() | ops_case();
   for (int prec = 0; prec < 3; ++prec)
     for (unsigned fl = 0; fl < 2; ++fl) {
       bad |= run_case({{16, 928}}, {{0, 3, 8}, {0, 3, 8}, {0, 3, 8}}, prec, fl);
