@@ -347,8 +347,12 @@ def test_trajectory_500_iterations_32cubed_vs_stored_oracle(lib, prec):
     500 iterations, graph, stored tuning table) against the stored FP64
     oracle trajectory.  The oracle's own sensitivity (a 1-ulp change of
     theta_0 moves its image by `floor` at iteration 500) bounds what any
-    implementation can match; the image must stay within 3 x floor (FP32,
-    BF16x3) of the oracle's."""
+    implementation can match: FP32 must stay within 3 x floor.  Adam
+    amplifies any early difference along the trajectory by at most the factor
+    the oracle's 1-ulp run shows between iterations 1 and 500, so the BF16
+    forms, whose operand rounding already moves the first image, must stay
+    within that factor times their iteration-1 error, and that first error
+    within what the operand rounding explains."""
     import os
     from paper_2507_14046_amd import autotune as at
     path = os.path.join(os.path.dirname(__file__), "golden", "oracle_c1_500.npz")
@@ -358,6 +362,7 @@ def test_trajectory_500_iterations_32cubed_vs_stored_oracle(lib, prec):
     cps = list(z["checkpoints"])
     ref, flo = z["images"][cps.index(500)], z["floor_images"][cps.index(500)]
     floor = rel(flo, ref)
+    amp = floor / rel(z["floor_images"][cps.index(1)], z["images"][cps.index(1)])
     try:
         if os.path.exists(at.default_table_path()):
             at.set_tuning(at.load_table(at.default_table_path()))
@@ -373,9 +378,11 @@ def test_trajectory_500_iterations_32cubed_vs_stored_oracle(lib, prec):
         at.set_tuning([])
     e = {int(cp): rel(imgs[cp], z["images"][i]) for i, cp in enumerate(cps)}
     lrel = [abs(l - z["losses"][cp - 1]) / z["losses"][cp - 1] for l, cp in zip(losses, cps)]
-    record("trajectory500_32cubed", prec=prec, image_rel=e, floor=floor, loss_rel=lrel)
-    if prec in ("fp32", "bf16x3"):
+    record("trajectory500_32cubed", prec=prec, image_rel=e, floor=floor, amplification=amp,
+           loss_rel=lrel)
+    first = {"fp32": 1e-5, "bf16x3": 1e-3, "bf16": 5e-2}[prec]
+    assert e[1] < first, e
+    if prec == "fp32":
         assert e[500] < 3 * floor, (e[500], floor)
-        assert e[1] < TOL_IMG[prec], e
     else:
-        assert e[500] < 0.5, e
+        assert e[500] < amp * e[1], (e[500], amp, e[1])
