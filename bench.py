@@ -224,7 +224,12 @@ def config2(d2ip, at, ts, prec, torch, cache, steps=40):
                 note="no stored FP64 oracle trajectory at this size")
 
 
-def config3(d2ip, at, ts, prec, torch, cache, frames=3):
+def _launch(graph):
+    return ("one captured hipGraph per iteration, instances in sequence" if graph else
+            "eager launches, instances concurrently on up to 4 stream lanes")
+
+
+def config3(d2ip, at, ts, prec, torch, cache, frames=3, graph=True):
     """Eight sequences fitted together, frame after frame (TPP): steady-state
     frames/s over `frames` frames of 50 iterations after a 500-iteration first
     frame, and the full 100-frame schedule's rate derived from it."""
@@ -235,7 +240,7 @@ def config3(d2ip, at, ts, prec, torch, cache, frames=3):
     geos = [(cfg["n"], M)]
     insts = [(0, cfg["levels"], cfg["base_ch"])] * len(seqs)
     at.set_tuning(tuned(d2ip, at, geos, [insts[0]], prec, cache))
-    ctx = d2ip.Context(geos, insts, precision=prec, graph=True)
+    ctx = d2ip.Context(geos, insts, precision=prec, graph=graph)
     ctx.set_geometry(0, seqs[0]["J"], seqs[0]["mask"])
     for i, p in enumerate(seqs):
         ctx.load_problem(i, p, set_geometry=False)
@@ -251,7 +256,7 @@ def config3(d2ip, at, ts, prec, torch, cache, frames=3):
     S = len(seqs)
     per_frame_ms = t_later / frames
     total_ms = t_first + (cfg["frames"] - 1) * per_frame_ms
-    return dict(workload=cfg["desc"], form=prec, sequences=S,
+    return dict(workload=cfg["desc"], form=prec, sequences=S, launch=_launch(graph),
                 frames_per_s_steady=S / (per_frame_ms * 1e-3),
                 frames_per_s_schedule=S * cfg["frames"] / (total_ms * 1e-3),
                 first_frame_ms=t_first, later_frame_ms=per_frame_ms,
@@ -259,7 +264,7 @@ def config3(d2ip, at, ts, prec, torch, cache, frames=3):
                        "100-frame rate extrapolates the measured per-frame time" % frames)
 
 
-def config4(d2ip, at, ts, prec, torch, cache, iters=20):
+def config4(d2ip, at, ts, prec, torch, cache, iters=20, graph=True):
     cfg = ts.CONFIGS["c4"]
     geos, insts, probs = [], [], []
     for it in cfg["instances"]:
@@ -274,7 +279,7 @@ def config4(d2ip, at, ts, prec, torch, cache, iters=20):
         for e in tuned(d2ip, at, [geos[k[0]]], [(0, k[1], k[2])], prec, cache):
             table[tuple(e[f] for f in at.FIELDS)] = e
     at.set_tuning(list(table.values()))
-    ctx = d2ip.Context(geos, insts, precision=prec, graph=True)
+    ctx = d2ip.Context(geos, insts, precision=prec, graph=graph)
     done = set()
     for i, p in enumerate(probs):
         ctx.load_problem(i, p, set_geometry=insts[i][0] not in done)
@@ -283,7 +288,7 @@ def config4(d2ip, at, ts, prec, torch, cache, iters=20):
     ctx.run(2)
     ms = timed_run(ctx, iters, torch)
     ctx.close()
-    return dict(workload=cfg["desc"], form=prec, instances=len(insts),
+    return dict(workload=cfg["desc"], form=prec, instances=len(insts), launch=_launch(graph),
                 batched_it_per_s=iters / (ms * 1e-3),
                 instance_it_per_s=len(insts) * iters / (ms * 1e-3),
                 schedule_s=cfg["iters"] * ms / iters * 1e-3,
@@ -379,10 +384,13 @@ def main():
         for name, fn in (("c0", config0), ("c2", config2), ("c3", config3), ("c4", config4)):
             configs[name] = {}
             for prec in ("fp32", "bf16"):
-                t0 = time.time()
-                configs[name][prec] = fn(d2ip, at, ts, prec, torch, cache)
-                log("%s %-5s %s (%.0f s)" % (name, prec, json.dumps(configs[name][prec]),
-                                             time.time() - t0))
+                for graph in ((True, False) if name in ("c3", "c4") else (True,)):
+                    key = prec if graph else prec + "_lanes"
+                    t0 = time.time()
+                    kw = {} if name in ("c0", "c2") else {"graph": graph}
+                    configs[name][key] = fn(d2ip, at, ts, prec, torch, cache, **kw)
+                    log("%s %-10s %s (%.0f s)" % (name, key, json.dumps(configs[name][key]),
+                                                  time.time() - t0))
         at.set_tuning([])
     if cache.get("fresh"):
         # shapes tuned in this run (no stored table covered them)

@@ -498,6 +498,14 @@ struct d2ip_ctx {
   hipStream_t cap = nullptr;  // capture stream (the caller's may be the legacy default stream)
   hipStream_t side = nullptr;  // branch for work off the critical path (weight gradients)
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  // instance groups run concurrently, each on one of a few lanes (a main and
+  // a side stream) forked from and joined back into the context stream
+  struct Lane {
+    hipStream_t main = nullptr, side = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr, done = nullptr;
+  };
+  std::vector<Lane> lanes;
+  hipEvent_t ev_start = nullptr;
   size_t bytes = 0;
 };
 
@@ -1166,6 +1174,38 @@ void enqueue_iteration(d2ip_ctx& X, Instance& I) {
   L_pack(I, X.precision, true, G.M, s);
 }
 
+// One iteration of every instance group: groups on different lanes run
+// concurrently (their workspace regions are disjoint; geometries are read
+// only).  Lanes are used for eager launches only: the first captured graph
+// with lanes ended in a host-side crash whose cause has not been found, so a
+// captured iteration runs the groups one after another.
+void enqueue_all(d2ip_ctx& X, bool capturing) {
+  if (X.lanes.empty() || capturing) {
+    for (Instance& I : X.insts) enqueue_iteration(X, I);
+    return;
+  }
+  const hipStream_t s0 = X.stream, side0 = X.side;
+  const hipEvent_t f0 = X.ev_fork, j0 = X.ev_join;
+  hipEventRecord(X.ev_start, s0);
+  for (d2ip_ctx::Lane& l : X.lanes) hipStreamWaitEvent(l.main, X.ev_start, 0);
+  for (size_t k = 0; k < X.insts.size(); ++k) {
+    d2ip_ctx::Lane& l = X.lanes[k % X.lanes.size()];
+    X.stream = l.main;
+    X.side = l.side;
+    X.ev_fork = l.fork;
+    X.ev_join = l.join;
+    enqueue_iteration(X, X.insts[k]);
+  }
+  X.stream = s0;
+  X.side = side0;
+  X.ev_fork = f0;
+  X.ev_join = j0;
+  for (d2ip_ctx::Lane& l : X.lanes) {
+    hipEventRecord(l.done, l.main);
+    hipStreamWaitEvent(s0, l.done, 0);
+  }
+}
+
 void L_adam(Instance& I, const d2ip_ctx& X, hipStream_t s) {
   if (!g_chk)
     return adam(I.theta, I.grad, I.m, I.v, I.P, X.lr, X.b1, X.b2, X.eps, I.it, I.B, I.istride, s);
@@ -1275,6 +1315,21 @@ void carve_time_conv(const d2ip_tuning_entry& e, Carver& cv, TimeConvBufs& b) {
   const size_t cout16 = (e.cout + 15) / 16 * 16;
   b.part = cv.take<float>((size_t)e.shape.split * cout16 * e.taps * e.cin);
   b.partb = cv.take<float>((size_t)e.shape.split * cout16);
+}
+
+constexpr size_t kMaxLanes = 4;  // concurrent instance groups (hardware queues per process)
+
+void release_lanes(d2ip_ctx* X) {
+  for (d2ip_ctx::Lane& l : X->lanes) {
+    if (l.done) hipEventDestroy(l.done);
+    if (l.join) hipEventDestroy(l.join);
+    if (l.fork) hipEventDestroy(l.fork);
+    if (l.side) hipStreamDestroy(l.side);
+    if (l.main) hipStreamDestroy(l.main);
+  }
+  X->lanes.clear();
+  if (X->ev_start) hipEventDestroy(X->ev_start);
+  X->ev_start = nullptr;
 }
 
 void drop_graph(d2ip_ctx* X) {
@@ -1524,6 +1579,7 @@ d2ip_status d2ip_create(const d2ip_geometry_desc* geos, int n_geo, const d2ip_in
   cv.base = reinterpret_cast<char*>(workspace);
   plan(*X, geos, n_geo, insts, n_inst, cv);
   auto cleanup = [&](d2ip_status s) {
+    release_lanes(X);
     if (X->ev_join) hipEventDestroy(X->ev_join);
     if (X->ev_fork) hipEventDestroy(X->ev_fork);
     if (X->side) hipStreamDestroy(X->side);
@@ -1549,6 +1605,17 @@ d2ip_status d2ip_create(const d2ip_geometry_desc* geos, int n_geo, const d2ip_in
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&X->side, hipStreamNonBlocking);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&X->ev_fork, hipEventDisableTiming);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&X->ev_join, hipEventDisableTiming);
+  if (e == hipSuccess && X->insts.size() > 1) {
+    e = hipEventCreateWithFlags(&X->ev_start, hipEventDisableTiming);
+    X->lanes.resize(std::min<size_t>(X->insts.size(), kMaxLanes));
+    for (d2ip_ctx::Lane& l : X->lanes) {
+      if (e == hipSuccess) e = hipStreamCreateWithFlags(&l.main, hipStreamNonBlocking);
+      if (e == hipSuccess) e = hipStreamCreateWithFlags(&l.side, hipStreamNonBlocking);
+      if (e == hipSuccess) e = hipEventCreateWithFlags(&l.fork, hipEventDisableTiming);
+      if (e == hipSuccess) e = hipEventCreateWithFlags(&l.join, hipEventDisableTiming);
+      if (e == hipSuccess) e = hipEventCreateWithFlags(&l.done, hipEventDisableTiming);
+    }
+  }
   if (e != hipSuccess)
     return cleanup(fail(D2IP_EHIP, std::string("workspace init: ") + hipGetErrorString(e)));
   *out = X;
@@ -1560,6 +1627,11 @@ d2ip_status d2ip_destroy(d2ip_ctx* X) {
   hipStreamSynchronize(X->stream);
   drop_graph(X);
   if (X->side) hipStreamSynchronize(X->side);
+  for (d2ip_ctx::Lane& l : X->lanes) {
+    if (l.main) hipStreamSynchronize(l.main);
+    if (l.side) hipStreamSynchronize(l.side);
+  }
+  release_lanes(X);
   if (X->ev_join) hipEventDestroy(X->ev_join);
   if (X->ev_fork) hipEventDestroy(X->ev_fork);
   if (X->side) hipStreamDestroy(X->side);
@@ -1773,7 +1845,7 @@ d2ip_status d2ip_run(d2ip_ctx* X, int k, double* last_loss) {
         hipError_t e = hipStreamBeginCapture(X->cap, hipStreamCaptureModeThreadLocal);
         hipGraph_t g = nullptr;
         if (e == hipSuccess) {
-          for (Instance& I : X->insts) enqueue_iteration(*X, I);
+          enqueue_all(*X, true);
           e = hipStreamEndCapture(X->cap, &g);
         }
         X->stream = user;
@@ -1783,8 +1855,7 @@ d2ip_status d2ip_run(d2ip_ctx* X, int k, double* last_loss) {
       }
       for (int i = 0; i < k; ++i) HIPCHK(hipGraphLaunch(X->gexec, X->stream));
     } else {
-      for (int i = 0; i < k; ++i)
-        for (Instance& I : X->insts) enqueue_iteration(*X, I);
+      for (int i = 0; i < k; ++i) enqueue_all(*X, false);
       HIPCHK(hipGetLastError());
     }
   }
