@@ -25,40 +25,49 @@ __global__ void k_gather_columns(const float* __restrict__ J, int M, int Q,
 }
 
 // Members of a group share J: each block reads its J tile once and forms the
-// partial products for every member (up to kJMaxB per launch).
+// partial products for every member (up to kJMaxB per launch).  Each wave
+// owns kJvecRows / 4 rows and issues all of their loads before reducing, so
+// a lane keeps 16 independent 16-byte loads in flight.
+constexpr int kJvecRowsPerWave = kJvecRows / 4;
 __global__ __launch_bounds__(256) void k_jvec(const float* __restrict__ Jc, int M, int qa_pad,
                                               const int* __restrict__ idx, const float* sigma,
                                               float* ppart, int B, long long istride) {
-  __shared__ __align__(16) float sv[kJMaxB][kJvecCols];
+  extern __shared__ __align__(16) float sv[];  // [B][kJvecCols]
   const int q0 = blockIdx.x * kJvecCols;
   const int qn = min(kJvecCols, qa_pad - q0);
   for (int b = 0; b < B; ++b) {
     const float* sg = ishift(sigma, b * istride);
-    for (int q = threadIdx.x; q < kJvecCols; q += 256) sv[b][q] = q < qn ? sg[idx[q0 + q]] : 0.f;
+    for (int q = threadIdx.x; q < kJvecCols; q += 256)
+      sv[b * kJvecCols + q] = q < qn ? sg[idx[q0 + q]] : 0.f;
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int m0 = blockIdx.y * kJvecRows + wave * kJvecRowsPerWave;
+  constexpr int KV = kJvecCols / 256;  // float4 per lane per row
+  float4 jv[kJvecRowsPerWave][KV];
+#pragma unroll
+  for (int r = 0; r < kJvecRowsPerWave; ++r) {
+    const int m = m0 + r;
+    const float* row = Jc + (size_t)min(m, M - 1) * qa_pad + q0;
+#pragma unroll
+    for (int k = 0; k < KV; ++k) {
+      const int j = lane * 4 + 256 * k;
+      jv[r][k] = (m < M && j < qn) ? *reinterpret_cast<const float4*>(row + j)
+                                   : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
   }
   __syncthreads();
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  for (int r = wave; r < kJvecRows; r += 4) {
-    const int m = blockIdx.y * kJvecRows + r;
-    if (m >= M) break;
-    const float* row = Jc + (size_t)m * qa_pad + q0;
-    float acc[kJMaxB];
+  for (int b = 0; b < B; ++b) {
 #pragma unroll
-    for (int b = 0; b < kJMaxB; ++b) acc[b] = 0.f;
-    for (int j = lane * 4; j < qn; j += 256) {
-      const float4 jv = *reinterpret_cast<const float4*>(row + j);
+    for (int r = 0; r < kJvecRowsPerWave; ++r) {
+      float acc = 0.f;
 #pragma unroll
-      for (int b = 0; b < kJMaxB; ++b) {
-        if (b >= B) break;
-        const float4 sb = *reinterpret_cast<const float4*>(&sv[b][j]);
-        acc[b] += jv.x * sb.x + jv.y * sb.y + jv.z * sb.z + jv.w * sb.w;
+      for (int k = 0; k < KV; ++k) {
+        const float4 sb = *reinterpret_cast<const float4*>(&sv[b * kJvecCols + lane * 4 + 256 * k]);
+        acc += jv[r][k].x * sb.x + jv[r][k].y * sb.y + jv[r][k].z * sb.z + jv[r][k].w * sb.w;
       }
-    }
-#pragma unroll
-    for (int b = 0; b < kJMaxB; ++b) {
-      if (b >= B) break;
-      const float v = wave_sum(acc[b]);
-      if (lane == 0) ishift(ppart, b * istride)[(size_t)blockIdx.x * M + m] = v;
+      const float v = wave_sum(acc);
+      const int m = m0 + r;
+      if (lane == 0 && m < M) ishift(ppart, b * istride)[(size_t)blockIdx.x * M + m] = v;
     }
   }
 }
@@ -337,7 +346,9 @@ void jvec(const float* Jc, int M, int qa_pad, const int* idx, const float* sigma
           int batch, long long istride, hipStream_t s) {
   dim3 grid(jvec_qblocks(qa_pad), (M + kJvecRows - 1) / kJvecRows);
   for (int b0 = 0; b0 < batch; b0 += kJMaxB)
-    hipLaunchKernelGGL(k_jvec, grid, dim3(256), 0, s, Jc, M, qa_pad, idx,
+    hipLaunchKernelGGL(k_jvec, grid, dim3(256),
+                       (size_t)std::min(kJMaxB, batch - b0) * kJvecCols * sizeof(float), s, Jc,
+                       M, qa_pad, idx,
                        ishift(sigma, b0 * istride), ishift(ppart, b0 * istride),
                        std::min(kJMaxB, batch - b0), istride);
 }

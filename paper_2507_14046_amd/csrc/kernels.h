@@ -150,7 +150,7 @@ struct ConvPack {  // one conv of the flat parameter vector
 };
 
 constexpr int kJvecCols = 1024;   // columns per J*sigma block
-constexpr int kJvecRows = 16;     // rows per J*sigma block
+constexpr int kJvecRows = 8;      // rows per J*sigma block
 constexpr int kJtRows = 32;       // rows per J^T g block
 constexpr int kJMaxB = 8;         // group members per J-product launch (J read once)
 inline int jvec_qblocks(int qa_pad) { return (qa_pad + kJvecCols - 1) / kJvecCols; }
