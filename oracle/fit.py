@@ -22,6 +22,7 @@ since the paper transfers only theta.
 import numpy as np
 
 from . import net
+from . import tv as tvmod
 
 ADAM_BETA1 = 0.9
 ADAM_BETA2 = 0.999
@@ -58,11 +59,20 @@ class Problem:
         out, _ = net.forward(theta, self.Z, self.n, self.levels, self.base_ch)
         return self.mask * out.ravel()
 
-    def loss_and_grad(self, theta, dv):
-        """(L, dL/dtheta, image) at theta for the data term of one frame."""
+    def loss_and_grad(self, theta, dv, tv=None):
+        """(L, dL/dtheta, image) at theta for one frame: the data term, plus
+        the 4D-TV term when tv = dict(history=[images], weights=[...],
+        lam=, lam_s=, lam_t=, eps=) is given (Eq. (14))."""
         out, cache = net.forward(theta, self.Z, self.n, self.levels, self.base_ch)
         sigma = self.mask * out.ravel()
         L, gs = data_loss(self.J, dv, sigma)
+        if tv is not None:
+            n = self.n
+            hist = [np.asarray(h, dtype=np.float64).reshape(n, n, n) for h in tv["history"]]
+            Lt, gt = tvmod.tv4d(sigma.reshape(n, n, n), hist, tv["weights"], tv["lam"],
+                                tv["lam_s"], tv["lam_t"], tv["eps"])
+            L += Lt
+            gs = gs + gt.ravel()
         gout = (self.mask * gs).reshape(self.n, self.n, self.n)
         g = net.backward(gout, theta, cache, self.n, self.levels, self.base_ch)
         return L, g, sigma
@@ -83,12 +93,12 @@ class State:
         self.t = 0
 
 
-def run(problem, state, dv, k, lr, b1=ADAM_BETA1, b2=ADAM_BETA2, eps=ADAM_EPS):
+def run(problem, state, dv, k, lr, b1=ADAM_BETA1, b2=ADAM_BETA2, eps=ADAM_EPS, tv=None):
     """k Adam iterations on one frame; returns the k recorded losses."""
     dv = np.asarray(dv, dtype=np.float64)
     losses = []
     for _ in range(k):
-        L, g, _ = problem.loss_and_grad(state.theta, dv)
+        L, g, _ = problem.loss_and_grad(state.theta, dv, tv)
         state.theta, state.m, state.v, state.t = adam_step(
             state.theta, g, state.m, state.v, state.t, lr, b1, b2, eps)
         losses.append(L)
@@ -96,13 +106,22 @@ def run(problem, state, dv, k, lr, b1=ADAM_BETA1, b2=ADAM_BETA2, eps=ADAM_EPS):
 
 
 def fit_sequence(problem, theta0, dvs, iters, lr, reset_on_frame=True,
-                 b1=ADAM_BETA1, b2=ADAM_BETA2, eps=ADAM_EPS):
-    """Frames in order with TPP.  iters[i] = N_i.  Returns (images, losses)."""
+                 b1=ADAM_BETA1, b2=ADAM_BETA2, eps=ADAM_EPS, tv=None):
+    """Frames in order with TPP.  iters[i] = N_i.  Returns (images, losses).
+
+    With tv = dict(lam=, lam_s=, lam_t=, eps=) every frame's loss carries the
+    4D-TV term, its temporal part over all earlier frames' final images."""
     st = State(theta0)
     images, losses = [], []
     for i, dv in enumerate(dvs):
         if reset_on_frame:
             st.reset_optimizer()
-        losses.append(run(problem, st, dv, iters[i], lr, b1, b2, eps))
+        frame_tv = None
+        if tv is not None:
+            frame = i + 1  # 1-based frame index of Eq. (13)
+            prev = list(range(1, frame))
+            frame_tv = dict(tv, history=list(images),
+                            weights=tvmod.temporal_weights(frame, prev) if prev else [])
+        losses.append(run(problem, st, dv, iters[i], lr, b1, b2, eps, frame_tv))
         images.append(problem.image(st.theta))
     return np.stack(images), losses, st
