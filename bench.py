@@ -142,13 +142,16 @@ def timed_run(ctx, steps, torch):
     return e0.elapsed_time(e1)
 
 
-def single_form(d2ip, at, p, cfg, prec, steps, warmup, torch, graph=True, tune=True, cache=None):
+def single_form(d2ip, at, p, cfg, prec, steps, warmup, torch, graph=True, tune=True, cache=None,
+                tv=False):
     geos = [(cfg["n"], p["J"].shape[0])]
     insts = [(0, cfg["levels"], cfg["base_ch"])]
     at.set_tuning(tuned(d2ip, at, geos, insts, prec, cache) if tune else [])
     ctx = d2ip.Context(geos, insts, precision=prec, graph=graph)
     ctx.load_problem(0, p)
     ctx.set_adam(lr=cfg["lr"])
+    if tv:
+        ctx.set_tv()  # Sec. III-E coefficients; a first frame has no temporal history
     ctx.run(warmup)
     ms = timed_run(ctx, steps, torch)
     loss = float(ctx.run(0)[0])
@@ -347,6 +350,13 @@ def main():
                  note="FP32, heuristic launch shapes, eager launches (no graph)")
     ctx.close()
     log("plain fp32     %9.1f it/s" % plain["it_per_s"])
+    ctx, ms, loss, img = single_form(d2ip, at, p, cfg, "fp32", a.steps, a.warmup, torch,
+                                     cache=cache, tv=True)
+    with_tv = dict(it_per_s=a.steps / (ms * 1e-3), ms_per_step=ms / a.steps, final_loss=loss,
+                   note="FP32, tuned, graph, loss with the 4D-TV term (lambda 0.002, 1, 0.1; "
+                        "first frame: spatial term only)")
+    ctx.close()
+    log("fp32 + 4D-TV   %9.1f it/s" % with_tv["it_per_s"])
     ok = [f for f in forms if forms[f]["within_bound"]]
     chosen = max(ok, key=lambda f: forms[f]["it_per_s"]) if ok else (
         "fp32" if "fp32" in forms else list(forms)[0])
@@ -419,6 +429,7 @@ def main():
         "frames_per_s_tpp50": res["it_per_s"] / 50.0,
         "forms": forms,
         "plain_fp32": plain,
+        "fp32_with_4d_tv": with_tv,
         "configs": configs,
         "roofline": roof,
         "cpu_baseline": cpu,

@@ -192,6 +192,34 @@ d2ip_status d2ip_time_kernel(d2ip_ctx* ctx, int inst, int which, int block, int 
 /* Image of `inst` at its current theta: mask * phi(theta | Z), n^3 FP32 (Eq. (5)). */
 d2ip_status d2ip_read_image(d2ip_ctx* ctx, int inst, float* sigma, int on_device);
 
+/* ---- 4D total variation (Sec. III-E) ------------------------------------
+ * With lambda_tv > 0 every iteration's loss is the data term plus
+ *   lambda_tv * (lambda_s * R_spatial(s) + lambda_t * R_temporal(history, s))
+ * (Eqs. (11)-(14)) for the current image s = mask * phi(theta | Z):
+ *   R_spatial  = (1/V) sum_v sqrt(dz^2 + dy^2 + dx^2 + eps), forward
+ *                differences, 0 where the neighbour is outside the grid;
+ *   R_temporal = sum_k w_k sum_v sqrt((s - h_k)^2 + eps) over the images h_k
+ *                of the k-th previous frame (k = 1 the newest), w_k =
+ *                exp(-k) / sum_k exp(-k); 0 with no history.
+ * The history holds at most 32 frames (an older frame's weight is below
+ * exp(-32) of the newest's, under FP32 resolution).  The paper's values are
+ * lambda_tv 0.002, lambda_s 1, lambda_t 0.1; eps (unstated) 1e-8. */
+typedef struct {
+  float lambda_tv, lambda_s, lambda_t, eps;
+} d2ip_tv_cfg;
+
+/* Set the 4D-TV coefficients of every instance (lambda_tv 0 switches the term
+ * off, the default).  Drops a captured graph. */
+d2ip_status d2ip_set_tv(d2ip_ctx* ctx, const d2ip_tv_cfg* cfg);
+
+/* End the current frame of `inst`: its image at the current theta becomes
+ * the newest entry of the temporal history.  Call before d2ip_set_frame of
+ * the next frame. */
+d2ip_status d2ip_commit_frame(d2ip_ctx* ctx, int inst);
+
+/* Empty the temporal history of `inst` (a new sequence). */
+d2ip_status d2ip_clear_history(d2ip_ctx* ctx, int inst);
+
 /* ---- launch shapes of the convolutions (for autotuning) ----------------
  * Every 3x3x3 / 1x1x1 convolution of the network (Eq. (3): the prior phi is
  * built from them) runs three passes: 0 forward, 1 input gradient, 2 weight

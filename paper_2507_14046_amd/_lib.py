@@ -29,6 +29,11 @@ class AdamCfg(ctypes.Structure):
                 ("eps", ctypes.c_float)]
 
 
+class TvCfg(ctypes.Structure):
+    _fields_ = [("lambda_tv", ctypes.c_float), ("lambda_s", ctypes.c_float),
+                ("lambda_t", ctypes.c_float), ("eps", ctypes.c_float)]
+
+
 class ConvShape(ctypes.Structure):
     _fields_ = [("tile", ctypes.c_int), ("bn", ctypes.c_int), ("ck", ctypes.c_int),
                 ("split", ctypes.c_int)]
@@ -80,6 +85,9 @@ SIGNATURES = {
     "d2ip_time_conv_bytes": [ctypes.POINTER(TuningEntry), _c_size_p],
     "d2ip_time_conv": [ctypes.POINTER(TuningEntry), _vp, ctypes.c_size_t, _vp, _i,
                        ctypes.POINTER(ctypes.c_double)],
+    "d2ip_set_tv": [_vp, ctypes.POINTER(TvCfg)],
+    "d2ip_commit_frame": [_vp, _i],
+    "d2ip_clear_history": [_vp, _i],
     # standalone operators
     "d2ip_op_conv3d_bytes": [_i, _i, _i, _i, _i, _c_size_p],
     "d2ip_op_conv3d_forward": [_vp, _vp, _vp, _vp, _i, _i, _i, _i, _i, _vp, ctypes.c_size_t, _vp],

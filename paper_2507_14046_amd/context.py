@@ -139,6 +139,18 @@ class Context:
         cfg = L.AdamCfg(lr, beta1, beta2, eps)
         L.check(self._lib.d2ip_set_adam(self._ctx, ctypes.byref(cfg)))
 
+    def set_tv(self, lambda_tv=0.002, lambda_s=1.0, lambda_t=0.1, eps=1e-8):
+        """4D-TV coefficients (lambda_tv = 0 switches the term off)."""
+        cfg = L.TvCfg(lambda_tv, lambda_s, lambda_t, eps)
+        L.check(self._lib.d2ip_set_tv(self._ctx, ctypes.byref(cfg)))
+
+    def commit_frame(self, inst):
+        """The image at the current theta joins the temporal history."""
+        L.check(self._lib.d2ip_commit_frame(self._ctx, inst))
+
+    def clear_history(self, inst):
+        L.check(self._lib.d2ip_clear_history(self._ctx, inst))
+
     def reset_optimizer(self, inst):
         L.check(self._lib.d2ip_reset_optimizer(self._ctx, inst))
 
@@ -179,6 +191,10 @@ class Context:
     def read_image(self, inst, out=None):
         n = self.geometries[self.instances[inst][0]][0]
         if out is not None:
+            import torch
+            if out.dtype != torch.float32 or not out.is_cuda or out.numel() != n ** 3 \
+                    or not out.is_contiguous():
+                raise TypeError("out must be a contiguous float32 device tensor of n^3 values")
             L.check(self._lib.d2ip_read_image(self._ctx, inst, ctypes.c_void_p(out.data_ptr()), 1))
             return out
         img = np.empty(n ** 3, dtype=np.float32)

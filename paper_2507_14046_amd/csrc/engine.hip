@@ -170,6 +170,11 @@ struct Instance {
   double* rsum = nullptr;
   float* kpart = nullptr;   // split-K partial outputs
   int* counters = nullptr;  // zeroed arrival counters of split-K tiles
+  // 4D-TV: gradient w.r.t. the image, per-block loss partials, image history
+  float *gtv = nullptr, *hist = nullptr;
+  double* tvsum = nullptr;
+  TvState* tvs = nullptr;
+  std::vector<int> tv_count, tv_head;  // host mirror per member
   // group: B members of identical shape; member b's data is b * istride
   // bytes after member 0's (every pointer above is member 0's)
   int B = 1;
@@ -493,6 +498,8 @@ struct d2ip_ctx {
   std::vector<Instance> insts;              // instance groups
   std::vector<std::pair<int, int>> members;  // API instance -> (group, member)
   float lr = 1e-3f, b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+  bool tv_on = false;
+  TvCoef tv{0.002f, 1.f, 0.1f, 1e-8f};
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
   hipStream_t cap = nullptr;  // capture stream (the caller's may be the legacy default stream)
@@ -629,6 +636,7 @@ void plan(d2ip_ctx& X, const d2ip_geometry_desc* gd, int n_geo, const d2ip_insta
     const long long o_tail = dtake((size_t)ntb * (C + 1));
     ln_seg(o_tail, ntb, C + 1, I.tail_w);
     const long long o_rsum = dtake(jt_mblocks(G.M));
+    const long long o_tv = dtake(tv_blocks(V0));
 
     I.theta = cv.take<float>(I.P);
     I.grad = cv.take<float>(I.P);
@@ -702,6 +710,12 @@ void plan(d2ip_ctx& X, const d2ip_geometry_desc* gd, int n_geo, const d2ip_insta
     I.tpart = cv.take<float>((size_t)jt_mblocks(G.M) * G.qa_cap);
     I.tail_part = dp(o_tail);
     I.rsum = dp(o_rsum);
+    I.tvsum = dp(o_tv);
+    I.gtv = cv.take<float>(V0);
+    I.hist = cv.take<float>((size_t)kTvHistory * V0);
+    I.tvs = cv.take<TvState>(1);
+    I.tv_count.assign(I.B, 0);
+    I.tv_head.assign(I.B, kTvHistory - 1);
     I.kpart = cv.take<float>(std::max<size_t>(kpart_max, 1));
     I.counters = cv.take<int>((size_t)tiles_max + 64);
     // members 1.. follow member 0 at a fixed stride
@@ -906,9 +920,9 @@ void L_jtvec(const float* Jc, int M, int qa_pad, const float* ppart, int nqb, co
 }
 
 void L_tail_bwd(const float* tpart, int nmb, int qa_pad, const int* inv, const float* d0, int C,
-                const float* w, size_t V, float* gd0, double* part, int B, long long is,
-                hipStream_t s) {
-  if (!g_chk) return tail_bwd(tpart, nmb, qa_pad, inv, d0, C, w, V, gd0, part, B, is, s);
+                const float* w, size_t V, float* gd0, double* part, const float* gtv, int B,
+                long long is, hipStream_t s) {
+  if (!g_chk) return tail_bwd(tpart, nmb, qa_pad, inv, d0, C, w, V, gd0, part, gtv, B, is, s);
   Checker& c = *g_chk;
   c.where = "tail_bwd";
   c.range(tpart, (size_t)nmb * qa_pad * 4, "tpart", B, is);
@@ -917,6 +931,20 @@ void L_tail_bwd(const float* tpart, int nmb, int qa_pad, const int* inv, const f
   c.range(w, C * 4, "w", B, is);
   c.range(gd0, V * C * 4, "gd0", B, is);
   c.range(part, (size_t)tail_bwd_blocks(V, C) * (C + 1) * 8, "partials", B, is);
+  c.range(gtv, V * 4, "gtv", B, is);
+}
+
+void L_tv(const float* sigma, int n, const float* hist, const TvState* ts, TvCoef k, float* gtv,
+          double* tvsum, int B, long long is, hipStream_t s) {
+  if (!g_chk) return tv_reg(sigma, n, hist, ts, k, gtv, tvsum, B, is, s);
+  Checker& c = *g_chk;
+  c.where = "tv";
+  const size_t V = (size_t)n * n * n;
+  c.range(sigma, V * 4, "sigma", B, is);
+  c.range(hist, (size_t)kTvHistory * V * 4, "history", B, is);
+  c.range(ts, sizeof(TvState), "tv state", B, is);
+  c.range(gtv, V * 4, "gtv", B, is);
+  c.range(tvsum, (size_t)tv_blocks(V) * 8, "tv partials", B, is);
 }
 
 void L_grad_reduce(const Instance& I, float* grad, hipStream_t s) {
@@ -946,7 +974,8 @@ void L_grad_reduce(const Instance& I, float* grad, hipStream_t s) {
 }
 
 void L_adam(Instance& I, const d2ip_ctx& X, hipStream_t s);
-void L_pack(Instance& I, int prec, bool end_iteration, int M, hipStream_t s);
+void L_pack(Instance& I, int prec, bool end_iteration, int M, hipStream_t s,
+            bool tv = false);
 
 // ---------------------------------------------------------------------------
 // launch schedule
@@ -1112,10 +1141,16 @@ void enqueue_iteration(d2ip_ctx& X, Instance& I) {
   enqueue_forward(X, I);
   // measurement operator, data term and its gradient w.r.t. the image
   const int nqb = jvec_qblocks(G.qa_pad);
+  if (X.tv_on) {
+    // the 4D-TV term only needs the image: beside the J products
+    fork(X);
+    L_tv(I.sigma, I.n, I.hist, I.tvs, X.tv, I.gtv, I.tvsum, I.B, I.istride, X.side);
+  }
   L_jvec(G.Jc, G.M, G.qa_pad, G.idx, I.sigma, I.ppart, I.V0, I.B, I.istride, s);
   L_jtvec(G.Jc, G.M, G.qa_pad, I.ppart, nqb, I.dv, I.rsum, I.tpart, I.B, I.istride, s);
+  if (X.tv_on) join(X);
   L_tail_bwd(I.tpart, jt_mblocks(G.M), G.qa_pad, G.inv, I.blocks.back().y, I.C, th + I.tail_w,
-           I.V0, I.lv[0].gy, I.tail_part, I.B, I.istride, s);
+           I.V0, I.lv[0].gy, I.tail_part, X.tv_on ? I.gtv : nullptr, I.B, I.istride, s);
   // network backward, decoder first.  Weight gradients only feed the batched
   // reduction at the end: they run on the side stream, overlapping the
   // input-gradient chain, and join before the reduction.
@@ -1171,7 +1206,7 @@ void enqueue_iteration(d2ip_ctx& X, Instance& I) {
   join(X);
   L_grad_reduce(I, gr, s);
   L_adam(I, X, s);
-  L_pack(I, X.precision, true, G.M, s);
+  L_pack(I, X.precision, true, G.M, s, X.tv_on);
 }
 
 // One iteration of every instance group: groups on different lanes run
@@ -1217,13 +1252,15 @@ void L_adam(Instance& I, const d2ip_ctx& X, hipStream_t s) {
   c.range(I.it, sizeof(IterState), "iteration state", I.B, I.istride);
 }
 
-void L_pack(Instance& I, int precision, bool end_iteration, int M, hipStream_t s) {
+void L_pack(Instance& I, int precision, bool end_iteration, int M, hipStream_t s, bool tv) {
   const long long lo = precision == D2IP_BF16X3_CONV ? I.wtotal : 0;
   const int nrs = jt_mblocks(M);
+  const int ntv = end_iteration && tv ? tv_blocks(I.V0) : 0;
   if (!g_chk)
     return pack_weights(I.packs_dev, (int)I.packs.size(), I.max_pack, I.theta, I.wf32, I.wbf16,
                         lo, end_iteration ? I.it : nullptr, end_iteration ? I.rsum : nullptr,
-                        end_iteration ? nrs : 0, end_iteration ? M : 1, I.B, I.istride, s);
+                        end_iteration ? nrs : 0, end_iteration ? M : 1, I.tvsum, ntv, I.B,
+                        I.istride, s);
   Checker& c = *g_chk;
   c.where = "pack_weights";
   c.range(I.packs_dev, I.packs.size() * sizeof(ConvPack), "pack table");
@@ -1243,6 +1280,7 @@ void L_pack(Instance& I, int precision, bool end_iteration, int M, hipStream_t s
       }
     }
   }
+  if (ntv) c.range(I.tvsum, (size_t)ntv * 8, "tv partials", I.B, I.istride);
   if (end_iteration) {
     c.range(I.rsum, nrs * 8, "rsum", I.B, I.istride);
     c.range(I.it, sizeof(IterState), "iteration state", I.B, I.istride);
@@ -1369,6 +1407,7 @@ d2ip_status d2ip_check_launches(const d2ip_geometry_desc* geos, int n_geo,
   d2ip_ctx X;
   X.precision = precision;
   X.flags = flags;
+  X.tv_on = true;  // walk the optional 4D-TV launches too
   Carver cv;
   cv.base = reinterpret_cast<char*>((uintptr_t)1 << 40);  // never dereferenced
   g_chk = &c;
@@ -1943,6 +1982,62 @@ d2ip_status d2ip_time_kernel(d2ip_ctx* X, int inst, int which, int block, int re
   HIPCHK(hipGetLastError());
   *avg_ms = (double)ms / reps;
   return D2IP_OK;
+}
+
+d2ip_status d2ip_set_tv(d2ip_ctx* X, const d2ip_tv_cfg* cfg) {
+  if (!X || !cfg) return fail(D2IP_EINVAL, "null argument");
+  if (!(cfg->lambda_tv >= 0.f) || !(cfg->lambda_s >= 0.f) || !(cfg->lambda_t >= 0.f) ||
+      !(cfg->eps > 0.f))
+    return fail(D2IP_EINVAL, "4D-TV needs lambda_tv, lambda_s, lambda_t >= 0 and eps > 0");
+  X->tv_on = cfg->lambda_tv > 0.f;
+  X->tv = TvCoef{cfg->lambda_tv, cfg->lambda_s, cfg->lambda_t, cfg->eps};
+  drop_graph(X);
+  return D2IP_OK;
+}
+
+namespace {
+// Upload member mb's history ring state with weights exp(-k) / sum, k = 1..count.
+d2ip_status put_tv_state(d2ip_ctx* X, Instance& I, int mb) {
+  TvState t;
+  std::memset(&t, 0, sizeof(t));
+  t.count = I.tv_count[mb];
+  t.head = I.tv_head[mb];
+  double sum = 0.0;
+  for (int k = 1; k <= t.count; ++k) sum += std::exp(-(double)k);
+  for (int k = 1; k <= t.count; ++k) t.w[k - 1] = (float)(std::exp(-(double)k) / sum);
+  HIPCHK(hipMemcpyAsync(ishift(I.tvs, (long long)mb * I.istride), &t, sizeof(t),
+                        hipMemcpyHostToDevice, X->stream));
+  HIPCHK(hipStreamSynchronize(X->stream));
+  return D2IP_OK;
+}
+}  // namespace
+
+d2ip_status d2ip_commit_frame(d2ip_ctx* X, int inst) {
+  d2ip_status st = check_inst(X, inst);
+  if (st != D2IP_OK) return st;
+  Instance& I = X->insts[X->members[inst].first];
+  const int mb = X->members[inst].second;
+  const long long mo = (long long)mb * I.istride;
+  if (!X->geos[I.geo].set) return fail(D2IP_ESTATE, "geometry not set");
+  for (int b = 0; b < I.B; ++b)
+    if (!I.has_z[b]) return fail(D2IP_ESTATE, "noise input not set");
+  enqueue_forward(*X, I);  // the image at the current theta
+  const int slot = (I.tv_head[mb] + 1) % kTvHistory;
+  HIPCHK(hipMemcpyAsync(ishift(I.hist, mo) + (size_t)slot * I.V0, ishift(I.sigma, mo),
+                        I.V0 * sizeof(float), hipMemcpyDeviceToDevice, X->stream));
+  I.tv_head[mb] = slot;
+  I.tv_count[mb] = std::min(I.tv_count[mb] + 1, kTvHistory);
+  return put_tv_state(X, I, mb);
+}
+
+d2ip_status d2ip_clear_history(d2ip_ctx* X, int inst) {
+  d2ip_status st = check_inst(X, inst);
+  if (st != D2IP_OK) return st;
+  Instance& I = X->insts[X->members[inst].first];
+  const int mb = X->members[inst].second;
+  I.tv_count[mb] = 0;
+  I.tv_head[mb] = kTvHistory - 1;
+  return put_tv_state(X, I, mb);
 }
 
 d2ip_status d2ip_read_image(d2ip_ctx* X, int inst, float* sigma, int on_device) {

@@ -154,11 +154,12 @@ constexpr int kTailVoxels = 256;
 __global__ __launch_bounds__(256) void k_tail_bwd(const float* tpart, int nmb, int qa_pad,
                                                   const int* __restrict__ inv, const float* d0,
                                                   int C, const float* w, size_t V, float* gd0,
-                                                  double* part, long long istride) {
+                                                  double* part, const float* gtv,
+                                                  long long istride) {
   {
     const long long off = (long long)blockIdx.y * istride;
     tpart = ishift(tpart, off); d0 = ishift(d0, off); w = ishift(w, off);
-    gd0 = ishift(gd0, off); part = ishift(part, off);
+    gd0 = ishift(gd0, off); part = ishift(part, off); gtv = ishift(gtv, off);
   }
   __shared__ float gsv[kTailVoxels];
   __shared__ double sh[256];
@@ -169,8 +170,10 @@ __global__ __launch_bounds__(256) void k_tail_bwd(const float* tpart, int nmb, i
     float g = 0.f;
     if (v < V) {
       const int q = inv[v];
-      if (q >= 0)
+      if (q >= 0) {
         for (int k = 0; k < nmb; ++k) g += tpart[(size_t)k * qa_pad + q];
+        if (gtv) g += gtv[v];  // the image is masked: d sigma / d out = mask
+      }
     }
     gsv[tid] = g;
   }
@@ -241,16 +244,20 @@ __device__ __forceinline__ void put_bf(uint16_t* w, long long i, long long lo_of
 
 __global__ void k_pack_weights(const ConvPack* __restrict__ packs, const float* theta,
                                float* wf32, uint16_t* wbf16, long long lo_off, IterState* it,
-                               const double* rsum, int nrs, int M, long long istride) {
+                               const double* rsum, int nrs, int M, const double* tvsum, int ntv,
+                               long long istride) {
   {
     const long long off = (long long)blockIdx.z * istride;
     theta = ishift(theta, off); wf32 = ishift(wf32, off); wbf16 = ishift(wbf16, off);
-    it = ishift(it, off); rsum = ishift(rsum, off);
+    it = ishift(it, off); rsum = ishift(rsum, off); tvsum = ishift(tvsum, off);
   }
   if (it && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) {
     double L = 0.0;
     for (int k = 0; k < nrs; ++k) L += rsum[k];
     L /= M;
+    double R = 0.0;
+    for (int k = 0; k < ntv; ++k) R += tvsum[k];
+    L += R;
     it->loss = L;
     if (!isfinite(L)) it->nonfinite = 1;
     it->t = it->t + 1;
@@ -327,6 +334,62 @@ __global__ void k_jt_sum(const float* part, int Q, float* out) {
   reinterpret_cast<float4*>(out)[q4] = acc;
 }
 
+// 4D-TV of one image (Sec. III-E, Eqs. (11)-(13)), one thread per voxel.
+// Spatial: q(v) = sqrt(dz^2 + dy^2 + dx^2 + eps) of the forward differences
+// (0 where the neighbour is outside the grid); v's gradient collects -d/q(v)
+// of its own differences and +d/q(u) of the differences of u = v - e that
+// end at v.  Temporal: sum_k w_k sqrt((s - h_k)^2 + eps) over the history.
+// Writes gtv[v] and one FP64 partial of lam * R per block (fixed order).
+__device__ __forceinline__ float tv_q(const float* s, int z, int y, int x, int n, float eps) {
+  const size_t v = ((size_t)z * n + y) * n + x;
+  const float c = s[v];
+  const float dz = z + 1 < n ? s[v + (size_t)n * n] - c : 0.f;
+  const float dy = y + 1 < n ? s[v + n] - c : 0.f;
+  const float dx = x + 1 < n ? s[v + 1] - c : 0.f;
+  return sqrtf(dz * dz + dy * dy + dx * dx + eps);
+}
+
+__global__ __launch_bounds__(256) void k_tv(const float* sigma, int n, const float* hist,
+                                            const TvState* ts, TvCoef c, float* gtv,
+                                            double* tvsum, long long istride) {
+  {
+    const long long off = (long long)blockIdx.y * istride;
+    sigma = ishift(sigma, off); hist = ishift(hist, off); ts = ishift(ts, off);
+    gtv = ishift(gtv, off); tvsum = ishift(tvsum, off);
+  }
+  __shared__ double sh[8];
+  const size_t V = (size_t)n * n * n;
+  const size_t v = (size_t)blockIdx.x * 256 + threadIdx.x;
+  double part = 0.0;
+  if (v < V) {
+    const int x = (int)(v % n), y = (int)((v / n) % n), z = (int)(v / ((size_t)n * n));
+    const float s = sigma[v];
+    const float dz = z + 1 < n ? sigma[v + (size_t)n * n] - s : 0.f;
+    const float dy = y + 1 < n ? sigma[v + n] - s : 0.f;
+    const float dx = x + 1 < n ? sigma[v + 1] - s : 0.f;
+    const float q = sqrtf(dz * dz + dy * dy + dx * dx + c.eps);
+    float gs = -(dz + dy + dx) / q;
+    if (z > 0) gs += (s - sigma[v - (size_t)n * n]) / tv_q(sigma, z - 1, y, x, n, c.eps);
+    if (y > 0) gs += (s - sigma[v - n]) / tv_q(sigma, z, y - 1, x, n, c.eps);
+    if (x > 0) gs += (s - sigma[v - 1]) / tv_q(sigma, z, y, x - 1, n, c.eps);
+    const float invV = 1.f / (float)V;
+    float gt = 0.f;
+    double rt = 0.0;
+    const int cnt = ts->count, head = ts->head;
+    for (int k = 1; k <= cnt; ++k) {
+      const int slot = (head - k + 1 + kTvHistory) % kTvHistory;
+      const float d = s - hist[(size_t)slot * V + v];
+      const float qt = sqrtf(d * d + c.eps);
+      gt += ts->w[k - 1] * (d / qt);
+      rt += (double)ts->w[k - 1] * qt;
+    }
+    gtv[v] = c.lam * (c.lam_s * gs * invV + c.lam_t * gt);
+    part = (double)c.lam * ((double)c.lam_s * q / (double)V + (double)c.lam_t * rt);
+  }
+  part = block_sum(part, sh);
+  if (threadIdx.x == 0) tvsum[blockIdx.x] = part;
+}
+
 inline int grid_for(size_t work) {
   size_t b = (work + 255) / 256;
   if (b > 8192) b = 8192;
@@ -375,10 +438,10 @@ int tail_bwd_blocks(size_t V, int C) {
 }
 
 void tail_bwd(const float* tpart, int nmb, int qa_pad, const int* inv, const float* d0, int C,
-              const float* w, size_t V, float* gd0, double* part, int batch, long long istride,
-              hipStream_t s) {
+              const float* w, size_t V, float* gd0, double* part, const float* gtv, int batch,
+              long long istride, hipStream_t s) {
   hipLaunchKernelGGL(k_tail_bwd, dim3(tail_bwd_blocks(V, C), batch), dim3(256), 0, s, tpart, nmb,
-                     qa_pad, inv, d0, C, w, V, gd0, part, istride);
+                     qa_pad, inv, d0, C, w, V, gd0, part, gtv, istride);
 }
 
 void adam(float* theta, const float* g, float* m, float* v, size_t P, float lr, float beta1,
@@ -390,12 +453,12 @@ void adam(float* theta, const float* g, float* m, float* v, size_t P, float lr, 
 
 void pack_weights(const ConvPack* packs, int npacks, int max_elems, const float* theta,
                   float* wf32, uint16_t* wbf16, long long lo_off, IterState* it,
-                  const double* rsum, int nrs, int M, int batch, long long istride,
-                  hipStream_t s) {
+                  const double* rsum, int nrs, int M, const double* tvsum, int ntv, int batch,
+                  long long istride, hipStream_t s) {
   dim3 grid((max_elems + 255) / 256, npacks, batch);
   if (grid.x > 1024) grid.x = 1024;
   hipLaunchKernelGGL(k_pack_weights, grid, dim3(256), 0, s, packs, theta, wf32, wbf16, lo_off, it,
-                     rsum, nrs, M, istride);
+                     rsum, nrs, M, tvsum, ntv, istride);
 }
 
 void jv_dense(const float* J, int M, int Q, const float* sigma, float* p, hipStream_t s) {
@@ -409,6 +472,15 @@ void jt_dense(const float* J, int M, int Q, const float* g, float* part, float* 
   const int bx = (Q / 4 + 255) / 256;
   hipLaunchKernelGGL(k_jt_dense, dim3(bx, kJtSlices), dim3(256), 0, s, J, M, Q, g, part);
   hipLaunchKernelGGL(k_jt_sum, dim3(bx), dim3(256), 0, s, part, Q, out);
+}
+
+int tv_blocks(size_t V) { return (int)((V + 255) / 256); }
+
+void tv_reg(const float* sigma, int n, const float* hist, const TvState* ts, TvCoef c, float* gtv,
+            double* tvsum, int batch, long long istride, hipStream_t s) {
+  const size_t V = (size_t)n * n * n;
+  hipLaunchKernelGGL(k_tv, dim3(tv_blocks(V), batch), dim3(256), 0, s, sigma, n, hist, ts, c, gtv,
+                     tvsum, istride);
 }
 
 }  // namespace d2ip

@@ -144,6 +144,19 @@ struct IterState {
   float bc1, bc2;   // 1 - beta1^t, 1 - beta2^t
 };
 
+// 4D-TV state of one instance (Sec. III-E): the last `count` frames' images
+// sit in a ring of kTvHistory slots, the k-th most recent (k = 1..count) in
+// slot (head - k + 1) mod kTvHistory, with normalised weight w[k - 1].
+constexpr int kTvHistory = 32;
+struct TvState {
+  int count, head;
+  float w[kTvHistory];
+};
+// Coefficients of the 4D-TV term.
+struct TvCoef {
+  float lam, lam_s, lam_t, eps;
+};
+
 struct ConvPack {  // one conv of the flat parameter vector
   int th_off, cout, cin_real, cin, taps, need_dgrad;
   long long wf_off, wd_off;  // element offsets in the packed buffers
@@ -177,8 +190,8 @@ int tail_bwd_blocks(size_t V, int C);
 // part[blk][c] = sum gs*d0[.][c], part[blk][C] = sum gs (gradient of the head,
 // reduced by grad_reduce).
 void tail_bwd(const float* tpart, int nmb, int qa_pad, const int* inv, const float* d0, int C,
-              const float* w, size_t V, float* gd0, double* part, int batch, long long istride,
-              hipStream_t s);
+              const float* w, size_t V, float* gd0, double* part, const float* gtv, int batch,
+              long long istride, hipStream_t s);
 // Adam step t + 1 (t = it->t, bias corrections 1 - beta^(t+1)).
 void adam(float* theta, const float* g, float* m, float* v, size_t P, float lr, float beta1,
           float beta2, float eps, const IterState* it, int batch, long long istride,
@@ -189,8 +202,13 @@ void adam(float* theta, const float* g, float* m, float* v, size_t P, float lr, 
 // the non-finite flag, and t += 1.
 void pack_weights(const ConvPack* packs, int npacks, int max_elems, const float* theta,
                   float* wf32, uint16_t* wbf16, long long lo_off, IterState* it,
-                  const double* rsum, int nrs, int M, int batch, long long istride,
-                  hipStream_t s);
+                  const double* rsum, int nrs, int M, const double* tvsum, int ntv, int batch,
+                  long long istride, hipStream_t s);
+int tv_blocks(size_t V);
+// 4D-TV of the image sigma (n^3): gtv = d(lam * R_4D-TV)/d sigma and per-block
+// partial sums of lam * R_4D-TV (Eqs. (11)-(13)); history per TvState.
+void tv_reg(const float* sigma, int n, const float* hist, const TvState* ts, TvCoef c, float* gtv,
+            double* tvsum, int batch, long long istride, hipStream_t s);
 
 // ---- standalone operators (op-level C-ABI) ----
 int block_stats_blocks(size_t n);

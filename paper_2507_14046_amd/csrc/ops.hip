@@ -128,7 +128,7 @@ d2ip_status conv_prepare(ConvOp& c, const float* w, hipStream_t s) {
   const int td = conv_tiles(c.n, c.d_tile) * ((c.cin + c.d_bn - 1) / c.d_bn);
   OPCHK(hipMemsetAsync(c.counters, 0, ((size_t)std::max(tf, td) + 64) * sizeof(int), s));
   pack_weights(c.pack, 1, c.cout * c.cin * c.taps, w, c.wf32, c.wbf16,
-               c.prec == PREC_BF16X3 ? c.wtotal : 0, nullptr, nullptr, 0, 1, 1, 0, s);
+               c.prec == PREC_BF16X3 ? c.wtotal : 0, nullptr, nullptr, 0, 1, nullptr, 0, 1, 0, s);
   return D2IP_OK;
 }
 

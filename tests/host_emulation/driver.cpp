@@ -69,6 +69,13 @@ static int run_case(const std::vector<d2ip_geometry_desc>& G,
   }
   EXPECT_ERR(d2ip_set_frame(X, (int)I.size(), nullptr, 0), D2IP_EINVAL);
   CK(d2ip_run(X, 4, loss.data()));
+  d2ip_tv_cfg tv = {0.002f, 1.f, 0.1f, 1e-8f};
+  CK(d2ip_set_tv(X, &tv));
+  for (int rep = 0; rep < 34; ++rep) CK(d2ip_commit_frame(X, rep % (int)I.size()));
+  CK(d2ip_run(X, 2, loss.data()));
+  CK(d2ip_clear_history(X, 0));
+  tv.eps = 0.f;
+  EXPECT_ERR(d2ip_set_tv(X, &tv), D2IP_EINVAL);
   d2ip_adam_cfg cfg = {2e-3f, 0.9f, 0.999f, 1e-8f};
   CK(d2ip_set_adam(X, &cfg));
   CK(d2ip_run(X, 2, nullptr));

@@ -161,7 +161,7 @@ def test_device_inputs_match_host_inputs(lib, probs):
     b.set_noise_input(0, dev(p["Z"]))
     b.set_frame(0, dev(p["dv"][0]))
     assert a.run(2)[0] == b.run(2)[0]
-    out = torch.empty(16 ** 3, device="cuda")
+    out = torch.empty(16 ** 3, dtype=torch.float32, device="cuda")
     b.read_image(0, out=out)
     torch.cuda.synchronize()
     np.testing.assert_array_equal(out.cpu().numpy(), a.read_image(0))

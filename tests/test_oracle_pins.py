@@ -15,7 +15,17 @@ import torch.nn.functional as F
 import tseit_synth as ts
 from oracle import net, fit
 
-torch.set_default_dtype(torch.float64)
+
+
+@pytest.fixture(autouse=True)
+def _float64_torch():
+    # torch builds its reference tensors in float64 inside this module only;
+    # the default is restored so GPU tests collected in the same process keep
+    # float32 defaults
+    prev = torch.get_default_dtype()
+    torch.set_default_dtype(torch.float64)
+    yield
+    torch.set_default_dtype(prev)
 
 
 def _rng(s):
