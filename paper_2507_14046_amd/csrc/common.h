@@ -66,37 +66,62 @@ struct PairRef {
   double count;        // elements normalised together
 };
 
-// Block-wide sum of `n` (a, b) pairs in a fixed order; the same value in all
-// threads.  Contains barriers: every thread of the block must call it.
-__device__ __forceinline__ void block_pair_sum(const double* part, int n, double& s1, double& s2) {
-  __shared__ double sh[2][16];
-  double a = 0.0, b = 0.0;
-  for (int i = threadIdx.x; i < n; i += blockDim.x) {
-    a += part[2 * i];
-    b += part[2 * i + 1];
+// Block-wide sums of the (a, b) pairs of up to two partial arrays, in a fixed
+// order; the same values in all threads.  Thread t adds pairs t, t + 256, ...
+// (the first four loads of each array issued together), waves combine by a
+// butterfly, then the four wave totals are added in wave order.  Contains
+// barriers: every thread of the block must call it (blockDim.x == 256).
+__device__ __forceinline__ void block_pair_sums(const double* p1, int n1, const double* p2, int n2,
+                                                double& s1, double& s2, double& s3, double& s4) {
+  __shared__ double sh[4][4];
+  const int t = threadIdx.x;
+  double a = 0.0, b = 0.0, c = 0.0, d = 0.0;
+  double ra[4], rb[4], rc[4], rd[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int i = t + 256 * k;
+    ra[k] = i < n1 ? p1[2 * i] : 0.0;
+    rb[k] = i < n1 ? p1[2 * i + 1] : 0.0;
+    rc[k] = i < n2 ? p2[2 * i] : 0.0;
+    rd[k] = i < n2 ? p2[2 * i + 1] : 0.0;
+  }
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    a += ra[k];
+    b += rb[k];
+    c += rc[k];
+    d += rd[k];
+  }
+  for (int i = t + 1024; i < n1; i += 256) {
+    a += p1[2 * i];
+    b += p1[2 * i + 1];
+  }
+  for (int i = t + 1024; i < n2; i += 256) {
+    c += p2[2 * i];
+    d += p2[2 * i + 1];
   }
   a = wave_sum(a);
   b = wave_sum(b);
-  const int w = threadIdx.x >> 6;
+  c = wave_sum(c);
+  d = wave_sum(d);
+  const int w = t >> 6;
   __syncthreads();
-  if ((threadIdx.x & 63) == 0) {
+  if ((t & 63) == 0) {
     sh[0][w] = a;
     sh[1][w] = b;
+    sh[2][w] = c;
+    sh[3][w] = d;
   }
   __syncthreads();
-  s1 = 0.0;
-  s2 = 0.0;
-  for (int i = 0; i < (int)(blockDim.x >> 6); ++i) {
-    s1 += sh[0][i];
-    s2 += sh[1][i];
-  }
+  s1 = (sh[0][0] + sh[0][1]) + (sh[0][2] + sh[0][3]);
+  s2 = (sh[1][0] + sh[1][1]) + (sh[1][2] + sh[1][3]);
+  s3 = (sh[2][0] + sh[2][1]) + (sh[2][2] + sh[2][3]);
+  s4 = (sh[3][0] + sh[3][1]) + (sh[3][2] + sh[3][3]);
 }
 
-__device__ __forceinline__ LnStat stat_of(const PairRef& r) {
-  double s1, s2;
-  block_pair_sum(r.part, r.nparts, s1, s2);
-  const double mean = s1 / r.count;
-  double var = s2 / r.count - mean * mean;
+__device__ __forceinline__ LnStat stat_from(double s1, double s2, double count) {
+  const double mean = s1 / count;
+  double var = s2 / count - mean * mean;
   if (var < 0.0) var = 0.0;
   LnStat st;
   st.mean = (float)mean;
@@ -104,13 +129,29 @@ __device__ __forceinline__ LnStat stat_of(const PairRef& r) {
   return st;
 }
 
+__device__ __forceinline__ LnStat stat_of(const PairRef& r) {
+  double s1, s2, s3, s4;
+  block_pair_sums(r.part, r.nparts, nullptr, 0, s1, s2, s3, s4);
+  return stat_from(s1, s2, r.count);
+}
+
 __device__ __forceinline__ LnBwd coef_of(const PairRef& r) {
-  double s1, s2;
-  block_pair_sum(r.part, r.nparts, s1, s2);
+  double s1, s2, s3, s4;
+  block_pair_sums(r.part, r.nparts, nullptr, 0, s1, s2, s3, s4);
   LnBwd c;
   c.A = (float)(s1 / r.count);
   c.B = (float)(s2 / r.count);
   return c;
+}
+
+// Statistics and LayerNorm-backward coefficients from one combined reduction.
+__device__ __forceinline__ void stat_coef_of(const PairRef& st, const PairRef& bw, LnStat& s,
+                                             LnBwd& c) {
+  double s1, s2, s3, s4;
+  block_pair_sums(st.part, st.nparts, bw.part, bw.nparts, s1, s2, s3, s4);
+  s = stat_from(s1, s2, st.count);
+  c.A = (float)(s3 / bw.count);
+  c.B = (float)(s4 / bw.count);
 }
 
 // "Last block finalises": called by every thread of a block after the block

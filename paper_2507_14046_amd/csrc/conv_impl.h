@@ -130,13 +130,16 @@ __device__ __forceinline__ void src_consts(const ConvSrc& s, float& mean, float&
   rstd = 1.f;
   A = 0.f;
   B = 0.f;
-  if (PRO != PRO_NONE) {
+  if (PRO == PRO_LN_RELU) {
     const LnStat st = stat_of(s.st);
     mean = st.mean;
     rstd = st.rstd;
-  }
-  if (PRO == PRO_LN_BWD) {
-    const LnBwd c = coef_of(s.bw);
+  } else if (PRO == PRO_LN_BWD) {
+    LnStat st;
+    LnBwd c;
+    stat_coef_of(s.st, s.bw, st, c);
+    mean = st.mean;
+    rstd = st.rstd;
     A = c.A;
     B = c.B;
   }
@@ -226,33 +229,56 @@ constexpr int halo_nb() {
   return (HP * (kCkMax / 4) + 255) / 256;
 }
 
+// Per-thread geometry of its halo elements, the same for every tile and
+// chunk of a launch: the element's position inside the halo (hz, hy, hx in
+// bytes 0..2; -1 when the element lies beyond the halo) and its offset from
+// the halo origin in the source tensor.
+template <int NB>
+struct HaloIdx {
+  int pos[NB];
+  int rel[NB];
+};
+
+template <int NB, int HZ, int HY, int HX>
+__device__ __forceinline__ void halo_prep(HaloIdx<NB>& hi, int n, int stride, int qs) {
+  constexpr int HP = HZ * HY * HX;
+  const int total = HP << qs;
+  const int q = threadIdx.x & ((1 << qs) - 1);
+#pragma unroll
+  for (int k = 0; k < NB; ++k) {
+    const int p = k * 256 + threadIdx.x;
+    const int pos = p >> qs;
+    const int hx = pos % HX, hy = (pos / HX) % HY, hz = pos / (HX * HY);
+    hi.pos[k] = p < total ? (hz | (hy << 8) | (hx << 16)) : -1;
+    hi.rel[k] = ((hz * n + hy) * n + hx) * stride + 4 * q;
+  }
+}
+
 // Issue the loads of a (HZ x HY x HX) halo of ck = 4 << qs channels starting
 // at ci0, anchored at (z0, y0, x0) - R.
 template <int NB, int PRO, int HZ, int HY, int HX>
-__device__ __forceinline__ void halo_load(Quads<NB, PRO>& r, const ConvSrc& s, int n, int qs,
-                                          int ci0, int z0, int y0, int x0, int R) {
+__device__ __forceinline__ void halo_load(Quads<NB, PRO>& r, const HaloIdx<NB>& hi,
+                                          const ConvSrc& s, int n, int qs, int ci0, int z0,
+                                          int y0, int x0, int R) {
   constexpr int HP = HZ * HY * HX;
   const int total = HP << qs;
-  const int c = ci0 + 4 * (threadIdx.x & ((1 << qs) - 1));
+  const int oz = z0 - R, oy = y0 - R, ox = x0 - R;
+  const long long base = ((long long)(oz * n + oy) * n + ox) * s.stride + ci0;
   r.in = 0u;
 #pragma unroll
   for (int k = 0; k < NB; ++k) {
     r.v[k] = make_float4(0.f, 0.f, 0.f, 0.f);
     if constexpr (PRO == PRO_LN_BWD) r.h[k] = r.v[k];
     if (k * 256 >= total) continue;  // uniform: dead for smaller chunks
-    const int p = k * 256 + threadIdx.x;
-    const int pos = p >> qs;
-    const int hx = pos % HX, hy = (pos / HX) % HY, hz = pos / (HX * HY);
-    const int gz = z0 + hz - R, gy = y0 + hy - R, gx = x0 + hx - R;
-    const bool ok = p < total && gz >= 0 && gz < n && gy >= 0 && gy < n && gx >= 0 && gx < n;
-    float4 v = make_float4(0.f, 0.f, 0.f, 0.f), h = v;
+    const int ps = hi.pos[k];
+    const bool ok = ps >= 0 && (unsigned)(oz + (ps & 255)) < (unsigned)n &&
+                    (unsigned)(oy + ((ps >> 8) & 255)) < (unsigned)n &&
+                    (unsigned)(ox + (ps >> 16)) < (unsigned)n;
     if (ok) {
-      const size_t i = (size_t)((gz * n + gy) * n + gx) * s.stride + c;
-      v = *reinterpret_cast<const float4*>(s.x + i);
-      if (PRO == PRO_LN_BWD) h = *reinterpret_cast<const float4*>(s.h + i);
+      const long long i = base + hi.rel[k];
+      r.v[k] = *reinterpret_cast<const float4*>(s.x + i);
+      if constexpr (PRO == PRO_LN_BWD) r.h[k] = *reinterpret_cast<const float4*>(s.h + i);
     }
-    r.v[k] = v;
-    if constexpr (PRO == PRO_LN_BWD) r.h[k] = h;
     r.in |= (ok ? 1u : 0u) << k;
   }
 }
@@ -404,8 +430,11 @@ __global__ __launch_bounds__(256) void k_conv_fwd(ConvFwd a) {
   const int qs = ck_shift - 2;
   constexpr int NBH = halo_nb<HP>();
   Quads<NBH, PRO> hq;
+  HaloIdx<NBH> hidx;
+  halo_prep<NBH, HZ, HY, HX>(hidx, n, a.src.stride, qs);
   // first chunk's halo in flight while the prologue statistics are reduced
-  halo_load<NBH, PRO, HZ, HY, HX>(hq, a.src, n, qs, (kz * cps) << ck_shift, z0, y0, x0, R);
+  halo_load<NBH, PRO, HZ, HY, HX>(hq, hidx, a.src, n, qs, (kz * cps) << ck_shift, z0, y0, x0,
+                                  R);
   float pmean, prstd, pA, pB;
   src_consts<PRO>(a.src, pmean, prstd, pA, pB);
   for (int ch = kz * cps; ch < (kz + 1) * cps; ++ch) {
@@ -458,7 +487,8 @@ __global__ __launch_bounds__(256) void k_conv_fwd(ConvFwd a) {
     __syncthreads();
     // next chunk's halo loads run under this chunk's MFMAs
     if (ch + 1 < (kz + 1) * cps)
-      halo_load<NBH, PRO, HZ, HY, HX>(hq, a.src, n, qs, (ch + 1) << ck_shift, z0, y0, x0, R);
+      halo_load<NBH, PRO, HZ, HY, HX>(hq, hidx, a.src, n, qs, (ch + 1) << ck_shift, z0, y0, x0,
+                                      R);
 #pragma unroll 2
     for (int step = wave; step < nstep; step += 4) {
       const uint32_t ko = ktab[step * 4 + g];
@@ -699,6 +729,8 @@ __global__ __launch_bounds__(256) void k_conv_wgrad(ConvWgrad a) {
   const int gco = co0 + 4 * (tid & 3);  // output channels of this thread's g quads
   Quads<NBH, PRO> hq;
   Quads<NBG, GPRO> gq;
+  HaloIdx<NBH> hidx;
+  halo_prep<NBH, HZ, HY, HX>(hidx, n, a.src.stride, qs);
   auto issue = [&](int t) {
     int b = t;
     const int x0 = (b % ntx) * TX;
@@ -706,7 +738,7 @@ __global__ __launch_bounds__(256) void k_conv_wgrad(ConvWgrad a) {
     const int y0 = (b % nty) * TY;
     b /= nty;
     const int z0 = b * TZ;
-    halo_load<NBH, PRO, HZ, HY, HX>(hq, a.src, n, qs, ci0, z0, y0, x0, R);
+    halo_load<NBH, PRO, HZ, HY, HX>(hq, hidx, a.src, n, qs, ci0, z0, y0, x0, R);
     gq.in = 0u;
 #pragma unroll
     for (int k = 0; k < NBG; ++k) {

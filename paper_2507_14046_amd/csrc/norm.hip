@@ -273,8 +273,9 @@ __global__ __launch_bounds__(256) void k_block_stats(const float* x, size_t n, s
 // the statistics of h and the coefficients (A, B) reduced from partials.
 __global__ void k_ln_dx(const float4* gz, const float4* h, PairRef st, PairRef bw,
                         const float* gamma, float4* gx, size_t n4, int C) {
-  const LnStat s = stat_of(st);
-  const LnBwd k = coef_of(bw);
+  LnStat s;
+  LnBwd k;
+  stat_coef_of(st, bw, s, k);
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n4;
        i += (size_t)gridDim.x * blockDim.x) {
     const int c = (int)((i * 4) % C);
