@@ -232,7 +232,7 @@ typedef struct {
   int ck;    /* input channels staged per step: 8, 16 or 32, dividing the pass's input */
   int split; /* passes 0/1: blocks sharing the channel chunks (split-K; divides
                 the chunk count; 1 for forward 1x1 convs); pass 2: voxel
-                splits, 1..min(64, voxel tiles) */
+                splits, 1..min(256, voxel tiles) */
 } d2ip_conv_shape;
 
 /* One pass of one convolution and its shape.  The convolution is named by

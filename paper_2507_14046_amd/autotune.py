@@ -3,9 +3,11 @@
 Each pass (forward, input gradient, weight gradient) of each convolution of a
 workload is timed in isolation on the GPU (``d2ip_time_conv``) for every valid
 launch shape: voxel tile, output-channel tile, staged channel chunk and split
-(split-K for passes 0/1, voxel splits for the weight gradient).  The fastest
-shape per pass becomes an entry of the process-wide tuning table that later
-plans use (``d2ip_set_tuning``).  Tables are plain JSON lists of entries.
+(split-K for passes 0/1, voxel splits for the weight gradient).  A weight
+gradient's cost also counts the reading of its per-split partials by the
+batched reduction that follows (``reduce_ms``).  The cheapest shape per pass
+becomes an entry of the process-wide tuning table that later plans use
+(``d2ip_set_tuning``).  Tables are plain JSON lists of entries.
 
     python -m paper_2507_14046_amd.autotune --out paper_2507_14046_amd/tuned_mi355x.json
 """
@@ -69,7 +71,7 @@ def candidates(e):
             if kin % ck:
                 continue
             if e["pass"] == 2:
-                for split in (1, 2, 4, 8, 16, 24, 32, 48, 64):
+                for split in (1, 2, 4, 8, 16, 24, 32, 48, 64, 96, 128, 192, 256):
                     out.append(dict(tile=tile, bn=0, ck=ck, split=split))
             else:
                 nch = kin // ck
@@ -101,27 +103,49 @@ def time_pass(e, shape, reps=20, device=0):
     return ms.value
 
 
-def tune(geometries, instances, precision="fp32", reps=10, log=None, margin=0.97):
-    """Tuning entries for every distinct conv pass of the workload.
+# rate at which partial bytes are charged to a weight gradient (bytes per ms).
+# The batched reduction reads them at about 3.9 TB/s on MI355X (83 MB in
+# 21.5 us), but it runs on the critical path after both streams join, while the
+# weight gradients overlap the input-gradient chain; charging 2.5 TB/s weights
+# the exposed reduction above the overlapped launch.
+REDUCE_BYTES_PER_MS = 2.5e9
 
-    Every valid shape is timed with `reps` launches; the three fastest and
+
+def reduce_ms(e, shape):
+    """Time the batched reduction spends on the partials of pass `e` (0 for
+    passes 0/1): splits x (weights + bias) FP32 partials per output tile."""
+    if e["pass"] != 2:
+        return 0.0
+    cout16 = (e["cout"] + 15) // 16 * 16
+    return shape["split"] * cout16 * (e["taps"] * e["cin"] + 1) * 4 / REDUCE_BYTES_PER_MS
+
+
+def tune(geometries, instances, precision="fp32", reps=10, log=None, margin=0.97, passes=(0, 1, 2)):
+    """Tuning entries for every distinct conv pass (of the listed `passes`)
+    of the workload.
+
+    Every valid shape is timed with `reps` launches; the three cheapest and
     the heuristic's shape are timed again with 3 * reps launches, and a shape
-    replaces the heuristic's only if it is faster by more than 1 - margin."""
+    replaces the heuristic's only if its cost (launch time plus `reduce_ms`)
+    is lower by more than 1 - margin.  `ms` in an entry is the launch time."""
     seen = {}
     set_tuning([])  # the heuristic's choice is the baseline
     for i in range(len(instances)):
         for e in plan_convs(geometries, instances, precision, inst=i):
-            seen.setdefault(_key(e), e)
+            if e["pass"] in passes:
+                seen.setdefault(_key(e), e)
     table = []
+    cost = lambda e, sh, ms: ms + reduce_ms(e, sh)
     for key, e in seen.items():
-        first = sorted(((time_pass(e, sh, reps), i, sh) for i, sh in enumerate(candidates(e))),
-                       key=lambda t: (t[0], t[1]))
+        first = sorted(((cost(e, sh, time_pass(e, sh, reps)), i, sh)
+                        for i, sh in enumerate(candidates(e))), key=lambda t: (t[0], t[1]))
         finals = [sh for _, _, sh in first[:3]]
         base = time_pass(e, e["shape"], 3 * reps)
         best, best_ms = e["shape"], base
         for sh in finals:
             ms = time_pass(e, sh, 3 * reps)
-            if ms < margin * base and ms < best_ms:
+            if cost(e, sh, ms) < margin * cost(e, e["shape"], base) and \
+                    cost(e, sh, ms) < cost(e, best, best_ms):
                 best, best_ms = sh, ms
         if log:
             log("n=%-3d %3d->%-3d taps %2d pass %d pro %d: %.4f ms -> %.4f ms %s"

@@ -5,6 +5,26 @@
 namespace d2ip {
 namespace {
 
+// Sum of the strided values x[k * stride], k = first, first + step, ... < n,
+// with eight loads in flight: eight running sums over interleaved subsets,
+// combined in a fixed tree, so the order depends on n alone.
+__device__ __forceinline__ float strided_sum(const float* x, long long stride, int first, int step,
+                                             int n) {
+  float a[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  int k = first;
+  for (; k + 7 * step < n; k += 8 * step) {
+    float v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = x[(long long)(k + u * step) * stride];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) a[u] += v[u];
+  }
+#pragma unroll
+  for (int u = 0; u < 7; ++u)  // at most 7 left
+    if (k + u * step < n) a[u] += x[(long long)(k + u * step) * stride];
+  return ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
+}
+
 // One block row per conv segment.  A block owns 64 consecutive partial
 // elements (layout [co][tap][ci]); its 4 thread groups sum interleaved split
 // subsets, combined in group order, so the sum order is fixed.
@@ -49,10 +69,7 @@ __global__ void k_grad_reduce(const GradSeg* __restrict__ segs, const float* par
   const int j = threadIdx.x & 63, q = threadIdx.x >> 6;
   for (int base = blockIdx.x * 64; base < total; base += gridDim.x * 64) {
     const int f = base + j;
-    float acc = 0.f;
-    if (f < total)
-      for (int k = q; k < sg.splits; k += 4) acc += P[k * per + f];
-    sh[q][j] = acc;
+    sh[q][j] = f < total ? strided_sum(P + f, per, q, 4, sg.splits) : 0.f;
     __syncthreads();
     if (q == 0 && f < total) {
       const float v = ((sh[0][j] + sh[1][j]) + sh[2][j]) + sh[3][j];
@@ -64,11 +81,20 @@ __global__ void k_grad_reduce(const GradSeg* __restrict__ segs, const float* par
     __syncthreads();
   }
   if (blockIdx.x == 0) {
+    // bias: 16 channels per pass, 16 split groups each, combined in group order
     const float* PB = partb + sg.partb_off;
-    for (int co = threadIdx.x; co < sg.cout; co += blockDim.x) {
-      float acc = 0.f;
-      for (int k = 0; k < sg.splits; ++k) acc += PB[(long long)k * cout16 + co];
-      grad[sg.th_b + co] = acc;
+    const int cl = threadIdx.x & 15, sgp = threadIdx.x >> 4;
+    float* shb = &sh[0][0];
+    for (int c0 = 0; c0 < sg.cout; c0 += 16) {
+      const int co = c0 + cl;
+      shb[sgp * 16 + cl] = co < sg.cout ? strided_sum(PB + co, cout16, sgp, 16, sg.splits) : 0.f;
+      __syncthreads();
+      if (sgp == 0 && co < sg.cout) {
+        float t = 0.f;
+        for (int k = 0; k < 16; ++k) t += shb[k * 16 + cl];
+        grad[sg.th_b + co] = t;
+      }
+      __syncthreads();
     }
   }
 }
@@ -90,7 +116,8 @@ void conv_fwd(const ConvFwd& a, hipStream_t s) {
 }
 
 int conv_wgrad_groups(int taps, int ck) {
-  return (taps * ck + conv_detail::kWgCols - 1) / conv_detail::kWgCols;
+  const int cols = conv_detail::wg_cols(taps, ck);
+  return (taps * ck + cols - 1) / cols;
 }
 
 void conv_wgrad(const ConvWgrad& a, hipStream_t s) {

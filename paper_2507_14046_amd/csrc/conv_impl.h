@@ -32,8 +32,17 @@ namespace d2ip {
 namespace conv_detail {
 
 constexpr int kCkMax = 32;       // largest channel chunk staged at once
-constexpr int kWgNg = 8;         // weight-gradient column tiles per block (every wave)
-constexpr int kWgCols = kWgNg * 16;  // columns per weight-gradient block
+constexpr int kWgNg = 8;         // weight-gradient column tiles per wave
+// Columns (tap, channel) of a weight-gradient block.  1x1x1: every wave works
+// on the same 8 column tiles over a quarter of the voxel k-steps (the column
+// count is only the chunk); 3x3x3: each wave owns wg_nj(ck) column tiles over
+// all k-steps (4 for 8 channels = 13.5 tiles, 7 for 16 and 32 = 27 and 54
+// tiles), so one staged halo feeds up to 28 tiles, the MFMAs need no guards
+// and no cross-wave exchange is needed.
+__host__ __device__ constexpr int wg_nj(int ck) { return ck == 8 ? 4 : 7; }
+__host__ __device__ constexpr int wg_cols(int taps, int ck) {
+  return taps == 27 ? 4 * wg_nj(ck) * 16 : kWgNg * 16;
+}
 
 template <int TILE>
 struct TileDims;
@@ -641,11 +650,14 @@ __host__ __device__ inline size_t wg_lds_bytes(int tile, int taps, int ck, int m
     const size_t plane = (size_t)(tz + 2 * r) * (ty + 2 * r) * tx + 8;
     stage = parts * 2 * ((taps == 27 ? 3 : 1) * ck * plane + 16 * (bm + 8));
   }
-  const size_t xch = (size_t)4 * kWgNg * 64 * 16;
+  const size_t xch = taps == 27 ? 0 : (size_t)4 * kWgNg * 64 * 16;
   return stage > xch ? stage : xch;
 }
 
-template <int MODE, int TAPS, int TILE, int PRO, int GPRO>
+// CK: the channel chunk, fixed at compile time for 3x3x3 (8, 16 or 32; it
+// sizes the halo prefetch and the column tiles of a wave), 0 for 1x1x1 (read
+// from the arguments).
+template <int MODE, int TAPS, int TILE, int PRO, int GPRO, int CK>
 __global__ __launch_bounds__(256) void k_conv_wgrad(ConvWgrad a) {
   // grid z = member * cout tiles + cout tile
   const int cotiles = (a.cout + 15) / 16;
@@ -672,17 +684,21 @@ __global__ __launch_bounds__(256) void k_conv_wgrad(ConvWgrad a) {
   constexpr int PLANE = HZ * HY * TX + 8;          // BF16: elements per (copy, channel)
   constexpr int GP = MD::BF ? BM + 8 : 17;         // g tile row pitch
   constexpr int GSZ = MD::BF ? 16 * GP : BM * GP;
+  constexpr bool WCOLS = TAPS == 27;               // waves own column tiles
+  static_assert(!WCOLS || CK == 8 || CK == 16 || CK == 32, "3x3x3 needs a fixed chunk");
+  constexpr int NJ = WCOLS ? wg_nj(CK) : kWgNg;    // column tiles per wave
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ float4 bred[256];
 
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int l16 = lane & 15, g = lane >> 4;
   const int n = a.n;
-  const int ck = a.ck;
+  const int ck = CK ? CK : a.ck;
   const int ck_shift = __builtin_ctz(ck);
   const int ckp = ck + 1;                          // FP32 halo row pitch
   const int ntot = TAPS * ck;
-  const int ngroups = (ntot + kWgCols - 1) / kWgCols;
+  const int ngroups = (ntot + wg_cols(TAPS, ck) - 1) / wg_cols(TAPS, ck);
   const int chunk = blockIdx.y / ngroups, grp = blockIdx.y - chunk * ngroups;
   const int ntx = (n + TX - 1) / TX, nty = (n + TY - 1) / TY, ntz = (n + TZ - 1) / TZ;
   const int ntiles = ntx * nty * ntz;
@@ -697,15 +713,18 @@ __global__ __launch_bounds__(256) void k_conv_wgrad(ConvWgrad a) {
   ST* gs = hal + (MD::SPLIT ? 2 : 1) * hal_sz;
   ST* gs_lo = gs + (MD::SPLIT ? GSZ : 0);
 
-  // this block's columns (tap, channel), shared by all waves
-  f32x4 acc[kWgNg];
+  // this wave's column tiles (tap, channel): 3x3x3 tile grp*4*NJ + 4j + wave
+  // (interleaved, so a wave's tiles past the last column are at its end; their
+  // operands read as zero), 1x1x1 tile grp*8 + j shared by all waves
+  auto col_tile = [&](int j) { return WCOLS ? grp * 4 * NJ + 4 * j + wave : grp * kWgNg + j; };
+  f32x4 acc[NJ];
 #pragma unroll
-  for (int j = 0; j < kWgNg; ++j) acc[j] = (f32x4){0.f, 0.f, 0.f, 0.f};
-  int ctap[kWgNg], cc[kWgNg], coff[kWgNg];
-  bool cval[kWgNg];
+  for (int j = 0; j < NJ; ++j) acc[j] = (f32x4){0.f, 0.f, 0.f, 0.f};
+  int ctap[NJ], cc[NJ], coff[NJ];
+  bool cval[NJ];
 #pragma unroll
-  for (int j = 0; j < kWgNg; ++j) {
-    const int nn = (grp * kWgNg + j) * 16 + l16;
+  for (int j = 0; j < NJ; ++j) {
+    const int nn = col_tile(j) * 16 + l16;
     cval[j] = nn < ntot;
     ctap[j] = cval[j] ? nn >> ck_shift : 0;
     cc[j] = nn & (ck - 1);
@@ -723,7 +742,7 @@ __global__ __launch_bounds__(256) void k_conv_wgrad(ConvWgrad a) {
   // staging of a voxel tile (halo of ck input channels, g tile of 16 output
   // channels) goes through registers: the next tile's loads are issued before
   // the current tile's MFMAs
-  constexpr int NBH = halo_nb<HP>();
+  constexpr int NBH = CK ? (HP * (CK / 4) + 255) / 256 : halo_nb<HP>();
   constexpr int NBG = (BM * 4 + 255) / 256;
   const int qs = ck_shift - 2;
   const int gco = co0 + 4 * (tid & 3);  // output channels of this thread's g quads
@@ -851,11 +870,12 @@ __global__ __launch_bounds__(256) void k_conv_wgrad(ConvWgrad a) {
     }
     __syncthreads();
     if (t + (int)gridDim.x < ntiles) issue(t + gridDim.x);
-    // ---- every wave: all column tiles, voxel k-steps ks = wave, wave + 4, ...
+    // ---- 3x3x3: every wave its own column tiles over all voxel k-steps;
+    // 1x1x1: every wave all column tiles over k-steps ks = wave, wave + 4, ...
 #pragma unroll 2
-    for (int ks = wave; ks < NSTEP; ks += 4) {
+    for (int ks = WCOLS ? 0 : wave; ks < NSTEP; ks += WCOLS ? 1 : 4) {
       FT A, Al;
-      FT B[kWgNg], Bl[MD::SPLIT ? kWgNg : 1];
+      FT B[NJ], Bl[MD::SPLIT ? NJ : 1];
       if constexpr (MD::BF) {
         const int v0 = ks * KSTEP + g * KPL;  // 8 consecutive voxels of one row
         A = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u32x4*>(gs + l16 * GP + v0));
@@ -864,7 +884,7 @@ __global__ __launch_bounds__(256) void k_conv_wgrad(ConvWgrad a) {
         const int tz = v0 / (TY * TX), ty = (v0 / TX) % TY, tx = v0 % TX;
         const int vb = (tz * HY + ty) * TX + tx;
 #pragma unroll
-        for (int j = 0; j < kWgNg; ++j) {
+        for (int j = 0; j < NJ; ++j) {
           B[j] = frag<MODE>(hal + coff[j] + vb, cval[j]);
           if constexpr (MD::SPLIT) Bl[j] = frag<MODE>(hal_lo + coff[j] + vb, cval[j]);
         }
@@ -874,10 +894,10 @@ __global__ __launch_bounds__(256) void k_conv_wgrad(ConvWgrad a) {
         const int tz = v / (TY * TX), ty = (v / TX) % TY, tx = v % TX;
         const int vp = ((tz * HY + ty) * HX + tx) * ckp;
 #pragma unroll
-        for (int j = 0; j < kWgNg; ++j) B[j] = frag<MODE>(hal + vp + coff[j], cval[j]);
+        for (int j = 0; j < NJ; ++j) B[j] = frag<MODE>(hal + vp + coff[j], cval[j]);
       }
 #pragma unroll
-      for (int j = 0; j < kWgNg; ++j) {
+      for (int j = 0; j < NJ; ++j) {
         if constexpr (MD::SPLIT) {
           acc[j] = mfma(Al, B[j], acc[j]);
           acc[j] = mfma(A, Bl[j], acc[j]);
@@ -888,26 +908,41 @@ __global__ __launch_bounds__(256) void k_conv_wgrad(ConvWgrad a) {
     __syncthreads();
   }
 
-  // ---- cross-wave exchange (fixed wave order), then this block's partials
-  f32x4* xch = reinterpret_cast<f32x4*>(smem);
-#pragma unroll
-  for (int j = 0; j < kWgNg; ++j) xch[(wave * kWgNg + j) * 64 + lane] = acc[j];
-  __syncthreads();
   const int cout16 = (a.cout + 15) & ~15;
   float* part = a.part + (size_t)blockIdx.x * cout16 * TAPS * a.cin;
+  if constexpr (WCOLS) {
+    // ---- every wave writes its own column tiles
 #pragma unroll
-  for (int jj = 0; jj < kWgNg / 4; ++jj) {
+    for (int j = 0; j < NJ; ++j) {
+      const int nn = col_tile(j) * 16 + l16;
+      if (nn >= ntot) continue;
+      const int tap = nn >> ck_shift, c = nn & (ck - 1);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int co = co0 + 4 * g + r;
+        if (co < a.cout) part[((size_t)co * TAPS + tap) * a.cin + ci0 + c] = acc[j][r];
+      }
+    }
+  } else {
+    // ---- cross-wave exchange (fixed wave order), then this block's partials
+    f32x4* xch = reinterpret_cast<f32x4*>(smem);
+#pragma unroll
+    for (int j = 0; j < kWgNg; ++j) xch[(wave * kWgNg + j) * 64 + lane] = acc[j];
+    __syncthreads();
+#pragma unroll
+    for (int jj = 0; jj < kWgNg / 4; ++jj) {
     const int j = wave + 4 * jj;
     f32x4 v = (f32x4){0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int w = 0; w < 4; ++w) v += xch[(w * kWgNg + j) * 64 + lane];
-    const int nn = (grp * kWgNg + j) * 16 + l16;
-    if (nn >= ntot) continue;
-    const int tap = nn >> ck_shift, c = nn & (ck - 1);
+      const int nn = (grp * kWgNg + j) * 16 + l16;
+      if (nn >= ntot) continue;
+      const int tap = nn >> ck_shift, c = nn & (ck - 1);
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int co = co0 + 4 * g + r;
-      if (co < a.cout) part[((size_t)co * TAPS + tap) * a.cin + ci0 + c] = v[r];
+      for (int r = 0; r < 4; ++r) {
+        const int co = co0 + 4 * g + r;
+        if (co < a.cout) part[((size_t)co * TAPS + tap) * a.cin + ci0 + c] = v[r];
+      }
     }
   }
   if (do_bias) {
@@ -989,7 +1024,17 @@ void launch_wg(const ConvWgrad& a, hipStream_t s) {
   dim3 grid(a.splits, (a.cin / a.ck) * conv_wgrad_groups(a.taps, a.ck),
             ((a.cout + 15) / 16) * a.batch);
   const size_t lds = wg_lds_bytes(TILE, TAPS, a.ck, MODE);
-  hipLaunchKernelGGL((k_conv_wgrad<MODE, TAPS, TILE, PRO, GPRO>), grid, dim3(256), lds, s, a);
+  if constexpr (TAPS == 27) {
+    // the plan admits chunks of 8, 16 and 32 channels only
+    if (a.ck == 8)
+      hipLaunchKernelGGL((k_conv_wgrad<MODE, TAPS, TILE, PRO, GPRO, 8>), grid, dim3(256), lds, s, a);
+    else if (a.ck == 16)
+      hipLaunchKernelGGL((k_conv_wgrad<MODE, TAPS, TILE, PRO, GPRO, 16>), grid, dim3(256), lds, s, a);
+    else
+      hipLaunchKernelGGL((k_conv_wgrad<MODE, TAPS, TILE, PRO, GPRO, 32>), grid, dim3(256), lds, s, a);
+  } else {
+    hipLaunchKernelGGL((k_conv_wgrad<MODE, TAPS, TILE, PRO, GPRO, 0>), grid, dim3(256), lds, s, a);
+  }
 }
 
 template <int MODE, int TAPS, int TILE>

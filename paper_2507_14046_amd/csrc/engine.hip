@@ -363,8 +363,8 @@ bool shape_ok(const d2ip_tuning_entry& e, std::string* why) {
   }
   if (e.pass == 2) {
     if (e.cin % sh.ck != 0) return no("ck must divide the input channels");
-    if (sh.split < 1 || sh.split > 64 || sh.split > conv_tiles(e.n, sh.tile))
-      return no("split must be in [1, min(64, voxel tiles)]");
+    if (sh.split < 1 || sh.split > 256 || sh.split > conv_tiles(e.n, sh.tile))
+      return no("split must be in [1, min(256, voxel tiles)]");
     const int xp = e.prologue / 3, gp = e.prologue % 3;
     if (e.prologue < 0 || xp > PRO_LN_RELU || (gp != PRO_NONE && gp != PRO_LN_BWD) ||
         (e.taps == 1 && e.prologue != 0))

@@ -149,6 +149,36 @@ def test_tuning_tables_plan_and_stay_in_bounds(L, geo, inst):
         at.set_tuning([])
 
 
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3", "bf16"])
+@pytest.mark.parametrize("geo,inst", [((24, 928), (0, 3, 8)), ((32, 928), (0, 3, 16)),
+                                      ((64, 928), (0, 4, 32))])
+def test_weight_gradient_chunks_and_splits_stay_in_bounds(L, geo, inst, prec):
+    """Every 3x3x3 weight gradient at each channel chunk, with the fewest and
+    the most voxel splits the tiles allow (up to 256): launches stay inside
+    the workspace."""
+    from paper_2507_14046_amd import autotune as at
+    import paper_2507_14046_amd as d2ip
+    passes = [e for e in at.plan_convs([geo], [inst], prec) if e["pass"] == 2 and e["taps"] == 27]
+    try:
+        for ck in (8, 16, 32):
+            for pick in (0, -1):
+                table = []
+                for e in passes:
+                    cands = sorted((c for c in at.candidates(e) if c["ck"] == ck),
+                                   key=lambda c: (c["split"], c["tile"]))
+                    if cands:
+                        table.append(dict(e, shape=cands[pick]))
+                if not table:
+                    continue
+                at.set_tuning(table)
+                d2ip.check_launches([geo], [inst], prec, graph=True)
+                big = [e["shape"]["split"] for e in table if e["n"] >= 32]
+                if pick == -1 and big:
+                    assert max(big) > 64
+    finally:
+        at.set_tuning([])
+
+
 def test_tuning_entry_validation(L):
     from paper_2507_14046_amd import autotune as at
     e = at.plan_convs([(32, 928)], [(0, 3, 16)])[2]

@@ -293,6 +293,46 @@ def test_every_launch_shape_family_matches_oracle(lib, probs, case):
         at.set_tuning([])
 
 
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("ck", [8, 16, 32])
+@pytest.mark.parametrize("case", ["n24_L3_C8", "n16_L3_C16_M928"])
+def test_weight_gradient_chunks_match_oracle(lib, probs, case, ck, prec):
+    """Every 3x3x3 weight gradient forced to one channel chunk (each chunk is
+    a kernel of its own: it fixes the halo prefetch and the column tiles each
+    wave owns), alternating the fewest and the most voxel splits, on a ragged
+    and a full grid: one-iteration gradient, per tensor, against the oracle."""
+    from paper_2507_14046_amd import autotune as at
+    p = probs[case]
+    geos, insts = [(p["n"], p["J"].shape[0])], [(0, p["levels"], p["base_ch"])]
+    table = []
+    for j, e in enumerate(at.plan_convs(geos, insts, prec)):
+        if e["pass"] != 2 or e["taps"] != 27:
+            continue
+        cands = sorted((c for c in at.candidates(e) if c["ck"] == ck),
+                       key=lambda c: (c["split"], c["tile"]))
+        if cands:
+            table.append(dict(e, shape=cands[-1] if j % 2 else cands[0]))
+    if not table:
+        pytest.skip("no 3x3x3 weight gradient takes %d-channel chunks here" % ck)
+    pr = oracle_problem(p)
+    _, gref, _ = pr.loss_and_grad(p["theta0"].astype(np.float64), p["dv"][0].astype(np.float64))
+    try:
+        at.set_tuning(table)
+        lib.check_launches(geos, insts, precision=prec)
+        ctx = make_ctx(lib, [p], prec)
+        ctx.run(1)
+        g = ctx.get_grad(0)
+        ctx.close()
+    finally:
+        at.set_tuning([])
+    per = per_tensor_rel(g, gref, p["levels"], p["base_ch"])
+    worst = max(per.items(), key=lambda kv: kv[1])
+    record("wgrad_chunks", case=case, ck=ck, prec=prec, passes=len(table),
+           grad_rel=rel(g, gref), worst_tensor=worst[0], worst_rel=worst[1])
+    assert rel(g, gref) < TOL_GRAD[prec]
+    assert worst[1] < 5 * TOL_GRAD[prec], per
+
+
 def test_standalone_conv_timing(lib):
     from paper_2507_14046_amd import autotune as at
     passes = at.plan_convs([(16, 208)], [(0, 2, 8)])
