@@ -338,7 +338,9 @@ __device__ __forceinline__ typename Mode<MODE>::FT frag(const typename Mode<MODE
   }
 }
 
-template <int MODE, int TAPS, int TILE, int BN, int PRO>
+// CK: the channel chunk, fixed at compile time for 3x3x3 (8, 16 or 32; it
+// sizes the halo prefetch), 0 for 1x1x1 (read from the arguments).
+template <int MODE, int TAPS, int TILE, int BN, int PRO, int CK>
 __global__ __launch_bounds__(256) void k_conv_fwd(ConvFwd a) {
   // grid z = member * ksplit + split
   const int ksplit = a.ksplit;
@@ -370,7 +372,7 @@ __global__ __launch_bounds__(256) void k_conv_fwd(ConvFwd a) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int l16 = lane & 15, g = lane >> 4;
   const int n = a.n;
-  const int ck = a.ck, ckp = ck + MD::PAD;
+  const int ck = CK ? CK : a.ck, ckp = ck + MD::PAD;
   const int ck_shift = __builtin_ctz(ck);
   // LDS: halo [HP][ckp] (+ lo parts), weight slab [BN][wrp] (+ lo parts); the
   // same space holds the cross-wave accumulator exchange after the K loop
@@ -437,67 +439,78 @@ __global__ __launch_bounds__(256) void k_conv_fwd(ConvFwd a) {
   const int nchunks = a.cin >> ck_shift;
   const int cps = nchunks / ksplit;
   const int qs = ck_shift - 2;
-  constexpr int NBH = halo_nb<HP>();
+  constexpr int NBH = CK ? (HP * (CK / 4) + 255) / 256 : halo_nb<HP>();
   Quads<NBH, PRO> hq;
   HaloIdx<NBH> hidx;
   halo_prep<NBH, HZ, HY, HX>(hidx, n, a.src.stride, qs);
-  // first chunk's halo in flight while the prologue statistics are reduced
+  // weight slab of a chunk: rows co0.., for every tap ck channels, in batches
+  // of NBW 16-byte vectors per thread; the first batch of the next chunk is
+  // loaded into registers under the current chunk's MFMAs
+  constexpr int EV = MD::BF ? 8 : 4;  // elements per 16-byte vector
+  constexpr int NBW = 8;              // loads in flight per thread
+  const int vs = ck_shift - (MD::BF ? 3 : 2);  // log2(vectors per (row, tap))
+  const int nv = (BN * TAPS) << vs;
+  u32x4 wv[NBW], wvl[MD::SPLIT ? NBW : 1];
+  auto w_issue = [&](int ci0, int p0) {
+#pragma unroll
+    for (int k = 0; k < NBW; ++k) {
+      const int p = p0 + k * 256 + tid;
+      const int rt = p >> vs, q = p & ((1 << vs) - 1);
+      const int r = rt / TAPS, tap = rt - r * TAPS;
+      const int co = co0 + r;
+      wv[k] = (u32x4){0u, 0u, 0u, 0u};
+      if constexpr (MD::SPLIT) wvl[k] = (u32x4){0u, 0u, 0u, 0u};
+      if (p < nv && co < a.w_rows) {
+        const size_t wi = ((size_t)co * TAPS + tap) * a.cin + ci0 + q * EV;
+        wv[k] = *reinterpret_cast<const u32x4*>(W + wi);
+        if constexpr (MD::SPLIT) wvl[k] = *reinterpret_cast<const u32x4*>(Wlo + wi);
+      }
+    }
+  };
+  auto w_store = [&](int p0) {
+#pragma unroll
+    for (int k = 0; k < NBW; ++k) {
+      const int p = p0 + k * 256 + tid;
+      if (p >= nv) continue;
+      const int rt = p >> vs, q = p & ((1 << vs) - 1);
+      const int r = rt / TAPS, tap = rt - r * TAPS;
+      const int o = r * wrp + tap * ck + q * EV;
+      if constexpr (MD::BF) {
+        *reinterpret_cast<u32x4*>(wsm + o) = wv[k];
+        if constexpr (MD::SPLIT) *reinterpret_cast<u32x4*>(wsm_lo + o) = wvl[k];
+      } else {
+        // FP32 rows are padded to an even pitch: 4-byte stores
+        ST* d = wsm + o;
+        d[0] = __uint_as_float(wv[k].x);
+        d[1] = __uint_as_float(wv[k].y);
+        d[2] = __uint_as_float(wv[k].z);
+        d[3] = __uint_as_float(wv[k].w);
+      }
+    }
+  };
+  // first chunk's halo and weights in flight while the prologue statistics
+  // are reduced
   halo_load<NBH, PRO, HZ, HY, HX>(hq, hidx, a.src, n, qs, (kz * cps) << ck_shift, z0, y0, x0,
                                   R);
+  w_issue((kz * cps) << ck_shift, 0);
   float pmean, prstd, pA, pB;
   src_consts<PRO>(a.src, pmean, prstd, pA, pB);
   for (int ch = kz * cps; ch < (kz + 1) * cps; ++ch) {
     const int ci0 = ch << ck_shift;
     const ChanConsts kc = chan_consts<PRO>(a.src, ci0 + 4 * (tid & ((1 << qs) - 1)));
     halo_store<MODE, NBH, PRO, HP>(hal, hal_lo, hq, qs, ckp, kc, pmean, prstd, pA, pB);
-    // weight slab of this chunk: rows co0.., for every tap ck channels
-    {
-      constexpr int EV = MD::BF ? 8 : 4;  // elements per 16-byte vector
-      constexpr int NBW = 8;              // loads in flight per thread
-      const int vs = ck_shift - (MD::BF ? 3 : 2);  // log2(vectors per (row, tap))
-      const int nv = (BN * TAPS) << vs;
-      for (int p0 = 0; p0 < nv; p0 += 256 * NBW) {
-        u32x4 v[NBW], vl[MD::SPLIT ? NBW : 1];
-#pragma unroll
-        for (int k = 0; k < NBW; ++k) {
-          const int p = p0 + k * 256 + tid;
-          const int rt = p >> vs, q = p & ((1 << vs) - 1);
-          const int r = rt / TAPS, tap = rt - r * TAPS;
-          const int co = co0 + r;
-          v[k] = (u32x4){0u, 0u, 0u, 0u};
-          if constexpr (MD::SPLIT) vl[k] = (u32x4){0u, 0u, 0u, 0u};
-          if (p < nv && co < a.w_rows) {
-            const size_t wi = ((size_t)co * TAPS + tap) * a.cin + ci0 + q * EV;
-            v[k] = *reinterpret_cast<const u32x4*>(W + wi);
-            if constexpr (MD::SPLIT) vl[k] = *reinterpret_cast<const u32x4*>(Wlo + wi);
-          }
-        }
-#pragma unroll
-        for (int k = 0; k < NBW; ++k) {
-          const int p = p0 + k * 256 + tid;
-          if (p >= nv) continue;
-          const int rt = p >> vs, q = p & ((1 << vs) - 1);
-          const int r = rt / TAPS, tap = rt - r * TAPS;
-          const int o = r * wrp + tap * ck + q * EV;
-          if constexpr (MD::BF) {
-            *reinterpret_cast<u32x4*>(wsm + o) = v[k];
-            if constexpr (MD::SPLIT) *reinterpret_cast<u32x4*>(wsm_lo + o) = vl[k];
-          } else {
-            // FP32 rows are padded to an even pitch: 4-byte stores
-            ST* d = wsm + o;
-            d[0] = __uint_as_float(v[k].x);
-            d[1] = __uint_as_float(v[k].y);
-            d[2] = __uint_as_float(v[k].z);
-            d[3] = __uint_as_float(v[k].w);
-          }
-        }
-      }
+    w_store(0);
+    for (int p0 = 256 * NBW; p0 < nv; p0 += 256 * NBW) {  // slabs beyond one batch
+      w_issue(ci0, p0);
+      w_store(p0);
     }
     __syncthreads();
-    // next chunk's halo loads run under this chunk's MFMAs
-    if (ch + 1 < (kz + 1) * cps)
+    // next chunk's halo and first weight batch load under this chunk's MFMAs
+    if (ch + 1 < (kz + 1) * cps) {
       halo_load<NBH, PRO, HZ, HY, HX>(hq, hidx, a.src, n, qs, (ch + 1) << ck_shift, z0, y0, x0,
                                       R);
+      w_issue((ch + 1) << ck_shift, 0);
+    }
 #pragma unroll 2
     for (int step = wave; step < nstep; step += 4) {
       const uint32_t ko = ktab[step * 4 + g];
@@ -985,7 +998,17 @@ template <int MODE, int TAPS, int TILE, int BN, int PRO>
 void launch_fwd(const ConvFwd& a, hipStream_t s) {
   dim3 grid(spatial_tiles(a.n, TILE), (a.cout + BN - 1) / BN, a.ksplit * a.batch);
   const size_t lds = fwd_lds_bytes(TILE, TAPS, BN, a.ck, MODE);
-  hipLaunchKernelGGL((k_conv_fwd<MODE, TAPS, TILE, BN, PRO>), grid, dim3(256), lds, s, a);
+  if constexpr (TAPS == 27) {
+    // the plan admits chunks of 8, 16 and 32 channels only
+    if (a.ck == 8)
+      hipLaunchKernelGGL((k_conv_fwd<MODE, TAPS, TILE, BN, PRO, 8>), grid, dim3(256), lds, s, a);
+    else if (a.ck == 16)
+      hipLaunchKernelGGL((k_conv_fwd<MODE, TAPS, TILE, BN, PRO, 16>), grid, dim3(256), lds, s, a);
+    else
+      hipLaunchKernelGGL((k_conv_fwd<MODE, TAPS, TILE, BN, PRO, 32>), grid, dim3(256), lds, s, a);
+  } else {
+    hipLaunchKernelGGL((k_conv_fwd<MODE, TAPS, TILE, BN, PRO, 0>), grid, dim3(256), lds, s, a);
+  }
 }
 
 template <int MODE, int TAPS, int TILE, int BN>
