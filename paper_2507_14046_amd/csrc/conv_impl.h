@@ -32,16 +32,16 @@ namespace d2ip {
 namespace conv_detail {
 
 constexpr int kCkMax = 32;       // largest channel chunk staged at once
-constexpr int kWgNg = 8;         // weight-gradient column tiles per wave
+constexpr int kWgNg1 = 2;        // 1x1x1 weight-gradient column tiles (chunks <= 32)
 // Columns (tap, channel) of a weight-gradient block.  1x1x1: every wave works
-// on the same 8 column tiles over a quarter of the voxel k-steps (the column
-// count is only the chunk); 3x3x3: each wave owns wg_nj(ck) column tiles over
-// all k-steps (4 for 8 channels = 13.5 tiles, 7 for 16 and 32 = 27 and 54
-// tiles), so one staged halo feeds up to 28 tiles, the MFMAs need no guards
-// and no cross-wave exchange is needed.
+// on the chunk's (at most 2) column tiles over a quarter of the voxel k-steps;
+// 3x3x3: each wave owns wg_nj(ck) column tiles over all k-steps (4 for 8
+// channels = 13.5 tiles, 7 for 16 and 32 = 27 and 54 tiles), so one staged
+// halo feeds up to 28 tiles, the MFMAs need no guards and no cross-wave
+// exchange is needed.
 __host__ __device__ constexpr int wg_nj(int ck) { return ck == 8 ? 4 : 7; }
 __host__ __device__ constexpr int wg_cols(int taps, int ck) {
-  return taps == 27 ? 4 * wg_nj(ck) * 16 : kWgNg * 16;
+  return taps == 27 ? 4 * wg_nj(ck) * 16 : kWgNg1 * 16;
 }
 
 template <int TILE>
@@ -663,7 +663,7 @@ __host__ __device__ inline size_t wg_lds_bytes(int tile, int taps, int ck, int m
     const size_t plane = (size_t)(tz + 2 * r) * (ty + 2 * r) * tx + 8;
     stage = parts * 2 * ((taps == 27 ? 3 : 1) * ck * plane + 16 * (bm + 8));
   }
-  const size_t xch = taps == 27 ? 0 : (size_t)4 * kWgNg * 64 * 16;
+  const size_t xch = taps == 27 ? 0 : (size_t)4 * kWgNg1 * 64 * 16;
   return stage > xch ? stage : xch;
 }
 
@@ -699,7 +699,7 @@ __global__ __launch_bounds__(256) void k_conv_wgrad(ConvWgrad a) {
   constexpr int GSZ = MD::BF ? 16 * GP : BM * GP;
   constexpr bool WCOLS = TAPS == 27;               // waves own column tiles
   static_assert(!WCOLS || CK == 8 || CK == 16 || CK == 32, "3x3x3 needs a fixed chunk");
-  constexpr int NJ = WCOLS ? wg_nj(CK) : kWgNg;    // column tiles per wave
+  constexpr int NJ = WCOLS ? wg_nj(CK) : kWgNg1;   // column tiles per wave
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ float4 bred[256];
 
@@ -728,8 +728,8 @@ __global__ __launch_bounds__(256) void k_conv_wgrad(ConvWgrad a) {
 
   // this wave's column tiles (tap, channel): 3x3x3 tile grp*4*NJ + 4j + wave
   // (interleaved, so a wave's tiles past the last column are at its end; their
-  // operands read as zero), 1x1x1 tile grp*8 + j shared by all waves
-  auto col_tile = [&](int j) { return WCOLS ? grp * 4 * NJ + 4 * j + wave : grp * kWgNg + j; };
+  // operands read as zero), 1x1x1 tile grp*2 + j shared by all waves
+  auto col_tile = [&](int j) { return WCOLS ? grp * 4 * NJ + 4 * j + wave : grp * NJ + j; };
   f32x4 acc[NJ];
 #pragma unroll
   for (int j = 0; j < NJ; ++j) acc[j] = (f32x4){0.f, 0.f, 0.f, 0.f};
@@ -940,15 +940,13 @@ __global__ __launch_bounds__(256) void k_conv_wgrad(ConvWgrad a) {
     // ---- cross-wave exchange (fixed wave order), then this block's partials
     f32x4* xch = reinterpret_cast<f32x4*>(smem);
 #pragma unroll
-    for (int j = 0; j < kWgNg; ++j) xch[(wave * kWgNg + j) * 64 + lane] = acc[j];
+    for (int j = 0; j < NJ; ++j) xch[(wave * NJ + j) * 64 + lane] = acc[j];
     __syncthreads();
+    for (int j = wave; j < NJ; j += 4) {
+      f32x4 v = (f32x4){0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int jj = 0; jj < kWgNg / 4; ++jj) {
-    const int j = wave + 4 * jj;
-    f32x4 v = (f32x4){0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-    for (int w = 0; w < 4; ++w) v += xch[(w * kWgNg + j) * 64 + lane];
-      const int nn = (grp * kWgNg + j) * 16 + l16;
+      for (int w = 0; w < 4; ++w) v += xch[(w * NJ + j) * 64 + lane];
+      const int nn = col_tile(j) * 16 + l16;
       if (nn >= ntot) continue;
       const int tap = nn >> ck_shift, c = nn & (ck - 1);
 #pragma unroll

@@ -18,13 +18,24 @@ __global__ void k_ln_apply(const float4* h, PairRef sr, const float* g, const fl
     h = ishift(h, off); sr.part = ishift(sr.part, off); g = ishift(g, off); b = ishift(b, off);
     skip = ishift(skip, off); y = ishift(y, off);
   }
+  // the first element's loads are in flight while the statistics are reduced
+  const float4 z4 = make_float4(0.f, 0.f, 0.f, 0.f);
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+  float4 vn = z4, sn = z4;
+  if (i < n4) {
+    vn = h[i];
+    if (skip) sn = skip[i];
+  }
   const LnStat st = stat_of(sr);
   const float mean = st.mean, rstd = st.rstd;
-  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n4;
-       i += (size_t)gridDim.x * blockDim.x) {
+  for (; i < n4; i += stride) {
     const int c = (int)((i * 4) % C);
-    float4 v = h[i];
-    float4 s = skip ? skip[i] : make_float4(0.f, 0.f, 0.f, 0.f);
+    const float4 v = vn, s = sn;
+    if (i + stride < n4) {
+      vn = h[i + stride];
+      if (skip) sn = skip[i + stride];
+    }
     float4 o;
     o.x = fmaxf(g[c + 0] * ((v.x - mean) * rstd) + b[c + 0] + s.x, 0.f);
     o.y = fmaxf(g[c + 1] * ((v.y - mean) * rstd) + b[c + 1] + s.y, 0.f);
@@ -48,24 +59,46 @@ __global__ __launch_bounds__(256) void k_ln_bwd(
     part_c = ishift(part_c, off); part_ab = ishift(part_ab, off); gamma = ishift(gamma, off);
   }
   __shared__ double sh1[256], sh2[256];
-  const LnStat st = stat_of(sr);
   const int tid = threadIdx.x;
   const int c = tid % C, r0 = tid / C, rpi = 256 / C;
+  const int v0 = blockIdx.x * vpb;
+  const int v1 = min(V, v0 + vpb);
+  // the first kLnPre elements of this thread are loaded while the statistics
+  // are reduced (vpb <= kLnPre * rpi for every C the plan uses)
+  constexpr int kLnPre = 4;
+  float hp[kLnPre], gp[kLnPre], mp[kLnPre];
+#pragma unroll
+  for (int k = 0; k < kLnPre; ++k) {
+    const int v = v0 + r0 + k * rpi;
+    hp[k] = gp[k] = mp[k] = 0.f;
+    if (v < v1) {
+      const size_t i = (size_t)v * C + c;
+      hp[k] = h[i];
+      gp[k] = gy[i];
+      if (mask_mode == LNMASK_Y) mp[k] = my[i];
+    }
+  }
+  const LnStat st = stat_of(sr);
   const float mean = st.mean, rstd = st.rstd;
   const float gam = mask_mode == LNMASK_LN ? mg[c] : 0.f;
   const float bet = mask_mode == LNMASK_LN ? mb[c] : 0.f;
   double s1 = 0.0, s2 = 0.0;
-  const int v0 = blockIdx.x * vpb;
-  const int v1 = min(V, v0 + vpb);
-  for (int v = v0 + r0; v < v1; v += rpi) {
-    const size_t i = (size_t)v * C + c;
-    const float xh = (h[i] - mean) * rstd;
-    float gv = gy[i];
-    if (mask_mode == LNMASK_Y) gv = my[i] > 0.f ? gv : 0.f;
+  auto elem = [&](size_t i, float hv, float gv, float mv) {
+    const float xh = (hv - mean) * rstd;
+    if (mask_mode == LNMASK_Y) gv = mv > 0.f ? gv : 0.f;
     else if (mask_mode == LNMASK_LN) gv = (gam * xh + bet) > 0.f ? gv : 0.f;
     gz[i] = gv;
     s1 += gv;
     s2 += (double)gv * xh;
+  };
+#pragma unroll
+  for (int k = 0; k < kLnPre; ++k) {
+    const int v = v0 + r0 + k * rpi;
+    if (v < v1) elem((size_t)v * C + c, hp[k], gp[k], mp[k]);
+  }
+  for (int v = v0 + r0 + kLnPre * rpi; v < v1; v += rpi) {
+    const size_t i = (size_t)v * C + c;
+    elem(i, h[i], gy[i], mask_mode == LNMASK_Y ? my[i] : 0.f);
   }
   sh1[tid] = s1;
   sh2[tid] = s2;
@@ -103,21 +136,43 @@ __global__ void k_ln_apply_pool(const float4* h, PairRef sr, const float* g, con
   }
   const int m = n / 2;
   const size_t total = (size_t)m * m * m * C4;
-  const LnStat st = stat_of(sr);
-  const float mean = st.mean, rstd = st.rstd;
-  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < total;
-       i += (size_t)gridDim.x * blockDim.x) {
+  const float4 z4 = make_float4(0.f, 0.f, 0.f, 0.f);
+  // element j of the 8 children of coarse element i
+  auto child = [&](size_t i, int k) {
     const int c4 = (int)(i % C4);
     const size_t vc = i / C4;
     const int xx = (int)(vc % m), yy = (int)((vc / m) % m), zz = (int)(vc / ((size_t)m * m));
-    const int c = 4 * c4;
+    const int fz = 2 * zz + (k >> 2), fy = 2 * yy + ((k >> 1) & 1), fx = 2 * xx + (k & 1);
+    return ((size_t)(fz * n + fy) * n + fx) * C4 + c4;
+  };
+  // the first element's 8 children are loaded while the statistics are reduced
+  const size_t i0 = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+  float4 hv[8], sv[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    hv[k] = z4;
+    sv[k] = z4;
+    if (i0 < total) {
+      hv[k] = h[child(i0, k)];
+      if (skip) sv[k] = skip[child(i0, k)];
+    }
+  }
+  const LnStat st = stat_of(sr);
+  const float mean = st.mean, rstd = st.rstd;
+  for (size_t i = i0; i < total; i += (size_t)gridDim.x * blockDim.x) {
+    const int c = 4 * (int)(i % C4);
     float4 s = make_float4(0.f, 0.f, 0.f, 0.f);
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
-      const int fz = 2 * zz + (k >> 2), fy = 2 * yy + ((k >> 1) & 1), fx = 2 * xx + (k & 1);
-      const size_t j = ((size_t)(fz * n + fy) * n + fx) * C4 + c4;
-      const float4 v = h[j];
-      const float4 sk = skip ? skip[j] : make_float4(0.f, 0.f, 0.f, 0.f);
+      const size_t j = child(i, k);
+      float4 v, sk;
+      if (i == i0) {
+        v = hv[k];
+        sk = sv[k];
+      } else {
+        v = h[j];
+        sk = skip ? skip[j] : z4;
+      }
       float4 o;
       o.x = fmaxf(g[c + 0] * ((v.x - mean) * rstd) + b[c + 0] + sk.x, 0.f);
       o.y = fmaxf(g[c + 1] * ((v.y - mean) * rstd) + b[c + 1] + sk.y, 0.f);
