@@ -35,14 +35,17 @@ __global__ __launch_bounds__(256) void k_jvec(const float* __restrict__ Jc, int 
   extern __shared__ __align__(16) float sv[];  // [B][kJvecCols]
   const int q0 = blockIdx.x * kJvecCols;
   const int qn = min(kJvecCols, qa_pad - q0);
-  for (int b = 0; b < B; ++b) {
-    const float* sg = ishift(sigma, b * istride);
-    for (int q = threadIdx.x; q < kJvecCols; q += 256)
-      sv[b * kJvecCols + q] = q < qn ? sg[idx[q0 + q]] : 0.f;
-  }
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int m0 = blockIdx.y * kJvecRows + wave * kJvecRowsPerWave;
   constexpr int KV = kJvecCols / 256;  // float4 per lane per row
+  // issue order: the gather indices, this wave's J rows, then the image
+  // values at the indices, so the dependent gather overlaps the J stream.
+  // Addresses are clamped in bounds (qn >= 64, a multiple of 64) so the loads
+  // carry no branches: a clamped column meets a zero image value and a
+  // clamped row's sum is not stored
+  int iq[KV];
+#pragma unroll
+  for (int k = 0; k < KV; ++k) iq[k] = idx[q0 + min((int)threadIdx.x + 256 * k, qn - 1)];
   float4 jv[kJvecRowsPerWave][KV];
 #pragma unroll
   for (int r = 0; r < kJvecRowsPerWave; ++r) {
@@ -51,8 +54,25 @@ __global__ __launch_bounds__(256) void k_jvec(const float* __restrict__ Jc, int 
 #pragma unroll
     for (int k = 0; k < KV; ++k) {
       const int j = lane * 4 + 256 * k;
-      jv[r][k] = (m < M && j < qn) ? *reinterpret_cast<const float4*>(row + j)
-                                   : make_float4(0.f, 0.f, 0.f, 0.f);
+      jv[r][k] = *reinterpret_cast<const float4*>(row + min(j, qn - 4));
+    }
+  }
+  {
+    float gv[KV];
+#pragma unroll
+    for (int k = 0; k < KV; ++k) gv[k] = sigma[iq[k]];
+#pragma unroll
+    for (int k = 0; k < KV; ++k) {
+      const int q = threadIdx.x + 256 * k;
+      sv[q] = q < qn ? gv[k] : 0.f;
+    }
+  }
+  for (int b = 1; b < B; ++b) {
+    const float* sg = ishift(sigma, b * istride);
+#pragma unroll
+    for (int k = 0; k < KV; ++k) {
+      const int q = threadIdx.x + 256 * k;
+      sv[b * kJvecCols + q] = q < qn ? sg[iq[k]] : 0.f;
     }
   }
   __syncthreads();
