@@ -100,20 +100,47 @@ __global__ __launch_bounds__(256) void k_jtvec(const float* __restrict__ Jc, int
   __shared__ double sh[16];
   const int m0 = blockIdx.y * kJtRows;
   const int mn = min(kJtRows, M - m0);
+  // Issue order: member 0's residual inputs (the first kJtPre column-block
+  // partials of this thread's row, and its measurement), then the first
+  // kJtBatch J rows of this thread's 4 columns, which load while the residual
+  // is formed.  Addresses are clamped in bounds (a clamped partial is
+  // dropped, a clamped row has a zero residual weight, a clamped column is not
+  // stored), so the loads carry no branches.
+  constexpr int kJtBatch = 8, kJtPre = 4;
+  const int r = threadIdx.x >> 3, j = threadIdx.x & 7;
+  const int rc = m0 + min(r, mn - 1);
+  float pv[kJtPre];
+#pragma unroll
+  for (int i = 0; i < kJtPre; ++i) pv[i] = ppart[(size_t)min(j + 8 * i, nqb - 1) * M + rc];
+  const float dv0 = dv[rc];
+  __builtin_amdgcn_sched_barrier(0);  // keep these loads ahead of the J rows
+  const int q = (blockIdx.x * 256 + threadIdx.x) * 4;
+  const float* base = Jc + (size_t)m0 * qa_pad + min(q, qa_pad - 4);
+  auto jrow = [&](int rr) {
+    return *reinterpret_cast<const float4*>(base + (size_t)min(rr, mn - 1) * qa_pad);
+  };
+  float4 jv[kJtBatch];
+#pragma unroll
+  for (int rr = 0; rr < kJtBatch; ++rr) jv[rr] = jrow(rr);
   // residual of this block's rows for every member: 8 threads per row,
   // column blocks k = j, j+8, .. combined by a butterfly (fixed order)
   for (int b = 0; b < B; ++b) {
     const long long off = b * istride;
     const float* pp = ishift(ppart, off);
-    const int r = threadIdx.x >> 3, j = threadIdx.x & 7;
     float p = 0.f;
-    if (r < mn)
+    if (b == 0) {
+#pragma unroll
+      for (int i = 0; i < kJtPre; ++i) p += j + 8 * i < nqb ? pv[i] : 0.f;
+      if (r < mn)
+        for (int k = j + 8 * kJtPre; k < nqb; k += 8) p += pp[(size_t)k * M + m0 + r];
+    } else if (r < mn) {
       for (int k = j; k < nqb; k += 8) p += pp[(size_t)k * M + m0 + r];
+    }
 #pragma unroll
     for (int o = 4; o > 0; o >>= 1) p += __shfl_xor(p, o, 8);
     double rr = 0.0;
     if (j == 0 && r < kJtRows) {
-      const float res = r < mn ? p - ishift(dv, off)[m0 + r] : 0.f;
+      const float res = r < mn ? p - (b == 0 ? dv0 : ishift(dv, off)[m0 + r]) : 0.f;
       gs[b][r] = (2.f / (float)M) * res;
       rr = (double)res * res;
     }
@@ -123,25 +150,36 @@ __global__ __launch_bounds__(256) void k_jtvec(const float* __restrict__ Jc, int
     }
   }
   __syncthreads();
-  const int q = (blockIdx.x * 256 + threadIdx.x) * 4;
-  if (q >= qa_pad) return;
   float4 acc[kJMaxB];
 #pragma unroll
   for (int b = 0; b < kJMaxB; ++b) acc[b] = make_float4(0.f, 0.f, 0.f, 0.f);
-  const float* base = Jc + (size_t)m0 * qa_pad + q;
-#pragma unroll 4
-  for (int r = 0; r < mn; ++r) {
-    const float4 jv = *reinterpret_cast<const float4*>(base + (size_t)r * qa_pad);
+  // all kJtRows rows in batches (rows beyond mn weigh zero), the next batch
+  // loading under the current one's arithmetic
 #pragma unroll
-    for (int b = 0; b < kJMaxB; ++b) {
-      if (b >= B) break;
-      const float g = gs[b][r];
-      acc[b].x += jv.x * g;
-      acc[b].y += jv.y * g;
-      acc[b].z += jv.z * g;
-      acc[b].w += jv.w * g;
+  for (int r0 = 0; r0 < kJtRows; r0 += kJtBatch) {
+    float4 nx[kJtBatch];
+    if (r0 + kJtBatch < kJtRows) {
+#pragma unroll
+      for (int r = 0; r < kJtBatch; ++r) nx[r] = jrow(r0 + kJtBatch + r);
+    }
+#pragma unroll
+    for (int r = 0; r < kJtBatch; ++r) {
+#pragma unroll
+      for (int b = 0; b < kJMaxB; ++b) {
+        if (b >= B) break;
+        const float g = gs[b][r0 + r];
+        acc[b].x += jv[r].x * g;
+        acc[b].y += jv[r].y * g;
+        acc[b].z += jv[r].z * g;
+        acc[b].w += jv[r].w * g;
+      }
+    }
+    if (r0 + kJtBatch < kJtRows) {
+#pragma unroll
+      for (int r = 0; r < kJtBatch; ++r) jv[r] = nx[r];
     }
   }
+  if (q >= qa_pad) return;
 #pragma unroll
   for (int b = 0; b < kJMaxB; ++b) {
     if (b >= B) break;
