@@ -73,6 +73,32 @@ def conv_flops(n, cin, cout, taps):
     return 2.0 * n ** 3 * cin * cout * taps
 
 
+def network_fwd_flops(levels, C, n):
+    """Forward FLOPs of the network: stem 1->C, every ResBlock's two 3x3x3
+    convs and its 1x1x1 projection when channels change, the 1x1x1 head."""
+    f = conv_flops(n, 1, C, 27) + conv_flops(n, C, 1, 1)
+    for (m, cin, cout) in block_convs(levels, C, n):
+        f += conv_flops(m, cin, cout, 27) + conv_flops(m, cout, cout, 27)
+        if cin != cout:
+            f += conv_flops(m, cin, cout, 1)
+    return f
+
+
+def iteration_roofline(cfg, prec, M, qa, P, measured_ms):
+    """Per-iteration lower bound from the serial phases: convs (forward, input
+    gradient and weight gradient = 3 x forward FLOPs) at the MFMA peak of the
+    form's operands, two streams of the compact J and Adam (28 B/param) at the
+    HBM peak; `frac` = bound sum / measured time."""
+    conv_us = 3 * network_fwd_flops(cfg["levels"], cfg["base_ch"], cfg["n"]) / (
+        PEAK_TFLOPS[prec] * 1e12) * 1e6
+    j_us = 2 * 4.0 * M * qa / (HBM_PEAK_GBS * 1e9) * 1e6
+    adam_us = 28.0 * P / (HBM_PEAK_GBS * 1e9) * 1e6
+    s = conv_us + j_us + adam_us
+    return dict(conv_us=conv_us, j_us=j_us, adam_us=adam_us, sum_us=s,
+                max_us=max(conv_us, j_us, adam_us), measured_us=measured_ms * 1e3,
+                frac=s / (measured_ms * 1e3))
+
+
 def block_convs(levels, C, n):
     """(level grid n, cin, cout) of conv1 of every ResBlock in flat order."""
     out = []
@@ -227,8 +253,31 @@ def config2(d2ip, at, ts, prec, torch, cache, steps=40, graph=True):
     p = ts.make_problem(cfg["n"], cfg["rings"], cfg["levels"], cfg["base_ch"], cfg["seed"])
     ctx, ms, loss, img = single_form(d2ip, at, p, cfg, prec, steps, 3, torch, graph=graph,
                                      cache=cache)
+    M, qa, P = p["J"].shape[0], int(p["mask"].sum()), ctx.n_params[0]
+    kernels = None
+    if not graph:
+        # at 64^3 the compact J (767 MB) exceeds the MALL: the J products are
+        # HBM streams; the largest conv (decoder level 0, 96 -> 32 channels)
+        L = d2ip._lib
+        kernels = {}
+        jbytes = 4.0 * M * qa
+        for name, kid in (("jvec", L.KERNEL_JVEC), ("jtvec", L.KERNEL_JTVEC)):
+            kms = ctx.time_kernel(0, kid, 0, 20)
+            kernels[name] = dict(ms=kms, achieved=jbytes / (kms * 1e-3) / 1e9, unit="GB/s",
+                                 frac=jbytes / (kms * 1e-3) / 1e9 / HBM_PEAK_GBS)
+        blocks = block_convs(cfg["levels"], cfg["base_ch"], cfg["n"])
+        k = len(blocks) - 1
+        n, cin, cout = blocks[k]
+        fl = conv_flops(n, cin, cout, 27)
+        for name, kid in (("conv_fwd", L.KERNEL_CONV_FWD), ("conv_dgrad", L.KERNEL_CONV_DGRAD),
+                          ("conv_wgrad", L.KERNEL_CONV_WGRAD)):
+            kms = ctx.time_kernel(0, kid, k, 5)
+            kernels["%s[block%d %d^3 %d->%d]" % (name, k, n, cin, cout)] = dict(
+                ms=kms, achieved=fl / (kms * 1e-3) / 1e12, unit="TFLOP/s",
+                frac=fl / (kms * 1e-3) / 1e12 / PEAK_TFLOPS[prec])
     ctx.close()
     return dict(workload=cfg["desc"], form=prec, launch="graph" if graph else "eager",
+                roofline=iteration_roofline(cfg, prec, M, qa, P, ms / steps), kernels=kernels,
                 it_per_s=steps / (ms * 1e-3), timed_iters=steps,
                 final_loss=loss, image_rel_err=None,
                 note="no stored FP64 oracle trajectory at this size")
@@ -315,6 +364,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-kernels", action="store_true")
     ap.add_argument("--no-configs", action="store_true")
+    ap.add_argument("--ablation", action="store_true",
+                    help="also run the D2IP schedule ablation (UPWS / TPP) on a 20-frame "
+                         "32^3 sequence in the chosen form (about a minute)")
     ap.add_argument("--traffic-probe", type=int, default=0,
                     help="MiB copied 3 times after the kernel table (counter calibration)")
     a = ap.parse_args()
@@ -430,6 +482,25 @@ def main():
         # shapes tuned in this run (no stored table covered them)
         os.makedirs(os.path.join(ROOT, "gpurun_out"), exist_ok=True)
         at.save(at.merge(cache["fresh"]), os.path.join(ROOT, "gpurun_out", "tuned_fresh.json"))
+    ablation = None
+    if a.ablation:
+        from paper_2507_14046_amd import schedule
+        t0 = time.time()
+        at.set_tuning(tuned(d2ip, at, [(cfg["n"], p["J"].shape[0])],
+                            [(0, cfg["levels"], cfg["base_ch"])], chosen, cache))
+        seq = ts.make_problem(cfg["n"], cfg["rings"], cfg["levels"], cfg["base_ch"], cfg["seed"],
+                              frames=20, breathing=True)
+        warm = ts.make_problem(cfg["n"], cfg["rings"], cfg["levels"], cfg["base_ch"],
+                               cfg["seed"] + 1000)
+        actx = d2ip.Context([(cfg["n"], seq["J"].shape[0])], [(0, cfg["levels"], cfg["base_ch"])],
+                            precision=chosen, graph=False)
+        actx.load_problem(0, seq)
+        ablation = schedule.ablation(actx, seq["theta0"], seq["dv"], warm["dv"][0])
+        actx.close()
+        ablation["form"] = chosen
+        log("ablation (%.0f s): %s" % (time.time() - t0, json.dumps(
+            {k: (v["total_iterations"], round(v["seconds"], 2), v["all_reached"])
+             for k, v in ablation["variants"].items()})))
     cpu = None if a.no_cpu else cpu_baseline(p, cfg, a.cpu_seconds)
     out = {
         "metric": METRIC,
@@ -450,11 +521,16 @@ def main():
                    "form": chosen, "launch": res["launch"], "autotuned": True, "instances": 1},
         "image_rel_err": res["image_rel_err_vs_fp64_oracle"],
         "speedup_vs_plain_fp32": res["it_per_s"] / plain["it_per_s"],
+        "iteration_roofline": iteration_roofline(cfg, chosen, p["J"].shape[0],
+                                                 int(p["mask"].sum()),
+                                                 d2ip.param_count(cfg["levels"], cfg["base_ch"]),
+                                                 res["ms_per_step"]),
         "frames_per_s_tpp50": res["it_per_s"] / 50.0,
         "forms": forms,
         "plain_fp32": plain,
         "fp32_with_4d_tv": with_tv,
         "configs": configs,
+        "ablation": ablation,
         "roofline": roof,
         "cpu_baseline": cpu,
     }

@@ -369,7 +369,8 @@ __global__ __launch_bounds__(256) void k_conv_fwd(ConvFwd a) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ double red[8];
 
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform: scalar k-loop
   const int l16 = lane & 15, g = lane >> 4;
   const int n = a.n;
   const int ck = CK ? CK : a.ck, ckp = ck + MD::PAD;

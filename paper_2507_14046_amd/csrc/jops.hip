@@ -92,9 +92,58 @@ __global__ __launch_bounds__(256) void k_jvec(const float* __restrict__ Jc, int 
   }
 }
 
+// Column blocks of J sigma partials up to which every J^T g block sums its
+// rows' partials itself; above it (large grids) one k_resid launch does it
+// once for all column blocks.
+constexpr int kJtFuseMax = 32;
+
+// Residual, loss partial and data gradient of the kJtRows rows of a block,
+// from the column-block partials of J sigma: 8 threads per row sum column
+// blocks k = j, j+8, .. in increasing order and combine by a butterfly, the
+// same order as the fused path of k_jtvec.  g_p = (2/M) r
+// is written over column block 0's partial of its row, a slot only the thread
+// that reads it writes.
+__global__ __launch_bounds__(256) void k_resid(float* ppart, int nqb, int M, const float* dv,
+                                               double* rsum, long long istride) {
+  {
+    const long long off = (long long)blockIdx.y * istride;
+    ppart = ishift(ppart, off); dv = ishift(dv, off); rsum = ishift(rsum, off);
+  }
+  __shared__ double sh[16];
+  const int m0 = blockIdx.x * kJtRows;
+  const int mn = min(kJtRows, M - m0);
+  const int r = threadIdx.x >> 3, j = threadIdx.x & 7;
+  float p = 0.f;
+  if (r < mn) {
+    // up to 32 column blocks per thread in flight at once (addresses clamped,
+    // clamped values added as zeros), summed in increasing order
+    const float* col = ppart + m0 + r;
+    for (int k0 = j; k0 < nqb; k0 += 8 * 32) {
+      float v[32];
+#pragma unroll
+      for (int u = 0; u < 32; ++u) v[u] = col[(size_t)min(k0 + 8 * u, nqb - 1) * M];
+#pragma unroll
+      for (int u = 0; u < 32; ++u) p += k0 + 8 * u < nqb ? v[u] : 0.f;
+    }
+  }
+#pragma unroll
+  for (int o = 4; o > 0; o >>= 1) p += __shfl_xor(p, o, 8);
+  double rr = 0.0;
+  if (j == 0 && r < mn) {
+    const float res = p - dv[m0 + r];
+    ppart[m0 + r] = (2.f / (float)M) * res;
+    rr = (double)res * res;
+  }
+  rr = block_sum(rr, sh);
+  if (threadIdx.x == 0) rsum[blockIdx.x] = rr;
+}
+
+// pre: the data gradient of every row is already in column block 0 of ppart
+// (k_resid), else each block forms it for its rows and block column 0 writes
+// the loss partials.
 __global__ __launch_bounds__(256) void k_jtvec(const float* __restrict__ Jc, int M, int qa_pad,
                                                const float* ppart, int nqb, const float* dv,
-                                               double* rsum, float* tpart, int B,
+                                               double* rsum, float* tpart, int B, int pre,
                                                long long istride) {
   __shared__ float gs[kJMaxB][kJtRows];
   __shared__ double sh[16];
@@ -109,10 +158,12 @@ __global__ __launch_bounds__(256) void k_jtvec(const float* __restrict__ Jc, int
   constexpr int kJtBatch = 8, kJtPre = 4;
   const int r = threadIdx.x >> 3, j = threadIdx.x & 7;
   const int rc = m0 + min(r, mn - 1);
-  float pv[kJtPre];
+  float pv[kJtPre] = {0.f, 0.f, 0.f, 0.f}, dv0 = 0.f;
+  if (!pre) {  // uniform
 #pragma unroll
-  for (int i = 0; i < kJtPre; ++i) pv[i] = ppart[(size_t)min(j + 8 * i, nqb - 1) * M + rc];
-  const float dv0 = dv[rc];
+    for (int i = 0; i < kJtPre; ++i) pv[i] = ppart[(size_t)min(j + 8 * i, nqb - 1) * M + rc];
+    dv0 = dv[rc];
+  }
   __builtin_amdgcn_sched_barrier(0);  // keep these loads ahead of the J rows
   const int q = (blockIdx.x * 256 + threadIdx.x) * 4;
   const float* base = Jc + (size_t)m0 * qa_pad + min(q, qa_pad - 4);
@@ -124,7 +175,13 @@ __global__ __launch_bounds__(256) void k_jtvec(const float* __restrict__ Jc, int
   for (int rr = 0; rr < kJtBatch; ++rr) jv[rr] = jrow(rr);
   // residual of this block's rows for every member: 8 threads per row,
   // column blocks k = j, j+8, .. combined by a butterfly (fixed order)
-  for (int b = 0; b < B; ++b) {
+  if (pre) {
+    for (int e = threadIdx.x; e < B * kJtRows; e += 256) {
+      const int b = e / kJtRows, rr = e - b * kJtRows;
+      gs[b][rr] = rr < mn ? ishift(ppart, b * istride)[m0 + rr] : 0.f;
+    }
+  }
+  for (int b = 0; b < (pre ? 0 : B); ++b) {
     const long long off = b * istride;
     const float* pp = ishift(ppart, off);
     float p = 0.f;
@@ -477,11 +534,18 @@ void jvec(const float* Jc, int M, int qa_pad, const int* idx, const float* sigma
 void jtvec(const float* Jc, int M, int qa_pad, const float* ppart, int nqb, const float* dv,
            double* rsum, float* tpart, int batch, long long istride, hipStream_t s) {
   dim3 grid((qa_pad / 4 + 255) / 256, jt_mblocks(M));
-  for (int b0 = 0; b0 < batch; b0 += kJMaxB)
+  const int pre = nqb > kJtFuseMax ? 1 : 0;
+  for (int b0 = 0; b0 < batch; b0 += kJMaxB) {
+    const int nb = std::min(kJMaxB, batch - b0);
+    if (pre)
+      hipLaunchKernelGGL(k_resid, dim3(jt_mblocks(M), nb), dim3(256), 0, s,
+                         const_cast<float*>(ishift(ppart, b0 * istride)), nqb, M,
+                         ishift(dv, b0 * istride), ishift(rsum, b0 * istride), istride);
     hipLaunchKernelGGL(k_jtvec, grid, dim3(256), 0, s, Jc, M, qa_pad,
                        ishift(ppart, b0 * istride), nqb, ishift(dv, b0 * istride),
-                       ishift(rsum, b0 * istride), ishift(tpart, b0 * istride),
-                       std::min(kJMaxB, batch - b0), istride);
+                       ishift(rsum, b0 * istride), ishift(tpart, b0 * istride), nb, pre,
+                       istride);
+  }
 }
 
 void tail_fwd(const float* d0, int C, const float* w, const float* b, const float* mask, size_t V,

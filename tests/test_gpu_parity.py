@@ -193,24 +193,24 @@ def test_error_paths(lib, probs):
 
 
 def test_full_size_32cubed_one_iteration(lib):
-    """The 32^3 / 928-measurement / L=3 / C=16 workload, in the launch
-    configuration the benchmark uses: loss and every gradient tensor vs the
-    oracle after one iteration."""
+    """The 32^3 / 928-measurement / L=3 / C=16 workload, in both launch
+    configurations the benchmark times (captured graph, eager launches on two
+    streams): loss and every gradient tensor vs the oracle after one
+    iteration."""
     c = ts.CONFIGS["c1"]
     p = problem(c["n"], c["rings"], c["levels"], c["base_ch"], c["seed"])
+    pr = oracle_problem(p)
+    L0, gref, _ = pr.loss_and_grad(p["theta0"].astype(np.float64), p["dv"][0].astype(np.float64))
     for prec in PRECS:
-        ctx = make_ctx(lib, [p], prec, graph=True)
-        loss = ctx.run(1)[0]
-        g = ctx.get_grad(0)
-        if prec == "fp32":
-            pr = oracle_problem(p)
-            L0, gref, _ = pr.loss_and_grad(p["theta0"].astype(np.float64),
-                                           p["dv"][0].astype(np.float64))
-        per = per_tensor_rel(g, gref, c["levels"], c["base_ch"])
-        record("full32_one_iteration", prec=prec, loss_rel=abs(loss - L0) / L0,
-               grad_rel=rel(g, gref), worst=max(per.values()))
-        assert rel(g, gref) < TOL_GRAD[prec]
-        ctx.close()
+        for graph in (True, False):
+            ctx = make_ctx(lib, [p], prec, graph=graph)
+            loss = ctx.run(1)[0]
+            g = ctx.get_grad(0)
+            per = per_tensor_rel(g, gref, c["levels"], c["base_ch"])
+            record("full32_one_iteration", prec=prec, graph=graph, loss_rel=abs(loss - L0) / L0,
+                   grad_rel=rel(g, gref), worst=max(per.values()))
+            assert rel(g, gref) < TOL_GRAD[prec]
+            ctx.close()
 
 
 @pytest.mark.skip(reason="instance groups (batched launches) are switched off: their first GPU run crashed the host process (SIGSEGV in d2ip_run) and the cause is not yet shown")
@@ -333,6 +333,24 @@ def test_weight_gradient_chunks_match_oracle(lib, probs, case, ck, prec):
     assert worst[1] < 5 * TOL_GRAD[prec], per
 
 
+def test_one_iteration_with_many_j_column_blocks(lib):
+    """40^3: the compact J has more than 32 column blocks of 1024 voxels, so
+    the residual is formed once by its own kernel before J^T g (the path of
+    large grids); one iteration's loss and gradient against the oracle."""
+    p = problem(40, 1, 2, 8, 5)
+    qa_pad = (int(p["mask"].sum()) + 63) // 64 * 64
+    assert (qa_pad + 1023) // 1024 > 32
+    ctx = make_ctx(lib, [p])
+    loss = ctx.run(1)[0]
+    g = ctx.get_grad(0)
+    ctx.close()
+    pr = oracle_problem(p)
+    L0, gref, _ = pr.loss_and_grad(p["theta0"].astype(np.float64), p["dv"][0].astype(np.float64))
+    record("many_column_blocks_40", loss_rel=abs(loss - L0) / L0, grad_rel=rel(g, gref))
+    assert abs(loss - L0) / L0 < TOL_IMG["fp32"]
+    assert rel(g, gref) < TOL_GRAD["fp32"]
+
+
 def test_standalone_conv_timing(lib):
     from paper_2507_14046_amd import autotune as at
     passes = at.plan_convs([(16, 208)], [(0, 2, 8)])
@@ -374,12 +392,13 @@ def test_stored_tuning_table_matches_oracle(lib, prec):
     _, gref, _ = pr.loss_and_grad(p["theta0"].astype(np.float64), p["dv"][0].astype(np.float64))
     try:
         at.set_tuning(at.load_table(path))
-        ctx = make_ctx(lib, [p], precision=prec, graph=True)
-        ctx.run(1)
-        g = ctx.get_grad(0)
-        record("stored_table_32cubed", prec=prec, grad_rel=rel(g, gref))
-        assert rel(g, gref) < TOL_GRAD[prec]
-        ctx.close()
+        for graph in (True, False):
+            ctx = make_ctx(lib, [p], precision=prec, graph=graph)
+            ctx.run(1)
+            g = ctx.get_grad(0)
+            record("stored_table_32cubed", prec=prec, graph=graph, grad_rel=rel(g, gref))
+            assert rel(g, gref) < TOL_GRAD[prec]
+            ctx.close()
     finally:
         at.set_tuning([])
 
@@ -387,8 +406,9 @@ def test_stored_tuning_table_matches_oracle(lib, prec):
 @pytest.mark.parametrize("prec", PRECS)
 def test_trajectory_500_iterations_32cubed_vs_stored_oracle(lib, prec):
     """The benchmark workload (32^3, 928 measurements, 3 levels, 16 channels,
-    500 iterations, graph, stored tuning table) against the stored FP64
-    oracle trajectory.  The oracle's own sensitivity (a 1-ulp change of
+    500 iterations, eager launches on two streams as the benchmark reports
+    them, stored tuning table) against the stored FP64 oracle trajectory; the
+    captured-graph run must end on the same image bit for bit.  The oracle's own sensitivity (a 1-ulp change of
     theta_0 moves its image by `floor` at iteration 500) bounds what any
     implementation can match: FP32 must stay within 3 x floor.  Adam
     amplifies any early difference along the trajectory by at most the factor
@@ -409,7 +429,7 @@ def test_trajectory_500_iterations_32cubed_vs_stored_oracle(lib, prec):
     try:
         if os.path.exists(at.default_table_path()):
             at.set_tuning(at.load_table(at.default_table_path()))
-        ctx = make_ctx(lib, [p], precision=prec, graph=True)
+        ctx = make_ctx(lib, [p], precision=prec, graph=False)
         losses, imgs = [], {}
         done = 0
         for cp in cps:
@@ -417,6 +437,10 @@ def test_trajectory_500_iterations_32cubed_vs_stored_oracle(lib, prec):
             done = cp
             imgs[cp] = ctx.read_image(0)
         ctx.close()
+        gctx = make_ctx(lib, [p], precision=prec, graph=True)
+        gctx.run(cps[-1])
+        np.testing.assert_array_equal(gctx.read_image(0), imgs[cps[-1]])
+        gctx.close()
     finally:
         at.set_tuning([])
     e = {int(cp): rel(imgs[cp], z["images"][i]) for i, cp in enumerate(cps)}
