@@ -916,7 +916,8 @@ void L_jtvec(const float* Jc, int M, int qa_pad, const float* ppart, int nqb, co
   c.range(ppart, (size_t)nqb * M * 4, "ppart", B, is);
   c.range(dv, (size_t)M * 4, "dv", B, is);
   c.range(rsum, (size_t)jt_mblocks(M) * 8, "rsum", B, is);
-  c.range(tpart, (size_t)jt_mblocks(M) * qa_pad * 4, "tpart", B, is);
+  c.require(jt_partials(M, qa_pad) <= jt_mblocks(M), "J^T g row groups beyond the partial buffer");
+  c.range(tpart, (size_t)jt_partials(M, qa_pad) * qa_pad * 4, "tpart", B, is);
 }
 
 void L_tail_bwd(const float* tpart, int nmb, int qa_pad, const int* inv, const float* d0, int C,
@@ -1149,7 +1150,7 @@ void enqueue_iteration(d2ip_ctx& X, Instance& I) {
   L_jvec(G.Jc, G.M, G.qa_pad, G.idx, I.sigma, I.ppart, I.V0, I.B, I.istride, s);
   L_jtvec(G.Jc, G.M, G.qa_pad, I.ppart, nqb, I.dv, I.rsum, I.tpart, I.B, I.istride, s);
   if (X.tv_on) join(X);
-  L_tail_bwd(I.tpart, jt_mblocks(G.M), G.qa_pad, G.inv, I.blocks.back().y, I.C, th + I.tail_w,
+  L_tail_bwd(I.tpart, jt_partials(G.M, G.qa_pad), G.qa_pad, G.inv, I.blocks.back().y, I.C, th + I.tail_w,
            I.V0, I.lv[0].gy, I.tail_part, X.tv_on ? I.gtv : nullptr, I.B, I.istride, s);
   // network backward, decoder first.  Weight gradients only feed the batched
   // reduction at the end: they run on the side stream, overlapping the

@@ -92,11 +92,6 @@ __global__ __launch_bounds__(256) void k_jvec(const float* __restrict__ Jc, int 
   }
 }
 
-// Column blocks of J sigma partials up to which every J^T g block sums its
-// rows' partials itself; above it (large grids) one k_resid launch does it
-// once for all column blocks.
-constexpr int kJtFuseMax = 32;
-
 // Residual, loss partial and data gradient of the kJtRows rows of a block,
 // from the column-block partials of J sigma: 8 threads per row sum column
 // blocks k = j, j+8, .. in increasing order and combine by a butterfly, the
@@ -138,12 +133,76 @@ __global__ __launch_bounds__(256) void k_resid(float* ppart, int nqb, int M, con
   if (threadIdx.x == 0) rsum[blockIdx.x] = rr;
 }
 
-// pre: the data gradient of every row is already in column block 0 of ppart
-// (k_resid), else each block forms it for its rows and block column 0 writes
-// the loss partials.
+// J^T g over row groups of rpg rows (large grids): the data gradient of every
+// row is in column block 0 of ppart (k_resid).  Each thread accumulates its 4
+// columns over the group's rows in batches of 8, the next batch loading under
+// the current one's arithmetic; addresses are clamped (a clamped row weighs
+// zero, a clamped column is not stored).
+__global__ __launch_bounds__(256) void k_jt_rows(const float* __restrict__ Jc, int M, int qa_pad,
+                                                 const float* gp, int rpg, float* tpart, int B,
+                                                 long long istride) {
+  constexpr int kB = 8;
+  const int m0 = blockIdx.y * rpg;
+  const int mn = min(rpg, M - m0);
+  const int q = (blockIdx.x * 256 + threadIdx.x) * 4;
+  const float* base = Jc + (size_t)m0 * qa_pad + min(q, qa_pad - 4);
+  auto jrow = [&](int r) {
+    return *reinterpret_cast<const float4*>(base + (size_t)min(r, mn - 1) * qa_pad);
+  };
+  float4 acc[kJMaxB];
+#pragma unroll
+  for (int b = 0; b < kJMaxB; ++b) acc[b] = make_float4(0.f, 0.f, 0.f, 0.f);
+  // member 0's data gradient of a batch: two aligned float4 (rpg and kB are
+  // multiples of 8 and the partial buffer is 256-byte aligned); rows past the
+  // group read (and drop) the next rows of the buffer, which holds
+  // nqb > kJtFuseMax column blocks of M rows, so m0 + r0 + 8 <= M + 8 stays
+  // inside it
+  auto gload = [&](int r0, float4& lo, float4& hi) {
+    lo = *reinterpret_cast<const float4*>(gp + m0 + r0);
+    hi = *reinterpret_cast<const float4*>(gp + m0 + r0 + 4);
+  };
+  float4 jv[kB], glo, ghi;
+#pragma unroll
+  for (int r = 0; r < kB; ++r) jv[r] = jrow(r);
+  gload(0, glo, ghi);
+  for (int r0 = 0; r0 < mn; r0 += kB) {
+    // the next batch (clamped: past the group it repeats the last row)
+    float4 nx[kB], nlo, nhi;
+#pragma unroll
+    for (int r = 0; r < kB; ++r) nx[r] = jrow(r0 + kB + r);
+    gload(r0 + kB < mn ? r0 + kB : r0, nlo, nhi);
+    const float g0[kB] = {glo.x, glo.y, glo.z, glo.w, ghi.x, ghi.y, ghi.z, ghi.w};
+#pragma unroll
+    for (int r = 0; r < kB; ++r) {
+      const bool ok = r0 + r < mn;
+#pragma unroll
+      for (int b = 0; b < kJMaxB; ++b) {
+        if (b >= B) break;
+        const float gv = b == 0 ? g0[r] : ishift(gp, b * istride)[m0 + r0 + r];
+        const float g = ok ? gv : 0.f;
+        acc[b].x += jv[r].x * g;
+        acc[b].y += jv[r].y * g;
+        acc[b].z += jv[r].z * g;
+        acc[b].w += jv[r].w * g;
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < kB; ++r) jv[r] = nx[r];
+    glo = nlo;
+    ghi = nhi;
+  }
+  if (q >= qa_pad) return;
+#pragma unroll
+  for (int b = 0; b < kJMaxB; ++b) {
+    if (b >= B) break;
+    *reinterpret_cast<float4*>(ishift(tpart, b * istride) + (size_t)blockIdx.y * qa_pad + q) =
+        acc[b];
+  }
+}
+
 __global__ __launch_bounds__(256) void k_jtvec(const float* __restrict__ Jc, int M, int qa_pad,
                                                const float* ppart, int nqb, const float* dv,
-                                               double* rsum, float* tpart, int B, int pre,
+                                               double* rsum, float* tpart, int B,
                                                long long istride) {
   __shared__ float gs[kJMaxB][kJtRows];
   __shared__ double sh[16];
@@ -158,12 +217,10 @@ __global__ __launch_bounds__(256) void k_jtvec(const float* __restrict__ Jc, int
   constexpr int kJtBatch = 8, kJtPre = 4;
   const int r = threadIdx.x >> 3, j = threadIdx.x & 7;
   const int rc = m0 + min(r, mn - 1);
-  float pv[kJtPre] = {0.f, 0.f, 0.f, 0.f}, dv0 = 0.f;
-  if (!pre) {  // uniform
+  float pv[kJtPre];
 #pragma unroll
-    for (int i = 0; i < kJtPre; ++i) pv[i] = ppart[(size_t)min(j + 8 * i, nqb - 1) * M + rc];
-    dv0 = dv[rc];
-  }
+  for (int i = 0; i < kJtPre; ++i) pv[i] = ppart[(size_t)min(j + 8 * i, nqb - 1) * M + rc];
+  const float dv0 = dv[rc];
   __builtin_amdgcn_sched_barrier(0);  // keep these loads ahead of the J rows
   const int q = (blockIdx.x * 256 + threadIdx.x) * 4;
   const float* base = Jc + (size_t)m0 * qa_pad + min(q, qa_pad - 4);
@@ -175,13 +232,7 @@ __global__ __launch_bounds__(256) void k_jtvec(const float* __restrict__ Jc, int
   for (int rr = 0; rr < kJtBatch; ++rr) jv[rr] = jrow(rr);
   // residual of this block's rows for every member: 8 threads per row,
   // column blocks k = j, j+8, .. combined by a butterfly (fixed order)
-  if (pre) {
-    for (int e = threadIdx.x; e < B * kJtRows; e += 256) {
-      const int b = e / kJtRows, rr = e - b * kJtRows;
-      gs[b][rr] = rr < mn ? ishift(ppart, b * istride)[m0 + rr] : 0.f;
-    }
-  }
-  for (int b = 0; b < (pre ? 0 : B); ++b) {
+  for (int b = 0; b < B; ++b) {
     const long long off = b * istride;
     const float* pp = ishift(ppart, off);
     float p = 0.f;
@@ -533,18 +584,23 @@ void jvec(const float* Jc, int M, int qa_pad, const int* idx, const float* sigma
 
 void jtvec(const float* Jc, int M, int qa_pad, const float* ppart, int nqb, const float* dv,
            double* rsum, float* tpart, int batch, long long istride, hipStream_t s) {
-  dim3 grid((qa_pad / 4 + 255) / 256, jt_mblocks(M));
-  const int pre = nqb > kJtFuseMax ? 1 : 0;
+  const int qb = (qa_pad / 4 + 255) / 256;
+  const bool large = nqb > kJtFuseMax;
+  const int rpg = jt_rows_per_group(M, qa_pad);
   for (int b0 = 0; b0 < batch; b0 += kJMaxB) {
     const int nb = std::min(kJMaxB, batch - b0);
-    if (pre)
+    if (large) {
       hipLaunchKernelGGL(k_resid, dim3(jt_mblocks(M), nb), dim3(256), 0, s,
                          const_cast<float*>(ishift(ppart, b0 * istride)), nqb, M,
                          ishift(dv, b0 * istride), ishift(rsum, b0 * istride), istride);
-    hipLaunchKernelGGL(k_jtvec, grid, dim3(256), 0, s, Jc, M, qa_pad,
-                       ishift(ppart, b0 * istride), nqb, ishift(dv, b0 * istride),
-                       ishift(rsum, b0 * istride), ishift(tpart, b0 * istride), nb, pre,
-                       istride);
+      hipLaunchKernelGGL(k_jt_rows, dim3(qb, jt_partials(M, qa_pad)), dim3(256), 0, s, Jc, M,
+                         qa_pad, ishift(ppart, b0 * istride), rpg, ishift(tpart, b0 * istride),
+                         nb, istride);
+    } else {
+      hipLaunchKernelGGL(k_jtvec, dim3(qb, jt_mblocks(M)), dim3(256), 0, s, Jc, M, qa_pad,
+                         ishift(ppart, b0 * istride), nqb, ishift(dv, b0 * istride),
+                         ishift(rsum, b0 * istride), ishift(tpart, b0 * istride), nb, istride);
+    }
   }
 }
 

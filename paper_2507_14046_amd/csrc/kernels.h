@@ -168,6 +168,24 @@ constexpr int kJtRows = 32;       // rows per J^T g block
 constexpr int kJMaxB = 8;         // group members per J-product launch (J read once)
 inline int jvec_qblocks(int qa_pad) { return (qa_pad + kJvecCols - 1) / kJvecCols; }
 inline int jt_mblocks(int M) { return (M + kJtRows - 1) / kJtRows; }
+// Column blocks of J sigma partials up to which every J^T g block forms its
+// rows' residual itself; above it (large grids) the residual is formed once
+// (k_resid) and J^T g runs over longer row groups, about 1024 blocks in all,
+// so it writes fewer partials.
+constexpr int kJtFuseMax = 32;
+inline int jt_rows_per_group(int M, int qa_pad) {
+  const int nqb = jvec_qblocks(qa_pad);
+  if (nqb <= kJtFuseMax) return kJtRows;
+  int R = (1024 + nqb - 1) / nqb;
+  if (R > jt_mblocks(M)) R = jt_mblocks(M);
+  if (R < 1) R = 1;
+  return ((M + R - 1) / R + 7) / 8 * 8;  // a multiple of 8: aligned batches of rows
+}
+// Row groups of J^T g partials (tpart rows) for an M x qa_pad compact J.
+inline int jt_partials(int M, int qa_pad) {
+  const int rpg = jt_rows_per_group(M, qa_pad);
+  return (M + rpg - 1) / rpg;
+}
 
 void gather_columns(const float* J, int M, int Q, const int* idx, int qa, int qa_pad, float* Jc,
                     hipStream_t s);
@@ -177,9 +195,11 @@ void gather_columns(const float* J, int M, int Q, const int* idx, int qa, int qa
 // ppart[qb][m] = sum_{q in column block qb} Jc[m][q] * sigma[idx[q]]
 void jvec(const float* Jc, int M, int qa_pad, const int* idx, const float* sigma, float* ppart,
           int batch, long long istride, hipStream_t s);
-// Each block first forms, for its kJtRows rows, p = sum_qb ppart (column-block
-// order), r = p - dv and gp = (2/M) r; blocks of the first column write
-// rsum[mb] = sum r^2 (FP64).  Then tpart[mb][q] = sum_{m in mb} Jc[m][q] gp[m].
+// For every group of kJtRows rows: p = sum_qb ppart (column-block order),
+// r = p - dv, gp = (2/M) r and rsum[mb] = sum r^2 (FP64); then for each of
+// the jt_partials(M, qa_pad) row groups g: tpart[g][q] = sum_{m in g}
+// Jc[m][q] gp[m].  (Few column blocks: every J^T g block forms its rows'
+// residual; many: one residual launch first, then longer row groups.)
 void jtvec(const float* Jc, int M, int qa_pad, const float* ppart, int nqb, const float* dv,
            double* rsum, float* tpart, int batch, long long istride, hipStream_t s);
 // sigma[v] = mask[v] * (b + sum_c w[c] d0[v][c])
