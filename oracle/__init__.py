@@ -9,7 +9,9 @@ NumPy in float64, written from the paper's definitions:
              reverse-mode gradient;
 * ``fit``  - the data term of Eq. (4), Adam, the TPP frame schedule
              (Eqs. (5), (9)) and the read-out;
-* ``tv``   - the 4D-TV regulariser of Eqs. (11)-(14).
+* ``tv``   - the 4D-TV regulariser of Eqs. (11)-(14);
+* ``dwsep``- the depthwise-separable 3D convolution of the lightweight
+             backbone (Sec. III-D) and its gradients.
 
 Parity pins (tests/test_oracle_*.py): central finite differences, brute-force
 7-loop convolution, torch CPU float64 library operations, adjoint identities,
