@@ -329,6 +329,29 @@ d2ip_status d2ip_op_ln_relu_backward(const float* x, const float* y, const float
                                      float* dgamma_dbeta, int n, int C, void* workspace,
                                      size_t bytes, void* hip_stream);
 
+/* Workspace bytes of d2ip_op_dwconv3d_backward's weight gradient (C a
+ * multiple of 4 in [4, 1024]). */
+d2ip_status d2ip_op_dwconv3d_bytes(int n, int C, size_t* out);
+
+/* Depthwise 3x3x3 convolution, the first half of a depthwise-separable
+ * convolution of the lightweight backbone (Sec. III-D):
+ * y[v][c] = b[c] + sum_tap w[c][tap] x[v + offset(tap)][c] (cross-correlation,
+ * zero padding; w [C][kz][ky][kx], i.e. the canonical [C][1][3][3][3]; b may be
+ * NULL).  x, y (and b) 16-byte aligned.  The second half, the pointwise
+ * 1x1x1 convolution, is d2ip_op_conv3d_forward with taps = 1.  Needs no
+ * workspace and uploads nothing. */
+d2ip_status d2ip_op_dwconv3d_forward(const float* x, const float* w, const float* b, float* y,
+                                     int n, int C, void* hip_stream);
+
+/* Gradients of d2ip_op_dwconv3d_forward given gy = dL/dy: gx = dL/dx (the
+ * same convolution with the taps reversed), gw = dL/dw [C][27] and
+ * gb = dL/db [C]; any output may be NULL; x is needed only for gw / gb, w only
+ * for gx, and the workspace only for gw / gb.  Sums over voxels are reduced
+ * in a fixed order (deterministic). */
+d2ip_status d2ip_op_dwconv3d_backward(const float* x, const float* w, const float* gy, float* gx,
+                                      float* gw, float* gb, int n, int C, void* workspace,
+                                      size_t bytes, void* hip_stream);
+
 /* p = J sigma for a dense row-major M x Q J (Eq. (1)); Q a multiple of 4. */
 d2ip_status d2ip_op_j_forward(const float* J, const float* sigma, float* p, int M, int Q,
                               void* hip_stream);

@@ -242,6 +242,15 @@ void jv_dense(const float* J, int M, int Q, const float* sigma, float* p, hipStr
 size_t jt_dense_scratch(int Q);  // floats of `part`
 void jt_dense(const float* J, int M, int Q, const float* g, float* part, float* out,
               hipStream_t s);
+// Depthwise 3x3x3 convolution (channels-last [n^3][C], C % 4 == 0, w [C][27]):
+// y = b + depthwise(x, w), or with flip the input gradient (taps reversed, b
+// unused); dw_wgrad writes dw_partials(n, C) floats of `part` and reduces them
+// into gw [C][27] and gb [C] (either may be null).
+size_t dw_partials(int n, int C);
+void dw_forward(const float* x, const float* w, const float* b, float* y, int n, int C, bool flip,
+                hipStream_t s);
+void dw_wgrad(const float* x, const float* gy, float* part, float* gw, float* gb, int n, int C,
+              hipStream_t s);
 // The launch shape the plan's heuristic picks for a forward / input-gradient
 // pass with `cin` inputs and `cout` outputs (precision: PREC_*).
 void default_conv_shape(int n, int cin, int cout, int taps, int prec, int* tile, int* bn, int* ck,

@@ -182,6 +182,15 @@ d2ip_status ln_check(int n, int C) {
   return D2IP_OK;
 }
 
+d2ip_status dw_check(int n, int C) {
+  if (n < 1 || n > 256) return api_fail(D2IP_EINVAL, "n must be in [1, 256]");
+  if (C < 4 || C > 1024 || C % 4 != 0)
+    return api_fail(D2IP_EINVAL, "C must be a multiple of 4 in [4, 1024]");
+  return D2IP_OK;
+}
+
+bool aligned16(const void* p) { return ((uintptr_t)p & 15) == 0; }
+
 struct LnOp {
   double *st = nullptr, *part_c = nullptr, *part_ab = nullptr;
   float* gz = nullptr;
@@ -354,6 +363,47 @@ d2ip_status d2ip_op_ln_relu_backward(const float* x, const float* y, const float
     OPCHK(hipMemcpyAsync(l.seg, &g, sizeof(g), hipMemcpyHostToDevice, s));
     grad_reduce(l.seg, 1, 2 * C, nullptr, nullptr, l.part_c, dgamma_dbeta, 1, 0, s);
   }
+  OPCHK(hipGetLastError());
+  return D2IP_OK;
+}
+
+d2ip_status d2ip_op_dwconv3d_bytes(int n, int C, size_t* out) {
+  if (!out) return api_fail(D2IP_EINVAL, "null output");
+  d2ip_status st = dw_check(n, C);
+  if (st != D2IP_OK) return st;
+  *out = dw_partials(n, C) * sizeof(float) + 256;
+  return D2IP_OK;
+}
+
+d2ip_status d2ip_op_dwconv3d_forward(const float* x, const float* w, const float* b, float* y,
+                                     int n, int C, void* hip_stream) {
+  d2ip_status st = dw_check(n, C);
+  if (st != D2IP_OK) return st;
+  if (!x || !w || !y) return api_fail(D2IP_EINVAL, "null x, w or y");
+  if (!aligned16(x) || !aligned16(y) || (b && !aligned16(b)))
+    return api_fail(D2IP_EINVAL, "x, y and b must be 16-byte aligned");
+  dw_forward(x, w, b, y, n, C, false, reinterpret_cast<hipStream_t>(hip_stream));
+  OPCHK(hipGetLastError());
+  return D2IP_OK;
+}
+
+d2ip_status d2ip_op_dwconv3d_backward(const float* x, const float* w, const float* gy, float* gx,
+                                      float* gw, float* gb, int n, int C, void* workspace,
+                                      size_t bytes, void* hip_stream) {
+  d2ip_status st = dw_check(n, C);
+  if (st != D2IP_OK) return st;
+  if (!gy || (gx && !w) || ((gw || gb) && !x))
+    return api_fail(D2IP_EINVAL, "null gy, or null w with gx, or null x with gw / gb");
+  if (!aligned16(gy) || (gx && !aligned16(gx)) || (x && !aligned16(x)))
+    return api_fail(D2IP_EINVAL, "x, gy and gx must be 16-byte aligned");
+  hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
+  if (gw || gb) {
+    size_t need = 0;
+    d2ip_op_dwconv3d_bytes(n, C, &need);
+    if ((st = ws_check(workspace, bytes, need)) != D2IP_OK) return st;
+    dw_wgrad(x, gy, reinterpret_cast<float*>(workspace), gw, gb, n, C, s);
+  }
+  if (gx) dw_forward(gy, w, nullptr, gx, n, C, true, s);
   OPCHK(hipGetLastError());
   return D2IP_OK;
 }

@@ -1,9 +1,11 @@
 """PyTorch autograd operators over the library's standalone kernels.
 
-``Conv3dFn``, ``LayerNormReLUFn`` and ``MeasureFn`` wrap the op-level C-ABI
-(include/d2ip.h): their forward and backward passes are the library's HIP
-kernels (implicit-GEMM convolutions with the input and weight gradients, the
-whole-volume LayerNorm + ReLU and its backward, J sigma and J^T g).  ``DIPNet``
+``Conv3dFn``, ``DWConv3dFn``, ``LayerNormReLUFn`` and ``MeasureFn`` wrap the
+op-level C-ABI (include/d2ip.h): their forward and backward passes are the
+library's HIP kernels (implicit-GEMM convolutions with the input and weight
+gradients, the depthwise 3x3x3 convolution of the depthwise-separable
+convolution and its gradients, the whole-volume LayerNorm + ReLU and its
+backward, J sigma and J^T g).  ``DIPNet``
 composes the prior of Eq. (3) from them; pooling, up-sampling, channel
 concatenation and the 1x1x1 output head are plain tensor operations of the
 model around the operators.  With ``recompute=True`` every ResBlock's
@@ -64,6 +66,24 @@ class LayerNormReLUFn:
         return _ln_fn().apply(x, gamma, beta, skip)
 
 
+class DWConv3dFn:
+    """y = depthwise conv3d(x, w, b): x [n^3, C] (C % 4 == 0), w [C, 1, 3, 3, 3] or
+    [C, 3, 3, 3], b [C] or None (Sec. III-D's depthwise-separable convolution,
+    first half)."""
+
+    @staticmethod
+    def apply(x, w, b=None):
+        return _dw_fn().apply(x, w, b)
+
+
+def dwsep_conv3d(x, wd, bd, wp, bp, precision="fp32"):
+    """Depthwise-separable convolution: the depthwise 3x3x3 convolution, then
+    the pointwise 1x1x1 one (wp [Cout, C] or [Cout, C, 1, 1, 1]), both on the
+    library's kernels."""
+    d = DWConv3dFn.apply(x, wd, bd)
+    return Conv3dFn.apply(d, wp.reshape(wp.shape[0], wp.shape[1], 1, 1, 1), bp, precision)
+
+
 class MeasureFn:
     """p = J sigma (J dense [M, Q]); its backward is g_sigma = J^T g_p."""
 
@@ -118,6 +138,49 @@ def _conv_fn():
 
     _FNS["conv"] = _Conv
     return _Conv
+
+
+def _dw_fn():
+    if "dw" in _FNS:
+        return _FNS["dw"]
+    torch = _torch()
+
+    class _DW(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, x, w, b):
+            lib = L.load()
+            x, w = x.contiguous(), w.contiguous()
+            b = b.contiguous() if b is not None else None
+            V, C = x.shape
+            if w.numel() != 27 * C:
+                raise ValueError("w must hold C x 27 taps")
+            n = _grid_n(V)
+            y = torch.empty_like(x)
+            L.check(lib.d2ip_op_dwconv3d_forward(_p(x), _p(w), _p(b), _p(y), n, C, _stream(x)))
+            ctx.save_for_backward(x, w)
+            ctx.meta = (n, C, b is not None)
+            return y
+
+        @staticmethod
+        def backward(ctx, gy):
+            lib = L.load()
+            x, w = ctx.saved_tensors
+            n, C, has_b = ctx.meta
+            gy = gy.contiguous()
+            need_x, need_w, need_b = ctx.needs_input_grad[:3]
+            gx = torch.empty_like(x) if need_x else None
+            gw = torch.empty_like(w) if need_w else None
+            gb = torch.empty(C, dtype=torch.float32, device=x.device) if (need_b and has_b) \
+                else None
+            ws, nb = (None, 0)
+            if gw is not None or gb is not None:
+                ws, nb = _workspace(lib.d2ip_op_dwconv3d_bytes, n, C, device=x.device)
+            L.check(lib.d2ip_op_dwconv3d_backward(_p(x), _p(w), _p(gy), _p(gx), _p(gw), _p(gb),
+                                                  n, C, _p(ws), nb, _stream(x)))
+            return gx, gw, gb
+
+    _FNS["dw"] = _DW
+    return _DW
 
 
 def _ln_fn():

@@ -171,6 +171,21 @@ static int ops_case() {
                               ggb.data(), n, C, ws, need, &token));
   free(ws);
   EXPECT_ERR(d2ip_op_ln_relu_bytes(n, 12, &need), D2IP_EINVAL);
+  for (int Cd : {4, 8, 12, 16, 32}) {
+    std::vector<float> wd((size_t)Cd * 27), bd(Cd), gwd(wd.size()), gbd(Cd);
+    CK(d2ip_op_dwconv3d_bytes(n, Cd, &need));
+    ws = (char*)aligned_alloc(256, (need + 255) / 256 * 256);
+    CK(d2ip_op_dwconv3d_forward(x.data(), wd.data(), bd.data(), y.data(), n, Cd, &token));
+    CK(d2ip_op_dwconv3d_backward(x.data(), wd.data(), g.data(), gx.data(), gwd.data(), gbd.data(),
+                                 n, Cd, ws, need, &token));
+    EXPECT_ERR(d2ip_op_dwconv3d_backward(x.data(), wd.data(), g.data(), gx.data(), gwd.data(),
+                                         nullptr, n, Cd, ws, need - 1, &token),
+               D2IP_ENOMEM);
+    free(ws);
+  }
+  EXPECT_ERR(d2ip_op_dwconv3d_bytes(n, 6, &need), D2IP_EINVAL);
+  EXPECT_ERR(d2ip_op_dwconv3d_forward(x.data() + 1, gam.data(), nullptr, y.data(), n, C, &token),
+             D2IP_EINVAL);
   CK(d2ip_op_j_forward(J.data(), x.data(), p.data(), M, Q, &token));
   CK(d2ip_op_jt_bytes(M, Q, &need));
   ws = (char*)aligned_alloc(256, (need + 255) / 256 * 256);

@@ -1,0 +1,150 @@
+"""GPU tests of the depthwise 3x3x3 convolution (forward, input and weight
+gradients) and of the depthwise-separable composition (depthwise, then the
+pointwise 1x1x1 convolution), against the FP64 oracle (oracle/dwsep.py).
+
+Cases span every channel-quad blocking the kernels pick (C/4 odd, even, a
+multiple of 4 and of 8, several channel chunks), ragged tiles in x, y and z,
+the degenerate one- and two-voxel grids, and the 64^3 x 64 workload that the
+benchmark times (there sampled outputs and the full weight gradient)."""
+import numpy as np
+import pytest
+
+from oracle import dwsep
+from tests.gpu_util import record, rel
+
+pytestmark = pytest.mark.gpu
+
+# FP32 against FP64: the forward and input gradient sum 27 products per
+# value; the weight and bias gradients sum n^3 products per value in a fixed
+# tree, whose rounding grows with the depth of the tree (log2 of the sum's
+# length), not with its length.
+TOL_Y = 2e-6
+TOL_W = 1e-5
+
+
+def cl(x):
+    return np.ascontiguousarray(x.reshape(x.shape[0], -1).T)
+
+
+def cf(x, n):
+    return np.ascontiguousarray(np.asarray(x).T.reshape(-1, n, n, n))
+
+
+def dev(a, grad=False):
+    import torch
+    return torch.tensor(np.ascontiguousarray(a), dtype=torch.float32, device="cuda",
+                        requires_grad=grad)
+
+
+def host(t):
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+def _case(n, C, seed):
+    rng = np.random.default_rng(seed)
+    x = rng.standard_normal((C, n, n, n)).astype(np.float32)
+    w = (0.3 * rng.standard_normal((C, 3, 3, 3))).astype(np.float32)
+    b = rng.standard_normal(C).astype(np.float32)
+    g = rng.standard_normal((C, n, n, n)).astype(np.float32)
+    return x, w, b, g
+
+
+@pytest.mark.parametrize("n,C", [(1, 4), (2, 8), (5, 12), (8, 16), (13, 24), (9, 32), (11, 64),
+                                 (16, 4), (17, 8), (20, 40)])
+def test_depthwise_matches_oracle(lib, n, C):
+    from paper_2507_14046_amd import ops
+    x, w, b, g = _case(n, C, 7000 + 100 * n + C)
+    f = lambda a: a.astype(np.float64)
+    yref = dwsep.dwconv3d(f(x), f(w), f(b))
+    gxr, gwr, gbr = dwsep.dwconv3d_backward(f(x), f(w), f(g))
+    X, W, B = dev(cl(x), True), dev(w[:, None], True), dev(b, True)
+    Y = ops.DWConv3dFn.apply(X, W, B)
+    Y.backward(dev(cl(g)))
+    e = dict(y=rel(cf(host(Y), n), yref), gx=rel(cf(host(X.grad), n), gxr),
+             gw=rel(host(W.grad)[:, 0], gwr), gb=rel(host(B.grad), gbr))
+    record("dwconv3d", n=n, C=C, **e)
+    assert e["y"] < TOL_Y and e["gx"] < TOL_Y, e
+    assert e["gw"] < TOL_W and e["gb"] < TOL_W, e
+
+
+def test_depthwise_adjoint_and_determinism(lib):
+    """<g, dw(x)> = <dw^T(g), x> with zero bias, and two backward passes give
+    the same bits."""
+    import torch
+    from paper_2507_14046_amd import ops
+    n, C = 12, 16
+    x, w, _, g = _case(n, C, 4242)
+    X, W, G = dev(cl(x)), dev(w), dev(cl(g))
+    Y = ops.DWConv3dFn.apply(X, W, None)
+    outs = []
+    for _ in range(2):
+        Xg, Wg = X.clone().requires_grad_(True), W.clone().requires_grad_(True)
+        ops.DWConv3dFn.apply(Xg, Wg, None).backward(G)
+        outs.append((Xg.grad.clone(), Wg.grad.clone()))
+    lhs = float((Y.double() * G.double()).sum())
+    rhs = float((outs[0][0].double() * X.double()).sum())
+    assert abs(lhs - rhs) <= 1e-5 * abs(lhs), (lhs, rhs)
+    assert torch.equal(outs[0][0], outs[1][0]) and torch.equal(outs[0][1], outs[1][1])
+
+
+@pytest.mark.parametrize("C,Co", [(16, 24), (32, 8)])
+def test_depthwise_separable_composition_matches_oracle(lib, C, Co):
+    from paper_2507_14046_amd import ops
+    n = 10
+    rng = np.random.default_rng(90 + C + Co)
+    x, wd, bd, _ = _case(n, C, 91 + C)
+    wp = (0.2 * rng.standard_normal((Co, C))).astype(np.float32)
+    bp = rng.standard_normal(Co).astype(np.float32)
+    R = rng.standard_normal((Co, n, n, n)).astype(np.float32)
+    f = lambda a: a.astype(np.float64)
+    yref, d = dwsep.dwsep_conv3d(f(x), f(wd), f(bd), f(wp), f(bp))
+    refs = dwsep.dwsep_conv3d_backward(f(x), f(wd), f(wp), d, f(R))
+    X, WD, BD = dev(cl(x), True), dev(wd, True), dev(bd, True)
+    WP, BP = dev(wp, True), dev(bp, True)
+    Y = ops.dwsep_conv3d(X, WD, BD, WP, BP)
+    Y.backward(dev(cl(R)))
+    got = (cf(host(X.grad), n), host(WD.grad), host(BD.grad), host(WP.grad), host(BP.grad))
+    e = dict(y=rel(cf(host(Y), n), yref))
+    for k, gg, rr in zip(("gx", "gwd", "gbd", "gwp", "gbp"), got, refs):
+        e[k] = rel(gg, rr)
+    record("dwsep_conv3d", C=C, Co=Co, **e)
+    assert e["y"] < TOL_Y and e["gx"] < TOL_Y, e
+    assert max(e["gwd"], e["gbd"], e["gwp"], e["gbp"]) < TOL_W, e
+
+
+def _dw_at(xp, w, b, c, z, y, x):
+    """Depthwise output at one voxel from the zero-padded input (FP64)."""
+    return b[c] + (w[c] * xp[c, z:z + 3, y:y + 3, x:x + 3]).sum()
+
+
+def test_depthwise_full_size_workload(lib):
+    """64^3 x 64: sampled forward and input-gradient outputs against the
+    oracle's definition at those voxels, the full weight and bias gradients
+    against the oracle."""
+    from paper_2507_14046_amd import ops
+    n, C = 64, 64
+    x, w, b, g = _case(n, C, 64064)
+    X, W, B = dev(cl(x), True), dev(w, True), dev(b, True)
+    Y = ops.DWConv3dFn.apply(X, W, B)
+    Y.backward(dev(cl(g)))
+    y, gx = host(Y), host(X.grad)
+    f = lambda a: a.astype(np.float64)
+    xp = np.pad(f(x), ((0, 0), (1, 1), (1, 1), (1, 1)))
+    gp = np.pad(f(g), ((0, 0), (1, 1), (1, 1), (1, 1)))
+    wf = f(w[:, ::-1, ::-1, ::-1])  # input gradient = taps reversed
+    rng = np.random.default_rng(5)
+    pts = [(0, 0, 0), (63, 63, 63), (0, 63, 31), (31, 0, 63)]
+    pts += [tuple(v) for v in rng.integers(0, n, (60, 3))]
+    ey = eg = 0.0
+    for (z, yy, xx) in pts:
+        v = (z * n + yy) * n + xx
+        for c in rng.integers(0, C, 4):
+            ry = _dw_at(xp, f(w), f(b), c, z, yy, xx)
+            rg = _dw_at(gp, wf, np.zeros(C), c, z, yy, xx)
+            ey = max(ey, abs(y[v, c] - ry) / (1 + abs(ry)))
+            eg = max(eg, abs(gx[v, c] - rg) / (1 + abs(rg)))
+    _, gwr, gbr = dwsep.dwconv3d_backward(f(x), f(w), f(g))
+    e = dict(y_sampled=ey, gx_sampled=eg, gw=rel(host(W.grad), gwr), gb=rel(host(B.grad), gbr))
+    record("dwconv3d_64", **e)
+    assert ey < 1e-5 and eg < 1e-5, e
+    assert e["gw"] < TOL_W and e["gb"] < TOL_W, e
