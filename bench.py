@@ -215,6 +215,74 @@ def kernel_table(d2ip, ctx, p, cfg, prec):
     return rows
 
 
+def dwsep_ops(d2ip, torch, shapes=((64, 64, 64), (32, 16, 16))):
+    """The depthwise-separable convolution's operators (depthwise 3x3x3:
+    forward, input gradient, weight gradient; pointwise 1x1x1 forward) through
+    the op-level C-ABI on synthetic channels-last FP32 tensors, each launch
+    timed with HIP events on the stream it is enqueued on.  Algorithmic bytes
+    of a depthwise pass: its two n^3 x C tensors (read + write, or the two
+    reads of the weight gradient), 8 bytes per value; the pointwise pass is
+    priced both ways (HBM bytes and FP32 flops)."""
+    import ctypes
+    L = d2ip._lib
+    lib = L.load()
+    P = lambda t: ctypes.c_void_p(t.data_ptr()) if t is not None else None
+    st = torch.cuda.current_stream()
+    sp = ctypes.c_void_p(st.cuda_stream)
+    g = torch.Generator(device="cuda").manual_seed(2507)
+    out = {}
+    for n, C, Co in shapes:
+        V = n ** 3
+        x = torch.randn(V, C, device="cuda", generator=g)
+        w = 0.2 * torch.randn(C, 27, device="cuda", generator=g)
+        b = torch.randn(C, device="cuda", generator=g)
+        gy = torch.randn(V, C, device="cuda", generator=g)
+        y, gx = torch.empty_like(x), torch.empty_like(x)
+        gw, gb = torch.empty_like(w), torch.empty_like(b)
+        wp = 0.2 * torch.randn(Co, C, 1, 1, 1, device="cuda", generator=g)
+        bp = torch.randn(Co, device="cuda", generator=g)
+        yp = torch.empty(V, Co, device="cuda")
+        nb = ctypes.c_size_t()
+        L.check(lib.d2ip_op_dwconv3d_bytes(n, C, ctypes.byref(nb)))
+        ws = torch.empty(nb.value, dtype=torch.uint8, device="cuda")
+        pb = ctypes.c_size_t()
+        L.check(lib.d2ip_op_conv3d_bytes(n, C, Co, 1, L.PLAIN_FP32, ctypes.byref(pb)))
+        pws = torch.empty(pb.value, dtype=torch.uint8, device="cuda")
+        calls = {
+            "dw_forward": lambda: lib.d2ip_op_dwconv3d_forward(P(x), P(w), P(b), P(y), n, C, sp),
+            "dw_input_grad": lambda: lib.d2ip_op_dwconv3d_backward(
+                None, P(w), P(gy), P(gx), None, None, n, C, None, 0, sp),
+            "dw_weight_grad": lambda: lib.d2ip_op_dwconv3d_backward(
+                P(x), None, P(gy), None, P(gw), P(gb), n, C, P(ws), nb.value, sp),
+            "pw_forward": lambda: lib.d2ip_op_conv3d_forward(
+                P(y), P(wp), P(bp), P(yp), n, C, Co, 1, L.PLAIN_FP32, P(pws), pb.value, sp),
+        }
+        rows = {}
+        for name, f in calls.items():
+            for _ in range(5):
+                L.check(f())
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(st)
+            for _ in range(50):
+                f()
+            e1.record(st)
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / 50
+            byts = 4.0 * V * (C + (Co if name == "pw_forward" else C))
+            r = dict(ms=ms, bound="hbm", achieved=byts / (ms * 1e-3) / 1e9, peak=HBM_PEAK_GBS,
+                     unit="GB/s")
+            r["frac"] = r["achieved"] / r["peak"]
+            if name == "pw_forward":
+                fl = 2.0 * V * C * Co
+                r["tflops"] = fl / (ms * 1e-3) / 1e12
+                r["tflops_frac_fp32"] = r["tflops"] / PEAK_TFLOPS["fp32"]
+            rows[name] = r
+            log("  %d^3 C=%d %-15s %8.4f ms  %7.0f GB/s (%.1f%% of HBM peak)"
+                % (n, C, name, ms, r["achieved"], 100 * r["frac"]))
+        out["%d^3 x %d -> %d" % (n, C, Co)] = rows
+    return out
+
+
 def cpu_baseline(p, cfg, budget_s):
     from oracle import fit
     try:
@@ -364,6 +432,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-kernels", action="store_true")
     ap.add_argument("--no-configs", action="store_true")
+    ap.add_argument("--no-dwsep", action="store_true")
     ap.add_argument("--ablation", action="store_true",
                     help="also run the D2IP schedule ablation (UPWS / TPP) on a 20-frame "
                          "32^3 sequence in the chosen form (about a minute)")
@@ -501,6 +570,7 @@ def main():
         log("ablation (%.0f s): %s" % (time.time() - t0, json.dumps(
             {k: (v["total_iterations"], round(v["seconds"], 2), v["all_reached"])
              for k, v in ablation["variants"].items()})))
+    dwsep = None if a.no_dwsep else dwsep_ops(d2ip, torch)
     cpu = None if a.no_cpu else cpu_baseline(p, cfg, a.cpu_seconds)
     out = {
         "metric": METRIC,
@@ -531,6 +601,7 @@ def main():
         "fp32_with_4d_tv": with_tv,
         "configs": configs,
         "ablation": ablation,
+        "dwsep_ops": dwsep,
         "roofline": roof,
         "cpu_baseline": cpu,
     }

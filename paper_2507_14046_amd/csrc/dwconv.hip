@@ -1,27 +1,34 @@
 // Depthwise 3x3x3 convolution of the lightweight backbone's depthwise-
 // separable convolutions (Sec. III-D): forward, input gradient and weight
 // gradient on channels-last FP32 tensors [n^3][C], C a multiple of 4.  An
-// output needs 27 multiply-adds per input value read, far too few for the
-// matrix cores to matter: the operator is bound by HBM.  A block stages the
-// halo of a voxel tile for KQ channel quads in LDS with coalesced loads (lanes
-// run over the quads of a voxel first, so a wave reads whole 16*KQ-byte
-// voxel rows), and each thread walks a z column of 4 outputs, so that every
-// LDS value loaded serves the three output planes it touches.
+// output value needs 27 multiply-adds per 8 bytes of HBM traffic (its input
+// read once, itself written once): a per-channel stencil, not a contraction,
+// so the matrix cores do not apply, and the FP32 vector rate puts the
+// arithmetic within reach of the HBM time.  A block takes a (y, x) tile for
+// KQ channel quads and streams a segment of z planes through LDS, loading the
+// halo plane with coalesced float4 loads (lanes run over the quads of a voxel
+// first) while the previous planes are computed; each thread walks one z
+// column, and every value it reads from LDS serves the three output planes it
+// touches.
 #include "kernels.h"
 
 namespace d2ip {
 namespace {
 
 constexpr int kDwParts = 28;  // per channel: 27 tap sums, then the bias sum
+constexpr int kDwFwdGroup = 4;  // halo planes per group: forward / input gradient
+constexpr int kDwWgGroup = 4;   // weight gradient (its accumulators leave fewer registers)
+constexpr int kDwRedChunk = 4;  // accumulators per step of the weight gradient's block sum
 
-// Tile of a block with KQ channel quads per voxel: 256 / KQ (y, x) columns of
-// 4 voxels along z, one thread per (column, quad).
+// A block covers a (y, x) tile of 256 / KQ columns for KQ channel quads and
+// walks a segment of z planes; one thread per (column, quad).  A halo plane
+// holds (TY + 2) x (TX + 2) positions x KQ quads.
 template <int KQ>
 struct DwGeo {
-  static constexpr int TZ = 4, TY = KQ >= 4 ? 8 : 16, TX = 256 / KQ / TY;
-  static constexpr int HY = TY + 2, HX = TX + 2, HALO = (TZ + 2) * HY * HX;
+  static constexpr int TY = KQ >= 4 ? 8 : 16, TX = 256 / KQ / TY;
+  static constexpr int HY = TY + 2, HX = TX + 2, PLANE = HY * HX * KQ;  // float4
   static constexpr int SHIFT = KQ == 8 ? 3 : KQ == 4 ? 2 : KQ == 2 ? 1 : 0;
-  static constexpr int NLOAD = (HALO * KQ + 255) / 256;  // halo loads per thread
+  static constexpr int NL = (PLANE + 255) / 256;  // halo-plane loads per thread
 };
 
 // Physical block -> logical block, so that consecutive logical blocks (which
@@ -33,60 +40,60 @@ __device__ __forceinline__ int dw_logical(int nb) {
   return (blockIdx.x & 7) * per + (blockIdx.x >> 3);
 }
 
+// Block coordinates: (y, x) tile fastest, then z segment, then channel chunk.
 template <int KQ>
-struct DwTile {
-  int z0, y0, x0;
-  __device__ DwTile(int t, int n) {
+struct DwBlock {
+  int x0, y0, zb, ze, sg, txy, c0;
+  __device__ DwBlock(int L, int n, int ntxy, int nseg, int seglen) {
     using G = DwGeo<KQ>;
-    const int ntx = (n + G::TX - 1) / G::TX, nty = (n + G::TY - 1) / G::TY;
-    x0 = (t % ntx) * G::TX;
-    t /= ntx;
-    y0 = (t % nty) * G::TY;
-    z0 = (t / nty) * G::TZ;
+    txy = L % ntxy;
+    sg = (L / ntxy) % nseg;
+    c0 = (L / (ntxy * nseg)) * 4 * KQ;
+    const int ntx = (n + G::TX - 1) / G::TX;
+    x0 = (txy % ntx) * G::TX;
+    y0 = (txy / ntx) * G::TY;
+    zb = sg * seglen;
+    ze = min(n, zb + seglen);
   }
 };
 
-// Loads the halo of the tile at (z0, y0, x0) for channel quads
-// c0/4 .. c0/4 + KQ - 1 (zeros outside the grid) and writes it to hal
-// [(hz * HY + hy) * HX + hx][q].  Every load is issued before the first LDS
-// write, from clamped (always valid) addresses.
-// Loads are issued in batches of BATCH per thread (all of a batch before its
-// LDS writes), which bounds the registers the staging holds.
-template <int KQ, int BATCH>
-__device__ __forceinline__ void dw_stage(float4* hal, const float* __restrict__ x, int n, int C,
-                                         int c0, int z0, int y0, int x0) {
+// The thread's share of a halo plane: element e = tid + 256 i of the plane
+// (position (hy, hx), quad q) sits at a fixed (y, x) for every plane, so its
+// clamped in-plane offset and in-grid flag are computed once.
+template <int KQ>
+struct DwStager {
   using G = DwGeo<KQ>;
-  constexpr int total = G::HALO * KQ;
+  size_t off[G::NL];
+  bool xyin[G::NL];
+  size_t plane_stride;
+  int n;
+  __device__ DwStager(int n_, int C, int c0, int y0, int x0) : n(n_) {
+    plane_stride = (size_t)n * n * C;
 #pragma unroll
-  for (int i0 = 0; i0 < G::NLOAD; i0 += BATCH) {
-    float4 r[BATCH];
-    bool in[BATCH];
-#pragma unroll
-    for (int j = 0; j < BATCH; ++j) {
-      const int e = min((int)threadIdx.x + 256 * (i0 + j), total - 1);
+    for (int i = 0; i < G::NL; ++i) {
+      const int e = min((int)threadIdx.x + 256 * i, G::PLANE - 1);
       const int q = e & (KQ - 1), p = e >> G::SHIFT;
-      const int hx = p % G::HX, hy = (p / G::HX) % G::HY, hz = p / (G::HX * G::HY);
-      const int gz = z0 + hz - 1, gy = y0 + hy - 1, gx = x0 + hx - 1;
-      in[j] = (unsigned)gz < (unsigned)n && (unsigned)gy < (unsigned)n &&
-              (unsigned)gx < (unsigned)n;
-      const int cz = min(max(gz, 0), n - 1), cy = min(max(gy, 0), n - 1),
-                cx = min(max(gx, 0), n - 1);
-      r[j] = *reinterpret_cast<const float4*>(x + ((size_t)(cz * n + cy) * n + cx) * C + c0 +
-                                              4 * q);
-    }
-#pragma unroll
-    for (int j = 0; j < BATCH; ++j) {
-      const int e = (int)threadIdx.x + 256 * (i0 + j);
-      if (i0 + j < G::NLOAD && e < total) hal[e] = in[j] ? r[j] : make_float4(0.f, 0.f, 0.f, 0.f);
+      const int gy = y0 + p / G::HX - 1, gx = x0 + p % G::HX - 1;
+      xyin[i] = (unsigned)gy < (unsigned)n && (unsigned)gx < (unsigned)n;
+      off[i] = ((size_t)min(max(gy, 0), n - 1) * n + min(max(gx, 0), n - 1)) * C + c0 + 4 * q;
     }
   }
-}
-
-// Keeps the compiler from sinking the accumulation of a below this point
-// (into the guarded stores), which would keep every LDS value loaded live.
-__device__ __forceinline__ void dw_pin(float4& a) {
-  asm volatile("" : "+v"(a.x), "+v"(a.y), "+v"(a.z), "+v"(a.w));
-}
+  // Issue the loads of plane z (clamped into the grid; always valid).
+  __device__ __forceinline__ void load(const float* __restrict__ x, int z, float4 (&r)[G::NL]) const {
+    const float* base = x + (size_t)min(max(z, 0), n - 1) * plane_stride;
+#pragma unroll
+    for (int i = 0; i < G::NL; ++i) r[i] = *reinterpret_cast<const float4*>(base + off[i]);
+  }
+  // Write plane z's loaded values to LDS (zeros outside the grid).
+  __device__ __forceinline__ void store(float4* hal, int z, const float4 (&r)[G::NL]) const {
+    const bool zin = (unsigned)z < (unsigned)n;
+#pragma unroll
+    for (int i = 0; i < G::NL; ++i) {
+      const int e = (int)threadIdx.x + 256 * i;
+      if (e < G::PLANE) hal[e] = (zin && xyin[i]) ? r[i] : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+  }
+};
 
 __device__ __forceinline__ void fma4(float4& a, const float4& k, const float4& v) {
   a.x += k.x * v.x;
@@ -95,163 +102,213 @@ __device__ __forceinline__ void fma4(float4& a, const float4& k, const float4& v
   a.w += k.w * v.w;
 }
 
+// Keeps the compiler from sinking an accumulation below this point (into a
+// guarded store), which would keep every LDS value loaded live.
+__device__ __forceinline__ void dw_pin(float4& a) {
+  asm volatile("" : "+v"(a.x), "+v"(a.y), "+v"(a.z), "+v"(a.w));
+}
+
 // y[v][c] = b[c] + sum_tap w[c][tap] x[v + offset(tap)][c]; with flip the
 // taps are taken in reverse (w[c][26 - tap]) and b is ignored, which makes
-// the kernel the input gradient of the forward one.  Logical blocks:
-// (voxel tile) fastest, then channel chunk of KQ quads.
-template <int KQ>
-__global__ __launch_bounds__(256, 3) void k_dw_fwd(const float* __restrict__ x,
-                                                const float* __restrict__ w,
-                                                const float* __restrict__ b, float* __restrict__ y,
-                                                int n, int C, int ntiles, int flip) {
+// the kernel the input gradient of the forward one.  Input planes zb-1 .. ze
+// pass through LDS in groups of D, the next group loading while one is
+// computed; when plane
+// p is in LDS the thread adds its 3 x 3 neighbourhood into outputs p+1 (taps
+// dz = 0), p (dz = 1) and p-1 (dz = 2), and output p-1 is then complete.
+template <int KQ, int D>
+__global__ __launch_bounds__(256, 2) void k_dw_fwd(const float* __restrict__ x,
+                                                   const float* __restrict__ w,
+                                                   const float* __restrict__ b,
+                                                   float* __restrict__ y, int n, int C, int ntxy,
+                                                   int nseg, int seglen, int flip) {
   using G = DwGeo<KQ>;
-  __shared__ float4 hal[G::HALO * KQ];
+  __shared__ float4 hal[D][G::PLANE];
   __shared__ float4 wl[27 * KQ];
-  const int nchunks = C / (4 * KQ);
-  const int L = dw_logical(ntiles * nchunks);
-  if (L >= ntiles * nchunks) return;  // whole block: no barrier reached
-  const int c0 = (L / ntiles) * 4 * KQ;
-  const DwTile<KQ> t(L % ntiles, n);
-  dw_stage<KQ, DwGeo<KQ>::NLOAD>(hal, x, n, C, c0, t.z0, t.y0, t.x0);
+  const int nb = ntxy * nseg * (C / (4 * KQ));
+  const int L = dw_logical(nb);
+  if (L >= nb) return;  // whole block: no barrier reached
+  const DwBlock<KQ> bk(L, n, ntxy, nseg, seglen);
+  const DwStager<KQ> st(n, C, bk.c0, bk.y0, bk.x0);
+  float4 r[D][G::NL];
+#pragma unroll
+  for (int j = 0; j < D; ++j) st.load(x, min(bk.zb - 1 + j, bk.ze), r[j]);
   if (threadIdx.x < 27 * KQ) {
     const int tap = threadIdx.x >> G::SHIFT, q = threadIdx.x & (KQ - 1);
-    const float* wc = w + (size_t)(c0 + 4 * q) * 27 + (flip ? 26 - tap : tap);
+    const float* wc = w + (size_t)(bk.c0 + 4 * q) * 27 + (flip ? 26 - tap : tap);
     wl[threadIdx.x] = make_float4(wc[0], wc[27], wc[54], wc[81]);
   }
   __syncthreads();
   const int q = threadIdx.x & (KQ - 1), col = threadIdx.x >> G::SHIFT;
   const int tx = col % G::TX, ty = col / G::TX;
+  const int gy = bk.y0 + ty, gx = bk.x0 + tx;
+  const bool colin = gy < n && gx < n;
   float4 k[27];
 #pragma unroll
   for (int i = 0; i < 27; ++i) k[i] = wl[i * KQ + q];
-  const float4 b0 = (b && !flip) ? *reinterpret_cast<const float4*>(b + c0 + 4 * q)
+  const float4 b0 = (b && !flip) ? *reinterpret_cast<const float4*>(b + bk.c0 + 4 * q)
                                  : make_float4(0.f, 0.f, 0.f, 0.f);
-  float4 acc[G::TZ];
+  float* yc = y + ((size_t)min(gy, n - 1) * n + min(gx, n - 1)) * C + bk.c0 + 4 * q;
+  const size_t pstride = (size_t)n * n * C;
+  float4 a_prev = b0, a_cur = b0, a_next = b0;  // outputs p-1, p, p+1
+  const int np = bk.ze - bk.zb + 2;             // input planes zb-1 .. ze
+  for (int s = 0; s < np; s += D) {
 #pragma unroll
-  for (int o = 0; o < G::TZ; ++o) acc[o] = b0;
-  // halo plane pz feeds output plane o = pz - dz through tap (dz, dy, dx)
+    for (int j = 0; j < D; ++j)
+      if (s + j < np) st.store(hal[j], bk.zb - 1 + s + j, r[j]);
+    __syncthreads();
+    if (s + D < np)  // uniform: the next group's loads fly during this group
 #pragma unroll
-  for (int pz = 0; pz < G::TZ + 2; ++pz)
+      for (int j = 0; j < D; ++j) st.load(x, min(bk.zb - 1 + s + D + j, bk.ze), r[j]);
 #pragma unroll
-    for (int dy = 0; dy < 3; ++dy)
+    for (int j = 0; j < D; ++j) {
+      if (s + j < np) {  // uniform
+        const int p = bk.zb - 1 + s + j;
 #pragma unroll
-      for (int dx = 0; dx < 3; ++dx) {
-        const float4 v = hal[((pz * G::HY + ty + dy) * G::HX + tx + dx) * KQ + q];
+        for (int dy = 0; dy < 3; ++dy)
 #pragma unroll
-        for (int dz = 0; dz < 3; ++dz) {
-          const int o = pz - dz;
-          if (o >= 0 && o < G::TZ) fma4(acc[o], k[(dz * 3 + dy) * 3 + dx], v);
-        }
-        // one plane's nine LDS values in registers at a time
-        if (dy == 2 && dx == 2)
-#pragma unroll
-          for (int o = 0; o < G::TZ; ++o) dw_pin(acc[o]);
+          for (int dx = 0; dx < 3; ++dx) {
+            const float4 v = hal[j][((ty + dy) * G::HX + tx + dx) * KQ + q];
+            fma4(a_next, k[dy * 3 + dx], v);
+            fma4(a_cur, k[9 + dy * 3 + dx], v);
+            fma4(a_prev, k[18 + dy * 3 + dx], v);
+          }
+        dw_pin(a_prev);
+        dw_pin(a_cur);
+        dw_pin(a_next);
+        if (p - 1 >= bk.zb && colin)
+          *reinterpret_cast<float4*>(yc + (size_t)(p - 1) * pstride) = a_prev;
+        a_prev = a_cur;
+        a_cur = a_next;
+        a_next = b0;
       }
-  const int gy = t.y0 + ty, gx = t.x0 + tx;
-  if (gy >= n || gx >= n) return;
-#pragma unroll
-  for (int o = 0; o < G::TZ; ++o)
-    if (t.z0 + o < n)
-      *reinterpret_cast<float4*>(y + ((size_t)((t.z0 + o) * n + gy) * n + gx) * C + c0 + 4 * q) =
-          acc[o];
+    }
+    __syncthreads();  // the group's planes are consumed before the next are written
+  }
 }
 
-// Weight-gradient partials: the block of (y, x) tile `txy`, z group `zg`
-// (zs consecutive z tiles) and channel chunk sums, over its voxels v,
-// gy[v][c] x[v + offset(tap)][c] (27 taps) and gy[v][c] (bias) and writes
-// them to part[(c * 28 + k) * nP + txy + ntxy * zg], nP = ntxy * nzg: one
-// partial per (y, x) tile and z group, column-major so that the reduction
-// reads them contiguously.  Threads sum in a fixed order, lanes of equal quad
-// by a fixed butterfly, waves in index order.
-template <int KQ>
+// Weight-gradient partials.  The block streams its z segment like the
+// forward kernel; when input plane p is in LDS the thread adds
+// g[p+1] * x (taps dz = 0), g[p] * x (dz = 1) and g[p-1] * x (dz = 2) over the
+// 3 x 3 neighbourhood, g being zero outside the segment and the grid, so each
+// output voxel is counted by exactly one block.  The block's sums go to
+// part[(c * 28 + k) * nP + txy + ntxy * sg], nP = ntxy * nseg (column-major,
+// so the reduction reads them contiguously).  Threads sum in plane order,
+// then threads of equal quad in a fixed order through LDS.
+template <int KQ, int D>
 __global__ __launch_bounds__(256, 2) void k_dw_wgrad(const float* __restrict__ x,
-                                                  const float* __restrict__ gyv,
-                                                  float* __restrict__ part, int n, int C,
-                                                  int ntxy, int nzg, int zs) {
+                                                     const float* __restrict__ gyv,
+                                                     float* __restrict__ part, int n, int C,
+                                                     int ntxy, int nseg, int seglen) {
   using G = DwGeo<KQ>;
-  __shared__ float4 hal[G::HALO * KQ];
-  static_assert(G::HALO * KQ >= 4 * kDwParts * KQ, "reduction buffer fits in the halo");
-  const int nchunks = C / (4 * KQ);
-  const int nb = ntxy * nzg * nchunks;
+  __shared__ float4 hal[D][G::PLANE];
+  const int nb = ntxy * nseg * (C / (4 * KQ));
   const int L = dw_logical(nb);
   if (L >= nb) return;  // whole block
-  const int txy = L % ntxy, zg = (L / ntxy) % nzg, c0 = (L / (ntxy * nzg)) * 4 * KQ;
-  const int ntz = (n + G::TZ - 1) / G::TZ;
+  const DwBlock<KQ> bk(L, n, ntxy, nseg, seglen);
+  const DwStager<KQ> st(n, C, bk.c0, bk.y0, bk.x0);
   const int q = threadIdx.x & (KQ - 1), col = threadIdx.x >> G::SHIFT;
   const int tx = col % G::TX, ty = col / G::TX;
-  const DwTile<KQ> t0(txy, n);  // z0 = 0: the (y, x) origin
-  const int gy = t0.y0 + ty, gx = t0.x0 + tx;
+  const int gy = bk.y0 + ty, gx = bk.x0 + tx;
   const bool colin = gy < n && gx < n;
-  const int cy = min(gy, n - 1), cx = min(gx, n - 1);
+  const float* gc = gyv + ((size_t)min(gy, n - 1) * n + min(gx, n - 1)) * C + bk.c0 + 4 * q;
+  const size_t pstride = (size_t)n * n * C;
+  // g of output plane o, clamped into the segment (always a valid address)
+  auto gload = [&](int o) {
+    return *reinterpret_cast<const float4*>(gc + (size_t)min(max(o, bk.zb), bk.ze - 1) * pstride);
+  };
+  auto gmask = [&](int o, float4 v) {
+    return (colin && o >= bk.zb && o < bk.ze) ? v : make_float4(0.f, 0.f, 0.f, 0.f);
+  };
+  float4 r[D][G::NL], gq[D];
+#pragma unroll
+  for (int j = 0; j < D; ++j) {
+    st.load(x, min(bk.zb - 1 + j, bk.ze), r[j]);
+    gq[j] = gload(bk.zb + 1 + j);
+  }
+  float4 g0 = make_float4(0.f, 0.f, 0.f, 0.f), g1 = g0;  // g of planes p-1, p
+  float4 g2 = gmask(bk.zb, gload(bk.zb));               // g of plane p+1
   float4 acc[kDwParts];
 #pragma unroll
   for (int i = 0; i < kDwParts; ++i) acc[i] = make_float4(0.f, 0.f, 0.f, 0.f);
-  const int zt_end = min(ntz, (zg + 1) * zs);
-  for (int zt = zg * zs; zt < zt_end; ++zt) {
-    const int z0 = zt * G::TZ;
-    float4 g[G::TZ];
+  const int np = bk.ze - bk.zb + 2;
+  for (int s = 0; s < np; s += D) {
+    float4 gn[D];  // g of planes p + 2 for this group's planes p
 #pragma unroll
-    for (int o = 0; o < G::TZ; ++o) {
-      const int z = min(z0 + o, n - 1);
-      g[o] = *reinterpret_cast<const float4*>(gyv + ((size_t)(z * n + cy) * n + cx) * C + c0 +
-                                              4 * q);
+    for (int j = 0; j < D; ++j) {
+      if (s + j < np) st.store(hal[j], bk.zb - 1 + s + j, r[j]);
+      gn[j] = gmask(bk.zb + 1 + s + j, gq[j]);
     }
-    if (zt > zg * zs) __syncthreads();  // the previous tile's halo is consumed
-    dw_stage<KQ, 4>(hal, x, n, C, c0, z0, t0.y0, t0.x0);
-#pragma unroll
-    for (int o = 0; o < G::TZ; ++o)
-      if (!colin || z0 + o >= n) g[o] = make_float4(0.f, 0.f, 0.f, 0.f);
     __syncthreads();
+    if (s + D < np)  // uniform: the next group's loads fly during this group
 #pragma unroll
-    for (int pz = 0; pz < G::TZ + 2; ++pz)
+      for (int j = 0; j < D; ++j) {
+        st.load(x, min(bk.zb - 1 + s + D + j, bk.ze), r[j]);
+        gq[j] = gload(bk.zb + 1 + s + D + j);
+      }
 #pragma unroll
-      for (int dy = 0; dy < 3; ++dy)
+    for (int j = 0; j < D; ++j) {
+      if (s + j < np) {  // uniform
 #pragma unroll
-        for (int dx = 0; dx < 3; ++dx) {
-          const float4 v = hal[((pz * G::HY + ty + dy) * G::HX + tx + dx) * KQ + q];
+        for (int dy = 0; dy < 3; ++dy)
 #pragma unroll
-          for (int dz = 0; dz < 3; ++dz) {
-            const int o = pz - dz;
-            if (o >= 0 && o < G::TZ) fma4(acc[(dz * 3 + dy) * 3 + dx], g[o], v);
+          for (int dx = 0; dx < 3; ++dx) {
+            const float4 v = hal[j][((ty + dy) * G::HX + tx + dx) * KQ + q];
+            fma4(acc[dy * 3 + dx], g2, v);
+            fma4(acc[9 + dy * 3 + dx], g1, v);
+            fma4(acc[18 + dy * 3 + dx], g0, v);
           }
-          if (dy == 2 && dx == 2) __builtin_amdgcn_sched_barrier(0);
-        }
-#pragma unroll
-    for (int o = 0; o < G::TZ; ++o) fma4(acc[27], make_float4(1.f, 1.f, 1.f, 1.f), g[o]);
+        fma4(acc[27], make_float4(1.f, 1.f, 1.f, 1.f), g1);
+        g0 = g1;
+        g1 = g2;
+        g2 = gn[j];
+      }
+    }
+    __syncthreads();  // the group's planes are consumed before the next are written
   }
-  // lanes of one quad: butterfly over lane offsets 32 .. KQ
+  // Sum over the threads of equal quad through LDS, kDwRedChunk
+  // accumulators at a time: each thread's values go to red[c][tid]; thread
+  // (o, part) of NO = chunk * KQ outputs sums M of them in order, then the
+  // P = 256 / NO part sums of each output are added in order.
+  constexpr int CH = kDwRedChunk, NO = CH * KQ, P = 256 / NO, M = 256 / KQ / P;
+  static_assert(D * G::PLANE >= CH * 256, "reduction buffer fits in the planes");
+  float4* red = &hal[0][0];
+  const int o = threadIdx.x % NO, part_i = threadIdx.x / NO;
+  const int oc = o / KQ, oq = o % KQ;
+  const size_t nP = (size_t)ntxy * nseg, P0 = bk.txy + (size_t)ntxy * bk.sg;
 #pragma unroll
-  for (int i = 0; i < kDwParts; ++i)
+  for (int i0 = 0; i0 < kDwParts; i0 += CH) {
+    __syncthreads();  // the previous chunk (or the planes) fully read
 #pragma unroll
-    for (int off = 32; off >= KQ; off >>= 1) {
-      acc[i].x += __shfl_xor(acc[i].x, off, 64);
-      acc[i].y += __shfl_xor(acc[i].y, off, 64);
-      acc[i].z += __shfl_xor(acc[i].z, off, 64);
-      acc[i].w += __shfl_xor(acc[i].w, off, 64);
+    for (int c = 0; c < CH; ++c) red[c * 256 + threadIdx.x] = acc[i0 + c];
+    __syncthreads();
+    float4 sum = make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+      const float4 v = red[oc * 256 + oq + KQ * (part_i * M + m)];
+      sum.x += v.x;
+      sum.y += v.y;
+      sum.z += v.z;
+      sum.w += v.w;
     }
-  __syncthreads();  // halo no longer read: reuse it for the wave sums
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  if (lane < KQ)
+    __syncthreads();
+    red[part_i * NO + o] = sum;
+    __syncthreads();
+    if (threadIdx.x < NO) {
+      float4 t = red[threadIdx.x];
 #pragma unroll
-    for (int i = 0; i < kDwParts; ++i) hal[(wave * kDwParts + i) * KQ + lane] = acc[i];
-  __syncthreads();
-  if (threadIdx.x < kDwParts * KQ) {
-    const int i = threadIdx.x / KQ, qq = threadIdx.x & (KQ - 1);
-    float4 s = hal[i * KQ + qq];
-#pragma unroll
-    for (int w2 = 1; w2 < 4; ++w2) {
-      const float4 v = hal[(w2 * kDwParts + i) * KQ + qq];
-      s.x += v.x;
-      s.y += v.y;
-      s.z += v.z;
-      s.w += v.w;
+      for (int pp = 1; pp < P; ++pp) {
+        const float4 v = red[pp * NO + threadIdx.x];
+        t.x += v.x;
+        t.y += v.y;
+        t.z += v.z;
+        t.w += v.w;
+      }
+      const int i = i0 + oc, c = bk.c0 + 4 * oq;
+      part[((size_t)(c + 0) * kDwParts + i) * nP + P0] = t.x;
+      part[((size_t)(c + 1) * kDwParts + i) * nP + P0] = t.y;
+      part[((size_t)(c + 2) * kDwParts + i) * nP + P0] = t.z;
+      part[((size_t)(c + 3) * kDwParts + i) * nP + P0] = t.w;
     }
-    const size_t nP = (size_t)ntxy * nzg, P = txy + (size_t)ntxy * zg;
-    const int c = c0 + 4 * qq;
-    part[((size_t)(c + 0) * kDwParts + i) * nP + P] = s.x;
-    part[((size_t)(c + 1) * kDwParts + i) * nP + P] = s.y;
-    part[((size_t)(c + 2) * kDwParts + i) * nP + P] = s.z;
-    part[((size_t)(c + 3) * kDwParts + i) * nP + P] = s.w;
   }
 }
 
@@ -291,80 +348,72 @@ int dw_kq(int C) {
   return c4 % 8 == 0 ? 8 : c4 % 4 == 0 ? 4 : c4 % 2 == 0 ? 2 : 1;
 }
 
-template <int KQ>
-int dw_tiles_kq(int n) {
-  using G = DwGeo<KQ>;
-  return ((n + G::TX - 1) / G::TX) * ((n + G::TY - 1) / G::TY) * ((n + G::TZ - 1) / G::TZ);
+// (y, x) tiles and z segments: segments of 32 planes, halved (down to 4)
+// while the grid has fewer than `target` blocks.
+struct DwPlan {
+  int kq, ntxy, nseg, seglen, nb;
+};
+
+constexpr int kDwFwdBlocks = 512;  // grid targets (two blocks fit a CU): forward / input gradient
+constexpr int kDwWgBlocks = 512;   // weight gradient
+
+DwPlan dw_plan(int n, int C, int target) {
+  DwPlan p;
+  p.kq = dw_kq(C);
+  const int ty = p.kq >= 4 ? 8 : 16, tx = 256 / p.kq / ty;
+  p.ntxy = ((n + tx - 1) / tx) * ((n + ty - 1) / ty);
+  const int nch = C / (4 * p.kq);
+  p.seglen = 32;
+  while (p.seglen > 4 && (long long)p.ntxy * ((n + p.seglen - 1) / p.seglen) * nch < target)
+    p.seglen /= 2;
+  p.nseg = (n + p.seglen - 1) / p.seglen;
+  p.nb = p.ntxy * p.nseg * nch;
+  return p;
 }
 
 template <int KQ>
-void dw_shape(int n, int C, int* ntxy, int* nzg, int* zs) {
-  using G = DwGeo<KQ>;
-  *ntxy = ((n + G::TX - 1) / G::TX) * ((n + G::TY - 1) / G::TY);
-  const int ntz = (n + G::TZ - 1) / G::TZ, nch = C / (4 * KQ);
-  // fewest partials that still give about 1024 blocks
-  int s = 1;
-  while (2 * s <= ntz && (long long)*ntxy * ((ntz + 2 * s - 1) / (2 * s)) * nch >= 1024) s *= 2;
-  *zs = s;
-  *nzg = (ntz + s - 1) / s;
-}
-
-void dw_shape_any(int n, int C, int* ntxy, int* nzg, int* zs) {
-  switch (dw_kq(C)) {
-    case 8: dw_shape<8>(n, C, ntxy, nzg, zs); break;
-    case 4: dw_shape<4>(n, C, ntxy, nzg, zs); break;
-    case 2: dw_shape<2>(n, C, ntxy, nzg, zs); break;
-    default: dw_shape<1>(n, C, ntxy, nzg, zs); break;
-  }
+void launch_fwd(const DwPlan& p, const float* x, const float* w, const float* b, float* y, int n,
+                int C, bool flip, hipStream_t s) {
+  hipLaunchKernelGGL((k_dw_fwd<KQ, kDwFwdGroup>), dim3((p.nb + 7) / 8 * 8), dim3(256), 0, s, x, w, b, y, n, C,
+                     p.ntxy, p.nseg, p.seglen, flip ? 1 : 0);
 }
 
 template <int KQ>
-void launch_fwd(const float* x, const float* w, const float* b, float* y, int n, int C, bool flip,
-                hipStream_t s) {
-  const int nt = dw_tiles_kq<KQ>(n), nb = nt * (C / (4 * KQ));
-  hipLaunchKernelGGL(k_dw_fwd<KQ>, dim3((nb + 7) / 8 * 8), dim3(256), 0, s, x, w, b, y, n, C, nt,
-                     flip ? 1 : 0);
-}
-
-template <int KQ>
-void launch_wgrad(const float* x, const float* gy, float* part, int n, int C, hipStream_t s) {
-  int ntxy, nzg, zs;
-  dw_shape<KQ>(n, C, &ntxy, &nzg, &zs);
-  const int nb = ntxy * nzg * (C / (4 * KQ));
-  hipLaunchKernelGGL(k_dw_wgrad<KQ>, dim3((nb + 7) / 8 * 8), dim3(256), 0, s, x, gy, part, n, C,
-                     ntxy, nzg, zs);
+void launch_wgrad(const DwPlan& p, const float* x, const float* gy, float* part, int n, int C,
+                  hipStream_t s) {
+  hipLaunchKernelGGL((k_dw_wgrad<KQ, kDwWgGroup>), dim3((p.nb + 7) / 8 * 8), dim3(256), 0, s, x, gy, part, n,
+                     C, p.ntxy, p.nseg, p.seglen);
 }
 
 }  // namespace
 
 size_t dw_partials(int n, int C) {
-  int ntxy, nzg, zs;
-  dw_shape_any(n, C, &ntxy, &nzg, &zs);
-  return (size_t)ntxy * nzg * C * kDwParts;
+  const DwPlan p = dw_plan(n, C, kDwWgBlocks);
+  return (size_t)p.ntxy * p.nseg * C * kDwParts;
 }
 
 void dw_forward(const float* x, const float* w, const float* b, float* y, int n, int C, bool flip,
                 hipStream_t s) {
-  switch (dw_kq(C)) {
-    case 8: launch_fwd<8>(x, w, b, y, n, C, flip, s); break;
-    case 4: launch_fwd<4>(x, w, b, y, n, C, flip, s); break;
-    case 2: launch_fwd<2>(x, w, b, y, n, C, flip, s); break;
-    default: launch_fwd<1>(x, w, b, y, n, C, flip, s); break;
+  const DwPlan p = dw_plan(n, C, kDwFwdBlocks);
+  switch (p.kq) {
+    case 8: launch_fwd<8>(p, x, w, b, y, n, C, flip, s); break;
+    case 4: launch_fwd<4>(p, x, w, b, y, n, C, flip, s); break;
+    case 2: launch_fwd<2>(p, x, w, b, y, n, C, flip, s); break;
+    default: launch_fwd<1>(p, x, w, b, y, n, C, flip, s); break;
   }
 }
 
 void dw_wgrad(const float* x, const float* gy, float* part, float* gw, float* gb, int n, int C,
               hipStream_t s) {
-  switch (dw_kq(C)) {
-    case 8: launch_wgrad<8>(x, gy, part, n, C, s); break;
-    case 4: launch_wgrad<4>(x, gy, part, n, C, s); break;
-    case 2: launch_wgrad<2>(x, gy, part, n, C, s); break;
-    default: launch_wgrad<1>(x, gy, part, n, C, s); break;
+  const DwPlan p = dw_plan(n, C, kDwWgBlocks);
+  switch (p.kq) {
+    case 8: launch_wgrad<8>(p, x, gy, part, n, C, s); break;
+    case 4: launch_wgrad<4>(p, x, gy, part, n, C, s); break;
+    case 2: launch_wgrad<2>(p, x, gy, part, n, C, s); break;
+    default: launch_wgrad<1>(p, x, gy, part, n, C, s); break;
   }
-  int ntxy, nzg, zs;
-  dw_shape_any(n, C, &ntxy, &nzg, &zs);
   hipLaunchKernelGGL(k_dw_wreduce, dim3((C * kDwParts + 3) / 4), dim3(256), 0, s, part,
-                     ntxy * nzg, C, gw, gb);
+                     p.ntxy * p.nseg, C, gw, gb);
 }
 
 }  // namespace d2ip
