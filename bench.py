@@ -220,9 +220,9 @@ def dwsep_ops(d2ip, torch, shapes=((64, 64, 64), (32, 16, 16))):
     forward, input gradient, weight gradient; pointwise 1x1x1 forward) through
     the op-level C-ABI on synthetic channels-last FP32 tensors, each launch
     timed with HIP events on the stream it is enqueued on.  Algorithmic bytes
-    of a depthwise pass: its two n^3 x C tensors (read + write, or the two
-    reads of the weight gradient), 8 bytes per value; the pointwise pass is
-    priced both ways (HBM bytes and FP32 flops)."""
+    of a pass: its two voxel tensors (read + write, or the two reads of a
+    weight gradient), 4 bytes per value; the pointwise passes, GEMMs of
+    2 n^3 C Cout flops, are priced both ways (HBM bytes and FP32 flops)."""
     import ctypes
     L = d2ip._lib
     lib = L.load()
@@ -245,8 +245,10 @@ def dwsep_ops(d2ip, torch, shapes=((64, 64, 64), (32, 16, 16))):
         nb = ctypes.c_size_t()
         L.check(lib.d2ip_op_dwconv3d_bytes(n, C, ctypes.byref(nb)))
         ws = torch.empty(nb.value, dtype=torch.uint8, device="cuda")
+        gyp = torch.randn(V, Co, device="cuda", generator=g)
+        gwp, gbp = torch.empty(Co, C, device="cuda"), torch.empty(Co, device="cuda")
         pb = ctypes.c_size_t()
-        L.check(lib.d2ip_op_conv3d_bytes(n, C, Co, 1, L.PLAIN_FP32, ctypes.byref(pb)))
+        L.check(lib.d2ip_op_pwconv3d_bytes(n, C, Co, ctypes.byref(pb)))
         pws = torch.empty(pb.value, dtype=torch.uint8, device="cuda")
         calls = {
             "dw_forward": lambda: lib.d2ip_op_dwconv3d_forward(P(x), P(w), P(b), P(y), n, C, sp),
@@ -254,8 +256,12 @@ def dwsep_ops(d2ip, torch, shapes=((64, 64, 64), (32, 16, 16))):
                 None, P(w), P(gy), P(gx), None, None, n, C, None, 0, sp),
             "dw_weight_grad": lambda: lib.d2ip_op_dwconv3d_backward(
                 P(x), None, P(gy), None, P(gw), P(gb), n, C, P(ws), nb.value, sp),
-            "pw_forward": lambda: lib.d2ip_op_conv3d_forward(
-                P(y), P(wp), P(bp), P(yp), n, C, Co, 1, L.PLAIN_FP32, P(pws), pb.value, sp),
+            "pw_forward": lambda: lib.d2ip_op_pwconv3d_forward(P(y), P(wp), P(bp), P(yp), n, C,
+                                                               Co, sp),
+            "pw_input_grad": lambda: lib.d2ip_op_pwconv3d_backward(
+                None, P(wp), P(gyp), P(gx), None, None, n, C, Co, None, 0, sp),
+            "pw_weight_grad": lambda: lib.d2ip_op_pwconv3d_backward(
+                P(y), None, P(gyp), None, P(gwp), P(gbp), n, C, Co, P(pws), pb.value, sp),
         }
         rows = {}
         for name, f in calls.items():
@@ -268,17 +274,18 @@ def dwsep_ops(d2ip, torch, shapes=((64, 64, 64), (32, 16, 16))):
             e1.record(st)
             torch.cuda.synchronize()
             ms = e0.elapsed_time(e1) / 50
-            byts = 4.0 * V * (C + (Co if name == "pw_forward" else C))
+            byts = 4.0 * V * (C + (Co if name.startswith("pw") else C))
             r = dict(ms=ms, bound="hbm", achieved=byts / (ms * 1e-3) / 1e9, peak=HBM_PEAK_GBS,
                      unit="GB/s")
             r["frac"] = r["achieved"] / r["peak"]
-            if name == "pw_forward":
+            if name.startswith("pw"):
                 fl = 2.0 * V * C * Co
                 r["tflops"] = fl / (ms * 1e-3) / 1e12
                 r["tflops_frac_fp32"] = r["tflops"] / PEAK_TFLOPS["fp32"]
             rows[name] = r
-            log("  %d^3 C=%d %-15s %8.4f ms  %7.0f GB/s (%.1f%% of HBM peak)"
-                % (n, C, name, ms, r["achieved"], 100 * r["frac"]))
+            log("  %d^3 C=%d %-15s %8.4f ms  %7.0f GB/s (%.1f%% of HBM peak)%s"
+                % (n, C, name, ms, r["achieved"], 100 * r["frac"],
+                   "  %.1f TFLOP/s" % r["tflops"] if "tflops" in r else ""))
         out["%d^3 x %d -> %d" % (n, C, Co)] = rows
     return out
 

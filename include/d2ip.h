@@ -337,9 +337,9 @@ d2ip_status d2ip_op_dwconv3d_bytes(int n, int C, size_t* out);
  * convolution of the lightweight backbone (Sec. III-D):
  * y[v][c] = b[c] + sum_tap w[c][tap] x[v + offset(tap)][c] (cross-correlation,
  * zero padding; w [C][kz][ky][kx], i.e. the canonical [C][1][3][3][3]; b may be
- * NULL).  x, y (and b) 16-byte aligned.  The second half, the pointwise
- * 1x1x1 convolution, is d2ip_op_conv3d_forward with taps = 1.  Needs no
- * workspace and uploads nothing. */
+ * NULL).  x, y (and b) 16-byte aligned.  The second half is the pointwise
+ * convolution d2ip_op_pwconv3d_forward.  Needs no workspace and uploads
+ * nothing. */
 d2ip_status d2ip_op_dwconv3d_forward(const float* x, const float* w, const float* b, float* y,
                                      int n, int C, void* hip_stream);
 
@@ -351,6 +351,26 @@ d2ip_status d2ip_op_dwconv3d_forward(const float* x, const float* w, const float
 d2ip_status d2ip_op_dwconv3d_backward(const float* x, const float* w, const float* gy, float* gx,
                                       float* gw, float* gb, int n, int C, void* workspace,
                                       size_t bytes, void* hip_stream);
+
+/* Workspace bytes of d2ip_op_pwconv3d_backward's weight gradient (cin and
+ * cout multiples of 4 in [4, 1024]). */
+d2ip_status d2ip_op_pwconv3d_bytes(int n, int cin, int cout, size_t* out);
+
+/* Pointwise 1x1x1 convolution, the second half of a depthwise-separable
+ * convolution (Sec. III-D), as an FP32 matrix-core GEMM:
+ * y[v][co] = b[co] + sum_ci w[co][ci] x[v][ci] (w [cout][cin], the canonical
+ * [cout][cin][1][1][1]; b may be NULL).  x, w and y 16-byte aligned.  Needs no
+ * workspace and uploads nothing. */
+d2ip_status d2ip_op_pwconv3d_forward(const float* x, const float* w, const float* b, float* y,
+                                     int n, int cin, int cout, void* hip_stream);
+
+/* Gradients of d2ip_op_pwconv3d_forward given gy: gx = gy w, gw = gy^T x
+ * ([cout][cin]) and gb = column sums of gy; any output may be NULL; x is
+ * needed only for gw / gb, w only for gx, the workspace only for gw / gb.
+ * Voxel sums are reduced in a fixed order (deterministic). */
+d2ip_status d2ip_op_pwconv3d_backward(const float* x, const float* w, const float* gy, float* gx,
+                                      float* gw, float* gb, int n, int cin, int cout,
+                                      void* workspace, size_t bytes, void* hip_stream);
 
 /* p = J sigma for a dense row-major M x Q J (Eq. (1)); Q a multiple of 4. */
 d2ip_status d2ip_op_j_forward(const float* J, const float* sigma, float* p, int M, int Q,

@@ -251,6 +251,16 @@ void dw_forward(const float* x, const float* w, const float* b, float* y, int n,
                 hipStream_t s);
 void dw_wgrad(const float* x, const float* gy, float* part, float* gw, float* gb, int n, int C,
               hipStream_t s);
+// Pointwise (1x1x1) convolution as FP32 matrix-core GEMMs on channels-last
+// tensors: Y[M][N] = X[M][K] B + bias with B[k][n] = W[n][k] (W [N][K]) or,
+// with transw, W[k][n] (W [K][N]); pw_wgrad writes pw_partials(M, K, N) floats
+// of `part` and reduces them into gw [N][K] = G^T X and gb [N] = column sums
+// of G (either may be null).  K and N multiples of 4.
+size_t pw_partials(size_t M, int K, int N);
+void pw_gemm(const float* X, const float* W, const float* bias, float* Y, size_t M, int K, int N,
+             bool transw, hipStream_t s);
+void pw_wgrad(const float* X, const float* G, float* part, float* gw, float* gb, size_t M, int K,
+              int N, hipStream_t s);
 // The launch shape the plan's heuristic picks for a forward / input-gradient
 // pass with `cin` inputs and `cout` outputs (precision: PREC_*).
 void default_conv_shape(int n, int cin, int cout, int taps, int prec, int* tile, int* bn, int* ck,

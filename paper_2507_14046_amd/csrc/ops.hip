@@ -191,6 +191,13 @@ d2ip_status dw_check(int n, int C) {
 
 bool aligned16(const void* p) { return ((uintptr_t)p & 15) == 0; }
 
+d2ip_status pw_check(int n, int cin, int cout) {
+  if (n < 1 || n > 256) return api_fail(D2IP_EINVAL, "n must be in [1, 256]");
+  if (cin < 4 || cout < 4 || cin % 4 || cout % 4 || cin > 1024 || cout > 1024)
+    return api_fail(D2IP_EINVAL, "cin and cout must be multiples of 4 in [4, 1024]");
+  return D2IP_OK;
+}
+
 struct LnOp {
   double *st = nullptr, *part_c = nullptr, *part_ab = nullptr;
   float* gz = nullptr;
@@ -404,6 +411,49 @@ d2ip_status d2ip_op_dwconv3d_backward(const float* x, const float* w, const floa
     dw_wgrad(x, gy, reinterpret_cast<float*>(workspace), gw, gb, n, C, s);
   }
   if (gx) dw_forward(gy, w, nullptr, gx, n, C, true, s);
+  OPCHK(hipGetLastError());
+  return D2IP_OK;
+}
+
+d2ip_status d2ip_op_pwconv3d_bytes(int n, int cin, int cout, size_t* out) {
+  if (!out) return api_fail(D2IP_EINVAL, "null output");
+  d2ip_status st = pw_check(n, cin, cout);
+  if (st != D2IP_OK) return st;
+  *out = pw_partials((size_t)n * n * n, cin, cout) * sizeof(float) + 256;
+  return D2IP_OK;
+}
+
+d2ip_status d2ip_op_pwconv3d_forward(const float* x, const float* w, const float* b, float* y,
+                                     int n, int cin, int cout, void* hip_stream) {
+  d2ip_status st = pw_check(n, cin, cout);
+  if (st != D2IP_OK) return st;
+  if (!x || !w || !y) return api_fail(D2IP_EINVAL, "null x, w or y");
+  if (!aligned16(x) || !aligned16(w) || !aligned16(y))
+    return api_fail(D2IP_EINVAL, "x, w and y must be 16-byte aligned");
+  pw_gemm(x, w, b, y, (size_t)n * n * n, cin, cout, false,
+          reinterpret_cast<hipStream_t>(hip_stream));
+  OPCHK(hipGetLastError());
+  return D2IP_OK;
+}
+
+d2ip_status d2ip_op_pwconv3d_backward(const float* x, const float* w, const float* gy, float* gx,
+                                      float* gw, float* gb, int n, int cin, int cout,
+                                      void* workspace, size_t bytes, void* hip_stream) {
+  d2ip_status st = pw_check(n, cin, cout);
+  if (st != D2IP_OK) return st;
+  if (!gy || (gx && !w) || ((gw || gb) && !x))
+    return api_fail(D2IP_EINVAL, "null gy, or null w with gx, or null x with gw / gb");
+  if (!aligned16(gy) || (gx && (!aligned16(gx) || !aligned16(w))) || (x && !aligned16(x)))
+    return api_fail(D2IP_EINVAL, "x, w, gy and gx must be 16-byte aligned");
+  hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
+  const size_t V = (size_t)n * n * n;
+  if (gw || gb) {
+    size_t need = 0;
+    d2ip_op_pwconv3d_bytes(n, cin, cout, &need);
+    if ((st = ws_check(workspace, bytes, need)) != D2IP_OK) return st;
+    pw_wgrad(x, gy, reinterpret_cast<float*>(workspace), gw, gb, V, cin, cout, s);
+  }
+  if (gx) pw_gemm(gy, w, nullptr, gx, V, cout, cin, true, s);
   OPCHK(hipGetLastError());
   return D2IP_OK;
 }

@@ -1,11 +1,11 @@
 """PyTorch autograd operators over the library's standalone kernels.
 
-``Conv3dFn``, ``DWConv3dFn``, ``LayerNormReLUFn`` and ``MeasureFn`` wrap the
-op-level C-ABI (include/d2ip.h): their forward and backward passes are the
-library's HIP kernels (implicit-GEMM convolutions with the input and weight
-gradients, the depthwise 3x3x3 convolution of the depthwise-separable
-convolution and its gradients, the whole-volume LayerNorm + ReLU and its
-backward, J sigma and J^T g).  ``DIPNet``
+``Conv3dFn``, ``DWConv3dFn``, ``PWConv3dFn``, ``LayerNormReLUFn`` and
+``MeasureFn`` wrap the op-level C-ABI (include/d2ip.h): their forward and
+backward passes are the library's HIP kernels (implicit-GEMM convolutions
+with the input and weight gradients, the depthwise 3x3x3 and pointwise 1x1x1
+convolutions of the depthwise-separable convolution and their gradients, the
+whole-volume LayerNorm + ReLU and its backward, J sigma and J^T g).  ``DIPNet``
 composes the prior of Eq. (3) from them; pooling, up-sampling, channel
 concatenation and the 1x1x1 output head are plain tensor operations of the
 model around the operators.  With ``recompute=True`` every ResBlock's
@@ -76,12 +76,19 @@ class DWConv3dFn:
         return _dw_fn().apply(x, w, b)
 
 
-def dwsep_conv3d(x, wd, bd, wp, bp, precision="fp32"):
+class PWConv3dFn:
+    """y = pointwise conv3d(x, w, b) as an FP32 matrix-core GEMM: x [n^3, C],
+    w [Cout, C] or [Cout, C, 1, 1, 1], b [Cout] or None (C, Cout % 4 == 0)."""
+
+    @staticmethod
+    def apply(x, w, b=None):
+        return _pw_fn().apply(x, w, b)
+
+
+def dwsep_conv3d(x, wd, bd, wp, bp):
     """Depthwise-separable convolution: the depthwise 3x3x3 convolution, then
-    the pointwise 1x1x1 one (wp [Cout, C] or [Cout, C, 1, 1, 1]), both on the
-    library's kernels."""
-    d = DWConv3dFn.apply(x, wd, bd)
-    return Conv3dFn.apply(d, wp.reshape(wp.shape[0], wp.shape[1], 1, 1, 1), bp, precision)
+    the pointwise 1x1x1 one, both on the library's kernels."""
+    return PWConv3dFn.apply(DWConv3dFn.apply(x, wd, bd), wp, bp)
 
 
 class MeasureFn:
@@ -181,6 +188,51 @@ def _dw_fn():
 
     _FNS["dw"] = _DW
     return _DW
+
+
+def _pw_fn():
+    if "pw" in _FNS:
+        return _FNS["pw"]
+    torch = _torch()
+
+    class _PW(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, x, w, b):
+            lib = L.load()
+            x, w = x.contiguous(), w.contiguous()
+            b = b.contiguous() if b is not None else None
+            V, cin = x.shape
+            cout = w.shape[0]
+            if w.numel() != cout * cin:
+                raise ValueError("w must be [Cout, C] (or [Cout, C, 1, 1, 1])")
+            n = _grid_n(V)
+            y = torch.empty(V, cout, dtype=torch.float32, device=x.device)
+            L.check(lib.d2ip_op_pwconv3d_forward(_p(x), _p(w), _p(b), _p(y), n, cin, cout,
+                                                 _stream(x)))
+            ctx.save_for_backward(x, w)
+            ctx.meta = (n, cin, cout, b is not None)
+            return y
+
+        @staticmethod
+        def backward(ctx, gy):
+            lib = L.load()
+            x, w = ctx.saved_tensors
+            n, cin, cout, has_b = ctx.meta
+            gy = gy.contiguous()
+            need_x, need_w, need_b = ctx.needs_input_grad[:3]
+            gx = torch.empty_like(x) if need_x else None
+            gw = torch.empty_like(w) if need_w else None
+            gb = torch.empty(cout, dtype=torch.float32, device=x.device) if (need_b and has_b) \
+                else None
+            ws, nb = (None, 0)
+            if gw is not None or gb is not None:
+                ws, nb = _workspace(lib.d2ip_op_pwconv3d_bytes, n, cin, cout, device=x.device)
+            L.check(lib.d2ip_op_pwconv3d_backward(_p(x), _p(w), _p(gy), _p(gx), _p(gw), _p(gb),
+                                                  n, cin, cout, _p(ws), nb, _stream(x)))
+            return gx, gw, gb
+
+    _FNS["pw"] = _PW
+    return _PW
 
 
 def _ln_fn():

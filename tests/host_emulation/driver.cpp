@@ -184,6 +184,22 @@ static int ops_case() {
     free(ws);
   }
   EXPECT_ERR(d2ip_op_dwconv3d_bytes(n, 6, &need), D2IP_EINVAL);
+  for (int ci : {4, 16, 100})
+    for (int co : {8, 64, 132}) {
+      CK(d2ip_op_pwconv3d_bytes(n, ci, co, &need));
+      ws = (char*)aligned_alloc(256, (need + 255) / 256 * 256);
+      std::vector<float> wpw((size_t)ci * co), bpw(co), gwp(wpw.size()), gbp(co),
+          ybig((size_t)Q * co), gbig((size_t)Q * co);
+      CK(d2ip_op_pwconv3d_forward(x.data(), wpw.data(), bpw.data(), ybig.data(), n, ci, co,
+                                  &token));
+      CK(d2ip_op_pwconv3d_backward(x.data(), wpw.data(), gbig.data(), gx.data(), gwp.data(),
+                                   gbp.data(), n, ci, co, ws, need, &token));
+      EXPECT_ERR(d2ip_op_pwconv3d_backward(x.data(), wpw.data(), gbig.data(), nullptr,
+                                           gwp.data(), nullptr, n, ci, co, ws, need - 1, &token),
+                 D2IP_ENOMEM);
+      free(ws);
+    }
+  EXPECT_ERR(d2ip_op_pwconv3d_bytes(n, 6, 8, &need), D2IP_EINVAL);
   EXPECT_ERR(d2ip_op_dwconv3d_forward(x.data() + 1, gam.data(), nullptr, y.data(), n, C, &token),
              D2IP_EINVAL);
   CK(d2ip_op_j_forward(J.data(), x.data(), p.data(), M, Q, &token));

@@ -1,11 +1,14 @@
-"""GPU tests of the depthwise 3x3x3 convolution (forward, input and weight
-gradients) and of the depthwise-separable composition (depthwise, then the
-pointwise 1x1x1 convolution), against the FP64 oracle (oracle/dwsep.py).
+"""GPU tests of the depthwise 3x3x3 convolution and the pointwise 1x1x1
+convolution (forward, input and weight gradients) and of their composition,
+the depthwise-separable convolution, against the FP64 oracle
+(oracle/dwsep.py).
 
-Cases span every channel-quad blocking the kernels pick (C/4 odd, even, a
-multiple of 4 and of 8, several channel chunks), ragged tiles in x, y and z,
-the degenerate one- and two-voxel grids, and the 64^3 x 64 workload that the
-benchmark times (there sampled outputs and the full weight gradient)."""
+Depthwise cases span every channel-quad blocking the kernels pick (C/4 odd,
+even, a multiple of 4 and of 8, several channel chunks), ragged tiles in x, y
+and z and the degenerate one- and two-voxel grids; pointwise cases span
+ragged row blocks, column tiles and k stages and several voxel chunks of the
+weight gradient; both run the 64^3 x 64 workload that the benchmark times
+(there sampled outputs and the full weight gradients)."""
 import numpy as np
 import pytest
 
@@ -87,7 +90,29 @@ def test_depthwise_adjoint_and_determinism(lib):
     assert torch.equal(outs[0][0], outs[1][0]) and torch.equal(outs[0][1], outs[1][1])
 
 
-@pytest.mark.parametrize("C,Co", [(16, 24), (32, 8)])
+@pytest.mark.parametrize("n,C,Co", [(1, 4, 4), (5, 8, 12), (8, 64, 64), (17, 100, 132),
+                                    (10, 36, 8), (20, 16, 72)])
+def test_pointwise_matches_oracle(lib, n, C, Co):
+    from paper_2507_14046_amd import ops
+    rng = np.random.default_rng(500 + n + C + Co)
+    x = rng.standard_normal((C, n, n, n)).astype(np.float32)
+    w = (0.2 * rng.standard_normal((Co, C))).astype(np.float32)
+    b = rng.standard_normal(Co).astype(np.float32)
+    g = rng.standard_normal((Co, n, n, n)).astype(np.float32)
+    f = lambda a: a.astype(np.float64)
+    yref = dwsep.pwconv3d(f(x), f(w), f(b))
+    gxr, gwr, gbr = dwsep.pwconv3d_backward(f(x), f(w), f(g))
+    X, W, B = dev(cl(x), True), dev(w, True), dev(b, True)
+    Y = ops.PWConv3dFn.apply(X, W, B)
+    Y.backward(dev(cl(g)))
+    e = dict(y=rel(cf(host(Y), n), yref), gx=rel(cf(host(X.grad), n), gxr),
+             gw=rel(host(W.grad), gwr), gb=rel(host(B.grad), gbr))
+    record("pwconv3d", n=n, C=C, Co=Co, **e)
+    assert e["y"] < TOL_Y and e["gx"] < TOL_Y, e
+    assert e["gw"] < TOL_W and e["gb"] < TOL_W, e
+
+
+@pytest.mark.parametrize("C,Co", [(16, 24), (32, 8), (12, 20)])
 def test_depthwise_separable_composition_matches_oracle(lib, C, Co):
     from paper_2507_14046_amd import ops
     n = 10
@@ -110,6 +135,32 @@ def test_depthwise_separable_composition_matches_oracle(lib, C, Co):
     record("dwsep_conv3d", C=C, Co=Co, **e)
     assert e["y"] < TOL_Y and e["gx"] < TOL_Y, e
     assert max(e["gwd"], e["gbd"], e["gwp"], e["gbp"]) < TOL_W, e
+
+
+def test_pointwise_full_size_workload(lib):
+    """64^3 x 64 -> 64: sampled output rows and input-gradient rows against
+    the definition at those voxels, the full weight and bias gradients
+    against the oracle."""
+    from paper_2507_14046_amd import ops
+    n, C, Co = 64, 64, 64
+    rng = np.random.default_rng(646464)
+    x = rng.standard_normal((n ** 3, C)).astype(np.float32)
+    w = (0.2 * rng.standard_normal((Co, C))).astype(np.float32)
+    b = rng.standard_normal(Co).astype(np.float32)
+    g = rng.standard_normal((n ** 3, Co)).astype(np.float32)
+    X, W, B = dev(x, True), dev(w, True), dev(b, True)
+    Y = ops.PWConv3dFn.apply(X, W, B)
+    Y.backward(dev(g))
+    y, gx = host(Y), host(X.grad)
+    f = lambda a: a.astype(np.float64)
+    rows = np.concatenate([[0, n ** 3 - 1, 4095, 4096, 127, 128], rng.integers(0, n ** 3, 200)])
+    ey = rel(y[rows], f(x[rows]) @ f(w).T + f(b))
+    eg = rel(gx[rows], f(g[rows]) @ f(w))
+    e = dict(y_rows=ey, gx_rows=eg, gw=rel(host(W.grad), f(g).T @ f(x)),
+             gb=rel(host(B.grad), f(g).sum(axis=0)))
+    record("pwconv3d_64", **e)
+    assert ey < TOL_Y and eg < TOL_Y, e
+    assert e["gw"] < TOL_W and e["gb"] < TOL_W, e
 
 
 def _dw_at(xp, w, b, c, z, y, x):
