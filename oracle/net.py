@@ -19,6 +19,10 @@ reading used throughout this project:
                out = relu(LN2(h2) + skip(x)), skip = 1x1x1 conv if the channel
                count changes, identity otherwise.
 
+With sep=True every ResBlock conv3 is the depthwise-separable convolution of
+the lightweight backbone (Sec. III-D; oracle/dwsep.py): a per-channel 3x3x3
+convolution with a bias, then a 1x1x1 convolution with a bias.
+
 Conventions: arrays are channel-first [C, n, n, n] in (z, y, x) order; conv3
 is a 3x3x3 cross-correlation with zero padding 1; LN normalises over all of
 (C, z, y, x) with the biased variance, eps = 1e-5 inside the square root, and
@@ -26,6 +30,8 @@ a per-channel affine (gamma, beta); avgpool2 averages 2x2x2 blocks; up2
 repeats every voxel into a 2x2x2 block (nearest neighbour); relu'(0) = 0.
 """
 import numpy as np
+
+from . import dwsep
 
 LN_EPS = 1e-5
 
@@ -36,38 +42,50 @@ LN_EPS = 1e-5
 # gamma then beta; ResBlock order conv1, norm1, conv2, norm2, proj)
 # ----------------------------------------------------------------------------
 
-def _block_shapes(cin, cout):
-    shapes = [("conv1.w", (cout, cin, 3, 3, 3)), ("conv1.b", (cout,)),
-              ("norm1.g", (cout,)), ("norm1.beta", (cout,)),
-              ("conv2.w", (cout, cout, 3, 3, 3)), ("conv2.b", (cout,)),
-              ("norm2.g", (cout,)), ("norm2.beta", (cout,))]
+def _conv_shapes(name, cin, cout, sep):
+    """A ResBlock's 3x3x3 convolution: dense (w, b), or with sep the
+    depthwise-separable form (depthwise dw [cin, 3, 3, 3] and dwb [cin], then
+    pointwise pw [cout, cin] and pwb [cout]; Sec. III-D)."""
+    if sep:
+        return [(name + ".dw", (cin, 3, 3, 3)), (name + ".dwb", (cin,)),
+                (name + ".pw", (cout, cin)), (name + ".pwb", (cout,))]
+    return [(name + ".w", (cout, cin, 3, 3, 3)), (name + ".b", (cout,))]
+
+
+def _block_shapes(cin, cout, sep=False):
+    shapes = (_conv_shapes("conv1", cin, cout, sep) +
+              [("norm1.g", (cout,)), ("norm1.beta", (cout,))] +
+              _conv_shapes("conv2", cout, cout, sep) +
+              [("norm2.g", (cout,)), ("norm2.beta", (cout,))])
     if cin != cout:
         shapes += [("proj.w", (cout, cin, 1, 1, 1)), ("proj.b", (cout,))]
     return shapes
 
 
-def module_list(levels, base_ch):
-    """[(module name, [(param name, shape)])] in flat order."""
+def module_list(levels, base_ch, sep=False):
+    """[(module name, [(param name, shape)])] in flat order.  With sep every
+    ResBlock convolution is depthwise-separable; the stem (one input channel)
+    and the 1x1x1 projections and tail stay dense."""
     ch = [base_ch * 2 ** l for l in range(levels)]
     mods = [("stem", [("conv.w", (base_ch, 1, 3, 3, 3)), ("conv.b", (base_ch,)),
                       ("norm.g", (base_ch,)), ("norm.beta", (base_ch,))])]
-    mods.append(("enc0", _block_shapes(ch[0], ch[0])))
+    mods.append(("enc0", _block_shapes(ch[0], ch[0], sep)))
     for l in range(1, levels):
-        mods.append(("enc%d" % l, _block_shapes(ch[l - 1], ch[l])))
+        mods.append(("enc%d" % l, _block_shapes(ch[l - 1], ch[l], sep)))
     for l in range(levels - 2, -1, -1):
-        mods.append(("dec%d" % l, _block_shapes(ch[l + 1] + ch[l], ch[l])))
+        mods.append(("dec%d" % l, _block_shapes(ch[l + 1] + ch[l], ch[l], sep)))
     mods.append(("tail", [("w", (1, base_ch, 1, 1, 1)), ("b", (1,))]))
     return mods
 
 
-def n_params(levels, base_ch):
-    return sum(int(np.prod(s)) for _, ps in module_list(levels, base_ch) for _, s in ps)
+def n_params(levels, base_ch, sep=False):
+    return sum(int(np.prod(s)) for _, ps in module_list(levels, base_ch, sep) for _, s in ps)
 
 
-def unpack(theta, levels, base_ch):
+def unpack(theta, levels, base_ch, sep=False):
     """Flat theta -> {module: {param: view}} (views into theta)."""
     out, off = {}, 0
-    for mod, ps in module_list(levels, base_ch):
+    for mod, ps in module_list(levels, base_ch, sep):
         d = {}
         for name, shape in ps:
             k = int(np.prod(shape))
@@ -170,25 +188,45 @@ def up2_backward(gout):
 # blocks and the whole network
 # ----------------------------------------------------------------------------
 
+def _conv3(x, P, name):
+    """A ResBlock convolution (dense or depthwise-separable, by its
+    parameters); returns the output and the depthwise output (or None)."""
+    if name + ".w" in P:
+        return conv3d(x, P[name + ".w"], P[name + ".b"]), None
+    y, d = dwsep.dwsep_conv3d(x, P[name + ".dw"], P[name + ".dwb"], P[name + ".pw"],
+                              P[name + ".pwb"])
+    return y, d
+
+
+def _conv3_backward(x, P, name, g, d, G):
+    """Input gradient of _conv3; its parameter gradients go into G."""
+    if name + ".w" in P:
+        gx, G[name + ".w"], G[name + ".b"] = conv3d_backward(x, P[name + ".w"], g)
+        return gx
+    gx, G[name + ".dw"], G[name + ".dwb"], G[name + ".pw"], G[name + ".pwb"] = \
+        dwsep.dwsep_conv3d_backward(x, P[name + ".dw"], P[name + ".pw"], d, g)
+    return gx
+
+
 def resblock_forward(x, P):
-    h1 = conv3d(x, P["conv1.w"], P["conv1.b"])
+    h1, d1 = _conv3(x, P, "conv1")
     n1, c1 = layer_norm(h1, P["norm1.g"], P["norm1.beta"])
     a1 = relu(n1)
-    h2 = conv3d(a1, P["conv2.w"], P["conv2.b"])
+    h2, d2 = _conv3(a1, P, "conv2")
     n2, c2 = layer_norm(h2, P["norm2.g"], P["norm2.beta"])
     s = conv3d(x, P["proj.w"], P["proj.b"]) if "proj.w" in P else x
     y = relu(n2 + s)
-    return y, dict(x=x, a1=a1, c1=c1, c2=c2, y=y)
+    return y, dict(x=x, a1=a1, c1=c1, c2=c2, y=y, d1=d1, d2=d2)
 
 
 def resblock_backward(gy, P, cache):
     G = {}
     gz = relu_backward(gy, cache["y"])
     gh2, G["norm2.g"], G["norm2.beta"] = layer_norm_backward(gz, P["norm2.g"], cache["c2"])
-    ga1, G["conv2.w"], G["conv2.b"] = conv3d_backward(cache["a1"], P["conv2.w"], gh2)
+    ga1 = _conv3_backward(cache["a1"], P, "conv2", gh2, cache["d2"], G)
     gn1 = relu_backward(ga1, cache["a1"])
     gh1, G["norm1.g"], G["norm1.beta"] = layer_norm_backward(gn1, P["norm1.g"], cache["c1"])
-    gx, G["conv1.w"], G["conv1.b"] = conv3d_backward(cache["x"], P["conv1.w"], gh1)
+    gx = _conv3_backward(cache["x"], P, "conv1", gh1, cache["d1"], G)
     if "proj.w" in P:
         gxs, G["proj.w"], G["proj.b"] = conv3d_backward(cache["x"], P["proj.w"], gz)
         gx = gx + gxs
@@ -197,9 +235,10 @@ def resblock_backward(gy, P, cache):
     return gx, G
 
 
-def forward(theta, Z, n, levels, base_ch):
-    """phi(theta | Z) before masking, as an (n, n, n) array, plus the cache."""
-    P = unpack(theta, levels, base_ch)
+def forward(theta, Z, n, levels, base_ch, sep=False):
+    """phi(theta | Z) before masking, as an (n, n, n) array, plus the cache
+    (sep: depthwise-separable ResBlock convolutions, see module_list)."""
+    P = unpack(theta, levels, base_ch, sep)
     z = Z.reshape(1, n, n, n)
     hs = conv3d(z, P["stem"]["conv.w"], P["stem"]["conv.b"])
     ns, cs = layer_norm(hs, P["stem"]["norm.g"], P["stem"]["norm.beta"])
@@ -221,11 +260,11 @@ def forward(theta, Z, n, levels, base_ch):
     return out[0], cache
 
 
-def backward(gout, theta, cache, n, levels, base_ch):
+def backward(gout, theta, cache, n, levels, base_ch, sep=False):
     """d(loss)/d(theta) as a flat array, given gout = d(loss)/d(phi) (n, n, n)."""
-    P = unpack(theta, levels, base_ch)
+    P = unpack(theta, levels, base_ch, sep)
     grad = np.zeros(theta.size, dtype=np.float64)
-    Gv = unpack(grad, levels, base_ch)
+    Gv = unpack(grad, levels, base_ch, sep)
     go = gout.reshape(1, n, n, n)
     gd, gtw, gtb = conv3d_backward(cache["d0"], P["tail"]["w"], go)
     Gv["tail"]["w"][...] = gtw

@@ -108,3 +108,75 @@ def test_planted_tap_flip_is_caught():
         dense[c, c] = wd[c]
     flipped = dwsep.dwconv3d(x, wd[:, ::-1, ::-1, ::-1], bd)
     assert not np.allclose(flipped, net.conv3d(x, dense, bd))
+
+
+def _sep_and_dense_thetas(rng, levels, C):
+    """A depthwise-separable network whose depthwise convolutions are the
+    identity (centre tap 1, bias 0) and the dense network it then equals:
+    each dense 3x3x3 convolution is zero except its centre tap, which holds
+    the pointwise weights."""
+    ts_ = rng.standard_normal(net.n_params(levels, C, sep=True)) * 0.3
+    Ps = net.unpack(ts_, levels, C, sep=True)
+    td = np.zeros(net.n_params(levels, C))
+    Pd = net.unpack(td, levels, C)
+    for mod, d in Ps.items():
+        for name, v in d.items():
+            if name.endswith(".dw"):
+                v[...] = 0.0
+                v[:, 1, 1, 1] = 1.0
+            elif name.endswith(".dwb"):
+                v[...] = 0.0
+    for mod, d in Pd.items():
+        for name, v in d.items():
+            if name in ("conv1.w", "conv2.w"):
+                v[:, :, 1, 1, 1] = Ps[mod][name[:-2] + ".pw"]
+            elif name in ("conv1.b", "conv2.b"):
+                v[...] = Ps[mod][name[:-2] + ".pwb"]
+            else:
+                v[...] = Ps[mod][name]
+    return ts_, td
+
+
+def test_separable_network_with_identity_depthwise_equals_dense_network():
+    rng = np.random.default_rng(6)
+    n, L, C = 8, 2, 4
+    ts_, td = _sep_and_dense_thetas(rng, L, C)
+    Z = rng.standard_normal(n ** 3)
+    ys, cs = net.forward(ts_, Z, n, L, C, sep=True)
+    yd, cd = net.forward(td, Z, n, L, C)
+    np.testing.assert_allclose(ys, yd, rtol=1e-10, atol=1e-10)
+    g = rng.standard_normal((n, n, n))
+    gs = net.unpack(net.backward(g, ts_, cs, n, L, C, sep=True), L, C, sep=True)
+    gd = net.unpack(net.backward(g, td, cd, n, L, C), L, C)
+    for mod, d in gd.items():
+        for name, v in d.items():
+            if name in ("conv1.w", "conv2.w"):
+                ref, got = v[:, :, 1, 1, 1], gs[mod][name[:-2] + ".pw"]
+            elif name in ("conv1.b", "conv2.b"):
+                ref, got = v, gs[mod][name[:-2] + ".pwb"]
+            else:
+                ref, got = v, gs[mod][name]
+            np.testing.assert_allclose(got, ref, rtol=1e-9, atol=1e-9, err_msg=mod + "." + name)
+
+
+def test_separable_network_gradient_matches_finite_differences():
+    rng = np.random.default_rng(7)
+    n, L, C = 4, 2, 4
+    th = rng.standard_normal(net.n_params(L, C, sep=True)) * 0.3
+    Z = rng.standard_normal(n ** 3)
+    R = rng.standard_normal((n, n, n))
+    y, cache = net.forward(th, Z, n, L, C, sep=True)
+    g = net.backward(R, th, cache, n, L, C, sep=True)
+    f = lambda t: (net.forward(t, Z, n, L, C, sep=True)[0] * R).sum()
+    h = 1e-6
+    P = net.unpack(np.arange(th.size, dtype=np.float64), L, C, sep=True)
+    for mod, name in (("enc0", "conv1.dw"), ("dec0", "conv2.pw"), ("enc1", "conv1.dwb"),
+                      (None, None)):
+        v = np.zeros_like(th)
+        if mod is None:
+            v = rng.standard_normal(th.size)
+        else:
+            idx = P[mod][name].astype(int).ravel()
+            v[idx] = rng.standard_normal(idx.size)
+        fd = (f(th + h * v) - f(th - h * v)) / (2 * h)
+        assert fd == pytest.approx(float(g @ v), rel=1e-6), (mod, name)
