@@ -290,6 +290,46 @@ def dwsep_ops(d2ip, torch, shapes=((64, 64, 64), (32, 16, 16))):
     return out
 
 
+def dwsep_network(d2ip, torch, ts, names=("c1", "c2"), reps=5):
+    """One loss + theta-gradient evaluation of the autograd network
+    (`ops.DIPNet`, every operator on the library's kernels) with dense and
+    with depthwise-separable ResBlock convolutions, FP32, on a config's
+    problem: ms per evaluation (HIP events, mean of `reps` after one warm-up)
+    and parameter counts."""
+    from paper_2507_14046_amd import ops
+    out = {}
+    for name in names:
+        c = ts.CONFIGS[name]
+        p = ts.make_problem(c["n"], c["rings"], c["levels"], c["base_ch"], c["seed"])
+        dev = lambda a: torch.tensor(np.ascontiguousarray(a), dtype=torch.float32, device="cuda")
+        Z, mask, J, dv = dev(p["Z"]), dev(p["mask"].astype(np.float32)), dev(p["J"]), \
+            dev(p["dv"][0])
+        row = {}
+        for conv in ("dense", "dwsep"):
+            model = ops.DIPNet(c["n"], c["levels"], c["base_ch"], conv=conv)
+            g = torch.Generator(device="cuda").manual_seed(11)
+            th = (0.1 * torch.randn(model.size, device="cuda", generator=g)).requires_grad_(True)
+
+            def once():
+                th.grad = None
+                model.loss(th, Z, mask, J, dv).backward()
+            once()
+            st = torch.cuda.current_stream()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(st)
+            for _ in range(reps):
+                once()
+            e1.record(st)
+            torch.cuda.synchronize()
+            row[conv] = dict(ms_per_loss_and_grad=e0.elapsed_time(e1) / reps, params=model.size)
+        row["speedup"] = row["dense"]["ms_per_loss_and_grad"] / row["dwsep"]["ms_per_loss_and_grad"]
+        out[name] = row
+        log("network %s: dense %.2f ms (%d params), dwsep %.2f ms (%d params), %.2fx"
+            % (name, row["dense"]["ms_per_loss_and_grad"], row["dense"]["params"],
+               row["dwsep"]["ms_per_loss_and_grad"], row["dwsep"]["params"], row["speedup"]))
+    return out
+
+
 def cpu_baseline(p, cfg, budget_s):
     from oracle import fit
     try:
@@ -577,7 +617,8 @@ def main():
         log("ablation (%.0f s): %s" % (time.time() - t0, json.dumps(
             {k: (v["total_iterations"], round(v["seconds"], 2), v["all_reached"])
              for k, v in ablation["variants"].items()})))
-    dwsep = None if a.no_dwsep else dwsep_ops(d2ip, torch)
+    dwsep = None if a.no_dwsep else dict(ops=dwsep_ops(d2ip, torch),
+                                         network=dwsep_network(d2ip, torch, ts))
     cpu = None if a.no_cpu else cpu_baseline(p, cfg, a.cpu_seconds)
     out = {
         "metric": METRIC,
@@ -608,7 +649,7 @@ def main():
         "fp32_with_4d_tv": with_tv,
         "configs": configs,
         "ablation": ablation,
-        "dwsep_ops": dwsep,
+        "dwsep": dwsep,
         "roofline": roof,
         "cpu_baseline": cpu,
     }

@@ -6,7 +6,8 @@ backward passes are the library's HIP kernels (implicit-GEMM convolutions
 with the input and weight gradients, the depthwise 3x3x3 and pointwise 1x1x1
 convolutions of the depthwise-separable convolution and their gradients, the
 whole-volume LayerNorm + ReLU and its backward, J sigma and J^T g).  ``DIPNet``
-composes the prior of Eq. (3) from them; pooling, up-sampling, channel
+composes the prior of Eq. (3) from them (with ``conv="dwsep"`` every ResBlock
+convolution is the depthwise-separable one of Sec. III-D); pooling, up-sampling, channel
 concatenation and the 1x1x1 output head are plain tensor operations of the
 model around the operators.  With ``recompute=True`` every ResBlock's
 activations are dropped after the forward and recomputed during the backward
@@ -314,19 +315,26 @@ def _measure_fn():
 # the prior of Eq. (3) composed from the operators
 # ----------------------------------------------------------------------------
 
-def param_shapes(levels, base_ch):
+def param_shapes(levels, base_ch, sep=False):
     """(name, shape) of every parameter tensor in the canonical flat order:
     stem, encoder ResBlocks 0..L-1, decoder ResBlocks L-2..0, head; in a
     module each conv's W [Cout][Cin][k][k][k] then b, each norm gamma then
-    beta, in the order conv1, norm1, conv2, norm2, projection."""
+    beta, in the order conv1, norm1, conv2, norm2, projection.  With sep each
+    ResBlock 3x3x3 conv is depthwise-separable (Sec. III-D): depthwise
+    [Cin][3][3][3] and its bias, then pointwise [Cout][Cin] and its bias."""
     C = base_ch
     ch = [C << l for l in range(levels)]
     out = [("stem.w", (C, 1, 3, 3, 3)), ("stem.b", (C,)), ("stem.g", (C,)), ("stem.beta", (C,))]
 
+    def conv(name, k, a, b):
+        if sep:
+            return [(name + ".dw" + k, (a, 3, 3, 3)), (name + ".dwb" + k, (a,)),
+                    (name + ".pw" + k, (b, a)), (name + ".pwb" + k, (b,))]
+        return [(name + ".w" + k, (b, a, 3, 3, 3)), (name + ".b" + k, (b,))]
+
     def block(name, a, b):
-        s = [(name + ".w1", (b, a, 3, 3, 3)), (name + ".b1", (b,)), (name + ".g1", (b,)),
-             (name + ".beta1", (b,)), (name + ".w2", (b, b, 3, 3, 3)), (name + ".b2", (b,)),
-             (name + ".g2", (b,)), (name + ".beta2", (b,))]
+        s = (conv(name, "1", a, b) + [(name + ".g1", (b,)), (name + ".beta1", (b,))] +
+             conv(name, "2", b, b) + [(name + ".g2", (b,)), (name + ".beta2", (b,))])
         if a != b:
             s += [(name + ".wp", (b, a, 1, 1, 1)), (name + ".bp", (b,))]
         return s
@@ -355,11 +363,14 @@ class DIPNet:
     """sigma = mask * phi(theta | Z) built from the operators; theta is one
     flat tensor in the canonical order (gradients flow to it through views)."""
 
-    def __init__(self, n, levels, base_ch, precision="fp32", recompute=False):
+    def __init__(self, n, levels, base_ch, precision="fp32", recompute=False, conv="dense"):
+        if conv not in ("dense", "dwsep"):
+            raise ValueError("conv must be 'dense' or 'dwsep'")
         self.n, self.L, self.C = n, levels, base_ch
         self.precision = precision
         self.recompute = recompute
-        self.shapes = param_shapes(levels, base_ch)
+        self.sep = conv == "dwsep"  # depthwise-separable ResBlock convs (FP32)
+        self.shapes = param_shapes(levels, base_ch, self.sep)
         self.size = int(sum(np.prod(s) for _, s in self.shapes))
 
     def views(self, theta):
@@ -370,11 +381,17 @@ class DIPNet:
             off += k
         return out
 
+    def _conv3(self, P, name, k, x):
+        if self.sep:
+            return dwsep_conv3d(x, P[name + ".dw" + k], P[name + ".dwb" + k], P[name + ".pw" + k],
+                                P[name + ".pwb" + k])
+        return Conv3dFn.apply(x, P[name + ".w" + k], P[name + ".b" + k], self.precision)
+
     def _block(self, P, name, x, n):
         prec = self.precision
-        h1 = Conv3dFn.apply(x, P[name + ".w1"], P[name + ".b1"], prec)
+        h1 = self._conv3(P, name, "1", x)
         a1 = LayerNormReLUFn.apply(h1, P[name + ".g1"], P[name + ".beta1"])
-        h2 = Conv3dFn.apply(a1, P[name + ".w2"], P[name + ".b2"], prec)
+        h2 = self._conv3(P, name, "2", a1)
         s = Conv3dFn.apply(x, P[name + ".wp"], P[name + ".bp"], prec) if name + ".wp" in P else x
         return LayerNormReLUFn.apply(h2, P[name + ".g2"], P[name + ".beta2"], s)
 

@@ -199,3 +199,29 @@ def test_depthwise_full_size_workload(lib):
     record("dwconv3d_64", **e)
     assert ey < 1e-5 and eg < 1e-5, e
     assert e["gw"] < TOL_W and e["gb"] < TOL_W, e
+
+
+@pytest.mark.parametrize("shape", [(8, 1, 2, 8), (16, 2, 3, 16)])
+def test_separable_network_gradient_matches_oracle(lib, shape):
+    """The autograd network with depthwise-separable ResBlock convolutions
+    (every conv on the library's kernels): loss and theta gradient against
+    the FP64 oracle network of the same layout."""
+    import torch
+    from oracle import fit, net
+    from paper_2507_14046_amd import ops
+    from tests.gpu_util import problem
+    n, rings, L, C = shape
+    p = problem(n, rings, L, C, 70 + n + L)
+    rng = np.random.default_rng(71 + n)
+    th = (0.3 * rng.standard_normal(net.n_params(L, C, sep=True))).astype(np.float32)
+    model = ops.DIPNet(n, L, C, conv="dwsep")
+    T = dev(th, True)
+    loss = model.loss(T, dev(p["Z"]), dev(p["mask"].astype(np.float32)), dev(p["J"]),
+                      dev(p["dv"][0]))
+    loss.backward()
+    torch.cuda.synchronize()
+    pr = fit.Problem(p["J"], p["mask"], p["Z"], n, L, C, sep=True)
+    L0, gref, _ = pr.loss_and_grad(th.astype(np.float64), p["dv"][0].astype(np.float64))
+    e = dict(loss=abs(float(loss) - L0) / L0, grad=rel(host(T.grad), gref))
+    record("dwsep_network", n=n, levels=L, C=C, **e)
+    assert e["loss"] < 1e-5 and e["grad"] < 2e-4, e
