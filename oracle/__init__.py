@@ -11,7 +11,9 @@ NumPy in float64, written from the paper's definitions:
              (Eqs. (5), (9)) and the read-out;
 * ``tv``   - the 4D-TV regulariser of Eqs. (11)-(14);
 * ``dwsep``- the depthwise-separable 3D convolution of the lightweight
-             backbone (Sec. III-D) and its gradients.
+             backbone (Sec. III-D) and its gradients;
+* ``se``   - the Squeeze-and-Excitation unit of the 3D-FastResUNet
+             (Sec. III-D) and its gradients.
 
 Parity pins (tests/test_oracle_*.py): central finite differences, brute-force
 7-loop convolution, torch CPU float64 library operations, adjoint identities,
