@@ -290,6 +290,61 @@ def dwsep_ops(d2ip, torch, shapes=((64, 64, 64), (32, 16, 16))):
     return out
 
 
+def se_ops(d2ip, torch, shapes=((64, 64, 16), (32, 16, 4))):
+    """The Squeeze-and-Excitation unit through the op-level C-ABI (FP32,
+    channels-last, HIP events per call).  Algorithmic bytes: the forward
+    streams three voxel tensors (x for the channel means, x again and y for
+    the scaling); the backward five (x for the recomputed means, gy and x for
+    the gate gradient, gy and gx for the input gradient)."""
+    import ctypes
+    L = d2ip._lib
+    lib = L.load()
+    P = lambda t: ctypes.c_void_p(t.data_ptr()) if t is not None else None
+    st = torch.cuda.current_stream()
+    sp = ctypes.c_void_p(st.cuda_stream)
+    g = torch.Generator(device="cuda").manual_seed(2508)
+    out = {}
+    for n, C, H in shapes:
+        V = n ** 3
+        x = 1.0 + torch.randn(V, C, device="cuda", generator=g)
+        gy = torch.randn(V, C, device="cuda", generator=g)
+        w1 = torch.randn(H, C, device="cuda", generator=g) / C ** 0.5
+        b1 = torch.zeros(H, device="cuda")
+        w2 = torch.randn(C, H, device="cuda", generator=g) / H ** 0.5
+        b2 = torch.zeros(C, device="cuda")
+        y, gx = torch.empty_like(x), torch.empty_like(x)
+        gw1, gb1, gw2, gb2 = (torch.empty_like(t) for t in (w1, b1, w2, b2))
+        nb = ctypes.c_size_t()
+        L.check(lib.d2ip_op_se_bytes(n, C, H, ctypes.byref(nb)))
+        ws = torch.empty(nb.value, dtype=torch.uint8, device="cuda")
+        calls = {
+            "se_forward": (3, lambda: lib.d2ip_op_se_forward(
+                P(x), P(w1), P(b1), P(w2), P(b2), P(y), n, C, H, P(ws), nb.value, sp)),
+            "se_backward": (5, lambda: lib.d2ip_op_se_backward(
+                P(x), P(w1), P(b1), P(w2), P(b2), P(gy), P(gx), P(gw1), P(gb1), P(gw2), P(gb2),
+                n, C, H, P(ws), nb.value, sp)),
+        }
+        rows = {}
+        for name, (passes, f) in calls.items():
+            for _ in range(5):
+                L.check(f())
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(st)
+            for _ in range(50):
+                f()
+            e1.record(st)
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / 50
+            byts = passes * 4.0 * V * C
+            rows[name] = dict(ms=ms, bound="hbm", achieved=byts / (ms * 1e-3) / 1e9,
+                              peak=HBM_PEAK_GBS, unit="GB/s",
+                              frac=byts / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS)
+            log("  %d^3 C=%d H=%d %-12s %8.4f ms  %7.0f GB/s (%.1f%% of HBM peak)"
+                % (n, C, H, name, ms, rows[name]["achieved"], 100 * rows[name]["frac"]))
+        out["%d^3 x %d, H %d" % (n, C, H)] = rows
+    return out
+
+
 def dwsep_network(d2ip, torch, ts, names=("c1", "c2"), reps=5):
     """One loss + theta-gradient evaluation of the autograd network
     (`ops.DIPNet`, every operator on the library's kernels) with dense and
@@ -479,7 +534,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-kernels", action="store_true")
     ap.add_argument("--no-configs", action="store_true")
-    ap.add_argument("--no-dwsep", action="store_true")
+    ap.add_argument("--no-dwsep", action="store_true",
+                    help="skip the depthwise-separable and SE operator timings")
     ap.add_argument("--ablation", action="store_true",
                     help="also run the D2IP schedule ablation (UPWS / TPP) on a 20-frame "
                          "32^3 sequence in the chosen form (about a minute)")
@@ -619,6 +675,7 @@ def main():
              for k, v in ablation["variants"].items()})))
     dwsep = None if a.no_dwsep else dict(ops=dwsep_ops(d2ip, torch),
                                          network=dwsep_network(d2ip, torch, ts))
+    se_unit = None if a.no_dwsep else se_ops(d2ip, torch)
     cpu = None if a.no_cpu else cpu_baseline(p, cfg, a.cpu_seconds)
     out = {
         "metric": METRIC,
@@ -650,6 +707,7 @@ def main():
         "configs": configs,
         "ablation": ablation,
         "dwsep": dwsep,
+        "se": se_unit,
         "roofline": roof,
         "cpu_baseline": cpu,
     }

@@ -372,6 +372,26 @@ d2ip_status d2ip_op_pwconv3d_backward(const float* x, const float* w, const floa
                                       float* gw, float* gb, int n, int cin, int cout,
                                       void* workspace, size_t bytes, void* hip_stream);
 
+/* Workspace bytes of the Squeeze-and-Excitation operators (C a multiple of
+ * 4 in [4, 1024], hidden width H in [1, 256]). */
+d2ip_status d2ip_op_se_bytes(int n, int C, int H, size_t* out);
+
+/* Squeeze-and-Excitation unit of the 3D-FastResUNet (Sec. III-D): the channel
+ * means s[c] = (1/n^3) sum_v x[v][c], the gate
+ * e = sigmoid(w2 relu(w1 s + b1) + b2) (w1 [H][C], b1 [H], w2 [C][H], b2 [C])
+ * and y[v][c] = e[c] x[v][c].  x and y 16-byte aligned. */
+d2ip_status d2ip_op_se_forward(const float* x, const float* w1, const float* b1, const float* w2,
+                               const float* b2, float* y, int n, int C, int H, void* workspace,
+                               size_t bytes, void* hip_stream);
+
+/* Gradients of d2ip_op_se_forward given its input x and gy = dL/dy: gx and the
+ * weight and bias gradients (any output may be NULL).  The pooled state is
+ * recomputed from x; voxel sums are reduced in a fixed order. */
+d2ip_status d2ip_op_se_backward(const float* x, const float* w1, const float* b1, const float* w2,
+                                const float* b2, const float* gy, float* gx, float* gw1,
+                                float* gb1, float* gw2, float* gb2, int n, int C, int H,
+                                void* workspace, size_t bytes, void* hip_stream);
+
 /* p = J sigma for a dense row-major M x Q J (Eq. (1)); Q a multiple of 4. */
 d2ip_status d2ip_op_j_forward(const float* J, const float* sigma, float* p, int M, int Q,
                               void* hip_stream);

@@ -261,6 +261,16 @@ void pw_gemm(const float* X, const float* W, const float* bias, float* Y, size_t
              bool transw, hipStream_t s);
 void pw_wgrad(const float* X, const float* G, float* part, float* gw, float* gb, size_t M, int K,
               int N, hipStream_t s);
+// Squeeze-and-Excitation unit on channels-last [V][C] (C % 4 == 0, C <= 1024,
+// H <= 256): w1 [H][C], b1 [H], w2 [C][H], b2 [C]; `ws` holds
+// se_scratch(V, C, H) floats (256-byte aligned).  The backward recomputes the
+// pooled state from x; any gradient output may be null.
+size_t se_scratch(int V, int C, int H);
+void se_forward(const float* x, const float* w1, const float* b1, const float* w2,
+                const float* b2, float* y, int V, int C, int H, float* ws, hipStream_t s);
+void se_backward(const float* x, const float* w1, const float* b1, const float* w2,
+                 const float* b2, const float* gy, float* gx, float* gw1, float* gb1, float* gw2,
+                 float* gb2, int V, int C, int H, float* ws, hipStream_t s);
 // The launch shape the plan's heuristic picks for a forward / input-gradient
 // pass with `cin` inputs and `cout` outputs (precision: PREC_*).
 void default_conv_shape(int n, int cin, int cout, int taps, int prec, int* tile, int* bn, int* ck,

@@ -191,6 +191,14 @@ d2ip_status dw_check(int n, int C) {
 
 bool aligned16(const void* p) { return ((uintptr_t)p & 15) == 0; }
 
+d2ip_status se_check(int n, int C, int H) {
+  if (n < 1 || n > 256) return api_fail(D2IP_EINVAL, "n must be in [1, 256]");
+  if (C < 4 || C > 1024 || C % 4 != 0)
+    return api_fail(D2IP_EINVAL, "C must be a multiple of 4 in [4, 1024]");
+  if (H < 1 || H > 256) return api_fail(D2IP_EINVAL, "H must be in [1, 256]");
+  return D2IP_OK;
+}
+
 d2ip_status pw_check(int n, int cin, int cout) {
   if (n < 1 || n > 256) return api_fail(D2IP_EINVAL, "n must be in [1, 256]");
   if (cin < 4 || cout < 4 || cin % 4 || cout % 4 || cin > 1024 || cout > 1024)
@@ -454,6 +462,49 @@ d2ip_status d2ip_op_pwconv3d_backward(const float* x, const float* w, const floa
     pw_wgrad(x, gy, reinterpret_cast<float*>(workspace), gw, gb, V, cin, cout, s);
   }
   if (gx) pw_gemm(gy, w, nullptr, gx, V, cout, cin, true, s);
+  OPCHK(hipGetLastError());
+  return D2IP_OK;
+}
+
+d2ip_status d2ip_op_se_bytes(int n, int C, int H, size_t* out) {
+  if (!out) return api_fail(D2IP_EINVAL, "null output");
+  d2ip_status st = se_check(n, C, H);
+  if (st != D2IP_OK) return st;
+  *out = se_scratch(n * n * n, C, H) * sizeof(float) + 256;
+  return D2IP_OK;
+}
+
+d2ip_status d2ip_op_se_forward(const float* x, const float* w1, const float* b1, const float* w2,
+                               const float* b2, float* y, int n, int C, int H, void* workspace,
+                               size_t bytes, void* hip_stream) {
+  d2ip_status st = se_check(n, C, H);
+  if (st != D2IP_OK) return st;
+  if (!x || !w1 || !b1 || !w2 || !b2 || !y) return api_fail(D2IP_EINVAL, "null x, y or weights");
+  if (!aligned16(x) || !aligned16(y)) return api_fail(D2IP_EINVAL, "x and y must be 16-byte aligned");
+  size_t need = 0;
+  d2ip_op_se_bytes(n, C, H, &need);
+  if ((st = ws_check(workspace, bytes, need)) != D2IP_OK) return st;
+  se_forward(x, w1, b1, w2, b2, y, n * n * n, C, H, reinterpret_cast<float*>(workspace),
+             reinterpret_cast<hipStream_t>(hip_stream));
+  OPCHK(hipGetLastError());
+  return D2IP_OK;
+}
+
+d2ip_status d2ip_op_se_backward(const float* x, const float* w1, const float* b1, const float* w2,
+                                const float* b2, const float* gy, float* gx, float* gw1,
+                                float* gb1, float* gw2, float* gb2, int n, int C, int H,
+                                void* workspace, size_t bytes, void* hip_stream) {
+  d2ip_status st = se_check(n, C, H);
+  if (st != D2IP_OK) return st;
+  if (!x || !w1 || !b1 || !w2 || !b2 || !gy)
+    return api_fail(D2IP_EINVAL, "null x, gy or weights");
+  if (!aligned16(x) || !aligned16(gy) || (gx && !aligned16(gx)))
+    return api_fail(D2IP_EINVAL, "x, gy and gx must be 16-byte aligned");
+  size_t need = 0;
+  d2ip_op_se_bytes(n, C, H, &need);
+  if ((st = ws_check(workspace, bytes, need)) != D2IP_OK) return st;
+  se_backward(x, w1, b1, w2, b2, gy, gx, gw1, gb1, gw2, gb2, n * n * n, C, H,
+              reinterpret_cast<float*>(workspace), reinterpret_cast<hipStream_t>(hip_stream));
   OPCHK(hipGetLastError());
   return D2IP_OK;
 }

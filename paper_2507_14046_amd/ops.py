@@ -1,11 +1,12 @@
 """PyTorch autograd operators over the library's standalone kernels.
 
-``Conv3dFn``, ``DWConv3dFn``, ``PWConv3dFn``, ``LayerNormReLUFn`` and
-``MeasureFn`` wrap the op-level C-ABI (include/d2ip.h): their forward and
+``Conv3dFn``, ``DWConv3dFn``, ``PWConv3dFn``, ``SEFn``, ``LayerNormReLUFn``
+and ``MeasureFn`` wrap the op-level C-ABI (include/d2ip.h): their forward and
 backward passes are the library's HIP kernels (implicit-GEMM convolutions
 with the input and weight gradients, the depthwise 3x3x3 and pointwise 1x1x1
 convolutions of the depthwise-separable convolution and their gradients, the
-whole-volume LayerNorm + ReLU and its backward, J sigma and J^T g).  ``DIPNet``
+Squeeze-and-Excitation unit, the whole-volume LayerNorm + ReLU and its
+backward, J sigma and J^T g).  ``DIPNet``
 composes the prior of Eq. (3) from them (with ``conv="dwsep"`` every ResBlock
 convolution is the depthwise-separable one of Sec. III-D); pooling, up-sampling, channel
 concatenation and the 1x1x1 output head are plain tensor operations of the
@@ -90,6 +91,16 @@ def dwsep_conv3d(x, wd, bd, wp, bp):
     """Depthwise-separable convolution: the depthwise 3x3x3 convolution, then
     the pointwise 1x1x1 one, both on the library's kernels."""
     return PWConv3dFn.apply(DWConv3dFn.apply(x, wd, bd), wp, bp)
+
+
+class SEFn:
+    """y = SE(x): the Squeeze-and-Excitation unit of Sec. III-D on x [n^3, C]
+    (C % 4 == 0): gate e = sigmoid(w2 relu(w1 mean(x) + b1) + b2), w1 [H, C],
+    w2 [C, H]; y = x * e."""
+
+    @staticmethod
+    def apply(x, w1, b1, w2, b2):
+        return _se_fn().apply(x, w1, b1, w2, b2)
 
 
 class MeasureFn:
@@ -234,6 +245,46 @@ def _pw_fn():
 
     _FNS["pw"] = _PW
     return _PW
+
+
+def _se_fn():
+    if "se" in _FNS:
+        return _FNS["se"]
+    torch = _torch()
+
+    class _SE(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, x, w1, b1, w2, b2):
+            lib = L.load()
+            x, w1, b1, w2, b2 = (t.contiguous() for t in (x, w1, b1, w2, b2))
+            V, C = x.shape
+            H = w1.shape[0]
+            n = _grid_n(V)
+            ws, nb = _workspace(lib.d2ip_op_se_bytes, n, C, H, device=x.device)
+            y = torch.empty_like(x)
+            L.check(lib.d2ip_op_se_forward(_p(x), _p(w1), _p(b1), _p(w2), _p(b2), _p(y), n, C,
+                                           H, _p(ws), nb, _stream(x)))
+            ctx.save_for_backward(x, w1, b1, w2, b2)
+            ctx.meta = (n, C, H)
+            return y
+
+        @staticmethod
+        def backward(ctx, gy):
+            lib = L.load()
+            x, w1, b1, w2, b2 = ctx.saved_tensors
+            n, C, H = ctx.meta
+            gy = gy.contiguous()
+            need = ctx.needs_input_grad[:5]
+            outs = [torch.empty_like(t) if nd else None
+                    for t, nd in zip((x, w1, b1, w2, b2), need)]
+            ws, nb = _workspace(lib.d2ip_op_se_bytes, n, C, H, device=x.device)
+            L.check(lib.d2ip_op_se_backward(_p(x), _p(w1), _p(b1), _p(w2), _p(b2), _p(gy),
+                                            *[_p(o) for o in outs], n, C, H, _p(ws), nb,
+                                            _stream(x)))
+            return tuple(outs)
+
+    _FNS["se"] = _SE
+    return _SE
 
 
 def _ln_fn():

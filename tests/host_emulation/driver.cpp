@@ -200,6 +200,23 @@ static int ops_case() {
       free(ws);
     }
   EXPECT_ERR(d2ip_op_pwconv3d_bytes(n, 6, 8, &need), D2IP_EINVAL);
+  for (int Cs : {4, 12, 32})
+    for (int Hs : {1, 3, 8}) {
+      CK(d2ip_op_se_bytes(n, Cs, Hs, &need));
+      ws = (char*)aligned_alloc(256, (need + 255) / 256 * 256);
+      std::vector<float> a1((size_t)Hs * Cs), c1(Hs), a2((size_t)Cs * Hs), c2(Cs);
+      std::vector<float> ga1(a1.size()), gc1(Hs), ga2(a2.size()), gc2(Cs);
+      CK(d2ip_op_se_forward(x.data(), a1.data(), c1.data(), a2.data(), c2.data(), y.data(), n,
+                            Cs, Hs, ws, need, &token));
+      CK(d2ip_op_se_backward(x.data(), a1.data(), c1.data(), a2.data(), c2.data(), g.data(),
+                             gx.data(), ga1.data(), gc1.data(), ga2.data(), gc2.data(), n, Cs, Hs,
+                             ws, need, &token));
+      EXPECT_ERR(d2ip_op_se_forward(x.data(), a1.data(), c1.data(), a2.data(), c2.data(),
+                                    y.data(), n, Cs, Hs, ws, need - 1, &token),
+                 D2IP_ENOMEM);
+      free(ws);
+    }
+  EXPECT_ERR(d2ip_op_se_bytes(n, 16, 0, &need), D2IP_EINVAL);
   EXPECT_ERR(d2ip_op_dwconv3d_forward(x.data() + 1, gam.data(), nullptr, y.data(), n, C, &token),
              D2IP_EINVAL);
   CK(d2ip_op_j_forward(J.data(), x.data(), p.data(), M, Q, &token));

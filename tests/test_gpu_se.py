@@ -1,0 +1,61 @@
+"""GPU tests of the Squeeze-and-Excitation unit (forward and backward through
+the C-ABI) against the FP64 oracle (oracle/se.py): channel counts with one,
+three, 16 and 256 quads (every column-sum lane layout), hidden widths down to
+1, ragged and one-voxel grids, and the 64^3 x 64 workload the benchmark
+times, compared in full."""
+import numpy as np
+import pytest
+
+from oracle import se
+from tests.gpu_util import record, rel
+
+pytestmark = pytest.mark.gpu
+
+# FP32 against FP64: the gate is one sigmoid of short dot products; the
+# weight gradients hang on column sums over n^3 voxels (fixed-order tree).
+TOL_Y = 2e-6
+TOL_W = 1e-5
+
+
+def cl(x):
+    return np.ascontiguousarray(x.reshape(x.shape[0], -1).T)
+
+
+def cf(x, n):
+    return np.ascontiguousarray(np.asarray(x).T.reshape(-1, n, n, n))
+
+
+def dev(a, grad=False):
+    import torch
+    return torch.tensor(np.ascontiguousarray(a), dtype=torch.float32, device="cuda",
+                        requires_grad=grad)
+
+
+def host(t):
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+@pytest.mark.parametrize("n,C,H", [(1, 4, 1), (5, 12, 3), (8, 16, 4), (13, 64, 16),
+                                   (16, 1024, 64), (64, 64, 16)])
+def test_se_matches_oracle(lib, n, C, H):
+    from paper_2507_14046_amd import ops
+    rng = np.random.default_rng(900 + n + C + H)
+    x = (1.0 + rng.standard_normal((C, n, n, n))).astype(np.float32)  # nonzero means
+    w1 = (rng.standard_normal((H, C)) / np.sqrt(C)).astype(np.float32)
+    b1 = (0.1 * rng.standard_normal(H)).astype(np.float32)
+    w2 = (rng.standard_normal((C, H)) / np.sqrt(H)).astype(np.float32)
+    b2 = (0.1 * rng.standard_normal(C)).astype(np.float32)
+    g = rng.standard_normal((C, n, n, n)).astype(np.float32)
+    f = lambda a: a.astype(np.float64)
+    yref, cache = se.se_forward(f(x), f(w1), f(b1), f(w2), f(b2))
+    refs = se.se_backward(f(x), f(w1), f(w2), cache, f(g))
+    T = [dev(cl(x), True)] + [dev(a, True) for a in (w1, b1, w2, b2)]
+    Y = ops.SEFn.apply(*T)
+    Y.backward(dev(cl(g)))
+    got = [cf(host(T[0].grad), n)] + [host(t.grad) for t in T[1:]]
+    e = dict(y=rel(cf(host(Y), n), yref))
+    for k, a, b in zip(("gx", "gw1", "gb1", "gw2", "gb2"), got, refs):
+        e[k] = rel(a, b)
+    record("se", n=n, C=C, H=H, **e)
+    assert e["y"] < TOL_Y and e["gx"] < TOL_Y, e
+    assert max(e["gw1"], e["gb1"], e["gw2"], e["gb2"]) < TOL_W, e
