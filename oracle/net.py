@@ -21,7 +21,10 @@ reading used throughout this project:
 
 With sep=True every ResBlock conv3 is the depthwise-separable convolution of
 the lightweight backbone (Sec. III-D; oracle/dwsep.py): a per-channel 3x3x3
-convolution with a bias, then a 1x1x1 convolution with a bias.
+convolution with a bias, then a 1x1x1 convolution with a bias.  With
+se_ratio = r > 0 a Squeeze-and-Excitation unit (Sec. III-D; oracle/se.py) of
+hidden width c // r gates the output of every encoder block (enc_l above
+stands for the gated output wherever it is used).
 
 Conventions: arrays are channel-first [C, n, n, n] in (z, y, x) order; conv3
 is a 3x3x3 cross-correlation with zero padding 1; LN normalises over all of
@@ -31,7 +34,7 @@ repeats every voxel into a 2x2x2 block (nearest neighbour); relu'(0) = 0.
 """
 import numpy as np
 
-from . import dwsep
+from . import dwsep, se
 
 LN_EPS = 1e-5
 
@@ -62,30 +65,46 @@ def _block_shapes(cin, cout, sep=False):
     return shapes
 
 
-def module_list(levels, base_ch, sep=False):
+def se_hidden(c, se_ratio):
+    """Hidden width of an SE unit on c channels with reduction ratio r."""
+    return max(1, c // se_ratio)
+
+
+def _se_shapes(c, se_ratio):
+    if not se_ratio:
+        return []
+    h = se_hidden(c, se_ratio)
+    return [("se.w1", (h, c)), ("se.b1", (h,)), ("se.w2", (c, h)), ("se.b2", (c,))]
+
+
+def module_list(levels, base_ch, sep=False, se_ratio=0):
     """[(module name, [(param name, shape)])] in flat order.  With sep every
     ResBlock convolution is depthwise-separable; the stem (one input channel)
-    and the 1x1x1 projections and tail stay dense."""
+    and the 1x1x1 projections and tail stay dense.  With se_ratio r > 0 every
+    encoder ResBlock is followed by a Squeeze-and-Excitation unit of hidden
+    width c // r (its parameters end the encoder module)."""
     ch = [base_ch * 2 ** l for l in range(levels)]
     mods = [("stem", [("conv.w", (base_ch, 1, 3, 3, 3)), ("conv.b", (base_ch,)),
                       ("norm.g", (base_ch,)), ("norm.beta", (base_ch,))])]
-    mods.append(("enc0", _block_shapes(ch[0], ch[0], sep)))
+    mods.append(("enc0", _block_shapes(ch[0], ch[0], sep) + _se_shapes(ch[0], se_ratio)))
     for l in range(1, levels):
-        mods.append(("enc%d" % l, _block_shapes(ch[l - 1], ch[l], sep)))
+        mods.append(("enc%d" % l, _block_shapes(ch[l - 1], ch[l], sep) +
+                     _se_shapes(ch[l], se_ratio)))
     for l in range(levels - 2, -1, -1):
         mods.append(("dec%d" % l, _block_shapes(ch[l + 1] + ch[l], ch[l], sep)))
     mods.append(("tail", [("w", (1, base_ch, 1, 1, 1)), ("b", (1,))]))
     return mods
 
 
-def n_params(levels, base_ch, sep=False):
-    return sum(int(np.prod(s)) for _, ps in module_list(levels, base_ch, sep) for _, s in ps)
+def n_params(levels, base_ch, sep=False, se_ratio=0):
+    return sum(int(np.prod(s)) for _, ps in module_list(levels, base_ch, sep, se_ratio)
+               for _, s in ps)
 
 
-def unpack(theta, levels, base_ch, sep=False):
+def unpack(theta, levels, base_ch, sep=False, se_ratio=0):
     """Flat theta -> {module: {param: view}} (views into theta)."""
     out, off = {}, 0
-    for mod, ps in module_list(levels, base_ch, sep):
+    for mod, ps in module_list(levels, base_ch, sep, se_ratio):
         d = {}
         for name, shape in ps:
             k = int(np.prod(shape))
@@ -235,10 +254,11 @@ def resblock_backward(gy, P, cache):
     return gx, G
 
 
-def forward(theta, Z, n, levels, base_ch, sep=False):
+def forward(theta, Z, n, levels, base_ch, sep=False, se_ratio=0):
     """phi(theta | Z) before masking, as an (n, n, n) array, plus the cache
-    (sep: depthwise-separable ResBlock convolutions, see module_list)."""
-    P = unpack(theta, levels, base_ch, sep)
+    (sep: depthwise-separable ResBlock convolutions; se_ratio: SE units after
+    the encoder blocks; see module_list)."""
+    P = unpack(theta, levels, base_ch, sep, se_ratio)
     z = Z.reshape(1, n, n, n)
     hs = conv3d(z, P["stem"]["conv.w"], P["stem"]["conv.b"])
     ns, cs = layer_norm(hs, P["stem"]["norm.g"], P["stem"]["norm.beta"])
@@ -250,6 +270,11 @@ def forward(theta, Z, n, levels, base_ch, sep=False):
         if l > 0:
             x = avgpool2(enc[-1])
         y, cache["enc%d" % l] = resblock_forward(x, P["enc%d" % l])
+        if se_ratio:
+            Q = P["enc%d" % l]
+            y_in = y
+            y, cse = se.se_forward(y_in, Q["se.w1"], Q["se.b1"], Q["se.w2"], Q["se.b2"])
+            cache["se%d" % l] = (y_in, cse)
         enc.append(y)
     d = enc[-1]
     for l in range(levels - 2, -1, -1):
@@ -260,11 +285,11 @@ def forward(theta, Z, n, levels, base_ch, sep=False):
     return out[0], cache
 
 
-def backward(gout, theta, cache, n, levels, base_ch, sep=False):
+def backward(gout, theta, cache, n, levels, base_ch, sep=False, se_ratio=0):
     """d(loss)/d(theta) as a flat array, given gout = d(loss)/d(phi) (n, n, n)."""
-    P = unpack(theta, levels, base_ch, sep)
+    P = unpack(theta, levels, base_ch, sep, se_ratio)
     grad = np.zeros(theta.size, dtype=np.float64)
-    Gv = unpack(grad, levels, base_ch, sep)
+    Gv = unpack(grad, levels, base_ch, sep, se_ratio)
     go = gout.reshape(1, n, n, n)
     gd, gtw, gtb = conv3d_backward(cache["d0"], P["tail"]["w"], go)
     Gv["tail"]["w"][...] = gtw
@@ -282,6 +307,12 @@ def backward(gout, theta, cache, n, levels, base_ch, sep=False):
     genc[levels - 1] = gd
     gy = genc[levels - 1]
     for l in range(levels - 1, -1, -1):
+        if se_ratio:  # through the SE unit that follows the block
+            Q, y_in, cse = P["enc%d" % l], cache["se%d" % l][0], cache["se%d" % l][1]
+            gy, gw1, gb1, gw2, gb2 = se.se_backward(y_in, Q["se.w1"], Q["se.w2"], cse, gy)
+            Ge = Gv["enc%d" % l]
+            Ge["se.w1"][...], Ge["se.b1"][...] = gw1, gb1
+            Ge["se.w2"][...], Ge["se.b2"][...] = gw2, gb2
         gx, G = resblock_backward(gy, P["enc%d" % l], cache["enc%d" % l])
         for k, v in G.items():
             Gv["enc%d" % l][k][...] = v

@@ -81,3 +81,61 @@ def test_planted_missing_mean_scale_is_caught():
         gs_over_v = gx - gy * e
         return gy * e + gs_over_v * V, a, b, c, d   # 1/V dropped
     assert not _fd_check(bad)
+
+
+def test_network_with_saturated_gates_equals_plain_network():
+    """SE units whose gates are 1 (w2 = 0, b2 = 40: sigmoid(40) rounds to 1 in
+    FP64) leave the network unchanged: same image, same gradient for every
+    shared parameter, zero gradient for w1 and b1."""
+    from oracle import net
+    rng = np.random.default_rng(3)
+    n, L, C, r = 8, 3, 4, 2
+    th_se = rng.standard_normal(net.n_params(L, C, se_ratio=r)) * 0.3
+    P = net.unpack(th_se, L, C, se_ratio=r)
+    th = np.zeros(net.n_params(L, C))
+    Pp = net.unpack(th, L, C)
+    for mod, d in P.items():
+        for name, v in d.items():
+            if name == "se.w2":
+                v[...] = 0.0
+            elif name == "se.b2":
+                v[...] = 40.0
+            elif not name.startswith("se."):
+                Pp[mod][name][...] = v
+    Z = rng.standard_normal(n ** 3)
+    y_se, c_se = net.forward(th_se, Z, n, L, C, se_ratio=r)
+    y, c = net.forward(th, Z, n, L, C)
+    np.testing.assert_array_equal(y_se, y)
+    g = rng.standard_normal((n, n, n))
+    G_se = net.unpack(net.backward(g, th_se, c_se, n, L, C, se_ratio=r), L, C, se_ratio=r)
+    G = net.unpack(net.backward(g, th, c, n, L, C), L, C)
+    for mod, d in G.items():
+        for name, v in d.items():
+            np.testing.assert_allclose(G_se[mod][name], v, rtol=1e-12, atol=1e-14,
+                                       err_msg=mod + "." + name)
+    for l in range(L):
+        assert not G_se["enc%d" % l]["se.w1"].any() and not G_se["enc%d" % l]["se.b1"].any()
+
+
+def test_network_with_se_units_matches_finite_differences():
+    from oracle import net
+    rng = np.random.default_rng(4)
+    n, L, C, r = 4, 2, 4, 2
+    th = rng.standard_normal(net.n_params(L, C, se_ratio=r)) * 0.3
+    Z = rng.standard_normal(n ** 3)
+    R = rng.standard_normal((n, n, n))
+    y, cache = net.forward(th, Z, n, L, C, se_ratio=r)
+    g = net.backward(R, th, cache, n, L, C, se_ratio=r)
+    f = lambda t: (net.forward(t, Z, n, L, C, se_ratio=r)[0] * R).sum()
+    idx = net.unpack(np.arange(th.size, dtype=np.float64), L, C, se_ratio=r)
+    h = 1e-6
+    for mod, name in (("enc0", "se.w1"), ("enc1", "se.w2"), ("enc1", "se.b1"),
+                      ("enc0", "conv1.w"), (None, None)):
+        v = np.zeros_like(th)
+        if mod is None:
+            v = rng.standard_normal(th.size)
+        else:
+            ii = idx[mod][name].astype(int).ravel()
+            v[ii] = rng.standard_normal(ii.size)
+        fd = (f(th + h * v) - f(th - h * v)) / (2 * h)
+        assert fd == pytest.approx(float(g @ v), rel=1e-6), (mod, name)
