@@ -8,7 +8,8 @@ convolutions of the depthwise-separable convolution and their gradients, the
 Squeeze-and-Excitation unit, the whole-volume LayerNorm + ReLU and its
 backward, J sigma and J^T g).  ``DIPNet``
 composes the prior of Eq. (3) from them (with ``conv="dwsep"`` every ResBlock
-convolution is the depthwise-separable one of Sec. III-D); pooling, up-sampling, channel
+convolution is the depthwise-separable one of Sec. III-D, with ``se_ratio`` an
+SE unit gates every encoder block); pooling, up-sampling, channel
 concatenation and the 1x1x1 output head are plain tensor operations of the
 model around the operators.  With ``recompute=True`` every ResBlock's
 activations are dropped after the forward and recomputed during the backward
@@ -366,13 +367,15 @@ def _measure_fn():
 # the prior of Eq. (3) composed from the operators
 # ----------------------------------------------------------------------------
 
-def param_shapes(levels, base_ch, sep=False):
+def param_shapes(levels, base_ch, sep=False, se_ratio=0):
     """(name, shape) of every parameter tensor in the canonical flat order:
     stem, encoder ResBlocks 0..L-1, decoder ResBlocks L-2..0, head; in a
     module each conv's W [Cout][Cin][k][k][k] then b, each norm gamma then
     beta, in the order conv1, norm1, conv2, norm2, projection.  With sep each
     ResBlock 3x3x3 conv is depthwise-separable (Sec. III-D): depthwise
-    [Cin][3][3][3] and its bias, then pointwise [Cout][Cin] and its bias."""
+    [Cin][3][3][3] and its bias, then pointwise [Cout][Cin] and its bias.
+    With se_ratio r > 0 each encoder module ends with an SE unit's w1 [H][c],
+    b1, w2 [c][H], b2 (H = max(1, c // r))."""
     C = base_ch
     ch = [C << l for l in range(levels)]
     out = [("stem.w", (C, 1, 3, 3, 3)), ("stem.b", (C,)), ("stem.g", (C,)), ("stem.beta", (C,))]
@@ -390,9 +393,16 @@ def param_shapes(levels, base_ch, sep=False):
             s += [(name + ".wp", (b, a, 1, 1, 1)), (name + ".bp", (b,))]
         return s
 
-    out += block("enc0", C, C)
+    def se_unit(name, c):
+        if not se_ratio:
+            return []
+        h = max(1, c // se_ratio)
+        return [(name + ".sw1", (h, c)), (name + ".sb1", (h,)), (name + ".sw2", (c, h)),
+                (name + ".sb2", (c,))]
+
+    out += block("enc0", C, C) + se_unit("enc0", C)
     for l in range(1, levels):
-        out += block("enc%d" % l, ch[l - 1], ch[l])
+        out += block("enc%d" % l, ch[l - 1], ch[l]) + se_unit("enc%d" % l, ch[l])
     for l in range(levels - 2, -1, -1):
         out += block("dec%d" % l, ch[l + 1] + ch[l], ch[l])
     out += [("head.w", (1, C, 1, 1, 1)), ("head.b", (1,))]
@@ -414,14 +424,16 @@ class DIPNet:
     """sigma = mask * phi(theta | Z) built from the operators; theta is one
     flat tensor in the canonical order (gradients flow to it through views)."""
 
-    def __init__(self, n, levels, base_ch, precision="fp32", recompute=False, conv="dense"):
+    def __init__(self, n, levels, base_ch, precision="fp32", recompute=False, conv="dense",
+                 se_ratio=0):
         if conv not in ("dense", "dwsep"):
             raise ValueError("conv must be 'dense' or 'dwsep'")
         self.n, self.L, self.C = n, levels, base_ch
         self.precision = precision
         self.recompute = recompute
         self.sep = conv == "dwsep"  # depthwise-separable ResBlock convs (FP32)
-        self.shapes = param_shapes(levels, base_ch, self.sep)
+        self.se_ratio = se_ratio    # SE units gating the encoder blocks (0: none)
+        self.shapes = param_shapes(levels, base_ch, self.sep, se_ratio)
         self.size = int(sum(np.prod(s) for _, s in self.shapes))
 
     def views(self, theta):
@@ -470,6 +482,9 @@ class DIPNet:
             if l > 0:
                 x = _pool(x, nl * 2)
             x = self._run_block(P, "enc%d" % l, x, nl)
+            if self.se_ratio:
+                e = "enc%d" % l
+                x = SEFn.apply(x, P[e + ".sw1"], P[e + ".sb1"], P[e + ".sw2"], P[e + ".sb2"])
             skips.append(x)
         for l in range(L - 2, -1, -1):
             nl = n >> l

@@ -222,6 +222,6 @@ def test_separable_network_gradient_matches_oracle(lib, shape):
     torch.cuda.synchronize()
     pr = fit.Problem(p["J"], p["mask"], p["Z"], n, L, C, sep=True)
     L0, gref, _ = pr.loss_and_grad(th.astype(np.float64), p["dv"][0].astype(np.float64))
-    e = dict(loss=abs(float(loss) - L0) / L0, grad=rel(host(T.grad), gref))
+    e = dict(loss=abs(float(loss.detach()) - L0) / L0, grad=rel(host(T.grad), gref))
     record("dwsep_network", n=n, levels=L, C=C, **e)
     assert e["loss"] < 1e-5 and e["grad"] < 2e-4, e

@@ -59,3 +59,31 @@ def test_se_matches_oracle(lib, n, C, H):
     record("se", n=n, C=C, H=H, **e)
     assert e["y"] < TOL_Y and e["gx"] < TOL_Y, e
     assert max(e["gw1"], e["gb1"], e["gw2"], e["gb2"]) < TOL_W, e
+
+
+@pytest.mark.parametrize("shape,sep", [((8, 1, 2, 8), False), ((16, 2, 3, 16), False),
+                                       ((16, 2, 3, 16), True)])
+def test_network_with_se_units_matches_oracle(lib, shape, sep):
+    """The autograd network with an SE unit after every encoder block (and
+    dense or depthwise-separable convs): loss and theta gradient against the
+    FP64 oracle network of the same layout."""
+    import torch
+    from oracle import fit, net
+    from paper_2507_14046_amd import ops
+    from tests.gpu_util import problem
+    n, rings, L, C = shape
+    r = 4
+    p = problem(n, rings, L, C, 80 + n + L)
+    rng = np.random.default_rng(81 + n + sep)
+    th = (0.3 * rng.standard_normal(net.n_params(L, C, sep, r))).astype(np.float32)
+    model = ops.DIPNet(n, L, C, conv="dwsep" if sep else "dense", se_ratio=r)
+    T = dev(th, True)
+    loss = model.loss(T, dev(p["Z"]), dev(p["mask"].astype(np.float32)), dev(p["J"]),
+                      dev(p["dv"][0]))
+    loss.backward()
+    torch.cuda.synchronize()
+    pr = fit.Problem(p["J"], p["mask"], p["Z"], n, L, C, sep=sep, se_ratio=r)
+    L0, gref, _ = pr.loss_and_grad(th.astype(np.float64), p["dv"][0].astype(np.float64))
+    e = dict(loss=abs(float(loss.detach()) - L0) / L0, grad=rel(host(T.grad), gref))
+    record("se_network", n=n, levels=L, C=C, sep=sep, **e)
+    assert e["loss"] < 1e-5 and e["grad"] < 2e-4, e
