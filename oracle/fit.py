@@ -49,17 +49,19 @@ def adam_step(theta, g, m, v, t, lr, b1=ADAM_BETA1, b2=ADAM_BETA2, eps=ADAM_EPS)
 class Problem:
     """Inputs of one instance promoted to FP64."""
 
-    def __init__(self, J, mask, Z, n, levels, base_ch, sep=False, se_ratio=0):
+    def __init__(self, J, mask, Z, n, levels, base_ch, sep=False, se_ratio=0, att=False,
+                 tail="linear"):
         self.J = np.asarray(J, dtype=np.float64)
         self.mask = np.asarray(mask, dtype=np.float64)
         self.Z = np.asarray(Z, dtype=np.float64)
         self.n, self.levels, self.base_ch = n, levels, base_ch
         self.sep = sep  # depthwise-separable ResBlock convolutions
         self.se_ratio = se_ratio  # SE units after the encoder blocks (0: none)
+        self.att, self.tail = att, tail  # attention units on the skips; output head
 
     def image(self, theta):
         out, _ = net.forward(theta, self.Z, self.n, self.levels, self.base_ch, self.sep,
-                                 self.se_ratio)
+                                 self.se_ratio, self.att, self.tail)
         return self.mask * out.ravel()
 
     def loss_and_grad(self, theta, dv, tv=None):
@@ -67,7 +69,7 @@ class Problem:
         the 4D-TV term when tv = dict(history=[images], weights=[...],
         lam=, lam_s=, lam_t=, eps=) is given (Eq. (14))."""
         out, cache = net.forward(theta, self.Z, self.n, self.levels, self.base_ch, self.sep,
-                                 self.se_ratio)
+                                 self.se_ratio, self.att, self.tail)
         sigma = self.mask * out.ravel()
         L, gs = data_loss(self.J, dv, sigma)
         if tv is not None:
@@ -79,7 +81,7 @@ class Problem:
             gs = gs + gt.ravel()
         gout = (self.mask * gs).reshape(self.n, self.n, self.n)
         g = net.backward(gout, theta, cache, self.n, self.levels, self.base_ch, self.sep,
-                         self.se_ratio)
+                         self.se_ratio, self.att, self.tail)
         return L, g, sigma
 
 

@@ -24,7 +24,11 @@ the lightweight backbone (Sec. III-D; oracle/dwsep.py): a per-channel 3x3x3
 convolution with a bias, then a 1x1x1 convolution with a bias.  With
 se_ratio = r > 0 a Squeeze-and-Excitation unit (Sec. III-D; oracle/se.py) of
 hidden width c // r gates the output of every encoder block (enc_l above
-stands for the gated output wherever it is used).
+stands for the gated output wherever it is used).  With att=True an additive
+attention unit (att_forward) gates each decoder skip enc_l by the up-sampled
+dec_{l+1} before the concatenation; with tail="sigmoid" the image is
+2 sigmoid(conv1(dec_0)) - 1 (the paper's sigmoid tail, shifted and scaled so
+that negative changes are representable).
 
 Conventions: arrays are channel-first [C, n, n, n] in (z, y, x) order; conv3
 is a 3x3x3 cross-correlation with zero padding 1; LN normalises over all of
@@ -77,12 +81,21 @@ def _se_shapes(c, se_ratio):
     return [("se.w1", (h, c)), ("se.b1", (h,)), ("se.w2", (c, h)), ("se.b2", (c,))]
 
 
-def module_list(levels, base_ch, sep=False, se_ratio=0):
+def _att_shapes(c, c_up, att):
+    if not att:
+        return []
+    return [("att.wx", (c, c)), ("att.wg", (c, c_up)), ("att.b", (c,)), ("att.psi", (c,)),
+            ("att.bpsi", (1,))]
+
+
+def module_list(levels, base_ch, sep=False, se_ratio=0, att=False, tail="linear"):
     """[(module name, [(param name, shape)])] in flat order.  With sep every
     ResBlock convolution is depthwise-separable; the stem (one input channel)
     and the 1x1x1 projections and tail stay dense.  With se_ratio r > 0 every
     encoder ResBlock is followed by a Squeeze-and-Excitation unit of hidden
-    width c // r (its parameters end the encoder module)."""
+    width c // r (its parameters end the encoder module).  With att every
+    decoder module ends with an attention unit on its skip input (wx [c][c],
+    wg [c][c_up], b [c], psi [c], bpsi [1]).  `tail` changes no parameter."""
     ch = [base_ch * 2 ** l for l in range(levels)]
     mods = [("stem", [("conv.w", (base_ch, 1, 3, 3, 3)), ("conv.b", (base_ch,)),
                       ("norm.g", (base_ch,)), ("norm.beta", (base_ch,))])]
@@ -91,20 +104,21 @@ def module_list(levels, base_ch, sep=False, se_ratio=0):
         mods.append(("enc%d" % l, _block_shapes(ch[l - 1], ch[l], sep) +
                      _se_shapes(ch[l], se_ratio)))
     for l in range(levels - 2, -1, -1):
-        mods.append(("dec%d" % l, _block_shapes(ch[l + 1] + ch[l], ch[l], sep)))
+        mods.append(("dec%d" % l, _block_shapes(ch[l + 1] + ch[l], ch[l], sep) +
+                     _att_shapes(ch[l], ch[l + 1], att)))
     mods.append(("tail", [("w", (1, base_ch, 1, 1, 1)), ("b", (1,))]))
     return mods
 
 
-def n_params(levels, base_ch, sep=False, se_ratio=0):
-    return sum(int(np.prod(s)) for _, ps in module_list(levels, base_ch, sep, se_ratio)
+def n_params(levels, base_ch, sep=False, se_ratio=0, att=False):
+    return sum(int(np.prod(s)) for _, ps in module_list(levels, base_ch, sep, se_ratio, att)
                for _, s in ps)
 
 
-def unpack(theta, levels, base_ch, sep=False, se_ratio=0):
+def unpack(theta, levels, base_ch, sep=False, se_ratio=0, att=False):
     """Flat theta -> {module: {param: view}} (views into theta)."""
     out, off = {}, 0
-    for mod, ps in module_list(levels, base_ch, sep, se_ratio):
+    for mod, ps in module_list(levels, base_ch, sep, se_ratio, att):
         d = {}
         for name, shape in ps:
             k = int(np.prod(shape))
@@ -254,11 +268,40 @@ def resblock_backward(gy, P, cache):
     return gx, G
 
 
-def forward(theta, Z, n, levels, base_ch, sep=False, se_ratio=0):
+def att_forward(x, g, Q):
+    """Additive attention unit on a decoder skip (Sec. III-D): x [c, ...] the
+    skip, g [c_up, ...] the up-sampled coarser decoder output (the gating
+    signal); a = wx x + wg g + b, q = relu(a), alpha = sigmoid(psi . q + bpsi)
+    (one gate per voxel), output alpha * x."""
+    c = x.shape[0]
+    shp = x.shape[1:]
+    X, G = x.reshape(c, -1), g.reshape(g.shape[0], -1)
+    a = Q["att.wx"] @ X + Q["att.wg"] @ G + Q["att.b"][:, None]
+    q = np.maximum(a, 0.0)
+    al = 1.0 / (1.0 + np.exp(-(Q["att.psi"] @ q + Q["att.bpsi"][0])))
+    return (al[None, :] * X).reshape((c,) + shp), dict(X=X, G=G, a=a, q=q, al=al)
+
+
+def att_backward(gout, Q, c):
+    """(gx, gg, {param grads}) of att_forward given gout = dL/d(output)."""
+    X, G, a, q, al = c["X"], c["G"], c["a"], c["q"], c["al"]
+    go = gout.reshape(X.shape)
+    gal = (go * X).sum(axis=0)                  # dL/dalpha per voxel
+    gt = gal * al * (1.0 - al)                  # through the sigmoid
+    gq = np.outer(Q["att.psi"], gt)
+    ga = gq * (a > 0)                           # through the ReLU
+    grads = {"att.wx": ga @ X.T, "att.wg": ga @ G.T, "att.b": ga.sum(axis=1),
+             "att.psi": q @ gt, "att.bpsi": np.array([gt.sum()])}
+    gx = (al[None, :] * go + Q["att.wx"].T @ ga).reshape(gout.shape)
+    gg = (Q["att.wg"].T @ ga).reshape((G.shape[0],) + gout.shape[1:])
+    return gx, gg, grads
+
+
+def forward(theta, Z, n, levels, base_ch, sep=False, se_ratio=0, att=False, tail="linear"):
     """phi(theta | Z) before masking, as an (n, n, n) array, plus the cache
     (sep: depthwise-separable ResBlock convolutions; se_ratio: SE units after
     the encoder blocks; see module_list)."""
-    P = unpack(theta, levels, base_ch, sep, se_ratio)
+    P = unpack(theta, levels, base_ch, sep, se_ratio, att)
     z = Z.reshape(1, n, n, n)
     hs = conv3d(z, P["stem"]["conv.w"], P["stem"]["conv.b"])
     ns, cs = layer_norm(hs, P["stem"]["norm.g"], P["stem"]["norm.beta"])
@@ -278,19 +321,33 @@ def forward(theta, Z, n, levels, base_ch, sep=False, se_ratio=0):
         enc.append(y)
     d = enc[-1]
     for l in range(levels - 2, -1, -1):
-        x = np.concatenate([up2(d), enc[l]], axis=0)
+        u = up2(d)
+        skip = enc[l]
+        if att:
+            skip, cache["att%d" % l] = att_forward(skip, u, P["dec%d" % l])
+        x = np.concatenate([u, skip], axis=0)
         d, cache["dec%d" % l] = resblock_forward(x, P["dec%d" % l])
     out = conv3d(d, P["tail"]["w"], P["tail"]["b"])
     cache["d0"] = d
+    if tail == "sigmoid":
+        # the sigmoid tail, shifted and scaled to (-1, 1) so that the negative
+        # conductivity changes stay representable: 2 sigmoid(t) - 1
+        sg = 1.0 / (1.0 + np.exp(-out))
+        cache["tail_sg"] = sg
+        out = 2.0 * sg - 1.0
     return out[0], cache
 
 
-def backward(gout, theta, cache, n, levels, base_ch, sep=False, se_ratio=0):
+def backward(gout, theta, cache, n, levels, base_ch, sep=False, se_ratio=0, att=False,
+             tail="linear"):
     """d(loss)/d(theta) as a flat array, given gout = d(loss)/d(phi) (n, n, n)."""
-    P = unpack(theta, levels, base_ch, sep, se_ratio)
+    P = unpack(theta, levels, base_ch, sep, se_ratio, att)
     grad = np.zeros(theta.size, dtype=np.float64)
-    Gv = unpack(grad, levels, base_ch, sep, se_ratio)
+    Gv = unpack(grad, levels, base_ch, sep, se_ratio, att)
     go = gout.reshape(1, n, n, n)
+    if tail == "sigmoid":
+        sg = cache["tail_sg"]
+        go = go * 2.0 * sg * (1.0 - sg)
     gd, gtw, gtb = conv3d_backward(cache["d0"], P["tail"]["w"], go)
     Gv["tail"]["w"][...] = gtw
     Gv["tail"]["b"][...] = gtb
@@ -301,8 +358,15 @@ def backward(gout, theta, cache, n, levels, base_ch, sep=False, se_ratio=0):
         for k, v in G.items():
             Gv["dec%d" % l][k][...] = v
         c_up = base_ch * 2 ** (l + 1)
-        gd = up2_backward(gx[:c_up])          # to dec_{l+1} (or enc_{L-1})
-        genc[l] = gx[c_up:]                    # skip contribution to enc_l
+        gu = gx[:c_up]
+        gskip = gx[c_up:]
+        if att:  # the skip passed through the attention unit, gated by u
+            gskip, gg, Ga = att_backward(gskip, P["dec%d" % l], cache["att%d" % l])
+            for k, v in Ga.items():
+                Gv["dec%d" % l][k][...] = v
+            gu = gu + gg
+        gd = up2_backward(gu)                  # to dec_{l+1} (or enc_{L-1})
+        genc[l] = gskip                        # skip contribution to enc_l
     # encoder, from the bottleneck down; gd is d(loss)/d(enc_{L-1} output)
     genc[levels - 1] = gd
     gy = genc[levels - 1]
