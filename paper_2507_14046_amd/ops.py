@@ -9,7 +9,8 @@ Squeeze-and-Excitation unit, the whole-volume LayerNorm + ReLU and its
 backward, J sigma and J^T g).  ``DIPNet``
 composes the prior of Eq. (3) from them (with ``conv="dwsep"`` every ResBlock
 convolution is the depthwise-separable one of Sec. III-D, with ``se_ratio`` an
-SE unit gates every encoder block); pooling, up-sampling, channel
+SE unit gates every encoder block, with ``att`` an attention unit gates every
+decoder skip, and ``tail="sigmoid"`` gives the image 2 sigmoid(t) - 1); pooling, up-sampling, channel
 concatenation and the 1x1x1 output head are plain tensor operations of the
 model around the operators.  With ``recompute=True`` every ResBlock's
 activations are dropped after the forward and recomputed during the backward
@@ -37,6 +38,15 @@ def _p(t):
 
 def _stream(t):
     return ctypes.c_void_p(_torch().cuda.current_stream(t.device).cuda_stream)
+
+
+def _a16(t):
+    """t contiguous and 16-byte aligned (the float4 kernels' requirement):
+    views into a flat parameter vector can start anywhere, so copy those."""
+    if t is None:
+        return None
+    t = t.contiguous()
+    return t if t.data_ptr() % 16 == 0 else t.clone()
 
 
 def _workspace(fn, *args, device):
@@ -144,7 +154,7 @@ def _conv_fn():
             lib = L.load()
             x, w = ctx.saved_tensors
             n, cin, cout, taps, prec, has_b = ctx.meta
-            gy = gy.contiguous()
+            gy = _a16(gy)
             need_x, need_w, need_b = ctx.needs_input_grad[:3]
             gx = torch.empty_like(x) if need_x else None
             gw = torch.empty_like(w) if need_w else None
@@ -169,8 +179,7 @@ def _dw_fn():
         @staticmethod
         def forward(ctx, x, w, b):
             lib = L.load()
-            x, w = x.contiguous(), w.contiguous()
-            b = b.contiguous() if b is not None else None
+            x, w, b = _a16(x), w.contiguous(), _a16(b)
             V, C = x.shape
             if w.numel() != 27 * C:
                 raise ValueError("w must hold C x 27 taps")
@@ -186,7 +195,7 @@ def _dw_fn():
             lib = L.load()
             x, w = ctx.saved_tensors
             n, C, has_b = ctx.meta
-            gy = gy.contiguous()
+            gy = _a16(gy)
             need_x, need_w, need_b = ctx.needs_input_grad[:3]
             gx = torch.empty_like(x) if need_x else None
             gw = torch.empty_like(w) if need_w else None
@@ -212,7 +221,7 @@ def _pw_fn():
         @staticmethod
         def forward(ctx, x, w, b):
             lib = L.load()
-            x, w = x.contiguous(), w.contiguous()
+            x, w = _a16(x), _a16(w)
             b = b.contiguous() if b is not None else None
             V, cin = x.shape
             cout = w.shape[0]
@@ -231,7 +240,7 @@ def _pw_fn():
             lib = L.load()
             x, w = ctx.saved_tensors
             n, cin, cout, has_b = ctx.meta
-            gy = gy.contiguous()
+            gy = _a16(gy)
             need_x, need_w, need_b = ctx.needs_input_grad[:3]
             gx = torch.empty_like(x) if need_x else None
             gw = torch.empty_like(w) if need_w else None
@@ -257,7 +266,8 @@ def _se_fn():
         @staticmethod
         def forward(ctx, x, w1, b1, w2, b2):
             lib = L.load()
-            x, w1, b1, w2, b2 = (t.contiguous() for t in (x, w1, b1, w2, b2))
+            x = _a16(x)
+            w1, b1, w2, b2 = (t.contiguous() for t in (w1, b1, w2, b2))
             V, C = x.shape
             H = w1.shape[0]
             n = _grid_n(V)
@@ -274,7 +284,7 @@ def _se_fn():
             lib = L.load()
             x, w1, b1, w2, b2 = ctx.saved_tensors
             n, C, H = ctx.meta
-            gy = gy.contiguous()
+            gy = _a16(gy)
             need = ctx.needs_input_grad[:5]
             outs = [torch.empty_like(t) if nd else None
                     for t, nd in zip((x, w1, b1, w2, b2), need)]
@@ -315,7 +325,7 @@ def _ln_fn():
             lib = L.load()
             x, y, gamma = ctx.saved_tensors
             n, C, has_skip = ctx.meta
-            gy = gy.contiguous()
+            gy = _a16(gy)
             gx = torch.empty_like(x) if ctx.needs_input_grad[0] else None
             gskip = torch.empty_like(x) if (has_skip and ctx.needs_input_grad[3]) else None
             need_gb = ctx.needs_input_grad[1] or ctx.needs_input_grad[2]
@@ -367,7 +377,7 @@ def _measure_fn():
 # the prior of Eq. (3) composed from the operators
 # ----------------------------------------------------------------------------
 
-def param_shapes(levels, base_ch, sep=False, se_ratio=0):
+def param_shapes(levels, base_ch, sep=False, se_ratio=0, att=False):
     """(name, shape) of every parameter tensor in the canonical flat order:
     stem, encoder ResBlocks 0..L-1, decoder ResBlocks L-2..0, head; in a
     module each conv's W [Cout][Cin][k][k][k] then b, each norm gamma then
@@ -375,7 +385,8 @@ def param_shapes(levels, base_ch, sep=False, se_ratio=0):
     ResBlock 3x3x3 conv is depthwise-separable (Sec. III-D): depthwise
     [Cin][3][3][3] and its bias, then pointwise [Cout][Cin] and its bias.
     With se_ratio r > 0 each encoder module ends with an SE unit's w1 [H][c],
-    b1, w2 [c][H], b2 (H = max(1, c // r))."""
+    b1, w2 [c][H], b2 (H = max(1, c // r)); with att each decoder module ends
+    with an attention unit's wx [c][c], wg [c][c_up], b [c], psi [c], bpsi [1]."""
     C = base_ch
     ch = [C << l for l in range(levels)]
     out = [("stem.w", (C, 1, 3, 3, 3)), ("stem.b", (C,)), ("stem.g", (C,)), ("stem.beta", (C,))]
@@ -403,8 +414,15 @@ def param_shapes(levels, base_ch, sep=False, se_ratio=0):
     out += block("enc0", C, C) + se_unit("enc0", C)
     for l in range(1, levels):
         out += block("enc%d" % l, ch[l - 1], ch[l]) + se_unit("enc%d" % l, ch[l])
+    def att_unit(name, c, c_up):
+        if not att:
+            return []
+        return [(name + ".awx", (c, c)), (name + ".awg", (c, c_up)), (name + ".ab", (c,)),
+                (name + ".apsi", (c,)), (name + ".abpsi", (1,))]
+
     for l in range(levels - 2, -1, -1):
-        out += block("dec%d" % l, ch[l + 1] + ch[l], ch[l])
+        out += block("dec%d" % l, ch[l + 1] + ch[l], ch[l]) + att_unit("dec%d" % l, ch[l],
+                                                                       ch[l + 1])
     out += [("head.w", (1, C, 1, 1, 1)), ("head.b", (1,))]
     return out
 
@@ -425,15 +443,18 @@ class DIPNet:
     flat tensor in the canonical order (gradients flow to it through views)."""
 
     def __init__(self, n, levels, base_ch, precision="fp32", recompute=False, conv="dense",
-                 se_ratio=0):
+                 se_ratio=0, att=False, tail="linear"):
         if conv not in ("dense", "dwsep"):
             raise ValueError("conv must be 'dense' or 'dwsep'")
+        if tail not in ("linear", "sigmoid"):
+            raise ValueError("tail must be 'linear' or 'sigmoid'")
+        self.att, self.tail = att, tail  # attention units on the skips; output head
         self.n, self.L, self.C = n, levels, base_ch
         self.precision = precision
         self.recompute = recompute
         self.sep = conv == "dwsep"  # depthwise-separable ResBlock convs (FP32)
         self.se_ratio = se_ratio    # SE units gating the encoder blocks (0: none)
-        self.shapes = param_shapes(levels, base_ch, self.sep, se_ratio)
+        self.shapes = param_shapes(levels, base_ch, self.sep, se_ratio, att)
         self.size = int(sum(np.prod(s) for _, s in self.shapes))
 
     def views(self, theta):
@@ -488,10 +509,26 @@ class DIPNet:
             skips.append(x)
         for l in range(L - 2, -1, -1):
             nl = n >> l
-            x = torch.cat([_up(x, nl // 2), skips[l]], dim=1)
+            u = _up(x, nl // 2)
+            s = skips[l]
+            if self.att:
+                s = self._attend(P, "dec%d" % l, s, u)
+            x = torch.cat([u, s], dim=1)
             x = self._run_block(P, "dec%d" % l, x, nl)
         out = x @ P["head.w"].view(1, self.C).t() + P["head.b"]
+        if self.tail == "sigmoid":
+            out = 2.0 * torch.sigmoid(out) - 1.0
         return out.view(-1) * mask
+
+    def _attend(self, P, d, s, u):
+        """Additive attention unit: the skip s gated per voxel by
+        sigmoid(psi . relu(wx s + wg u + b) + bpsi), u the up-sampled coarser
+        decoder output; the two 1x1x1 convs run on the pointwise GEMM."""
+        torch = _torch()
+        a = PWConv3dFn.apply(s, P[d + ".awx"], P[d + ".ab"]) + PWConv3dFn.apply(
+            u, P[d + ".awg"], None)
+        gate = torch.sigmoid(torch.relu(a) @ P[d + ".apsi"] + P[d + ".abpsi"])
+        return s * gate[:, None]
 
     def loss(self, theta, Z, mask, J, dv):
         """(1/M) sum (J sigma - dv)^2, with J sigma and J^T on the library's kernels."""

@@ -212,13 +212,27 @@ def test_stored_tuning_table_plans_every_workload(L):
 @pytest.mark.parametrize("L_,C", [(2, 8), (3, 16), (4, 32)])
 @pytest.mark.parametrize("sep", [False, True])
 @pytest.mark.parametrize("r", [0, 4, 64])
-def test_operator_network_layout_matches_oracle(L, L_, C, sep, r):
+@pytest.mark.parametrize("att", [False, True])
+def test_operator_network_layout_matches_oracle(L, L_, C, sep, r, att):
     """The autograd network's flat parameter order (dense or depthwise-separable
     ResBlock convs, with or without SE units) is the oracle's, tensor by
     tensor."""
     import numpy as np
     from oracle import net
     from paper_2507_14046_amd import ops
-    mine = [int(np.prod(s)) for _, s in ops.param_shapes(L_, C, sep, r)]
-    ref = [int(np.prod(s)) for _, ps in net.module_list(L_, C, sep, r) for _, s in ps]
+    mine = [int(np.prod(s)) for _, s in ops.param_shapes(L_, C, sep, r, att)]
+    ref = [int(np.prod(s)) for _, ps in net.module_list(L_, C, sep, r, att) for _, s in ps]
     assert mine == ref
+
+
+def test_misaligned_parameter_views_are_copied_for_the_float4_kernels(L):
+    """Views into a flat parameter vector can start off a 16-byte boundary;
+    the autograd wrappers hand the float4 kernels aligned copies of those."""
+    import torch
+    from paper_2507_14046_amd import ops
+    flat = torch.zeros(1001)
+    for off in range(4):
+        v = flat[off + 1:off + 1 + 64].view(8, 8)
+        a = ops._a16(v)
+        assert a.data_ptr() % 16 == 0 and torch.equal(a, v)
+    assert ops._a16(None) is None
