@@ -16,32 +16,36 @@ with zeros outside the grid (the cross-correlation and padding convention of
 import numpy as np
 
 
-def dwconv3d(x, w, b):
-    """Depthwise 3x3x3 convolution: x [C, n, n, n], w [C, 3, 3, 3], b [C]."""
-    n = x.shape[1]
-    xp = np.pad(x, ((0, 0), (1, 1), (1, 1), (1, 1)))
+def dwconv3d(x, w, b, dil=1):
+    """Depthwise 3x3x3 convolution: x [C, n, n, n], w [C, 3, 3, 3], b [C]; with
+    dil > 1 the taps sit dil voxels apart (atrous convolution, as in the ASPP
+    branches): out[c, v] = b[c] + sum_t w[c, t] x[c, v + dil (t - 1)]."""
+    n, d = x.shape[1], dil
+    xp = np.pad(x, ((0, 0), (d, d), (d, d), (d, d)))
     out = np.broadcast_to(b[:, None, None, None], x.shape).astype(np.float64).copy()
     for dz in range(3):
         for dy in range(3):
             for dx in range(3):
-                out += w[:, dz, dy, dx, None, None, None] * xp[:, dz:dz + n, dy:dy + n, dx:dx + n]
+                oz, oy, ox = dz * d, dy * d, dx * d
+                out += w[:, dz, dy, dx, None, None, None] * xp[:, oz:oz + n, oy:oy + n, ox:ox + n]
     return out
 
 
-def dwconv3d_backward(x, w, gout):
+def dwconv3d_backward(x, w, gout, dil=1):
     """(gx, gw, gb) of dwconv3d given gout = dL/dout."""
-    n = x.shape[1]
-    xp = np.pad(x, ((0, 0), (1, 1), (1, 1), (1, 1)))
+    n, d = x.shape[1], dil
+    xp = np.pad(x, ((0, 0), (d, d), (d, d), (d, d)))
     gxp = np.zeros_like(xp)
     gw = np.zeros_like(w, dtype=np.float64)
     for dz in range(3):
         for dy in range(3):
             for dx in range(3):
-                win = xp[:, dz:dz + n, dy:dy + n, dx:dx + n]
+                oz, oy, ox = dz * d, dy * d, dx * d
+                win = xp[:, oz:oz + n, oy:oy + n, ox:ox + n]
                 gw[:, dz, dy, dx] = (gout * win).sum(axis=(1, 2, 3))
-                gxp[:, dz:dz + n, dy:dy + n, dx:dx + n] += w[:, dz, dy, dx, None, None, None] * gout
+                gxp[:, oz:oz + n, oy:oy + n, ox:ox + n] += w[:, dz, dy, dx, None, None, None] * gout
     gb = gout.sum(axis=(1, 2, 3))
-    return gxp[:, 1:n + 1, 1:n + 1, 1:n + 1], gw, gb
+    return gxp[:, d:n + d, d:n + d, d:n + d], gw, gb
 
 
 def pwconv3d(x, w, b):

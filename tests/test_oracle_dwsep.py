@@ -180,3 +180,31 @@ def test_separable_network_gradient_matches_finite_differences():
             v[idx] = rng.standard_normal(idx.size)
         fd = (f(th + h * v) - f(th - h * v)) / (2 * h)
         assert fd == pytest.approx(float(g @ v), rel=1e-6), (mod, name)
+
+
+@pytest.mark.parametrize("dil", [2, 3])
+def test_dilated_depthwise_matches_torch_and_autograd(dil):
+    rng = np.random.default_rng(20 + dil)
+    x, wd, bd, _, _ = _rand(rng, C=4, n=7)
+    C = x.shape[0]
+    xt = torch.tensor(x, requires_grad=True)
+    wt = torch.tensor(wd[:, None], requires_grad=True)
+    bt = torch.tensor(bd, requires_grad=True)
+    yt = F.conv3d(xt[None], wt, bt, padding=dil, dilation=dil, groups=C)[0]
+    np.testing.assert_allclose(dwsep.dwconv3d(x, wd, bd, dil), yt.detach().numpy(),
+                               rtol=1e-11, atol=1e-11)
+    g = rng.standard_normal(x.shape)
+    (yt * torch.tensor(g)).sum().backward()
+    gx, gw, gb = dwsep.dwconv3d_backward(x, wd, g, dil)
+    np.testing.assert_allclose(gx, xt.grad.numpy(), rtol=1e-11, atol=1e-11)
+    np.testing.assert_allclose(gw, wt.grad.numpy()[:, 0], rtol=1e-11, atol=1e-11)
+    np.testing.assert_allclose(gb, bt.grad.numpy(), rtol=1e-11, atol=1e-11)
+
+
+def test_dilation_beyond_the_grid_leaves_only_the_centre_tap():
+    """With dil >= n every off-centre tap falls outside the grid."""
+    rng = np.random.default_rng(23)
+    x, wd, bd, _, _ = _rand(rng, C=4, n=3)
+    y = dwsep.dwconv3d(x, wd, bd, dil=3)
+    np.testing.assert_allclose(y, bd[:, None, None, None] + wd[:, 1, 1, 1, None, None, None] * x,
+                               rtol=1e-14, atol=1e-14)
