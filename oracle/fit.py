@@ -50,7 +50,7 @@ class Problem:
     """Inputs of one instance promoted to FP64."""
 
     def __init__(self, J, mask, Z, n, levels, base_ch, sep=False, se_ratio=0, att=False,
-                 tail="linear"):
+                 tail="linear", aspp=False):
         self.J = np.asarray(J, dtype=np.float64)
         self.mask = np.asarray(mask, dtype=np.float64)
         self.Z = np.asarray(Z, dtype=np.float64)
@@ -58,10 +58,11 @@ class Problem:
         self.sep = sep  # depthwise-separable ResBlock convolutions
         self.se_ratio = se_ratio  # SE units after the encoder blocks (0: none)
         self.att, self.tail = att, tail  # attention units on the skips; output head
+        self.aspp = aspp  # ASPP module at the bottleneck
 
     def image(self, theta):
         out, _ = net.forward(theta, self.Z, self.n, self.levels, self.base_ch, self.sep,
-                                 self.se_ratio, self.att, self.tail)
+                                 self.se_ratio, self.att, self.tail, self.aspp)
         return self.mask * out.ravel()
 
     def loss_and_grad(self, theta, dv, tv=None):
@@ -69,7 +70,7 @@ class Problem:
         the 4D-TV term when tv = dict(history=[images], weights=[...],
         lam=, lam_s=, lam_t=, eps=) is given (Eq. (14))."""
         out, cache = net.forward(theta, self.Z, self.n, self.levels, self.base_ch, self.sep,
-                                 self.se_ratio, self.att, self.tail)
+                                 self.se_ratio, self.att, self.tail, self.aspp)
         sigma = self.mask * out.ravel()
         L, gs = data_loss(self.J, dv, sigma)
         if tv is not None:
@@ -81,7 +82,7 @@ class Problem:
             gs = gs + gt.ravel()
         gout = (self.mask * gs).reshape(self.n, self.n, self.n)
         g = net.backward(gout, theta, cache, self.n, self.levels, self.base_ch, self.sep,
-                         self.se_ratio, self.att, self.tail)
+                         self.se_ratio, self.att, self.tail, self.aspp)
         return L, g, sigma
 
 

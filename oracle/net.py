@@ -28,7 +28,8 @@ stands for the gated output wherever it is used).  With att=True an additive
 attention unit (att_forward) gates each decoder skip enc_l by the up-sampled
 dec_{l+1} before the concatenation; with tail="sigmoid" the image is
 2 sigmoid(conv1(dec_0)) - 1 (the paper's sigmoid tail, shifted and scaled so
-that negative changes are representable).
+that negative changes are representable); with aspp=True the ASPP module
+(aspp_forward) transforms the bottleneck enc_{L-1} before the decoder.
 
 Conventions: arrays are channel-first [C, n, n, n] in (z, y, x) order; conv3
 is a 3x3x3 cross-correlation with zero padding 1; LN normalises over all of
@@ -88,14 +89,56 @@ def _att_shapes(c, c_up, att):
             ("att.bpsi", (1,))]
 
 
-def module_list(levels, base_ch, sep=False, se_ratio=0, att=False, tail="linear"):
+ASPP_RATES = (1, 2, 3)  # dilations of the atrous branches at the bottleneck
+
+
+def _aspp_shapes(c):
+    shapes = [("w0", (c, c)), ("b0", (c,))]
+    for d in ASPP_RATES:
+        shapes += [("dw%d" % d, (c, 3, 3, 3)), ("dwb%d" % d, (c,)), ("pw%d" % d, (c, c)),
+                   ("pwb%d" % d, (c,))]
+    return shapes + [("wp", (c, c * (1 + len(ASPP_RATES)))), ("bp", (c,))]
+
+
+def aspp_forward(x, Q):
+    """ASPP at the bottleneck (Sec. III-D): a 1x1x1 branch and one
+    depthwise-separable atrous branch per rate in ASPP_RATES, concatenated,
+    projected by a 1x1x1 conv and passed through a ReLU."""
+    br = [dwsep.pwconv3d(x, Q["w0"], Q["b0"])]
+    ds = []
+    for d in ASPP_RATES:
+        dd = dwsep.dwconv3d(x, Q["dw%d" % d], Q["dwb%d" % d], d)
+        ds.append(dd)
+        br.append(dwsep.pwconv3d(dd, Q["pw%d" % d], Q["pwb%d" % d]))
+    cat = np.concatenate(br, axis=0)
+    y = relu(dwsep.pwconv3d(cat, Q["wp"], Q["bp"]))
+    return y, dict(x=x, ds=ds, cat=cat, y=y)
+
+
+def aspp_backward(gy, Q, c):
+    """(gx, {param grads}) of aspp_forward."""
+    G = {}
+    gz = relu_backward(gy, c["y"])
+    gcat, G["wp"], G["bp"] = dwsep.pwconv3d_backward(c["cat"], Q["wp"], gz)
+    k = c["x"].shape[0]
+    gx, G["w0"], G["b0"] = dwsep.pwconv3d_backward(c["x"], Q["w0"], gcat[:k])
+    for i, d in enumerate(ASPP_RATES):
+        gb = gcat[(i + 1) * k:(i + 2) * k]
+        gd, G["pw%d" % d], G["pwb%d" % d] = dwsep.pwconv3d_backward(c["ds"][i], Q["pw%d" % d], gb)
+        gxi, G["dw%d" % d], G["dwb%d" % d] = dwsep.dwconv3d_backward(c["x"], Q["dw%d" % d], gd, d)
+        gx = gx + gxi
+    return gx, G
+
+
+def module_list(levels, base_ch, sep=False, se_ratio=0, att=False, tail="linear", aspp=False):
     """[(module name, [(param name, shape)])] in flat order.  With sep every
     ResBlock convolution is depthwise-separable; the stem (one input channel)
     and the 1x1x1 projections and tail stay dense.  With se_ratio r > 0 every
     encoder ResBlock is followed by a Squeeze-and-Excitation unit of hidden
     width c // r (its parameters end the encoder module).  With att every
     decoder module ends with an attention unit on its skip input (wx [c][c],
-    wg [c][c_up], b [c], psi [c], bpsi [1]).  `tail` changes no parameter."""
+    wg [c][c_up], b [c], psi [c], bpsi [1]).  With aspp an ASPP module on the
+    bottleneck follows the encoder modules.  `tail` changes no parameter."""
     ch = [base_ch * 2 ** l for l in range(levels)]
     mods = [("stem", [("conv.w", (base_ch, 1, 3, 3, 3)), ("conv.b", (base_ch,)),
                       ("norm.g", (base_ch,)), ("norm.beta", (base_ch,))])]
@@ -103,6 +146,8 @@ def module_list(levels, base_ch, sep=False, se_ratio=0, att=False, tail="linear"
     for l in range(1, levels):
         mods.append(("enc%d" % l, _block_shapes(ch[l - 1], ch[l], sep) +
                      _se_shapes(ch[l], se_ratio)))
+    if aspp:
+        mods.append(("aspp", _aspp_shapes(ch[-1])))
     for l in range(levels - 2, -1, -1):
         mods.append(("dec%d" % l, _block_shapes(ch[l + 1] + ch[l], ch[l], sep) +
                      _att_shapes(ch[l], ch[l + 1], att)))
@@ -110,15 +155,15 @@ def module_list(levels, base_ch, sep=False, se_ratio=0, att=False, tail="linear"
     return mods
 
 
-def n_params(levels, base_ch, sep=False, se_ratio=0, att=False):
-    return sum(int(np.prod(s)) for _, ps in module_list(levels, base_ch, sep, se_ratio, att)
-               for _, s in ps)
+def n_params(levels, base_ch, sep=False, se_ratio=0, att=False, aspp=False):
+    return sum(int(np.prod(s)) for _, ps in
+               module_list(levels, base_ch, sep, se_ratio, att, aspp=aspp) for _, s in ps)
 
 
-def unpack(theta, levels, base_ch, sep=False, se_ratio=0, att=False):
+def unpack(theta, levels, base_ch, sep=False, se_ratio=0, att=False, aspp=False):
     """Flat theta -> {module: {param: view}} (views into theta)."""
     out, off = {}, 0
-    for mod, ps in module_list(levels, base_ch, sep, se_ratio, att):
+    for mod, ps in module_list(levels, base_ch, sep, se_ratio, att, aspp=aspp):
         d = {}
         for name, shape in ps:
             k = int(np.prod(shape))
@@ -297,11 +342,12 @@ def att_backward(gout, Q, c):
     return gx, gg, grads
 
 
-def forward(theta, Z, n, levels, base_ch, sep=False, se_ratio=0, att=False, tail="linear"):
+def forward(theta, Z, n, levels, base_ch, sep=False, se_ratio=0, att=False, tail="linear",
+            aspp=False):
     """phi(theta | Z) before masking, as an (n, n, n) array, plus the cache
     (sep: depthwise-separable ResBlock convolutions; se_ratio: SE units after
     the encoder blocks; see module_list)."""
-    P = unpack(theta, levels, base_ch, sep, se_ratio, att)
+    P = unpack(theta, levels, base_ch, sep, se_ratio, att, aspp)
     z = Z.reshape(1, n, n, n)
     hs = conv3d(z, P["stem"]["conv.w"], P["stem"]["conv.b"])
     ns, cs = layer_norm(hs, P["stem"]["norm.g"], P["stem"]["norm.beta"])
@@ -320,6 +366,8 @@ def forward(theta, Z, n, levels, base_ch, sep=False, se_ratio=0, att=False, tail
             cache["se%d" % l] = (y_in, cse)
         enc.append(y)
     d = enc[-1]
+    if aspp:
+        d, cache["aspp"] = aspp_forward(d, P["aspp"])
     for l in range(levels - 2, -1, -1):
         u = up2(d)
         skip = enc[l]
@@ -339,11 +387,11 @@ def forward(theta, Z, n, levels, base_ch, sep=False, se_ratio=0, att=False, tail
 
 
 def backward(gout, theta, cache, n, levels, base_ch, sep=False, se_ratio=0, att=False,
-             tail="linear"):
+             tail="linear", aspp=False):
     """d(loss)/d(theta) as a flat array, given gout = d(loss)/d(phi) (n, n, n)."""
-    P = unpack(theta, levels, base_ch, sep, se_ratio, att)
+    P = unpack(theta, levels, base_ch, sep, se_ratio, att, aspp)
     grad = np.zeros(theta.size, dtype=np.float64)
-    Gv = unpack(grad, levels, base_ch, sep, se_ratio, att)
+    Gv = unpack(grad, levels, base_ch, sep, se_ratio, att, aspp)
     go = gout.reshape(1, n, n, n)
     if tail == "sigmoid":
         sg = cache["tail_sg"]
@@ -367,6 +415,10 @@ def backward(gout, theta, cache, n, levels, base_ch, sep=False, se_ratio=0, att=
             gu = gu + gg
         gd = up2_backward(gu)                  # to dec_{l+1} (or enc_{L-1})
         genc[l] = gskip                        # skip contribution to enc_l
+    if aspp:  # gd is d(loss)/d(ASPP output): back through the module
+        gd, Ga = aspp_backward(gd, P["aspp"], cache["aspp"])
+        for k, v in Ga.items():
+            Gv["aspp"][k][...] = v
     # encoder, from the bottleneck down; gd is d(loss)/d(enc_{L-1} output)
     genc[levels - 1] = gd
     gy = genc[levels - 1]

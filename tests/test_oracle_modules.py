@@ -85,3 +85,46 @@ def test_module_gradients_match_finite_differences(sep, r, att, tail):
         sets += [idx["dec0"][k].astype(int).ravel()
                  for k in ("att.wx", "att.wg", "att.b", "att.psi", "att.bpsi")]
     _fd(th, f, g, sets, rng)
+
+
+def test_aspp_matches_torch_autograd():
+    """The ASPP module against torch's float64 grouped, dilated and 1x1x1
+    convolutions and autograd."""
+    import torch
+    F = torch.nn.functional
+    rng = np.random.default_rng(30)
+    c, n = 4, 6
+    x = rng.standard_normal((c, n, n, n))
+    Q = {k: rng.standard_normal(s) * 0.4 for k, s in net._aspp_shapes(c)}
+    y, cache = net.aspp_forward(x, Q)
+    T = {k: torch.tensor(v, requires_grad=True) for k, v in Q.items()}
+    xt = torch.tensor(x, requires_grad=True)
+    pw = lambda t, w, b: F.conv3d(t[None], w[:, :, None, None, None], b)[0]
+    br = [pw(xt, T["w0"], T["b0"])]
+    for d in net.ASPP_RATES:
+        dd = F.conv3d(xt[None], T["dw%d" % d][:, None], T["dwb%d" % d], padding=d, dilation=d,
+                      groups=c)[0]
+        br.append(pw(dd, T["pw%d" % d], T["pwb%d" % d]))
+    yt = torch.relu(pw(torch.cat(br), T["wp"], T["bp"]))
+    np.testing.assert_allclose(y, yt.detach().numpy(), rtol=1e-11, atol=1e-11)
+    g = rng.standard_normal(y.shape)
+    (yt * torch.tensor(g)).sum().backward()
+    gx, G = net.aspp_backward(g, Q, cache)
+    np.testing.assert_allclose(gx, xt.grad.numpy(), rtol=1e-10, atol=1e-11)
+    for k in Q:
+        np.testing.assert_allclose(G[k], T[k].grad.numpy(), rtol=1e-10, atol=1e-11, err_msg=k)
+
+
+def test_network_with_aspp_matches_finite_differences():
+    rng = np.random.default_rng(31)
+    n, L, C = 8, 2, 4
+    kw = dict(aspp=True, sep=True)
+    th = rng.standard_normal(net.n_params(L, C, sep=True, aspp=True)) * 0.3
+    Z = rng.standard_normal(n ** 3)
+    R = rng.standard_normal((n, n, n))
+    y, cache = net.forward(th, Z, n, L, C, **kw)
+    g = net.backward(R, th, cache, n, L, C, **kw)
+    f = lambda t: (net.forward(t, Z, n, L, C, **kw)[0] * R).sum()
+    idx = net.unpack(np.arange(th.size, dtype=np.float64), L, C, sep=True, aspp=True)
+    sets = [idx["aspp"][k].astype(int).ravel() for k in ("w0", "dw2", "pw3", "wp", "dwb1")]
+    _fd(th, f, g, sets + [None], rng)
