@@ -352,6 +352,24 @@ d2ip_status d2ip_op_dwconv3d_backward(const float* x, const float* w, const floa
                                       float* gw, float* gb, int n, int C, void* workspace,
                                       size_t bytes, void* hip_stream);
 
+/* Workspace bytes of d2ip_op_dwconv3d_dilated_backward's weight gradient. */
+d2ip_status d2ip_op_dwconv3d_dilated_bytes(int n, int C, int dilation, size_t* out);
+
+/* The depthwise 3x3x3 convolution with its taps `dilation` voxels apart
+ * (dilation in [1, 256]; the atrous branches of the ASPP module at the
+ * bottleneck, Sec. III-D): y[v][c] = b[c] + sum_tap w[c][tap]
+ * x[v + dilation (tap - 1)][c], zero outside the grid.  A direct kernel for
+ * the small grids it runs on; otherwise as d2ip_op_dwconv3d_forward. */
+d2ip_status d2ip_op_dwconv3d_dilated_forward(const float* x, const float* w, const float* b,
+                                             float* y, int n, int C, int dilation,
+                                             void* hip_stream);
+
+/* Gradients of d2ip_op_dwconv3d_dilated_forward, as d2ip_op_dwconv3d_backward. */
+d2ip_status d2ip_op_dwconv3d_dilated_backward(const float* x, const float* w, const float* gy,
+                                              float* gx, float* gw, float* gb, int n, int C,
+                                              int dilation, void* workspace, size_t bytes,
+                                              void* hip_stream);
+
 /* Workspace bytes of d2ip_op_pwconv3d_backward's weight gradient (cin and
  * cout multiples of 4 in [4, 1024]). */
 d2ip_status d2ip_op_pwconv3d_bytes(int n, int cin, int cout, size_t* out);

@@ -101,6 +101,10 @@ SIGNATURES = {
     "d2ip_op_dwconv3d_forward": [_vp, _vp, _vp, _vp, _i, _i, _vp],
     "d2ip_op_dwconv3d_backward": [_vp, _vp, _vp, _vp, _vp, _vp, _i, _i, _vp, ctypes.c_size_t,
                                   _vp],
+    "d2ip_op_dwconv3d_dilated_bytes": [_i, _i, _i, _c_size_p],
+    "d2ip_op_dwconv3d_dilated_forward": [_vp, _vp, _vp, _vp, _i, _i, _i, _vp],
+    "d2ip_op_dwconv3d_dilated_backward": [_vp, _vp, _vp, _vp, _vp, _vp, _i, _i, _i, _vp,
+                                          ctypes.c_size_t, _vp],
     "d2ip_op_pwconv3d_bytes": [_i, _i, _i, _c_size_p],
     "d2ip_op_pwconv3d_forward": [_vp, _vp, _vp, _vp, _i, _i, _i, _vp],
     "d2ip_op_pwconv3d_backward": [_vp, _vp, _vp, _vp, _vp, _vp, _i, _i, _i, _vp,

@@ -312,6 +312,103 @@ __global__ __launch_bounds__(256, 2) void k_dw_wgrad(const float* __restrict__ x
   }
 }
 
+// Dilated depthwise convolution (taps `dil` voxels apart, the atrous branches
+// of an ASPP module), direct form for the small grids it runs on: thread per
+// (voxel, channel quad), 27 clamped float4 loads masked outside the grid; flip
+// reverses the taps (input gradient; b ignored).  Grid: ceil(V * C4 / 256).
+__global__ __launch_bounds__(256) void k_dwd_fwd(const float* __restrict__ x,
+                                                 const float* __restrict__ w,
+                                                 const float* __restrict__ b,
+                                                 float* __restrict__ y, int n, int C, int dil,
+                                                 int flip) {
+  const int C4 = C >> 2;
+  const long long e = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (e >= (long long)n * n * n * C4) return;
+  const int q = (int)(e % C4);
+  const int v = (int)(e / C4);
+  const int vx = v % n, vy = (v / n) % n, vz = v / (n * n);
+  float4 acc = (b && !flip) ? *reinterpret_cast<const float4*>(b + 4 * q)
+                            : make_float4(0.f, 0.f, 0.f, 0.f);
+  const float* wq = w + (size_t)(4 * q) * 27;
+#pragma unroll
+  for (int t = 0; t < 27; ++t) {
+    const int dz = t / 9 - 1, dy = (t / 3) % 3 - 1, dx = t % 3 - 1;
+    const int gz = vz + dil * dz, gy = vy + dil * dy, gx = vx + dil * dx;
+    const bool in = (unsigned)gz < (unsigned)n && (unsigned)gy < (unsigned)n &&
+                    (unsigned)gx < (unsigned)n;
+    const int cz = min(max(gz, 0), n - 1), cy = min(max(gy, 0), n - 1), cx = min(max(gx, 0), n - 1);
+    float4 xv = *reinterpret_cast<const float4*>(x + ((size_t)(cz * n + cy) * n + cx) * C + 4 * q);
+    if (!in) xv = make_float4(0.f, 0.f, 0.f, 0.f);
+    const int tt = flip ? 26 - t : t;
+    acc.x += wq[tt] * xv.x;
+    acc.y += wq[27 + tt] * xv.y;
+    acc.z += wq[54 + tt] * xv.z;
+    acc.w += wq[81 + tt] * xv.w;
+  }
+  *reinterpret_cast<float4*>(y + (size_t)v * C + 4 * q) = acc;
+}
+
+// Weight-gradient partials of the dilated depthwise convolution: block b of
+// a chunk of `chunk` voxels; thread (r, q) of R = 256 / C4 row lanes sums
+// gy[v] x[v + dil (t - 1)] (27 taps) and gy[v] (bias) over voxels
+// v0 + r, v0 + r + R, ...; the lanes of a quad are added in order through
+// LDS, four sums at a time, into part[(c * 28 + k) * nP + b].
+__global__ __launch_bounds__(256) void k_dwd_wgrad(const float* __restrict__ x,
+                                                   const float* __restrict__ gyv,
+                                                   float* __restrict__ part, int n, int C,
+                                                   int dil, int chunk, int nP) {
+  __shared__ float4 red[4 * 256];
+  const int C4 = C >> 2, R = 256 / C4;
+  const int q = threadIdx.x % C4, r = threadIdx.x / C4;
+  const int V = n * n * n;
+  const int v0 = blockIdx.x * chunk, v1 = min(V, v0 + chunk);
+  float4 acc[kDwParts];
+#pragma unroll
+  for (int i = 0; i < kDwParts; ++i) acc[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+  if (r < R)
+    for (int v = v0 + r; v < v1; v += R) {
+      const int vx = v % n, vy = (v / n) % n, vz = v / (n * n);
+      const float4 g = *reinterpret_cast<const float4*>(gyv + (size_t)v * C + 4 * q);
+#pragma unroll
+      for (int t = 0; t < 27; ++t) {
+        const int dz = t / 9 - 1, dy = (t / 3) % 3 - 1, dx = t % 3 - 1;
+        const int gz = vz + dil * dz, gy = vy + dil * dy, gx = vx + dil * dx;
+        const bool in = (unsigned)gz < (unsigned)n && (unsigned)gy < (unsigned)n &&
+                        (unsigned)gx < (unsigned)n;
+        const int cz = min(max(gz, 0), n - 1), cy = min(max(gy, 0), n - 1),
+                  cx = min(max(gx, 0), n - 1);
+        float4 xv =
+            *reinterpret_cast<const float4*>(x + ((size_t)(cz * n + cy) * n + cx) * C + 4 * q);
+        if (!in) xv = make_float4(0.f, 0.f, 0.f, 0.f);
+        fma4(acc[t], g, xv);
+      }
+      fma4(acc[27], make_float4(1.f, 1.f, 1.f, 1.f), g);
+    }
+#pragma unroll
+  for (int i0 = 0; i0 < kDwParts; i0 += 4) {
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < 4; ++c) red[c * 256 + threadIdx.x] = acc[i0 + c];
+    __syncthreads();
+    if (threadIdx.x < 4 * C4) {
+      const int c = threadIdx.x / C4, qq = threadIdx.x % C4;
+      float4 s = red[c * 256 + qq];
+      for (int rr = 1; rr < R; ++rr) {
+        const float4 t = red[c * 256 + rr * C4 + qq];
+        s.x += t.x;
+        s.y += t.y;
+        s.z += t.z;
+        s.w += t.w;
+      }
+      const int k = i0 + c, ch = 4 * qq;
+      part[((size_t)(ch + 0) * kDwParts + k) * nP + blockIdx.x] = s.x;
+      part[((size_t)(ch + 1) * kDwParts + k) * nP + blockIdx.x] = s.y;
+      part[((size_t)(ch + 2) * kDwParts + k) * nP + blockIdx.x] = s.z;
+      part[((size_t)(ch + 3) * kDwParts + k) * nP + blockIdx.x] = s.w;
+    }
+  }
+}
+
 // gw[c][tap] and gb[c] from the partials: one wave per (c, k), lanes over the
 // partials with eight loads in flight, then a fixed butterfly.
 __global__ __launch_bounds__(256) void k_dw_wreduce(const float* __restrict__ part, int nP, int C,
@@ -386,6 +483,38 @@ void launch_wgrad(const DwPlan& p, const float* x, const float* gy, float* part,
 }
 
 }  // namespace
+
+// Voxel chunks of the dilated weight gradient: at most 256, whole lane passes.
+static void dwd_chunks(int n, int C, int* chunk, int* nchunks) {
+  const int V = n * n * n, R = 256 / (C / 4);
+  int len = (V + 255) / 256;
+  len = (len + R - 1) / R * R;
+  *chunk = len;
+  *nchunks = (V + len - 1) / len;
+}
+
+size_t dwd_partials(int n, int C) {
+  int chunk, nchunks;
+  dwd_chunks(n, C, &chunk, &nchunks);
+  return (size_t)nchunks * C * kDwParts;
+}
+
+void dwd_forward(const float* x, const float* w, const float* b, float* y, int n, int C, int dil,
+                 bool flip, hipStream_t s) {
+  const long long total = (long long)n * n * n * (C / 4);
+  hipLaunchKernelGGL(k_dwd_fwd, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, x, w, b, y,
+                     n, C, dil, flip ? 1 : 0);
+}
+
+void dwd_wgrad(const float* x, const float* gy, float* part, float* gw, float* gb, int n, int C,
+               int dil, hipStream_t s) {
+  int chunk, nchunks;
+  dwd_chunks(n, C, &chunk, &nchunks);
+  hipLaunchKernelGGL(k_dwd_wgrad, dim3(nchunks), dim3(256), 0, s, x, gy, part, n, C, dil, chunk,
+                     nchunks);
+  hipLaunchKernelGGL(k_dw_wreduce, dim3((C * kDwParts + 3) / 4), dim3(256), 0, s, part, nchunks,
+                     C, gw, gb);
+}
 
 size_t dw_partials(int n, int C) {
   const DwPlan p = dw_plan(n, C, kDwWgBlocks);

@@ -251,6 +251,14 @@ void dw_forward(const float* x, const float* w, const float* b, float* y, int n,
                 hipStream_t s);
 void dw_wgrad(const float* x, const float* gy, float* part, float* gw, float* gb, int n, int C,
               hipStream_t s);
+// The same convolution with taps `dil` voxels apart (direct form, for small
+// grids): forward / input gradient and the weight gradient through
+// dwd_partials(n, C) floats of `part`.
+size_t dwd_partials(int n, int C);
+void dwd_forward(const float* x, const float* w, const float* b, float* y, int n, int C, int dil,
+                 bool flip, hipStream_t s);
+void dwd_wgrad(const float* x, const float* gy, float* part, float* gw, float* gb, int n, int C,
+               int dil, hipStream_t s);
 // Pointwise (1x1x1) convolution as FP32 matrix-core GEMMs on channels-last
 // tensors: Y[M][N] = X[M][K] B + bias with B[k][n] = W[n][k] (W [N][K]) or,
 // with transw, W[k][n] (W [K][N]); pw_wgrad writes pw_partials(M, K, N) floats

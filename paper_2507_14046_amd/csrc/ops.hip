@@ -423,6 +423,52 @@ d2ip_status d2ip_op_dwconv3d_backward(const float* x, const float* w, const floa
   return D2IP_OK;
 }
 
+d2ip_status d2ip_op_dwconv3d_dilated_bytes(int n, int C, int dilation, size_t* out) {
+  if (!out) return api_fail(D2IP_EINVAL, "null output");
+  d2ip_status st = dw_check(n, C);
+  if (st != D2IP_OK) return st;
+  if (dilation < 1 || dilation > 256) return api_fail(D2IP_EINVAL, "dilation must be in [1, 256]");
+  *out = dwd_partials(n, C) * sizeof(float) + 256;
+  return D2IP_OK;
+}
+
+d2ip_status d2ip_op_dwconv3d_dilated_forward(const float* x, const float* w, const float* b,
+                                             float* y, int n, int C, int dilation,
+                                             void* hip_stream) {
+  d2ip_status st = dw_check(n, C);
+  if (st != D2IP_OK) return st;
+  if (dilation < 1 || dilation > 256) return api_fail(D2IP_EINVAL, "dilation must be in [1, 256]");
+  if (!x || !w || !y) return api_fail(D2IP_EINVAL, "null x, w or y");
+  if (!aligned16(x) || !aligned16(y) || (b && !aligned16(b)))
+    return api_fail(D2IP_EINVAL, "x, y and b must be 16-byte aligned");
+  dwd_forward(x, w, b, y, n, C, dilation, false, reinterpret_cast<hipStream_t>(hip_stream));
+  OPCHK(hipGetLastError());
+  return D2IP_OK;
+}
+
+d2ip_status d2ip_op_dwconv3d_dilated_backward(const float* x, const float* w, const float* gy,
+                                              float* gx, float* gw, float* gb, int n, int C,
+                                              int dilation, void* workspace, size_t bytes,
+                                              void* hip_stream) {
+  d2ip_status st = dw_check(n, C);
+  if (st != D2IP_OK) return st;
+  if (dilation < 1 || dilation > 256) return api_fail(D2IP_EINVAL, "dilation must be in [1, 256]");
+  if (!gy || (gx && !w) || ((gw || gb) && !x))
+    return api_fail(D2IP_EINVAL, "null gy, or null w with gx, or null x with gw / gb");
+  if (!aligned16(gy) || (gx && !aligned16(gx)) || (x && !aligned16(x)))
+    return api_fail(D2IP_EINVAL, "x, gy and gx must be 16-byte aligned");
+  hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
+  if (gw || gb) {
+    size_t need = 0;
+    d2ip_op_dwconv3d_dilated_bytes(n, C, dilation, &need);
+    if ((st = ws_check(workspace, bytes, need)) != D2IP_OK) return st;
+    dwd_wgrad(x, gy, reinterpret_cast<float*>(workspace), gw, gb, n, C, dilation, s);
+  }
+  if (gx) dwd_forward(gy, w, nullptr, gx, n, C, dilation, true, s);
+  OPCHK(hipGetLastError());
+  return D2IP_OK;
+}
+
 d2ip_status d2ip_op_pwconv3d_bytes(int n, int cin, int cout, size_t* out) {
   if (!out) return api_fail(D2IP_EINVAL, "null output");
   d2ip_status st = pw_check(n, cin, cout);

@@ -10,7 +10,8 @@ backward, J sigma and J^T g).  ``DIPNet``
 composes the prior of Eq. (3) from them (with ``conv="dwsep"`` every ResBlock
 convolution is the depthwise-separable one of Sec. III-D, with ``se_ratio`` an
 SE unit gates every encoder block, with ``att`` an attention unit gates every
-decoder skip, and ``tail="sigmoid"`` gives the image 2 sigmoid(t) - 1); pooling, up-sampling, channel
+decoder skip, with ``aspp`` an ASPP module transforms the bottleneck, and
+``tail="sigmoid"`` gives the image 2 sigmoid(t) - 1); pooling, up-sampling, channel
 concatenation and the 1x1x1 output head are plain tensor operations of the
 model around the operators.  With ``recompute=True`` every ResBlock's
 activations are dropped after the forward and recomputed during the backward
@@ -82,11 +83,11 @@ class LayerNormReLUFn:
 class DWConv3dFn:
     """y = depthwise conv3d(x, w, b): x [n^3, C] (C % 4 == 0), w [C, 1, 3, 3, 3] or
     [C, 3, 3, 3], b [C] or None (Sec. III-D's depthwise-separable convolution,
-    first half)."""
+    first half); dil > 1 spaces the taps dil voxels apart (atrous)."""
 
     @staticmethod
-    def apply(x, w, b=None):
-        return _dw_fn().apply(x, w, b)
+    def apply(x, w, b=None, dil=1):
+        return _dw_fn().apply(x, w, b, dil)
 
 
 class PWConv3dFn:
@@ -177,7 +178,7 @@ def _dw_fn():
 
     class _DW(torch.autograd.Function):
         @staticmethod
-        def forward(ctx, x, w, b):
+        def forward(ctx, x, w, b, dil):
             lib = L.load()
             x, w, b = _a16(x), w.contiguous(), _a16(b)
             V, C = x.shape
@@ -185,16 +186,21 @@ def _dw_fn():
                 raise ValueError("w must hold C x 27 taps")
             n = _grid_n(V)
             y = torch.empty_like(x)
-            L.check(lib.d2ip_op_dwconv3d_forward(_p(x), _p(w), _p(b), _p(y), n, C, _stream(x)))
+            if dil == 1:
+                L.check(lib.d2ip_op_dwconv3d_forward(_p(x), _p(w), _p(b), _p(y), n, C,
+                                                     _stream(x)))
+            else:
+                L.check(lib.d2ip_op_dwconv3d_dilated_forward(_p(x), _p(w), _p(b), _p(y), n, C,
+                                                             dil, _stream(x)))
             ctx.save_for_backward(x, w)
-            ctx.meta = (n, C, b is not None)
+            ctx.meta = (n, C, b is not None, dil)
             return y
 
         @staticmethod
         def backward(ctx, gy):
             lib = L.load()
             x, w = ctx.saved_tensors
-            n, C, has_b = ctx.meta
+            n, C, has_b, dil = ctx.meta
             gy = _a16(gy)
             need_x, need_w, need_b = ctx.needs_input_grad[:3]
             gx = torch.empty_like(x) if need_x else None
@@ -202,11 +208,19 @@ def _dw_fn():
             gb = torch.empty(C, dtype=torch.float32, device=x.device) if (need_b and has_b) \
                 else None
             ws, nb = (None, 0)
-            if gw is not None or gb is not None:
-                ws, nb = _workspace(lib.d2ip_op_dwconv3d_bytes, n, C, device=x.device)
-            L.check(lib.d2ip_op_dwconv3d_backward(_p(x), _p(w), _p(gy), _p(gx), _p(gw), _p(gb),
-                                                  n, C, _p(ws), nb, _stream(x)))
-            return gx, gw, gb
+            if dil == 1:
+                if gw is not None or gb is not None:
+                    ws, nb = _workspace(lib.d2ip_op_dwconv3d_bytes, n, C, device=x.device)
+                L.check(lib.d2ip_op_dwconv3d_backward(_p(x), _p(w), _p(gy), _p(gx), _p(gw),
+                                                      _p(gb), n, C, _p(ws), nb, _stream(x)))
+            else:
+                if gw is not None or gb is not None:
+                    ws, nb = _workspace(lib.d2ip_op_dwconv3d_dilated_bytes, n, C, dil,
+                                        device=x.device)
+                L.check(lib.d2ip_op_dwconv3d_dilated_backward(_p(x), _p(w), _p(gy), _p(gx),
+                                                              _p(gw), _p(gb), n, C, dil, _p(ws),
+                                                              nb, _stream(x)))
+            return gx, gw, gb, None
 
     _FNS["dw"] = _DW
     return _DW
@@ -377,7 +391,10 @@ def _measure_fn():
 # the prior of Eq. (3) composed from the operators
 # ----------------------------------------------------------------------------
 
-def param_shapes(levels, base_ch, sep=False, se_ratio=0, att=False):
+ASPP_RATES = (1, 2, 3)  # dilations of the ASPP module's atrous branches
+
+
+def param_shapes(levels, base_ch, sep=False, se_ratio=0, att=False, aspp=False):
     """(name, shape) of every parameter tensor in the canonical flat order:
     stem, encoder ResBlocks 0..L-1, decoder ResBlocks L-2..0, head; in a
     module each conv's W [Cout][Cin][k][k][k] then b, each norm gamma then
@@ -420,6 +437,13 @@ def param_shapes(levels, base_ch, sep=False, se_ratio=0, att=False):
         return [(name + ".awx", (c, c)), (name + ".awg", (c, c_up)), (name + ".ab", (c,)),
                 (name + ".apsi", (c,)), (name + ".abpsi", (1,))]
 
+    if aspp:  # on the bottleneck, between the encoder and decoder modules
+        c = ch[-1]
+        out += [("aspp.w0", (c, c)), ("aspp.b0", (c,))]
+        for d in ASPP_RATES:
+            out += [("aspp.dw%d" % d, (c, 3, 3, 3)), ("aspp.dwb%d" % d, (c,)),
+                    ("aspp.pw%d" % d, (c, c)), ("aspp.pwb%d" % d, (c,))]
+        out += [("aspp.wp", (c, c * (1 + len(ASPP_RATES)))), ("aspp.bp", (c,))]
     for l in range(levels - 2, -1, -1):
         out += block("dec%d" % l, ch[l + 1] + ch[l], ch[l]) + att_unit("dec%d" % l, ch[l],
                                                                        ch[l + 1])
@@ -443,7 +467,7 @@ class DIPNet:
     flat tensor in the canonical order (gradients flow to it through views)."""
 
     def __init__(self, n, levels, base_ch, precision="fp32", recompute=False, conv="dense",
-                 se_ratio=0, att=False, tail="linear"):
+                 se_ratio=0, att=False, tail="linear", aspp=False):
         if conv not in ("dense", "dwsep"):
             raise ValueError("conv must be 'dense' or 'dwsep'")
         if tail not in ("linear", "sigmoid"):
@@ -454,7 +478,8 @@ class DIPNet:
         self.recompute = recompute
         self.sep = conv == "dwsep"  # depthwise-separable ResBlock convs (FP32)
         self.se_ratio = se_ratio    # SE units gating the encoder blocks (0: none)
-        self.shapes = param_shapes(levels, base_ch, self.sep, se_ratio, att)
+        self.aspp = aspp  # ASPP module at the bottleneck
+        self.shapes = param_shapes(levels, base_ch, self.sep, se_ratio, att, aspp)
         self.size = int(sum(np.prod(s) for _, s in self.shapes))
 
     def views(self, theta):
@@ -507,6 +532,8 @@ class DIPNet:
                 e = "enc%d" % l
                 x = SEFn.apply(x, P[e + ".sw1"], P[e + ".sb1"], P[e + ".sw2"], P[e + ".sb2"])
             skips.append(x)
+        if self.aspp:
+            x = self._aspp(P, x)
         for l in range(L - 2, -1, -1):
             nl = n >> l
             u = _up(x, nl // 2)
@@ -519,6 +546,16 @@ class DIPNet:
         if self.tail == "sigmoid":
             out = 2.0 * torch.sigmoid(out) - 1.0
         return out.view(-1) * mask
+
+    def _aspp(self, P, x):
+        """ASPP on the bottleneck: a 1x1x1 branch and one depthwise-separable
+        atrous branch per rate, concatenated, projected (1x1x1), ReLU."""
+        torch = _torch()
+        br = [PWConv3dFn.apply(x, P["aspp.w0"], P["aspp.b0"])]
+        for d in ASPP_RATES:
+            t = DWConv3dFn.apply(x, P["aspp.dw%d" % d], P["aspp.dwb%d" % d], d)
+            br.append(PWConv3dFn.apply(t, P["aspp.pw%d" % d], P["aspp.pwb%d" % d]))
+        return torch.relu(PWConv3dFn.apply(torch.cat(br, dim=1), P["aspp.wp"], P["aspp.bp"]))
 
     def _attend(self, P, d, s, u):
         """Additive attention unit: the skip s gated per voxel by

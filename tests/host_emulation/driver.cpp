@@ -184,6 +184,17 @@ static int ops_case() {
     free(ws);
   }
   EXPECT_ERR(d2ip_op_dwconv3d_bytes(n, 6, &need), D2IP_EINVAL);
+  for (int dil : {1, 2, 5}) {
+    std::vector<float> wd((size_t)16 * 27), bd(16), gwd(wd.size()), gbd(16);
+    CK(d2ip_op_dwconv3d_dilated_bytes(n, 16, dil, &need));
+    ws = (char*)aligned_alloc(256, (need + 255) / 256 * 256);
+    CK(d2ip_op_dwconv3d_dilated_forward(x.data(), wd.data(), bd.data(), y.data(), n, 16, dil,
+                                        &token));
+    CK(d2ip_op_dwconv3d_dilated_backward(x.data(), wd.data(), g.data(), gx.data(), gwd.data(),
+                                         gbd.data(), n, 16, dil, ws, need, &token));
+    free(ws);
+  }
+  EXPECT_ERR(d2ip_op_dwconv3d_dilated_bytes(n, 16, 0, &need), D2IP_EINVAL);
   for (int ci : {4, 16, 100})
     for (int co : {8, 64, 132}) {
       CK(d2ip_op_pwconv3d_bytes(n, ci, co, &need));

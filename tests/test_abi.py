@@ -212,16 +212,18 @@ def test_stored_tuning_table_plans_every_workload(L):
 @pytest.mark.parametrize("L_,C", [(2, 8), (3, 16), (4, 32)])
 @pytest.mark.parametrize("sep", [False, True])
 @pytest.mark.parametrize("r", [0, 4, 64])
-@pytest.mark.parametrize("att", [False, True])
-def test_operator_network_layout_matches_oracle(L, L_, C, sep, r, att):
+@pytest.mark.parametrize("att,aspp", [(False, False), (True, False), (True, True)])
+def test_operator_network_layout_matches_oracle(L, L_, C, sep, r, att, aspp):
     """The autograd network's flat parameter order (dense or depthwise-separable
     ResBlock convs, with or without SE units) is the oracle's, tensor by
     tensor."""
     import numpy as np
     from oracle import net
     from paper_2507_14046_amd import ops
-    mine = [int(np.prod(s)) for _, s in ops.param_shapes(L_, C, sep, r, att)]
-    ref = [int(np.prod(s)) for _, ps in net.module_list(L_, C, sep, r, att) for _, s in ps]
+    mine = [int(np.prod(s)) for _, s in ops.param_shapes(L_, C, sep, r, att, aspp)]
+    ref = [int(np.prod(s)) for _, ps in net.module_list(L_, C, sep, r, att, aspp=aspp)
+           for _, s in ps]
+    assert ops.ASPP_RATES == net.ASPP_RATES
     assert mine == ref
 
 

@@ -225,3 +225,38 @@ def test_separable_network_gradient_matches_oracle(lib, shape):
     e = dict(loss=abs(float(loss.detach()) - L0) / L0, grad=rel(host(T.grad), gref))
     record("dwsep_network", n=n, levels=L, C=C, **e)
     assert e["loss"] < 1e-5 and e["grad"] < 2e-4, e
+
+
+@pytest.mark.parametrize("n,C,dil", [(8, 16, 2), (5, 12, 3), (4, 8, 5), (16, 64, 2), (9, 4, 1)])
+def test_dilated_depthwise_matches_oracle(lib, n, C, dil):
+    """The atrous depthwise convolution (direct kernel) against the oracle,
+    including a dilation past the grid (only the centre tap left) and
+    dilation 1, which must agree with the streaming kernels as well."""
+    import ctypes
+    import torch
+    from paper_2507_14046_amd import ops
+    x, w, b, g = _case(n, C, 5000 + 10 * n + C + dil)
+    f = lambda a: a.astype(np.float64)
+    yref = dwsep.dwconv3d(f(x), f(w), f(b), dil)
+    gxr, gwr, gbr = dwsep.dwconv3d_backward(f(x), f(w), f(g), dil)
+    X, W, B = dev(cl(x), True), dev(w, True), dev(b, True)
+    if dil == 1:  # force the direct kernel through the C-ABI
+        from paper_2507_14046_amd import _lib as L
+        y1 = torch.empty_like(X)
+        P = lambda t: ctypes.c_void_p(t.data_ptr())
+        L.check(L.load().d2ip_op_dwconv3d_dilated_forward(
+            P(X), P(W), P(B), P(y1), n, C, 1,
+            ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)))
+        Y = y1
+        ys = ops.DWConv3dFn.apply(X, W, B)
+        assert rel(host(Y), host(ys)) < TOL_Y
+    else:
+        Y = ops.DWConv3dFn.apply(X, W, B, dil)
+        Y.backward(dev(cl(g)))
+    e = dict(y=rel(cf(host(Y), n), yref))
+    if dil != 1:
+        e.update(gx=rel(cf(host(X.grad), n), gxr), gw=rel(host(W.grad), gwr),
+                 gb=rel(host(B.grad), gbr))
+    record("dwconv3d_dilated", n=n, C=C, dil=dil, **e)
+    assert e["y"] < TOL_Y and e.get("gx", 0) < TOL_Y, e
+    assert e.get("gw", 0) < TOL_W and e.get("gb", 0) < TOL_W, e

@@ -89,15 +89,17 @@ def test_network_with_se_units_matches_oracle(lib, shape, sep):
     assert e["loss"] < 1e-5 and e["grad"] < 2e-4, e
 
 
-@pytest.mark.parametrize("shape,sep,r,att,tail", [
-    ((8, 1, 2, 8), False, 0, True, "linear"),
-    ((8, 1, 2, 8), False, 0, False, "sigmoid"),
-    ((16, 2, 3, 16), True, 4, True, "sigmoid")])
-def test_network_modules_match_oracle(lib, shape, sep, r, att, tail):
-    """Attention units on the decoder skips, the sigmoid tail, and all of the
-    3D-FastResUNet modules built here together (depthwise-separable convs, SE
-    units, attention units, sigmoid tail): loss and theta gradient of the
-    autograd network against the FP64 oracle network of the same layout."""
+@pytest.mark.parametrize("shape,sep,r,att,tail,aspp", [
+    ((8, 1, 2, 8), False, 0, True, "linear", False),
+    ((8, 1, 2, 8), False, 0, False, "sigmoid", False),
+    ((16, 2, 3, 16), False, 0, False, "linear", True),
+    ((16, 2, 3, 16), True, 4, True, "sigmoid", True)])
+def test_network_modules_match_oracle(lib, shape, sep, r, att, tail, aspp):
+    """Attention units on the decoder skips, the sigmoid tail, the ASPP module,
+    and all of the 3D-FastResUNet modules together (depthwise-separable
+    convs, SE units, ASPP, attention units, sigmoid tail): loss and theta
+    gradient of the autograd network against the FP64 oracle network of the
+    same layout."""
     import torch
     from oracle import fit, net
     from paper_2507_14046_amd import ops
@@ -105,17 +107,18 @@ def test_network_modules_match_oracle(lib, shape, sep, r, att, tail):
     n, rings, L, C = shape
     p = problem(n, rings, L, C, 90 + n + L)
     rng = np.random.default_rng(91 + n + 2 * att + r)
-    th = (0.3 * rng.standard_normal(net.n_params(L, C, sep, r, att))).astype(np.float32)
+    th = (0.3 * rng.standard_normal(net.n_params(L, C, sep, r, att, aspp))).astype(np.float32)
     model = ops.DIPNet(n, L, C, conv="dwsep" if sep else "dense", se_ratio=r, att=att,
-                       tail=tail)
+                       tail=tail, aspp=aspp)
     T = dev(th, True)
     loss = model.loss(T, dev(p["Z"]), dev(p["mask"].astype(np.float32)), dev(p["J"]),
                       dev(p["dv"][0]))
     loss.backward()
     torch.cuda.synchronize()
     pr = fit.Problem(p["J"], p["mask"], p["Z"], n, L, C, sep=sep, se_ratio=r, att=att,
-                     tail=tail)
+                     tail=tail, aspp=aspp)
     L0, gref, _ = pr.loss_and_grad(th.astype(np.float64), p["dv"][0].astype(np.float64))
     e = dict(loss=abs(float(loss.detach()) - L0) / L0, grad=rel(host(T.grad), gref))
-    record("modules_network", n=n, levels=L, C=C, sep=sep, se_ratio=r, att=att, tail=tail, **e)
+    record("modules_network", n=n, levels=L, C=C, sep=sep, se_ratio=r, att=att, tail=tail,
+           aspp=aspp, **e)
     assert e["loss"] < 1e-5 and e["grad"] < 2e-4, e
