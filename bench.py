@@ -349,7 +349,7 @@ def dwsep_network(d2ip, torch, ts, names=("c1", "c2"), reps=10):
     """One loss + theta-gradient evaluation of the autograd network
     (`ops.DIPNet`, every operator on the library's kernels) with dense and
     with depthwise-separable ResBlock convolutions, and with the
-    3D-FastResUNet modules built here (depthwise-separable convs, SE units,
+    3D-FastResUNet modules (depthwise-separable convs, SE units, ASPP,
     attention units, sigmoid tail), FP32, on a config's problem: ms per
     evaluation (HIP events, mean of `reps` after three warm-up calls) and
     parameter counts."""
@@ -363,7 +363,8 @@ def dwsep_network(d2ip, torch, ts, names=("c1", "c2"), reps=10):
             dev(p["dv"][0])
         row = {}
         variants = {"dense": {}, "dwsep": dict(conv="dwsep"),
-                    "fastres_modules": dict(conv="dwsep", se_ratio=4, att=True, tail="sigmoid")}
+                    "fastres_modules": dict(conv="dwsep", se_ratio=4, att=True, tail="sigmoid",
+                                            aspp=True)}
         for conv, kw in variants.items():
             model = ops.DIPNet(c["n"], c["levels"], c["base_ch"], **kw)
             g = torch.Generator(device="cuda").manual_seed(11)
@@ -386,7 +387,7 @@ def dwsep_network(d2ip, torch, ts, names=("c1", "c2"), reps=10):
         row["speedup"] = row["dense"]["ms_per_loss_and_grad"] / row["dwsep"]["ms_per_loss_and_grad"]
         out[name] = row
         log("network %s: dense %.2f ms (%d params), dwsep %.2f ms (%d params), %.2fx; "
-            "dwsep + SE + attention + sigmoid tail %.2f ms (%d params)"
+            "dwsep + SE + ASPP + attention + sigmoid tail %.2f ms (%d params)"
             % (name, row["dense"]["ms_per_loss_and_grad"], row["dense"]["params"],
                row["dwsep"]["ms_per_loss_and_grad"], row["dwsep"]["params"], row["speedup"],
                row["fastres_modules"]["ms_per_loss_and_grad"], row["fastres_modules"]["params"]))
