@@ -75,9 +75,11 @@ __global__ __launch_bounds__(256) void k_pw_gemm(const float* __restrict__ X,
   for (int rt = 0; rt < 2; ++rt)
 #pragma unroll
     for (int ct = 0; ct < 4; ++ct) acc[rt][ct] = f32x4{0.f, 0.f, 0.f, 0.f};
-  for (int k0 = 0; k0 < K; k0 += kPwKC) {
-    // A: 128 rows x 32 k as 1024 float4, rows contiguous in k (coalesced)
-    float4 ra[4], rb[2];
+  // stage loads: A 128 rows x 32 k as 1024 float4 (rows contiguous in k,
+  // coalesced), B 64 columns x 32 k; the next stage's loads are issued before
+  // this stage's MFMAs
+  float4 ra[4], rb[2];
+  auto load = [&](int k0) {
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const int e = tid + 256 * i, r = e >> 3, c4 = (e & 7) * 4;
@@ -86,7 +88,6 @@ __global__ __launch_bounds__(256) void k_pw_gemm(const float* __restrict__ X,
       ra[i] = *reinterpret_cast<const float4*>(X + row * K + (ok ? k0 + c4 : 0));
       if (!ok) ra[i] = make_float4(0.f, 0.f, 0.f, 0.f);
     }
-    // B: 64 columns x 32 k
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
       const int e = tid + 256 * i;
@@ -104,6 +105,9 @@ __global__ __launch_bounds__(256) void k_pw_gemm(const float* __restrict__ X,
         if (!ok) rb[i] = make_float4(0.f, 0.f, 0.f, 0.f);
       }
     }
+  };
+  load(0);
+  for (int k0 = 0; k0 < K; k0 += kPwKC) {
     __syncthreads();  // the previous stage is consumed
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
@@ -125,6 +129,7 @@ __global__ __launch_bounds__(256) void k_pw_gemm(const float* __restrict__ X,
       }
     }
     __syncthreads();
+    if (k0 + kPwKC < K) load(k0 + kPwKC);  // uniform
     pw_stage_mma(As, Bs, wave, l16, g, acc);
   }
 #pragma unroll
@@ -163,9 +168,10 @@ __global__ __launch_bounds__(256) void k_pw_wgrad(const float* __restrict__ X,
 #pragma unroll
   for (int ct = 0; ct < 4; ++ct) acc[ct] = f32x4{0.f, 0.f, 0.f, 0.f};
   float csum = 0.f;  // column sum of G for n = n0 + tid (tid < 64, k tile 0)
-  for (size_t vb = v0; vb < v1; vb += kPwKC) {
-    // 32 voxels x 64 columns of G and of X as 512 float4 each
-    float4 rg[2], rx[2];
+  // 32 voxels x 64 columns of G and of X as 512 float4 each; the next
+  // stage's loads are issued before this stage's MFMAs
+  float4 rg[2], rx[2];
+  auto load = [&](size_t vb) {
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
       const int e = tid + 256 * i, v = e >> 4, c4 = (e & 15) * 4;
@@ -177,6 +183,9 @@ __global__ __launch_bounds__(256) void k_pw_wgrad(const float* __restrict__ X,
       if (!gok) rg[i] = make_float4(0.f, 0.f, 0.f, 0.f);
       if (!xok) rx[i] = make_float4(0.f, 0.f, 0.f, 0.f);
     }
+  };
+  load(v0);
+  for (size_t vb = v0; vb < v1; vb += kPwKC) {
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
@@ -191,6 +200,7 @@ __global__ __launch_bounds__(256) void k_pw_wgrad(const float* __restrict__ X,
       Bs[(c4 + 3) * kPwLd + v] = rx[i].w;
     }
     __syncthreads();
+    if (vb + kPwKC < v1) load(vb + kPwKC);  // uniform
     if (blockIdx.z == 0 && tid < 64) {
 #pragma unroll
       for (int v = 0; v < kPwKC; v += 4) {
