@@ -545,6 +545,8 @@ def main():
     ap.add_argument("--no-configs", action="store_true")
     ap.add_argument("--no-dwsep", action="store_true",
                     help="skip the depthwise-separable and SE operator timings")
+    ap.add_argument("--no-network", action="store_true",
+                    help="skip the network-level timing of the module variants")
     ap.add_argument("--ablation", action="store_true",
                     help="also run the D2IP schedule ablation (UPWS / TPP) on a 20-frame "
                          "32^3 sequence in the chosen form (about a minute)")
@@ -682,8 +684,9 @@ def main():
         log("ablation (%.0f s): %s" % (time.time() - t0, json.dumps(
             {k: (v["total_iterations"], round(v["seconds"], 2), v["all_reached"])
              for k, v in ablation["variants"].items()})))
-    dwsep = None if a.no_dwsep else dict(ops=dwsep_ops(d2ip, torch),
-                                         network=dwsep_network(d2ip, torch, ts))
+    dwsep = None if a.no_dwsep else dict(
+        ops=dwsep_ops(d2ip, torch),
+        network=None if a.no_network else dwsep_network(d2ip, torch, ts))
     se_unit = None if a.no_dwsep else se_ops(d2ip, torch)
     cpu = None if a.no_cpu else cpu_baseline(p, cfg, a.cpu_seconds)
     out = {
