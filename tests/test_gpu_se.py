@@ -122,3 +122,25 @@ def test_network_modules_match_oracle(lib, shape, sep, r, att, tail, aspp):
     record("modules_network", n=n, levels=L, C=C, sep=sep, se_ratio=r, att=att, tail=tail,
            aspp=aspp, **e)
     assert e["loss"] < 1e-5 and e["grad"] < 2e-4, e
+
+
+def test_se_and_pointwise_backward_are_bitwise_repeatable(lib):
+    """The voxel sums of the SE unit and of the pointwise weight gradient are
+    reduced in a fixed order: two backward passes give the same bits."""
+    import torch
+    from paper_2507_14046_amd import ops
+    rng = np.random.default_rng(77)
+    n, C, H = 24, 32, 8
+    x = dev(rng.standard_normal((n ** 3, C)))
+    g = dev(rng.standard_normal((n ** 3, C)))
+    w1, b1 = dev(rng.standard_normal((H, C)) / 6), dev(rng.standard_normal(H))
+    w2, b2 = dev(rng.standard_normal((C, H)) / 3), dev(rng.standard_normal(C))
+    wp, bp = dev(rng.standard_normal((C, C)) / 6), dev(rng.standard_normal(C))
+    outs = []
+    for _ in range(2):
+        T = [t.clone().requires_grad_(True) for t in (x, w1, b1, w2, b2, wp, bp)]
+        y = ops.PWConv3dFn.apply(ops.SEFn.apply(*T[:5]), T[5], T[6])
+        y.backward(g)
+        outs.append([t.grad.clone() for t in T])
+    for a, b in zip(*outs):
+        assert torch.equal(a, b)
