@@ -238,3 +238,48 @@ def test_misaligned_parameter_views_are_copied_for_the_float4_kernels(L):
         a = ops._a16(v)
         assert a.data_ptr() % 16 == 0 and torch.equal(a, v)
     assert ops._a16(None) is None
+
+
+def test_module_operators_validate_their_arguments(L):
+    """The depthwise, atrous, pointwise and SE entry points reject bad sizes,
+    null and misaligned pointers and short workspaces before touching the
+    device (every call below returns an error from host checks alone)."""
+    lib = L.load()
+    nb = ctypes.c_size_t()
+    sz = ctypes.byref(nb)
+    for args in ((8, 6), (0, 8), (257, 8), (8, 2048), (8, 0)):
+        assert lib.d2ip_op_dwconv3d_bytes(*args, sz) == L.EINVAL, args
+    assert lib.d2ip_op_dwconv3d_bytes(8, 16, None) == L.EINVAL
+    for args in ((8, 16, 0), (8, 16, 300), (8, 6, 2)):
+        assert lib.d2ip_op_dwconv3d_dilated_bytes(*args, sz) == L.EINVAL, args
+    for args in ((8, 6, 8), (8, 8, 2048), (0, 8, 8), (8, 4, 2)):
+        assert lib.d2ip_op_pwconv3d_bytes(*args, sz) == L.EINVAL, args
+    for args in ((8, 16, 0), (8, 16, 300), (8, 6, 4), (8, 2048, 4)):
+        assert lib.d2ip_op_se_bytes(*args, sz) == L.EINVAL, args
+    for ok in ((8, 16), (1, 4), (256, 1024)):
+        assert lib.d2ip_op_dwconv3d_bytes(*ok, sz) == L.OK and nb.value > 0
+    assert lib.d2ip_op_pwconv3d_bytes(8, 4, 4, sz) == L.OK and nb.value > 0
+    assert lib.d2ip_op_se_bytes(8, 1024, 256, sz) == L.OK and nb.value > 0
+    P = ctypes.c_void_p
+    a, odd = P(4096), P(4100)  # never dereferenced: the checks fail first
+    # null and misaligned operands
+    assert lib.d2ip_op_dwconv3d_forward(None, a, None, a, 8, 16, None) == L.EINVAL
+    assert lib.d2ip_op_dwconv3d_forward(odd, a, None, a, 8, 16, None) == L.EINVAL
+    assert b"aligned" in lib.d2ip_last_error()
+    assert lib.d2ip_op_dwconv3d_dilated_forward(a, a, None, odd, 8, 16, 2, None) == L.EINVAL
+    assert lib.d2ip_op_pwconv3d_forward(a, odd, None, a, 8, 16, 16, None) == L.EINVAL
+    assert lib.d2ip_op_se_forward(a, a, a, a, a, None, 8, 16, 4, a, 1 << 30, None) == L.EINVAL
+    # gradients that need x without x, gx without w
+    assert lib.d2ip_op_dwconv3d_backward(None, a, a, None, a, None, 8, 16, a, 1 << 30,
+                                         None) == L.EINVAL
+    assert lib.d2ip_op_pwconv3d_backward(a, None, a, a, None, None, 8, 16, 16, None, 0,
+                                         None) == L.EINVAL
+    # short workspaces
+    assert lib.d2ip_op_dwconv3d_backward(a, a, a, None, a, None, 8, 16, a, 1, None) == L.ENOMEM
+    assert lib.d2ip_op_dwconv3d_dilated_backward(a, a, a, None, a, None, 8, 16, 2, a, 1,
+                                                 None) == L.ENOMEM
+    assert lib.d2ip_op_pwconv3d_backward(a, a, a, None, a, None, 8, 16, 16, a, 1,
+                                         None) == L.ENOMEM
+    assert lib.d2ip_op_se_backward(a, a, a, a, a, a, a, None, None, None, None, 8, 16, 4, a, 1,
+                                   None) == L.ENOMEM
+    assert b"workspace too small" in lib.d2ip_last_error()
