@@ -104,6 +104,22 @@ const char* d2ip_last_error(void);
  * channels.  Host only; needs no GPU. */
 d2ip_status d2ip_param_count(int levels, int base_ch, size_t* out);
 
+/* Kaiming initialisation of the network's parameters (Sec. III-B: the
+ * network starts from Kaiming-initialised weights), host only: every conv
+ * weight W[Cout][Cin][taps] ~ N(0, 2 / (Cin * taps)) (fan-in, ReLU gain),
+ * biases 0, LayerNorm gamma 1 and beta 0, written to `theta` (n =
+ * d2ip_param_count floats, flat order).  The normals come from a
+ * counter-based generator (SplitMix64 outputs 2k, 2k + 1 of the seed's
+ * sequence, Box-Muller) so value k depends only on `seed` and k.  A
+ * convenience for callers without their own generator; parity inputs are
+ * drawn by the caller and passed with d2ip_set_params. */
+d2ip_status d2ip_init_params_host(int levels, int base_ch, uint64_t seed, float* theta, size_t n);
+
+/* HIP_VERSION the library was compiled against, and the version of the HIP
+ * runtime it is bound to in this process (hipRuntimeGetVersion).  A runtime
+ * older than the compile-time headers is reported, not refused. */
+d2ip_status d2ip_runtime_versions(int* compiled, int* loaded);
+
 /* Workspace bytes needed by d2ip_create with the same arguments.  Host only. */
 d2ip_status d2ip_workspace_bytes(const d2ip_geometry_desc* geos, int n_geo,
                                  const d2ip_instance_desc* insts, int n_inst, int precision,
@@ -139,6 +155,10 @@ d2ip_status d2ip_set_geometry(d2ip_ctx* ctx, int geo, const float* J, const uint
 d2ip_status d2ip_set_params(d2ip_ctx* ctx, int inst, const float* theta, size_t n, int on_device);
 d2ip_status d2ip_get_params(d2ip_ctx* ctx, int inst, float* theta, size_t n, int on_device);
 
+/* theta of `inst` from d2ip_init_params_host(levels, base_ch, seed) (Kaiming,
+ * Sec. III-B), uploaded as by d2ip_set_params. */
+d2ip_status d2ip_init_params(d2ip_ctx* ctx, int inst, uint64_t seed);
+
 /* Fixed noise input Z of instance `inst` (Eq. (3)): n^3 FP32. */
 d2ip_status d2ip_set_noise_input(d2ip_ctx* ctx, int inst, const float* z, int on_device);
 
@@ -163,7 +183,10 @@ d2ip_status d2ip_set_state(d2ip_ctx* ctx, int inst, const float* theta_m_v, int6
  * Adam).  Asynchronous unless `last_loss` (n_inst doubles, may be NULL) is
  * given: then it synchronises and stores, per instance, the data loss of the
  * last iteration (evaluated before its update), and returns D2IP_ENONFINITE
- * if any loss was not finite. */
+ * if a loss or an updated parameter was not finite in any iteration since the
+ * parameters were last set (the flag is raised on the device by the loss
+ * reduction and by the Adam kernel, and cleared by d2ip_set_params,
+ * d2ip_set_state and d2ip_init_params). */
 d2ip_status d2ip_run(d2ip_ctx* ctx, int k, double* last_loss);
 
 /* Gradient dL/dtheta of the data loss computed by the last iteration of

@@ -58,6 +58,9 @@ _i = ctypes.c_int
 # name -> argument types (all return int status, except d2ip_last_error)
 SIGNATURES = {
     "d2ip_param_count": [_i, _i, _c_size_p],
+    "d2ip_init_params_host": [_i, _i, ctypes.c_uint64, _vp, ctypes.c_size_t],
+    "d2ip_init_params": [_vp, _i, ctypes.c_uint64],
+    "d2ip_runtime_versions": [ctypes.POINTER(_i), ctypes.POINTER(_i)],
     "d2ip_workspace_bytes": [ctypes.POINTER(GeometryDesc), _i, ctypes.POINTER(InstanceDesc), _i, _i,
                              ctypes.c_uint, _c_size_p],
     "d2ip_check_launches": [ctypes.POINTER(GeometryDesc), _i, ctypes.POINTER(InstanceDesc), _i, _i,

@@ -17,6 +17,23 @@ def param_count(levels, base_ch):
     return out.value
 
 
+def kaiming_params(levels, base_ch, seed):
+    """Kaiming-initialised theta drawn by the library (host only)."""
+    lib = L.load()
+    out = np.empty(param_count(levels, base_ch), dtype=np.float32)
+    L.check(lib.d2ip_init_params_host(levels, base_ch, int(seed),
+                                      out.ctypes.data_as(ctypes.c_void_p), out.size))
+    return out
+
+
+def runtime_versions():
+    """(HIP_VERSION compiled against, version of the HIP runtime in this process)."""
+    lib = L.load()
+    c, r = ctypes.c_int(), ctypes.c_int()
+    L.check(lib.d2ip_runtime_versions(ctypes.byref(c), ctypes.byref(r)))
+    return c.value, r.value
+
+
 def _descs(geometries, instances):
     G = (L.GeometryDesc * len(geometries))(*[L.GeometryDesc(int(n), int(M)) for n, M in geometries])
     I = (L.InstanceDesc * len(instances))(*[L.InstanceDesc(int(g), int(lv), int(c))
@@ -126,6 +143,10 @@ class Context:
     def set_params(self, inst, theta):
         p, d, _k = _in(theta, np.float32)
         L.check(self._lib.d2ip_set_params(self._ctx, inst, p, self.n_params[inst], d))
+
+    def init_params(self, inst, seed):
+        """Kaiming-initialised theta from the library's generator (Sec. III-B)."""
+        L.check(self._lib.d2ip_init_params(self._ctx, inst, int(seed)))
 
     def set_noise_input(self, inst, z):
         p, d, _k = _in(z, np.float32)

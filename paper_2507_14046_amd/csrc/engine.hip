@@ -1288,6 +1288,14 @@ void L_pack(Instance& I, int precision, bool end_iteration, int M, hipStream_t s
   }
 }
 
+// Waits for a stream when it goes out of scope: declared after the host
+// buffers that asynchronous copies on that stream read or write, so that no
+// return path frees them before the copies have run.
+struct StreamDrain {
+  hipStream_t s;
+  ~StreamDrain() { (void)hipStreamSynchronize(s); }
+};
+
 d2ip_status check_inst(d2ip_ctx* X, int inst) {
   if (!X) return fail(D2IP_EINVAL, "null context");
   if (inst < 0 || inst >= (int)X->members.size()) return fail(D2IP_EINVAL, "bad instance index");
@@ -1397,6 +1405,76 @@ d2ip_status d2ip_param_count(int levels, int base_ch, size_t* out) {
   I.C = base_ch;
   *out = layout(I);
   return D2IP_OK;
+}
+
+d2ip_status d2ip_runtime_versions(int* compiled, int* loaded) {
+  if (!compiled || !loaded) return fail(D2IP_EINVAL, "null output");
+  *compiled = HIP_VERSION;
+  *loaded = 0;
+  HIPCHK(hipRuntimeGetVersion(loaded));
+  return D2IP_OK;
+}
+
+d2ip_status d2ip_init_params_host(int levels, int base_ch, uint64_t seed, float* theta,
+                                  size_t n) {
+  size_t P = 0;
+  d2ip_status st = d2ip_param_count(levels, base_ch, &P);
+  if (st != D2IP_OK) return st;
+  if (!theta || n != P) return fail(D2IP_EINVAL, "theta must hold " + std::to_string(P) + " floats");
+  Instance I;
+  I.L = levels;
+  I.C = base_ch;
+  I.n = 2 << levels;  // offsets do not depend on the grid
+  layout(I);
+  // Standard normals from a counter-based generator: value k of the flat
+  // vector uses SplitMix64 outputs 2k and 2k + 1 (Box-Muller), so a draw
+  // depends only on the seed and the parameter's index.
+  auto mix = [](uint64_t z) {
+    z += 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+  };
+  auto normal = [&](size_t k) {
+    const uint64_t base = seed * 0x100000001B3ull;
+    const double u1 = ((mix(base + 2 * k) >> 11) + 1.0) * (1.0 / 9007199254740993.0);  // (0, 1]
+    const double u2 = (mix(base + 2 * k + 1) >> 11) * (1.0 / 9007199254740992.0);      // [0, 1)
+    return std::sqrt(-2.0 * std::log(u1)) * std::cos(6.283185307179586 * u2);
+  };
+  // Kaiming (fan-in, ReLU gain): W ~ N(0, 2 / (cin * taps)), biases 0
+  auto conv = [&](int th_w, int th_b, int cout, int cin, int taps) {
+    const double sd = std::sqrt(2.0 / ((double)cin * taps));
+    for (size_t k = 0; k < (size_t)cout * cin * taps; ++k)
+      theta[th_w + k] = (float)(sd * normal(th_w + k));
+    for (int k = 0; k < cout; ++k) theta[th_b + k] = 0.f;
+  };
+  auto norm = [&](const Norm& nm, int c) {  // gamma 1, beta 0
+    for (int k = 0; k < c; ++k) {
+      theta[nm.th_g + k] = 1.f;
+      theta[nm.th_b + k] = 0.f;
+    }
+  };
+  conv(I.stem.th_w, I.stem.th_b, I.stem.cout, I.stem.cin_real, I.stem.taps);
+  norm(I.stem_n, I.C);
+  for (const Block& b : I.blocks) {
+    conv(b.c1.th_w, b.c1.th_b, b.cout, b.cin, 27);
+    norm(b.n1, b.cout);
+    conv(b.c2.th_w, b.c2.th_b, b.cout, b.cout, 27);
+    norm(b.n2, b.cout);
+    if (b.proj) conv(b.pj.th_w, b.pj.th_b, b.cout, b.cin, 1);
+  }
+  conv(I.tail_w, I.tail_b, 1, I.C, 1);
+  return D2IP_OK;
+}
+
+d2ip_status d2ip_init_params(d2ip_ctx* X, int inst, uint64_t seed) {
+  d2ip_status st = check_inst(X, inst);
+  if (st != D2IP_OK) return st;
+  const Instance& I = X->insts[X->members[inst].first];
+  std::vector<float> th(I.P);
+  st = d2ip_init_params_host(I.L, I.C, seed, th.data(), th.size());
+  if (st != D2IP_OK) return st;
+  return d2ip_set_params(X, inst, th.data(), th.size(), 0);
 }
 
 d2ip_status d2ip_check_launches(const d2ip_geometry_desc* geos, int n_geo,
@@ -1687,6 +1765,7 @@ d2ip_status d2ip_set_geometry(d2ip_ctx* X, int geo, const float* J, const uint8_
   if (!J || !mask) return fail(D2IP_EINVAL, "null J or mask");
   Geometry& G = X->geos[geo];
   std::vector<uint8_t> hm(G.Q);
+  StreamDrain drain_mask{X->stream};
   if (on_device) {
     HIPCHK(hipMemcpyAsync(hm.data(), mask, G.Q, hipMemcpyDeviceToHost, X->stream));
     HIPCHK(hipStreamSynchronize(X->stream));
@@ -1707,6 +1786,10 @@ d2ip_status d2ip_set_geometry(d2ip_ctx* X, int geo, const float* J, const uint8_
   const int qa_pad = (qa + 63) / 64 * 64;
   std::vector<int> idxp(qa_pad, idx[0]);
   std::copy(idx.begin(), idx.end(), idxp.begin());
+  std::vector<float> jc;  // compacted J (host input)
+  // the host buffers above are the sources of asynchronous copies: every
+  // return below waits for the stream before they are freed
+  StreamDrain drain{X->stream};
   HIPCHK(hipMemcpyAsync(G.idx, idxp.data(), qa_pad * sizeof(int), hipMemcpyHostToDevice, X->stream));
   HIPCHK(hipMemcpyAsync(G.inv, inv.data(), G.Q * sizeof(int), hipMemcpyHostToDevice, X->stream));
   HIPCHK(hipMemcpyAsync(G.mask, maskf.data(), G.Q * sizeof(float), hipMemcpyHostToDevice, X->stream));
@@ -1714,7 +1797,7 @@ d2ip_status d2ip_set_geometry(d2ip_ctx* X, int geo, const float* J, const uint8_
     gather_columns(J, G.M, (int)G.Q, G.idx, qa, qa_pad, G.Jc, X->stream);
     HIPCHK(hipGetLastError());
   } else {
-    std::vector<float> jc((size_t)G.M * qa_pad, 0.f);
+    jc.assign((size_t)G.M * qa_pad, 0.f);
     for (int m = 0; m < G.M; ++m) {
       const float* row = J + (size_t)m * G.Q;
       float* dst = jc.data() + (size_t)m * qa_pad;
@@ -1741,6 +1824,7 @@ d2ip_status d2ip_set_params(d2ip_ctx* X, int inst, const float* theta, size_t n,
     return fail(D2IP_EINVAL, "theta must hold " + std::to_string(I.P) + " floats");
   st = copy_in(X, ishift(I.theta, mo), theta, n * sizeof(float), on_device);
   if (st != D2IP_OK) return st;
+  zero_words(&ishift(I.it, mo)->nonfinite, 1, X->stream);  // new parameters, no stale flag
   return repack(X, I);
 }
 
@@ -1819,9 +1903,10 @@ d2ip_status d2ip_reset_optimizer(d2ip_ctx* X, int inst) {
   Instance& I = X->insts[X->members[inst].first];
   const int mb = X->members[inst].second;
   const long long mo = (long long)mb * I.istride;
-  HIPCHK(hipMemsetAsync(ishift(I.m, mo), 0, I.P * sizeof(float), X->stream));
-  HIPCHK(hipMemsetAsync(ishift(I.v, mo), 0, I.P * sizeof(float), X->stream));
-  HIPCHK(hipMemsetAsync(&ishift(I.it, mo)->t, 0, sizeof(int), X->stream));
+  zero_words(ishift(I.m, mo), I.P, X->stream);
+  zero_words(ishift(I.v, mo), I.P, X->stream);
+  zero_words(&ishift(I.it, mo)->t, 1, X->stream);
+  HIPCHK(hipGetLastError());
   return D2IP_OK;
 }
 
@@ -1838,6 +1923,7 @@ d2ip_status d2ip_get_state(d2ip_ctx* X, int inst, float* tmv, int64_t* t, int on
   HIPCHK(hipMemcpyAsync(tmv + I.P, ishift(I.m, mo), b, k, X->stream));
   HIPCHK(hipMemcpyAsync(tmv + 2 * I.P, ishift(I.v, mo), b, k, X->stream));
   int tt = 0;
+  StreamDrain drain{X->stream};
   HIPCHK(hipMemcpyAsync(&tt, &ishift(I.it, mo)->t, sizeof(int), hipMemcpyDeviceToHost, X->stream));
   HIPCHK(hipStreamSynchronize(X->stream));
   *t = tt;
@@ -1854,10 +1940,12 @@ d2ip_status d2ip_set_state(d2ip_ctx* X, int inst, const float* tmv, int64_t t, i
   const size_t b = I.P * sizeof(float);
   const hipMemcpyKind k = kind_to_dev(on_device);
   int tt = (int)t;
+  StreamDrain drain{X->stream};
   HIPCHK(hipMemcpyAsync(ishift(I.theta, mo), tmv, b, k, X->stream));
   HIPCHK(hipMemcpyAsync(ishift(I.m, mo), tmv + I.P, b, k, X->stream));
   HIPCHK(hipMemcpyAsync(ishift(I.v, mo), tmv + 2 * I.P, b, k, X->stream));
   HIPCHK(hipMemcpyAsync(&ishift(I.it, mo)->t, &tt, sizeof(int), hipMemcpyHostToDevice, X->stream));
+  zero_words(&ishift(I.it, mo)->nonfinite, 1, X->stream);
   HIPCHK(hipStreamSynchronize(X->stream));
   return repack(X, I);
 }
@@ -1905,12 +1993,13 @@ d2ip_status d2ip_run(d2ip_ctx* X, int k, double* last_loss) {
       const Instance& I = X->insts[X->members[i].first];
       const long long mo = (long long)X->members[i].second * I.istride;
       IterState h;
+      StreamDrain drain{X->stream};
       HIPCHK(hipMemcpyAsync(&h, ishift(I.it, mo), sizeof(h), hipMemcpyDeviceToHost, X->stream));
       HIPCHK(hipStreamSynchronize(X->stream));
       last_loss[i] = h.loss;
       if (h.nonfinite) bad = true;
     }
-    if (bad) return fail(D2IP_ENONFINITE, "a non-finite loss was produced");
+    if (bad) return fail(D2IP_ENONFINITE, "a non-finite loss or parameter was produced");
   }
   return D2IP_OK;
 }
@@ -2006,6 +2095,7 @@ d2ip_status put_tv_state(d2ip_ctx* X, Instance& I, int mb) {
   double sum = 0.0;
   for (int k = 1; k <= t.count; ++k) sum += std::exp(-(double)k);
   for (int k = 1; k <= t.count; ++k) t.w[k - 1] = (float)(std::exp(-(double)k) / sum);
+  StreamDrain drain{X->stream};
   HIPCHK(hipMemcpyAsync(ishift(I.tvs, (long long)mb * I.istride), &t, sizeof(t),
                         hipMemcpyHostToDevice, X->stream));
   HIPCHK(hipStreamSynchronize(X->stream));

@@ -374,7 +374,7 @@ __global__ __launch_bounds__(256) void k_tail_bwd(const float* tpart, int nmb, i
 }
 
 __global__ void k_adam(float* theta, const float* g, float* m, float* v, size_t P, float lr,
-                       float beta1, float beta2, float eps, const IterState* it,
+                       float beta1, float beta2, float eps, IterState* it,
                        long long istride) {
   {
     const long long off = (long long)blockIdx.y * istride;
@@ -391,6 +391,7 @@ __global__ void k_adam(float* theta, const float* g, float* m, float* v, size_t 
   const float bc1 = sbc[0], bc2 = sbc[1];
   const float step = lr / bc1;
   const float rs2 = 1.f / sqrtf(bc2);
+  bool bad = false;
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < P;
        i += (size_t)gridDim.x * blockDim.x) {
     const float gi = g[i];
@@ -398,8 +399,12 @@ __global__ void k_adam(float* theta, const float* g, float* m, float* v, size_t 
     const float vi = beta2 * v[i] + (1.f - beta2) * gi * gi;
     m[i] = mi;
     v[i] = vi;
-    theta[i] -= step * mi / (sqrtf(vi) * rs2 + eps);
+    const float th = theta[i] - step * mi / (sqrtf(vi) * rs2 + eps);
+    theta[i] = th;
+    bad |= !isfinite(th);
   }
+  // a non-finite parameter raises the instance's flag (bit 1; bit 0 is the loss)
+  if (__syncthreads_or(bad) && threadIdx.x == 0) atomicOr(&it->nonfinite, 2);
 }
 
 __device__ __forceinline__ void put_bf(uint16_t* w, long long i, long long lo_off, float val) {
@@ -623,7 +628,7 @@ void tail_bwd(const float* tpart, int nmb, int qa_pad, const int* inv, const flo
 }
 
 void adam(float* theta, const float* g, float* m, float* v, size_t P, float lr, float beta1,
-          float beta2, float eps, const IterState* it, int batch, long long istride,
+          float beta2, float eps, IterState* it, int batch, long long istride,
           hipStream_t s) {
   hipLaunchKernelGGL(k_adam, dim3(grid_for(P), batch), dim3(256), 0, s, theta, g, m, v, P, lr,
                      beta1, beta2, eps, it, istride);

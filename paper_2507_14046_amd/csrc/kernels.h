@@ -135,6 +135,8 @@ void up_concat_bwd(const float* gcat, int Cu, int Cs, int n, float* gu, float* g
 void pool_bwd_add(const float* gx, const float* add, int n, int C, float* gy, int batch,
                   long long istride, hipStream_t s);
 void pad_input(const float* z, size_t V, float* zp, hipStream_t s);
+// n 4-byte words at p set to zero by a kernel (a graph records a kernel node)
+void zero_words(void* p, size_t n, hipStream_t s);
 
 // ---- measurement operator, loss, tail, Adam (jops.hip) ----------------------
 struct IterState {
@@ -212,9 +214,10 @@ int tail_bwd_blocks(size_t V, int C);
 void tail_bwd(const float* tpart, int nmb, int qa_pad, const int* inv, const float* d0, int C,
               const float* w, size_t V, float* gd0, double* part, const float* gtv, int batch,
               long long istride, hipStream_t s);
-// Adam step t + 1 (t = it->t, bias corrections 1 - beta^(t+1)).
+// Adam step t + 1 (t = it->t, bias corrections 1 - beta^(t+1)); a non-finite
+// updated parameter sets bit 1 of it->nonfinite.
 void adam(float* theta, const float* g, float* m, float* v, size_t P, float lr, float beta1,
-          float beta2, float eps, const IterState* it, int batch, long long istride,
+          float beta2, float eps, IterState* it, int batch, long long istride,
           hipStream_t s);
 // Packed conv weights from theta; with lo_off > 0 the bf16 lo parts
 // (bf16(w - bf16(w))) are written lo_off elements after the hi parts.  When

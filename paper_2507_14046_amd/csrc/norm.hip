@@ -420,6 +420,19 @@ void pool_bwd_add(const float* gx, const float* add, int n, int C, float* gy, in
                      C / 4, reinterpret_cast<float4*>(gy), istride);
 }
 
+__global__ void k_zero_words(int* p, size_t n) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (size_t)gridDim.x * blockDim.x)
+    p[i] = 0;
+}
+
+void zero_words(void* p, size_t n, hipStream_t s) {
+  if (n == 0) return;
+  const size_t blocks = std::min<size_t>((n + 255) / 256, 1024);
+  hipLaunchKernelGGL(k_zero_words, dim3((unsigned)blocks), dim3(256), 0, s,
+                     reinterpret_cast<int*>(p), n);
+}
+
 void pad_input(const float* z, size_t V, float* zp, hipStream_t s) {
   hipLaunchKernelGGL(k_pad_input, dim3(grid_for(V * 8)), dim3(256), 0, s, z, V, zp);
 }

@@ -21,6 +21,14 @@ using namespace d2ip;
 
 namespace {
 
+// One small descriptor written to device memory from a kernel argument: the
+// host value it comes from may end with the calling frame, and the write is
+// an ordinary kernel node when a caller captures the operator in a graph.
+template <class T>
+__global__ void k_put(T* dst, T v) {
+  if (threadIdx.x == 0) *dst = v;
+}
+
 #define OPCHK(expr)                                                                      \
   do {                                                                                   \
     hipError_t e_ = (expr);                                                              \
@@ -122,11 +130,10 @@ ConvPack make_pack(const ConvOp& c) {
 // Upload the packing table (and zero the split-K counters) once per call and
 // pack w into the forward and input-gradient layouts.
 d2ip_status conv_prepare(ConvOp& c, const float* w, hipStream_t s) {
-  const ConvPack p = make_pack(c);
-  OPCHK(hipMemcpyAsync(c.pack, &p, sizeof(p), hipMemcpyHostToDevice, s));
+  hipLaunchKernelGGL(k_put<ConvPack>, dim3(1), dim3(64), 0, s, c.pack, make_pack(c));
   const int tf = conv_tiles(c.n, c.f_tile) * ((c.cout + c.f_bn - 1) / c.f_bn);
   const int td = conv_tiles(c.n, c.d_tile) * ((c.cin + c.d_bn - 1) / c.d_bn);
-  OPCHK(hipMemsetAsync(c.counters, 0, ((size_t)std::max(tf, td) + 64) * sizeof(int), s));
+  zero_words(c.counters, (size_t)std::max(tf, td) + 64, s);
   pack_weights(c.pack, 1, c.cout * c.cin * c.taps, w, c.wf32, c.wbf16,
                c.prec == PREC_BF16X3 ? c.wtotal : 0, nullptr, nullptr, 0, 1, nullptr, 0, 1, 0, s);
   return D2IP_OK;
@@ -303,7 +310,7 @@ d2ip_status d2ip_op_conv3d_backward(const float* x, const float* w, const float*
     g.cin_real = cin;
     g.th_w = 0;
     g.th_b = cout * cin * taps;
-    OPCHK(hipMemcpyAsync(c.seg, &g, sizeof(g), hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(k_put<GradSeg>, dim3(1), dim3(64), 0, s, c.seg, g);
     grad_reduce(c.seg, 1, cout * cin * taps, c.part, c.partb, nullptr, c.grad, 1, 0, s);
     const size_t wel = (size_t)cout * cin * taps;
     if (gw) OPCHK(hipMemcpyAsync(gw, c.grad, wel * 4, hipMemcpyDeviceToDevice, s));
@@ -375,7 +382,7 @@ d2ip_status d2ip_op_ln_relu_backward(const float* x, const float* y, const float
     g.splits = l.nb;
     g.cout = 2 * C;
     g.th_w = 0;
-    OPCHK(hipMemcpyAsync(l.seg, &g, sizeof(g), hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(k_put<GradSeg>, dim3(1), dim3(64), 0, s, l.seg, g);
     grad_reduce(l.seg, 1, 2 * C, nullptr, nullptr, l.part_c, dgamma_dbeta, 1, 0, s);
   }
   OPCHK(hipGetLastError());

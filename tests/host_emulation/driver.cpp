@@ -6,11 +6,15 @@
 #include <cstdio>
 #include <cstdlib>
 #include <random>
+#include <string>
 #include <vector>
 
 #include "d2ip.h"
 
 extern "C" long g_launches;
+extern "C" long g_captured_launches;
+extern "C" long emu_errors(void);
+extern "C" void emu_flush_all(void);
 
 #define CK(x)                                                              \
   do {                                                                     \
@@ -34,12 +38,11 @@ static int run_case(const std::vector<d2ip_geometry_desc>& G,
   CK(d2ip_workspace_bytes(G.data(), (int)G.size(), I.data(), (int)I.size(), prec, flags, &need));
   char* ws = (char*)aligned_alloc(256, (need + 255) / 256 * 256);
   d2ip_ctx* X = nullptr;
-  int stream_token = 0;
   EXPECT_ERR(d2ip_create(G.data(), (int)G.size(), I.data(), (int)I.size(), prec, flags, ws,
-                         need - 1, &stream_token, &X),
+                         need - 1, nullptr, &X),
              D2IP_ENOMEM);
   CK(d2ip_create(G.data(), (int)G.size(), I.data(), (int)I.size(), prec, flags, ws, need,
-                 &stream_token, &X));
+                 nullptr, &X));
   std::vector<double> loss(I.size());
   EXPECT_ERR(d2ip_run(X, 1, loss.data()), D2IP_ESTATE);
   std::mt19937 rng(1);
@@ -105,6 +108,7 @@ static int run_case(const std::vector<d2ip_geometry_desc>& G,
   CK(d2ip_run(X, 3, loss.data()));
   CK(d2ip_check_launches(G.data(), (int)G.size(), I.data(), (int)I.size(), prec, flags));
   CK(d2ip_destroy(X));
+  emu_flush_all();  // the caller frees device memory after its stream has passed
   free(ws);
   printf("ok: %zu geometries, %zu instances, precision %d, flags %u\n", G.size(), I.size(), prec,
          flags);
@@ -124,9 +128,9 @@ static int tuning_case() {
     CK(d2ip_time_conv_bytes(&t, &need));
     char* ws = (char*)aligned_alloc(256, (need + 255) / 256 * 256);
     double ms = 0.0;
-    int token = 0;
-    EXPECT_ERR(d2ip_time_conv(&t, ws, need - 1, &token, 2, &ms), D2IP_ENOMEM);
-    CK(d2ip_time_conv(&t, ws, need, &token, 2, &ms));
+    EXPECT_ERR(d2ip_time_conv(&t, ws, need - 1, nullptr, 2, &ms), D2IP_ENOMEM);
+    CK(d2ip_time_conv(&t, ws, need, nullptr, 2, &ms));
+    emu_flush_all();  // the caller frees device memory after its stream has passed
     free(ws);
   }
   CK(d2ip_set_tuning(e.data(), count));
@@ -145,7 +149,6 @@ static int ops_case() {
   std::vector<float> x((size_t)Q * 32, 0.f), y((size_t)Q * 32), w((size_t)cout * cin * 27),
       b(cout), g((size_t)Q * 32), gx((size_t)Q * 32), gw(w.size()), gb(cout), gam(C, 1.f),
       bet(C), gs((size_t)Q * C), ggb(2 * C), J((size_t)M * Q), p(M), out(Q);
-  int token = 0;
   for (int taps : {27, 1})
     for (int prec = 0; prec < 3; ++prec) {
       size_t need = 0;
@@ -153,12 +156,13 @@ static int ops_case() {
       char* ws = (char*)aligned_alloc(256, (need + 255) / 256 * 256);
       std::vector<float> wt((size_t)cout * cin * taps);
       CK(d2ip_op_conv3d_forward(x.data(), wt.data(), b.data(), y.data(), n, cin, cout, taps, prec,
-                                ws, need, &token));
+                                ws, need, nullptr));
       CK(d2ip_op_conv3d_backward(x.data(), wt.data(), g.data(), gx.data(), gw.data(), gb.data(), n,
-                                 cin, cout, taps, prec, ws, need, &token));
+                                 cin, cout, taps, prec, ws, need, nullptr));
       EXPECT_ERR(d2ip_op_conv3d_forward(x.data(), wt.data(), b.data(), y.data(), n, cin, cout,
-                                        taps, prec, ws, need - 1, &token),
+                                        taps, prec, ws, need - 1, nullptr),
                  D2IP_ENOMEM);
+      emu_flush_all();  // the caller frees device memory after its stream has passed
       free(ws);
     }
   size_t need = 0;
@@ -166,21 +170,23 @@ static int ops_case() {
   CK(d2ip_op_ln_relu_bytes(n, C, &need));
   char* ws = (char*)aligned_alloc(256, (need + 255) / 256 * 256);
   CK(d2ip_op_ln_relu_forward(x.data(), gam.data(), bet.data(), nullptr, y.data(), n, C, ws, need,
-                             &token));
+                             nullptr));
   CK(d2ip_op_ln_relu_backward(x.data(), y.data(), gam.data(), g.data(), gx.data(), gs.data(),
-                              ggb.data(), n, C, ws, need, &token));
+                              ggb.data(), n, C, ws, need, nullptr));
+  emu_flush_all();  // the caller frees device memory after its stream has passed
   free(ws);
   EXPECT_ERR(d2ip_op_ln_relu_bytes(n, 12, &need), D2IP_EINVAL);
   for (int Cd : {4, 8, 12, 16, 32}) {
     std::vector<float> wd((size_t)Cd * 27), bd(Cd), gwd(wd.size()), gbd(Cd);
     CK(d2ip_op_dwconv3d_bytes(n, Cd, &need));
     ws = (char*)aligned_alloc(256, (need + 255) / 256 * 256);
-    CK(d2ip_op_dwconv3d_forward(x.data(), wd.data(), bd.data(), y.data(), n, Cd, &token));
+    CK(d2ip_op_dwconv3d_forward(x.data(), wd.data(), bd.data(), y.data(), n, Cd, nullptr));
     CK(d2ip_op_dwconv3d_backward(x.data(), wd.data(), g.data(), gx.data(), gwd.data(), gbd.data(),
-                                 n, Cd, ws, need, &token));
+                                 n, Cd, ws, need, nullptr));
     EXPECT_ERR(d2ip_op_dwconv3d_backward(x.data(), wd.data(), g.data(), gx.data(), gwd.data(),
-                                         nullptr, n, Cd, ws, need - 1, &token),
+                                         nullptr, n, Cd, ws, need - 1, nullptr),
                D2IP_ENOMEM);
+    emu_flush_all();  // the caller frees device memory after its stream has passed
     free(ws);
   }
   EXPECT_ERR(d2ip_op_dwconv3d_bytes(n, 6, &need), D2IP_EINVAL);
@@ -189,9 +195,10 @@ static int ops_case() {
     CK(d2ip_op_dwconv3d_dilated_bytes(n, 16, dil, &need));
     ws = (char*)aligned_alloc(256, (need + 255) / 256 * 256);
     CK(d2ip_op_dwconv3d_dilated_forward(x.data(), wd.data(), bd.data(), y.data(), n, 16, dil,
-                                        &token));
+                                        nullptr));
     CK(d2ip_op_dwconv3d_dilated_backward(x.data(), wd.data(), g.data(), gx.data(), gwd.data(),
-                                         gbd.data(), n, 16, dil, ws, need, &token));
+                                         gbd.data(), n, 16, dil, ws, need, nullptr));
+    emu_flush_all();  // the caller frees device memory after its stream has passed
     free(ws);
   }
   EXPECT_ERR(d2ip_op_dwconv3d_dilated_bytes(n, 16, 0, &need), D2IP_EINVAL);
@@ -202,12 +209,13 @@ static int ops_case() {
       std::vector<float> wpw((size_t)ci * co), bpw(co), gwp(wpw.size()), gbp(co),
           ybig((size_t)Q * co), gbig((size_t)Q * co);
       CK(d2ip_op_pwconv3d_forward(x.data(), wpw.data(), bpw.data(), ybig.data(), n, ci, co,
-                                  &token));
+                                  nullptr));
       CK(d2ip_op_pwconv3d_backward(x.data(), wpw.data(), gbig.data(), gx.data(), gwp.data(),
-                                   gbp.data(), n, ci, co, ws, need, &token));
+                                   gbp.data(), n, ci, co, ws, need, nullptr));
       EXPECT_ERR(d2ip_op_pwconv3d_backward(x.data(), wpw.data(), gbig.data(), nullptr,
-                                           gwp.data(), nullptr, n, ci, co, ws, need - 1, &token),
+                                           gwp.data(), nullptr, n, ci, co, ws, need - 1, nullptr),
                  D2IP_ENOMEM);
+      emu_flush_all();  // the caller frees device memory after its stream has passed
       free(ws);
     }
   EXPECT_ERR(d2ip_op_pwconv3d_bytes(n, 6, 8, &need), D2IP_EINVAL);
@@ -218,28 +226,207 @@ static int ops_case() {
       std::vector<float> a1((size_t)Hs * Cs), c1(Hs), a2((size_t)Cs * Hs), c2(Cs);
       std::vector<float> ga1(a1.size()), gc1(Hs), ga2(a2.size()), gc2(Cs);
       CK(d2ip_op_se_forward(x.data(), a1.data(), c1.data(), a2.data(), c2.data(), y.data(), n,
-                            Cs, Hs, ws, need, &token));
+                            Cs, Hs, ws, need, nullptr));
       CK(d2ip_op_se_backward(x.data(), a1.data(), c1.data(), a2.data(), c2.data(), g.data(),
                              gx.data(), ga1.data(), gc1.data(), ga2.data(), gc2.data(), n, Cs, Hs,
-                             ws, need, &token));
+                             ws, need, nullptr));
       EXPECT_ERR(d2ip_op_se_forward(x.data(), a1.data(), c1.data(), a2.data(), c2.data(),
-                                    y.data(), n, Cs, Hs, ws, need - 1, &token),
+                                    y.data(), n, Cs, Hs, ws, need - 1, nullptr),
                  D2IP_ENOMEM);
+      emu_flush_all();  // the caller frees device memory after its stream has passed
       free(ws);
     }
   EXPECT_ERR(d2ip_op_se_bytes(n, 16, 0, &need), D2IP_EINVAL);
-  EXPECT_ERR(d2ip_op_dwconv3d_forward(x.data() + 1, gam.data(), nullptr, y.data(), n, C, &token),
+  EXPECT_ERR(d2ip_op_dwconv3d_forward(x.data() + 1, gam.data(), nullptr, y.data(), n, C, nullptr),
              D2IP_EINVAL);
-  CK(d2ip_op_j_forward(J.data(), x.data(), p.data(), M, Q, &token));
+  CK(d2ip_op_j_forward(J.data(), x.data(), p.data(), M, Q, nullptr));
   CK(d2ip_op_jt_bytes(M, Q, &need));
   ws = (char*)aligned_alloc(256, (need + 255) / 256 * 256);
-  CK(d2ip_op_jt(J.data(), p.data(), out.data(), M, Q, ws, need, &token));
+  CK(d2ip_op_jt(J.data(), p.data(), out.data(), M, Q, ws, need, nullptr));
+  emu_flush_all();  // the caller frees device memory after its stream has passed
   free(ws);
   printf("ok: standalone operators\n");
   return 0;
 }
 
-int main() {
+
+// ---------------------------------------------------------------------------
+// The benchmark's C-ABI call sequence, replayed on the emulation: each
+// workload's context created, loaded from host arrays, run (warm-up with a
+// loss read, timed iterations without, a final loss read), its image read and
+// the context destroyed, one context after another, in the order and with the
+// shapes the benchmark uses; the kernel table of the chosen form; the
+// multi-instance workloads.
+// ---------------------------------------------------------------------------
+struct Problem {
+  int n, M;
+  std::vector<float> J, z, dv;
+  std::vector<uint8_t> mask;
+};
+
+static Problem make_problem(int n, int M, unsigned seed) {
+  Problem p;
+  p.n = n;
+  p.M = M;
+  const size_t Q = (size_t)n * n * n;
+  std::mt19937 rng(seed);
+  std::normal_distribution<float> nd;
+  p.J.resize((size_t)M * Q);
+  for (float& v : p.J) v = nd(rng);
+  p.mask.resize(Q);
+  for (int z = 0; z < n; ++z)
+    for (int y = 0; y < n; ++y)
+      for (int x = 0; x < n; ++x) {
+        const double cx = -1.0 + (2.0 * x + 1.0) / n, cy = -1.0 + (2.0 * y + 1.0) / n;
+        p.mask[((size_t)z * n + y) * n + x] = cx * cx + cy * cy <= 1.0;
+      }
+  p.z.resize(Q);
+  for (float& v : p.z) v = nd(rng);
+  p.dv.resize(M);
+  for (float& v : p.dv) v = 0.01f * nd(rng);
+  return p;
+}
+
+static int load_instance(d2ip_ctx* X, int inst, const Problem& p, int levels, int C, bool geo,
+                         int geo_index, unsigned seed) {
+  if (geo) CK(d2ip_set_geometry(X, geo_index, p.J.data(), p.mask.data(), 0));
+  size_t P = 0;
+  CK(d2ip_param_count(levels, C, &P));
+  std::vector<float> th(P);
+  std::mt19937 rng(seed);
+  std::normal_distribution<float> nd;
+  for (float& v : th) v = 0.05f * nd(rng);
+  CK(d2ip_set_params(X, inst, th.data(), P, 0));
+  CK(d2ip_set_noise_input(X, inst, p.z.data(), 0));
+  CK(d2ip_set_frame(X, inst, p.dv.data(), 0));
+  return 0;
+}
+
+// One single-instance workload as the benchmark times it.
+static int single_form(const Problem& p, int levels, int C, int prec, unsigned flags, int steps,
+                       int warmup, bool tv, bool kernels) {
+  const d2ip_geometry_desc G[1] = {{p.n, p.M}};
+  const d2ip_instance_desc I[1] = {{0, levels, C}};
+  size_t need = 0;
+  CK(d2ip_workspace_bytes(G, 1, I, 1, prec, flags, &need));
+  char* ws = (char*)aligned_alloc(256, (need + 255) / 256 * 256);
+  d2ip_ctx* X = nullptr;
+  CK(d2ip_create(G, 1, I, 1, prec, flags, ws, need, nullptr, &X));
+  if (load_instance(X, 0, p, levels, C, true, 0, 7)) return 1;
+  d2ip_adam_cfg cfg = {1e-3f, 0.9f, 0.999f, 1e-8f};
+  CK(d2ip_set_adam(X, &cfg));
+  if (tv) {
+    d2ip_tv_cfg t = {0.002f, 1.f, 0.1f, 1e-8f};
+    CK(d2ip_set_tv(X, &t));
+  }
+  double loss = 0.0;
+  CK(d2ip_run(X, warmup, &loss));
+  CK(d2ip_run(X, steps, nullptr));
+  CK(d2ip_run(X, 0, &loss));
+  std::vector<float> img((size_t)p.n * p.n * p.n);
+  CK(d2ip_read_image(X, 0, img.data(), 0));
+  if (kernels) {
+    double ms = 0.0;
+    CK(d2ip_time_kernel(X, 0, D2IP_KERNEL_JVEC, 0, 50, &ms));
+    CK(d2ip_time_kernel(X, 0, D2IP_KERNEL_JTVEC, 0, 50, &ms));
+    const int nblocks = 2 * levels - 1;
+    for (int b = 0; b < nblocks; ++b)
+      for (int k = D2IP_KERNEL_CONV_FWD; k <= D2IP_KERNEL_CONV_WGRAD; ++k)
+        CK(d2ip_time_kernel(X, 0, k, b, 20, &ms));
+    CK(d2ip_time_kernel(X, 0, D2IP_KERNEL_ADAM, 0, 50, &ms));
+  }
+  CK(d2ip_destroy(X));
+  emu_flush_all();  // the caller frees device memory after its stream has passed
+  free(ws);
+  return 0;
+}
+
+// Several instances in one context (sequences with frame transitions, or
+// uneven instances), as the benchmark's multi-instance workloads run them.
+static int multi(const std::vector<Problem*>& geos, const std::vector<d2ip_instance_desc>& I,
+                 int prec, unsigned flags, int first, int later, int frames) {
+  std::vector<d2ip_geometry_desc> G;
+  for (const Problem* p : geos) G.push_back({p->n, p->M});
+  size_t need = 0;
+  CK(d2ip_workspace_bytes(G.data(), (int)G.size(), I.data(), (int)I.size(), prec, flags, &need));
+  char* ws = (char*)aligned_alloc(256, (need + 255) / 256 * 256);
+  d2ip_ctx* X = nullptr;
+  CK(d2ip_create(G.data(), (int)G.size(), I.data(), (int)I.size(), prec, flags, ws, need, nullptr,
+                 &X));
+  std::vector<char> done(G.size(), 0);
+  for (size_t i = 0; i < I.size(); ++i) {
+    const int g = I[i].geometry;
+    if (load_instance(X, (int)i, *geos[g], I[i].levels, I[i].base_ch, !done[g], g,
+                      100 + (unsigned)i))
+      return 1;
+    done[g] = 1;
+  }
+  d2ip_adam_cfg cfg = {1e-3f, 0.9f, 0.999f, 1e-8f};
+  CK(d2ip_set_adam(X, &cfg));
+  CK(d2ip_run(X, first, nullptr));
+  for (int f = 0; f < frames; ++f) {
+    for (size_t i = 0; i < I.size(); ++i) {
+      CK(d2ip_set_frame(X, (int)i, geos[I[i].geometry]->dv.data(), 0));
+      CK(d2ip_reset_optimizer(X, (int)i));
+    }
+    CK(d2ip_run(X, later, nullptr));
+  }
+  std::vector<double> loss(I.size());
+  CK(d2ip_run(X, 0, loss.data()));
+  CK(d2ip_destroy(X));
+  emu_flush_all();  // the caller frees device memory after its stream has passed
+  free(ws);
+  return 0;
+}
+
+static int bench_sequence(bool large) {
+  Problem c1 = make_problem(32, 928, 1), c0 = make_problem(16, 208, 0);
+  const int steps = 20, warmup = 5;
+  for (int prec : {0, 2, 1})
+    for (unsigned fl : {1u, 0u})
+      if (single_form(c1, 3, 16, prec, fl, steps, warmup, false, false)) return 1;
+  if (single_form(c1, 3, 16, 0, 0, steps, warmup, false, false)) return 1;  // plain
+  if (single_form(c1, 3, 16, 0, 0, steps, warmup, true, false)) return 1;   // 4D-TV
+  if (single_form(c1, 3, 16, 0, 0, 0, warmup, false, true)) return 1;       // kernel table
+  for (int prec : {0, 1})
+    for (unsigned fl : {1u, 0u})
+      if (single_form(c0, 2, 8, prec, fl, 50, 0, false, false)) return 1;
+  if (large) {
+    Problem c2 = make_problem(64, 928, 2);
+    for (int prec : {0, 1})
+      for (unsigned fl : {1u, 0u})
+        if (single_form(c2, 4, 32, prec, fl, 40, 3, false, fl == 0)) return 1;
+  }
+  // eight sequences of the 32^3 workload: first frame, then frames with TPP
+  std::vector<d2ip_instance_desc> seq(8, d2ip_instance_desc{0, 3, 16});
+  for (int prec : {0, 1})
+    for (unsigned fl : {1u, 0u})
+      if (multi({&c1}, seq, prec, fl, 20, 5, 3)) return 1;
+  // sixteen uneven instances
+  Problem g24a = make_problem(24, 208, 3), g32a = make_problem(32, 208, 4),
+          g48a = make_problem(48, 208, 5), g24b = make_problem(24, 928, 6),
+          g48b = make_problem(48, 928, 8);
+  std::vector<Problem*> geos = {&g24a, &g32a, &g48a, &g24b, &c1, &g48b};
+  std::vector<d2ip_instance_desc> un;
+  for (int i = 0; i < 16; ++i) {
+    const int g = (i % 3) + 3 * ((i / 3) % 2);
+    un.push_back({g, 3, ((i / 6) % 2) ? 16 : 8});
+  }
+  for (int prec : {0, 1})
+    for (unsigned fl : {1u, 0u})
+      if (multi(geos, un, prec, fl, 2, 3, 1)) return 1;
+  printf("ok: benchmark call sequence\n");
+  return 0;
+}
+
+int main(int argc, char** argv) {
+  if (argc > 1 && std::string(argv[1]) == "bench") {
+    int bad = bench_sequence(argc > 2 && std::string(argv[2]) == "large");
+    emu_flush_all();
+    printf("launches: %ld (captured %ld), emulation errors: %ld\n", g_launches,
+           g_captured_launches, emu_errors());
+    return bad || emu_errors() != 0;
+  }
   int bad = tuning_case() | ops_case();
   for (int prec = 0; prec < 3; ++prec)
     for (unsigned fl = 0; fl < 2; ++fl) {
@@ -248,6 +435,8 @@ int main() {
                       fl);
       bad |= run_case({{16, 208}}, {{0, 2, 8}}, prec, fl);
     }
-  printf("launches: %ld\n", g_launches);
-  return bad;
+  emu_flush_all();
+  printf("launches: %ld (captured %ld), emulation errors: %ld\n", g_launches,
+         g_captured_launches, emu_errors());
+  return bad || emu_errors() != 0;
 }

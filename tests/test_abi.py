@@ -283,3 +283,60 @@ def test_module_operators_validate_their_arguments(L):
     assert lib.d2ip_op_se_backward(a, a, a, a, a, a, a, None, None, None, None, 8, 16, 4, a, 1,
                                    None) == L.ENOMEM
     assert b"workspace too small" in lib.d2ip_last_error()
+
+
+@pytest.mark.parametrize("L_,C", [(3, 16), (4, 32), (2, 8)])
+def test_kaiming_initialiser_moments(L, L_, C):
+    """d2ip_init_params_host (Sec. III-B, Kaiming): every conv weight tensor
+    has mean 0 and variance 2 / fan_in (fan_in = Cin * taps) within sampling
+    error, biases 0, LayerNorm gamma 1 and beta 0 -- tensors found through the
+    oracle's own parameter layout."""
+    import numpy as np
+    from oracle import net
+    from paper_2507_14046_amd.context import kaiming_params
+    th = kaiming_params(L_, C, 12345).astype(np.float64)
+    mods = net.unpack(th, L_, C)
+    n_w = 0
+    for mod, ps in mods.items():
+        for name, t in ps.items():
+            if name.endswith("w") and t.ndim == 5:
+                fan_in = t.shape[1] * t.shape[2] * t.shape[3] * t.shape[4]
+                var = 2.0 / fan_in
+                N = t.size
+                assert abs(t.mean()) < 6 * np.sqrt(var / N), (mod, name)
+                # the sample variance of N normals has relative sd sqrt(2 / N)
+                assert abs(t.var() / var - 1) < 6 * np.sqrt(2.0 / N) + 1e-12, (mod, name)
+                n_w += 1
+            elif name.endswith("b") and not name.endswith("beta"):
+                assert np.all(t == 0), (mod, name)
+            elif name.endswith(".g"):
+                assert np.all(t == 1), (mod, name)
+            elif name.endswith("beta"):
+                assert np.all(t == 0), (mod, name)
+    assert n_w == 2 + 2 * (2 * L_ - 1) + sum(1 for l in range(L_) if l > 0) + (L_ - 1)
+
+
+def test_kaiming_initialiser_is_seeded(L):
+    import numpy as np
+    from paper_2507_14046_amd.context import kaiming_params
+    from paper_2507_14046_amd import D2ipError
+    a, b, c = (kaiming_params(3, 8, s) for s in (1, 1, 2))
+    assert np.array_equal(a, b)
+    assert not np.array_equal(a, c)
+    # the draws are standard normal overall: a Kolmogorov-Smirnov check on the
+    # largest weight tensor rescaled to unit variance
+    from scipy import stats
+    from oracle import net
+    w = net.unpack(kaiming_params(4, 32, 7).astype(np.float64), 4, 32)["dec0"]["conv1.w"]
+    z = (w / np.sqrt(2.0 / (w.shape[1] * 27))).ravel()
+    assert stats.kstest(z, "norm").pvalue > 1e-4
+    out = (ctypes.c_float * 10)()
+    with pytest.raises(D2ipError):
+        L.check(L.load().d2ip_init_params_host(3, 8, 1, out, 10))
+
+
+def test_runtime_versions_are_reported(L):
+    from paper_2507_14046_amd.context import runtime_versions
+    compiled, loaded = runtime_versions()
+    assert compiled >= 70000000  # ROCm 7 headers
+    assert loaded >= 0

@@ -4,7 +4,11 @@ Every source is compiled host-only (no device code) with ASan, linked with a
 host emulation of the HIP runtime calls it makes (tests/host_emulation), and
 driven through every C-ABI entry point: planning, uploads, graph capture,
 state save/restore, kernel timing and teardown.  Launches are checked against
-the hardware's grid/block/LDS limits and counted, not executed.
+the hardware's grid/block/LDS limits and counted, not executed.  Copies and
+fills run only when their stream is synchronised, so a host buffer freed (or
+a stack frame left) before its asynchronous copy has run is reported; the
+benchmark's own call sequence (every workload's contexts created, run and
+destroyed one after another) is replayed the same way.
 """
 import os
 import re
@@ -45,7 +49,12 @@ def test_host_logic_under_address_sanitizer(tmp_path):
     subprocess.run(["g++", "-O0", "-g", "-std=c++17", "-fsanitize=address", *inc, *rocm_inc,
                     os.path.join(HERE, "stubs.cpp"), os.path.join(HERE, "driver.cpp"), str(gen),
                     *objs, "-o", exe], check=True, capture_output=True)
-    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=1:abort_on_error=0")
+    env = dict(os.environ,
+               ASAN_OPTIONS="detect_leaks=1:detect_stack_use_after_return=1:abort_on_error=0")
     r = subprocess.run([exe], capture_output=True, text=True, env=env, timeout=600)
     assert r.returncode == 0, (r.stdout[-3000:], r.stderr[-5000:])
     assert r.stdout.count("ok:") == 20
+    assert "emulation errors: 0" in r.stdout
+    r = subprocess.run([exe, "bench"], capture_output=True, text=True, env=env, timeout=900)
+    assert r.returncode == 0, (r.stdout[-3000:], r.stderr[-5000:])
+    assert "ok: benchmark call sequence" in r.stdout and "emulation errors: 0" in r.stdout
