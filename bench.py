@@ -2,22 +2,33 @@
 
 A step is one DIP iteration of the whole hot path (network forward, J sigma,
 loss, J^T, network backward, Adam) over the 32^3 / 928-measurement / 3-level /
-16-channel workload.  Warm-up plus timed steps default to that workload's
-500-iteration fit, so the image after the timed region is compared with the
-stored FP64 oracle image at iteration 500: each precision form is reported
-with its image error, and `value` is the fastest form whose error is within
-its bound (FP32 1e-5, BF16 forms 2e-3, or 3x the oracle's own 1-ulp
-sensitivity when larger).  Each form runs with autotuned conv launch shapes,
-once as one captured hipGraph per iteration and once as eager launches on the
-context's two streams (weight gradients beside the input-gradient chain); the
-faster is reported and both rates are recorded.  "plain" is FP32 with the
-heuristic shapes and eager launches.
+16-channel workload, inputs resident in HBM.
 
-The other workloads are reported under "configs": 16^3 (50 iterations), 64^3,
-eight 32^3 sequences fitted frame after frame (frames/s) and sixteen uneven
-instances.
+The default run is one process:
+  * each precision form (fp32, bf16x3, bf16), with the stored tuning table,
+    launched as one captured hipGraph per iteration and as eager launches on
+    the context's two streams: an untimed 500-iteration fit whose images are
+    compared with the stored FP64 oracle images at every stored checkpoint
+    (the form's image error, whatever --steps and --warmup are), then --warmup
+    untimed and --steps timed iterations (HIP events on the context stream);
+    the faster launch mode is the form's rate;
+  * plain FP32 (heuristic launch shapes, eager launches) the same way;
+  * tsEIT frames/s: one breathing sequence fitted frame after frame with TPP
+    (500 iterations for the first frame, 50 per later frame), chosen form and
+    plain FP32;
+  * the kernel table of the chosen form (each kernel timed with HIP events on
+    the context stream) and the roofline entry of its dominant kernel;
+  * the FP64 oracle on the host's cores (cpu_baseline).
+`value` is the it/s of the fastest form whose image error after 500
+iterations is within its bound (FP32 1e-5, BF16 forms 2e-3, or 3x the
+oracle's own 1-ulp sensitivity at that iteration when larger).
 
-    python bench.py [--steps 480] [--warmup 20] [--gpus 1]
+The other workloads (--configs: 16^3, 64^3, eight 32^3 sequences, sixteen
+uneven instances; --ops: the depthwise-separable and SE operators and the
+module variants of the network; --ablation: the UPWS/TPP schedule ablation)
+each run in a child process of their own and are reported under "sections".
+
+    python bench.py [--steps 480] [--warmup 20] [--gpus 1] [--configs] [--ops] [--ablation]
 
 Prints one JSON line on stdout; progress goes to stderr.
 """
@@ -25,6 +36,7 @@ import argparse
 import glob
 import json
 import os
+import subprocess
 import sys
 import time
 
@@ -394,28 +406,6 @@ def dwsep_network(d2ip, torch, ts, names=("c1", "c2"), reps=10):
     return out
 
 
-def cpu_baseline(p, cfg, budget_s):
-    from oracle import fit
-    try:
-        from threadpoolctl import threadpool_info
-        cores = max([i.get("num_threads", 1) for i in threadpool_info()] or [os.cpu_count()])
-    except Exception:
-        cores = os.cpu_count()
-    pr = fit.Problem(p["J"], p["mask"], p["Z"], cfg["n"], cfg["levels"], cfg["base_ch"])
-    st = fit.State(p["theta0"])
-    t0 = time.time()
-    k = 0
-    while True:
-        fit.run(pr, st, p["dv"][0], 1, cfg["lr"])
-        k += 1
-        if time.time() - t0 >= budget_s:
-            break
-    dt = time.time() - t0
-    return dict(value=k / dt, unit="it/s", cores=int(cores), kind="oracle",
-                sample="%d FP64 oracle iterations of the 32^3 workload from theta_0 (%.1f s)"
-                       % (k, dt))
-
-
 def config0(d2ip, at, ts, prec, torch, cache, graph=True):
     cfg = ts.CONFIGS["c0"]
     p = ts.make_problem(cfg["n"], cfg["rings"], cfg["levels"], cfg["base_ch"], cfg["seed"])
@@ -533,23 +523,201 @@ def config4(d2ip, at, ts, prec, torch, cache, iters=20, graph=True):
                 sample="%d batched iterations timed after 2 warm-up iterations" % iters)
 
 
+
+def golden(cfg_name, upto):
+    """Stored FP64 oracle images of a workload at its checkpoints <= upto, and
+    the relative distance of the oracle's own run from a 1-ulp perturbed
+    theta_0 at each (the sensitivity floor)."""
+    for path in sorted(glob.glob(os.path.join(ROOT, "tests", "golden",
+                                              "oracle_%s_*.npz" % cfg_name))):
+        z = np.load(path)
+        cps = [int(c) for c in z["checkpoints"]]
+        out = {}
+        for i, c in enumerate(cps):
+            if c <= upto:
+                fl = rel_err(z["floor_images"][i], z["images"][i]) if "floor_images" in z else None
+                out[c] = (z["images"][i], fl)
+        if out:
+            return out
+    return {}
+
+
+def fit_and_time(d2ip, at, p, cfg, prec, steps, warmup, torch, gold, graph, tune=True,
+                 cache=None):
+    """Untimed fit through the stored checkpoints (image error at each), then
+    `warmup` untimed and `steps` timed iterations in the same context."""
+    geos = [(cfg["n"], p["J"].shape[0])]
+    insts = [(0, cfg["levels"], cfg["base_ch"])]
+    at.set_tuning(tuned(d2ip, at, geos, insts, prec, cache) if tune else [])
+    ctx = d2ip.Context(geos, insts, precision=prec, graph=graph)
+    try:
+        ctx.load_problem(0, p)
+        ctx.set_adam(lr=cfg["lr"])
+        errs, done = {}, 0
+        last_img = None
+        for k in sorted(gold):
+            ctx.run(k - done)
+            done = k
+            last_img = ctx.read_image(0)
+            errs[k] = rel_err(last_img, gold[k][0])
+        loss = float(ctx.run(0)[0])
+        kmax = max(gold) if gold else None
+        max_abs = float(np.max(np.abs(last_img - gold[kmax][0]))) if kmax else None
+        ctx.run(warmup)
+        ms = timed_run(ctx, steps, torch)
+        ctx.run(0)  # synchronising read: raises on a non-finite loss or parameter
+    finally:
+        ctx.close()
+    return dict(ms=ms, errs=errs, loss_at_fit_end=loss, fit_iters=done, max_abs=max_abs)
+
+
+def tpp_frames(d2ip, at, cfg, prec, torch, graph, tune=True, cache=None, frames=5):
+    """tsEIT frames/s of one breathing sequence (Sec. III-C): a 500-iteration
+    first frame, then `frames` frames of 50 iterations, each started from the
+    previous frame's parameters (Eq. (9)) with the optimiser restarted."""
+    import tseit_synth as ts
+    c3 = ts.CONFIGS["c3"]
+    seq = ts.make_problem(cfg["n"], cfg["rings"], cfg["levels"], cfg["base_ch"], c3["seeds"][0],
+                          frames=frames + 1, breathing=True)
+    geos = [(cfg["n"], seq["J"].shape[0])]
+    insts = [(0, cfg["levels"], cfg["base_ch"])]
+    at.set_tuning(tuned(d2ip, at, geos, insts, prec, cache) if tune else [])
+    ctx = d2ip.Context(geos, insts, precision=prec, graph=graph)
+    try:
+        ctx.load_problem(0, seq)
+        ctx.set_adam(lr=c3["lr"])
+        first_ms = timed_run(ctx, c3["iters"], torch)
+        # frame transitions included: dv upload (host array) and optimiser reset
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(ctx.stream)
+        for f in range(1, frames + 1):
+            ctx.set_frame(0, seq["dv"][f])
+            ctx.reset_optimizer(0)
+            ctx.run(c3["later_iters"], sync=False)
+        e1.record(ctx.stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        ms = e0.elapsed_time(e1)
+        ctx.run(0)
+    finally:
+        ctx.close()
+    return dict(frames_per_s=frames / (wall), later_frame_ms=wall * 1e3 / frames,
+                later_frame_ms_gpu_events=ms / frames, first_frame_ms=first_ms,
+                sample="1 sequence: first frame 500 iterations, then %d frames of 50 iterations "
+                       "(dv upload + optimiser reset per frame, host wall clock)" % frames)
+
+
+def cpu_baseline(p, cfg, iters=3):
+    """The FP64 oracle as it stands on this host's cores: one warm-up
+    iteration, then the median of `iters` timed iterations."""
+    from oracle import fit
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([i.get("num_threads", 1) for i in threadpool_info()] or [os.cpu_count()])
+    except Exception:
+        cores = os.cpu_count()
+    pr = fit.Problem(p["J"], p["mask"], p["Z"], cfg["n"], cfg["levels"], cfg["base_ch"])
+    st = fit.State(p["theta0"])
+    fit.run(pr, st, p["dv"][0], 1, cfg["lr"])
+    ts_ = []
+    for _ in range(iters):
+        t0 = time.perf_counter()
+        fit.run(pr, st, p["dv"][0], 1, cfg["lr"])
+        ts_.append(time.perf_counter() - t0)
+    med = float(np.median(ts_))
+    return dict(value=1.0 / med, unit="it/s", cores=int(cores), kind="oracle",
+                sample="median of %d FP64 oracle iterations of the 32^3 workload after 1 "
+                       "warm-up iteration (%s s each)" % (iters, ", ".join("%.1f" % t for t in ts_)))
+
+
+SECTIONS = ("c0", "c2", "c3", "c4", "ops", "network", "ablation")
+
+
+def run_section(name, a):
+    """One optional workload in this process (the child side of --configs,
+    --ops and --ablation); returns a JSON-able result."""
+    import torch
+    import paper_2507_14046_amd as d2ip
+    from paper_2507_14046_amd import autotune as at
+    import tseit_synth as ts
+    cache = {}
+    out = {}
+    if name in ("c0", "c2", "c3", "c4"):
+        fn = {"c0": config0, "c2": config2, "c3": config3, "c4": config4}[name]
+        for prec in ("fp32", "bf16"):
+            for graph in (True, False):
+                key = prec + ("" if graph else "_eager")
+                t0 = time.time()
+                out[key] = fn(d2ip, at, ts, prec, torch, cache, graph=graph)
+                log("%s %-10s %s (%.0f s)" % (name, key, json.dumps(out[key]), time.time() - t0))
+        at.set_tuning([])
+    elif name == "ops":
+        out = dict(dwsep=dwsep_ops(d2ip, torch), se=se_ops(d2ip, torch))
+    elif name == "network":
+        out = dwsep_network(d2ip, torch, ts)
+    elif name == "ablation":
+        from paper_2507_14046_amd import schedule
+        cfg = ts.CONFIGS["c1"]
+        seq = ts.make_problem(cfg["n"], cfg["rings"], cfg["levels"], cfg["base_ch"], cfg["seed"],
+                              frames=20, breathing=True)
+        warm = ts.make_problem(cfg["n"], cfg["rings"], cfg["levels"], cfg["base_ch"],
+                               cfg["seed"] + 1000)
+        geos = [(cfg["n"], seq["J"].shape[0])]
+        insts = [(0, cfg["levels"], cfg["base_ch"])]
+        at.set_tuning(tuned(d2ip, at, geos, insts, a.ablation_form, cache))
+        actx = d2ip.Context(geos, insts, precision=a.ablation_form, graph=False)
+        actx.load_problem(0, seq)
+        out = schedule.ablation(actx, seq["theta0"], seq["dv"], warm["dv"][0])
+        actx.close()
+        out["form"] = a.ablation_form
+    if cache.get("fresh"):
+        os.makedirs(os.path.join(ROOT, "gpurun_out"), exist_ok=True)
+        at.save(at.merge(cache["fresh"]),
+                os.path.join(ROOT, "gpurun_out", "tuned_fresh_%s.json" % name))
+    return out
+
+
+def spawn_section(name, a, timeout_s):
+    """Run one optional workload in a child process; its result, or its exit
+    status when it failed."""
+    cmd = [sys.executable, os.path.abspath(__file__), "--section", name,
+           "--ablation-form", a.ablation_form]
+    log("section %s: starting a child process" % name)
+    t0 = time.time()
+    try:
+        r = subprocess.run(cmd, stdout=subprocess.PIPE, timeout=timeout_s, text=True)
+    except subprocess.TimeoutExpired:
+        return dict(status="timeout", seconds=time.time() - t0)
+    lines = [l for l in r.stdout.splitlines() if l.startswith("SECTION_JSON: ")]
+    if r.returncode != 0 or not lines:
+        return dict(status="failed", returncode=r.returncode, seconds=time.time() - t0)
+    res = json.loads(lines[-1][len("SECTION_JSON: "):])
+    res["seconds"] = time.time() - t0
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=480)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--forms", default="fp32,bf16x3,bf16")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-kernels", action="store_true")
-    ap.add_argument("--no-configs", action="store_true")
-    ap.add_argument("--no-dwsep", action="store_true",
-                    help="skip the depthwise-separable and SE operator timings")
-    ap.add_argument("--no-network", action="store_true",
-                    help="skip the network-level timing of the module variants")
+    ap.add_argument("--no-frames", action="store_true")
+    ap.add_argument("--no-tv", action="store_true")
+    ap.add_argument("--configs", action="store_true",
+                    help="also the 16^3, 64^3, eight-sequence and sixteen-instance workloads")
+    ap.add_argument("--ops", action="store_true",
+                    help="also the depthwise-separable / SE operators and the module variants "
+                         "of the network")
     ap.add_argument("--ablation", action="store_true",
-                    help="also run the D2IP schedule ablation (UPWS / TPP) on a 20-frame "
-                         "32^3 sequence in the chosen form (about a minute)")
+                    help="also the D2IP schedule ablation (UPWS / TPP), 20 frames at 32^3")
+    ap.add_argument("--ablation-form", default="fp32")
+    ap.add_argument("--section", choices=SECTIONS, help=argparse.SUPPRESS)
     ap.add_argument("--traffic-probe", type=int, default=0,
                     help="MiB copied 3 times after the kernel table (counter calibration)")
     a = ap.parse_args()
@@ -557,89 +725,120 @@ def main():
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(the fitting of one instance runs on one device); use --gpus 1", file=sys.stderr)
         sys.exit(2)
+    if a.section:
+        res = run_section(a.section, a)
+        print("SECTION_JSON: " + json.dumps(res), flush=True)
+        return
 
     import torch
     import paper_2507_14046_amd as d2ip
     from paper_2507_14046_amd import autotune as at
+    from paper_2507_14046_amd.context import runtime_versions
     import tseit_synth as ts
 
+    hip_compiled, hip_runtime = runtime_versions()
+    log("HIP headers %d, runtime %d" % (hip_compiled, hip_runtime))
     cfg = ts.CONFIGS["c1"]
     p = ts.make_problem(cfg["n"], cfg["rings"], cfg["levels"], cfg["base_ch"], cfg["seed"])
-    total = a.warmup + a.steps
-    gimg = golden_image("c1", total)
-    floor = golden_image("c1", total, floor=True)
+    gold = golden("c1", cfg["iters"])
+    kref = max(gold) if gold else None
     cache = {}
     forms = {}
-    # every measurement runs with no other context alive: eager launches were
-    # measured ~25 % slower while a context holding a captured graph existed
     for prec in a.forms.split(","):
-        # each form launched both ways: one captured hipGraph per iteration,
-        # and eager launches on the context's two streams; the faster is kept
         runs = {}
         for graph in (True, False):
-            ctx, ms, loss, img = single_form(d2ip, at, p, cfg, prec, a.steps, a.warmup, torch,
-                                             graph=graph, cache=cache)
-            ctx.close()
-            runs[graph] = (None, ms, loss, img)
-        graph = min(runs, key=lambda g: runs[g][1])
-        _, ms, loss, img = runs[graph]
-        err = rel_err(img, gimg)
-        err_other = rel_err(runs[not graph][3], gimg)
-        # a result cannot be closer to the oracle than the oracle is to itself
-        # under a 1-ulp change of theta_0: the bound is max(stated, 3 x floor)
+            runs[graph] = fit_and_time(d2ip, at, p, cfg, prec, a.steps, a.warmup, torch, gold,
+                                       graph, cache=cache)
+        graph = min(runs, key=lambda g: runs[g]["ms"])
+        r = runs[graph]
+        err = r["errs"].get(kref)
+        floor = gold[kref][1] if kref else None
         bound = max(ERR_BOUND[prec], 3 * floor) if floor is not None else ERR_BOUND[prec]
-        forms[prec] = dict(it_per_s=a.steps / (ms * 1e-3), ms_per_step=ms / a.steps,
+        bounds = {k: max(ERR_BOUND[prec], 3 * gold[k][1]) if gold[k][1] is not None
+                  else ERR_BOUND[prec] for k in gold}
+        forms[prec] = dict(it_per_s=a.steps / (r["ms"] * 1e-3), ms_per_step=r["ms"] / a.steps,
                            launch="graph" if graph else "eager",
-                           graph_it_per_s=a.steps / (runs[True][1] * 1e-3),
-                           eager_it_per_s=a.steps / (runs[False][1] * 1e-3),
-                           final_loss=loss, image_rel_err_vs_fp64_oracle=err,
-                           image_rel_err_other_launch=err_other,
+                           graph_it_per_s=a.steps / (runs[True]["ms"] * 1e-3),
+                           eager_it_per_s=a.steps / (runs[False]["ms"] * 1e-3),
+                           image_rel_err_vs_fp64_oracle=err, image_err_iteration=kref,
+                           image_max_abs_err=r["max_abs"],
+                           image_rel_err_by_iteration={str(k): v for k, v in r["errs"].items()},
+                           image_rel_err_other_launch=runs[not graph]["errs"].get(kref),
                            error_bound_stated=ERR_BOUND[prec], oracle_floor=floor,
                            error_bound=bound,
+                           checkpoints_within_bound=[k for k in sorted(r["errs"])
+                                                     if r["errs"][k] <= bounds[k]],
+                           loss_at_iteration_500=r["loss_at_fit_end"],
                            within_bound=(err is not None and err <= bound))
-        log("form %-7s %9.1f it/s  %.4f ms/it  loss %.4e  image err %s  (graph %.1f, eager %.1f)"
-            % (prec, forms[prec]["it_per_s"], ms / a.steps, loss, err,
-               forms[prec]["graph_it_per_s"], forms[prec]["eager_it_per_s"]))
-    ctx, ms, loss, img = single_form(d2ip, at, p, cfg, "fp32", a.steps, a.warmup, torch,
-                                     graph=False, tune=False, cache=cache)
-    plain = dict(it_per_s=a.steps / (ms * 1e-3), ms_per_step=ms / a.steps, final_loss=loss,
-                 image_rel_err_vs_fp64_oracle=rel_err(img, gimg),
+        log("form %-7s %9.1f it/s  %.4f ms/it  image err at %s: %s (bound %.2g)  (graph %.1f, "
+            "eager %.1f)" % (prec, forms[prec]["it_per_s"], r["ms"] / a.steps, kref, err, bound,
+                             forms[prec]["graph_it_per_s"], forms[prec]["eager_it_per_s"]))
+    r = fit_and_time(d2ip, at, p, cfg, "fp32", a.steps, a.warmup, torch, gold, False, tune=False,
+                     cache=cache)
+    plain = dict(it_per_s=a.steps / (r["ms"] * 1e-3), ms_per_step=r["ms"] / a.steps,
+                 image_rel_err_vs_fp64_oracle=r["errs"].get(kref),
                  note="FP32, heuristic launch shapes, eager launches (no graph)")
-    ctx.close()
-    log("plain fp32     %9.1f it/s" % plain["it_per_s"])
-    tv_graph = forms.get("fp32", {}).get("launch", "graph") == "graph"
-    ctx, ms, loss, img = single_form(d2ip, at, p, cfg, "fp32", a.steps, a.warmup, torch,
-                                     graph=tv_graph, cache=cache, tv=True)
-    with_tv = dict(it_per_s=a.steps / (ms * 1e-3), ms_per_step=ms / a.steps, final_loss=loss,
-                   note="FP32, tuned, %s launches, loss with the 4D-TV term (lambda 0.002, 1, "
-                        "0.1; first frame: spatial term only)" % ("graph" if tv_graph else "eager"))
-    ctx.close()
-    log("fp32 + 4D-TV   %9.1f it/s" % with_tv["it_per_s"])
+    log("plain fp32     %9.1f it/s  image err %s" % (plain["it_per_s"], plain["image_rel_err_vs_fp64_oracle"]))
     ok = [f for f in forms if forms[f]["within_bound"]]
     chosen = max(ok, key=lambda f: forms[f]["it_per_s"]) if ok else (
         "fp32" if "fp32" in forms else list(forms)[0])
     res = forms[chosen]
+    chosen_graph = res["launch"] == "graph"
+
+    frames = None
+    if not a.no_frames:
+        fc = tpp_frames(d2ip, at, cfg, chosen, torch, chosen_graph, cache=cache)
+        fp = tpp_frames(d2ip, at, cfg, "fp32", torch, False, tune=False, cache=cache)
+        frames = dict(chosen=dict(form=chosen, launch=res["launch"], **fc), plain_fp32=fp,
+                      speedup=fc["frames_per_s"] / fp["frames_per_s"])
+        log("tsEIT frames/s (50 it/frame, TPP): %s %.2f, plain fp32 %.2f"
+            % (chosen, fc["frames_per_s"], fp["frames_per_s"]))
+    with_tv = None
+    if not a.no_tv:
+        geos = [(cfg["n"], p["J"].shape[0])]
+        insts = [(0, cfg["levels"], cfg["base_ch"])]
+        at.set_tuning(tuned(d2ip, at, geos, insts, "fp32", cache))
+        ctx = d2ip.Context(geos, insts, precision="fp32", graph=False)
+        try:
+            ctx.load_problem(0, p)
+            ctx.set_adam(lr=cfg["lr"])
+            ctx.set_tv()  # Sec. III-E coefficients; a first frame has no temporal history
+            ctx.run(a.warmup)
+            ms = timed_run(ctx, a.steps, torch)
+            loss = float(ctx.run(0)[0])
+        finally:
+            ctx.close()
+        with_tv = dict(it_per_s=a.steps / (ms * 1e-3), ms_per_step=ms / a.steps, final_loss=loss,
+                       note="FP32, tuned, eager launches, loss with the 4D-TV term (lambda 0.002, "
+                            "1, 0.1; first frame: spatial term only)")
+        log("fp32 + 4D-TV   %9.1f it/s" % with_tv["it_per_s"])
 
     roof = None
     if not a.no_kernels:
         at.set_tuning(tuned(d2ip, at, [(cfg["n"], p["J"].shape[0])],
                             [(0, cfg["levels"], cfg["base_ch"])], chosen, cache))
-        kctx, _, _, _ = single_form(d2ip, at, p, cfg, chosen, 0, a.warmup, torch, graph=False,
-                                    cache=cache)
-        rows = kernel_table(d2ip, kctx, p, cfg, chosen)
-        kctx.close()
-        for r in rows:
+        kctx = d2ip.Context([(cfg["n"], p["J"].shape[0])], [(0, cfg["levels"], cfg["base_ch"])],
+                            precision=chosen, graph=False)
+        try:
+            kctx.load_problem(0, p)
+            kctx.set_adam(lr=cfg["lr"])
+            kctx.run(a.warmup + 1)
+            rows = kernel_table(d2ip, kctx, p, cfg, chosen)
+        finally:
+            kctx.close()
+        for r_ in rows:
             log("  %-40s %8.4f ms  %9.2f %s  (%.1f%% of %s peak)" %
-                (r["kernel"], r["ms"], r["achieved"], r["unit"], 100 * r["frac"], r["bound"]))
-        dom = max(rows, key=lambda r: r["ms"])
+                (r_["kernel"], r_["ms"], r_["achieved"], r_["unit"], 100 * r_["frac"], r_["bound"]))
+        dom = max(rows, key=lambda r_: r_["ms"])
         table = tuned(d2ip, at, [(cfg["n"], p["J"].shape[0])],
                       [(0, cfg["levels"], cfg["base_ch"])], chosen, cache)
         roof = dict(kernel=dom["kernel"], bound=dom["bound"], achieved=dom["achieved"],
                     peak=dom["peak"], unit=dom["unit"], frac=dom["frac"],
                     traffic=traffic_record(at, dom["kernel"], chosen, table),
-                    ms_per_launch=dom["ms"],
-                    kernels={r["kernel"]: dict(ms=r["ms"], achieved=r["achieved"],
-                                               unit=r["unit"], frac=r["frac"]) for r in rows})
+                    ms_per_launch=dom["ms"], work_per_launch=dom["work"],
+                    kernels={r_["kernel"]: dict(ms=r_["ms"], achieved=r_["achieved"],
+                                                unit=r_["unit"], frac=r_["frac"]) for r_ in rows})
+        at.set_tuning([])
     if a.traffic_probe > 0:
         # plain device copies of known size: the scale of the HBM byte counters
         src = torch.ones(a.traffic_probe << 18, dtype=torch.float32, device="cuda")
@@ -648,47 +847,21 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         log("traffic probe: 3 copies of %d MiB" % a.traffic_probe)
-    configs = {}
-    if not a.no_configs:
-        for name, fn in (("c0", config0), ("c2", config2), ("c3", config3), ("c4", config4)):
-            configs[name] = {}
-            for prec in ("fp32", "bf16"):
-                for graph in (True, False):
-                    key = prec if graph else prec + ("_eager" if name in ("c0", "c2") else
-                                                     "_lanes")
-                    t0 = time.time()
-                    configs[name][key] = fn(d2ip, at, ts, prec, torch, cache, graph=graph)
-                    log("%s %-10s %s (%.0f s)" % (name, key, json.dumps(configs[name][key]),
-                                                  time.time() - t0))
-        at.set_tuning([])
     if cache.get("fresh"):
         # shapes tuned in this run (no stored table covered them)
         os.makedirs(os.path.join(ROOT, "gpurun_out"), exist_ok=True)
         at.save(at.merge(cache["fresh"]), os.path.join(ROOT, "gpurun_out", "tuned_fresh.json"))
-    ablation = None
-    if a.ablation:
-        from paper_2507_14046_amd import schedule
-        t0 = time.time()
-        at.set_tuning(tuned(d2ip, at, [(cfg["n"], p["J"].shape[0])],
-                            [(0, cfg["levels"], cfg["base_ch"])], chosen, cache))
-        seq = ts.make_problem(cfg["n"], cfg["rings"], cfg["levels"], cfg["base_ch"], cfg["seed"],
-                              frames=20, breathing=True)
-        warm = ts.make_problem(cfg["n"], cfg["rings"], cfg["levels"], cfg["base_ch"],
-                               cfg["seed"] + 1000)
-        actx = d2ip.Context([(cfg["n"], seq["J"].shape[0])], [(0, cfg["levels"], cfg["base_ch"])],
-                            precision=chosen, graph=False)
-        actx.load_problem(0, seq)
-        ablation = schedule.ablation(actx, seq["theta0"], seq["dv"], warm["dv"][0])
-        actx.close()
-        ablation["form"] = chosen
-        log("ablation (%.0f s): %s" % (time.time() - t0, json.dumps(
-            {k: (v["total_iterations"], round(v["seconds"], 2), v["all_reached"])
-             for k, v in ablation["variants"].items()})))
-    dwsep = None if a.no_dwsep else dict(
-        ops=dwsep_ops(d2ip, torch),
-        network=None if a.no_network else dwsep_network(d2ip, torch, ts))
-    se_unit = None if a.no_dwsep else se_ops(d2ip, torch)
-    cpu = None if a.no_cpu else cpu_baseline(p, cfg, a.cpu_seconds)
+
+    sections = {}
+    wanted = ([s for s in ("c0", "c2", "c3", "c4") if a.configs] +
+              (["ops", "network"] if a.ops else []) + (["ablation"] if a.ablation else []))
+    for name in wanted:
+        sections[name] = spawn_section(name, a, timeout_s=900)
+        log("section %s: %s" % (name, sections[name].get("status", "ok")))
+    cpu = None if a.no_cpu else cpu_baseline(p, cfg)
+    if cpu:
+        log("cpu baseline: %.4f it/s on %d cores (%s)" % (cpu["value"], cpu["cores"], cpu["sample"]))
+    total = a.warmup + a.steps
     out = {
         "metric": METRIC,
         "value": res["it_per_s"],
@@ -704,26 +877,27 @@ def main():
         "data": "synthetic",
         "config": {"workload": "32^3 voxels, 928 measurements (2 rings x 16 electrodes), "
                                "3-level residual U-Net with 16 base channels, 1 frame, "
-                               "Adam lr 1e-3, %d iterations" % total,
+                               "Adam lr 1e-3; image error after a 500-iteration fit, then "
+                               "%d + %d iterations timed after it" % (a.warmup, a.steps),
                    "form": chosen, "launch": res["launch"], "autotuned": True, "instances": 1},
         "image_rel_err": res["image_rel_err_vs_fp64_oracle"],
+        "image_err_iteration": kref,
+        "image_error_bound": res["error_bound"],
         "speedup_vs_plain_fp32": res["it_per_s"] / plain["it_per_s"],
         "iteration_roofline": iteration_roofline(cfg, chosen, p["J"].shape[0],
                                                  int(p["mask"].sum()),
                                                  d2ip.param_count(cfg["levels"], cfg["base_ch"]),
                                                  res["ms_per_step"]),
-        "frames_per_s_tpp50": res["it_per_s"] / 50.0,
+        "tseit_frames_per_s": frames,
         "forms": forms,
         "plain_fp32": plain,
         "fp32_with_4d_tv": with_tv,
-        "configs": configs,
-        "ablation": ablation,
-        "dwsep": dwsep,
-        "se": se_unit,
+        "sections": sections,
+        "hip_version": {"compiled": hip_compiled, "runtime": hip_runtime},
         "roofline": roof,
         "cpu_baseline": cpu,
     }
-    print(json.dumps(out))
+    print(json.dumps(out), flush=True)
 
 
 if __name__ == "__main__":
