@@ -190,7 +190,9 @@ def conv3d(x, w, b):
         for dy in range(k):
             for dx in range(k):
                 win = xp[:, dz:dz + n, dy:dy + n, dx:dx + n].reshape(cin, -1)
-                out += w[:, :, dz, dy, dx] @ win
+                # (a tap's weight slice is copied to a contiguous block so the
+                # product is one BLAS call)
+                out += np.ascontiguousarray(w[:, :, dz, dy, dx]) @ win
     out += b[:, None]
     return out.reshape(w.shape[0], n, n, n)
 
@@ -211,7 +213,7 @@ def conv3d_backward(x, w, gout, need_gx=True):
                 gw[:, :, dz, dy, dx] = g2 @ win.T
                 if need_gx:
                     gxp[:, dz:dz + n, dy:dy + n, dx:dx + n] += \
-                        (w[:, :, dz, dy, dx].T @ g2).reshape(cin, n, n, n)
+                        (np.ascontiguousarray(w[:, :, dz, dy, dx].T) @ g2).reshape(cin, n, n, n)
     gb = g2.sum(axis=1)
     gx = gxp[:, p:p + n, p:p + n, p:p + n] if need_gx else None
     return gx, gw, gb

@@ -9,6 +9,11 @@ between the two trajectories is the sensitivity floor that FP32 rounding
 alone can cause.
 
     python tests/golden/make_golden.py c1 --iters 500 --floor
+    python tests/golden/make_golden.py c2 --iters 50 --floor --grad
+
+With --grad it also stores the loss and the theta-gradient of the first
+iteration (at theta_0), the gradient rounded once to FP32 to keep the file
+small (a relative change of at most 2^-24 per entry).
 """
 import argparse
 import hashlib
@@ -51,9 +56,10 @@ def trajectory(pr, theta0, dv, iters, lr, checkpoints, log=None):
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("config", choices=["c0", "c1"])
+    ap.add_argument("config", choices=["c0", "c1", "c2"])
     ap.add_argument("--iters", type=int, default=None)
     ap.add_argument("--floor", action="store_true")
+    ap.add_argument("--grad", action="store_true")
     ap.add_argument("--out", default=None)
     a = ap.parse_args()
     cfg = ts.CONFIGS[a.config]
@@ -68,6 +74,12 @@ def main():
     out = dict(config=a.config, iters=iters, lr=cfg["lr"], checkpoints=np.array(cps),
                sha_J=sha(p["J"]), sha_Z=sha(p["Z"]), sha_theta0=sha(p["theta0"]),
                sha_dv=sha(p["dv"]))
+    if a.grad:
+        L1, g1, _ = pr.loss_and_grad(np.asarray(p["theta0"], dtype=np.float64),
+                                     np.asarray(p["dv"][0], dtype=np.float64))
+        out["loss1"] = L1
+        out["grad1"] = g1.astype(np.float32)
+        log("iteration 1 gradient stored (loss %.6e)" % L1)
     losses, imgs = trajectory(pr, p["theta0"], p["dv"][0], iters, cfg["lr"], cps, log)
     out["losses"] = losses
     out["images"] = np.stack([imgs[c] for c in cps])
