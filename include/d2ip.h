@@ -445,6 +445,20 @@ d2ip_status d2ip_op_jt_bytes(int M, int Q, size_t* out);
 d2ip_status d2ip_op_jt(const float* J, const float* g, float* out, int M, int Q, void* workspace,
                        size_t bytes, void* hip_stream);
 
+/* d2ip_op_jt without a workspace, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid allocation).  Same arguments minus the workspace, same kernels and
+ * summation order, so the result equals d2ip_op_jt's bit for bit.  The row
+ * partial sums live in a static 8 MiB device array inside the library (one
+ * per GPU, held until the process ends; its address is looked up on the first
+ * call on each device), which limits Q to 262144 (64^3) columns: larger Q is
+ * rejected with D2IP_EINVAL before anything is enqueued.  J and out must be
+ * 16-byte aligned.  Allocates nothing.  Every call on one GPU shares that
+ * array: calls that overlap on one GPU (two streams, or two threads) race and
+ * must be serialised by the caller. */
+d2ip_status d2ip_op_jt_noalloc(const float* J, const float* g, float* out, int M, int Q,
+                               void* hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -5,6 +5,7 @@
 // with its own autograd.
 #include <algorithm>
 #include <cstring>
+#include <mutex>
 #include <string>
 
 #include "d2ip.h"
@@ -229,6 +230,35 @@ void ln_plan(LnOp& l, int n, int C, Piece& w) {
   l.part_ab = w.take<double>(2 * (size_t)l.nb);
   l.gz = w.take<float>(V * C);
   l.seg = w.take<GradSeg>(1);
+}
+
+// Scratch of d2ip_op_jt_noalloc: the per-slice partial sums of J^T g for up
+// to kNoAllocMaxQ columns, in a file-scope device array (one copy per GPU,
+// held until the process ends).  Host code never uses the array's name as an
+// address: its device address is looked up once per device and kept.
+constexpr int kNoAllocMaxQ = 64 * 64 * 64;
+constexpr size_t kNoAllocScratchBytes = (size_t)8 * kNoAllocMaxQ * sizeof(float);  // 8 MiB
+static __device__ __align__(256) char scratch[kNoAllocScratchBytes];
+
+constexpr int kNoAllocMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_dev[kNoAllocMaxDevices] = {};
+
+// Device address of `scratch` on the current device (looked up on the first
+// call on that device).
+d2ip_status scratch_address(void** out) {
+  int dev = -1;
+  OPCHK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kNoAllocMaxDevices) return api_fail(D2IP_EINVAL, "device index out of range");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* p = nullptr;
+    OPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return api_fail(D2IP_EHIP, "no device address for the scratch array");
+    g_scratch_dev[dev] = p;
+  }
+  *out = g_scratch_dev[dev];
+  return D2IP_OK;
 }
 
 }  // namespace
@@ -586,6 +616,27 @@ d2ip_status d2ip_op_jt(const float* J, const float* g, float* out, int M, int Q,
   if (st != D2IP_OK) return st;
   if ((st = ws_check(workspace, bytes, need)) != D2IP_OK) return st;
   jt_dense(J, M, Q, g, reinterpret_cast<float*>(workspace), out,
+           reinterpret_cast<hipStream_t>(hip_stream));
+  OPCHK(hipGetLastError());
+  return D2IP_OK;
+}
+
+d2ip_status d2ip_op_jt_noalloc(const float* J, const float* g, float* out, int M, int Q,
+                               void* hip_stream) {
+  if (!J || !g || !out) return api_fail(D2IP_EINVAL, "null J, g or out");
+  if (M < 1 || Q < 4 || Q % 4 != 0) return api_fail(D2IP_EINVAL, "need M >= 1 and Q % 4 == 0");
+  if (Q > kNoAllocMaxQ)
+    return api_fail(D2IP_EINVAL, "Q = " + std::to_string(Q) + " exceeds the " +
+                                     std::to_string(kNoAllocMaxQ) +
+                                     " columns of the static scratch (use d2ip_op_jt)");
+  if (jt_dense_scratch(Q) * sizeof(float) > kNoAllocScratchBytes)
+    return api_fail(D2IP_EINVAL, "static scratch too small");
+  if (!aligned16(J) || !aligned16(out)) return api_fail(D2IP_EINVAL, "J and out must be 16-byte aligned");
+  void* part = nullptr;
+  d2ip_status st = scratch_address(&part);
+  if (st != D2IP_OK) return st;
+  // every partial the sum reads is written first: nothing to clear
+  jt_dense(J, M, Q, g, reinterpret_cast<float*>(part), out,
            reinterpret_cast<hipStream_t>(hip_stream));
   OPCHK(hipGetLastError());
   return D2IP_OK;

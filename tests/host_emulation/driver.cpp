@@ -243,6 +243,9 @@ static int ops_case() {
   CK(d2ip_op_jt_bytes(M, Q, &need));
   ws = (char*)aligned_alloc(256, (need + 255) / 256 * 256);
   CK(d2ip_op_jt(J.data(), p.data(), out.data(), M, Q, ws, need, nullptr));
+  CK(d2ip_op_jt_noalloc(J.data(), p.data(), out.data(), M, Q, nullptr));
+  EXPECT_ERR(d2ip_op_jt_noalloc(J.data(), p.data(), out.data(), M, 64 * 64 * 64 + 4, nullptr),
+             D2IP_EINVAL);
   emu_flush_all();  // the caller frees device memory after its stream has passed
   free(ws);
   printf("ok: standalone operators\n");

@@ -150,6 +150,7 @@ void emu_flush_all(void) {
 
 void** __hipRegisterFatBinary(const void*) { static void* h[4]; return h; }
 void __hipUnregisterFatBinary(void**) {}
+void __hipRegisterVar(void**, void*, char*, const char*, int, size_t, int, int) {}
 void __hipRegisterFunction(void**, const void*, char*, const char*, unsigned int, void*, void*,
                            dim3*, dim3*, int*) {}
 hipError_t __hipPushCallConfiguration(dim3 g, dim3 b, size_t shm, hipStream_t s) {
@@ -174,6 +175,9 @@ hipError_t hipLaunchKernel(const void*, dim3 g, dim3 b, void** args, size_t shm,
   return hipSuccess;
 }
 hipError_t hipRuntimeGetVersion(int* v) { *v = HIP_VERSION; return hipSuccess; }
+hipError_t hipGetDevice(int* d) { *d = 0; return hipSuccess; }
+// a device variable's address is its host shadow (device memory is host memory)
+hipError_t hipGetSymbolAddress(void** p, const void* sym) { *p = const_cast<void*>(sym); return hipSuccess; }
 hipError_t hipEventCreate(hipEvent_t* e) { *e = (hipEvent_t) new Event(); return hipSuccess; }
 hipError_t hipEventCreateWithFlags(hipEvent_t* e, unsigned) { *e = (hipEvent_t) new Event(); return hipSuccess; }
 hipError_t hipEventDestroy(hipEvent_t e) { delete (Event*)e; return hipSuccess; }
