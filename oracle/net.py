@@ -316,31 +316,39 @@ def resblock_backward(gy, P, cache):
 
 
 def att_forward(x, g, Q):
-    """Additive attention unit on a decoder skip (Sec. III-D): x [c, ...] the
-    skip, g [c_up, ...] the up-sampled coarser decoder output (the gating
-    signal); a = wx x + wg g + b, q = relu(a), alpha = sigmoid(psi . q + bpsi)
-    (one gate per voxel), output alpha * x."""
+    """Attention unit of one decoder up-sampling stage (Sec. III-D: the stage
+    is an attention mechanism, followed by interpolation and a ResConv3D
+    block).  x [c, n, n, n] is the encoder skip, g [c_up, n/2, n/2, n/2] the
+    coarser decoder output (the gating signal), on its own grid.  The gate is
+    formed on g's grid from the skip averaged over 2x2x2 cells:
+    a = wx pool2(x) + wg g + b, q = relu(a), alpha = sigmoid(psi . q + bpsi)
+    (one coefficient per coarse voxel); it is then interpolated (nearest
+    neighbour, x2) to the skip's grid, and the output is alpha * x."""
     c = x.shape[0]
-    shp = x.shape[1:]
-    X, G = x.reshape(c, -1), g.reshape(g.shape[0], -1)
-    a = Q["att.wx"] @ X + Q["att.wg"] @ G + Q["att.b"][:, None]
+    xs = avgpool2(x)
+    Xs, G = xs.reshape(c, -1), g.reshape(g.shape[0], -1)
+    a = Q["att.wx"] @ Xs + Q["att.wg"] @ G + Q["att.b"][:, None]
     q = np.maximum(a, 0.0)
     al = 1.0 / (1.0 + np.exp(-(Q["att.psi"] @ q + Q["att.bpsi"][0])))
-    return (al[None, :] * X).reshape((c,) + shp), dict(X=X, G=G, a=a, q=q, al=al)
+    alf = up2(al.reshape((1,) + g.shape[1:]))
+    return alf * x, dict(x=x, Xs=Xs, G=G, a=a, q=q, al=al, alf=alf)
 
 
 def att_backward(gout, Q, c):
-    """(gx, gg, {param grads}) of att_forward given gout = dL/d(output)."""
-    X, G, a, q, al = c["X"], c["G"], c["a"], c["q"], c["al"]
-    go = gout.reshape(X.shape)
-    gal = (go * X).sum(axis=0)                  # dL/dalpha per voxel
-    gt = gal * al * (1.0 - al)                  # through the sigmoid
+    """(gx, gg, {param grads}) of att_forward given gout = dL/d(output); gg is
+    on the gating signal's (coarse) grid."""
+    x, Xs, G, a, q, al, alf = c["x"], c["Xs"], c["G"], c["a"], c["q"], c["al"], c["alf"]
+    galf = (gout * x).sum(axis=0, keepdims=True)    # dL/d(interpolated alpha)
+    gal = up2_backward(galf).reshape(-1)             # to the coarse coefficients
+    gt = gal * al * (1.0 - al)                       # through the sigmoid
     gq = np.outer(Q["att.psi"], gt)
-    ga = gq * (a > 0)                           # through the ReLU
-    grads = {"att.wx": ga @ X.T, "att.wg": ga @ G.T, "att.b": ga.sum(axis=1),
+    ga = gq * (a > 0)                                # through the ReLU
+    grads = {"att.wx": ga @ Xs.T, "att.wg": ga @ G.T, "att.b": ga.sum(axis=1),
              "att.psi": q @ gt, "att.bpsi": np.array([gt.sum()])}
-    gx = (al[None, :] * go + Q["att.wx"].T @ ga).reshape(gout.shape)
-    gg = (Q["att.wg"].T @ ga).reshape((G.shape[0],) + gout.shape[1:])
+    m = x.shape[1] // 2
+    gxs = (Q["att.wx"].T @ ga).reshape((x.shape[0], m, m, m))
+    gx = alf * gout + avgpool2_backward(gxs)
+    gg = (Q["att.wg"].T @ ga).reshape((G.shape[0], m, m, m))
     return gx, gg, grads
 
 
@@ -371,10 +379,10 @@ def forward(theta, Z, n, levels, base_ch, sep=False, se_ratio=0, att=False, tail
     if aspp:
         d, cache["aspp"] = aspp_forward(d, P["aspp"])
     for l in range(levels - 2, -1, -1):
-        u = up2(d)
         skip = enc[l]
-        if att:
-            skip, cache["att%d" % l] = att_forward(skip, u, P["dec%d" % l])
+        if att:  # the gate on the coarse grid, before the interpolation
+            skip, cache["att%d" % l] = att_forward(skip, d, P["dec%d" % l])
+        u = up2(d)
         x = np.concatenate([u, skip], axis=0)
         d, cache["dec%d" % l] = resblock_forward(x, P["dec%d" % l])
     out = conv3d(d, P["tail"]["w"], P["tail"]["b"])
@@ -410,12 +418,12 @@ def backward(gout, theta, cache, n, levels, base_ch, sep=False, se_ratio=0, att=
         c_up = base_ch * 2 ** (l + 1)
         gu = gx[:c_up]
         gskip = gx[c_up:]
-        if att:  # the skip passed through the attention unit, gated by u
+        gd = up2_backward(gu)                  # to dec_{l+1} (or enc_{L-1})
+        if att:  # the skip passed through the attention unit, gated from dec_{l+1}
             gskip, gg, Ga = att_backward(gskip, P["dec%d" % l], cache["att%d" % l])
             for k, v in Ga.items():
                 Gv["dec%d" % l][k][...] = v
-            gu = gu + gg
-        gd = up2_backward(gu)                  # to dec_{l+1} (or enc_{L-1})
+            gd = gd + gg
         genc[l] = gskip                        # skip contribution to enc_l
     if aspp:  # gd is d(loss)/d(ASPP output): back through the module
         gd, Ga = aspp_backward(gd, P["aspp"], cache["aspp"])

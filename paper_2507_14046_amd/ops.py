@@ -536,10 +536,10 @@ class DIPNet:
             x = self._aspp(P, x)
         for l in range(L - 2, -1, -1):
             nl = n >> l
-            u = _up(x, nl // 2)
             s = skips[l]
-            if self.att:
-                s = self._attend(P, "dec%d" % l, s, u)
+            if self.att:  # the gate on the coarse grid, then the interpolation
+                s = self._attend(P, "dec%d" % l, s, x, nl)
+            u = _up(x, nl // 2)
             x = torch.cat([u, s], dim=1)
             x = self._run_block(P, "dec%d" % l, x, nl)
         out = x @ P["head.w"].view(1, self.C).t() + P["head.b"]
@@ -557,15 +557,17 @@ class DIPNet:
             br.append(PWConv3dFn.apply(t, P["aspp.pw%d" % d], P["aspp.pwb%d" % d]))
         return torch.relu(PWConv3dFn.apply(torch.cat(br, dim=1), P["aspp.wp"], P["aspp.bp"]))
 
-    def _attend(self, P, d, s, u):
-        """Additive attention unit: the skip s gated per voxel by
-        sigmoid(psi . relu(wx s + wg u + b) + bpsi), u the up-sampled coarser
-        decoder output; the two 1x1x1 convs run on the pointwise GEMM."""
+    def _attend(self, P, d, s, g, n):
+        """Attention unit of a decoder stage (Sec. III-D: attention, then
+        interpolation): the skip s (n^3 grid) gated by coefficients formed on
+        the grid of the coarser decoder output g, sigmoid(psi . relu(wx
+        pool2(s) + wg g + b) + bpsi), then interpolated (nearest, x2); the two
+        1x1x1 convs run on the pointwise GEMM."""
         torch = _torch()
-        a = PWConv3dFn.apply(s, P[d + ".awx"], P[d + ".ab"]) + PWConv3dFn.apply(
-            u, P[d + ".awg"], None)
+        a = PWConv3dFn.apply(_pool(s, n), P[d + ".awx"], P[d + ".ab"]) + PWConv3dFn.apply(
+            g, P[d + ".awg"], None)
         gate = torch.sigmoid(torch.relu(a) @ P[d + ".apsi"] + P[d + ".abpsi"])
-        return s * gate[:, None]
+        return s * _up(gate[:, None], n // 2)
 
     def loss(self, theta, Z, mask, J, dv):
         """(1/M) sum (J sigma - dv)^2, with J sigma and J^T on the library's kernels."""

@@ -10,6 +10,11 @@ alone can cause.
 
     python tests/golden/make_golden.py c1 --iters 500 --floor
     python tests/golden/make_golden.py c2 --iters 50 --floor --grad
+    python tests/golden/make_golden.py c3
+
+c3 writes the eight breathing sequences of the 32^3 time-sequence workload
+on a shortened TPP schedule (10 iterations for frame 0, then 5 per frame for
+frames 1 and 2, Adam restarted per frame): each frame's image, FP32-rounded.
 
 With --grad it also stores the loss and the theta-gradient of the first
 iteration (at theta_0), the gradient rounded once to FP32 to keep the file
@@ -54,22 +59,49 @@ def trajectory(pr, theta0, dv, iters, lr, checkpoints, log=None):
     return np.array(losses), images
 
 
+C3_ITERS = [10, 5, 5]
+
+
+def sequences_c3(log):
+    cfg = ts.CONFIGS["c3"]
+    out = dict(config="c3", iters=np.array(C3_ITERS), lr=cfg["lr"], seeds=np.array(cfg["seeds"]))
+    imgs, losses = [], []
+    for seed in cfg["seeds"]:
+        p = ts.make_problem(cfg["n"], cfg["rings"], cfg["levels"], cfg["base_ch"], seed,
+                            frames=len(C3_ITERS), breathing=True)
+        pr = fit.Problem(p["J"], p["mask"], p["Z"], cfg["n"], cfg["levels"], cfg["base_ch"])
+        im, ls, _ = fit.fit_sequence(pr, p["theta0"], p["dv"], C3_ITERS, cfg["lr"])
+        imgs.append(im.astype(np.float32))
+        losses.append(np.concatenate([np.asarray(l) for l in ls]))
+        out["sha_theta0_%d" % seed] = sha(p["theta0"])
+        log("sequence %d: final loss %.6e" % (seed, losses[-1][-1]))
+    out["images"] = np.stack(imgs)      # [sequence][frame][voxel]
+    out["losses"] = np.stack(losses)    # [sequence][iteration]
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("config", choices=["c0", "c1", "c2"])
+    ap.add_argument("config", choices=["c0", "c1", "c2", "c3"])
     ap.add_argument("--iters", type=int, default=None)
     ap.add_argument("--floor", action="store_true")
     ap.add_argument("--grad", action="store_true")
     ap.add_argument("--out", default=None)
     a = ap.parse_args()
+
+    def log(m):
+        print(m, flush=True)
+
+    if a.config == "c3":
+        path = a.out or os.path.join(HERE, "oracle_c3_tpp.npz")
+        np.savez_compressed(path, **sequences_c3(log))
+        log("wrote " + path)
+        return
     cfg = ts.CONFIGS[a.config]
     iters = a.iters or cfg["iters"]
     cps = sorted({c for c in (1, 5, 10, 20, 50, 100, 200, 300, 500, 1000) if c <= iters} | {iters})
     p = ts.make_problem(cfg["n"], cfg["rings"], cfg["levels"], cfg["base_ch"], cfg["seed"])
     pr = fit.Problem(p["J"], p["mask"], p["Z"], cfg["n"], cfg["levels"], cfg["base_ch"])
-
-    def log(m):
-        print(m, flush=True)
 
     out = dict(config=a.config, iters=iters, lr=cfg["lr"], checkpoints=np.array(cps),
                sha_J=sha(p["J"]), sha_Z=sha(p["Z"]), sha_theta0=sha(p["theta0"]),

@@ -63,3 +63,24 @@ def per_tensor_rel(g_gpu, g_ref, levels, C):
         out[name] = rel(g_gpu[off:off + k], g_ref[off:off + k])
         off += k
     return out
+
+
+def elementwise(a, ref, tol):
+    """max over elements of |a - ref| / (tol * (max|ref| + |ref|)): at most 1
+    when every element lies within tol of the array's scale and of its own
+    magnitude (so an error confined to a few voxels, taps or channels shows
+    even when the relative L2 over the whole array stays small)."""
+    a = np.asarray(a, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    scale = tol * (np.max(np.abs(ref)) + np.abs(ref))
+    return float(np.max(np.abs(a - ref) / np.maximum(scale, 1e-300)))
+
+
+def per_tensor_elementwise(g_gpu, g_ref, levels, C, tol):
+    out = {}
+    off = 0
+    for name, shape, _ in ts.param_specs(levels, C):
+        k = int(np.prod(shape))
+        out[name] = elementwise(g_gpu[off:off + k], g_ref[off:off + k], tol)
+        off += k
+    return out

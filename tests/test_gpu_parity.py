@@ -1,22 +1,27 @@
 """Parity of the HIP fitting iteration with the FP64 oracle, through the C-ABI.
 
-Tolerances.  FP32 path: the oracle's own trajectory moves by ~5e-7 (relative
-L2 of the image) when theta_0 is moved by one FP32 ulp, so FP32 rounding in the
-kernels is expected to stay within ~1e-5; forward images and gradients of one
-iteration are compared per tensor.  BF16x3 path (hi+lo split operands): the
-product error is ~2^-17, measured forward 1e-5 and gradients ~2e-5; Adam
-normalises every gradient component by its own magnitude, so components whose
-gradient is near the noise level take full-size steps of either sign and the
-50-iteration image drifts to ~2.5e-3.  BF16 path (operands rounded once,
-relative step 2^-8): gradients are off by several percent; only gross failures
-are asserted and the measured errors are recorded.
+Tolerances.  The stated image bounds are 1e-5 (FP32) and 2e-3 (the BF16 forms)
+relative L2 against the FP64 oracle; one-iteration gradients are held to the
+same relative bound for the BF16 forms and to 5e-6 overall / 1e-4 per tensor
+for FP32 (about ten times the measured 2-8e-7 / 3.6e-5), and FP32 images and
+gradient tensors are also checked element by element (every value within a
+fixed fraction of its array's scale).  The pure BF16 form (operands rounded
+once to bfloat16, 2^-9 relative per operand) misses the 2e-3 bound already on
+one forward pass (3-5e-3) and its gradients by 2-10e-2; the BF16x3 form (hi +
+lo operands, product error near 2^-16) meets it for one iteration but not along
+Adam trajectories, which amplify any per-iteration difference (the oracle's own
+1-ulp run grows 1400-fold by iteration 500).  Those cases are strict expected
+failures carrying the measured numbers, and
+tests/test_gpu_bf16_rounding.py shows the BF16 kernels exact against the
+oracle fed the same rounded operands.
 """
 import numpy as np
 import pytest
 
 import tseit_synth as ts
 from oracle import fit
-from tests.gpu_util import (make_ctx, oracle_problem, per_tensor_rel, problem, record, rel)
+from tests.gpu_util import (elementwise, make_ctx, oracle_problem, per_tensor_elementwise,
+                            per_tensor_rel, problem, record, rel)
 
 pytestmark = pytest.mark.gpu
 
@@ -27,11 +32,27 @@ CASES = {
     "n16_L3_C16_M928": (16, 2, 3, 16, 3),
 }
 
-# pure BF16 operands: errors are recorded, bounds only catch gross failures
-TOL_IMG = {"fp32": 1e-5, "bf16x3": 2e-5, "bf16": 2e-2}
-TOL_GRAD = {"fp32": 2e-4, "bf16x3": 5e-4, "bf16": 0.3}
-TOL_TRAJ = {"fp32": 2e-5, "bf16x3": 5e-3, "bf16": 0.5}
+# stated bounds (relative L2 vs the FP64 oracle)
+TOL_IMG = {"fp32": 1e-5, "bf16x3": 2e-3, "bf16": 2e-3}
+TOL_GRAD = {"fp32": 5e-6, "bf16x3": 2e-3, "bf16": 2e-3}
+# per gradient tensor; small tensors whose gradients cancel (biases and gains
+# in front of a LayerNorm) carry larger relative errors than the whole vector
+TOL_TENSOR = {"fp32": 1e-4, "bf16x3": 5e-3, "bf16": 5e-3}
+TOL_TRAJ = {"fp32": 1e-5, "bf16x3": 2e-3, "bf16": 2e-3}
+# element-wise (FP32): every value within this fraction of max|ref| + |ref|
+ELEM_IMG, ELEM_GRAD = 1e-5, 3e-4
 PRECS = ["fp32", "bf16x3", "bf16"]
+
+
+def precs(**xfail):
+    """PRECS with the named forms marked as strict expected failures."""
+    return [pytest.param(p, marks=pytest.mark.xfail(strict=True, reason=xfail[p]))
+            if p in xfail else p for p in PRECS]
+
+
+BF16_FWD = "pure BF16 operands move the first image by 3.0-5.1e-3 (> 2e-3)"
+BF16_GRAD = ("pure BF16 operands: one-iteration gradient 2-10e-2 from the FP64 oracle "
+             "(exact against the oracle fed the same rounded operands)")
 
 
 @pytest.fixture(scope="module")
@@ -39,7 +60,7 @@ def probs():
     return {k: problem(*v) for k, v in CASES.items()}
 
 
-@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("prec", precs(bf16=BF16_FWD))
 @pytest.mark.parametrize("case", list(CASES))
 def test_forward_image(lib, probs, case, prec):
     p = probs[case]
@@ -47,12 +68,28 @@ def test_forward_image(lib, probs, case, prec):
     img = ctx.read_image(0)
     ref = oracle_problem(p).image(p["theta0"].astype(np.float64))
     e = rel(img, ref)
-    record("forward_image", case=case, prec=prec, rel=e)
+    el = elementwise(img, ref, ELEM_IMG)
+    record("forward_image", case=case, prec=prec, rel=e, elementwise=el)
     assert np.all(img[p["mask"] == 0] == 0.0)
     assert e < TOL_IMG[prec]
+    if prec == "fp32":
+        assert el <= 1.0, el
 
 
-@pytest.mark.parametrize("prec", PRECS)
+def _check_gradient(g, gref, levels, C, prec, tag, **kw):
+    per = per_tensor_rel(g, gref, levels, C)
+    worst = max(per.items(), key=lambda kv: kv[1])
+    pel = per_tensor_elementwise(g, gref, levels, C, ELEM_GRAD)
+    wel = max(pel.items(), key=lambda kv: kv[1])
+    record(tag, prec=prec, grad_rel=rel(g, gref), worst_tensor=worst[0], worst_rel=worst[1],
+           worst_elementwise_tensor=wel[0], worst_elementwise=wel[1], **kw)
+    assert rel(g, gref) < TOL_GRAD[prec], rel(g, gref)
+    assert worst[1] < TOL_TENSOR[prec], per
+    if prec == "fp32":
+        assert wel[1] <= 1.0, pel
+
+
+@pytest.mark.parametrize("prec", precs(bf16=BF16_GRAD))
 @pytest.mark.parametrize("case", list(CASES))
 def test_one_iteration_loss_and_gradient(lib, probs, case, prec):
     p = probs[case]
@@ -61,16 +98,14 @@ def test_one_iteration_loss_and_gradient(lib, probs, case, prec):
     g = ctx.get_grad(0)
     pr = oracle_problem(p)
     L0, gref, _ = pr.loss_and_grad(p["theta0"].astype(np.float64), p["dv"][0].astype(np.float64))
-    per = per_tensor_rel(g, gref, p["levels"], p["base_ch"])
-    worst = max(per.items(), key=lambda kv: kv[1])
-    record("one_iteration", case=case, prec=prec, loss_rel=abs(loss - L0) / L0,
-           grad_rel=rel(g, gref), worst_tensor=worst[0], worst_rel=worst[1])
-    assert abs(loss - L0) / L0 < TOL_IMG[prec]
-    assert rel(g, gref) < TOL_GRAD[prec]
-    assert worst[1] < 5 * TOL_GRAD[prec], per
+    assert abs(loss - L0) / L0 < TOL_IMG[prec], abs(loss - L0) / L0
+    _check_gradient(g, gref, p["levels"], p["base_ch"], prec, "one_iteration", case=case,
+                    loss_rel=abs(loss - L0) / L0)
 
 
-@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("prec", precs(
+    bf16x3="BF16x3: 50 Adam iterations at 16^3 end 2.4e-3 from the oracle (> 2e-3)",
+    bf16="pure BF16: 50 Adam iterations at 16^3 end 0.15 from the oracle"))
 def test_trajectory_50_iterations_16cubed(lib, probs, prec):
     p = probs["n16_L2_C8"]
     ctx = make_ctx(lib, [p], prec)
@@ -82,8 +117,11 @@ def test_trajectory_50_iterations_16cubed(lib, probs, prec):
     ref = pr.image(st.theta)
     e = rel(img, ref)
     lrel = float(np.max(np.abs(np.array(losses) - lref) / np.array(lref)))
-    record("trajectory50_n16", prec=prec, image_rel=e, loss_max_rel=lrel)
+    el = elementwise(img, ref, ELEM_IMG * 10)
+    record("trajectory50_n16", prec=prec, image_rel=e, loss_max_rel=lrel, elementwise=el)
     assert e < TOL_TRAJ[prec]
+    if prec == "fp32":
+        assert el <= 1.0, el
 
 
 def test_tpp_two_frames_matches_oracle(lib):
@@ -192,25 +230,32 @@ def test_error_paths(lib, probs):
     assert np.isfinite(ctx.run(1)[0])
 
 
-def test_full_size_32cubed_one_iteration(lib):
-    """The 32^3 / 928-measurement / L=3 / C=16 workload, in both launch
-    configurations the benchmark times (captured graph, eager launches on two
-    streams): loss and every gradient tensor vs the oracle after one
-    iteration."""
+@pytest.fixture(scope="module")
+def c1_reference():
     c = ts.CONFIGS["c1"]
     p = problem(c["n"], c["rings"], c["levels"], c["base_ch"], c["seed"])
     pr = oracle_problem(p)
     L0, gref, _ = pr.loss_and_grad(p["theta0"].astype(np.float64), p["dv"][0].astype(np.float64))
-    for prec in PRECS:
-        for graph in (True, False):
-            ctx = make_ctx(lib, [p], prec, graph=graph)
-            loss = ctx.run(1)[0]
-            g = ctx.get_grad(0)
-            per = per_tensor_rel(g, gref, c["levels"], c["base_ch"])
-            record("full32_one_iteration", prec=prec, graph=graph, loss_rel=abs(loss - L0) / L0,
-                   grad_rel=rel(g, gref), worst=max(per.values()))
-            assert rel(g, gref) < TOL_GRAD[prec]
-            ctx.close()
+    return p, L0, gref
+
+
+@pytest.mark.parametrize("prec", precs(bf16="pure BF16 operands: 32^3 one-iteration gradient "
+                                            "1.9e-2 from the FP64 oracle, worst tensor 0.63"))
+def test_full_size_32cubed_one_iteration(lib, c1_reference, prec):
+    """The 32^3 / 928-measurement / L=3 / C=16 workload, in both launch
+    configurations the benchmark times (captured graph, eager launches on two
+    streams): loss and every gradient tensor vs the oracle after one
+    iteration, element by element for FP32."""
+    p, L0, gref = c1_reference
+    c = ts.CONFIGS["c1"]
+    for graph in (True, False):
+        ctx = make_ctx(lib, [p], prec, graph=graph)
+        loss = ctx.run(1)[0]
+        g = ctx.get_grad(0)
+        ctx.close()
+        assert abs(loss - L0) / L0 < TOL_IMG[prec]
+        _check_gradient(g, gref, c["levels"], c["base_ch"], prec, "full32_one_iteration",
+                        graph=graph, loss_rel=abs(loss - L0) / L0)
 
 
 @pytest.mark.skip(reason="instance groups (batched launches) are switched off: their first GPU run crashed the host process (SIGSEGV in d2ip_run) and the cause is not yet shown")
@@ -293,7 +338,7 @@ def test_every_launch_shape_family_matches_oracle(lib, probs, case):
         at.set_tuning([])
 
 
-@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("prec", precs(bf16=BF16_GRAD))
 @pytest.mark.parametrize("ck", [8, 16, 32])
 @pytest.mark.parametrize("case", ["n24_L3_C8", "n16_L3_C16_M928"])
 def test_weight_gradient_chunks_match_oracle(lib, probs, case, ck, prec):
@@ -325,12 +370,8 @@ def test_weight_gradient_chunks_match_oracle(lib, probs, case, ck, prec):
         ctx.close()
     finally:
         at.set_tuning([])
-    per = per_tensor_rel(g, gref, p["levels"], p["base_ch"])
-    worst = max(per.items(), key=lambda kv: kv[1])
-    record("wgrad_chunks", case=case, ck=ck, prec=prec, passes=len(table),
-           grad_rel=rel(g, gref), worst_tensor=worst[0], worst_rel=worst[1])
-    assert rel(g, gref) < TOL_GRAD[prec]
-    assert worst[1] < 5 * TOL_GRAD[prec], per
+    _check_gradient(g, gref, p["levels"], p["base_ch"], prec, "wgrad_chunks", case=case, ck=ck,
+                    passes=len(table))
 
 
 def test_one_iteration_with_many_j_column_blocks(lib):
@@ -377,8 +418,9 @@ def test_instances_sharing_a_geometry_match_separate(lib, graph):
     both.close()
 
 
-@pytest.mark.parametrize("prec", PRECS)
-def test_stored_tuning_table_matches_oracle(lib, prec):
+@pytest.mark.parametrize("prec", precs(bf16="pure BF16 operands: 32^3 one-iteration gradient "
+                                            "1.9e-2 from the FP64 oracle"))
+def test_stored_tuning_table_matches_oracle(lib, c1_reference, prec):
     """The chip's stored tuning table (the bench's launch shapes) on the
     full-size 32^3 workload: one-iteration gradient against the oracle."""
     import os
@@ -387,35 +429,36 @@ def test_stored_tuning_table_matches_oracle(lib, prec):
     if not os.path.exists(path):
         pytest.skip("no stored tuning table")
     c = ts.CONFIGS["c1"]
-    p = problem(c["n"], c["rings"], c["levels"], c["base_ch"], c["seed"])
-    pr = oracle_problem(p)
-    _, gref, _ = pr.loss_and_grad(p["theta0"].astype(np.float64), p["dv"][0].astype(np.float64))
+    p, _, gref = c1_reference
     try:
         at.set_tuning(at.load_table(path))
         for graph in (True, False):
             ctx = make_ctx(lib, [p], precision=prec, graph=graph)
             ctx.run(1)
             g = ctx.get_grad(0)
-            record("stored_table_32cubed", prec=prec, graph=graph, grad_rel=rel(g, gref))
-            assert rel(g, gref) < TOL_GRAD[prec]
             ctx.close()
+            _check_gradient(g, gref, c["levels"], c["base_ch"], prec, "stored_table_32cubed",
+                            graph=graph)
     finally:
         at.set_tuning([])
 
 
-@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("prec", precs(
+    bf16x3="BF16x3 along the 500-iteration fit: 2.9e-4 after iteration 1, then 8.6e-3 at 5, "
+           "1.3e-2 at 10, 4.8e-2 at 500 (> 2e-3 from iteration 5 on)",
+    bf16="pure BF16 along the 500-iteration fit: 1.8e-2 after iteration 1, 0.19 at 500"))
 def test_trajectory_500_iterations_32cubed_vs_stored_oracle(lib, prec):
     """The benchmark workload (32^3, 928 measurements, 3 levels, 16 channels,
     500 iterations, eager launches on two streams as the benchmark reports
     them, stored tuning table) against the stored FP64 oracle trajectory; the
-    captured-graph run must end on the same image bit for bit.  The oracle's own sensitivity (a 1-ulp change of
-    theta_0 moves its image by `floor` at iteration 500) bounds what any
-    implementation can match: FP32 must stay within 3 x floor.  Adam
-    amplifies any early difference along the trajectory by at most the factor
-    the oracle's 1-ulp run shows between iterations 1 and 500, so the BF16
-    forms, whose operand rounding already moves the first image, must stay
-    within that factor times their iteration-1 error, and that first error
-    within what the operand rounding explains."""
+    captured-graph run must end on the same image bit for bit.  The oracle's
+    own sensitivity (a 1-ulp change of theta_0 moves its image by `floor` at
+    iteration 500) bounds what any implementation can match: FP32 must stay
+    within 3 x floor at iteration 500.  The BF16 forms are held to the stated
+    2e-3 at every stored checkpoint whose oracle floor is at most a third of it
+    (all of them here); Adam amplifies any early difference by up to the
+    factor the oracle's 1-ulp run shows (about 1400 by iteration 500), which
+    their operand rounding cannot survive."""
     import os
     from paper_2507_14046_amd import autotune as at
     path = os.path.join(os.path.dirname(__file__), "golden", "oracle_c1_500.npz")
@@ -447,9 +490,11 @@ def test_trajectory_500_iterations_32cubed_vs_stored_oracle(lib, prec):
     lrel = [abs(l - z["losses"][cp - 1]) / z["losses"][cp - 1] for l, cp in zip(losses, cps)]
     record("trajectory500_32cubed", prec=prec, image_rel=e, floor=floor, amplification=amp,
            loss_rel=lrel)
-    first = {"fp32": 1e-5, "bf16x3": 1e-3, "bf16": 5e-2}[prec]
-    assert e[1] < first, e
+    assert e[1] < TOL_IMG[prec], e
     if prec == "fp32":
         assert e[500] < 3 * floor, (e[500], floor)
     else:
-        assert e[500] < amp * e[1], (e[500], amp, e[1])
+        floors = {int(cp): rel(z["floor_images"][i], z["images"][i]) for i, cp in enumerate(cps)}
+        for cp, err in e.items():
+            if floors[cp] <= TOL_IMG[prec] / 3:
+                assert err <= TOL_IMG[prec], (cp, err, e)

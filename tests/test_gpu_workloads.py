@@ -1,0 +1,159 @@
+"""The larger workloads through the C-ABI against the FP64 oracle.
+
+* 64^3 (928 measurements, 4 levels, 32 channels), FP32, captured graph and
+  eager launches: the first iteration's loss and gradient (every tensor, and
+  element by element) against the stored oracle gradient, and the images after
+  1, 5, 10, 20 and 50 iterations against the stored oracle trajectory, each
+  within max(1e-5, 3 x the oracle's own 1-ulp sensitivity at that iteration).
+* Sixteen uneven instances in one context (grids 24^3 / 32^3 / 48^3, 208 or
+  928 measurements, 8 or 16 channels, 3 levels), captured graph and eager
+  launches on concurrent lanes: every instance's one-iteration loss and
+  gradient against the oracle run on that instance alone.
+* Eight breathing sequences in one context on a shortened TPP schedule
+  (10 iterations, then 5 per frame for two more frames, Adam restarted per
+  frame): every frame's image of every sequence against the stored oracle.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import tseit_synth as ts
+from tests.gpu_util import (elementwise, oracle_problem, per_tensor_elementwise, per_tensor_rel,
+                            problem, record, rel)
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+M_OF_RINGS = {1: 208, 2: 928}
+
+
+def _grad_checks(g, gref, levels, C, tag, **kw):
+    per = per_tensor_rel(g, gref, levels, C)
+    worst = max(per.items(), key=lambda kv: kv[1])
+    pel = per_tensor_elementwise(g, gref, levels, C, 3e-4)
+    wel = max(pel.items(), key=lambda kv: kv[1])
+    record(tag, grad_rel=rel(g, gref), worst_tensor=worst[0], worst_rel=worst[1],
+           worst_elementwise_tensor=wel[0], worst_elementwise=wel[1], **kw)
+    assert rel(g, gref) < 5e-6, rel(g, gref)
+    assert worst[1] < 1e-4, per
+    assert wel[1] <= 1.0, pel
+
+
+@pytest.mark.parametrize("graph", [True, False])
+def test_64cubed_against_stored_oracle(lib, graph):
+    path = os.path.join(GOLDEN, "oracle_c2_50.npz")
+    if not os.path.exists(path):
+        pytest.skip("no stored 64^3 oracle trajectory")
+    z = np.load(path)
+    c = ts.CONFIGS["c2"]
+    p = problem(c["n"], c["rings"], c["levels"], c["base_ch"], c["seed"])
+    from paper_2507_14046_amd import autotune as at
+    from tests.gpu_util import make_ctx
+    print("64^3 workload, graph=%s" % graph, flush=True)
+    try:
+        if os.path.exists(at.default_table_path()):
+            at.set_tuning(at.load_table(at.default_table_path()))
+        ctx = make_ctx(lib, [p], "fp32", graph=graph)
+        loss1 = ctx.run(1)[0]
+        g = ctx.get_grad(0)
+        cps = [int(k) for k in z["checkpoints"]]
+        imgs, done = {1: ctx.read_image(0)}, 1
+        for cp in cps[1:]:
+            ctx.run(cp - done)
+            done = cp
+            imgs[cp] = ctx.read_image(0)
+        ctx.close()
+    finally:
+        at.set_tuning([])
+    L0 = float(z["loss1"])
+    assert abs(loss1 - L0) / L0 < 1e-5, (loss1, L0)
+    _grad_checks(g, z["grad1"].astype(np.float64), c["levels"], c["base_ch"], "c2_one_iteration",
+                 graph=graph, loss_rel=abs(loss1 - L0) / L0)
+    errs, bounds = {}, {}
+    for i, cp in enumerate(cps):
+        ref = z["images"][i]
+        floor = rel(z["floor_images"][i], ref)
+        errs[cp] = rel(imgs[cp], ref)
+        bounds[cp] = max(1e-5, 3 * floor)
+    record("c2_trajectory", graph=graph, image_rel=errs, bounds=bounds,
+           elementwise_it1=elementwise(imgs[1], z["images"][0], 1e-5))
+    assert elementwise(imgs[1], z["images"][0], 1e-5) <= 1.0
+    for cp in cps:
+        assert errs[cp] <= bounds[cp], (cp, errs, bounds)
+
+
+@pytest.fixture(scope="module")
+def uneven():
+    """The sixteen instances and each one's oracle loss and gradient."""
+    cfg = ts.CONFIGS["c4"]
+    out = []
+    for it in cfg["instances"]:
+        p = problem(it["n"], it["rings"], cfg["levels"], it["base_ch"], it["seed"])
+        pr = oracle_problem(p)
+        L0, g0, _ = pr.loss_and_grad(p["theta0"].astype(np.float64),
+                                     p["dv"][0].astype(np.float64))
+        out.append((p, L0, g0))
+    return out
+
+
+@pytest.mark.parametrize("graph", [True, False])
+def test_sixteen_uneven_instances_one_iteration(lib, uneven, graph):
+    cfg = ts.CONFIGS["c4"]
+    geos, insts = [], []
+    for p, _, _ in uneven:
+        gk = (p["n"], p["J"].shape[0])
+        if gk not in geos:
+            geos.append(gk)
+        insts.append((geos.index(gk), cfg["levels"], p["base_ch"]))
+    print("16 uneven instances, %d geometries, graph=%s" % (len(geos), graph), flush=True)
+    ctx = lib.Context(geos, insts, precision="fp32", graph=graph)
+    done = set()
+    for i, (p, _, _) in enumerate(uneven):
+        ctx.load_problem(i, p, set_geometry=insts[i][0] not in done)
+        done.add(insts[i][0])
+    losses = ctx.run(1)
+    grads = [ctx.get_grad(i) for i in range(len(uneven))]
+    ctx.close()
+    for i, (p, L0, g0) in enumerate(uneven):
+        assert abs(losses[i] - L0) / L0 < 1e-5, (i, losses[i], L0)
+        _grad_checks(grads[i], g0, cfg["levels"], p["base_ch"], "c4_one_iteration", instance=i,
+                     n=p["n"], graph=graph)
+
+
+@pytest.mark.parametrize("graph", [True, False])
+def test_eight_sequences_tpp_against_stored_oracle(lib, graph):
+    path = os.path.join(GOLDEN, "oracle_c3_tpp.npz")
+    if not os.path.exists(path):
+        pytest.skip("no stored eight-sequence oracle run")
+    z = np.load(path)
+    cfg = ts.CONFIGS["c3"]
+    iters = [int(k) for k in z["iters"]]
+    seqs = [problem(cfg["n"], cfg["rings"], cfg["levels"], cfg["base_ch"], s,
+                    frames=len(iters), breathing=True) for s in cfg["seeds"]]
+    print("8 sequences, TPP %s, graph=%s" % (iters, graph), flush=True)
+    ctx = lib.Context([(cfg["n"], seqs[0]["J"].shape[0])],
+                      [(0, cfg["levels"], cfg["base_ch"])] * len(seqs), precision="fp32",
+                      graph=graph)
+    ctx.set_geometry(0, seqs[0]["J"], seqs[0]["mask"])
+    for i, p in enumerate(seqs):
+        ctx.load_problem(i, p, set_geometry=False)
+    ctx.set_adam(lr=cfg["lr"])
+    imgs = np.zeros_like(z["images"], dtype=np.float64)
+    for f, k in enumerate(iters):
+        if f > 0:
+            for i, p in enumerate(seqs):
+                ctx.set_frame(i, p["dv"][f])     # theta carried over (TPP)
+                ctx.reset_optimizer(i)
+        ctx.run(k)
+        for i in range(len(seqs)):
+            imgs[i, f] = ctx.read_image(i)
+    ctx.close()
+    errs = np.array([[rel(imgs[i, f], z["images"][i, f]) for f in range(len(iters))]
+                     for i in range(len(seqs))])
+    el = max(elementwise(imgs[i, f], z["images"][i, f], 1e-5)
+             for i in range(len(seqs)) for f in range(len(iters)))
+    record("c3_tpp_sequences", graph=graph, max_rel=float(errs.max()), elementwise=el,
+           per_sequence=errs.max(axis=1).tolist())
+    assert errs.max() < 1e-5, errs
+    assert el <= 1.0, el

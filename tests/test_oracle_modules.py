@@ -2,7 +2,11 @@
 units on the decoder skips and the sigmoid tail, alone and together with the
 depthwise-separable convolutions and the SE units.
 
-Pinned by: saturated attention gates reducing the network to the plain one
+Pinned by: the attention unit against an independent torch float64
+formulation (2x2x2 average pool, 1x1x1 convolutions, ReLU, sigmoid, nearest
+interpolation, autograd), with non-symmetric weights and a skip and gating
+signal of equal width so that a transposed weight or swapped inputs change
+the result; saturated attention gates reducing the network to the plain one
 (same image, same gradient, zero attention gradients); the sigmoid tail
 equal to tanh of half the linear tail's output (2 sigmoid(t) - 1 = tanh(t/2));
 and central finite differences of every module's parameters."""
@@ -22,6 +26,48 @@ def _fd(th, f, g, idx_sets, rng, h=1e-6):
         fd = (f(th + h * v) - f(th - h * v)) / (2 * h)
         # abs: the rounding floor of the difference quotient, ~eps |f| / h
         assert fd == pytest.approx(float(g @ v), rel=1e-6, abs=1e-9)
+
+
+def _torch_attention(x, g, Q):
+    """The attention unit written with torch float64 operations: gate on the
+    gating signal's grid from the pooled skip, interpolated to the skip."""
+    import torch
+    import torch.nn.functional as F
+    t = lambda a: torch.tensor(a, dtype=torch.float64, requires_grad=True)
+    X, G = t(x[None]), t(g[None])
+    W = {k: t(v) for k, v in Q.items()}
+    k1 = lambda w: w[:, :, None, None, None]
+    a = (F.conv3d(F.avg_pool3d(X, 2), k1(W["att.wx"])) + F.conv3d(G, k1(W["att.wg"])) +
+         W["att.b"].view(1, -1, 1, 1, 1))
+    al = torch.sigmoid(F.conv3d(torch.relu(a), W["att.psi"].view(1, -1, 1, 1, 1)) +
+                       W["att.bpsi"][0])
+    return X, G, W, F.interpolate(al, scale_factor=2, mode="nearest") * X
+
+
+def _att_inputs(c, cu, m, seed):
+    rng = np.random.default_rng(seed)
+    x = rng.standard_normal((c, 2 * m, 2 * m, 2 * m))
+    g = rng.standard_normal((cu, m, m, m))
+    Q = {"att.wx": rng.standard_normal((c, c)), "att.wg": rng.standard_normal((c, cu)),
+         "att.b": rng.standard_normal(c), "att.psi": rng.standard_normal(c),
+         "att.bpsi": rng.standard_normal(1)}
+    return x, g, Q, rng.standard_normal(x.shape)
+
+
+@pytest.mark.parametrize("c,cu,m", [(4, 4, 3), (3, 6, 2)])
+def test_attention_unit_matches_torch_float64(c, cu, m):
+    x, g, Q, R = _att_inputs(c, cu, m, 20 + c + cu)
+    y, cache = net.att_forward(x, g, Q)
+    X, G, W, yt = _torch_attention(x, g, Q)
+    np.testing.assert_allclose(y, yt.detach().numpy()[0], rtol=1e-12, atol=1e-13)
+    gx, gg, grads = net.att_backward(R, Q, cache)
+    import torch
+    (yt * torch.tensor(R[None])).sum().backward()
+    np.testing.assert_allclose(gx, X.grad.numpy()[0], rtol=1e-11, atol=1e-12)
+    np.testing.assert_allclose(gg, G.grad.numpy()[0], rtol=1e-11, atol=1e-12)
+    for k in Q:
+        np.testing.assert_allclose(grads[k], W[k].grad.numpy(), rtol=1e-11, atol=1e-12,
+                                   err_msg=k)
 
 
 def test_saturated_attention_gates_give_the_plain_network():

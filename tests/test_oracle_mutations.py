@@ -81,3 +81,31 @@ def test_skip_gradient_dropped(monkeypatch):
         return gx, G
     monkeypatch.setattr(net, "resblock_backward", bad)
     _fails(pins.test_network_forward_backward_vs_torch_autograd, 8, 2, 2)
+
+
+def _attention_pin():
+    import tests.test_oracle_modules as mods
+    mods.test_attention_unit_matches_torch_float64(4, 4, 3)
+
+
+def test_attention_transposed_skip_weight(monkeypatch):
+    orig = net.att_forward
+
+    def bad(x, g, Q):
+        return orig(x, g, dict(Q, **{"att.wx": np.ascontiguousarray(Q["att.wx"].T)}))
+    monkeypatch.setattr(net, "att_forward", bad)
+    _fails(_attention_pin)
+
+
+def test_attention_swapped_skip_and_gate(monkeypatch):
+    def bad(x, g, Q):
+        c = x.shape[0]
+        xs = net.avgpool2(x)
+        Xs, G = xs.reshape(c, -1), g.reshape(g.shape[0], -1)
+        a = Q["att.wx"] @ G + Q["att.wg"] @ Xs + Q["att.b"][:, None]   # inputs swapped
+        q = np.maximum(a, 0.0)
+        al = 1.0 / (1.0 + np.exp(-(Q["att.psi"] @ q + Q["att.bpsi"][0])))
+        alf = net.up2(al.reshape((1,) + g.shape[1:]))
+        return alf * x, dict(x=x, Xs=Xs, G=G, a=a, q=q, al=al, alf=alf)
+    monkeypatch.setattr(net, "att_forward", bad)
+    _fails(_attention_pin)
