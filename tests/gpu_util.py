@@ -84,3 +84,109 @@ def per_tensor_elementwise(g_gpu, g_ref, levels, C, tol):
         out[name] = elementwise(g_gpu[off:off + k], g_ref[off:off + k], tol)
         off += k
     return out
+
+
+def oracle_gradient_floor(p):
+    """The oracle's one-iteration gradient from theta_0 moved by one FP32 ulp
+    per entry (random direction): how far FP32 rounding of theta_0 alone moves
+    the gradient being compared (its sensitivity floor)."""
+    from tests.golden.make_golden import ulp_perturb
+    pr = oracle_problem(p)
+    _, g, _ = pr.loss_and_grad(ulp_perturb(p["theta0"]).astype(np.float64),
+                               p["dv"][0].astype(np.float64))
+    return g
+
+
+def oracle_kink_variants(p, rel_tau=1e-6, max_kinks=3):
+    """Oracle one-iteration gradients with the ReLU decisions whose
+    pre-activation lies within rel_tau of its tensor's median magnitude taken
+    the other way, every non-empty combination of them (none if there are more
+    than max_kinks).  Such a decision rests on the last bits of the
+    pre-activation, which FP32 arithmetic can put on either side of the kink;
+    the derivative there is 0 or 1 and the two gradients differ by whole
+    terms.  A flipped decision moves the forward value by at most rel_tau of
+    the scale."""
+    from oracle import net
+    pr = oracle_problem(p)
+    th = p["theta0"].astype(np.float64)
+    dv = p["dv"][0].astype(np.float64)
+    orig = net.relu
+    calls = []
+
+    def spy(x):
+        a = np.abs(x).ravel()
+        calls.append(np.flatnonzero(a < rel_tau * np.median(a)))
+        return orig(x)
+    try:
+        net.relu = spy
+        pr.loss_and_grad(th, dv)
+        kinks = [(ci, int(j)) for ci, idx in enumerate(calls) for j in idx]
+        if not kinks or len(kinks) > max_kinks:
+            return []
+        out = []
+        for sel in range(1, 2 ** len(kinks)):
+            flips = [kinks[b] for b in range(len(kinks)) if (sel >> b) & 1]
+            count = [0]
+
+            def flipped(x, flips=flips, count=count):
+                ci = count[0]
+                count[0] += 1
+                y = orig(x).copy()
+                yf, xf = y.reshape(-1), x.reshape(-1)
+                for c, j in flips:
+                    if c == ci:  # taken inactive, or active with a value below any scale
+                        yf[j] = 0.0 if xf[j] > 0 else 1e-300
+                return y
+            net.relu = flipped
+            out.append(pr.loss_and_grad(th, dv)[1])
+        return out
+    finally:
+        net.relu = orig
+
+
+def _grad_bounds(g, gref, levels, C, tol, tol_tensor, tol_elem):
+    per = per_tensor_rel(g, gref, levels, C)
+    pel = per_tensor_elementwise(g, gref, levels, C, tol_elem)
+    out = dict(grad_rel=rel(g, gref), worst_tensor=max(per.items(), key=lambda kv: kv[1]),
+               worst_elementwise=max(pel.items(), key=lambda kv: kv[1]))
+    ok = (out["grad_rel"] < tol and out["worst_tensor"][1] < tol_tensor and
+          out["worst_elementwise"][1] <= 1.0)
+    return ok, out, per, pel
+
+
+def check_gradient(g, gref, levels, C, tol, tol_tensor, tol_elem, floor_fn=None, kink_fn=None):
+    """Relative L2 of the whole gradient within `tol`, of every tensor within
+    `tol_tensor`, and every value within `tol_elem` of its tensor's scale.
+    Where that fails: the same bounds against any oracle gradient with the
+    ReLU decisions taken within FP32 resolution of the kink the other way
+    (`kink_fn`), or, where `floor_fn` gives the oracle's gradient from a 1-ulp
+    perturbed theta_0, within 3x that floor (the gradient is no better
+    conditioned than that).  Returns the numbers, with "ok"."""
+    ok, out, per, pel = _grad_bounds(g, gref, levels, C, tol, tol_tensor, tol_elem)
+    out["floor"] = None
+    out["kink_alternative"] = None
+    if ok:
+        out["ok"] = True
+        return out
+    if kink_fn is not None:
+        alts = kink_fn()
+        out["kink_alternatives"] = len(alts)
+        for k, ga in enumerate(alts):
+            ok_k, out_k, _, _ = _grad_bounds(g, ga, levels, C, tol, tol_tensor, tol_elem)
+            if ok_k:
+                out["kink_alternative"] = dict(index=k, **out_k)
+                out["ok"] = True
+                return out
+    if floor_fn is None:
+        out["ok"] = False
+        return out
+    gf = floor_fn()
+    fper = per_tensor_rel(gf, gref, levels, C)
+    fpel = per_tensor_elementwise(gf, gref, levels, C, tol_elem)
+    out["floor"] = rel(gf, gref)
+    out["floor_worst_tensor"] = max(fper.items(), key=lambda kv: kv[1])
+    ok = out["grad_rel"] < max(tol, 3 * out["floor"])
+    ok = ok and all(per[k] < max(tol_tensor, 3 * fper[k]) for k in per)
+    ok = ok and all(pel[k] <= max(1.0, 3 * fpel[k]) for k in pel)
+    out["ok"] = ok
+    return out
