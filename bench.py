@@ -633,7 +633,50 @@ def cpu_baseline(p, cfg, iters=3):
                        "warm-up iteration (%s s each)" % (iters, ", ".join("%.1f" % t for t in ts_)))
 
 
-SECTIONS = ("c0", "c2", "c3", "c4", "ops", "network", "ablation")
+SECTIONS = ("c0", "c2", "c3", "c4", "ops", "network", "ablation", "kernels64")
+
+
+def kernels64(d2ip, at, ts, prec, torch, cache, reps=20):
+    """The 64^3 workload's kernels in one form, each timed in isolation with
+    HIP events on the context stream (after two eager iterations): J sigma and
+    J^T g (HBM streams of the 767 MB compact J), Adam over its 5.97 M
+    parameters, and the three passes of the largest conv (decoder level 0,
+    96 -> 32 channels, 43.5 GFLOP per pass)."""
+    cfg = ts.CONFIGS["c2"]
+    p = ts.make_problem(cfg["n"], cfg["rings"], cfg["levels"], cfg["base_ch"], cfg["seed"])
+    geos, insts = [(cfg["n"], p["J"].shape[0])], [(0, cfg["levels"], cfg["base_ch"])]
+    at.set_tuning(tuned(d2ip, at, geos, insts, prec, cache))
+    ctx = d2ip.Context(geos, insts, precision=prec, graph=False)
+    L = d2ip._lib
+    out = {}
+    try:
+        ctx.load_problem(0, p)
+        ctx.set_adam(lr=cfg["lr"])
+        ctx.run(2)
+        M, qa, P = p["J"].shape[0], int(p["mask"].sum()), ctx.n_params[0]
+        jb = 4.0 * M * qa
+        for name, kid, work in (("jvec", L.KERNEL_JVEC, jb), ("jtvec", L.KERNEL_JTVEC, jb),
+                                ("adam", L.KERNEL_ADAM, 28.0 * P)):
+            ms = ctx.time_kernel(0, kid, 0, reps)
+            out[name] = dict(ms=ms, bytes=work, achieved=work / (ms * 1e-3) / 1e9, unit="GB/s",
+                             frac=work / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS)
+        blocks = block_convs(cfg["levels"], cfg["base_ch"], cfg["n"])
+        k = len(blocks) - 1
+        n, cin, cout = blocks[k]
+        fl = conv_flops(n, cin, cout, 27)
+        for name, kid in (("conv_fwd", L.KERNEL_CONV_FWD), ("conv_dgrad", L.KERNEL_CONV_DGRAD),
+                          ("conv_wgrad", L.KERNEL_CONV_WGRAD)):
+            ms = ctx.time_kernel(0, kid, k, reps)
+            out["%s[block%d %d^3 %d->%d]" % (name, k, n, cin, cout)] = dict(
+                ms=ms, flop=fl, achieved=fl / (ms * 1e-3) / 1e12, unit="TFLOP/s",
+                frac=fl / (ms * 1e-3) / 1e12 / PEAK_TFLOPS[prec])
+    finally:
+        ctx.close()
+        at.set_tuning([])
+    for name, r in out.items():
+        log("  64^3 %s %-36s %9.4f ms  %9.2f %s (%.1f%% of peak)"
+            % (prec, name, r["ms"], r["achieved"], r["unit"], 100 * r["frac"]))
+    return dict(form=prec, kernels=out)
 
 
 def run_section(name, a):
@@ -658,6 +701,8 @@ def run_section(name, a):
         out = dict(dwsep=dwsep_ops(d2ip, torch), se=se_ops(d2ip, torch))
     elif name == "network":
         out = dwsep_network(d2ip, torch, ts)
+    elif name == "kernels64":
+        out = {prec: kernels64(d2ip, at, ts, prec, torch, cache) for prec in a.forms.split(",")}
     elif name == "ablation":
         from paper_2507_14046_amd import schedule
         cfg = ts.CONFIGS["c1"]
@@ -684,7 +729,7 @@ def spawn_section(name, a, timeout_s):
     """Run one optional workload in a child process; its result, or its exit
     status when it failed."""
     cmd = [sys.executable, os.path.abspath(__file__), "--section", name,
-           "--ablation-form", a.ablation_form]
+           "--ablation-form", a.ablation_form, "--forms", "fp32,bf16"]
     log("section %s: starting a child process" % name)
     t0 = time.time()
     try:
@@ -697,6 +742,17 @@ def spawn_section(name, a, timeout_s):
     res = json.loads(lines[-1][len("SECTION_JSON: "):])
     res["seconds"] = time.time() - t0
     return res
+
+
+def traffic_probe(mib):
+    """Plain device copies of known size: the scale of the HBM byte counters."""
+    import torch
+    src = torch.ones(mib << 18, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    log("traffic probe: 3 copies of %d MiB" % mib)
 
 
 def main():
@@ -717,7 +773,9 @@ def main():
     ap.add_argument("--ablation", action="store_true",
                     help="also the D2IP schedule ablation (UPWS / TPP), 20 frames at 32^3")
     ap.add_argument("--ablation-form", default="fp32")
-    ap.add_argument("--section", choices=SECTIONS, help=argparse.SUPPRESS)
+    ap.add_argument("--section", choices=SECTIONS,
+                    help="run one optional workload alone in this process (kernels64: the "
+                         "64^3 kernels of each --forms form) and print its result")
     ap.add_argument("--traffic-probe", type=int, default=0,
                     help="MiB copied 3 times after the kernel table (counter calibration)")
     a = ap.parse_args()
@@ -727,6 +785,8 @@ def main():
         sys.exit(2)
     if a.section:
         res = run_section(a.section, a)
+        if a.traffic_probe > 0:
+            traffic_probe(a.traffic_probe)
         print("SECTION_JSON: " + json.dumps(res), flush=True)
         return
 
@@ -840,20 +900,14 @@ def main():
                                                 unit=r_["unit"], frac=r_["frac"]) for r_ in rows})
         at.set_tuning([])
     if a.traffic_probe > 0:
-        # plain device copies of known size: the scale of the HBM byte counters
-        src = torch.ones(a.traffic_probe << 18, dtype=torch.float32, device="cuda")
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        log("traffic probe: 3 copies of %d MiB" % a.traffic_probe)
+        traffic_probe(a.traffic_probe)
     if cache.get("fresh"):
         # shapes tuned in this run (no stored table covered them)
         os.makedirs(os.path.join(ROOT, "gpurun_out"), exist_ok=True)
         at.save(at.merge(cache["fresh"]), os.path.join(ROOT, "gpurun_out", "tuned_fresh.json"))
 
     sections = {}
-    wanted = ([s for s in ("c0", "c2", "c3", "c4") if a.configs] +
+    wanted = ([s for s in ("c0", "c2", "c3", "c4", "kernels64") if a.configs] +
               (["ops", "network"] if a.ops else []) + (["ablation"] if a.ablation else []))
     for name in wanted:
         sections[name] = spawn_section(name, a, timeout_s=900)

@@ -438,6 +438,13 @@ d2ip_status d2ip_op_se_backward(const float* x, const float* w1, const float* b1
 d2ip_status d2ip_op_j_forward(const float* J, const float* sigma, float* p, int M, int Q,
                               void* hip_stream);
 
+/* Data term of Eq. (4) in its mean-squared form (Sec. V-A calls it the MSE
+ * loss) for M predicted voltages p against the measured dv: r = p - dv,
+ * *loss = (1/M) sum r^2 (one double in device memory), accumulated in FP64 in
+ * a fixed order, and gp = (2/M) r (M floats; may be NULL). */
+d2ip_status d2ip_op_mse_loss(const float* p, const float* dv, float* gp, double* loss, int M,
+                             void* hip_stream);
+
 /* Workspace bytes of d2ip_op_jt. */
 d2ip_status d2ip_op_jt_bytes(int M, int Q, size_t* out);
 

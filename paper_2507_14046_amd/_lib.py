@@ -117,6 +117,7 @@ SIGNATURES = {
     "d2ip_op_se_backward": [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _i, _i, _i,
                             _vp, ctypes.c_size_t, _vp],
     "d2ip_op_j_forward": [_vp, _vp, _vp, _i, _i, _vp],
+    "d2ip_op_mse_loss": [_vp, _vp, _vp, _vp, _i, _vp],
     "d2ip_op_jt_bytes": [_i, _i, _c_size_p],
     "d2ip_op_jt": [_vp, _vp, _vp, _i, _i, _vp, ctypes.c_size_t, _vp],
     "d2ip_op_jt_noalloc": [_vp, _vp, _vp, _i, _i, _vp],

@@ -505,6 +505,24 @@ __global__ void k_jt_sum(const float* part, int Q, float* out) {
   reinterpret_cast<float4*>(out)[q4] = acc;
 }
 
+// Data term of Eq. (4) in the mean-squared form: r = p - dv (FP32), loss =
+// (1/M) sum r^2 accumulated in FP64 and reduced in one block in a fixed
+// order, gp = (2/M) r.
+__global__ __launch_bounds__(256) void k_mse(const float* __restrict__ p,
+                                             const float* __restrict__ dv, int M,
+                                             float* __restrict__ gp, double* __restrict__ loss) {
+  __shared__ double sh[4];
+  double acc = 0.0;
+  const float two_m = 2.f / (float)M;
+  for (int m = threadIdx.x; m < M; m += 256) {
+    const float r = p[m] - dv[m];
+    acc += (double)r * (double)r;
+    if (gp) gp[m] = two_m * r;
+  }
+  const double t = block_sum(acc, sh);
+  if (threadIdx.x == 0) *loss = t / (double)M;
+}
+
 // 4D-TV of one image (Sec. III-E, Eqs. (11)-(13)), one thread per voxel.
 // Spatial: q(v) = sqrt(dz^2 + dy^2 + dx^2 + eps) of the forward differences
 // (0 where the neighbour is outside the grid); v's gradient collects -d/q(v)
@@ -649,6 +667,10 @@ void jv_dense(const float* J, int M, int Q, const float* sigma, float* p, hipStr
 }
 
 size_t jt_dense_scratch(int Q) { return (size_t)kJtSlices * Q; }
+
+void mse_loss(const float* p, const float* dv, int M, float* gp, double* loss, hipStream_t s) {
+  hipLaunchKernelGGL(k_mse, dim3(1), dim3(256), 0, s, p, dv, M, gp, loss);
+}
 
 void jt_dense(const float* J, int M, int Q, const float* g, float* part, float* out,
               hipStream_t s) {

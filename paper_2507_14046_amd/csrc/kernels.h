@@ -243,6 +243,8 @@ void ln_dx(const float* gz, const float* h, PairRef st, PairRef bw, const float*
 // p = J sigma and out = J^T g for a dense row-major M x Q J (Q % 4 == 0).
 void jv_dense(const float* J, int M, int Q, const float* sigma, float* p, hipStream_t s);
 size_t jt_dense_scratch(int Q);  // floats of `part`
+// loss = (1/M) sum (p - dv)^2 (FP64 accumulation, one block), gp = (2/M)(p - dv)
+void mse_loss(const float* p, const float* dv, int M, float* gp, double* loss, hipStream_t s);
 void jt_dense(const float* J, int M, int Q, const float* g, float* part, float* out,
               hipStream_t s);
 // Depthwise 3x3x3 convolution (channels-last [n^3][C], C % 4 == 0, w [C][27]):

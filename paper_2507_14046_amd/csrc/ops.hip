@@ -621,6 +621,15 @@ d2ip_status d2ip_op_jt(const float* J, const float* g, float* out, int M, int Q,
   return D2IP_OK;
 }
 
+d2ip_status d2ip_op_mse_loss(const float* p, const float* dv, float* gp, double* loss, int M,
+                             void* hip_stream) {
+  if (!p || !dv || !loss) return api_fail(D2IP_EINVAL, "null p, dv or loss");
+  if (M < 1) return api_fail(D2IP_EINVAL, "need M >= 1");
+  mse_loss(p, dv, M, gp, loss, reinterpret_cast<hipStream_t>(hip_stream));
+  OPCHK(hipGetLastError());
+  return D2IP_OK;
+}
+
 d2ip_status d2ip_op_jt_noalloc(const float* J, const float* g, float* out, int M, int Q,
                                void* hip_stream) {
   if (!J || !g || !out) return api_fail(D2IP_EINVAL, "null J, g or out");

@@ -387,6 +387,43 @@ def _measure_fn():
     return _J
 
 
+class MSELossFn:
+    """(1/M) sum (p - dv)^2 as a float64 scalar tensor: reduced in FP64 on the
+    device by the library (the data term of Eq. (4)); gradient (2/M)(p - dv)."""
+
+    @staticmethod
+    def apply(p, dv):
+        return _mse_fn().apply(p, dv)
+
+
+def _mse_fn():
+    if "mse" in _FNS:
+        return _FNS["mse"]
+    torch = _torch()
+
+    class _MSE(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, p, dv):
+            lib = L.load()
+            p, dv = p.contiguous(), dv.contiguous()
+            if p.dtype != torch.float32 or dv.dtype != torch.float32 or p.numel() != dv.numel():
+                raise TypeError("p and dv must be float32 tensors of equal size")
+            loss = torch.empty((), dtype=torch.float64, device=p.device)
+            gp = torch.empty_like(p)
+            L.check(lib.d2ip_op_mse_loss(_p(p), _p(dv), _p(gp), _p(loss), p.numel(),
+                                         _stream(p)))
+            ctx.save_for_backward(gp)
+            return loss
+
+        @staticmethod
+        def backward(ctx, gl):
+            (gp,) = ctx.saved_tensors
+            return gp * gl.to(torch.float32), None
+
+    _FNS["mse"] = _MSE
+    return _MSE
+
+
 # ----------------------------------------------------------------------------
 # the prior of Eq. (3) composed from the operators
 # ----------------------------------------------------------------------------
@@ -570,7 +607,7 @@ class DIPNet:
         return s * _up(gate[:, None], n // 2)
 
     def loss(self, theta, Z, mask, J, dv):
-        """(1/M) sum (J sigma - dv)^2, with J sigma and J^T on the library's kernels."""
+        """(1/M) sum (J sigma - dv)^2 (float64 scalar), with J sigma, J^T and
+        the FP64 loss reduction on the library's kernels."""
         sigma = self.forward(theta, Z, mask)
-        r = MeasureFn.apply(sigma, J) - dv
-        return (r * r).sum() / J.shape[0]
+        return MSELossFn.apply(MeasureFn.apply(sigma, J), dv)

@@ -18,7 +18,10 @@ frames 1 and 2, Adam restarted per frame): each frame's image, FP32-rounded.
 
 With --grad it also stores the loss and the theta-gradient of the first
 iteration (at theta_0), the gradient rounded once to FP32 to keep the file
-small (a relative change of at most 2^-24 per entry).
+small (a relative change of at most 2^-24 per entry).  --shrink PATH rewrites
+a stored file with its images rounded once to FP32 and without the stored
+gradient (for files that would otherwise be tens of MB; a test can compute
+the first gradient itself).
 """
 import argparse
 import hashlib
@@ -82,15 +85,26 @@ def sequences_c3(log):
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("config", choices=["c0", "c1", "c2", "c3"])
+    ap.add_argument("config", choices=["c0", "c1", "c2", "c3"], nargs="?", default="c1")
     ap.add_argument("--iters", type=int, default=None)
     ap.add_argument("--floor", action="store_true")
     ap.add_argument("--grad", action="store_true")
     ap.add_argument("--out", default=None)
+    ap.add_argument("--shrink", default=None)
     a = ap.parse_args()
 
     def log(m):
         print(m, flush=True)
+
+    if a.shrink:
+        z = dict(np.load(a.shrink))
+        z.pop("grad1", None)
+        for k in ("images", "floor_images"):
+            if k in z:
+                z[k] = z[k].astype(np.float32)
+        np.savez_compressed(a.shrink, **z)
+        log("shrunk " + a.shrink)
+        return
 
     if a.config == "c3":
         path = a.out or os.path.join(HERE, "oracle_c3_tpp.npz")

@@ -212,3 +212,25 @@ def test_recomputed_activations_at_64cubed(lib):
     np.testing.assert_array_equal(g_keep, g_rec)
     assert peak_rec < peak_keep, e
     assert e["grad_vs_fused"] < 1e-3, e
+
+
+@pytest.mark.parametrize("M", [1, 208, 928, 5000])
+def test_mse_loss_operator_matches_fp64(lib, M):
+    """d2ip_op_mse_loss: the data term (1/M) sum (p - dv)^2 reduced in FP64 on
+    the device, and its gradient (2/M)(p - dv), against FP64 on the host; the
+    autograd wrapper passes the gradient on."""
+    import torch
+    from paper_2507_14046_amd import ops
+    rng = np.random.default_rng(M)
+    p = rng.standard_normal(M).astype(np.float32)
+    dv = (p + 1e-3 * rng.standard_normal(M)).astype(np.float32)  # small residuals
+    P, DV = dev(p, True), dev(dv)
+    loss = ops.MSELossFn.apply(P, DV)
+    loss.backward()
+    r = p.astype(np.float64) - dv.astype(np.float64)
+    want = float(r @ r) / M
+    got = float(loss)
+    assert loss.dtype == torch.float64
+    record("op_mse_loss", M=M, rel=abs(got - want) / want)
+    assert abs(got - want) / want < 1e-6, (got, want)
+    np.testing.assert_allclose(host(P.grad), 2.0 * r / M, rtol=1e-6, atol=1e-6 * np.abs(2 * r / M).max())
