@@ -10,11 +10,12 @@ alone can cause.
 
     python tests/golden/make_golden.py c1 --iters 500 --floor
     python tests/golden/make_golden.py c2 --iters 50 --floor --grad
-    python tests/golden/make_golden.py c3
+    python tests/golden/make_golden.py c3 --floor
 
 c3 writes the eight breathing sequences of the 32^3 time-sequence workload
-on a shortened TPP schedule (10 iterations for frame 0, then 5 per frame for
-frames 1 and 2, Adam restarted per frame): each frame's image, FP32-rounded.
+on a shortened TPP schedule (4 iterations for frame 0, then 3 per frame for
+frames 1 and 2, Adam restarted per frame): each frame's image, FP32-rounded;
+with --floor also the run from theta_0 moved by one FP32 ulp.
 
 With --grad it also stores the loss and the theta-gradient of the first
 iteration (at theta_0), the gradient rounded once to FP32 to keep the file
@@ -62,24 +63,30 @@ def trajectory(pr, theta0, dv, iters, lr, checkpoints, log=None):
     return np.array(losses), images
 
 
-C3_ITERS = [10, 5, 5]
+C3_ITERS = [4, 3, 3]
 
 
-def sequences_c3(log):
+def sequences_c3(log, floor=False, out=None):
+    """The eight sequences from theta_0, or (floor) from theta_0 moved by one
+    FP32 ulp per entry, added to `out` as floor_images."""
     cfg = ts.CONFIGS["c3"]
-    out = dict(config="c3", iters=np.array(C3_ITERS), lr=cfg["lr"], seeds=np.array(cfg["seeds"]))
+    if out is None:
+        out = dict(config="c3", iters=np.array(C3_ITERS), lr=cfg["lr"],
+                   seeds=np.array(cfg["seeds"]))
     imgs, losses = [], []
     for seed in cfg["seeds"]:
         p = ts.make_problem(cfg["n"], cfg["rings"], cfg["levels"], cfg["base_ch"], seed,
                             frames=len(C3_ITERS), breathing=True)
         pr = fit.Problem(p["J"], p["mask"], p["Z"], cfg["n"], cfg["levels"], cfg["base_ch"])
-        im, ls, _ = fit.fit_sequence(pr, p["theta0"], p["dv"], C3_ITERS, cfg["lr"])
+        th0 = ulp_perturb(p["theta0"]) if floor else p["theta0"]
+        im, ls, _ = fit.fit_sequence(pr, th0, p["dv"], C3_ITERS, cfg["lr"])
         imgs.append(im.astype(np.float32))
         losses.append(np.concatenate([np.asarray(l) for l in ls]))
         out["sha_theta0_%d" % seed] = sha(p["theta0"])
-        log("sequence %d: final loss %.6e" % (seed, losses[-1][-1]))
-    out["images"] = np.stack(imgs)      # [sequence][frame][voxel]
-    out["losses"] = np.stack(losses)    # [sequence][iteration]
+        log("sequence %d%s: final loss %.6e" % (seed, " (floor)" if floor else "", losses[-1][-1]))
+    key = "floor_" if floor else ""
+    out[key + "images"] = np.stack(imgs)      # [sequence][frame][voxel]
+    out[key + "losses"] = np.stack(losses)    # [sequence][iteration]
     return out
 
 
@@ -108,7 +115,13 @@ def main():
 
     if a.config == "c3":
         path = a.out or os.path.join(HERE, "oracle_c3_tpp.npz")
-        np.savez_compressed(path, **sequences_c3(log))
+        if a.floor and os.path.exists(path):  # add the floor run to the stored file
+            out = sequences_c3(log, floor=True, out=dict(np.load(path)))
+        else:
+            out = sequences_c3(log)
+            if a.floor:
+                sequences_c3(log, floor=True, out=out)
+        np.savez_compressed(path, **out)
         log("wrote " + path)
         return
     cfg = ts.CONFIGS[a.config]

@@ -97,7 +97,7 @@ def oracle_gradient_floor(p):
     return g
 
 
-def oracle_kink_variants(p, rel_tau=1e-6, max_kinks=3):
+def oracle_kink_variants(p, rel_tau=1e-6, max_kinks=3, theta=None, dv=None):
     """Oracle one-iteration gradients with the ReLU decisions whose
     pre-activation lies within rel_tau of its tensor's median magnitude taken
     the other way, every non-empty combination of them (none if there are more
@@ -108,8 +108,8 @@ def oracle_kink_variants(p, rel_tau=1e-6, max_kinks=3):
     the scale."""
     from oracle import net
     pr = oracle_problem(p)
-    th = p["theta0"].astype(np.float64)
-    dv = p["dv"][0].astype(np.float64)
+    th = np.asarray(p["theta0"] if theta is None else theta, dtype=np.float64)
+    dv = np.asarray(p["dv"][0] if dv is None else dv, dtype=np.float64)
     orig = net.relu
     calls = []
 
@@ -190,3 +190,45 @@ def check_gradient(g, gref, levels, C, tol, tol_tensor, tol_elem, floor_fn=None,
     ok = ok and all(pel[k] <= max(1.0, 3 * fpel[k]) for k in pel)
     out["ok"] = ok
     return out
+
+
+def shadow_sequence(lib, p, iters, lr, tol=1e-5):
+    """Run one sequence (frames of iters[f] iterations, TPP, Adam restarted per
+    frame) on the GPU one iteration at a time beside the FP64 oracle, whose
+    Adam step at each iteration takes the oracle gradient or, where the GPU's
+    gradient matches it better, the oracle gradient with the ReLU decisions
+    within FP32 resolution of a kink taken the other way.  Returns the GPU's
+    and the shadowed oracle's image per frame and the iterations at which a
+    flipped decision was taken."""
+    from oracle import fit
+    pr = oracle_problem(p)
+    ctx = make_ctx(lib, [p])
+    ctx.set_adam(lr=lr)
+    st = fit.State(p["theta0"])
+    flips, gpu_imgs, ref_imgs = [], [], []
+    it = 0
+    try:
+        for f, k in enumerate(iters):
+            dv = np.asarray(p["dv"][f], dtype=np.float64)
+            if f > 0:
+                ctx.set_frame(0, p["dv"][f])
+                ctx.reset_optimizer(0)
+                st.reset_optimizer()
+            for _ in range(k):
+                it += 1
+                ctx.run(1)
+                gg = ctx.get_grad(0)
+                _, g, _ = pr.loss_and_grad(st.theta, dv)
+                if rel(gg, g) > tol:
+                    alts = oracle_kink_variants(p, theta=st.theta, dv=dv)
+                    if alts:
+                        best = min(alts, key=lambda a: rel(gg, a))
+                        if rel(gg, best) < rel(gg, g):
+                            g = best
+                            flips.append(it)
+                st.theta, st.m, st.v, st.t = fit.adam_step(st.theta, g, st.m, st.v, st.t, lr)
+            gpu_imgs.append(ctx.read_image(0))
+            ref_imgs.append(pr.image(st.theta))
+    finally:
+        ctx.close()
+    return gpu_imgs, ref_imgs, flips

@@ -11,7 +11,9 @@
   gradient against the oracle run on that instance alone.
 * Eight breathing sequences in one context on a shortened TPP schedule
   (10 iterations, then 5 per frame for two more frames, Adam restarted per
-  frame): every frame's image of every sequence against the stored oracle.
+  frame): every frame's image of every sequence against the stored oracle,
+  within max(1e-5, 3 x the oracle's own 1-ulp run at that frame); some seeds'
+  trajectories are that sensitive from the first Adam steps on.
 """
 import os
 
@@ -19,8 +21,8 @@ import numpy as np
 import pytest
 
 import tseit_synth as ts
-from tests.gpu_util import (check_gradient, elementwise, oracle_gradient_floor, oracle_kink_variants, oracle_problem,
-                            problem, record, rel)
+from tests.gpu_util import (check_gradient, elementwise, oracle_gradient_floor, oracle_kink_variants,
+                            oracle_problem, problem, record, rel, shadow_sequence)
 
 pytestmark = pytest.mark.gpu
 
@@ -87,9 +89,13 @@ def test_64cubed_against_stored_oracle(lib, c2_gradient, graph):
         floor = rel(z["floor_images"][i], ref)
         errs[cp] = rel(imgs[cp], ref)
         bounds[cp] = max(1e-5, 3 * floor)
-    record("c2_trajectory", graph=graph, image_rel=errs, bounds=bounds,
-           elementwise_it1=elementwise(imgs[1], z["images"][0], 1e-5))
-    assert elementwise(imgs[1], z["images"][0], 1e-5) <= 1.0
+    # element by element after the first iteration, against 1e-5 of the scale
+    # or 3x what the oracle's own 1-ulp run shows there
+    el = elementwise(imgs[1], z["images"][0], 1e-5)
+    el_floor = elementwise(z["floor_images"][0], z["images"][0], 1e-5)
+    record("c2_trajectory", graph=graph, image_rel=errs, bounds=bounds, elementwise_it1=el,
+           elementwise_it1_floor=el_floor)
+    assert el <= max(1.0, 3 * el_floor), (el, el_floor)
     for cp in cps:
         assert errs[cp] <= bounds[cp], (cp, errs, bounds)
 
@@ -136,6 +142,13 @@ def test_sixteen_uneven_instances_one_iteration(lib, uneven, graph):
 
 @pytest.mark.parametrize("graph", [True, False])
 def test_eight_sequences_tpp_against_stored_oracle(lib, graph):
+    """Eight sequences in one context, frame after frame: every frame's image
+    bitwise equal to the same sequence run in a context of its own, and
+    within max(1e-5, 3 x the oracle's own 1-ulp run) of the stored oracle --
+    or, for a sequence whose trajectory left the oracle's at a ReLU decision
+    taken within FP32 resolution of the kink (Adam turns the one-term gradient
+    difference into full +-lr steps), within 1e-5 of the oracle shadowing the
+    GPU's decisions iteration by iteration."""
     path = os.path.join(GOLDEN, "oracle_c3_tpp.npz")
     if not os.path.exists(path):
         pytest.skip("no stored eight-sequence oracle run")
@@ -145,28 +158,45 @@ def test_eight_sequences_tpp_against_stored_oracle(lib, graph):
     seqs = [problem(cfg["n"], cfg["rings"], cfg["levels"], cfg["base_ch"], s,
                     frames=len(iters), breathing=True) for s in cfg["seeds"]]
     print("8 sequences, TPP %s, graph=%s" % (iters, graph), flush=True)
-    ctx = lib.Context([(cfg["n"], seqs[0]["J"].shape[0])],
-                      [(0, cfg["levels"], cfg["base_ch"])] * len(seqs), precision="fp32",
-                      graph=graph)
-    ctx.set_geometry(0, seqs[0]["J"], seqs[0]["mask"])
+
+    def run(ps, gr):
+        ctx = lib.Context([(cfg["n"], ps[0]["J"].shape[0])],
+                          [(0, cfg["levels"], cfg["base_ch"])] * len(ps), precision="fp32",
+                          graph=gr)
+        ctx.set_geometry(0, ps[0]["J"], ps[0]["mask"])
+        for i, p in enumerate(ps):
+            ctx.load_problem(i, p, set_geometry=False)
+        ctx.set_adam(lr=cfg["lr"])
+        out = np.zeros((len(ps), len(iters), cfg["n"] ** 3), dtype=np.float32)
+        for f, k in enumerate(iters):
+            if f > 0:
+                for i, p in enumerate(ps):
+                    ctx.set_frame(i, p["dv"][f])     # theta carried over (TPP)
+                    ctx.reset_optimizer(i)
+            ctx.run(k)
+            for i in range(len(ps)):
+                out[i, f] = ctx.read_image(i)
+        ctx.close()
+        return out
+
+    imgs = run(seqs, graph)
     for i, p in enumerate(seqs):
-        ctx.load_problem(i, p, set_geometry=False)
-    ctx.set_adam(lr=cfg["lr"])
-    imgs = np.zeros_like(z["images"], dtype=np.float64)
-    for f, k in enumerate(iters):
-        if f > 0:
-            for i, p in enumerate(seqs):
-                ctx.set_frame(i, p["dv"][f])     # theta carried over (TPP)
-                ctx.reset_optimizer(i)
-        ctx.run(k)
-        for i in range(len(seqs)):
-            imgs[i, f] = ctx.read_image(i)
-    ctx.close()
-    errs = np.array([[rel(imgs[i, f], z["images"][i, f]) for f in range(len(iters))]
-                     for i in range(len(seqs))])
-    el = max(elementwise(imgs[i, f], z["images"][i, f], 1e-5)
-             for i in range(len(seqs)) for f in range(len(iters)))
-    record("c3_tpp_sequences", graph=graph, max_rel=float(errs.max()), elementwise=el,
-           per_sequence=errs.max(axis=1).tolist())
-    assert errs.max() < 1e-5, errs
-    assert el <= 1.0, el
+        np.testing.assert_array_equal(run([p], graph)[0], imgs[i])
+    S, F = len(seqs), len(iters)
+    ref, flo = z["images"], z["floor_images"]
+    errs = np.array([[rel(imgs[i, f], ref[i, f]) for f in range(F)] for i in range(S)])
+    floors = np.array([[rel(flo[i, f], ref[i, f]) for f in range(F)] for i in range(S)])
+    ok = errs <= np.maximum(1e-5, 3 * floors)
+    shadowed = {}
+    for i in range(S):
+        if ok[i].all():
+            continue
+        g_imgs, r_imgs, flips = shadow_sequence(lib, seqs[i], iters, cfg["lr"])
+        for f in range(F):
+            np.testing.assert_array_equal(g_imgs[f], imgs[i, f])
+        shadowed[i] = dict(flips=flips, image_rel=[rel(g_imgs[f], r_imgs[f]) for f in range(F)])
+    record("c3_tpp_sequences", graph=graph, image_rel=errs.tolist(), floors=floors.tolist(),
+           shadowed=shadowed)
+    for i, sh in shadowed.items():
+        assert sh["flips"], (i, sh)
+        assert max(sh["image_rel"]) < 1e-5, (i, sh)
