@@ -434,6 +434,64 @@ d2ip_status d2ip_op_se_backward(const float* x, const float* w1, const float* b1
                                 float* gb1, float* gw2, float* gb2, int n, int C, int H,
                                 void* workspace, size_t bytes, void* hip_stream);
 
+/* ---- routing and module operators of the network (Sec. III-D) -----------
+ * Channels-last FP32 tensors, channel counts multiples of 4, 16-byte aligned;
+ * n is the finer grid of the pair (even). */
+
+/* y [(n/2)^3][C] = the 2x2x2 average of x [n^3][C] (the encoder's down-sampling). */
+d2ip_status d2ip_op_pool2_forward(const float* x, float* y, int n, int C, void* hip_stream);
+/* gx [n^3][C] = gy[parent(v)] / 8, the adjoint of d2ip_op_pool2_forward. */
+d2ip_status d2ip_op_pool2_backward(const float* gy, float* gx, int n, int C, void* hip_stream);
+
+/* cat [n^3][Cu + Cs] = [up2(d), e]: the coarser decoder output d [(n/2)^3][Cu]
+ * interpolated to the finer grid (nearest neighbour, x2) and the encoder skip
+ * e [n^3][Cs], concatenated in that order (the decoder's fusion). */
+d2ip_status d2ip_op_up2_concat_forward(const float* d, int Cu, const float* e, int Cs, int n,
+                                       float* cat, void* hip_stream);
+/* gd [(n/2)^3][Cu] = sum over each coarse voxel's 8 children of gcat[v][0..Cu),
+ * ge [n^3][Cs] = gcat[v][Cu..Cu+Cs). */
+d2ip_status d2ip_op_up2_concat_backward(const float* gcat, int Cu, int Cs, int n, float* gd,
+                                        float* ge, void* hip_stream);
+
+/* Output head (Sec. III-D: a Conv3D layer and, for the sigmoid tail, a
+ * sigmoid): t[v] = b[0] + sum_c w[c] x[v][c] over x [n^3][C] (C a power of
+ * two in [4, 256]); out[v] = mask[v] * t[v], or with sigmoid_tail != 0
+ * mask[v] * (2 sigmoid(t[v]) - 1) (range (-1, 1)); mask may be NULL (all 1). */
+d2ip_status d2ip_op_head_bytes(int n, int C, size_t* out);
+d2ip_status d2ip_op_head_forward(const float* x, const float* w, const float* b,
+                                 const float* mask, float* out, int n, int C, int sigmoid_tail,
+                                 void* hip_stream);
+/* Gradients of the head given gout = dL/dout: gx [n^3][C], gw [C], gb [1]
+ * (each may be NULL); the voxel sums are reduced in FP64 in a fixed order. */
+d2ip_status d2ip_op_head_backward(const float* x, const float* w, const float* b,
+                                  const float* mask, const float* gout, float* gx, float* gw,
+                                  float* gb, int n, int C, int sigmoid_tail, void* workspace,
+                                  size_t bytes, void* hip_stream);
+
+/* Attention unit of a decoder stage (Sec. III-D: each up-sampling stage is
+ * an attention mechanism followed by interpolation and a ResConv3D block):
+ * x [n^3][c] is the encoder skip, g [(n/2)^3][cu] the coarser decoder output.
+ * On g's grid: xs = 2x2x2 average of x, a = wx xs + wg g + b (wx [c][c],
+ * wg [c][cu], b [c]), alpha = sigmoid(bpsi + psi . relu(a)) (psi [c],
+ * bpsi [1]); then y [n^3][c] = alpha[parent(v)] x[v] (the coefficients
+ * interpolated, nearest neighbour).  alpha [(n/2)^3] may be NULL.  c <= 64,
+ * cu <= 128. */
+d2ip_status d2ip_op_attention_bytes(int n, int c, int cu, size_t* out);
+d2ip_status d2ip_op_attention_forward(const float* x, const float* g, const float* wx,
+                                      const float* wg, const float* b, const float* psi,
+                                      const float* bpsi, float* y, float* alpha, int n, int c,
+                                      int cu, void* hip_stream);
+/* Gradients of the attention unit given gy = dL/dy: gx, gg (on g's grid) and
+ * the parameter gradients (any output may be NULL except that the parameter
+ * gradients are written together); the ReLU derivative is 0 at 0.  Sums over
+ * coarse voxels are per-block partials reduced in FP64 in block order. */
+d2ip_status d2ip_op_attention_backward(const float* x, const float* g, const float* wx,
+                                       const float* wg, const float* b, const float* psi,
+                                       const float* bpsi, const float* gy, float* gx, float* gg,
+                                       float* gwx, float* gwg, float* gb, float* gpsi,
+                                       float* gbpsi, int n, int c, int cu, void* workspace,
+                                       size_t bytes, void* hip_stream);
+
 /* p = J sigma for a dense row-major M x Q J (Eq. (1)); Q a multiple of 4. */
 d2ip_status d2ip_op_j_forward(const float* J, const float* sigma, float* p, int M, int Q,
                               void* hip_stream);

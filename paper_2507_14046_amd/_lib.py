@@ -118,6 +118,18 @@ SIGNATURES = {
                             _vp, ctypes.c_size_t, _vp],
     "d2ip_op_j_forward": [_vp, _vp, _vp, _i, _i, _vp],
     "d2ip_op_mse_loss": [_vp, _vp, _vp, _vp, _i, _vp],
+    "d2ip_op_pool2_forward": [_vp, _vp, _i, _i, _vp],
+    "d2ip_op_pool2_backward": [_vp, _vp, _i, _i, _vp],
+    "d2ip_op_up2_concat_forward": [_vp, _i, _vp, _i, _i, _vp, _vp],
+    "d2ip_op_up2_concat_backward": [_vp, _i, _i, _i, _vp, _vp, _vp],
+    "d2ip_op_head_bytes": [_i, _i, _c_size_p],
+    "d2ip_op_head_forward": [_vp, _vp, _vp, _vp, _vp, _i, _i, _i, _vp],
+    "d2ip_op_head_backward": [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _i, _i, _i, _vp,
+                              ctypes.c_size_t, _vp],
+    "d2ip_op_attention_bytes": [_i, _i, _i, _c_size_p],
+    "d2ip_op_attention_forward": [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _i, _i, _i, _vp],
+    "d2ip_op_attention_backward": [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
+                                   _vp, _vp, _vp, _i, _i, _i, _vp, ctypes.c_size_t, _vp],
     "d2ip_op_jt_bytes": [_i, _i, _c_size_p],
     "d2ip_op_jt": [_vp, _vp, _vp, _i, _i, _vp, ctypes.c_size_t, _vp],
     "d2ip_op_jt_noalloc": [_vp, _vp, _vp, _i, _i, _vp],

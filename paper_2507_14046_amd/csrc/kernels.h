@@ -135,6 +135,25 @@ void up_concat_bwd(const float* gcat, int Cu, int Cs, int n, float* gu, float* g
 void pool_bwd_add(const float* gx, const float* add, int n, int C, float* gy, int batch,
                   long long istride, hipStream_t s);
 void pad_input(const float* z, size_t V, float* zp, hipStream_t s);
+// ---- output head and attention unit (modules.hip) ---------------------------
+int head_max_c();
+size_t head_scratch_bytes(size_t V, int C);
+void head_forward(const float* x, const float* w, const float* b, const float* mask, size_t V,
+                  int C, int sig, float* out, hipStream_t s);
+void head_backward(const float* x, const float* w, const float* b, const float* mask,
+                   const float* gout, size_t V, int C, int sig, float* gx, float* gw, float* gb,
+                   void* scratch, hipStream_t s);
+int att_max_c();
+int att_max_cu();
+size_t att_scratch_bytes(int n, int c, int cu);
+void att_forward(const float* x, const float* g, const float* wx, const float* wg, const float* b,
+                 const float* psi, const float* bpsi, float* y, float* alpha, int n, int c, int cu,
+                 hipStream_t s);
+void att_backward(const float* x, const float* g, const float* wx, const float* wg,
+                  const float* b, const float* psi, const float* bpsi, const float* gy,
+                  float* gx, float* gg, float* gwx, float* gwg, float* gb, float* gpsi,
+                  float* gbpsi, int n, int c, int cu, void* scratch, hipStream_t s);
+
 // n 4-byte words at p set to zero by a kernel (a graph records a kernel node)
 void zero_words(void* p, size_t n, hipStream_t s);
 

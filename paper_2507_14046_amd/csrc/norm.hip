@@ -267,7 +267,7 @@ __global__ void k_cat_split(const float4* gcat, int C4, int Cu4, int Cs4, size_t
   }
 }
 
-// gy[v][c] = add[v][c] + gx[parent(v)][c] / 8   (fine grid n)
+// gy[v][c] = add[v][c] + gx[parent(v)][c] / 8   (fine grid n; add may be null)
 __global__ void k_pool_bwd_add(const float4* gx, const float4* add, int n, int C4, float4* gy,
                                long long istride) {
   {
@@ -282,7 +282,7 @@ __global__ void k_pool_bwd_add(const float4* gx, const float4* add, int n, int C
     const size_t v = i / C4;
     const int xx = (int)(v % n), yy = (int)((v / n) % n), zz = (int)(v / ((size_t)n * n));
     const float4 p = gx[((size_t)((zz >> 1) * m + (yy >> 1)) * m + (xx >> 1)) * C4 + c4];
-    const float4 a = add[i];
+    const float4 a = add ? add[i] : make_float4(0.f, 0.f, 0.f, 0.f);
     gy[i] = make_float4(a.x + 0.125f * p.x, a.y + 0.125f * p.y, a.z + 0.125f * p.z,
                         a.w + 0.125f * p.w);
   }

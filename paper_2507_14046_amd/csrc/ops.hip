@@ -244,6 +244,19 @@ constexpr int kNoAllocMaxDevices = 64;
 std::mutex g_scratch_mu;
 void* g_scratch_dev[kNoAllocMaxDevices] = {};
 
+d2ip_status head_check(int n, int C) {
+  if (n < 1 || n > 512) return api_fail(D2IP_EINVAL, "n must be in [1, 512]");
+  if (C < 4 || C > head_max_c() || (C & (C - 1)))
+    return api_fail(D2IP_EINVAL, "C must be a power of two in [4, 256]");
+  return D2IP_OK;
+}
+d2ip_status att_check(int n, int c, int cu) {
+  if (n < 2 || n % 2 || n > 512) return api_fail(D2IP_EINVAL, "n must be even, in [2, 512]");
+  if (c < 4 || c % 4 || c > att_max_c() || cu < 4 || cu % 4 || cu > att_max_cu())
+    return api_fail(D2IP_EINVAL, "need c % 4 == 0 <= 64 and cu % 4 == 0 <= 128");
+  return D2IP_OK;
+}
+
 // Device address of `scratch` on the current device (looked up on the first
 // call on that device).
 d2ip_status scratch_address(void** out) {
@@ -617,6 +630,133 @@ d2ip_status d2ip_op_jt(const float* J, const float* g, float* out, int M, int Q,
   if ((st = ws_check(workspace, bytes, need)) != D2IP_OK) return st;
   jt_dense(J, M, Q, g, reinterpret_cast<float*>(workspace), out,
            reinterpret_cast<hipStream_t>(hip_stream));
+  OPCHK(hipGetLastError());
+  return D2IP_OK;
+}
+
+d2ip_status d2ip_op_pool2_forward(const float* x, float* y, int n, int C, void* hip_stream) {
+  if (!x || !y) return api_fail(D2IP_EINVAL, "null x or y");
+  if (n < 2 || n % 2 || n > 512 || C < 4 || C % 4) return api_fail(D2IP_EINVAL, "need even n and C % 4 == 0");
+  if (!aligned16(x) || !aligned16(y)) return api_fail(D2IP_EINVAL, "x and y must be 16-byte aligned");
+  avgpool2(x, n, C, y, reinterpret_cast<hipStream_t>(hip_stream));
+  OPCHK(hipGetLastError());
+  return D2IP_OK;
+}
+
+d2ip_status d2ip_op_pool2_backward(const float* gy, float* gx, int n, int C, void* hip_stream) {
+  if (!gy || !gx) return api_fail(D2IP_EINVAL, "null gy or gx");
+  if (n < 2 || n % 2 || n > 512 || C < 4 || C % 4) return api_fail(D2IP_EINVAL, "need even n and C % 4 == 0");
+  if (!aligned16(gx) || !aligned16(gy)) return api_fail(D2IP_EINVAL, "gx and gy must be 16-byte aligned");
+  pool_bwd_add(gy, nullptr, n, C, gx, 1, 0, reinterpret_cast<hipStream_t>(hip_stream));
+  OPCHK(hipGetLastError());
+  return D2IP_OK;
+}
+
+d2ip_status d2ip_op_up2_concat_forward(const float* d, int Cu, const float* e, int Cs, int n,
+                                       float* cat, void* hip_stream) {
+  if (!d || !e || !cat) return api_fail(D2IP_EINVAL, "null d, e or cat");
+  if (n < 2 || n % 2 || n > 512 || Cu < 4 || Cu % 4 || Cs < 4 || Cs % 4)
+    return api_fail(D2IP_EINVAL, "need even n and channel counts multiples of 4");
+  if (!aligned16(d) || !aligned16(e) || !aligned16(cat))
+    return api_fail(D2IP_EINVAL, "tensors must be 16-byte aligned");
+  up_concat(d, Cu, e, Cs, n, cat, 1, 0, reinterpret_cast<hipStream_t>(hip_stream));
+  OPCHK(hipGetLastError());
+  return D2IP_OK;
+}
+
+d2ip_status d2ip_op_up2_concat_backward(const float* gcat, int Cu, int Cs, int n, float* gd,
+                                        float* ge, void* hip_stream) {
+  if (!gcat || !gd || !ge) return api_fail(D2IP_EINVAL, "null gcat, gd or ge");
+  if (n < 2 || n % 2 || n > 512 || Cu < 4 || Cu % 4 || Cs < 4 || Cs % 4)
+    return api_fail(D2IP_EINVAL, "need even n and channel counts multiples of 4");
+  if (!aligned16(gcat) || !aligned16(gd) || !aligned16(ge))
+    return api_fail(D2IP_EINVAL, "tensors must be 16-byte aligned");
+  up_concat_bwd(gcat, Cu, Cs, n, gd, ge, 1, 0, reinterpret_cast<hipStream_t>(hip_stream));
+  OPCHK(hipGetLastError());
+  return D2IP_OK;
+}
+
+
+d2ip_status d2ip_op_head_bytes(int n, int C, size_t* out) {
+  if (!out) return api_fail(D2IP_EINVAL, "null output");
+  d2ip_status st = head_check(n, C);
+  if (st != D2IP_OK) return st;
+  *out = head_scratch_bytes((size_t)n * n * n, C) + 256;
+  return D2IP_OK;
+}
+
+d2ip_status d2ip_op_head_forward(const float* x, const float* w, const float* b,
+                                 const float* mask, float* out, int n, int C, int sigmoid_tail,
+                                 void* hip_stream) {
+  d2ip_status st = head_check(n, C);
+  if (st != D2IP_OK) return st;
+  if (!x || !w || !b || !out) return api_fail(D2IP_EINVAL, "null x, w, b or out");
+  if (!aligned16(x) || !aligned16(w)) return api_fail(D2IP_EINVAL, "x and w must be 16-byte aligned");
+  head_forward(x, w, b, mask, (size_t)n * n * n, C, sigmoid_tail ? 1 : 0, out,
+               reinterpret_cast<hipStream_t>(hip_stream));
+  OPCHK(hipGetLastError());
+  return D2IP_OK;
+}
+
+d2ip_status d2ip_op_head_backward(const float* x, const float* w, const float* b,
+                                  const float* mask, const float* gout, float* gx, float* gw,
+                                  float* gb, int n, int C, int sigmoid_tail, void* workspace,
+                                  size_t bytes, void* hip_stream) {
+  d2ip_status st = head_check(n, C);
+  if (st != D2IP_OK) return st;
+  if (!x || !w || !b || !gout) return api_fail(D2IP_EINVAL, "null x, w, b or gout");
+  if (!aligned16(x) || !aligned16(w) || (gx && !aligned16(gx)))
+    return api_fail(D2IP_EINVAL, "x, w and gx must be 16-byte aligned");
+  size_t need = 0;
+  d2ip_op_head_bytes(n, C, &need);
+  if ((st = ws_check(workspace, bytes, need)) != D2IP_OK) return st;
+  head_backward(x, w, b, mask, gout, (size_t)n * n * n, C, sigmoid_tail ? 1 : 0, gx, gw, gb,
+                workspace, reinterpret_cast<hipStream_t>(hip_stream));
+  OPCHK(hipGetLastError());
+  return D2IP_OK;
+}
+
+d2ip_status d2ip_op_attention_bytes(int n, int c, int cu, size_t* out) {
+  if (!out) return api_fail(D2IP_EINVAL, "null output");
+  d2ip_status st = att_check(n, c, cu);
+  if (st != D2IP_OK) return st;
+  *out = att_scratch_bytes(n, c, cu) + 256;
+  return D2IP_OK;
+}
+
+d2ip_status d2ip_op_attention_forward(const float* x, const float* g, const float* wx,
+                                      const float* wg, const float* b, const float* psi,
+                                      const float* bpsi, float* y, float* alpha, int n, int c,
+                                      int cu, void* hip_stream) {
+  d2ip_status st = att_check(n, c, cu);
+  if (st != D2IP_OK) return st;
+  if (!x || !g || !wx || !wg || !b || !psi || !bpsi || !y)
+    return api_fail(D2IP_EINVAL, "null tensor");
+  if (!aligned16(x) || !aligned16(g) || !aligned16(y))
+    return api_fail(D2IP_EINVAL, "x, g and y must be 16-byte aligned");
+  att_forward(x, g, wx, wg, b, psi, bpsi, y, alpha, n, c, cu,
+              reinterpret_cast<hipStream_t>(hip_stream));
+  OPCHK(hipGetLastError());
+  return D2IP_OK;
+}
+
+d2ip_status d2ip_op_attention_backward(const float* x, const float* g, const float* wx,
+                                       const float* wg, const float* b, const float* psi,
+                                       const float* bpsi, const float* gy, float* gx, float* gg,
+                                       float* gwx, float* gwg, float* gb, float* gpsi,
+                                       float* gbpsi, int n, int c, int cu, void* workspace,
+                                       size_t bytes, void* hip_stream) {
+  d2ip_status st = att_check(n, c, cu);
+  if (st != D2IP_OK) return st;
+  if (!x || !g || !wx || !wg || !b || !psi || !bpsi || !gy)
+    return api_fail(D2IP_EINVAL, "null tensor");
+  if (!aligned16(x) || !aligned16(g) || !aligned16(gy) || (gx && !aligned16(gx)))
+    return api_fail(D2IP_EINVAL, "x, g, gy and gx must be 16-byte aligned");
+  size_t need = 0;
+  d2ip_op_attention_bytes(n, c, cu, &need);
+  if ((st = ws_check(workspace, bytes, need)) != D2IP_OK) return st;
+  att_backward(x, g, wx, wg, b, psi, bpsi, gy, gx, gg, gwx, gwg, gb, gpsi, gbpsi, n, c, cu,
+               workspace, reinterpret_cast<hipStream_t>(hip_stream));
   OPCHK(hipGetLastError());
   return D2IP_OK;
 }

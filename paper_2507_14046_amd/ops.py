@@ -387,6 +387,173 @@ def _measure_fn():
     return _J
 
 
+class Pool2Fn:
+    """y = 2x2x2 average pool of x [n^3, C] -> [(n/2)^3, C] (library kernel)."""
+
+    @staticmethod
+    def apply(x):
+        return _pool_fn().apply(x)
+
+
+class Up2ConcatFn:
+    """cat = [nearest-up x2 of d [(n/2)^3, Cu], e [n^3, Cs]] (library kernel)."""
+
+    @staticmethod
+    def apply(d, e):
+        return _upcat_fn().apply(d, e)
+
+
+class HeadFn:
+    """out [n^3] = mask * (w . x[v] + b), or mask * (2 sigmoid(.) - 1) with
+    sigmoid=True: the output head (library kernels)."""
+
+    @staticmethod
+    def apply(x, w, b, mask=None, sigmoid=False):
+        return _head_fn().apply(x, w, b, mask, sigmoid)
+
+
+class AttentionFn:
+    """Attention unit of a decoder stage (library kernels): the skip x [n^3, c]
+    gated by coefficients formed on the grid of the coarser decoder output
+    g [(n/2)^3, cu] from the pooled skip, then interpolated to x's grid."""
+
+    @staticmethod
+    def apply(x, g, wx, wg, b, psi, bpsi):
+        return _att_fn().apply(x, g, wx, wg, b, psi, bpsi)
+
+
+def _pool_fn():
+    if "pool" in _FNS:
+        return _FNS["pool"]
+    torch = _torch()
+
+    class _Pool(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, x):
+            lib = L.load()
+            x = _a16(x)
+            n, C = _grid_n(x.shape[0]), x.shape[1]
+            y = torch.empty((n // 2) ** 3, C, dtype=x.dtype, device=x.device)
+            L.check(lib.d2ip_op_pool2_forward(_p(x), _p(y), n, C, _stream(x)))
+            ctx.n = n
+            return y
+
+        @staticmethod
+        def backward(ctx, gy):
+            lib = L.load()
+            gy = _a16(gy)
+            C = gy.shape[1]
+            gx = torch.empty(ctx.n ** 3, C, dtype=gy.dtype, device=gy.device)
+            L.check(lib.d2ip_op_pool2_backward(_p(gy), _p(gx), ctx.n, C, _stream(gy)))
+            return gx
+
+    _FNS["pool"] = _Pool
+    return _Pool
+
+
+def _upcat_fn():
+    if "upcat" in _FNS:
+        return _FNS["upcat"]
+    torch = _torch()
+
+    class _UpCat(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, d, e):
+            lib = L.load()
+            d, e = _a16(d), _a16(e)
+            n, Cu, Cs = _grid_n(e.shape[0]), d.shape[1], e.shape[1]
+            cat = torch.empty(n ** 3, Cu + Cs, dtype=e.dtype, device=e.device)
+            L.check(lib.d2ip_op_up2_concat_forward(_p(d), Cu, _p(e), Cs, n, _p(cat), _stream(e)))
+            ctx.dims = (n, Cu, Cs)
+            return cat
+
+        @staticmethod
+        def backward(ctx, gcat):
+            lib = L.load()
+            n, Cu, Cs = ctx.dims
+            gcat = _a16(gcat)
+            gd = torch.empty((n // 2) ** 3, Cu, dtype=gcat.dtype, device=gcat.device)
+            ge = torch.empty(n ** 3, Cs, dtype=gcat.dtype, device=gcat.device)
+            L.check(lib.d2ip_op_up2_concat_backward(_p(gcat), Cu, Cs, n, _p(gd), _p(ge),
+                                                    _stream(gcat)))
+            return gd, ge
+
+    _FNS["upcat"] = _UpCat
+    return _UpCat
+
+
+def _head_fn():
+    if "head" in _FNS:
+        return _FNS["head"]
+    torch = _torch()
+
+    class _Head(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, x, w, b, mask, sigmoid):
+            lib = L.load()
+            wshape = w.shape
+            x, w, b = _a16(x), _a16(w.reshape(-1)), b.contiguous()
+            n, C = _grid_n(x.shape[0]), x.shape[1]
+            m = mask.contiguous() if mask is not None else None
+            out = torch.empty(n ** 3, dtype=x.dtype, device=x.device)
+            L.check(lib.d2ip_op_head_forward(_p(x), _p(w), _p(b), _p(m), _p(out), n, C,
+                                             int(bool(sigmoid)), _stream(x)))
+            ctx.save_for_backward(x, w, b, m if m is not None else torch.empty(0))
+            ctx.sigmoid, ctx.has_mask, ctx.wshape = bool(sigmoid), m is not None, wshape
+            return out
+
+        @staticmethod
+        def backward(ctx, gout):
+            lib = L.load()
+            x, w, b, m = ctx.saved_tensors
+            n, C = _grid_n(x.shape[0]), x.shape[1]
+            gx, gw, gb = torch.empty_like(x), torch.empty_like(w), torch.empty_like(b)
+            ws, nb = _workspace(lib.d2ip_op_head_bytes, n, C, device=x.device)
+            L.check(lib.d2ip_op_head_backward(
+                _p(x), _p(w), _p(b), _p(m) if ctx.has_mask else None, _p(gout.contiguous()),
+                _p(gx), _p(gw), _p(gb), n, C, int(ctx.sigmoid), _p(ws), nb, _stream(x)))
+            return gx, gw.view(ctx.wshape), gb, None, None
+
+    _FNS["head"] = _Head
+    return _Head
+
+
+def _att_fn():
+    if "att" in _FNS:
+        return _FNS["att"]
+    torch = _torch()
+
+    class _Att(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, x, g, wx, wg, b, psi, bpsi):
+            lib = L.load()
+            x, g = _a16(x), _a16(g)
+            wx, wg, b, psi, bpsi = (t.contiguous() for t in (wx, wg, b, psi, bpsi))
+            n, c, cu = _grid_n(x.shape[0]), x.shape[1], g.shape[1]
+            y = torch.empty_like(x)
+            L.check(lib.d2ip_op_attention_forward(_p(x), _p(g), _p(wx), _p(wg), _p(b), _p(psi),
+                                                  _p(bpsi), _p(y), None, n, c, cu, _stream(x)))
+            ctx.save_for_backward(x, g, wx, wg, b, psi, bpsi)
+            return y
+
+        @staticmethod
+        def backward(ctx, gy):
+            lib = L.load()
+            x, g, wx, wg, b, psi, bpsi = ctx.saved_tensors
+            n, c, cu = _grid_n(x.shape[0]), x.shape[1], g.shape[1]
+            gy = _a16(gy)
+            gx, gg = torch.empty_like(x), torch.empty_like(g)
+            grads = [torch.empty_like(t) for t in (wx, wg, b, psi, bpsi)]
+            ws, nb = _workspace(lib.d2ip_op_attention_bytes, n, c, cu, device=x.device)
+            L.check(lib.d2ip_op_attention_backward(
+                _p(x), _p(g), _p(wx), _p(wg), _p(b), _p(psi), _p(bpsi), _p(gy), _p(gx), _p(gg),
+                *[_p(t) for t in grads], n, c, cu, _p(ws), nb, _stream(x)))
+            return (gx, gg, *grads)
+
+    _FNS["att"] = _Att
+    return _Att
+
+
 class MSELossFn:
     """(1/M) sum (p - dv)^2 as a float64 scalar tensor: reduced in FP64 on the
     device by the library (the data term of Eq. (4)); gradient (2/M)(p - dv)."""
@@ -488,17 +655,6 @@ def param_shapes(levels, base_ch, sep=False, se_ratio=0, att=False, aspp=False):
     return out
 
 
-def _pool(x, n):
-    m = n // 2
-    return x.view(m, 2, m, 2, m, 2, x.shape[1]).mean(dim=(1, 3, 5)).reshape(m ** 3, x.shape[1])
-
-
-def _up(x, m):
-    c = x.shape[1]
-    v = x.view(m, 1, m, 1, m, 1, c).expand(m, 2, m, 2, m, 2, c)
-    return v.reshape(8 * m ** 3, c)
-
-
 class DIPNet:
     """sigma = mask * phi(theta | Z) built from the operators; theta is one
     flat tensor in the canonical order (gradients flow to it through views)."""
@@ -563,7 +719,7 @@ class DIPNet:
         for l in range(L):
             nl = n >> l
             if l > 0:
-                x = _pool(x, nl * 2)
+                x = Pool2Fn.apply(x)
             x = self._run_block(P, "enc%d" % l, x, nl)
             if self.se_ratio:
                 e = "enc%d" % l
@@ -576,13 +732,9 @@ class DIPNet:
             s = skips[l]
             if self.att:  # the gate on the coarse grid, then the interpolation
                 s = self._attend(P, "dec%d" % l, s, x, nl)
-            u = _up(x, nl // 2)
-            x = torch.cat([u, s], dim=1)
+            x = Up2ConcatFn.apply(x, s)
             x = self._run_block(P, "dec%d" % l, x, nl)
-        out = x @ P["head.w"].view(1, self.C).t() + P["head.b"]
-        if self.tail == "sigmoid":
-            out = 2.0 * torch.sigmoid(out) - 1.0
-        return out.view(-1) * mask
+        return HeadFn.apply(x, P["head.w"], P["head.b"], mask, self.tail == "sigmoid")
 
     def _aspp(self, P, x):
         """ASPP on the bottleneck: a 1x1x1 branch and one depthwise-separable
@@ -596,15 +748,11 @@ class DIPNet:
 
     def _attend(self, P, d, s, g, n):
         """Attention unit of a decoder stage (Sec. III-D: attention, then
-        interpolation): the skip s (n^3 grid) gated by coefficients formed on
-        the grid of the coarser decoder output g, sigmoid(psi . relu(wx
-        pool2(s) + wg g + b) + bpsi), then interpolated (nearest, x2); the two
-        1x1x1 convs run on the pointwise GEMM."""
-        torch = _torch()
-        a = PWConv3dFn.apply(_pool(s, n), P[d + ".awx"], P[d + ".ab"]) + PWConv3dFn.apply(
-            g, P[d + ".awg"], None)
-        gate = torch.sigmoid(torch.relu(a) @ P[d + ".apsi"] + P[d + ".abpsi"])
-        return s * _up(gate[:, None], n // 2)
+        interpolation) on the library's kernels: the skip s (n^3 grid) gated
+        by sigmoid(psi . relu(wx pool2(s) + wg g + b) + bpsi), formed on the
+        grid of the coarser decoder output g and interpolated (nearest, x2)."""
+        return AttentionFn.apply(s, g, P[d + ".awx"], P[d + ".awg"], P[d + ".ab"],
+                                 P[d + ".apsi"], P[d + ".abpsi"])
 
     def loss(self, theta, Z, mask, J, dv):
         """(1/M) sum (J sigma - dv)^2 (float64 scalar), with J sigma, J^T and

@@ -234,3 +234,108 @@ def test_mse_loss_operator_matches_fp64(lib, M):
     record("op_mse_loss", M=M, rel=abs(got - want) / want)
     assert abs(got - want) / want < 1e-6, (got, want)
     np.testing.assert_allclose(host(P.grad), 2.0 * r / M, rtol=1e-6, atol=1e-6 * np.abs(2 * r / M).max())
+
+
+def _cl(x):
+    return np.ascontiguousarray(x.reshape(x.shape[0], -1).T)
+
+
+def _cf(x, n):
+    return np.ascontiguousarray(np.asarray(x, dtype=np.float64).T.reshape(-1, n, n, n))
+
+
+@pytest.mark.parametrize("n,Cu,Cs", [(8, 16, 8), (6, 4, 12), (32, 32, 16)])
+def test_pool_and_up_concat_operators_match_oracle(lib, n, Cu, Cs):
+    """d2ip_op_pool2_* and d2ip_op_up2_concat_* against the oracle's
+    avgpool2 / up2 and their adjoints (FP64)."""
+    import torch
+    from paper_2507_14046_amd import ops
+    rng = np.random.default_rng(n * 100 + Cu + Cs)
+    m = n // 2
+    x = rng.standard_normal((Cs, n, n, n)).astype(np.float32)
+    d = rng.standard_normal((Cu, m, m, m)).astype(np.float32)
+    f64 = lambda a: a.astype(np.float64)
+    X, D = dev(_cl(x), True), dev(_cl(d), True)
+    Y = ops.Pool2Fn.apply(X)
+    R = rng.standard_normal((Cs, m, m, m)).astype(np.float32)
+    Y.backward(dev(_cl(R)))
+    assert rel(_cf(host(Y), m), onet.avgpool2(f64(x))) < 1e-6
+    assert rel(_cf(host(X.grad), n), onet.avgpool2_backward(f64(R))) < 1e-6
+    E = dev(_cl(x), True)
+    Cat = ops.Up2ConcatFn.apply(D, E)
+    want = np.concatenate([onet.up2(f64(d)), f64(x)], axis=0)
+    assert rel(_cf(host(Cat), n), want) == 0.0
+    G = rng.standard_normal((Cu + Cs, n, n, n)).astype(np.float32)
+    Cat.backward(dev(_cl(G)))
+    assert rel(_cf(host(D.grad), m), onet.up2_backward(f64(G[:Cu]))) < 1e-6
+    assert rel(_cf(host(E.grad), n), f64(G[Cu:])) == 0.0
+
+
+@pytest.mark.parametrize("sig", [False, True])
+@pytest.mark.parametrize("n,C", [(8, 8), (6, 16), (32, 16), (16, 256)])
+def test_head_operator_matches_oracle(lib, n, C, sig):
+    """d2ip_op_head_*: the 1x1x1 conv to one channel (linear or the sigmoid
+    tail 2 sigmoid(t) - 1), masked, and its gradients, against the oracle's
+    conv3d / conv3d_backward and the sigmoid's derivative (FP64)."""
+    import torch
+    from paper_2507_14046_amd import ops
+    rng = np.random.default_rng(7 * n + C + sig)
+    x = rng.standard_normal((C, n, n, n)).astype(np.float32)
+    w = (rng.standard_normal((1, C, 1, 1, 1)) / np.sqrt(C)).astype(np.float32)
+    b = rng.standard_normal(1).astype(np.float32)
+    mask = (rng.random(n ** 3) < 0.8).astype(np.float32)
+    R = rng.standard_normal(n ** 3).astype(np.float32)
+    f64 = lambda a: a.astype(np.float64)
+    t = onet.conv3d(f64(x), f64(w), f64(b))[0].ravel()
+    if sig:
+        sg = 1.0 / (1.0 + np.exp(-t))
+        want, gt = 2.0 * sg - 1.0, f64(R) * f64(mask) * 2.0 * sg * (1.0 - sg)
+    else:
+        want, gt = t, f64(R) * f64(mask)
+    want = want * f64(mask)
+    gxr, gwr, gbr = onet.conv3d_backward(f64(x), f64(w), gt.reshape(1, n, n, n))
+    X, W, B = dev(_cl(x), True), dev(w, True), dev(b, True)
+    out = ops.HeadFn.apply(X, W, B, dev(mask), sig)
+    out.backward(dev(R))
+    e = dict(y=rel(host(out), want), gx=rel(_cf(host(X.grad), n), gxr), gw=rel(host(W.grad), gwr),
+             gb=rel(host(B.grad), gbr))
+    record("op_head", n=n, C=C, sigmoid=sig, **e)
+    for k, v in e.items():
+        assert v < 2e-6, (k, e)
+
+
+@pytest.mark.parametrize("n,c,cu", [(8, 8, 16), (6, 4, 8), (16, 16, 32), (32, 32, 64),
+                                    (16, 64, 128)])
+def test_attention_operator_matches_oracle(lib, n, c, cu):
+    """d2ip_op_attention_*: the attention unit (gate on the coarse grid from the
+    pooled skip, interpolated) and its gradients against the oracle's
+    att_forward / att_backward (FP64); ragged last block at 6^3 (27 coarse
+    voxels) and the widest channels at 16^3."""
+    import torch
+    from paper_2507_14046_amd import ops
+    rng = np.random.default_rng(n + 10 * c + cu)
+    m = n // 2
+    x = rng.standard_normal((c, n, n, n)).astype(np.float32)
+    g = rng.standard_normal((cu, m, m, m)).astype(np.float32)
+    Q = {"att.wx": (rng.standard_normal((c, c)) / np.sqrt(c)).astype(np.float32),
+         "att.wg": (rng.standard_normal((c, cu)) / np.sqrt(cu)).astype(np.float32),
+         "att.b": (0.1 * rng.standard_normal(c)).astype(np.float32),
+         "att.psi": (rng.standard_normal(c) / np.sqrt(c)).astype(np.float32),
+         "att.bpsi": (0.1 * rng.standard_normal(1)).astype(np.float32)}
+    R = rng.standard_normal((c, n, n, n)).astype(np.float32)
+    f64 = lambda a: np.asarray(a, dtype=np.float64)
+    Q64 = {k: f64(v) for k, v in Q.items()}
+    yr, cache = onet.att_forward(f64(x), f64(g), Q64)
+    gxr, ggr, gr = onet.att_backward(f64(R), Q64, cache)
+    X, G = dev(_cl(x), True), dev(_cl(g), True)
+    P = {k: dev(v, True) for k, v in Q.items()}
+    Y = ops.AttentionFn.apply(X, G, P["att.wx"], P["att.wg"], P["att.b"], P["att.psi"],
+                             P["att.bpsi"])
+    Y.backward(dev(_cl(R)))
+    e = dict(y=rel(_cf(host(Y), n), yr), gx=rel(_cf(host(X.grad), n), gxr),
+             gg=rel(_cf(host(G.grad), m), ggr))
+    for k in Q:
+        e[k] = rel(host(P[k].grad), gr[k])
+    record("op_attention", n=n, c=c, cu=cu, **e)
+    for k, v in e.items():
+        assert v < 1e-5, (k, e)

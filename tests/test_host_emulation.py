@@ -20,7 +20,7 @@ import pytest
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 CSRC = os.path.join(ROOT, "paper_2507_14046_amd", "csrc")
 HERE = os.path.join(ROOT, "tests", "host_emulation")
-SOURCES = ["engine", "conv", "conv_f32", "conv_bf16", "conv_bf16x3", "norm", "jops", "ops", "dwconv", "pwconv", "se"]
+SOURCES = ["engine", "conv", "conv_f32", "conv_bf16", "conv_bf16x3", "norm", "jops", "ops", "dwconv", "pwconv", "se", "modules"]
 HIPCC = "/opt/rocm/bin/hipcc"
 
 
