@@ -357,6 +357,91 @@ def se_ops(d2ip, torch, shapes=((64, 64, 16), (32, 16, 4))):
     return out
 
 
+def module_ops(d2ip, torch, att_shapes=((64, 16, 32), (32, 32, 64), (64, 64, 128)),
+               head_shapes=((64, 16), (32, 16))):
+    """The attention unit, the output head (sigmoid tail), pooling and
+    up-sampling + concatenation through the op-level C-ABI (FP32,
+    channels-last, HIP events per call).  Algorithmic bytes (4 per value):
+    attention forward reads x [n^3][c] and g [(n/2)^3][cu] and writes y;
+    backward reads x, g, gy and writes gx, gg; head forward reads x [n^3][C]
+    and the mask and writes the image, backward reads x, the mask and gout and
+    writes gx; pooling reads n^3 C and writes n^3 C / 8; up + concat reads the
+    coarse d and the skip and writes the concatenation."""
+    import ctypes
+    L = d2ip._lib
+    lib = L.load()
+    P = lambda t: ctypes.c_void_p(t.data_ptr()) if t is not None else None
+    st = torch.cuda.current_stream()
+    sp = ctypes.c_void_p(st.cuda_stream)
+    g0 = torch.Generator(device="cuda").manual_seed(2509)
+    rnd = lambda *sh: torch.randn(*sh, device="cuda", generator=g0)
+
+    def timed(f, byts, label):
+        for _ in range(5):
+            L.check(f())
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        for _ in range(50):
+            f()
+        e1.record(st)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / 50
+        r = dict(ms=ms, bound="hbm", achieved=byts / (ms * 1e-3) / 1e9, peak=HBM_PEAK_GBS,
+                 unit="GB/s", bytes=byts)
+        r["frac"] = r["achieved"] / r["peak"]
+        log("  %-34s %8.4f ms  %7.0f GB/s (%.1f%% of HBM peak)"
+            % (label, ms, r["achieved"], 100 * r["frac"]))
+        return r
+
+    out = {}
+    for n, c, cu in att_shapes:
+        V, m3 = n ** 3, (n // 2) ** 3
+        x, g, gy = rnd(V, c), rnd(m3, cu), rnd(V, c)
+        wx, wg = rnd(c, c) / c ** 0.5, rnd(c, cu) / cu ** 0.5
+        b, psi, bpsi = 0.1 * rnd(c), rnd(c) / c ** 0.5, 0.1 * rnd(1)
+        y, gx, gg = torch.empty_like(x), torch.empty_like(x), torch.empty_like(g)
+        gwx, gwg, gb, gpsi, gbpsi = (torch.empty_like(t) for t in (wx, wg, b, psi, bpsi))
+        nb = ctypes.c_size_t()
+        L.check(lib.d2ip_op_attention_bytes(n, c, cu, ctypes.byref(nb)))
+        ws = torch.empty(nb.value, dtype=torch.uint8, device="cuda")
+        key = "attention %d^3 c=%d cu=%d" % (n, c, cu)
+        out[key] = dict(
+            forward=timed(lambda: lib.d2ip_op_attention_forward(
+                P(x), P(g), P(wx), P(wg), P(b), P(psi), P(bpsi), P(y), None, n, c, cu, sp),
+                4.0 * (2 * V * c + m3 * cu), key + " fwd"),
+            backward=timed(lambda: lib.d2ip_op_attention_backward(
+                P(x), P(g), P(wx), P(wg), P(b), P(psi), P(bpsi), P(gy), P(gx), P(gg), P(gwx),
+                P(gwg), P(gb), P(gpsi), P(gbpsi), n, c, cu, P(ws), nb.value, sp),
+                4.0 * (3 * V * c + 2 * m3 * cu), key + " bwd"))
+    for n, C in head_shapes:
+        V = n ** 3
+        x, w, b = rnd(V, C), rnd(C) / C ** 0.5, rnd(1)
+        mask = (rnd(V) > -1.0).float()
+        o, go, gx = torch.empty(V, device="cuda"), rnd(V), torch.empty_like(x)
+        gw, gb = torch.empty_like(w), torch.empty_like(b)
+        nb = ctypes.c_size_t()
+        L.check(lib.d2ip_op_head_bytes(n, C, ctypes.byref(nb)))
+        ws = torch.empty(nb.value, dtype=torch.uint8, device="cuda")
+        key = "head (sigmoid) %d^3 C=%d" % (n, C)
+        out[key] = dict(
+            forward=timed(lambda: lib.d2ip_op_head_forward(P(x), P(w), P(b), P(mask), P(o), n, C,
+                                                           1, sp),
+                          4.0 * V * (C + 2), key + " fwd"),
+            backward=timed(lambda: lib.d2ip_op_head_backward(
+                P(x), P(w), P(b), P(mask), P(go), P(gx), P(gw), P(gb), n, C, 1, P(ws), nb.value,
+                sp), 4.0 * V * (2 * C + 2), key + " bwd"))
+    n, C = 64, 32
+    V = n ** 3
+    x, d = rnd(V, C), rnd(V // 8, 2 * C)
+    y, cat = torch.empty(V // 8, C, device="cuda"), torch.empty(V, 3 * C, device="cuda")
+    out["pool2 64^3 C=32"] = timed(lambda: lib.d2ip_op_pool2_forward(P(x), P(y), n, C, sp),
+                                   4.0 * V * C * 9 / 8, "pool2 64^3 C=32")
+    out["up2+concat 64^3 32+32"] = timed(
+        lambda: lib.d2ip_op_up2_concat_forward(P(d), 2 * C, P(x), C, n, P(cat), sp),
+        4.0 * (V // 8 * 2 * C + V * C + V * 3 * C), "up2+concat 64^3 (2C from 32^3) + C")
+    return out
+
+
 def dwsep_network(d2ip, torch, ts, names=("c1", "c2"), reps=10):
     """One loss + theta-gradient evaluation of the autograd network
     (`ops.DIPNet`, every operator on the library's kernels) with dense and
@@ -698,7 +783,8 @@ def run_section(name, a):
                 log("%s %-10s %s (%.0f s)" % (name, key, json.dumps(out[key]), time.time() - t0))
         at.set_tuning([])
     elif name == "ops":
-        out = dict(dwsep=dwsep_ops(d2ip, torch), se=se_ops(d2ip, torch))
+        out = dict(dwsep=dwsep_ops(d2ip, torch), se=se_ops(d2ip, torch),
+                   modules=module_ops(d2ip, torch))
     elif name == "network":
         out = dwsep_network(d2ip, torch, ts)
     elif name == "kernels64":

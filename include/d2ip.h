@@ -453,6 +453,22 @@ d2ip_status d2ip_op_up2_concat_forward(const float* d, int Cu, const float* e, i
 d2ip_status d2ip_op_up2_concat_backward(const float* gcat, int Cu, int Cs, int n, float* gd,
                                         float* ge, void* hip_stream);
 
+/* Channel range copy between channels-last tensors of `voxels` rows:
+ * dst[v][dst_off + j] = src[v][src_off + j] for j < ch; src has src_ch
+ * channels per voxel, dst dst_ch.  All counts and offsets multiples of 4,
+ * both tensors 16-byte aligned and not overlapping (D2IP_EINVAL otherwise).
+ * The ASPP module (Sec. III-D: parallel atrous branches fused into one
+ * tensor) concatenates its branches with one call per branch and splits the
+ * gradient back out the same way. */
+d2ip_status d2ip_op_channel_copy(const float* src, int src_ch, int src_off, float* dst, int dst_ch,
+                                 int dst_off, int ch, size_t voxels, void* hip_stream);
+
+/* y = max(x, 0) over count values (count % 4 == 0; y may equal x), and its
+ * gradient gx = gy where y > 0, else 0 (gx may equal gy). */
+d2ip_status d2ip_op_relu_forward(const float* x, float* y, size_t count, void* hip_stream);
+d2ip_status d2ip_op_relu_backward(const float* y, const float* gy, float* gx, size_t count,
+                                  void* hip_stream);
+
 /* Output head (Sec. III-D: a Conv3D layer and, for the sigmoid tail, a
  * sigmoid): t[v] = b[0] + sum_c w[c] x[v][c] over x [n^3][C] (C a power of
  * two in [4, 256]); out[v] = mask[v] * t[v], or with sigmoid_tail != 0
@@ -474,8 +490,9 @@ d2ip_status d2ip_op_head_backward(const float* x, const float* w, const float* b
  * On g's grid: xs = 2x2x2 average of x, a = wx xs + wg g + b (wx [c][c],
  * wg [c][cu], b [c]), alpha = sigmoid(bpsi + psi . relu(a)) (psi [c],
  * bpsi [1]); then y [n^3][c] = alpha[parent(v)] x[v] (the coefficients
- * interpolated, nearest neighbour).  alpha [(n/2)^3] may be NULL.  c <= 64,
- * cu <= 128. */
+ * interpolated, nearest neighbour).  alpha [(n/2)^3] may be NULL.  c and cu
+ * multiples of 4, c <= 64, cu <= 128; x, g, y (gy, gx), wx and wg 16-byte
+ * aligned. */
 d2ip_status d2ip_op_attention_bytes(int n, int c, int cu, size_t* out);
 d2ip_status d2ip_op_attention_forward(const float* x, const float* g, const float* wx,
                                       const float* wg, const float* b, const float* psi,

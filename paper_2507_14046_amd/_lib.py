@@ -122,6 +122,9 @@ SIGNATURES = {
     "d2ip_op_pool2_backward": [_vp, _vp, _i, _i, _vp],
     "d2ip_op_up2_concat_forward": [_vp, _i, _vp, _i, _i, _vp, _vp],
     "d2ip_op_up2_concat_backward": [_vp, _i, _i, _i, _vp, _vp, _vp],
+    "d2ip_op_channel_copy": [_vp, _i, _i, _vp, _i, _i, _i, ctypes.c_size_t, _vp],
+    "d2ip_op_relu_forward": [_vp, _vp, ctypes.c_size_t, _vp],
+    "d2ip_op_relu_backward": [_vp, _vp, _vp, ctypes.c_size_t, _vp],
     "d2ip_op_head_bytes": [_i, _i, _c_size_p],
     "d2ip_op_head_forward": [_vp, _vp, _vp, _vp, _vp, _i, _i, _i, _vp],
     "d2ip_op_head_backward": [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _i, _i, _i, _vp,

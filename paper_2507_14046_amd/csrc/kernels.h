@@ -143,6 +143,12 @@ void head_forward(const float* x, const float* w, const float* b, const float* m
 void head_backward(const float* x, const float* w, const float* b, const float* mask,
                    const float* gout, size_t V, int C, int sig, float* gx, float* gw, float* gb,
                    void* scratch, hipStream_t s);
+// Channel range copy between channels-last tensors (counts and offsets
+// multiples of 4) and ReLU forward / backward on count values (count % 4 == 0).
+void channel_copy(const float* src, int sC, int soff, float* dst, int dC, int doff, int c,
+                  size_t V, hipStream_t s);
+void relu_forward(const float* x, float* y, size_t count, hipStream_t s);
+void relu_backward(const float* y, const float* gy, float* gx, size_t count, hipStream_t s);
 int att_max_c();
 int att_max_cu();
 size_t att_scratch_bytes(int n, int c, int cu);

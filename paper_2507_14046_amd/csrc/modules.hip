@@ -12,11 +12,16 @@
 //   a[u][k] = b[k] + sum_j wx[k][j] xs[u][j] + sum_j wg[k][j] g[u][j],
 //   alpha[u] = sigmoid(bpsi + sum_k psi[k] relu(a[u][k])),
 //   y[v] = alpha[parent(v)] x[v].
-// A block takes kAttU coarse voxels: their pooled skip and gating rows and
-// the pre-activations a go through LDS, the per-voxel sums run in fixed
-// order.  The backward recomputes a and alpha, writes gx and gg and one
-// partial of every parameter gradient per block, reduced in FP64 in block
-// order by a second kernel (deterministic).
+// Both products with weights (the pre-activations a = [xs, g] W^T and, in
+// the backward, the weight gradient and the gradients of xs and g) run on the
+// matrix cores; the children's x and gy quads stay in registers from the
+// pooling to the output, so each tensor crosses HBM once.  Parameter
+// gradients are accumulated per block and reduced in FP64 in a fixed order
+// (deterministic).
+//
+// Channel slices and ReLU: the ASPP's concatenation of its branches (each
+// branch copied into its channel range of the concatenated tensor, and the
+// gradient's ranges copied back out) and its output activation.
 #include <algorithm>
 
 #include "kernels.h"
@@ -52,10 +57,72 @@ __global__ __launch_bounds__(256) void k_head_fwd(const float* __restrict__ x,
   }
 }
 
-// gt = gout * mask * dout/dt; gx[v][c] = gt w[c]; one partial per block of
-// (sum_v gt x[v][c], sum_v gt) over the block's voxels, reduced across the
-// block's threads in a fixed order.
+// ---- fixed-order column sums ----------------------------------------------
+
+// Stage 1 of out[i] = sum_k part[k][i] (k < nrows, i < ncols): slice s of the
+// rows (contiguous, S slices) is summed per column in FP64 by four row lanes
+// (rows r0 + l, r0 + l + 4, ...) whose sums are then added in lane order.
+// Grid (ceil(ncols / 64), S), 256 threads.
+template <class T>
+__global__ __launch_bounds__(256) void k_colsum1(const T* __restrict__ part, int nrows, int ncols,
+                                                 double* __restrict__ tmp) {
+  __shared__ double red[4][64];
+  const int cl = threadIdx.x & 63, ln = threadIdx.x >> 6;
+  const int col = blockIdx.x * 64 + cl;
+  const int S = gridDim.y, sl = blockIdx.y;
+  const int r0 = (int)((long long)nrows * sl / S), r1 = (int)((long long)nrows * (sl + 1) / S);
+  double acc = 0.0;
+  if (col < ncols)
+    for (int k = r0 + ln; k < r1; k += 4) acc += (double)part[(size_t)k * ncols + col];
+  red[ln][cl] = acc;
+  __syncthreads();
+  if (ln == 0 && col < ncols)
+    tmp[(size_t)sl * ncols + col] = ((red[0][cl] + red[1][cl]) + red[2][cl]) + red[3][cl];
+}
+
+// Output tensors of a column sum: column i lands in dst[j][i - start[j]] for
+// start[j] <= i < start[j + 1] (a null dst[j] drops its columns).
+struct ColOut {
+  float* dst[5];
+  int start[6];
+  int nseg;
+};
+
+// Stage 2: the S slice sums of every column added in slice order.
+__global__ __launch_bounds__(256) void k_colsum2(const double* __restrict__ tmp, int S, int ncols,
+                                                 ColOut o) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= ncols) return;
+  double s = 0.0;
+  for (int k = 0; k < S; ++k) s += tmp[(size_t)k * ncols + i];
+  for (int j = 0; j < o.nseg; ++j)
+    if (i >= o.start[j] && i < o.start[j + 1]) {
+      if (o.dst[j]) o.dst[j][i - o.start[j]] = (float)s;
+      break;
+    }
+}
+
+constexpr int kColSlices = 32;
+
+int colsum_slices(int nrows) { return nrows < kColSlices ? nrows : kColSlices; }
+
+template <class T>
+void colsum(const T* part, int nrows, int ncols, double* tmp, const ColOut& o, hipStream_t s) {
+  const int S = colsum_slices(nrows);
+  hipLaunchKernelGGL(k_colsum1<T>, dim3((ncols + 63) / 64, S), dim3(256), 0, s, part, nrows,
+                     ncols, tmp);
+  hipLaunchKernelGGL(k_colsum2, dim3((ncols + 255) / 256), dim3(256), 0, s, tmp, S, ncols, o);
+}
+
+// ---- head backward ----------------------------------------------------------
+
+// gt[v] = gout[v] mask[v] dout/dt; gx[v][c] = gt w[c]; one FP64 partial per
+// block of (sum_v gt x[v][c], sum_v gt).  A block walks chunks of 256 voxels
+// (chunk k, k + gridDim, ...): each thread forms one voxel's gt into LDS, then
+// thread (q, r) takes channel quad q of voxels r, r + R, ... (R = 256 / (C/4)),
+// coalesced rows; the R row lanes are added in lane order at the end.
 constexpr int kHeadMaxC = 256;
+constexpr int kHeadChunk = 256;
 __global__ __launch_bounds__(256) void k_head_bwd(const float* __restrict__ x,
                                                   const float* __restrict__ w,
                                                   const float* __restrict__ b,
@@ -63,164 +130,208 @@ __global__ __launch_bounds__(256) void k_head_bwd(const float* __restrict__ x,
                                                   const float* __restrict__ gout, size_t V, int C,
                                                   int sig, float* __restrict__ gx,
                                                   double* __restrict__ part) {
-  __shared__ float red[256][5];
+  __shared__ float gts[kHeadChunk];
+  __shared__ double red[256][5];
   const int C4 = C / 4;
-  // thread t accumulates channel quad (t % C4) over the voxels v = v0 + r,
-  // r = t / C4, t / C4 + R, ...  (R = 256 / C4 voxel lanes)
   const int R = 256 / C4, q = threadIdx.x % C4, r = threadIdx.x / C4;
-  const size_t per = (V + gridDim.x - 1) / gridDim.x;
-  const size_t v0 = blockIdx.x * per, v1 = min(V, v0 + per);
-  float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
-  float accb = 0.f;
   const float4 wq = reinterpret_cast<const float4*>(w)[q];
-  if (r < R) {
-    for (size_t v = v0 + r; v < v1; v += R) {
+  double acc[4] = {0.0, 0.0, 0.0, 0.0}, accb = 0.0;
+  for (size_t c0 = (size_t)blockIdx.x * kHeadChunk; c0 < V; c0 += (size_t)gridDim.x * kHeadChunk) {
+    const int nv = (int)min((size_t)kHeadChunk, V - c0);
+    if ((int)threadIdx.x < nv) {
+      const size_t v = c0 + threadIdx.x;
       float gt = gout[v];
       if (mask) gt *= mask[v];
       if (sig) {
-        const float s = 1.f / (1.f + expf(-head_t(x, w, b[0], C, v)));
-        gt *= 2.f * s * (1.f - s);
+        const float sg = 1.f / (1.f + expf(-head_t(x, w, b[0], C, v)));
+        gt *= 2.f * sg * (1.f - sg);
       }
+      gts[threadIdx.x] = gt;
+    }
+    __syncthreads();
+    float4 a = make_float4(0.f, 0.f, 0.f, 0.f);
+    float ab = 0.f;
+    for (int rr = r; rr < nv; rr += R) {
+      const size_t v = c0 + rr;
+      const float gt = gts[rr];
       const float4 xv = reinterpret_cast<const float4*>(x + v * C)[q];
-      acc.x += gt * xv.x;
-      acc.y += gt * xv.y;
-      acc.z += gt * xv.z;
-      acc.w += gt * xv.w;
-      if (q == 0) accb += gt;
+      a.x += gt * xv.x;
+      a.y += gt * xv.y;
+      a.z += gt * xv.z;
+      a.w += gt * xv.w;
+      ab += gt;
       if (gx)
         reinterpret_cast<float4*>(gx + v * C)[q] =
             make_float4(gt * wq.x, gt * wq.y, gt * wq.z, gt * wq.w);
     }
+    acc[0] += a.x;
+    acc[1] += a.y;
+    acc[2] += a.z;
+    acc[3] += a.w;
+    accb += ab;
+    __syncthreads();  // gts is refilled by the next chunk
   }
-  red[threadIdx.x][0] = acc.x;
-  red[threadIdx.x][1] = acc.y;
-  red[threadIdx.x][2] = acc.z;
-  red[threadIdx.x][3] = acc.w;
+  for (int e = 0; e < 4; ++e) red[threadIdx.x][e] = acc[e];
   red[threadIdx.x][4] = accb;
   __syncthreads();
-  if (threadIdx.x < C4) {
-    double s[4] = {0.0, 0.0, 0.0, 0.0};
-    double sb = 0.0;
+  if ((int)threadIdx.x < C4) {
+    double sm[4] = {0.0, 0.0, 0.0, 0.0}, sb = 0.0;
     for (int rr = 0; rr < R; ++rr) {
       const int t = rr * C4 + threadIdx.x;
-      for (int e = 0; e < 4; ++e) s[e] += red[t][e];
-      if (threadIdx.x == 0) sb += red[t][4];
+      for (int e = 0; e < 4; ++e) sm[e] += red[t][e];
+      sb += red[t][4];
     }
     double* p = part + (size_t)blockIdx.x * (C + 1);
-    for (int e = 0; e < 4; ++e) p[4 * threadIdx.x + e] = s[e];
+    for (int e = 0; e < 4; ++e) p[4 * threadIdx.x + e] = sm[e];
     if (threadIdx.x == 0) p[C] = sb;
   }
 }
 
-// out[i] = sum over blocks k of part[k][i] (fixed order), i < n
-__global__ void k_part_sum(const double* __restrict__ part, int nblocks, int n,
-                           float* __restrict__ out0, int n0, float* __restrict__ out1) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  double s = 0.0;
-  for (int k = 0; k < nblocks; ++k) s += part[(size_t)k * n + i];
-  if (i < n0) {
-    if (out0) out0[i] = (float)s;
-  } else if (out1) {
-    out1[i - n0] = (float)s;
-  }
-}
-
 // ---- attention unit ---------------------------------------------------------
+//
+// A tile is kAttU = 64 coarse voxels (four row tiles of 16, one per wave).
+// Z [u][0, c) holds the pooled skip rows, Z [u][c, c + cu) the gating rows
+// (LDS, zero past the tile's voxels and past K = c + cu up to K16, the next
+// multiple of 16).  W [k][j] = [wx[k][:], wg[k][:]] is read from global
+// memory (L1/L2-resident).  The matrix-core step is v_mfma_f32_16x16x4f32:
+// lane l = l16 + 16 g supplies A[row l16][slot g] and B[slot g][col l16] and
+// receives D[row 4 g + i][col l16] in register i.
 
-constexpr int kAttU = 32;      // coarse voxels per block
+constexpr int kAttU = 64;
 constexpr int kAttMaxC = 64;   // skip channels
 constexpr int kAttMaxCu = 128; // gating channels
+constexpr int kAttMaxK = kAttMaxC + kAttMaxCu;
+constexpr int kAttZp = kAttMaxK + 4;  // LDS row stride of Z (floats)
+constexpr int kAttAp = kAttMaxC + 4;  // LDS row stride of a, ga
+constexpr int kAttPp = kAttMaxC / 4 + 1;
 
 struct AttArgs {
   const float *x, *g, *wx, *wg, *b, *psi, *bpsi;
   int n, c, cu;
 };
 
-// Stage the block's pooled skip rows xs[u][c], gating rows gg[u][cu] and
-// pre-activations a[u][c]; returns the block's coarse voxel count.
-__device__ int att_stage(const AttArgs& A, int u0, float* xs, float* gs, float* as) {
-  const int m = A.n / 2;
-  const int mc = m * m * m;
-  const int nu = min(kAttU, mc - u0);
-  const int c4 = A.c / 4, cu4 = A.cu / 4;
-  for (int i = threadIdx.x; i < nu * c4; i += blockDim.x) {
-    const int u = i / c4, q = i - u * c4;
-    const int cu_ = u0 + u;
-    const int xx = cu_ % m, yy = (cu_ / m) % m, zz = cu_ / (m * m);
-    float4 s = make_float4(0.f, 0.f, 0.f, 0.f);
-#pragma unroll
-    for (int k = 0; k < 8; ++k) {
-      const int fz = 2 * zz + (k >> 2), fy = 2 * yy + ((k >> 1) & 1), fx = 2 * xx + (k & 1);
-      const float4 v =
-          reinterpret_cast<const float4*>(A.x + ((size_t)(fz * A.n + fy) * A.n + fx) * A.c)[q];
-      s.x += v.x;
-      s.y += v.y;
-      s.z += v.z;
-      s.w += v.w;
-    }
-    float* d = xs + u * A.c + 4 * q;
-    d[0] = 0.125f * s.x;
-    d[1] = 0.125f * s.y;
-    d[2] = 0.125f * s.z;
-    d[3] = 0.125f * s.w;
-  }
-  for (int i = threadIdx.x; i < nu * cu4; i += blockDim.x) {
-    const int u = i / cu4, q = i - u * cu4;
-    const float4 v = reinterpret_cast<const float4*>(A.g + (size_t)(u0 + u) * A.cu)[q];
-    float* d = gs + u * A.cu + 4 * q;
-    d[0] = v.x;
-    d[1] = v.y;
-    d[2] = v.z;
-    d[3] = v.w;
-  }
-  __syncthreads();
-  for (int i = threadIdx.x; i < nu * A.c; i += blockDim.x) {
-    const int u = i / A.c, k = i - u * A.c;
-    float t = A.b[k];
-    const float* wr = A.wx + (size_t)k * A.c;
-    const float* xr = xs + u * A.c;
-    for (int j = 0; j < A.c; ++j) t += wr[j] * xr[j];
-    const float* gr = A.wg + (size_t)k * A.cu;
-    const float* gsr = gs + u * A.cu;
-    for (int j = 0; j < A.cu; ++j) t += gr[j] * gsr[j];
-    as[u * A.c + k] = t;
-  }
-  __syncthreads();
-  return nu;
+__device__ __forceinline__ f32x4 mfma4(float a, float b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
-__device__ __forceinline__ float att_alpha(const AttArgs& A, const float* as, int u) {
+__device__ __forceinline__ float comp4(const float4& v, int s) {
+  return s == 0 ? v.x : s == 1 ? v.y : s == 2 ? v.z : v.w;
+}
+
+// Offset (floats) of child ch (0..7, bits z y x) of coarse voxel uc.
+__device__ __forceinline__ size_t att_child(const AttArgs& A, int uc, int ch) {
+  const int m = A.n / 2;
+  const int xx = uc % m, yy = (uc / m) % m, zz = uc / (m * m);
+  const int fz = 2 * zz + (ch >> 2), fy = 2 * yy + ((ch >> 1) & 1), fx = 2 * xx + (ch & 1);
+  return ((size_t)(fz * A.n + fy) * A.n + fx) * A.c;
+}
+
+// W [k][j0 .. j0 + 3] (j0 % 4 == 0), zero outside k < c, j < K.
+__device__ __forceinline__ float4 att_w4(const AttArgs& A, int k, int j0) {
+  if (k >= A.c || j0 >= A.c + A.cu) return make_float4(0.f, 0.f, 0.f, 0.f);
+  return j0 < A.c ? *reinterpret_cast<const float4*>(A.wx + (size_t)k * A.c + j0)
+                  : *reinterpret_cast<const float4*>(A.wg + (size_t)k * A.cu + (j0 - A.c));
+}
+
+// W [k][j], zero outside.
+__device__ __forceinline__ float att_w(const AttArgs& A, int k, int j) {
+  if (k >= A.c || j >= A.c + A.cu) return 0.f;
+  return j < A.c ? A.wx[(size_t)k * A.c + j] : A.wg[(size_t)k * A.cu + (j - A.c)];
+}
+
+// Gating rows (and zero padding) of the tile into Z [u][c, K16).
+__device__ __forceinline__ void att_stage_g(const AttArgs& A, int u0, int nu, int K16, float* Z) {
+  const int w4 = (K16 - A.c) / 4;
+  for (int it = threadIdx.x; it < kAttU * w4; it += blockDim.x) {
+    const int u = it / w4, j0 = A.c + 4 * (it - u * w4);
+    float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (u < nu && j0 < A.c + A.cu)
+      v = *reinterpret_cast<const float4*>(A.g + (size_t)(u0 + u) * A.cu + (j0 - A.c));
+    *reinterpret_cast<float4*>(Z + u * kAttZp + j0) = v;
+  }
+}
+
+// a [u][k] = b[k] + sum_j Z[u][j] W[k][j] into As (k < c): wave w takes rows
+// 16 w .. 16 w + 15 of the tile and every column tile.
+__device__ __forceinline__ void att_preact(const AttArgs& A, int K16, const float* Z, float* As) {
+  const int lane = threadIdx.x & 63, l16 = lane & 15, g = lane >> 4;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  for (int nt = 0; nt * 16 < A.c; ++nt) {
+    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+    for (int k16 = 0; k16 < K16; k16 += 16) {
+      const float4 a = *reinterpret_cast<const float4*>(Z + (16 * wave + l16) * kAttZp + k16 + 4 * g);
+      const float4 bw = att_w4(A, 16 * nt + l16, k16 + 4 * g);
+#pragma unroll
+      for (int s = 0; s < 4; ++s) acc = mfma4(comp4(a, s), comp4(bw, s), acc);
+    }
+    const int k = 16 * nt + l16;
+    if (k < A.c) {
+      const float bk = A.b[k];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) As[(16 * wave + 4 * g + i) * kAttAp + k] = acc[i] + bk;
+    }
+  }
+}
+
+__device__ __forceinline__ float att_alpha_of(const AttArgs& A, const float* As, int u) {
   float s = A.bpsi[0];
-  const float* ar = as + u * A.c;
+  const float* ar = As + u * kAttAp;
   for (int k = 0; k < A.c; ++k) s += A.psi[k] * fmaxf(ar[k], 0.f);
   return 1.f / (1.f + expf(-s));
 }
 
-__global__ __launch_bounds__(256) void k_att_fwd(AttArgs A, float* __restrict__ y,
+// Forward.  ITEMS = ceil(c / 16): a thread owns items it = tid + 256 i
+// (coarse voxel u = it / (c/4), channel quad q), whose eight children's x
+// quads it keeps in registers from the pooling to the output.
+template <int ITEMS>
+__global__ __launch_bounds__(256) void k_att_fwd(AttArgs A, int ntiles, float* __restrict__ y,
                                                  float* __restrict__ alpha) {
-  __shared__ float xs[kAttU * kAttMaxC];
-  __shared__ float gs[kAttU * kAttMaxCu];
-  __shared__ float as[kAttU * kAttMaxC];
+  __shared__ __align__(16) float Z[kAttU * kAttZp];
+  __shared__ float As[kAttU * kAttAp];
   __shared__ float al[kAttU];
-  const int m = A.n / 2;
-  const int u0 = blockIdx.x * kAttU;
-  const int nu = att_stage(A, u0, xs, gs, as);
-  if (threadIdx.x < nu) {
-    al[threadIdx.x] = att_alpha(A, as, threadIdx.x);
-    if (alpha) alpha[u0 + threadIdx.x] = al[threadIdx.x];
-  }
-  __syncthreads();
-  const int c4 = A.c / 4;
-  for (int i = threadIdx.x; i < nu * 8 * c4; i += blockDim.x) {
-    const int q = i % c4, ch = (i / c4) & 7, u = i / (8 * c4);
-    const int cu_ = u0 + u;
-    const int xx = cu_ % m, yy = (cu_ / m) % m, zz = cu_ / (m * m);
-    const int fz = 2 * zz + (ch >> 2), fy = 2 * yy + ((ch >> 1) & 1), fx = 2 * xx + (ch & 1);
-    const size_t o = ((size_t)(fz * A.n + fy) * A.n + fx) * A.c;
-    const float4 v = reinterpret_cast<const float4*>(A.x + o)[q];
-    const float a = al[u];
-    reinterpret_cast<float4*>(y + o)[q] = make_float4(a * v.x, a * v.y, a * v.z, a * v.w);
+  const int c4 = A.c / 4, K16 = (A.c + A.cu + 15) & ~15;
+  const int m = A.n / 2, mc = m * m * m;
+  for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const int u0 = tile * kAttU, nu = min(kAttU, mc - u0);
+    float4 xr[ITEMS][8];
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) {
+      const int it = threadIdx.x + 256 * i, u = it / c4, q = it - u * c4;
+      if (it >= kAttU * c4) continue;
+      float4 sm = make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+      for (int ch = 0; ch < 8; ++ch) {
+        xr[i][ch] = u < nu ? reinterpret_cast<const float4*>(A.x + att_child(A, u0 + u, ch))[q]
+                           : make_float4(0.f, 0.f, 0.f, 0.f);
+        sm.x += xr[i][ch].x;
+        sm.y += xr[i][ch].y;
+        sm.z += xr[i][ch].z;
+        sm.w += xr[i][ch].w;
+      }
+      *reinterpret_cast<float4*>(Z + u * kAttZp + 4 * q) =
+          make_float4(0.125f * sm.x, 0.125f * sm.y, 0.125f * sm.z, 0.125f * sm.w);
+    }
+    att_stage_g(A, u0, nu, K16, Z);
+    __syncthreads();
+    att_preact(A, K16, Z, As);
+    __syncthreads();
+    if ((int)threadIdx.x < nu) {
+      const float a = att_alpha_of(A, As, threadIdx.x);
+      al[threadIdx.x] = a;
+      if (alpha) alpha[u0 + threadIdx.x] = a;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) {
+      const int it = threadIdx.x + 256 * i, u = it / c4, q = it - u * c4;
+      if (it >= kAttU * c4 || u >= nu) continue;
+      const float a = al[u];
+#pragma unroll
+      for (int ch = 0; ch < 8; ++ch)
+        reinterpret_cast<float4*>(y + att_child(A, u0 + u, ch))[q] =
+            make_float4(a * xr[i][ch].x, a * xr[i][ch].y, a * xr[i][ch].z, a * xr[i][ch].w);
+    }
+    __syncthreads();  // Z, As and al are refilled by the next tile
   }
 }
 
@@ -228,143 +339,235 @@ __global__ __launch_bounds__(256) void k_att_fwd(AttArgs A, float* __restrict__ 
 // psi [c], bpsi [1].
 __host__ __device__ inline int att_nparams(int c, int cu) { return c * c + c * cu + 2 * c + 1; }
 
-__global__ __launch_bounds__(256) void k_att_bwd(AttArgs A, const float* __restrict__ gy,
+// Backward of a block's tiles (tile k, k + gridDim, ...): the same items as
+// the forward keep the children's gy quads in registers; dL/dalpha[u] is the
+// sum of gy x over the children, added per quad and then over the quads in
+// order.  ga [u][k] = psi[k] gt[u] where a > 0; the weight gradient
+// gW [k][j] += sum_u ga[u][k] Z[u][j] accumulates over the block's tiles in
+// the matrix-core registers (wave w: column tiles w, w + 4, w + 8); the
+// pooled and gating gradients gZ [u][j] = sum_k ga[u][k] W[k][j] (wave w:
+// rows 16 w ..) give gg directly and gx = alpha gy + gZ[u][j] / 8.
+template <int ITEMS>
+__global__ __launch_bounds__(256) void k_att_bwd(AttArgs A, int ntiles, const float* __restrict__ gy,
                                                  float* __restrict__ gx, float* __restrict__ gg,
                                                  float* __restrict__ part) {
-  __shared__ float xs[kAttU * kAttMaxC];
-  __shared__ float gs[kAttU * kAttMaxCu];
-  __shared__ float as[kAttU * kAttMaxC];   // a, then ga = dL/da
+  __shared__ __align__(16) float Z[kAttU * kAttZp];  // Z, then gZ [u][0, c) / 8
+  __shared__ __align__(16) float As[kAttU * kAttAp]; // a, then ga
+  __shared__ float Pd[kAttU * kAttPp];               // per-quad dots gy . x
   __shared__ float al[kAttU], gt[kAttU];
-  const int m = A.n / 2;
-  const int u0 = blockIdx.x * kAttU;
-  const int nu = att_stage(A, u0, xs, gs, as);
-  const int c = A.c, cu = A.cu, c4 = c / 4;
-  // dL/dalpha[u] = sum over the 8 children and channels of gy * x (fixed order)
-  if (threadIdx.x < nu) {
-    const int u = threadIdx.x;
-    const float a = att_alpha(A, as, u);
-    const int cu_ = u0 + u;
-    const int xx = cu_ % m, yy = (cu_ / m) % m, zz = cu_ / (m * m);
-    float s = 0.f;
-    for (int ch = 0; ch < 8; ++ch) {
-      const int fz = 2 * zz + (ch >> 2), fy = 2 * yy + ((ch >> 1) & 1), fx = 2 * xx + (ch & 1);
-      const size_t o = ((size_t)(fz * A.n + fy) * A.n + fx) * c;
-      for (int q = 0; q < c4; ++q) {
-        const float4 gv = reinterpret_cast<const float4*>(gy + o)[q];
-        const float4 xv = reinterpret_cast<const float4*>(A.x + o)[q];
-        s += gv.x * xv.x + gv.y * xv.y + gv.z * xv.z + gv.w * xv.w;
+  const int c = A.c, c4 = c / 4, K = c + A.cu, K16 = (K + 15) & ~15;
+  const int m = A.n / 2, mc = m * m * m;
+  const int lane = threadIdx.x & 63, l16 = lane & 15, g = lane >> 4;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int MT = (c + 15) / 16;  // row tiles of gW (k)
+  f32x4 gw[4][3];
+#pragma unroll
+  for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+    for (int t = 0; t < 3; ++t) gw[mt][t] = f32x4{0.f, 0.f, 0.f, 0.f};
+  float acc_psi = 0.f, acc_b = 0.f, acc_bpsi = 0.f;
+  for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const int u0 = tile * kAttU, nu = min(kAttU, mc - u0);
+    float4 gr[ITEMS][8];
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) {
+      const int it = threadIdx.x + 256 * i, u = it / c4, q = it - u * c4;
+      if (it >= kAttU * c4) continue;
+      float4 sm = make_float4(0.f, 0.f, 0.f, 0.f);
+      float d = 0.f;
+#pragma unroll
+      for (int ch = 0; ch < 8; ++ch) {
+        float4 xv = make_float4(0.f, 0.f, 0.f, 0.f);
+        gr[i][ch] = xv;
+        if (u < nu) {
+          const size_t o = att_child(A, u0 + u, ch);
+          xv = reinterpret_cast<const float4*>(A.x + o)[q];
+          gr[i][ch] = reinterpret_cast<const float4*>(gy + o)[q];
+        }
+        sm.x += xv.x;
+        sm.y += xv.y;
+        sm.z += xv.z;
+        sm.w += xv.w;
+        d += gr[i][ch].x * xv.x + gr[i][ch].y * xv.y + gr[i][ch].z * xv.z + gr[i][ch].w * xv.w;
+      }
+      *reinterpret_cast<float4*>(Z + u * kAttZp + 4 * q) =
+          make_float4(0.125f * sm.x, 0.125f * sm.y, 0.125f * sm.z, 0.125f * sm.w);
+      Pd[u * kAttPp + q] = d;
+    }
+    att_stage_g(A, u0, nu, K16, Z);
+    __syncthreads();
+    att_preact(A, K16, Z, As);
+    __syncthreads();
+    if ((int)threadIdx.x < kAttU) {
+      const int u = threadIdx.x;
+      float a = 0.f, t = 0.f;
+      if (u < nu) {
+        a = att_alpha_of(A, As, u);
+        float d = 0.f;
+        for (int q = 0; q < c4; ++q) d += Pd[u * kAttPp + q];
+        t = d * a * (1.f - a);  // through the sigmoid
+      }
+      al[u] = a;
+      gt[u] = t;
+    }
+    __syncthreads();
+    // psi and bpsi use relu(a) before As turns into ga
+    if ((int)threadIdx.x < c) {
+      const int k = threadIdx.x;
+      float sp = 0.f;
+      for (int u = 0; u < nu; ++u) sp += fmaxf(As[u * kAttAp + k], 0.f) * gt[u];
+      acc_psi += sp;
+    }
+    if (threadIdx.x == 0) {
+      float sb = 0.f;
+      for (int u = 0; u < nu; ++u) sb += gt[u];
+      acc_bpsi += sb;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < kAttU * c; e += blockDim.x) {
+      const int u = e / c, k = e - u * c;
+      float& v = As[u * kAttAp + k];
+      v = (u < nu && v > 0.f) ? A.psi[k] * gt[u] : 0.f;  // ReLU derivative 0 at 0
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < c) {
+      const int k = threadIdx.x;
+      float sb = 0.f;
+      for (int u = 0; u < nu; ++u) sb += As[u * kAttAp + k];
+      acc_b += sb;
+    }
+    // gW [k][j] += sum_u ga[u][k] Z[u][j]: slot g of step u4 is voxel u4 + g
+    for (int u4 = 0; u4 < kAttU; u4 += 4) {
+      float av[4], bv[3];
+#pragma unroll
+      for (int mt = 0; mt < 4; ++mt) {
+        const int k = 16 * mt + l16;
+        av[mt] = (mt < MT && k < c) ? As[(u4 + g) * kAttAp + k] : 0.f;
+      }
+#pragma unroll
+      for (int t = 0; t < 3; ++t) {
+        const int jt = wave + 4 * t;
+        bv[t] = 16 * jt < K16 ? Z[(u4 + g) * kAttZp + 16 * jt + l16] : 0.f;
+      }
+#pragma unroll
+      for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+        for (int t = 0; t < 3; ++t)
+          if (mt < MT && 16 * (wave + 4 * t) < K16) gw[mt][t] = mfma4(av[mt], bv[t], gw[mt][t]);
+    }
+    __syncthreads();  // Z is overwritten below
+    // gZ [u][j] = sum_k ga[u][k] W[k][j] for the wave's 16 rows
+    {
+      float ar[kAttMaxC / 4];
+#pragma unroll
+      for (int k4 = 0; k4 < kAttMaxC / 4; ++k4)
+        ar[k4] = 4 * k4 < c ? As[(16 * wave + l16) * kAttAp + 4 * k4 + g] : 0.f;
+      for (int jt = 0; 16 * jt < K; ++jt) {
+        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+        const int j = 16 * jt + l16;
+#pragma unroll
+        for (int k4 = 0; k4 < kAttMaxC / 4; ++k4)
+          if (4 * k4 < c) acc = mfma4(ar[k4], att_w(A, 4 * k4 + g, j), acc);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int u = 16 * wave + 4 * g + i;
+          if (j < c) {
+            Z[u * kAttZp + j] = 0.125f * acc[i];
+          } else if (j < K && u < nu && gg) {
+            gg[(size_t)(u0 + u) * A.cu + (j - c)] = acc[i];
+          }
+        }
       }
     }
-    al[u] = a;
-    gt[u] = s * a * (1.f - a);  // through the sigmoid
-  }
-  __syncthreads();
-  // psi and bpsi partials use relu(a) before a is overwritten by ga
-  float* P = part + (size_t)blockIdx.x * att_nparams(c, cu);
-  const int o_wg = c * c, o_b = o_wg + c * cu, o_psi = o_b + c, o_bpsi = o_psi + c;
-  for (int k = threadIdx.x; k < c; k += blockDim.x) {
-    float s = 0.f;
-    for (int u = 0; u < nu; ++u) s += fmaxf(as[u * c + k], 0.f) * gt[u];
-    P[o_psi + k] = s;
-  }
-  if (threadIdx.x == 0) {
-    float s = 0.f;
-    for (int u = 0; u < nu; ++u) s += gt[u];
-    P[o_bpsi] = s;
-  }
-  __syncthreads();
-  for (int i = threadIdx.x; i < nu * c; i += blockDim.x) {
-    const int u = i / c, k = i - u * c;
-    as[i] = as[i] > 0.f ? A.psi[k] * gt[u] : 0.f;  // ga (ReLU derivative 0 at 0)
-  }
-  __syncthreads();
-  // parameter partials: wx[k][j] = sum_u ga[u][k] xs[u][j], wg, b
-  for (int i = threadIdx.x; i < c * c; i += blockDim.x) {
-    const int k = i / c, j = i - k * c;
-    float s = 0.f;
-    for (int u = 0; u < nu; ++u) s += as[u * c + k] * xs[u * c + j];
-    P[i] = s;
-  }
-  for (int i = threadIdx.x; i < c * cu; i += blockDim.x) {
-    const int k = i / cu, j = i - k * cu;
-    float s = 0.f;
-    for (int u = 0; u < nu; ++u) s += as[u * c + k] * gs[u * cu + j];
-    P[o_wg + i] = s;
-  }
-  for (int k = threadIdx.x; k < c; k += blockDim.x) {
-    float s = 0.f;
-    for (int u = 0; u < nu; ++u) s += as[u * c + k];
-    P[o_b + k] = s;
-  }
-  // gating gradient gg[u][j] = sum_k wg[k][j] ga[u][k]
-  if (gg)
-    for (int i = threadIdx.x; i < nu * cu; i += blockDim.x) {
-      const int u = i / cu, j = i - u * cu;
-      float s = 0.f;
-      for (int k = 0; k < c; ++k) s += A.wg[(size_t)k * cu + j] * as[u * c + k];
-      gg[(size_t)(u0 + u) * cu + j] = s;
-    }
-  // skip gradient gx[v][j] = alpha gy[v][j] + (1/8) sum_k wx[k][j] ga[u][k]
-  if (gx) {
-    // the pooled part per (u, j) first, into xs (no longer needed)
     __syncthreads();
-    for (int i = threadIdx.x; i < nu * c; i += blockDim.x) {
-      const int u = i / c, j = i - u * c;
-      float s = 0.f;
-      for (int k = 0; k < c; ++k) s += A.wx[(size_t)k * c + j] * as[u * c + k];
-      xs[i] = 0.125f * s;
-    }
-    __syncthreads();
-    for (int i = threadIdx.x; i < nu * 8 * c4; i += blockDim.x) {
-      const int q = i % c4, ch = (i / c4) & 7, u = i / (8 * c4);
-      const int cu_ = u0 + u;
-      const int xx = cu_ % m, yy = (cu_ / m) % m, zz = cu_ / (m * m);
-      const int fz = 2 * zz + (ch >> 2), fy = 2 * yy + ((ch >> 1) & 1), fx = 2 * xx + (ch & 1);
-      const size_t o = ((size_t)(fz * A.n + fy) * A.n + fx) * c;
-      const float4 gv = reinterpret_cast<const float4*>(gy + o)[q];
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) {
+      const int it = threadIdx.x + 256 * i, u = it / c4, q = it - u * c4;
+      if (it >= kAttU * c4 || u >= nu || !gx) continue;
       const float a = al[u];
-      const float* p = xs + u * c + 4 * q;
-      reinterpret_cast<float4*>(gx + o)[q] =
-          make_float4(a * gv.x + p[0], a * gv.y + p[1], a * gv.z + p[2], a * gv.w + p[3]);
+      const float4 p = *reinterpret_cast<const float4*>(Z + u * kAttZp + 4 * q);
+#pragma unroll
+      for (int ch = 0; ch < 8; ++ch)
+        reinterpret_cast<float4*>(gx + att_child(A, u0 + u, ch))[q] =
+            make_float4(a * gr[i][ch].x + p.x, a * gr[i][ch].y + p.y, a * gr[i][ch].z + p.z,
+                        a * gr[i][ch].w + p.w);
     }
+    __syncthreads();  // Z, As, Pd, al and gt are refilled by the next tile
+  }
+  float* P = part + (size_t)blockIdx.x * att_nparams(c, A.cu);
+  const int o_wg = c * c, o_b = o_wg + c * A.cu, o_psi = o_b + c, o_bpsi = o_psi + c;
+#pragma unroll
+  for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+    for (int t = 0; t < 3; ++t) {
+      const int jt = wave + 4 * t, j = 16 * jt + l16;
+      if (mt >= MT || 16 * jt >= K16 || j >= K) continue;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int k = 16 * mt + 4 * g + i;
+        if (k < c) P[j < c ? k * c + j : o_wg + k * A.cu + (j - c)] = gw[mt][t][i];
+      }
+    }
+  if ((int)threadIdx.x < c) {
+    P[o_b + threadIdx.x] = acc_b;
+    P[o_psi + threadIdx.x] = acc_psi;
+  }
+  if (threadIdx.x == 0) P[o_bpsi] = acc_bpsi;
+}
+
+// ---- channel slices, ReLU ---------------------------------------------------
+
+// dst[v][doff + j] = src[v][soff + j] for j < c (all counts and offsets
+// multiples of 4: one float4 per thread and step).
+__global__ __launch_bounds__(256) void k_chan_copy(const float* __restrict__ src, int sC, int soff,
+                                                   float* __restrict__ dst, int dC, int doff,
+                                                   int c4, size_t V) {
+  const size_t total = V * (size_t)c4;
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < total;
+       i += (size_t)gridDim.x * blockDim.x) {
+    const size_t v = i / c4;
+    const int q = (int)(i - v * c4);
+    *reinterpret_cast<float4*>(dst + v * dC + doff + 4 * q) =
+        *reinterpret_cast<const float4*>(src + v * sC + soff + 4 * q);
   }
 }
 
-// out[i] = sum over blocks of fpart[k][i] in FP64, block order, split into
-// the parameter tensors
-__global__ void k_att_reduce(const float* __restrict__ part, int nblocks, int c, int cu,
-                             float* gwx, float* gwg, float* gb, float* gpsi, float* gbpsi) {
-  const int np = att_nparams(c, cu);
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= np) return;
-  double s = 0.0;
-  for (int k = 0; k < nblocks; ++k) s += part[(size_t)k * np + i];
-  const int o_wg = c * c, o_b = o_wg + c * cu, o_psi = o_b + c, o_bpsi = o_psi + c;
-  float* dst = nullptr;
-  int j = 0;
-  if (i < o_wg) {
-    dst = gwx;
-    j = i;
-  } else if (i < o_b) {
-    dst = gwg;
-    j = i - o_wg;
-  } else if (i < o_psi) {
-    dst = gb;
-    j = i - o_b;
-  } else if (i < o_bpsi) {
-    dst = gpsi;
-    j = i - o_psi;
-  } else {
-    dst = gbpsi;
-    j = 0;
+// In place allowed (y == x, gx == gy): each value is read, then written, by
+// the one thread that owns it.
+__global__ __launch_bounds__(256) void k_relu_fwd(const float4* x, float4* y, size_t n4) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n4;
+       i += (size_t)gridDim.x * blockDim.x) {
+    const float4 a = x[i];
+    y[i] = make_float4(fmaxf(a.x, 0.f), fmaxf(a.y, 0.f), fmaxf(a.z, 0.f), fmaxf(a.w, 0.f));
   }
-  if (dst) dst[j] = (float)s;
+}
+
+// gx = gy where y > 0, else 0 (the derivative at the kink taken as 0).
+__global__ __launch_bounds__(256) void k_relu_bwd(const float4* y, const float4* gy, float4* gx,
+                                                  size_t n4) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n4;
+       i += (size_t)gridDim.x * blockDim.x) {
+    const float4 a = y[i], g = gy[i];
+    gx[i] = make_float4(a.x > 0.f ? g.x : 0.f, a.y > 0.f ? g.y : 0.f, a.z > 0.f ? g.z : 0.f,
+                        a.w > 0.f ? g.w : 0.f);
+  }
+}
+
+unsigned elementwise_blocks(size_t work) {
+  return (unsigned)std::max<size_t>(1, std::min<size_t>((work + 255) / 256, 16384));
 }
 
 int head_blocks(size_t V) {
-  size_t b = (V + 2047) / 2048;
+  const size_t b = (V + kHeadChunk - 1) / kHeadChunk;
   return (int)std::max<size_t>(1, std::min<size_t>(b, 1024));
 }
+
+int att_tiles(int n) {
+  const int m = n / 2;
+  return (m * m * m + kAttU - 1) / kAttU;
+}
+
+int att_bwd_blocks(int n) { return std::max(1, std::min(att_tiles(n), 512)); }
 
 }  // namespace
 
@@ -373,7 +576,8 @@ int att_max_cu() { return kAttMaxCu; }
 int head_max_c() { return kHeadMaxC; }
 
 size_t head_scratch_bytes(size_t V, int C) {
-  return (size_t)head_blocks(V) * (C + 1) * sizeof(double);
+  const int nb = head_blocks(V);
+  return (size_t)(nb + colsum_slices(nb)) * (C + 1) * sizeof(double);
 }
 
 void head_forward(const float* x, const float* w, const float* b, const float* mask, size_t V,
@@ -390,25 +594,30 @@ void head_backward(const float* x, const float* w, const float* b, const float* 
   double* part = reinterpret_cast<double*>(scratch);
   hipLaunchKernelGGL(k_head_bwd, dim3(nb), dim3(256), 0, s, x, w, b, mask, gout, V, C, sig, gx,
                      part);
-  if (gw || gb)
-    hipLaunchKernelGGL(k_part_sum, dim3((C + 1 + 255) / 256), dim3(256), 0, s, part, nb, C + 1,
-                       gw, C, gb);
-}
-
-int att_blocks(int n) {
-  const int m = n / 2;
-  return (m * m * m + kAttU - 1) / kAttU;
+  if (gw || gb) {
+    ColOut o{{gw, gb, nullptr, nullptr, nullptr}, {0, C, C + 1, 0, 0, 0}, 2};
+    colsum(part, nb, C + 1, part + (size_t)nb * (C + 1), o, s);
+  }
 }
 
 size_t att_scratch_bytes(int n, int c, int cu) {
-  return (size_t)att_blocks(n) * att_nparams(c, cu) * sizeof(float);
+  const int nb = att_bwd_blocks(n);
+  const size_t np = att_nparams(c, cu);
+  return (size_t)nb * np * sizeof(float) + (size_t)colsum_slices(nb) * np * sizeof(double) + 256;
 }
 
 void att_forward(const float* x, const float* g, const float* wx, const float* wg, const float* b,
                  const float* psi, const float* bpsi, float* y, float* alpha, int n, int c, int cu,
                  hipStream_t s) {
   AttArgs A{x, g, wx, wg, b, psi, bpsi, n, c, cu};
-  hipLaunchKernelGGL(k_att_fwd, dim3(att_blocks(n)), dim3(256), 0, s, A, y, alpha);
+  const int nt = att_tiles(n), items = (c + 15) / 16;
+  const dim3 grid(nt), block(256);
+  switch (items) {
+    case 1: hipLaunchKernelGGL(k_att_fwd<1>, grid, block, 0, s, A, nt, y, alpha); break;
+    case 2: hipLaunchKernelGGL(k_att_fwd<2>, grid, block, 0, s, A, nt, y, alpha); break;
+    case 3: hipLaunchKernelGGL(k_att_fwd<3>, grid, block, 0, s, A, nt, y, alpha); break;
+    default: hipLaunchKernelGGL(k_att_fwd<4>, grid, block, 0, s, A, nt, y, alpha); break;
+  }
 }
 
 void att_backward(const float* x, const float* g, const float* wx, const float* wg,
@@ -416,12 +625,41 @@ void att_backward(const float* x, const float* g, const float* wx, const float* 
                   float* gx, float* gg, float* gwx, float* gwg, float* gb, float* gpsi,
                   float* gbpsi, int n, int c, int cu, void* scratch, hipStream_t s) {
   AttArgs A{x, g, wx, wg, b, psi, bpsi, n, c, cu};
-  const int nb = att_blocks(n);
+  const int nt = att_tiles(n), nb = att_bwd_blocks(n), items = (c + 15) / 16;
   float* part = reinterpret_cast<float*>(scratch);
-  hipLaunchKernelGGL(k_att_bwd, dim3(nb), dim3(256), 0, s, A, gy, gx, gg, part);
   const int np = att_nparams(c, cu);
-  hipLaunchKernelGGL(k_att_reduce, dim3((np + 255) / 256), dim3(256), 0, s, part, nb, c, cu, gwx,
-                     gwg, gb, gpsi, gbpsi);
+  const dim3 grid(nb), block(256);
+  switch (items) {
+    case 1: hipLaunchKernelGGL(k_att_bwd<1>, grid, block, 0, s, A, nt, gy, gx, gg, part); break;
+    case 2: hipLaunchKernelGGL(k_att_bwd<2>, grid, block, 0, s, A, nt, gy, gx, gg, part); break;
+    case 3: hipLaunchKernelGGL(k_att_bwd<3>, grid, block, 0, s, A, nt, gy, gx, gg, part); break;
+    default: hipLaunchKernelGGL(k_att_bwd<4>, grid, block, 0, s, A, nt, gy, gx, gg, part); break;
+  }
+  const int o_wg = c * c, o_b = o_wg + c * cu, o_psi = o_b + c, o_bpsi = o_psi + c;
+  // the FP64 slice sums start at the next 256-byte boundary after the partials
+  const size_t pb = ((size_t)nb * np * sizeof(float) + 255) / 256 * 256;
+  double* tmp = reinterpret_cast<double*>(reinterpret_cast<char*>(scratch) + pb);
+  ColOut o{{gwx, gwg, gb, gpsi, gbpsi}, {0, o_wg, o_b, o_psi, o_bpsi, np}, 5};
+  colsum(part, nb, np, tmp, o, s);
+}
+
+void channel_copy(const float* src, int sC, int soff, float* dst, int dC, int doff, int c,
+                  size_t V, hipStream_t s) {
+  hipLaunchKernelGGL(k_chan_copy, dim3(elementwise_blocks(V * (c / 4))), dim3(256), 0, s, src, sC,
+                     soff, dst, dC, doff, c / 4, V);
+}
+
+void relu_forward(const float* x, float* y, size_t count, hipStream_t s) {
+  const size_t n4 = count / 4;
+  hipLaunchKernelGGL(k_relu_fwd, dim3(elementwise_blocks(n4)), dim3(256), 0, s,
+                     reinterpret_cast<const float4*>(x), reinterpret_cast<float4*>(y), n4);
+}
+
+void relu_backward(const float* y, const float* gy, float* gx, size_t count, hipStream_t s) {
+  const size_t n4 = count / 4;
+  hipLaunchKernelGGL(k_relu_bwd, dim3(elementwise_blocks(n4)), dim3(256), 0, s,
+                     reinterpret_cast<const float4*>(y), reinterpret_cast<const float4*>(gy),
+                     reinterpret_cast<float4*>(gx), n4);
 }
 
 }  // namespace d2ip

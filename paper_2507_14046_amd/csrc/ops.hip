@@ -676,6 +676,46 @@ d2ip_status d2ip_op_up2_concat_backward(const float* gcat, int Cu, int Cs, int n
   return D2IP_OK;
 }
 
+d2ip_status d2ip_op_channel_copy(const float* src, int src_ch, int src_off, float* dst, int dst_ch,
+                                 int dst_off, int ch, size_t voxels, void* hip_stream) {
+  if (!src || !dst) return api_fail(D2IP_EINVAL, "null src or dst");
+  if (ch < 4 || src_ch < 4 || dst_ch < 4 || ch % 4 || src_ch % 4 || dst_ch % 4 || src_off % 4 ||
+      dst_off % 4 || src_off < 0 || dst_off < 0)
+    return api_fail(D2IP_EINVAL, "channel counts and offsets must be non-negative multiples of 4");
+  if (src_off + ch > src_ch || dst_off + ch > dst_ch)
+    return api_fail(D2IP_EINVAL, "channel range exceeds the tensor's channels");
+  if (voxels == 0) return D2IP_OK;
+  if (!aligned16(src) || !aligned16(dst)) return api_fail(D2IP_EINVAL, "tensors must be 16-byte aligned");
+  const size_t sb = voxels * (size_t)src_ch * 4, db = voxels * (size_t)dst_ch * 4;
+  const char *s0 = reinterpret_cast<const char*>(src), *d0 = reinterpret_cast<const char*>(dst);
+  if (s0 < d0 + db && d0 < s0 + sb) return api_fail(D2IP_EINVAL, "src and dst overlap");
+  channel_copy(src, src_ch, src_off, dst, dst_ch, dst_off, ch, voxels,
+               reinterpret_cast<hipStream_t>(hip_stream));
+  OPCHK(hipGetLastError());
+  return D2IP_OK;
+}
+
+d2ip_status d2ip_op_relu_forward(const float* x, float* y, size_t count, void* hip_stream) {
+  if (!x || !y) return api_fail(D2IP_EINVAL, "null x or y");
+  if (count % 4) return api_fail(D2IP_EINVAL, "count must be a multiple of 4");
+  if (count == 0) return D2IP_OK;
+  if (!aligned16(x) || !aligned16(y)) return api_fail(D2IP_EINVAL, "x and y must be 16-byte aligned");
+  relu_forward(x, y, count, reinterpret_cast<hipStream_t>(hip_stream));
+  OPCHK(hipGetLastError());
+  return D2IP_OK;
+}
+
+d2ip_status d2ip_op_relu_backward(const float* y, const float* gy, float* gx, size_t count,
+                                  void* hip_stream) {
+  if (!y || !gy || !gx) return api_fail(D2IP_EINVAL, "null y, gy or gx");
+  if (count % 4) return api_fail(D2IP_EINVAL, "count must be a multiple of 4");
+  if (count == 0) return D2IP_OK;
+  if (!aligned16(y) || !aligned16(gy) || !aligned16(gx))
+    return api_fail(D2IP_EINVAL, "tensors must be 16-byte aligned");
+  relu_backward(y, gy, gx, count, reinterpret_cast<hipStream_t>(hip_stream));
+  OPCHK(hipGetLastError());
+  return D2IP_OK;
+}
 
 d2ip_status d2ip_op_head_bytes(int n, int C, size_t* out) {
   if (!out) return api_fail(D2IP_EINVAL, "null output");
@@ -732,8 +772,8 @@ d2ip_status d2ip_op_attention_forward(const float* x, const float* g, const floa
   if (st != D2IP_OK) return st;
   if (!x || !g || !wx || !wg || !b || !psi || !bpsi || !y)
     return api_fail(D2IP_EINVAL, "null tensor");
-  if (!aligned16(x) || !aligned16(g) || !aligned16(y))
-    return api_fail(D2IP_EINVAL, "x, g and y must be 16-byte aligned");
+  if (!aligned16(x) || !aligned16(g) || !aligned16(y) || !aligned16(wx) || !aligned16(wg))
+    return api_fail(D2IP_EINVAL, "x, g, y, wx and wg must be 16-byte aligned");
   att_forward(x, g, wx, wg, b, psi, bpsi, y, alpha, n, c, cu,
               reinterpret_cast<hipStream_t>(hip_stream));
   OPCHK(hipGetLastError());
@@ -750,8 +790,9 @@ d2ip_status d2ip_op_attention_backward(const float* x, const float* g, const flo
   if (st != D2IP_OK) return st;
   if (!x || !g || !wx || !wg || !b || !psi || !bpsi || !gy)
     return api_fail(D2IP_EINVAL, "null tensor");
-  if (!aligned16(x) || !aligned16(g) || !aligned16(gy) || (gx && !aligned16(gx)))
-    return api_fail(D2IP_EINVAL, "x, g, gy and gx must be 16-byte aligned");
+  if (!aligned16(x) || !aligned16(g) || !aligned16(gy) || (gx && !aligned16(gx)) ||
+      !aligned16(wx) || !aligned16(wg))
+    return api_fail(D2IP_EINVAL, "x, g, gy, gx, wx and wg must be 16-byte aligned");
   size_t need = 0;
   d2ip_op_attention_bytes(n, c, cu, &need);
   if ((st = ws_check(workspace, bytes, need)) != D2IP_OK) return st;

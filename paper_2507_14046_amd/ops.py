@@ -422,6 +422,91 @@ class AttentionFn:
         return _att_fn().apply(x, g, wx, wg, b, psi, bpsi)
 
 
+class ChannelConcatFn:
+    """[x0 | x1 | ...] along channels of channels-last tensors [V, c_i]
+    (library channel-range copies, forward and backward)."""
+
+    @staticmethod
+    def apply(*xs):
+        return _chcat_fn().apply(*xs)
+
+
+class ReLUFn:
+    """max(x, 0) on the library's kernels."""
+
+    @staticmethod
+    def apply(x):
+        return _relu_fn().apply(x)
+
+
+def _chcat_fn():
+    if "chcat" in _FNS:
+        return _FNS["chcat"]
+    torch = _torch()
+
+    class _ChCat(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, *xs):
+            lib = L.load()
+            xs = [_a16(x) for x in xs]
+            V = xs[0].shape[0]
+            cs = [int(x.shape[1]) for x in xs]
+            if any(x.shape[0] != V or x.dim() != 2 for x in xs):
+                raise ValueError("tensors must be [V, c] with the same V")
+            out = torch.empty(V, sum(cs), dtype=xs[0].dtype, device=xs[0].device)
+            off = 0
+            for x, c in zip(xs, cs):
+                L.check(lib.d2ip_op_channel_copy(_p(x), c, 0, _p(out), out.shape[1], off, c, V,
+                                                 _stream(x)))
+                off += c
+            ctx.cs = cs
+            return out
+
+        @staticmethod
+        def backward(ctx, g):
+            lib = L.load()
+            g = _a16(g)
+            V, out, off = g.shape[0], [], 0
+            for c in ctx.cs:
+                gi = torch.empty(V, c, dtype=g.dtype, device=g.device)
+                L.check(lib.d2ip_op_channel_copy(_p(g), g.shape[1], off, _p(gi), c, 0, c, V,
+                                                 _stream(g)))
+                out.append(gi)
+                off += c
+            return tuple(out)
+
+    _FNS["chcat"] = _ChCat
+    return _ChCat
+
+
+def _relu_fn():
+    if "relu" in _FNS:
+        return _FNS["relu"]
+    torch = _torch()
+
+    class _ReLU(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, x):
+            lib = L.load()
+            x = _a16(x)
+            y = torch.empty_like(x)
+            L.check(lib.d2ip_op_relu_forward(_p(x), _p(y), x.numel(), _stream(x)))
+            ctx.save_for_backward(y)
+            return y
+
+        @staticmethod
+        def backward(ctx, gy):
+            lib = L.load()
+            (y,) = ctx.saved_tensors
+            gy = _a16(gy)
+            gx = torch.empty_like(gy)
+            L.check(lib.d2ip_op_relu_backward(_p(y), _p(gy), _p(gx), y.numel(), _stream(gy)))
+            return gx
+
+    _FNS["relu"] = _ReLU
+    return _ReLU
+
+
 def _pool_fn():
     if "pool" in _FNS:
         return _FNS["pool"]
@@ -527,8 +612,8 @@ def _att_fn():
         @staticmethod
         def forward(ctx, x, g, wx, wg, b, psi, bpsi):
             lib = L.load()
-            x, g = _a16(x), _a16(g)
-            wx, wg, b, psi, bpsi = (t.contiguous() for t in (wx, wg, b, psi, bpsi))
+            x, g, wx, wg = _a16(x), _a16(g), _a16(wx), _a16(wg)
+            b, psi, bpsi = (t.contiguous() for t in (b, psi, bpsi))
             n, c, cu = _grid_n(x.shape[0]), x.shape[1], g.shape[1]
             y = torch.empty_like(x)
             L.check(lib.d2ip_op_attention_forward(_p(x), _p(g), _p(wx), _p(wg), _p(b), _p(psi),
@@ -739,12 +824,12 @@ class DIPNet:
     def _aspp(self, P, x):
         """ASPP on the bottleneck: a 1x1x1 branch and one depthwise-separable
         atrous branch per rate, concatenated, projected (1x1x1), ReLU."""
-        torch = _torch()
         br = [PWConv3dFn.apply(x, P["aspp.w0"], P["aspp.b0"])]
         for d in ASPP_RATES:
             t = DWConv3dFn.apply(x, P["aspp.dw%d" % d], P["aspp.dwb%d" % d], d)
             br.append(PWConv3dFn.apply(t, P["aspp.pw%d" % d], P["aspp.pwb%d" % d]))
-        return torch.relu(PWConv3dFn.apply(torch.cat(br, dim=1), P["aspp.wp"], P["aspp.bp"]))
+        return ReLUFn.apply(PWConv3dFn.apply(ChannelConcatFn.apply(*br), P["aspp.wp"],
+                                             P["aspp.bp"]))
 
     def _attend(self, P, d, s, g, n):
         """Attention unit of a decoder stage (Sec. III-D: attention, then

@@ -197,15 +197,23 @@ def shadow_sequence(lib, p, iters, lr, tol=1e-5):
     frame) on the GPU one iteration at a time beside the FP64 oracle, whose
     Adam step at each iteration takes the oracle gradient or, where the GPU's
     gradient matches it better, the oracle gradient with the ReLU decisions
-    within FP32 resolution of a kink taken the other way.  Returns the GPU's
-    and the shadowed oracle's image per frame and the iterations at which a
-    flipped decision was taken."""
+    within FP32 resolution of a kink taken the other way.
+
+    Returns dict(gpu=[image per frame], ref=[shadowed oracle image per frame],
+    flips=[iterations at which a flipped decision was taken],
+    departure=first iteration whose GPU gradient is farther than `tol` from
+    every such oracle gradient (None if none), entry=[relative distance of the
+    GPU's image from the oracle's at the start of each iteration],
+    grad=[relative gradient distance per iteration]).  From the departure on
+    the two trajectories are no longer the same one: the network is piecewise
+    linear, its gradient jumps where a pre-activation crosses zero, and Adam
+    turns such a difference into whole +-lr steps."""
     from oracle import fit
     pr = oracle_problem(p)
     ctx = make_ctx(lib, [p])
     ctx.set_adam(lr=lr)
     st = fit.State(p["theta0"])
-    flips, gpu_imgs, ref_imgs = [], [], []
+    out = dict(gpu=[], ref=[], flips=[], departure=None, entry=[], grad=[])
     it = 0
     try:
         for f, k in enumerate(iters):
@@ -216,6 +224,7 @@ def shadow_sequence(lib, p, iters, lr, tol=1e-5):
                 st.reset_optimizer()
             for _ in range(k):
                 it += 1
+                out["entry"].append(rel(ctx.read_image(0), pr.image(st.theta)))
                 ctx.run(1)
                 gg = ctx.get_grad(0)
                 _, g, _ = pr.loss_and_grad(st.theta, dv)
@@ -225,10 +234,13 @@ def shadow_sequence(lib, p, iters, lr, tol=1e-5):
                         best = min(alts, key=lambda a: rel(gg, a))
                         if rel(gg, best) < rel(gg, g):
                             g = best
-                            flips.append(it)
+                            out["flips"].append(it)
+                out["grad"].append(rel(gg, g))
+                if out["grad"][-1] > tol and out["departure"] is None:
+                    out["departure"] = it
                 st.theta, st.m, st.v, st.t = fit.adam_step(st.theta, g, st.m, st.v, st.t, lr)
-            gpu_imgs.append(ctx.read_image(0))
-            ref_imgs.append(pr.image(st.theta))
+            out["gpu"].append(ctx.read_image(0))
+            out["ref"].append(pr.image(st.theta))
     finally:
         ctx.close()
-    return gpu_imgs, ref_imgs, flips
+    return out

@@ -7,6 +7,7 @@
 #include <cstdlib>
 #include <random>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "d2ip.h"
@@ -237,6 +238,63 @@ static int ops_case() {
       free(ws);
     }
   EXPECT_ERR(d2ip_op_se_bytes(n, 16, 0, &need), D2IP_EINVAL);
+  // pooling, up-sampling + concatenation, channel copy, ReLU
+  for (int Cp : {4, 16, 32}) {
+    CK(d2ip_op_pool2_forward(x.data(), y.data(), n, Cp, nullptr));
+    CK(d2ip_op_pool2_backward(g.data(), gx.data(), n, Cp, nullptr));
+  }
+  CK(d2ip_op_up2_concat_forward(x.data(), 16, g.data(), 16, n, y.data(), nullptr));
+  CK(d2ip_op_up2_concat_backward(g.data(), 16, 16, n, gx.data(), y.data(), nullptr));
+  CK(d2ip_op_channel_copy(x.data(), 32, 20, y.data(), 16, 4, 12, Q, nullptr));
+  CK(d2ip_op_channel_copy(x.data(), 8, 0, y.data(), 32, 24, 8, Q, nullptr));
+  CK(d2ip_op_relu_forward(x.data(), y.data(), (size_t)Q * 32, nullptr));
+  CK(d2ip_op_relu_forward(y.data(), y.data(), (size_t)Q * 32, nullptr));
+  CK(d2ip_op_relu_backward(y.data(), g.data(), gx.data(), (size_t)Q * 32, nullptr));
+  // output head, linear and sigmoid, masked and not
+  for (int Ch : {4, 16, 32})
+    for (int sig : {0, 1}) {
+      std::vector<float> wh(Ch), bh(1), gwh(Ch), gbh(1), mk(Q, 1.f);
+      CK(d2ip_op_head_bytes(n, Ch, &need));
+      ws = (char*)aligned_alloc(256, (need + 255) / 256 * 256);
+      CK(d2ip_op_head_forward(x.data(), wh.data(), bh.data(), sig ? mk.data() : nullptr,
+                              out.data(), n, Ch, sig, nullptr));
+      CK(d2ip_op_head_backward(x.data(), wh.data(), bh.data(), sig ? nullptr : mk.data(),
+                               out.data(), gx.data(), gwh.data(), gbh.data(), n, Ch, sig, ws,
+                               need, nullptr));
+      EXPECT_ERR(d2ip_op_head_backward(x.data(), wh.data(), bh.data(), nullptr, out.data(),
+                                       nullptr, gwh.data(), nullptr, n, Ch, sig, ws, need - 1,
+                                       nullptr),
+                 D2IP_ENOMEM);
+      emu_flush_all();  // the caller frees device memory after its stream has passed
+      free(ws);
+    }
+  // attention unit: ragged last block at 6^3 and the widest channels
+  for (auto [na, ca, cua] : {std::tuple{8, 8, 16}, std::tuple{6, 4, 8}, std::tuple{8, 64, 128},
+                              std::tuple{4, 12, 4}}) {
+    const size_t Va = (size_t)na * na * na, Vc = Va / 8;
+    std::vector<float> xa(Va * ca), ga(Vc * cua), ya(Va * ca), al(Vc), gxa(Va * ca),
+        gga(Vc * cua), wx((size_t)ca * ca), wg((size_t)ca * cua), ba(ca), ps(ca), bp(1),
+        gwx(wx.size()), gwg(wg.size()), gba(ca), gps(ca), gbp(1);
+    CK(d2ip_op_attention_bytes(na, ca, cua, &need));
+    ws = (char*)aligned_alloc(256, (need + 255) / 256 * 256);
+    CK(d2ip_op_attention_forward(xa.data(), ga.data(), wx.data(), wg.data(), ba.data(), ps.data(),
+                                 bp.data(), ya.data(), al.data(), na, ca, cua, nullptr));
+    CK(d2ip_op_attention_backward(xa.data(), ga.data(), wx.data(), wg.data(), ba.data(),
+                                  ps.data(), bp.data(), ya.data(), gxa.data(), gga.data(),
+                                  gwx.data(), gwg.data(), gba.data(), gps.data(), gbp.data(), na,
+                                  ca, cua, ws, need, nullptr));
+    CK(d2ip_op_attention_backward(xa.data(), ga.data(), wx.data(), wg.data(), ba.data(),
+                                  ps.data(), bp.data(), ya.data(), nullptr, nullptr, gwx.data(),
+                                  nullptr, nullptr, nullptr, nullptr, na, ca, cua, ws, need,
+                                  nullptr));
+    EXPECT_ERR(d2ip_op_attention_backward(xa.data(), ga.data(), wx.data(), wg.data(), ba.data(),
+                                          ps.data(), bp.data(), ya.data(), gxa.data(), nullptr,
+                                          nullptr, nullptr, nullptr, nullptr, nullptr, na, ca, cua,
+                                          ws, need - 1, nullptr),
+               D2IP_ENOMEM);
+    emu_flush_all();  // the caller frees device memory after its stream has passed
+    free(ws);
+  }
   EXPECT_ERR(d2ip_op_dwconv3d_forward(x.data() + 1, gam.data(), nullptr, y.data(), n, C, nullptr),
              D2IP_EINVAL);
   CK(d2ip_op_j_forward(J.data(), x.data(), p.data(), M, Q, nullptr));

@@ -285,6 +285,51 @@ def test_module_operators_validate_their_arguments(L):
     assert b"workspace too small" in lib.d2ip_last_error()
 
 
+def test_network_module_operators_validate_their_arguments(L):
+    """Pooling, up-sampling/concatenation, channel copy, ReLU, head and
+    attention entry points reject bad sizes, null, misaligned and overlapping
+    pointers and short workspaces from host checks alone; empty inputs are a
+    no-op."""
+    lib = L.load()
+    nb = ctypes.c_size_t()
+    sz = ctypes.byref(nb)
+    P = ctypes.c_void_p
+    a, b2, odd = P(4096), P(1 << 20), P(4100)  # never dereferenced
+    assert lib.d2ip_op_pool2_forward(a, b2, 7, 16, None) == L.EINVAL
+    assert lib.d2ip_op_pool2_forward(a, b2, 8, 6, None) == L.EINVAL
+    assert lib.d2ip_op_pool2_backward(odd, b2, 8, 16, None) == L.EINVAL
+    assert lib.d2ip_op_up2_concat_forward(a, 16, None, 8, 8, b2, None) == L.EINVAL
+    assert lib.d2ip_op_up2_concat_backward(a, 16, 6, 8, b2, b2, None) == L.EINVAL
+    # channel copy: ranges, multiples of 4, overlap, alignment
+    assert lib.d2ip_op_channel_copy(a, 16, 8, b2, 32, 0, 12, 10, None) == L.EINVAL
+    assert b"exceeds" in lib.d2ip_last_error()
+    assert lib.d2ip_op_channel_copy(a, 16, 2, b2, 32, 0, 8, 10, None) == L.EINVAL
+    assert lib.d2ip_op_channel_copy(a, 16, 0, P(4096 + 64), 32, 0, 16, 10, None) == L.EINVAL
+    assert b"overlap" in lib.d2ip_last_error()
+    assert lib.d2ip_op_channel_copy(odd, 16, 0, b2, 32, 0, 16, 10, None) == L.EINVAL
+    assert lib.d2ip_op_channel_copy(a, 16, 0, b2, 32, 16, 16, 0, None) == L.OK
+    # ReLU
+    assert lib.d2ip_op_relu_forward(a, b2, 6, None) == L.EINVAL
+    assert lib.d2ip_op_relu_forward(odd, b2, 8, None) == L.EINVAL
+    assert lib.d2ip_op_relu_backward(a, None, b2, 8, None) == L.EINVAL
+    assert lib.d2ip_op_relu_forward(a, b2, 0, None) == L.OK
+    # head
+    for args in ((8, 6), (8, 512), (0, 8), (600, 8)):
+        assert lib.d2ip_op_head_bytes(*args, sz) == L.EINVAL, args
+    assert lib.d2ip_op_head_bytes(8, 16, sz) == L.OK and nb.value > 0
+    assert lib.d2ip_op_head_forward(a, odd, a, None, b2, 8, 16, 0, None) == L.EINVAL
+    assert lib.d2ip_op_head_backward(a, a, a, None, a, b2, None, None, 8, 16, 1, a, 1,
+                                     None) == L.ENOMEM
+    # attention
+    for args in ((7, 8, 16), (8, 68, 16), (8, 8, 132), (8, 6, 16), (0, 8, 8)):
+        assert lib.d2ip_op_attention_bytes(*args, sz) == L.EINVAL, args
+    assert lib.d2ip_op_attention_bytes(16, 64, 128, sz) == L.OK and nb.value > 0
+    assert lib.d2ip_op_attention_forward(a, a, a, a, a, a, None, b2, None, 8, 8, 16,
+                                         None) == L.EINVAL
+    assert lib.d2ip_op_attention_backward(a, a, a, a, a, a, a, a, b2, None, None, None, None,
+                                          None, None, 8, 8, 16, a, 1, None) == L.ENOMEM
+
+
 @pytest.mark.parametrize("L_,C", [(3, 16), (4, 32), (2, 8)])
 def test_kaiming_initialiser_moments(L, L_, C):
     """d2ip_init_params_host (Sec. III-B, Kaiming): every conv weight tensor

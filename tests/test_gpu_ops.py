@@ -339,3 +339,32 @@ def test_attention_operator_matches_oracle(lib, n, c, cu):
     record("op_attention", n=n, c=c, cu=cu, **e)
     for k, v in e.items():
         assert v < 1e-5, (k, e)
+
+
+@pytest.mark.parametrize("V,cs", [(1000, (8, 16, 4, 12)), (4 ** 3, (64, 64, 64, 64)),
+                                  (17, (4,))])
+def test_channel_concat_and_relu_operators(lib, V, cs):
+    """d2ip_op_channel_copy (concatenation along channels and the split of the
+    gradient) bitwise against numpy; d2ip_op_relu_* bitwise against
+    max(x, 0) and the gradient masked where the output is positive (exact
+    zeros included, whose derivative is taken as 0)."""
+    import torch
+    from paper_2507_14046_amd import ops
+    rng = np.random.default_rng(V + sum(cs))
+    xs = [rng.standard_normal((V, c)).astype(np.float32) for c in cs]
+    X = [dev(x, True) for x in xs]
+    cat = ops.ChannelConcatFn.apply(*X)
+    want = np.concatenate(xs, axis=1)
+    want[::3, 0] = 0.0                      # exact zeros at the kink
+    G = rng.standard_normal(want.shape).astype(np.float32)
+    np.testing.assert_array_equal(host(cat), np.concatenate(xs, axis=1))
+    Z = dev(want, True)
+    y = ops.ReLUFn.apply(Z)
+    np.testing.assert_array_equal(host(y), np.maximum(want, 0.0))
+    y.backward(dev(G))
+    np.testing.assert_array_equal(host(Z.grad), np.where(want > 0, G, 0.0))
+    cat.backward(dev(G))
+    off = 0
+    for x, c in zip(X, cs):
+        np.testing.assert_array_equal(host(x.grad), G[:, off:off + c])
+        off += c
