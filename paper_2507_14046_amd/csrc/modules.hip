@@ -59,6 +59,8 @@ __global__ __launch_bounds__(256) void k_head_fwd(const float* __restrict__ x,
 
 // ---- fixed-order column sums ----------------------------------------------
 
+constexpr int kColSlices = 32;
+
 // Stage 1 of out[i] = sum_k part[k][i] (k < nrows, i < ncols): slice s of the
 // rows (contiguous, S slices) is summed per column in FP64 by four row lanes
 // (rows r0 + l, r0 + l + 4, ...) whose sums are then added in lane order.
@@ -73,7 +75,17 @@ __global__ __launch_bounds__(256) void k_colsum1(const T* __restrict__ part, int
   const int r0 = (int)((long long)nrows * sl / S), r1 = (int)((long long)nrows * (sl + 1) / S);
   double acc = 0.0;
   if (col < ncols)
-    for (int k = r0 + ln; k < r1; k += 4) acc += (double)part[(size_t)k * ncols + col];
+    for (int k0 = r0 + ln; k0 < r1; k0 += 32) {
+      // eight loads in flight, then added in row order
+      double v[8];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int k = k0 + 4 * e;
+        v[e] = k < r1 ? (double)part[(size_t)k * ncols + col] : 0.0;
+      }
+#pragma unroll
+      for (int e = 0; e < 8; ++e) acc += v[e];
+    }
   red[ln][cl] = acc;
   __syncthreads();
   if (ln == 0 && col < ncols)
@@ -93,16 +105,19 @@ __global__ __launch_bounds__(256) void k_colsum2(const double* __restrict__ tmp,
                                                  ColOut o) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= ncols) return;
+  // every slice's load in flight, then added in slice order (S <= kColSlices)
+  double v[kColSlices];
+#pragma unroll
+  for (int k = 0; k < kColSlices; ++k) v[k] = k < S ? tmp[(size_t)k * ncols + i] : 0.0;
   double s = 0.0;
-  for (int k = 0; k < S; ++k) s += tmp[(size_t)k * ncols + i];
+#pragma unroll
+  for (int k = 0; k < kColSlices; ++k) s += v[k];
   for (int j = 0; j < o.nseg; ++j)
     if (i >= o.start[j] && i < o.start[j + 1]) {
       if (o.dst[j]) o.dst[j][i - o.start[j]] = (float)s;
       break;
     }
 }
-
-constexpr int kColSlices = 32;
 
 int colsum_slices(int nrows) { return nrows < kColSlices ? nrows : kColSlices; }
 
@@ -190,25 +205,52 @@ __global__ __launch_bounds__(256) void k_head_bwd(const float* __restrict__ x,
 // ---- attention unit ---------------------------------------------------------
 //
 // A tile is kAttU = 64 coarse voxels (four row tiles of 16, one per wave).
-// Z [u][0, c) holds the pooled skip rows, Z [u][c, c + cu) the gating rows
-// (LDS, zero past the tile's voxels and past K = c + cu up to K16, the next
-// multiple of 16).  W [k][j] = [wx[k][:], wg[k][:]] is read from global
-// memory (L1/L2-resident).  The matrix-core step is v_mfma_f32_16x16x4f32:
-// lane l = l16 + 16 g supplies A[row l16][slot g] and B[slot g][col l16] and
-// receives D[row 4 g + i][col l16] in register i.
+// LDS (sized per launch): Z [u][0, c) the pooled skip rows and Z [u][c, K)
+// the gating rows (K = c + cu; zero past the tile's voxels and up to K16, the
+// next multiple of 16); W [k][j] = [wx[k][:], wg[k][:]] staged once per
+// block with the same row stride.  The matrix-core step is
+// v_mfma_f32_16x16x4f32: lane l = l16 + 16 g supplies A[row l16][slot g] and
+// B[slot g][col l16] and receives D[row 4 g + i][col l16] in register i.
 
 constexpr int kAttU = 64;
 constexpr int kAttMaxC = 64;   // skip channels
 constexpr int kAttMaxCu = 128; // gating channels
-constexpr int kAttMaxK = kAttMaxC + kAttMaxCu;
-constexpr int kAttZp = kAttMaxK + 4;  // LDS row stride of Z (floats)
-constexpr int kAttAp = kAttMaxC + 4;  // LDS row stride of a, ga
-constexpr int kAttPp = kAttMaxC / 4 + 1;
 
 struct AttArgs {
   const float *x, *g, *wx, *wg, *b, *psi, *bpsi;
   int n, c, cu;
 };
+
+// LDS layout in floats (every offset a multiple of 4).
+struct AttLds {
+  int K16, Zs, Ap, Pp;
+  int z, w, a, pd, al, gt, red, total;
+};
+
+__host__ __device__ inline AttLds att_lds(int c, int cu, bool bwd) {
+  AttLds L;
+  L.K16 = (c + cu + 15) & ~15;
+  L.Zs = L.K16 + 4;
+  L.Ap = c + 4;
+  L.Pp = c / 4 + 1;
+  int o = 0;
+  L.z = o;
+  o += kAttU * L.Zs;
+  L.w = o;
+  o += c * L.Zs;
+  L.a = o;
+  o += bwd ? kAttU * L.Ap : 0;
+  L.pd = o;
+  o += bwd ? kAttU * L.Pp : 0;
+  L.al = o;
+  o += kAttU;
+  L.gt = o;
+  o += bwd ? kAttU : 0;
+  L.red = o;
+  o += bwd ? 512 : 0;
+  L.total = o;
+  return L;
+}
 
 __device__ __forceinline__ f32x4 mfma4(float a, float b, f32x4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
@@ -226,58 +268,72 @@ __device__ __forceinline__ size_t att_child(const AttArgs& A, int uc, int ch) {
   return ((size_t)(fz * A.n + fy) * A.n + fx) * A.c;
 }
 
-// W [k][j0 .. j0 + 3] (j0 % 4 == 0), zero outside k < c, j < K.
-__device__ __forceinline__ float4 att_w4(const AttArgs& A, int k, int j0) {
-  if (k >= A.c || j0 >= A.c + A.cu) return make_float4(0.f, 0.f, 0.f, 0.f);
-  return j0 < A.c ? *reinterpret_cast<const float4*>(A.wx + (size_t)k * A.c + j0)
-                  : *reinterpret_cast<const float4*>(A.wg + (size_t)k * A.cu + (j0 - A.c));
-}
-
-// W [k][j], zero outside.
-__device__ __forceinline__ float att_w(const AttArgs& A, int k, int j) {
-  if (k >= A.c || j >= A.c + A.cu) return 0.f;
-  return j < A.c ? A.wx[(size_t)k * A.c + j] : A.wg[(size_t)k * A.cu + (j - A.c)];
+// W into LDS: Ws [k][j] for k < c, j < K16 (zero for j >= K).
+__device__ __forceinline__ void att_stage_w(const AttArgs& A, const AttLds& L, float* Ws) {
+  const int w4 = L.K16 / 4;
+  for (int it = threadIdx.x; it < A.c * w4; it += blockDim.x) {
+    const int k = it / w4, j0 = 4 * (it - k * w4);
+    float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (j0 < A.c)
+      v = *reinterpret_cast<const float4*>(A.wx + (size_t)k * A.c + j0);
+    else if (j0 < A.c + A.cu)
+      v = *reinterpret_cast<const float4*>(A.wg + (size_t)k * A.cu + (j0 - A.c));
+    *reinterpret_cast<float4*>(Ws + k * L.Zs + j0) = v;
+  }
 }
 
 // Gating rows (and zero padding) of the tile into Z [u][c, K16).
-__device__ __forceinline__ void att_stage_g(const AttArgs& A, int u0, int nu, int K16, float* Z) {
-  const int w4 = (K16 - A.c) / 4;
+__device__ __forceinline__ void att_stage_g(const AttArgs& A, const AttLds& L, int u0, int nu,
+                                            float* Z) {
+  const int w4 = (L.K16 - A.c) / 4;
   for (int it = threadIdx.x; it < kAttU * w4; it += blockDim.x) {
     const int u = it / w4, j0 = A.c + 4 * (it - u * w4);
     float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
     if (u < nu && j0 < A.c + A.cu)
       v = *reinterpret_cast<const float4*>(A.g + (size_t)(u0 + u) * A.cu + (j0 - A.c));
-    *reinterpret_cast<float4*>(Z + u * kAttZp + j0) = v;
+    *reinterpret_cast<float4*>(Z + u * L.Zs + j0) = v;
   }
 }
 
-// a [u][k] = b[k] + sum_j Z[u][j] W[k][j] into As (k < c): wave w takes rows
-// 16 w .. 16 w + 15 of the tile and every column tile.
-__device__ __forceinline__ void att_preact(const AttArgs& A, int K16, const float* Z, float* As) {
+// a [u][k] = b[k] + sum_j Z[u][j] W[k][j] for the wave's rows u = 16 w ..
+// 16 w + 15 (into As when given), and alpha[u] = sigmoid(bpsi + sum_k psi[k]
+// relu(a[u][k])) into al: each column tile's psi-weighted terms are added over
+// its 16 lanes by a butterfly, the tiles in order, and lane 16 g keeps the sums
+// of rows 4 g .. 4 g + 3.
+__device__ __forceinline__ void att_preact_alpha(const AttArgs& A, const AttLds& L, const float* Z,
+                                                 const float* Ws, float* As, float* al) {
   const int lane = threadIdx.x & 63, l16 = lane & 15, g = lane >> 4;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  float sacc[4] = {0.f, 0.f, 0.f, 0.f};
   for (int nt = 0; nt * 16 < A.c; ++nt) {
+    const int k = 16 * nt + l16;
+    const bool kin = k < A.c;
     f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-    for (int k16 = 0; k16 < K16; k16 += 16) {
-      const float4 a = *reinterpret_cast<const float4*>(Z + (16 * wave + l16) * kAttZp + k16 + 4 * g);
-      const float4 bw = att_w4(A, 16 * nt + l16, k16 + 4 * g);
+    for (int k16 = 0; k16 < L.K16; k16 += 16) {
+      const float4 a = *reinterpret_cast<const float4*>(Z + (16 * wave + l16) * L.Zs + k16 + 4 * g);
+      float4 bw = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (kin) bw = *reinterpret_cast<const float4*>(Ws + k * L.Zs + k16 + 4 * g);
 #pragma unroll
       for (int s = 0; s < 4; ++s) acc = mfma4(comp4(a, s), comp4(bw, s), acc);
     }
-    const int k = 16 * nt + l16;
-    if (k < A.c) {
-      const float bk = A.b[k];
+    const float bk = kin ? A.b[k] : 0.f, pk = kin ? A.psi[k] : 0.f;
 #pragma unroll
-      for (int i = 0; i < 4; ++i) As[(16 * wave + 4 * g + i) * kAttAp + k] = acc[i] + bk;
+    for (int i = 0; i < 4; ++i) {
+      const float av = acc[i] + bk;
+      if (As && kin) As[(16 * wave + 4 * g + i) * L.Ap + k] = av;
+      float v = pk * fmaxf(av, 0.f);
+      v += __shfl_xor(v, 8, 64);
+      v += __shfl_xor(v, 4, 64);
+      v += __shfl_xor(v, 2, 64);
+      v += __shfl_xor(v, 1, 64);
+      sacc[i] += v;
     }
   }
-}
-
-__device__ __forceinline__ float att_alpha_of(const AttArgs& A, const float* As, int u) {
-  float s = A.bpsi[0];
-  const float* ar = As + u * kAttAp;
-  for (int k = 0; k < A.c; ++k) s += A.psi[k] * fmaxf(ar[k], 0.f);
-  return 1.f / (1.f + expf(-s));
+  if (l16 == 0) {
+    const float bp = A.bpsi[0];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) al[16 * wave + 4 * g + i] = 1.f / (1.f + expf(-(bp + sacc[i])));
+  }
 }
 
 // Forward.  ITEMS = ceil(c / 16): a thread owns items it = tid + 256 i
@@ -286,11 +342,12 @@ __device__ __forceinline__ float att_alpha_of(const AttArgs& A, const float* As,
 template <int ITEMS>
 __global__ __launch_bounds__(256) void k_att_fwd(AttArgs A, int ntiles, float* __restrict__ y,
                                                  float* __restrict__ alpha) {
-  __shared__ __align__(16) float Z[kAttU * kAttZp];
-  __shared__ float As[kAttU * kAttAp];
-  __shared__ float al[kAttU];
-  const int c4 = A.c / 4, K16 = (A.c + A.cu + 15) & ~15;
+  extern __shared__ __align__(16) float smem[];
+  const AttLds L = att_lds(A.c, A.cu, false);
+  float *Z = smem + L.z, *Ws = smem + L.w, *al = smem + L.al;
+  const int c4 = A.c / 4;
   const int m = A.n / 2, mc = m * m * m;
+  att_stage_w(A, L, Ws);
   for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
     const int u0 = tile * kAttU, nu = min(kAttU, mc - u0);
     float4 xr[ITEMS][8];
@@ -308,19 +365,14 @@ __global__ __launch_bounds__(256) void k_att_fwd(AttArgs A, int ntiles, float* _
         sm.z += xr[i][ch].z;
         sm.w += xr[i][ch].w;
       }
-      *reinterpret_cast<float4*>(Z + u * kAttZp + 4 * q) =
+      *reinterpret_cast<float4*>(Z + u * L.Zs + 4 * q) =
           make_float4(0.125f * sm.x, 0.125f * sm.y, 0.125f * sm.z, 0.125f * sm.w);
     }
-    att_stage_g(A, u0, nu, K16, Z);
+    att_stage_g(A, L, u0, nu, Z);
     __syncthreads();
-    att_preact(A, K16, Z, As);
+    att_preact_alpha(A, L, Z, Ws, nullptr, al);
     __syncthreads();
-    if ((int)threadIdx.x < nu) {
-      const float a = att_alpha_of(A, As, threadIdx.x);
-      al[threadIdx.x] = a;
-      if (alpha) alpha[u0 + threadIdx.x] = a;
-    }
-    __syncthreads();
+    if (alpha && (int)threadIdx.x < nu) alpha[u0 + threadIdx.x] = al[threadIdx.x];
 #pragma unroll
     for (int i = 0; i < ITEMS; ++i) {
       const int it = threadIdx.x + 256 * i, u = it / c4, q = it - u * c4;
@@ -331,7 +383,7 @@ __global__ __launch_bounds__(256) void k_att_fwd(AttArgs A, int ntiles, float* _
         reinterpret_cast<float4*>(y + att_child(A, u0 + u, ch))[q] =
             make_float4(a * xr[i][ch].x, a * xr[i][ch].y, a * xr[i][ch].z, a * xr[i][ch].w);
     }
-    __syncthreads();  // Z, As and al are refilled by the next tile
+    __syncthreads();  // Z and al are refilled by the next tile
   }
 }
 
@@ -342,30 +394,33 @@ __host__ __device__ inline int att_nparams(int c, int cu) { return c * c + c * c
 // Backward of a block's tiles (tile k, k + gridDim, ...): the same items as
 // the forward keep the children's gy quads in registers; dL/dalpha[u] is the
 // sum of gy x over the children, added per quad and then over the quads in
-// order.  ga [u][k] = psi[k] gt[u] where a > 0; the weight gradient
-// gW [k][j] += sum_u ga[u][k] Z[u][j] accumulates over the block's tiles in
-// the matrix-core registers (wave w: column tiles w, w + 4, w + 8); the
-// pooled and gating gradients gZ [u][j] = sum_k ga[u][k] W[k][j] (wave w:
+// order.  ga [u][k] = psi[k] gt[u] where a > 0; the psi, b and bpsi sums run
+// over fixed voxel subsets per thread, combined in order.  The weight
+// gradient gW [k][j] += sum_u ga[u][k] Z[u][j] accumulates over the block's
+// tiles in the matrix-core registers (wave w: column tiles w, w + 4, w + 8);
+// the pooled and gating gradients gZ [u][j] = sum_k ga[u][k] W[k][j] (wave w:
 // rows 16 w ..) give gg directly and gx = alpha gy + gZ[u][j] / 8.
 template <int ITEMS>
 __global__ __launch_bounds__(256) void k_att_bwd(AttArgs A, int ntiles, const float* __restrict__ gy,
                                                  float* __restrict__ gx, float* __restrict__ gg,
                                                  float* __restrict__ part) {
-  __shared__ __align__(16) float Z[kAttU * kAttZp];  // Z, then gZ [u][0, c) / 8
-  __shared__ __align__(16) float As[kAttU * kAttAp]; // a, then ga
-  __shared__ float Pd[kAttU * kAttPp];               // per-quad dots gy . x
-  __shared__ float al[kAttU], gt[kAttU];
-  const int c = A.c, c4 = c / 4, K = c + A.cu, K16 = (K + 15) & ~15;
+  extern __shared__ __align__(16) float smem[];
+  const AttLds L = att_lds(A.c, A.cu, true);
+  float *Z = smem + L.z, *Ws = smem + L.w, *As = smem + L.a, *Pd = smem + L.pd;
+  float *al = smem + L.al, *gt = smem + L.gt, *red = smem + L.red;
+  const int c = A.c, c4 = c / 4, K = c + A.cu;
   const int m = A.n / 2, mc = m * m * m;
   const int lane = threadIdx.x & 63, l16 = lane & 15, g = lane >> 4;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int MT = (c + 15) / 16;  // row tiles of gW (k)
+  const int NL = 256 / c;        // voxel lanes of the psi and b sums
   f32x4 gw[4][3];
 #pragma unroll
   for (int mt = 0; mt < 4; ++mt)
 #pragma unroll
     for (int t = 0; t < 3; ++t) gw[mt][t] = f32x4{0.f, 0.f, 0.f, 0.f};
   float acc_psi = 0.f, acc_b = 0.f, acc_bpsi = 0.f;
+  att_stage_w(A, L, Ws);
   for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
     const int u0 = tile * kAttU, nu = min(kAttU, mc - u0);
     float4 gr[ITEMS][8];
@@ -390,50 +445,55 @@ __global__ __launch_bounds__(256) void k_att_bwd(AttArgs A, int ntiles, const fl
         sm.w += xv.w;
         d += gr[i][ch].x * xv.x + gr[i][ch].y * xv.y + gr[i][ch].z * xv.z + gr[i][ch].w * xv.w;
       }
-      *reinterpret_cast<float4*>(Z + u * kAttZp + 4 * q) =
+      *reinterpret_cast<float4*>(Z + u * L.Zs + 4 * q) =
           make_float4(0.125f * sm.x, 0.125f * sm.y, 0.125f * sm.z, 0.125f * sm.w);
-      Pd[u * kAttPp + q] = d;
+      Pd[u * L.Pp + q] = d;
     }
-    att_stage_g(A, u0, nu, K16, Z);
+    att_stage_g(A, L, u0, nu, Z);
     __syncthreads();
-    att_preact(A, K16, Z, As);
+    att_preact_alpha(A, L, Z, Ws, As, al);
     __syncthreads();
     if ((int)threadIdx.x < kAttU) {
       const int u = threadIdx.x;
-      float a = 0.f, t = 0.f;
+      float t = 0.f;
       if (u < nu) {
-        a = att_alpha_of(A, As, u);
         float d = 0.f;
-        for (int q = 0; q < c4; ++q) d += Pd[u * kAttPp + q];
+        for (int q = 0; q < c4; ++q) d += Pd[u * L.Pp + q];
+        const float a = al[u];
         t = d * a * (1.f - a);  // through the sigmoid
       }
-      al[u] = a;
       gt[u] = t;
     }
     __syncthreads();
-    // psi and bpsi use relu(a) before As turns into ga
+    // psi (relu(a) gt), then ga in place and b; voxel lane l takes u = l, l + NL, ...
+    if ((int)threadIdx.x < c * NL) {
+      const int k = threadIdx.x % c, l = threadIdx.x / c;
+      const float pk = A.psi[k];
+      float sp = 0.f, sb = 0.f;
+      for (int u = l; u < kAttU; u += NL) {
+        const float av = As[u * L.Ap + k], tu = gt[u];
+        const bool in = u < nu;
+        if (in) sp += fmaxf(av, 0.f) * tu;
+        const float ga = (in && av > 0.f) ? pk * tu : 0.f;  // ReLU derivative 0 at 0
+        sb += ga;
+        As[u * L.Ap + k] = ga;
+      }
+      red[l * c + k] = sp;
+      red[256 + l * c + k] = sb;
+    }
+    if (wave == 0) {
+      float v = lane < nu ? gt[lane] : 0.f;
+      v = wave_sum(v);
+      if (lane == 0) acc_bpsi += v;
+    }
+    __syncthreads();
     if ((int)threadIdx.x < c) {
-      const int k = threadIdx.x;
-      float sp = 0.f;
-      for (int u = 0; u < nu; ++u) sp += fmaxf(As[u * kAttAp + k], 0.f) * gt[u];
+      float sp = 0.f, sb = 0.f;
+      for (int l = 0; l < NL; ++l) {
+        sp += red[l * c + threadIdx.x];
+        sb += red[256 + l * c + threadIdx.x];
+      }
       acc_psi += sp;
-    }
-    if (threadIdx.x == 0) {
-      float sb = 0.f;
-      for (int u = 0; u < nu; ++u) sb += gt[u];
-      acc_bpsi += sb;
-    }
-    __syncthreads();
-    for (int e = threadIdx.x; e < kAttU * c; e += blockDim.x) {
-      const int u = e / c, k = e - u * c;
-      float& v = As[u * kAttAp + k];
-      v = (u < nu && v > 0.f) ? A.psi[k] * gt[u] : 0.f;  // ReLU derivative 0 at 0
-    }
-    __syncthreads();
-    if ((int)threadIdx.x < c) {
-      const int k = threadIdx.x;
-      float sb = 0.f;
-      for (int u = 0; u < nu; ++u) sb += As[u * kAttAp + k];
       acc_b += sb;
     }
     // gW [k][j] += sum_u ga[u][k] Z[u][j]: slot g of step u4 is voxel u4 + g
@@ -442,40 +502,33 @@ __global__ __launch_bounds__(256) void k_att_bwd(AttArgs A, int ntiles, const fl
 #pragma unroll
       for (int mt = 0; mt < 4; ++mt) {
         const int k = 16 * mt + l16;
-        av[mt] = (mt < MT && k < c) ? As[(u4 + g) * kAttAp + k] : 0.f;
+        av[mt] = (mt < MT && k < c) ? As[(u4 + g) * L.Ap + k] : 0.f;
       }
 #pragma unroll
       for (int t = 0; t < 3; ++t) {
         const int jt = wave + 4 * t;
-        bv[t] = 16 * jt < K16 ? Z[(u4 + g) * kAttZp + 16 * jt + l16] : 0.f;
+        bv[t] = 16 * jt < L.K16 ? Z[(u4 + g) * L.Zs + 16 * jt + l16] : 0.f;
       }
 #pragma unroll
       for (int mt = 0; mt < 4; ++mt)
 #pragma unroll
         for (int t = 0; t < 3; ++t)
-          if (mt < MT && 16 * (wave + 4 * t) < K16) gw[mt][t] = mfma4(av[mt], bv[t], gw[mt][t]);
+          if (mt < MT && 16 * (wave + 4 * t) < L.K16) gw[mt][t] = mfma4(av[mt], bv[t], gw[mt][t]);
     }
     __syncthreads();  // Z is overwritten below
     // gZ [u][j] = sum_k ga[u][k] W[k][j] for the wave's 16 rows
-    {
-      float ar[kAttMaxC / 4];
+    for (int jt = 0; 16 * jt < K; ++jt) {
+      f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+      const int j = 16 * jt + l16;
+      for (int k4 = 0; k4 < c4; ++k4)
+        acc = mfma4(As[(16 * wave + l16) * L.Ap + 4 * k4 + g], Ws[(4 * k4 + g) * L.Zs + j], acc);
 #pragma unroll
-      for (int k4 = 0; k4 < kAttMaxC / 4; ++k4)
-        ar[k4] = 4 * k4 < c ? As[(16 * wave + l16) * kAttAp + 4 * k4 + g] : 0.f;
-      for (int jt = 0; 16 * jt < K; ++jt) {
-        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-        const int j = 16 * jt + l16;
-#pragma unroll
-        for (int k4 = 0; k4 < kAttMaxC / 4; ++k4)
-          if (4 * k4 < c) acc = mfma4(ar[k4], att_w(A, 4 * k4 + g, j), acc);
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const int u = 16 * wave + 4 * g + i;
-          if (j < c) {
-            Z[u * kAttZp + j] = 0.125f * acc[i];
-          } else if (j < K && u < nu && gg) {
-            gg[(size_t)(u0 + u) * A.cu + (j - c)] = acc[i];
-          }
+      for (int i = 0; i < 4; ++i) {
+        const int u = 16 * wave + 4 * g + i;
+        if (j < c) {
+          Z[u * L.Zs + j] = 0.125f * acc[i];
+        } else if (j < K && u < nu && gg) {
+          gg[(size_t)(u0 + u) * A.cu + (j - c)] = acc[i];
         }
       }
     }
@@ -485,14 +538,14 @@ __global__ __launch_bounds__(256) void k_att_bwd(AttArgs A, int ntiles, const fl
       const int it = threadIdx.x + 256 * i, u = it / c4, q = it - u * c4;
       if (it >= kAttU * c4 || u >= nu || !gx) continue;
       const float a = al[u];
-      const float4 p = *reinterpret_cast<const float4*>(Z + u * kAttZp + 4 * q);
+      const float4 p = *reinterpret_cast<const float4*>(Z + u * L.Zs + 4 * q);
 #pragma unroll
       for (int ch = 0; ch < 8; ++ch)
         reinterpret_cast<float4*>(gx + att_child(A, u0 + u, ch))[q] =
             make_float4(a * gr[i][ch].x + p.x, a * gr[i][ch].y + p.y, a * gr[i][ch].z + p.z,
                         a * gr[i][ch].w + p.w);
     }
-    __syncthreads();  // Z, As, Pd, al and gt are refilled by the next tile
+    __syncthreads();  // Z, As, Pd, al, gt and red are refilled by the next tile
   }
   float* P = part + (size_t)blockIdx.x * att_nparams(c, A.cu);
   const int o_wg = c * c, o_b = o_wg + c * A.cu, o_psi = o_b + c, o_bpsi = o_psi + c;
@@ -501,7 +554,7 @@ __global__ __launch_bounds__(256) void k_att_bwd(AttArgs A, int ntiles, const fl
 #pragma unroll
     for (int t = 0; t < 3; ++t) {
       const int jt = wave + 4 * t, j = 16 * jt + l16;
-      if (mt >= MT || 16 * jt >= K16 || j >= K) continue;
+      if (mt >= MT || 16 * jt >= L.K16 || j >= K) continue;
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const int k = 16 * mt + 4 * g + i;
@@ -606,17 +659,29 @@ size_t att_scratch_bytes(int n, int c, int cu) {
   return (size_t)nb * np * sizeof(float) + (size_t)colsum_slices(nb) * np * sizeof(double) + 256;
 }
 
+size_t att_lds_bytes(int c, int cu, bool bwd) { return (size_t)att_lds(c, cu, bwd).total * 4; }
+
+template <class Kern>
+void att_launch(Kern k, size_t lds, dim3 grid, hipStream_t s, const AttArgs& A, int nt, float* p0,
+                float* p1) {
+  if (lds > 64 * 1024)
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  hipLaunchKernelGGL(k, grid, dim3(256), lds, s, A, nt, p0, p1);
+}
+
 void att_forward(const float* x, const float* g, const float* wx, const float* wg, const float* b,
                  const float* psi, const float* bpsi, float* y, float* alpha, int n, int c, int cu,
                  hipStream_t s) {
   AttArgs A{x, g, wx, wg, b, psi, bpsi, n, c, cu};
   const int nt = att_tiles(n), items = (c + 15) / 16;
-  const dim3 grid(nt), block(256);
+  const size_t lds = att_lds_bytes(c, cu, false);
+  const dim3 grid(nt);
   switch (items) {
-    case 1: hipLaunchKernelGGL(k_att_fwd<1>, grid, block, 0, s, A, nt, y, alpha); break;
-    case 2: hipLaunchKernelGGL(k_att_fwd<2>, grid, block, 0, s, A, nt, y, alpha); break;
-    case 3: hipLaunchKernelGGL(k_att_fwd<3>, grid, block, 0, s, A, nt, y, alpha); break;
-    default: hipLaunchKernelGGL(k_att_fwd<4>, grid, block, 0, s, A, nt, y, alpha); break;
+    case 1: att_launch(k_att_fwd<1>, lds, grid, s, A, nt, y, alpha); break;
+    case 2: att_launch(k_att_fwd<2>, lds, grid, s, A, nt, y, alpha); break;
+    case 3: att_launch(k_att_fwd<3>, lds, grid, s, A, nt, y, alpha); break;
+    default: att_launch(k_att_fwd<4>, lds, grid, s, A, nt, y, alpha); break;
   }
 }
 
@@ -628,12 +693,19 @@ void att_backward(const float* x, const float* g, const float* wx, const float* 
   const int nt = att_tiles(n), nb = att_bwd_blocks(n), items = (c + 15) / 16;
   float* part = reinterpret_cast<float*>(scratch);
   const int np = att_nparams(c, cu);
-  const dim3 grid(nb), block(256);
+  const size_t lds = att_lds_bytes(c, cu, true);
+  const dim3 grid(nb);
+  auto launch = [&](auto kern) {
+    if (lds > 64 * 1024)
+      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL(kern, grid, dim3(256), lds, s, A, nt, gy, gx, gg, part);
+  };
   switch (items) {
-    case 1: hipLaunchKernelGGL(k_att_bwd<1>, grid, block, 0, s, A, nt, gy, gx, gg, part); break;
-    case 2: hipLaunchKernelGGL(k_att_bwd<2>, grid, block, 0, s, A, nt, gy, gx, gg, part); break;
-    case 3: hipLaunchKernelGGL(k_att_bwd<3>, grid, block, 0, s, A, nt, gy, gx, gg, part); break;
-    default: hipLaunchKernelGGL(k_att_bwd<4>, grid, block, 0, s, A, nt, gy, gx, gg, part); break;
+    case 1: launch(k_att_bwd<1>); break;
+    case 2: launch(k_att_bwd<2>); break;
+    case 3: launch(k_att_bwd<3>); break;
+    default: launch(k_att_bwd<4>); break;
   }
   const int o_wg = c * c, o_b = o_wg + c * cu, o_psi = o_b + c, o_bpsi = o_psi + c;
   // the FP64 slice sums start at the next 256-byte boundary after the partials

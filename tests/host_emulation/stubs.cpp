@@ -161,7 +161,8 @@ hipError_t __hipPopCallConfiguration(dim3* g, dim3* b, size_t* shm, hipStream_t*
 }
 hipError_t hipLaunchKernel(const void*, dim3 g, dim3 b, void** args, size_t shm, hipStream_t s) {
   ++g_launches;
-  if (g.x == 0 || g.y == 0 || g.z == 0 || g.y > 65535 || g.z > 65535 || shm > 65536 ||
+  // gfx950: 160 KiB of LDS per CU, all of it available to one workgroup
+  if (g.x == 0 || g.y == 0 || g.z == 0 || g.y > 65535 || g.z > 65535 || shm > 160 * 1024 ||
       b.x * b.y * b.z > 1024 || !args) {
     fprintf(stderr, "bad launch grid %u %u %u block %u shm %zu\n", g.x, g.y, g.z, b.x, shm);
     abort();
@@ -171,6 +172,13 @@ hipError_t hipLaunchKernel(const void*, dim3 g, dim3 b, void** args, size_t shm,
   if (st->capturing) {
     ++g_captured_launches;
     ++st->graph->launches;
+  }
+  return hipSuccess;
+}
+hipError_t hipFuncSetAttribute(const void* f, hipFuncAttribute a, int v) {
+  if (!f || a != hipFuncAttributeMaxDynamicSharedMemorySize || v < 0 || v > 160 * 1024) {
+    fprintf(stderr, "bad function attribute %d = %d\n", (int)a, v);
+    abort();
   }
   return hipSuccess;
 }
