@@ -442,6 +442,40 @@ def module_ops(d2ip, torch, att_shapes=((64, 16, 32), (32, 32, 64), (64, 64, 128
     return out
 
 
+def module_fit(d2ip, torch, ts, reps=20):
+    """The 3D-FastResUNet fitting iteration in one library call per k
+    iterations (d2ip_mnet_run) at the 32^3 / 928-measurement / 3-level /
+    16-channel workload: the plain network and each module mix, ms per
+    iteration after 3 warm-up iterations (HIP events on the context stream)."""
+    from paper_2507_14046_amd.context import ModuleFit
+    cfg = ts.CONFIGS["c1"]
+    p = ts.make_problem(cfg["n"], cfg["rings"], cfg["levels"], cfg["base_ch"], cfg["seed"])
+    mixes = {"plain": {}, "dwsep": dict(sep=True), "se": dict(se_ratio=4),
+             "attention+sigmoid": dict(att=True, tail="sigmoid"), "aspp": dict(aspp=True),
+             "all modules": dict(sep=True, se_ratio=4, att=True, tail="sigmoid", aspp=True)}
+    out = {}
+    for name, kw in mixes.items():
+        f = ModuleFit(cfg["n"], p["J"].shape[0], cfg["levels"], cfg["base_ch"], **kw)
+        rng = np.random.default_rng(7)
+        th = (0.1 * rng.standard_normal(f.n_params)).astype(np.float32)
+        f.set_problem(p["J"], p["mask"], p["Z"])
+        f.set_params(th)
+        f.set_frame(p["dv"][0])
+        f.set_adam(lr=cfg["lr"])
+        f.run(3)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(f.stream)
+        f.run(reps, sync=False)
+        e1.record(f.stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        out[name] = dict(ms_per_it=ms, it_per_s=1e3 / ms, params=f.n_params)
+        log("  module fit %-18s %8.3f ms/it  %7.1f it/s  (%d parameters)"
+            % (name, ms, 1e3 / ms, f.n_params))
+        f.close()
+    return out
+
+
 def dwsep_network(d2ip, torch, ts, names=("c1", "c2"), reps=10):
     """One loss + theta-gradient evaluation of the autograd network
     (`ops.DIPNet`, every operator on the library's kernels) with dense and
@@ -459,9 +493,10 @@ def dwsep_network(d2ip, torch, ts, names=("c1", "c2"), reps=10):
         Z, mask, J, dv = dev(p["Z"]), dev(p["mask"].astype(np.float32)), dev(p["J"]), \
             dev(p["dv"][0])
         row = {}
-        variants = {"dense": {}, "dwsep": dict(conv="dwsep"),
-                    "fastres_modules": dict(conv="dwsep", se_ratio=4, att=True, tail="sigmoid",
-                                            aspp=True)}
+        variants = {"dense": {}, "dwsep": dict(conv="dwsep")}
+        if c["base_ch"] << (c["levels"] - 2) <= 64:  # attention units up to 64 skip channels
+            variants["fastres_modules"] = dict(conv="dwsep", se_ratio=4, att=True,
+                                               tail="sigmoid", aspp=True)
         for conv, kw in variants.items():
             model = ops.DIPNet(c["n"], c["levels"], c["base_ch"], **kw)
             g = torch.Generator(device="cuda").manual_seed(11)
@@ -483,11 +518,13 @@ def dwsep_network(d2ip, torch, ts, names=("c1", "c2"), reps=10):
             row[conv] = dict(ms_per_loss_and_grad=e0.elapsed_time(e1) / reps, params=model.size)
         row["speedup"] = row["dense"]["ms_per_loss_and_grad"] / row["dwsep"]["ms_per_loss_and_grad"]
         out[name] = row
-        log("network %s: dense %.2f ms (%d params), dwsep %.2f ms (%d params), %.2fx; "
-            "dwsep + SE + ASPP + attention + sigmoid tail %.2f ms (%d params)"
+        log("network %s: dense %.2f ms (%d params), dwsep %.2f ms (%d params), %.2fx"
             % (name, row["dense"]["ms_per_loss_and_grad"], row["dense"]["params"],
-               row["dwsep"]["ms_per_loss_and_grad"], row["dwsep"]["params"], row["speedup"],
-               row["fastres_modules"]["ms_per_loss_and_grad"], row["fastres_modules"]["params"]))
+               row["dwsep"]["ms_per_loss_and_grad"], row["dwsep"]["params"], row["speedup"]))
+        if "fastres_modules" in row:
+            log("network %s: dwsep + SE + ASPP + attention + sigmoid tail %.2f ms (%d params)"
+                % (name, row["fastres_modules"]["ms_per_loss_and_grad"],
+                   row["fastres_modules"]["params"]))
     return out
 
 
@@ -786,7 +823,7 @@ def run_section(name, a):
         out = dict(dwsep=dwsep_ops(d2ip, torch), se=se_ops(d2ip, torch),
                    modules=module_ops(d2ip, torch))
     elif name == "network":
-        out = dwsep_network(d2ip, torch, ts)
+        out = dict(autograd=dwsep_network(d2ip, torch, ts), module_fit=module_fit(d2ip, torch, ts))
     elif name == "kernels64":
         out = {prec: kernels64(d2ip, at, ts, prec, torch, cache) for prec in a.forms.split(",")}
     elif name == "ablation":

@@ -243,6 +243,71 @@ d2ip_status d2ip_commit_frame(d2ip_ctx* ctx, int inst);
 /* Empty the temporal history of `inst` (a new sequence). */
 d2ip_status d2ip_clear_history(d2ip_ctx* ctx, int inst);
 
+/* ---- the 3D-FastResUNet fitting iteration (Sec. III-D) -------------------
+ * One instance of the fitting iteration with the paper's lightweight
+ * modules switched on individually: depthwise-separable ResBlock convs
+ * (sep), an SE unit after every encoder ResBlock (se_ratio r > 0: hidden
+ * width max(1, c / r)), an ASPP module at the bottleneck (aspp: a 1x1x1
+ * branch and depthwise-separable atrous branches at dilations 1, 2, 3,
+ * concatenated, projected, ReLU), attention units on the decoder skips
+ * (att: the gate formed on the coarser decoder output's grid, then
+ * interpolated) and the output head 2 sigmoid(t) - 1 (sigmoid_tail).  One
+ * iteration: the forward from the fixed noise input, p = J sigma (Eq. (2)),
+ * the data term (1/M) sum (p - dv)^2 reduced in FP64 and its gradient
+ * (Eq. (4)), J^T, the backward of every module and an Adam step (Eq. (5)).
+ * Every step runs the kernels of the standalone operators below; the
+ * iteration is FP32 throughout (FP64 in the loss reduction), eager launches
+ * on the caller's stream.
+ *
+ * theta's flat order: stem (W [C][1][3][3][3], b, gamma, beta); encoder
+ * modules 0 .. L-1 (conv1, norm1, conv2, norm2, projection when the
+ * channels change, then the SE unit's w1 [H][c], b1, w2 [c][H], b2); the
+ * ASPP module (w0 [c][c], b0, then per dilation dw [c][27], dwb, pw [c][c],
+ * pwb, then wp [c][4c], bp); decoder modules L-2 .. 0 (the ResBlock, then
+ * the attention unit's wx [c][c], wg [c][c_up], b [c], psi [c], bpsi [1]);
+ * head w [C], b.  A separable conv is dw [Cin][27], dwb, pw [Cout][Cin],
+ * pwb in place of W, b.  J is M x n^3 row-major FP32 (the full grid),
+ * mask n^3 bytes (0 outside), z the n^3 noise input.
+ *
+ * Limits: levels 2..5, base_ch 8, 16 or 32, base_ch 2^(levels-1) <= 256, n a
+ * multiple of 2^(levels-1) with n / 2^(levels-1) >= 2 and n <= 128; with
+ * att the skip channels must stay <= 64 and the gating channels <= 128.
+ * The workspace (256-byte aligned, d2ip_mnet_workspace_bytes) holds J,
+ * every activation, gradients, Adam moments and the operators' scratch; the
+ * context keeps pointers into it until d2ip_mnet_destroy, which waits for
+ * the stream.  Host inputs are copied before the call returns. */
+typedef struct d2ip_mnet d2ip_mnet;
+
+typedef struct {
+  int n, M, levels, base_ch;
+  int sep, se_ratio, att, sigmoid_tail, aspp;
+} d2ip_mnet_desc;
+
+d2ip_status d2ip_mnet_param_count(const d2ip_mnet_desc* desc, size_t* out);
+d2ip_status d2ip_mnet_workspace_bytes(const d2ip_mnet_desc* desc, size_t* out);
+d2ip_status d2ip_mnet_create(const d2ip_mnet_desc* desc, void* workspace, size_t bytes,
+                             void* hip_stream, d2ip_mnet** out);
+d2ip_status d2ip_mnet_destroy(d2ip_mnet* net);
+/* J [M][n^3] FP32, mask [n^3] bytes, z [n^3] FP32: host or device memory. */
+d2ip_status d2ip_mnet_set_problem(d2ip_mnet* net, const float* J, const uint8_t* mask,
+                                  const float* z, int on_device);
+/* theta in the flat order above (n must equal d2ip_mnet_param_count); also
+ * restarts Adam (moments and step count). */
+d2ip_status d2ip_mnet_set_params(d2ip_mnet* net, const float* theta, size_t n, int on_device);
+d2ip_status d2ip_mnet_get_params(d2ip_mnet* net, float* theta, size_t n, int on_device);
+/* dL/dtheta of the last iteration, at the parameters it started from. */
+d2ip_status d2ip_mnet_get_grad(d2ip_mnet* net, float* grad, size_t n, int on_device);
+/* The frame's measured voltage differences dv [M]; theta is kept (Eq. (9)). */
+d2ip_status d2ip_mnet_set_frame(d2ip_mnet* net, const float* dv, int on_device);
+d2ip_status d2ip_mnet_set_adam(d2ip_mnet* net, const d2ip_adam_cfg* cfg);
+d2ip_status d2ip_mnet_reset_optimizer(d2ip_mnet* net);
+/* k iterations; with last_loss the call waits and returns the last
+ * iteration's loss (at the parameters before its update), and reports
+ * D2IP_ENONFINITE if a loss or parameter was not finite. */
+d2ip_status d2ip_mnet_run(d2ip_mnet* net, int k, double* last_loss);
+/* sigma = mask * phi(theta | z) at the current theta (n^3 values). */
+d2ip_status d2ip_mnet_read_image(d2ip_mnet* net, float* sigma, int on_device);
+
 /* ---- launch shapes of the convolutions (for autotuning) ----------------
  * Every 3x3x3 / 1x1x1 convolution of the network (Eq. (3): the prior phi is
  * built from them) runs three passes: 0 forward, 1 input gradient, 2 weight

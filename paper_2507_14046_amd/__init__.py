@@ -11,6 +11,6 @@ built: there is no other execution path.
 from . import _lib
 from ._lib import D2ipError, LIB_PATH
 from ._lib import load
-from .context import Context, check_launches, param_count, workspace_bytes
+from .context import Context, ModuleFit, check_launches, module_param_count, param_count, workspace_bytes
 
-__all__ = ["Context", "check_launches", "param_count", "workspace_bytes", "D2ipError", "LIB_PATH", "load"]
+__all__ = ["Context", "ModuleFit", "module_param_count", "check_launches", "param_count", "workspace_bytes", "D2ipError", "LIB_PATH", "load"]

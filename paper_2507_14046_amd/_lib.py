@@ -24,6 +24,12 @@ class InstanceDesc(ctypes.Structure):
     _fields_ = [("geometry", ctypes.c_int), ("levels", ctypes.c_int), ("base_ch", ctypes.c_int)]
 
 
+class MnetDesc(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int), ("M", ctypes.c_int), ("levels", ctypes.c_int),
+                ("base_ch", ctypes.c_int), ("sep", ctypes.c_int), ("se_ratio", ctypes.c_int),
+                ("att", ctypes.c_int), ("sigmoid_tail", ctypes.c_int), ("aspp", ctypes.c_int)]
+
+
 class AdamCfg(ctypes.Structure):
     _fields_ = [("lr", ctypes.c_float), ("beta1", ctypes.c_float), ("beta2", ctypes.c_float),
                 ("eps", ctypes.c_float)]
@@ -125,6 +131,19 @@ SIGNATURES = {
     "d2ip_op_channel_copy": [_vp, _i, _i, _vp, _i, _i, _i, ctypes.c_size_t, _vp],
     "d2ip_op_relu_forward": [_vp, _vp, ctypes.c_size_t, _vp],
     "d2ip_op_relu_backward": [_vp, _vp, _vp, ctypes.c_size_t, _vp],
+    "d2ip_mnet_param_count": [ctypes.POINTER(MnetDesc), _c_size_p],
+    "d2ip_mnet_workspace_bytes": [ctypes.POINTER(MnetDesc), _c_size_p],
+    "d2ip_mnet_create": [ctypes.POINTER(MnetDesc), _vp, ctypes.c_size_t, _vp, ctypes.POINTER(_vp)],
+    "d2ip_mnet_destroy": [_vp],
+    "d2ip_mnet_set_problem": [_vp, _vp, _vp, _vp, _i],
+    "d2ip_mnet_set_params": [_vp, _vp, ctypes.c_size_t, _i],
+    "d2ip_mnet_get_params": [_vp, _vp, ctypes.c_size_t, _i],
+    "d2ip_mnet_get_grad": [_vp, _vp, ctypes.c_size_t, _i],
+    "d2ip_mnet_set_frame": [_vp, _vp, _i],
+    "d2ip_mnet_set_adam": [_vp, ctypes.POINTER(AdamCfg)],
+    "d2ip_mnet_reset_optimizer": [_vp],
+    "d2ip_mnet_run": [_vp, _i, ctypes.POINTER(ctypes.c_double)],
+    "d2ip_mnet_read_image": [_vp, _vp, _i],
     "d2ip_op_head_bytes": [_i, _i, _c_size_p],
     "d2ip_op_head_forward": [_vp, _vp, _vp, _vp, _vp, _i, _i, _i, _vp],
     "d2ip_op_head_backward": [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _i, _i, _i, _vp,

@@ -18,7 +18,8 @@ CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libd2ip.so")
 SOURCES = ["engine.hip", "conv.hip", "conv_f32.hip", "conv_bf16.hip", "conv_bf16x3.hip",
-           "norm.hip", "jops.hip", "ops.hip", "dwconv.hip", "pwconv.hip", "se.hip", "modules.hip"]
+           "norm.hip", "jops.hip", "ops.hip", "dwconv.hip", "pwconv.hip", "se.hip", "modules.hip",
+           "mnet.hip"]
 ARCH = "gfx950"
 
 

@@ -236,3 +236,111 @@ class Context:
         self.set_params(inst, prob["theta0"])
         self.set_noise_input(inst, prob["Z"])
         self.set_frame(inst, prob["dv"][frame])
+
+
+def _mnet_desc(n, M, levels, base_ch, sep=False, se_ratio=0, att=False, tail="linear",
+               aspp=False):
+    if tail not in ("linear", "sigmoid"):
+        raise ValueError("tail must be 'linear' or 'sigmoid'")
+    return L.MnetDesc(int(n), int(M), int(levels), int(base_ch), int(bool(sep)), int(se_ratio),
+                      int(bool(att)), int(tail == "sigmoid"), int(bool(aspp)))
+
+
+def module_param_count(levels, base_ch, sep=False, se_ratio=0, att=False, aspp=False, n=None):
+    """Parameters of the 3D-FastResUNet variant (the grid does not matter)."""
+    lib = L.load()
+    d = _mnet_desc(n or (4 << levels), 1, levels, base_ch, sep, se_ratio, att, "linear", aspp)
+    out = ctypes.c_size_t()
+    L.check(lib.d2ip_mnet_param_count(ctypes.byref(d), ctypes.byref(out)))
+    return out.value
+
+
+class ModuleFit:
+    """The fitting iteration of one instance of the 3D-FastResUNet variants
+    (any mix of depthwise-separable convs, SE units, ASPP, attention units and
+    the sigmoid tail) in the library; see d2ip_mnet_* in include/d2ip.h."""
+
+    def __init__(self, n, M, levels, base_ch, sep=False, se_ratio=0, att=False, tail="linear",
+                 aspp=False, device=0, stream=None):
+        import torch
+        self._lib = L.load()
+        self.n, self.M = int(n), int(M)
+        self.desc = _mnet_desc(n, M, levels, base_ch, sep, se_ratio, att, tail, aspp)
+        out = ctypes.c_size_t()
+        L.check(self._lib.d2ip_mnet_workspace_bytes(ctypes.byref(self.desc), ctypes.byref(out)))
+        self.device = torch.device("cuda", device) if isinstance(device, int) else torch.device(device)
+        self.workspace = torch.empty(out.value, dtype=torch.uint8, device=self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        h = ctypes.c_void_p()
+        L.check(self._lib.d2ip_mnet_create(ctypes.byref(self.desc),
+                                           ctypes.c_void_p(self.workspace.data_ptr()), out.value,
+                                           ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)))
+        self._h = h
+        pc = ctypes.c_size_t()
+        L.check(self._lib.d2ip_mnet_param_count(ctypes.byref(self.desc), ctypes.byref(pc)))
+        self.n_params = pc.value
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.d2ip_mnet_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def set_problem(self, J, mask, z):
+        jp, jd, _k1 = _in(J, np.float32)
+        mp, md, _k2 = _in(mask, np.uint8)
+        zp, zd, _k3 = _in(z, np.float32)
+        if not (jd == md == zd):
+            raise ValueError("J, mask and z must all be host arrays or all device tensors")
+        L.check(self._lib.d2ip_mnet_set_problem(self._h, jp, mp, zp, jd))
+
+    def set_params(self, theta):
+        p, d, _k = _in(theta, np.float32)
+        L.check(self._lib.d2ip_mnet_set_params(self._h, p, self.n_params, d))
+
+    def set_frame(self, dv):
+        p, d, _k = _in(dv, np.float32)
+        L.check(self._lib.d2ip_mnet_set_frame(self._h, p, d))
+
+    def set_adam(self, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+        cfg = L.AdamCfg(lr, beta1, beta2, eps)
+        L.check(self._lib.d2ip_mnet_set_adam(self._h, ctypes.byref(cfg)))
+
+    def reset_optimizer(self):
+        L.check(self._lib.d2ip_mnet_reset_optimizer(self._h))
+
+    def run(self, k, sync=True):
+        if not sync:
+            L.check(self._lib.d2ip_mnet_run(self._h, int(k), None))
+            return None
+        out = ctypes.c_double()
+        L.check(self._lib.d2ip_mnet_run(self._h, int(k), ctypes.byref(out)))
+        return out.value
+
+    def get_params(self):
+        out = np.empty(self.n_params, dtype=np.float32)
+        L.check(self._lib.d2ip_mnet_get_params(self._h, out.ctypes.data_as(ctypes.c_void_p),
+                                               out.size, 0))
+        return out
+
+    def get_grad(self):
+        out = np.empty(self.n_params, dtype=np.float32)
+        L.check(self._lib.d2ip_mnet_get_grad(self._h, out.ctypes.data_as(ctypes.c_void_p),
+                                             out.size, 0))
+        return out
+
+    def read_image(self):
+        img = np.empty(self.n ** 3, dtype=np.float32)
+        L.check(self._lib.d2ip_mnet_read_image(self._h, img.ctypes.data_as(ctypes.c_void_p), 0))
+        return img

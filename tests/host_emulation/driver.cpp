@@ -480,6 +480,48 @@ static int bench_sequence(bool large) {
   return 0;
 }
 
+// The module-network context (every module mix) on host-emulated buffers.
+static int mnet_case() {
+  const int n = 8, M = 40;
+  const size_t Q = (size_t)n * n * n;
+  std::vector<float> J((size_t)M * Q, 0.01f), z(Q, 0.5f), dv(M, 0.1f), img(Q);
+  std::vector<uint8_t> mask(Q, 1);
+  int mixes[][5] = {{0, 0, 0, 0, 0}, {1, 0, 0, 0, 0}, {0, 4, 0, 0, 0}, {0, 0, 1, 1, 0},
+                    {0, 0, 0, 0, 1}, {1, 4, 1, 1, 1}};
+  for (auto& mx : mixes)
+    for (int levels : {2, 3}) {
+      d2ip_mnet_desc d{n, M, levels, 8, mx[0], mx[1], mx[2], mx[3], mx[4]};
+      size_t bytes = 0, P = 0;
+      CK(d2ip_mnet_workspace_bytes(&d, &bytes));
+      CK(d2ip_mnet_param_count(&d, &P));
+      char* ws = (char*)aligned_alloc(256, (bytes + 255) / 256 * 256);
+      d2ip_mnet* net = nullptr;
+      EXPECT_ERR(d2ip_mnet_create(&d, ws, bytes - 1, nullptr, &net), D2IP_ENOMEM);
+      CK(d2ip_mnet_create(&d, ws, bytes, nullptr, &net));
+      EXPECT_ERR(d2ip_mnet_run(net, 1, nullptr), D2IP_ESTATE);
+      std::vector<float> th(P, 0.01f), g(P);
+      CK(d2ip_mnet_set_problem(net, J.data(), mask.data(), z.data(), 0));
+      CK(d2ip_mnet_set_params(net, th.data(), P, 0));
+      EXPECT_ERR(d2ip_mnet_set_params(net, th.data(), P + 1, 0), D2IP_EINVAL);
+      CK(d2ip_mnet_set_frame(net, dv.data(), 0));
+      d2ip_adam_cfg cfg{1e-3f, 0.9f, 0.999f, 1e-8f};
+      CK(d2ip_mnet_set_adam(net, &cfg));
+      double loss = -1.0;
+      CK(d2ip_mnet_run(net, 2, &loss));
+      CK(d2ip_mnet_get_params(net, th.data(), P, 0));
+      CK(d2ip_mnet_get_grad(net, g.data(), P, 0));
+      CK(d2ip_mnet_read_image(net, img.data(), 0));
+      CK(d2ip_mnet_set_frame(net, dv.data(), 0));
+      CK(d2ip_mnet_reset_optimizer(net));
+      CK(d2ip_mnet_run(net, 1, nullptr));
+      CK(d2ip_mnet_destroy(net));
+      emu_flush_all();
+      free(ws);
+    }
+  printf("ok: module networks\n");
+  return 0;
+}
+
 int main(int argc, char** argv) {
   if (argc > 1 && std::string(argv[1]) == "bench") {
     int bad = bench_sequence(argc > 2 && std::string(argv[2]) == "large");
@@ -488,7 +530,7 @@ int main(int argc, char** argv) {
            g_captured_launches, emu_errors());
     return bad || emu_errors() != 0;
   }
-  int bad = tuning_case() | ops_case();
+  int bad = tuning_case() | ops_case() | mnet_case();
   for (int prec = 0; prec < 3; ++prec)
     for (unsigned fl = 0; fl < 2; ++fl) {
       bad |= run_case({{16, 928}}, {{0, 3, 8}, {0, 3, 8}, {0, 3, 8}}, prec, fl);

@@ -385,3 +385,44 @@ def test_runtime_versions_are_reported(L):
     compiled, loaded = runtime_versions()
     assert compiled >= 70000000  # ROCm 7 headers
     assert loaded >= 0
+
+
+MODULE_MIXES = [dict(), dict(sep=True), dict(se_ratio=4), dict(att=True), dict(aspp=True),
+                dict(sep=True, se_ratio=4, att=True, aspp=True)]
+
+
+@pytest.mark.parametrize("kw", MODULE_MIXES)
+@pytest.mark.parametrize("L_,C", [(2, 8), (3, 16), (4, 16)])
+def test_module_network_layout_matches_the_canonical_order(L, L_, C, kw):
+    """d2ip_mnet_param_count equals the flat layout the autograd network and
+    the oracle use, for every module mix (host only)."""
+    import numpy as np
+    from oracle import net
+    from paper_2507_14046_amd import ops
+    from paper_2507_14046_amd.context import module_param_count
+    want = int(sum(np.prod(s) for _, s in ops.param_shapes(L_, C, **kw)))
+    assert module_param_count(L_, C, **kw) == want
+    assert net.n_params(L_, C, kw.get("sep", False), kw.get("se_ratio", 0), kw.get("att", False),
+                        kw.get("aspp", False)) == want
+
+
+def test_module_network_validates_its_description(L):
+    """Bad descriptions and short or misaligned workspaces are rejected by
+    host checks before anything touches the device."""
+    lib = L.load()
+    sz = ctypes.c_size_t()
+    ok = L.MnetDesc(16, 208, 3, 8, 1, 4, 1, 1, 1)
+    assert lib.d2ip_mnet_workspace_bytes(ctypes.byref(ok), ctypes.byref(sz)) == L.OK
+    assert sz.value > 208 * 16 ** 3 * 4
+    for bad in (L.MnetDesc(16, 208, 1, 8, 0, 0, 0, 0, 0), L.MnetDesc(16, 208, 3, 12, 0, 0, 0, 0, 0),
+                L.MnetDesc(6, 208, 3, 8, 0, 0, 0, 0, 0), L.MnetDesc(16, 0, 3, 8, 0, 0, 0, 0, 0),
+                L.MnetDesc(16, 208, 3, 8, 0, -1, 0, 0, 0),
+                L.MnetDesc(64, 208, 4, 32, 0, 0, 1, 0, 0)):  # attention skip of 128 channels
+        assert lib.d2ip_mnet_workspace_bytes(ctypes.byref(bad), ctypes.byref(sz)) == L.EINVAL
+    h = ctypes.c_void_p()
+    assert lib.d2ip_mnet_create(ctypes.byref(ok), ctypes.c_void_p(4096), 1024, None,
+                                ctypes.byref(h)) == L.ENOMEM
+    assert lib.d2ip_mnet_create(ctypes.byref(ok), ctypes.c_void_p(4100), 1 << 40, None,
+                                ctypes.byref(h)) == L.EINVAL
+    assert lib.d2ip_mnet_run(None, 1, None) == L.EINVAL
+    assert lib.d2ip_mnet_destroy(None) == L.OK

@@ -1,0 +1,150 @@
+"""GPU tests of the 3D-FastResUNet fitting iteration in one library call
+(d2ip_mnet_*): every module mix against the FP64 oracle network of the same
+layout (one iteration's loss and theta gradient, element by element, and
+short Adam trajectories against the oracle's own 1-ulp floor), bitwise
+repeatability, and a frame transition that keeps theta."""
+import numpy as np
+import pytest
+
+from tests.gpu_util import elementwise, problem, record, rel
+
+pytestmark = pytest.mark.gpu
+
+MIXES = [dict(), dict(sep=True), dict(se_ratio=4), dict(att=True), dict(tail="sigmoid"),
+         dict(aspp=True), dict(sep=True, se_ratio=4, att=True, tail="sigmoid", aspp=True)]
+
+
+def _fit(lib, p, kw, th, lr=1e-3):
+    from paper_2507_14046_amd.context import ModuleFit
+    f = ModuleFit(p["n"], p["J"].shape[0], p["levels"], p["base_ch"], **kw)
+    f.set_problem(p["J"], p["mask"], p["Z"])
+    f.set_params(th)
+    f.set_frame(p["dv"][0])
+    f.set_adam(lr=lr)
+    return f
+
+
+def _oracle(p, kw):
+    from oracle import fit
+    return fit.Problem(p["J"], p["mask"], p["Z"], p["n"], p["levels"], p["base_ch"],
+                       sep=kw.get("sep", False), se_ratio=kw.get("se_ratio", 0),
+                       att=kw.get("att", False), tail=kw.get("tail", "linear"),
+                       aspp=kw.get("aspp", False))
+
+
+def _theta(p, kw, seed):
+    from oracle import net
+    P = net.n_params(p["levels"], p["base_ch"], kw.get("sep", False), kw.get("se_ratio", 0),
+                     kw.get("att", False), kw.get("aspp", False))
+    rng = np.random.default_rng(seed)
+    return (0.3 * rng.standard_normal(P)).astype(np.float32)
+
+
+@pytest.mark.parametrize("kw", MIXES, ids=lambda k: "-".join("%s=%s" % i for i in k.items()) or "plain")
+@pytest.mark.parametrize("shape", [(16, 2, 3, 8), (32, 2, 3, 16)])
+def test_one_iteration_matches_oracle(lib, shape, kw):
+    """Loss (FP64 reduction) and theta gradient of one library iteration
+    against the FP64 oracle network of the same layout: loss within 5e-6,
+    relative L2 of the gradient within 5e-6 and every value within 2e-5 of
+    its vector's scale (FP32 against FP64 over products of up to 27 x 3c
+    terms and voxel sums of up to 32^3 terms; measured 1.6-7.9e-7 and
+    1e-6 of the scale)."""
+    n, rings, L, C = shape
+    p = problem(n, rings, L, C, 300 + n + L)
+    th = _theta(p, kw, 17 + n)
+    f = _fit(lib, p, kw, th)
+    loss = f.run(1)
+    g = f.get_grad()
+    f.close()
+    L0, gref, img = _oracle(p, kw).loss_and_grad(th.astype(np.float64),
+                                                 p["dv"][0].astype(np.float64))
+    e = dict(loss=abs(loss - L0) / L0, grad=rel(g, gref), grad_elem=elementwise(g, gref, 2e-5))
+    record("mnet_one_iteration", n=n, levels=L, C=C, **{k: str(v) for k, v in kw.items()}, **e)
+    assert e["loss"] < 5e-6 and e["grad"] < 5e-6 and e["grad_elem"] <= 1.0, e
+
+
+def test_image_and_theta_readback(lib):
+    """read_image returns mask * phi(theta | z) at the current theta and
+    get_params the parameters after the steps taken (against the oracle's
+    image at those parameters)."""
+    kw = dict(sep=True, se_ratio=4, att=True, tail="sigmoid", aspp=True)
+    p = problem(16, 2, 3, 8, 333)
+    th = _theta(p, kw, 5)
+    f = _fit(lib, p, kw, th)
+    np.testing.assert_array_equal(f.get_params(), th)
+    img0 = f.read_image()
+    f.run(2)
+    th2 = f.get_params()
+    img2 = f.read_image()
+    f.close()
+    pr = _oracle(p, kw)
+    e = dict(img0=rel(img0, pr.image(th.astype(np.float64))),
+             img2=rel(img2, pr.image(th2.astype(np.float64))))
+    record("mnet_readback", **e)
+    assert e["img0"] < 1e-5 and e["img2"] < 1e-5, e
+    assert not np.array_equal(th2, th)
+
+
+@pytest.mark.parametrize("kw", [dict(), dict(sep=True, se_ratio=4, att=True, tail="sigmoid",
+                                                aspp=True)], ids=["plain", "all-modules"])
+def test_trajectory_against_oracle_floor(lib, kw):
+    """Five Adam iterations: the image after each within max(1e-5, 3 x the
+    oracle's distance from itself when theta_0 is moved by one ulp), the
+    reading used for every FP32 trajectory (Adam's first step moves each
+    parameter by +-lr whatever the size of its gradient, so trajectories are
+    compared against the oracle's own sensitivity)."""
+    from oracle import fit
+    p = problem(16, 2, 3, 8, 350)
+    th = _theta(p, kw, 23)
+    pr = _oracle(p, kw)
+    dv = p["dv"][0].astype(np.float64)
+
+    def oracle_run(t0, k):
+        st = fit.State(t0)
+        out = []
+        for _ in range(k):
+            _, g, _ = pr.loss_and_grad(st.theta, dv)
+            st.theta, st.m, st.v, st.t = fit.adam_step(st.theta, g, st.m, st.v, st.t, 1e-3)
+            out.append(pr.image(st.theta))
+        return out
+
+    t0 = th.astype(np.float64)
+    ref = oracle_run(t0, 5)
+    flo = oracle_run(np.nextafter(th, np.float32(np.inf)).astype(np.float64), 5)
+    f = _fit(lib, p, kw, th)
+    errs, floors = [], []
+    for k in range(5):
+        f.run(1)
+        errs.append(rel(f.read_image(), ref[k]))
+        floors.append(rel(flo[k], ref[k]))
+    f.close()
+    record("mnet_trajectory", mix=str(kw), errs=errs, floors=floors)
+    for k in range(5):
+        assert errs[k] <= max(1e-5, 3 * floors[k]), (k, errs, floors)
+
+
+def test_bitwise_repeatable_and_frames_keep_theta(lib):
+    """Two contexts on the same inputs give the same bits after several
+    iterations (every sum has a fixed order); a new frame keeps theta and
+    restarts Adam (Eq. (9)), so frame 2 from the carried theta equals a fresh
+    context started from that theta."""
+    kw = dict(sep=True, se_ratio=4, att=True, tail="sigmoid", aspp=True)
+    p = problem(16, 2, 3, 8, 360, frames=2, breathing=True)
+    th = _theta(p, kw, 31)
+    a, b = _fit(lib, p, kw, th), _fit(lib, p, kw, th)
+    la, lb = a.run(3), b.run(3)
+    assert la == lb
+    np.testing.assert_array_equal(a.get_params(), b.get_params())
+    np.testing.assert_array_equal(a.get_grad(), b.get_grad())
+    th1 = a.get_params()
+    a.set_frame(p["dv"][1])
+    a.reset_optimizer()
+    np.testing.assert_array_equal(a.get_params(), th1)
+    a.run(2)
+    c = _fit(lib, p, kw, th1)
+    c.set_frame(p["dv"][1])
+    c.run(2)
+    np.testing.assert_array_equal(a.get_params(), c.get_params())
+    np.testing.assert_array_equal(a.read_image(), c.read_image())
+    for x in (a, b, c):
+        x.close()

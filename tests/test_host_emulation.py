@@ -20,7 +20,7 @@ import pytest
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 CSRC = os.path.join(ROOT, "paper_2507_14046_amd", "csrc")
 HERE = os.path.join(ROOT, "tests", "host_emulation")
-SOURCES = ["engine", "conv", "conv_f32", "conv_bf16", "conv_bf16x3", "norm", "jops", "ops", "dwconv", "pwconv", "se", "modules"]
+SOURCES = ["engine", "conv", "conv_f32", "conv_bf16", "conv_bf16x3", "norm", "jops", "ops", "dwconv", "pwconv", "se", "modules", "mnet"]
 HIPCC = "/opt/rocm/bin/hipcc"
 
 
@@ -53,7 +53,7 @@ def test_host_logic_under_address_sanitizer(tmp_path):
                ASAN_OPTIONS="detect_leaks=1:detect_stack_use_after_return=1:abort_on_error=0")
     r = subprocess.run([exe], capture_output=True, text=True, env=env, timeout=600)
     assert r.returncode == 0, (r.stdout[-3000:], r.stderr[-5000:])
-    assert r.stdout.count("ok:") == 20
+    assert r.stdout.count("ok:") == 21
     assert "emulation errors: 0" in r.stdout
     r = subprocess.run([exe, "bench"], capture_output=True, text=True, env=env, timeout=900)
     assert r.returncode == 0, (r.stdout[-3000:], r.stderr[-5000:])
