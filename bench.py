@@ -455,24 +455,29 @@ def module_fit(d2ip, torch, ts, reps=20):
              "all modules": dict(sep=True, se_ratio=4, att=True, tail="sigmoid", aspp=True)}
     out = {}
     for name, kw in mixes.items():
-        f = ModuleFit(cfg["n"], p["J"].shape[0], cfg["levels"], cfg["base_ch"], **kw)
-        rng = np.random.default_rng(7)
-        th = (0.1 * rng.standard_normal(f.n_params)).astype(np.float32)
-        f.set_problem(p["J"], p["mask"], p["Z"])
-        f.set_params(th)
-        f.set_frame(p["dv"][0])
-        f.set_adam(lr=cfg["lr"])
-        f.run(3)
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record(f.stream)
-        f.run(reps, sync=False)
-        e1.record(f.stream)
-        torch.cuda.synchronize()
-        ms = e0.elapsed_time(e1) / reps
-        out[name] = dict(ms_per_it=ms, it_per_s=1e3 / ms, params=f.n_params)
-        log("  module fit %-18s %8.3f ms/it  %7.1f it/s  (%d parameters)"
-            % (name, ms, 1e3 / ms, f.n_params))
-        f.close()
+        row = {}
+        for graph in (False, True):
+            f = ModuleFit(cfg["n"], p["J"].shape[0], cfg["levels"], cfg["base_ch"], graph=graph,
+                          **kw)
+            rng = np.random.default_rng(7)
+            th = (0.1 * rng.standard_normal(f.n_params)).astype(np.float32)
+            f.set_problem(p["J"], p["mask"], p["Z"])
+            f.set_params(th)
+            f.set_frame(p["dv"][0])
+            f.set_adam(lr=cfg["lr"])
+            f.run(3)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(f.stream)
+            f.run(reps, sync=False)
+            e1.record(f.stream)
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / reps
+            row["graph" if graph else "eager"] = dict(ms_per_it=ms, it_per_s=1e3 / ms)
+            row["params"] = f.n_params
+            f.close()
+        out[name] = row
+        log("  module fit %-18s eager %7.3f ms/it, graph %7.3f ms/it  (%d parameters)"
+            % (name, row["eager"]["ms_per_it"], row["graph"]["ms_per_it"], row["params"]))
     return out
 
 

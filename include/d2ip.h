@@ -278,9 +278,14 @@ d2ip_status d2ip_clear_history(d2ip_ctx* ctx, int inst);
  * the stream.  Host inputs are copied before the call returns. */
 typedef struct d2ip_mnet d2ip_mnet;
 
+/* graph != 0: the first d2ip_mnet_run captures one iteration in a hipGraph
+ * (on a stream of the context's own) and every iteration replays it on the
+ * caller's stream; d2ip_mnet_set_adam discards the graph (its Adam step holds
+ * the hyper-parameters), the next run captures again. */
 typedef struct {
   int n, M, levels, base_ch;
   int sep, se_ratio, att, sigmoid_tail, aspp;
+  int graph;
 } d2ip_mnet_desc;
 
 d2ip_status d2ip_mnet_param_count(const d2ip_mnet_desc* desc, size_t* out);

@@ -27,7 +27,8 @@ class InstanceDesc(ctypes.Structure):
 class MnetDesc(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int), ("M", ctypes.c_int), ("levels", ctypes.c_int),
                 ("base_ch", ctypes.c_int), ("sep", ctypes.c_int), ("se_ratio", ctypes.c_int),
-                ("att", ctypes.c_int), ("sigmoid_tail", ctypes.c_int), ("aspp", ctypes.c_int)]
+                ("att", ctypes.c_int), ("sigmoid_tail", ctypes.c_int), ("aspp", ctypes.c_int),
+                ("graph", ctypes.c_int)]
 
 
 class AdamCfg(ctypes.Structure):

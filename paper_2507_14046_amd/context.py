@@ -239,11 +239,11 @@ class Context:
 
 
 def _mnet_desc(n, M, levels, base_ch, sep=False, se_ratio=0, att=False, tail="linear",
-               aspp=False):
+               aspp=False, graph=False):
     if tail not in ("linear", "sigmoid"):
         raise ValueError("tail must be 'linear' or 'sigmoid'")
     return L.MnetDesc(int(n), int(M), int(levels), int(base_ch), int(bool(sep)), int(se_ratio),
-                      int(bool(att)), int(tail == "sigmoid"), int(bool(aspp)))
+                      int(bool(att)), int(tail == "sigmoid"), int(bool(aspp)), int(bool(graph)))
 
 
 def module_param_count(levels, base_ch, sep=False, se_ratio=0, att=False, aspp=False, n=None):
@@ -261,11 +261,11 @@ class ModuleFit:
     the sigmoid tail) in the library; see d2ip_mnet_* in include/d2ip.h."""
 
     def __init__(self, n, M, levels, base_ch, sep=False, se_ratio=0, att=False, tail="linear",
-                 aspp=False, device=0, stream=None):
+                 aspp=False, graph=False, device=0, stream=None):
         import torch
         self._lib = L.load()
         self.n, self.M = int(n), int(M)
-        self.desc = _mnet_desc(n, M, levels, base_ch, sep, se_ratio, att, tail, aspp)
+        self.desc = _mnet_desc(n, M, levels, base_ch, sep, se_ratio, att, tail, aspp, graph)
         out = ctypes.c_size_t()
         L.check(self._lib.d2ip_mnet_workspace_bytes(ctypes.byref(self.desc), ctypes.byref(out)))
         self.device = torch.device("cuda", device) if isinstance(device, int) else torch.device(device)

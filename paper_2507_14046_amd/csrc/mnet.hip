@@ -203,6 +203,10 @@ struct d2ip_mnet {
   float lr = 1e-3f, b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
   bool has_problem = false, has_frame = false;
   hipStream_t stream = nullptr;
+  // graph form: one iteration captured on `cap`, replayed on `stream`
+  hipStream_t cap = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
 };
 
 namespace {
@@ -719,6 +723,41 @@ d2ip_status total_bytes(d2ip_mnet& N, size_t* out) {
   return D2IP_OK;
 }
 
+void drop_graph(d2ip_mnet& N) {
+  if (N.gexec) (void)hipGraphExecDestroy(N.gexec);
+  if (N.graph) (void)hipGraphDestroy(N.graph);
+  N.gexec = nullptr;
+  N.graph = nullptr;
+}
+
+// Records one iteration on the capture stream (every operator's launches and
+// copies; none allocates, fills with memset or synchronises) and instantiates it.
+d2ip_status capture(d2ip_mnet& N) {
+  hipStream_t user = N.stream;
+  N.stream = N.cap;
+  hipError_t e = hipStreamBeginCapture(N.cap, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) {
+    N.stream = user;
+    return api_fail(D2IP_EHIP, std::string("graph capture: ") + hipGetErrorString(e));
+  }
+  const d2ip_status st = iteration(N);
+  hipGraph_t g = nullptr;
+  e = hipStreamEndCapture(N.cap, &g);
+  N.stream = user;
+  if (st != D2IP_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    return st;
+  }
+  if (e != hipSuccess) return api_fail(D2IP_EHIP, std::string("graph capture: ") + hipGetErrorString(e));
+  N.graph = g;
+  e = hipGraphInstantiate(&N.gexec, N.graph, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    drop_graph(N);
+    return api_fail(D2IP_EHIP, std::string("graph instantiate: ") + hipGetErrorString(e));
+  }
+  return D2IP_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -762,6 +801,10 @@ d2ip_status d2ip_mnet_create(const d2ip_mnet_desc* desc, void* workspace, size_t
     return st;
   }
   N->stream = reinterpret_cast<hipStream_t>(hip_stream);
+  if (desc->graph && hipStreamCreateWithFlags(&N->cap, hipStreamNonBlocking) != hipSuccess) {
+    delete N;
+    return api_fail(D2IP_EHIP, "capture stream");
+  }
   Carve cv;
   cv.base = reinterpret_cast<char*>(workspace);
   carve(*N, cv);
@@ -774,6 +817,7 @@ d2ip_status d2ip_mnet_create(const d2ip_mnet_desc* desc, void* workspace, size_t
   st = copy_in(N->segs, N->lay.segs.data(), N->lay.segs.size() * sizeof(Seg), 0, N->stream);
   if (st == D2IP_OK && hipGetLastError() != hipSuccess) st = api_fail(D2IP_EHIP, "setup launch");
   if (st != D2IP_OK) {
+    if (N->cap) (void)hipStreamDestroy(N->cap);
     delete N;
     return st;
   }
@@ -784,6 +828,8 @@ d2ip_status d2ip_mnet_create(const d2ip_mnet_desc* desc, void* workspace, size_t
 d2ip_status d2ip_mnet_destroy(d2ip_mnet* N) {
   if (!N) return D2IP_OK;
   const hipError_t e = hipStreamSynchronize(N->stream);  // nothing may still use the workspace
+  drop_graph(*N);
+  if (N->cap) (void)hipStreamDestroy(N->cap);
   delete N;
   if (e != hipSuccess) return api_fail(D2IP_EHIP, std::string("destroy: ") + hipGetErrorString(e));
   return D2IP_OK;
@@ -852,6 +898,7 @@ d2ip_status d2ip_mnet_set_adam(d2ip_mnet* N, const d2ip_adam_cfg* cfg) {
   N->b1 = cfg->beta1;
   N->b2 = cfg->beta2;
   N->eps = cfg->eps;
+  drop_graph(*N);  // the captured Adam step holds the old values
   return D2IP_OK;
 }
 
@@ -869,7 +916,12 @@ d2ip_status d2ip_mnet_run(d2ip_mnet* N, int k, double* last_loss) {
   if (k < 0) return api_fail(D2IP_EINVAL, "k must be >= 0");
   if (!N->has_problem) return api_fail(D2IP_ESTATE, "problem (J, mask, noise input) not set");
   if (!N->has_frame) return api_fail(D2IP_ESTATE, "frame not set");
-  for (int i = 0; i < k; ++i) MNOK(iteration(*N));
+  if (k > 0 && N->d.graph) {
+    if (!N->gexec) MNOK(capture(*N));
+    for (int i = 0; i < k; ++i) MNCHK(hipGraphLaunch(N->gexec, N->stream));
+  } else {
+    for (int i = 0; i < k; ++i) MNOK(iteration(*N));
+  }
   if (last_loss) {
     IterState st{};
     MNCHK(hipMemcpyAsync(&st, N->it, sizeof(st), hipMemcpyDeviceToHost, N->stream));

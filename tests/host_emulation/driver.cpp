@@ -489,8 +489,9 @@ static int mnet_case() {
   int mixes[][5] = {{0, 0, 0, 0, 0}, {1, 0, 0, 0, 0}, {0, 4, 0, 0, 0}, {0, 0, 1, 1, 0},
                     {0, 0, 0, 0, 1}, {1, 4, 1, 1, 1}};
   for (auto& mx : mixes)
-    for (int levels : {2, 3}) {
-      d2ip_mnet_desc d{n, M, levels, 8, mx[0], mx[1], mx[2], mx[3], mx[4]};
+    for (int levels : {2, 3})
+      for (int graph : {0, 1}) {
+      d2ip_mnet_desc d{n, M, levels, 8, mx[0], mx[1], mx[2], mx[3], mx[4], graph};
       size_t bytes = 0, P = 0;
       CK(d2ip_mnet_workspace_bytes(&d, &bytes));
       CK(d2ip_mnet_param_count(&d, &P));
@@ -514,10 +515,12 @@ static int mnet_case() {
       CK(d2ip_mnet_set_frame(net, dv.data(), 0));
       CK(d2ip_mnet_reset_optimizer(net));
       CK(d2ip_mnet_run(net, 1, nullptr));
+      CK(d2ip_mnet_set_adam(net, &cfg));  // discards a captured graph
+      CK(d2ip_mnet_run(net, 2, &loss));
       CK(d2ip_mnet_destroy(net));
       emu_flush_all();
       free(ws);
-    }
+      }
   printf("ok: module networks\n");
   return 0;
 }

@@ -411,13 +411,13 @@ def test_module_network_validates_its_description(L):
     host checks before anything touches the device."""
     lib = L.load()
     sz = ctypes.c_size_t()
-    ok = L.MnetDesc(16, 208, 3, 8, 1, 4, 1, 1, 1)
+    ok = L.MnetDesc(16, 208, 3, 8, 1, 4, 1, 1, 1, 1)
     assert lib.d2ip_mnet_workspace_bytes(ctypes.byref(ok), ctypes.byref(sz)) == L.OK
     assert sz.value > 208 * 16 ** 3 * 4
-    for bad in (L.MnetDesc(16, 208, 1, 8, 0, 0, 0, 0, 0), L.MnetDesc(16, 208, 3, 12, 0, 0, 0, 0, 0),
-                L.MnetDesc(6, 208, 3, 8, 0, 0, 0, 0, 0), L.MnetDesc(16, 0, 3, 8, 0, 0, 0, 0, 0),
-                L.MnetDesc(16, 208, 3, 8, 0, -1, 0, 0, 0),
-                L.MnetDesc(64, 208, 4, 32, 0, 0, 1, 0, 0)):  # attention skip of 128 channels
+    for bad in (L.MnetDesc(16, 208, 1, 8, 0, 0, 0, 0, 0, 0), L.MnetDesc(16, 208, 3, 12, 0, 0, 0, 0, 0, 0),
+                L.MnetDesc(6, 208, 3, 8, 0, 0, 0, 0, 0, 0), L.MnetDesc(16, 0, 3, 8, 0, 0, 0, 0, 0, 0),
+                L.MnetDesc(16, 208, 3, 8, 0, -1, 0, 0, 0, 0),
+                L.MnetDesc(64, 208, 4, 32, 0, 0, 1, 0, 0, 0)):  # attention skip of 128 channels
         assert lib.d2ip_mnet_workspace_bytes(ctypes.byref(bad), ctypes.byref(sz)) == L.EINVAL
     h = ctypes.c_void_p()
     assert lib.d2ip_mnet_create(ctypes.byref(ok), ctypes.c_void_p(4096), 1024, None,

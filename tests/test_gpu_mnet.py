@@ -148,3 +148,35 @@ def test_bitwise_repeatable_and_frames_keep_theta(lib):
     np.testing.assert_array_equal(a.read_image(), c.read_image())
     for x in (a, b, c):
         x.close()
+
+
+@pytest.mark.parametrize("kw", [dict(), dict(sep=True, se_ratio=4, att=True, tail="sigmoid",
+                                                aspp=True)], ids=["plain", "all-modules"])
+def test_graph_replay_equals_eager(lib, kw):
+    """With graph=True the first run captures one iteration and replays it:
+    parameters, gradient, loss and image equal the eager context's bit for
+    bit over several runs; a new Adam setting is captured anew (the old
+    graph held the old learning rate)."""
+    from paper_2507_14046_amd.context import ModuleFit
+    p = problem(16, 2, 3, 8, 370)
+    th = _theta(p, kw, 41)
+
+    def make(graph):
+        f = ModuleFit(p["n"], p["J"].shape[0], p["levels"], p["base_ch"], graph=graph, **kw)
+        f.set_problem(p["J"], p["mask"], p["Z"])
+        f.set_params(th)
+        f.set_frame(p["dv"][0])
+        f.set_adam(lr=1e-3)
+        return f
+    e, g = make(False), make(True)
+    for k in (1, 3, 2):
+        assert e.run(k) == g.run(k)
+        np.testing.assert_array_equal(e.get_params(), g.get_params())
+        np.testing.assert_array_equal(e.get_grad(), g.get_grad())
+    e.set_adam(lr=3e-3)
+    g.set_adam(lr=3e-3)
+    assert e.run(2) == g.run(2)
+    np.testing.assert_array_equal(e.get_params(), g.get_params())
+    np.testing.assert_array_equal(e.read_image(), g.read_image())
+    e.close()
+    g.close()
