@@ -380,6 +380,8 @@ d2ip_status d2ip_op_ln_relu_forward(const float* x, const float* gamma, const fl
   d2ip_status st = ln_check(n, C);
   if (st != D2IP_OK) return st;
   if (!x || !gamma || !beta || !y) return api_fail(D2IP_EINVAL, "null x, gamma, beta or y");
+  if (!aligned16(x) || !aligned16(y) || (skip && !aligned16(skip)))
+    return api_fail(D2IP_EINVAL, "x, y and skip must be 16-byte aligned");
   size_t need = 0;
   d2ip_op_ln_relu_bytes(n, C, &need);
   if ((st = ws_check(workspace, bytes, need)) != D2IP_OK) return st;
@@ -402,6 +404,9 @@ d2ip_status d2ip_op_ln_relu_backward(const float* x, const float* y, const float
   d2ip_status st = ln_check(n, C);
   if (st != D2IP_OK) return st;
   if (!x || !y || !gamma || !gy) return api_fail(D2IP_EINVAL, "null x, y, gamma or gy");
+  if (!aligned16(x) || !aligned16(y) || !aligned16(gy) || (gx && !aligned16(gx)) ||
+      (gskip && !aligned16(gskip)))
+    return api_fail(D2IP_EINVAL, "x, y, gy, gx and gskip must be 16-byte aligned");
   size_t need = 0;
   d2ip_op_ln_relu_bytes(n, C, &need);
   if ((st = ws_check(workspace, bytes, need)) != D2IP_OK) return st;

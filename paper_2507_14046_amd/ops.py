@@ -321,8 +321,8 @@ def _ln_fn():
         @staticmethod
         def forward(ctx, x, gamma, beta, skip):
             lib = L.load()
-            x = x.contiguous()
-            skip = skip.contiguous() if skip is not None else None
+            x = _a16(x)
+            skip = _a16(skip) if skip is not None else None
             V, C = x.shape
             n = _grid_n(V)
             ws, nb = _workspace(lib.d2ip_op_ln_relu_bytes, n, C, device=x.device)
