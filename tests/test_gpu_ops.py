@@ -244,7 +244,7 @@ def _cf(x, n):
     return np.ascontiguousarray(np.asarray(x, dtype=np.float64).T.reshape(-1, n, n, n))
 
 
-@pytest.mark.parametrize("n,Cu,Cs", [(8, 16, 8), (6, 4, 12), (32, 32, 16)])
+@pytest.mark.parametrize("n,Cu,Cs", [(8, 16, 8), (6, 4, 12), (32, 32, 16), (2, 4, 4)])
 def test_pool_and_up_concat_operators_match_oracle(lib, n, Cu, Cs):
     """d2ip_op_pool2_* and d2ip_op_up2_concat_* against the oracle's
     avgpool2 / up2 and their adjoints (FP64)."""
@@ -272,7 +272,7 @@ def test_pool_and_up_concat_operators_match_oracle(lib, n, Cu, Cs):
 
 
 @pytest.mark.parametrize("sig", [False, True])
-@pytest.mark.parametrize("n,C", [(8, 8), (6, 16), (32, 16), (16, 256)])
+@pytest.mark.parametrize("n,C", [(8, 8), (6, 16), (32, 16), (16, 256), (1, 256), (3, 4)])
 def test_head_operator_matches_oracle(lib, n, C, sig):
     """d2ip_op_head_*: the 1x1x1 conv to one channel (linear or the sigmoid
     tail 2 sigmoid(t) - 1), masked, and its gradients, against the oracle's
@@ -305,12 +305,16 @@ def test_head_operator_matches_oracle(lib, n, C, sig):
 
 
 @pytest.mark.parametrize("n,c,cu", [(8, 8, 16), (6, 4, 8), (16, 16, 32), (32, 32, 64),
-                                    (16, 64, 128)])
+                                    (16, 64, 128), (2, 4, 4), (4, 12, 8), (10, 20, 44),
+                                    (4, 64, 4), (6, 4, 128)])
 def test_attention_operator_matches_oracle(lib, n, c, cu):
     """d2ip_op_attention_*: the attention unit (gate on the coarse grid from the
     pooled skip, interpolated) and its gradients against the oracle's
     att_forward / att_backward (FP64); ragged last block at 6^3 (27 coarse
-    voxels) and the widest channels at 16^3."""
+    voxels), the widest channels at 16^3, a one-voxel coarse grid (2^3),
+    channel counts off the 16-wide matrix-core tiles (12, 20, 44: partial row
+    and column tiles, K = c + cu padded to a multiple of 16) and the extreme
+    c / cu mixes."""
     import torch
     from paper_2507_14046_amd import ops
     rng = np.random.default_rng(n + 10 * c + cu)
