@@ -357,7 +357,7 @@ def se_ops(d2ip, torch, shapes=((64, 64, 16), (32, 16, 4))):
     return out
 
 
-def module_ops(d2ip, torch, att_shapes=((64, 16, 32), (32, 32, 64), (64, 64, 128)),
+def module_ops(d2ip, torch, att_shapes=((64, 16, 32), (32, 32, 64), (64, 64, 128), (16, 128, 256)),
                head_shapes=((64, 16), (32, 16))):
     """The attention unit, the output head (sigmoid tail), pooling and
     up-sampling + concatenation through the op-level C-ABI (FP32,
@@ -407,7 +407,8 @@ def module_ops(d2ip, torch, att_shapes=((64, 16, 32), (32, 32, 64), (64, 64, 128
         key = "attention %d^3 c=%d cu=%d" % (n, c, cu)
         out[key] = dict(
             forward=timed(lambda: lib.d2ip_op_attention_forward(
-                P(x), P(g), P(wx), P(wg), P(b), P(psi), P(bpsi), P(y), None, n, c, cu, sp),
+                P(x), P(g), P(wx), P(wg), P(b), P(psi), P(bpsi), P(y), None, n, c, cu, P(ws),
+                nb.value, sp),
                 4.0 * (2 * V * c + m3 * cu), key + " fwd"),
             backward=timed(lambda: lib.d2ip_op_attention_backward(
                 P(x), P(g), P(wx), P(wg), P(b), P(psi), P(bpsi), P(gy), P(gx), P(gg), P(gwx),
@@ -498,10 +499,9 @@ def dwsep_network(d2ip, torch, ts, names=("c1", "c2"), reps=10):
         Z, mask, J, dv = dev(p["Z"]), dev(p["mask"].astype(np.float32)), dev(p["J"]), \
             dev(p["dv"][0])
         row = {}
-        variants = {"dense": {}, "dwsep": dict(conv="dwsep")}
-        if c["base_ch"] << (c["levels"] - 2) <= 64:  # attention units up to 64 skip channels
-            variants["fastres_modules"] = dict(conv="dwsep", se_ratio=4, att=True,
-                                               tail="sigmoid", aspp=True)
+        variants = {"dense": {}, "dwsep": dict(conv="dwsep"),
+                    "fastres_modules": dict(conv="dwsep", se_ratio=4, att=True, tail="sigmoid",
+                                            aspp=True)}
         for conv, kw in variants.items():
             model = ops.DIPNet(c["n"], c["levels"], c["base_ch"], **kw)
             g = torch.Generator(device="cuda").manual_seed(11)

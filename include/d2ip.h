@@ -270,8 +270,7 @@ d2ip_status d2ip_clear_history(d2ip_ctx* ctx, int inst);
  * mask n^3 bytes (0 outside), z the n^3 noise input.
  *
  * Limits: levels 2..5, base_ch 8, 16 or 32, base_ch 2^(levels-1) <= 256, n a
- * multiple of 2^(levels-1) with n / 2^(levels-1) >= 2 and n <= 128; with
- * att the skip channels must stay <= 64 and the gating channels <= 128.
+ * multiple of 2^(levels-1) with n / 2^(levels-1) >= 2 and n <= 128.
  * The workspace (256-byte aligned, d2ip_mnet_workspace_bytes) holds J,
  * every activation, gradients, Adam moments and the operators' scratch; the
  * context keeps pointers into it until d2ip_mnet_destroy, which waits for
@@ -561,13 +560,16 @@ d2ip_status d2ip_op_head_backward(const float* x, const float* w, const float* b
  * wg [c][cu], b [c]), alpha = sigmoid(bpsi + psi . relu(a)) (psi [c],
  * bpsi [1]); then y [n^3][c] = alpha[parent(v)] x[v] (the coefficients
  * interpolated, nearest neighbour).  alpha [(n/2)^3] may be NULL.  c and cu
- * multiples of 4, c <= 64, cu <= 128; x, g, y (gy, gx), wx and wg 16-byte
- * aligned. */
+ * multiples of 4, c <= 256, cu <= 512 (up to 64 / 128 one fused pass; wider
+ * through pointwise matrix-core GEMMs); x, g, y (gy, gx), wx and wg 16-byte
+ * aligned.  The workspace (256-byte aligned, d2ip_op_attention_bytes, the
+ * same for forward and backward) holds the wide form's intermediates and the
+ * backward's partial sums. */
 d2ip_status d2ip_op_attention_bytes(int n, int c, int cu, size_t* out);
 d2ip_status d2ip_op_attention_forward(const float* x, const float* g, const float* wx,
                                       const float* wg, const float* b, const float* psi,
                                       const float* bpsi, float* y, float* alpha, int n, int c,
-                                      int cu, void* hip_stream);
+                                      int cu, void* workspace, size_t bytes, void* hip_stream);
 /* Gradients of the attention unit given gy = dL/dy: gx, gg (on g's grid) and
  * the parameter gradients (any output may be NULL except that the parameter
  * gradients are written together); the ReLU derivative is 0 at 0.  Sums over

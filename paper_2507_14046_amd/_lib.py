@@ -150,7 +150,8 @@ SIGNATURES = {
     "d2ip_op_head_backward": [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _i, _i, _i, _vp,
                               ctypes.c_size_t, _vp],
     "d2ip_op_attention_bytes": [_i, _i, _i, _c_size_p],
-    "d2ip_op_attention_forward": [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _i, _i, _i, _vp],
+    "d2ip_op_attention_forward": [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _i, _i, _i, _vp,
+                                  ctypes.c_size_t, _vp],
     "d2ip_op_attention_backward": [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
                                    _vp, _vp, _vp, _i, _i, _i, _vp, ctypes.c_size_t, _vp],
     "d2ip_op_jt_bytes": [_i, _i, _c_size_p],

@@ -151,10 +151,13 @@ void relu_forward(const float* x, float* y, size_t count, hipStream_t s);
 void relu_backward(const float* y, const float* gy, float* gx, size_t count, hipStream_t s);
 int att_max_c();
 int att_max_cu();
+// Wider channels run the composed form (pointwise GEMMs and gate kernels).
+int att_max_c_wide();
+int att_max_cu_wide();
 size_t att_scratch_bytes(int n, int c, int cu);
 void att_forward(const float* x, const float* g, const float* wx, const float* wg, const float* b,
                  const float* psi, const float* bpsi, float* y, float* alpha, int n, int c, int cu,
-                 hipStream_t s);
+                 void* scratch, hipStream_t s);
 void att_backward(const float* x, const float* g, const float* wx, const float* wg,
                   const float* b, const float* psi, const float* bpsi, const float* gy,
                   float* gx, float* gg, float* gwx, float* gwg, float* gb, float* gpsi,

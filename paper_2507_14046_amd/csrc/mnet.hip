@@ -531,7 +531,7 @@ d2ip_status forward(d2ip_mnet& N) {
     if (N.d.att) {
       const AttP& a = N.att[l];
       MNOK(d2ip_op_attention_forward(s, g, th + a.wx, th + a.wg, th + a.b, th + a.psi, th + a.bpsi,
-                                     N.atto[l], nullptr, P.n, N.ch[l], N.ch[l + 1], N.stream));
+                                     N.atto[l], nullptr, P.n, N.ch[l], N.ch[l + 1], WS));
       s = N.atto[l];
     }
     MNOK(d2ip_op_up2_concat_forward(g, N.ch[l + 1], s, N.ch[l], P.n, N.cat[l], N.stream));

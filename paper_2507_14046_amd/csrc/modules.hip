@@ -568,6 +568,191 @@ __global__ __launch_bounds__(256) void k_att_bwd(AttArgs A, int ntiles, const fl
   if (threadIdx.x == 0) P[o_bpsi] = acc_bpsi;
 }
 
+// ---- attention unit, wide channels -------------------------------------------
+//
+// Skip channels above kAttMaxC or gating channels above kAttMaxCu: the unit
+// is composed from pieces that scale with the channel counts.  Z [u][K]
+// (K = c + cu) holds the pooled skip and the gating rows, Wcat [c][K] the
+// weights [wx | wg]; a = Z Wcat^T + b and, in the backward, gW = ga^T Z and
+// gZ = ga Wcat run on the pointwise matrix-core GEMM; the gate, the scaling
+// and their gradients are the kernels below.  One wave per coarse voxel where
+// a voxel's values are summed (butterfly, lane 0's result), so every result
+// is run-to-run identical.
+
+// Z [u][0, c) = mean of x over the 8 children of u, Z [u][c, K) = g [u].
+__global__ __launch_bounds__(256) void k_attw_stage(const float* __restrict__ x,
+                                                    const float* __restrict__ g, int n, int c,
+                                                    int cu, float* __restrict__ Z) {
+  const int m = n / 2, K4 = (c + cu) / 4, c4 = c / 4;
+  const size_t total = (size_t)m * m * m * K4;
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < total;
+       i += (size_t)gridDim.x * blockDim.x) {
+    const size_t u = i / K4;
+    const int q = (int)(i - u * K4);
+    float4 v;
+    if (q < c4) {
+      const int xx = (int)(u % m), yy = (int)((u / m) % m), zz = (int)(u / ((size_t)m * m));
+      float4 s = make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+      for (int ch = 0; ch < 8; ++ch) {
+        const int fz = 2 * zz + (ch >> 2), fy = 2 * yy + ((ch >> 1) & 1), fx = 2 * xx + (ch & 1);
+        const float4 a =
+            reinterpret_cast<const float4*>(x + ((size_t)(fz * n + fy) * n + fx) * c)[q];
+        s.x += a.x;
+        s.y += a.y;
+        s.z += a.z;
+        s.w += a.w;
+      }
+      v = make_float4(0.125f * s.x, 0.125f * s.y, 0.125f * s.z, 0.125f * s.w);
+    } else {
+      v = reinterpret_cast<const float4*>(g + u * cu)[q - c4];
+    }
+    reinterpret_cast<float4*>(Z + u * (size_t)(c + cu))[q] = v;
+  }
+}
+
+// Wcat [k][K] = [wx [k][:], wg [k][:]].
+__global__ void k_attw_catw(const float* __restrict__ wx, const float* __restrict__ wg, int c,
+                            int cu, float* __restrict__ W) {
+  const int K = c + cu;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < c * K; i += gridDim.x * blockDim.x) {
+    const int k = i / K, j = i - k * K;
+    W[i] = j < c ? wx[k * c + j] : wg[k * cu + (j - c)];
+  }
+}
+
+// al[u] = sigmoid(bpsi + sum_k psi[k] relu(a[u][k])): wave per coarse voxel.
+__global__ __launch_bounds__(256) void k_attw_gate(const float* __restrict__ a,
+                                                   const float* __restrict__ psi,
+                                                   const float* __restrict__ bpsi, size_t Vc,
+                                                   int c, float* __restrict__ al,
+                                                   float* __restrict__ alpha) {
+  const int lane = threadIdx.x & 63;
+  const size_t w0 = blockIdx.x * (size_t)4 + (threadIdx.x >> 6);
+  for (size_t u = w0; u < Vc; u += (size_t)gridDim.x * 4) {
+    float s = 0.f;
+    for (int k = lane; k < c; k += 64) s += psi[k] * fmaxf(a[u * c + k], 0.f);
+    s = wave_sum(s);
+    if (lane == 0) {
+      const float v = 1.f / (1.f + expf(-(bpsi[0] + s)));
+      al[u] = v;
+      if (alpha) alpha[u] = v;
+    }
+  }
+}
+
+// y[v] = al[parent(v)] x[v] (float4 quads).
+__global__ __launch_bounds__(256) void k_attw_scale(const float* __restrict__ x,
+                                                    const float* __restrict__ al, int n, int c,
+                                                    float* __restrict__ y) {
+  const int c4 = c / 4, m = n / 2;
+  const size_t total = (size_t)n * n * n * c4;
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < total;
+       i += (size_t)gridDim.x * blockDim.x) {
+    const size_t v = i / c4;
+    const int fx = (int)(v % n), fy = (int)((v / n) % n), fz = (int)(v / ((size_t)n * n));
+    const float a = al[((size_t)(fz / 2) * m + fy / 2) * m + fx / 2];
+    const float4 t = reinterpret_cast<const float4*>(x)[i];
+    reinterpret_cast<float4*>(y)[i] = make_float4(a * t.x, a * t.y, a * t.z, a * t.w);
+  }
+}
+
+// gt[u] = (sum over the children and channels of gy x) al (1 - al): wave per
+// coarse voxel, lanes over (child, quad) items.
+__global__ __launch_bounds__(256) void k_attw_gdot(const float* __restrict__ x,
+                                                   const float* __restrict__ gy,
+                                                   const float* __restrict__ al, int n, int c,
+                                                   float* __restrict__ gt) {
+  const int lane = threadIdx.x & 63, c4 = c / 4, m = n / 2;
+  const size_t Vc = (size_t)m * m * m;
+  const size_t w0 = blockIdx.x * (size_t)4 + (threadIdx.x >> 6);
+  for (size_t u = w0; u < Vc; u += (size_t)gridDim.x * 4) {
+    const int xx = (int)(u % m), yy = (int)((u / m) % m), zz = (int)(u / ((size_t)m * m));
+    float s = 0.f;
+    for (int it = lane; it < 8 * c4; it += 64) {
+      const int ch = it / c4, q = it - ch * c4;
+      const int fz = 2 * zz + (ch >> 2), fy = 2 * yy + ((ch >> 1) & 1), fx = 2 * xx + (ch & 1);
+      const size_t o = ((size_t)(fz * n + fy) * n + fx) * c;
+      const float4 a = reinterpret_cast<const float4*>(x + o)[q];
+      const float4 b = reinterpret_cast<const float4*>(gy + o)[q];
+      s += a.x * b.x + a.y * b.y + a.z * b.z + a.w * b.w;
+    }
+    s = wave_sum(s);
+    if (lane == 0) {
+      const float a = al[u];
+      gt[u] = s * a * (1.f - a);
+    }
+  }
+}
+
+// ga[u][k] = psi[k] gt[u] where a[u][k] > 0 (else 0); one FP64 partial per
+// block of (sum_u relu(a[u][k]) gt[u] for every k, sum_u gt[u]): thread
+// (quad q, row lane r) takes rows r, r + R, ... of the block's chunk of
+// kAttwRows coarse voxels, the row lanes added in lane order at the end.
+constexpr int kAttwRows = 256;
+__global__ __launch_bounds__(256) void k_attw_gate_bwd(const float* __restrict__ a,
+                                                       const float* __restrict__ psi,
+                                                       const float* __restrict__ gt, size_t Vc,
+                                                       int c, float* __restrict__ ga,
+                                                       double* __restrict__ part) {
+  __shared__ double red[256][5];
+  const int c4 = c / 4, R = 256 / c4, q = threadIdx.x % c4, r = threadIdx.x / c4;
+  const float4 pq = reinterpret_cast<const float4*>(psi)[q];
+  double acc[4] = {0.0, 0.0, 0.0, 0.0}, accb = 0.0;
+  for (size_t u0 = blockIdx.x * (size_t)kAttwRows; u0 < Vc; u0 += (size_t)gridDim.x * kAttwRows) {
+    const int nu = (int)min((size_t)kAttwRows, Vc - u0);
+    if (r < R)
+      for (int rr = r; rr < nu; rr += R) {
+        const size_t u = u0 + rr;
+        const float t = gt[u];
+        const float4 av = reinterpret_cast<const float4*>(a + u * c)[q];
+        acc[0] += (double)(fmaxf(av.x, 0.f) * t);
+        acc[1] += (double)(fmaxf(av.y, 0.f) * t);
+        acc[2] += (double)(fmaxf(av.z, 0.f) * t);
+        acc[3] += (double)(fmaxf(av.w, 0.f) * t);
+        if (q == 0) accb += (double)t;
+        reinterpret_cast<float4*>(ga + u * c)[q] =
+            make_float4(av.x > 0.f ? pq.x * t : 0.f, av.y > 0.f ? pq.y * t : 0.f,
+                        av.z > 0.f ? pq.z * t : 0.f, av.w > 0.f ? pq.w * t : 0.f);
+      }
+  }
+  for (int e = 0; e < 4; ++e) red[threadIdx.x][e] = acc[e];
+  red[threadIdx.x][4] = accb;
+  __syncthreads();
+  if ((int)threadIdx.x < c4) {
+    double sm[4] = {0.0, 0.0, 0.0, 0.0}, sb = 0.0;
+    for (int rr = 0; rr < R; ++rr) {
+      const int t = rr * c4 + threadIdx.x;
+      for (int e = 0; e < 4; ++e) sm[e] += red[t][e];
+      sb += red[t][4];
+    }
+    double* p = part + (size_t)blockIdx.x * (c + 1);
+    for (int e = 0; e < 4; ++e) p[4 * threadIdx.x + e] = sm[e];
+    if (threadIdx.x == 0) p[c] = sb;
+  }
+}
+
+// gx[v] = al[parent(v)] gy[v] + gZ[parent(v)][0, c) / 8.
+__global__ __launch_bounds__(256) void k_attw_scale_bwd(const float* __restrict__ gy,
+                                                        const float* __restrict__ al,
+                                                        const float* __restrict__ gZ, int n,
+                                                        int c, int K, float* __restrict__ gx) {
+  const int c4 = c / 4, m = n / 2;
+  const size_t total = (size_t)n * n * n * c4;
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < total;
+       i += (size_t)gridDim.x * blockDim.x) {
+    const size_t v = i / c4;
+    const int q = (int)(i - v * c4);
+    const int fx = (int)(v % n), fy = (int)((v / n) % n), fz = (int)(v / ((size_t)n * n));
+    const size_t u = ((size_t)(fz / 2) * m + fy / 2) * m + fx / 2;
+    const float a = al[u];
+    const float4 t = reinterpret_cast<const float4*>(gy)[i];
+    const float4 z = reinterpret_cast<const float4*>(gZ + u * K)[q];
+    reinterpret_cast<float4*>(gx)[i] = make_float4(a * t.x + 0.125f * z.x, a * t.y + 0.125f * z.y,
+                                                   a * t.z + 0.125f * z.z, a * t.w + 0.125f * z.w);
+  }
+}
+
 // ---- channel slices, ReLU ---------------------------------------------------
 
 // dst[v][doff + j] = src[v][soff + j] for j < c (all counts and offsets
@@ -653,7 +838,73 @@ void head_backward(const float* x, const float* w, const float* b, const float* 
   }
 }
 
+namespace {
+
+size_t vox3(int n) { return (size_t)n * n * n; }
+
+// Wide channels (composed form): workspace pieces, 256-byte aligned.
+struct AttwWs {
+  float *Z = nullptr, *W = nullptr, *a = nullptr, *al = nullptr, *gt = nullptr, *ga = nullptr,
+        *gZ = nullptr, *gW = nullptr, *pwp = nullptr;
+  double *gp = nullptr, *tmp = nullptr;
+  int nbg = 0;
+  size_t bytes = 0;
+};
+
+AttwWs attw_carve(char* base, int n, int c, int cu, bool bwd) {
+  AttwWs w;
+  const size_t m = n / 2, Vc = m * m * m, K = c + cu;
+  size_t off = 0;
+  auto take = [&](size_t bytes) -> char* {
+    off = (off + 255) & ~size_t(255);
+    char* p = base ? base + off : nullptr;
+    off += bytes;
+    return p;
+  };
+  w.Z = reinterpret_cast<float*>(take(Vc * K * 4));
+  w.W = reinterpret_cast<float*>(take((size_t)c * K * 4));
+  w.a = reinterpret_cast<float*>(take(Vc * c * 4));
+  w.al = reinterpret_cast<float*>(take(Vc * 4));
+  if (bwd) {
+    w.nbg = (int)std::max<size_t>(1, std::min<size_t>((Vc + kAttwRows - 1) / kAttwRows, 1024));
+    w.gt = reinterpret_cast<float*>(take(Vc * 4));
+    w.ga = reinterpret_cast<float*>(take(Vc * c * 4));
+    w.gZ = reinterpret_cast<float*>(take(Vc * K * 4));
+    w.gW = reinterpret_cast<float*>(take((size_t)c * K * 4));
+    w.pwp = reinterpret_cast<float*>(take(pw_partials(Vc, (int)K, c) * 4));
+    w.gp = reinterpret_cast<double*>(take((size_t)w.nbg * (c + 1) * 8));
+    w.tmp = reinterpret_cast<double*>(take((size_t)colsum_slices(w.nbg) * (c + 1) * 8));
+  }
+  w.bytes = off;
+  return w;
+}
+
+bool att_wide(int c, int cu) { return c > kAttMaxC || cu > kAttMaxCu; }
+
+unsigned wave_blocks(size_t items) {  // four waves per block, one item per wave
+  return (unsigned)std::max<size_t>(1, std::min<size_t>((items + 3) / 4, 8192));
+}
+
+// a = Z Wcat^T + b and the gate, from x and g (both forms of the wide path).
+void attw_gate_fwd(const AttArgs& A, const AttwWs& w, float* alpha, hipStream_t s) {
+  const int c = A.c, cu = A.cu, K = c + cu, m = A.n / 2;
+  const size_t Vc = (size_t)m * m * m;
+  hipLaunchKernelGGL(k_attw_stage, dim3(elementwise_blocks(Vc * (K / 4))), dim3(256), 0, s, A.x,
+                     A.g, A.n, c, cu, w.Z);
+  hipLaunchKernelGGL(k_attw_catw, dim3((c * K + 255) / 256), dim3(256), 0, s, A.wx, A.wg, c, cu,
+                     w.W);
+  pw_gemm(w.Z, w.W, A.b, w.a, Vc, K, c, false, s);
+  hipLaunchKernelGGL(k_attw_gate, dim3(wave_blocks(Vc)), dim3(256), 0, s, w.a, A.psi, A.bpsi, Vc, c,
+                     w.al, alpha);
+}
+
+}  // namespace
+
+int att_max_c_wide() { return 256; }
+int att_max_cu_wide() { return 512; }
+
 size_t att_scratch_bytes(int n, int c, int cu) {
+  if (att_wide(c, cu)) return attw_carve(nullptr, n, c, cu, true).bytes + 256;
   const int nb = att_bwd_blocks(n);
   const size_t np = att_nparams(c, cu);
   return (size_t)nb * np * sizeof(float) + (size_t)colsum_slices(nb) * np * sizeof(double) + 256;
@@ -672,8 +923,15 @@ void att_launch(Kern k, size_t lds, dim3 grid, hipStream_t s, const AttArgs& A, 
 
 void att_forward(const float* x, const float* g, const float* wx, const float* wg, const float* b,
                  const float* psi, const float* bpsi, float* y, float* alpha, int n, int c, int cu,
-                 hipStream_t s) {
+                 void* scratch, hipStream_t s) {
   AttArgs A{x, g, wx, wg, b, psi, bpsi, n, c, cu};
+  if (att_wide(c, cu)) {
+    const AttwWs w = attw_carve(reinterpret_cast<char*>(scratch), n, c, cu, false);
+    attw_gate_fwd(A, w, alpha, s);
+    hipLaunchKernelGGL(k_attw_scale, dim3(elementwise_blocks(vox3(n) * (c / 4))), dim3(256), 0, s,
+                       x, w.al, n, c, y);
+    return;
+  }
   const int nt = att_tiles(n), items = (c + 15) / 16;
   const size_t lds = att_lds_bytes(c, cu, false);
   const dim3 grid(nt);
@@ -690,6 +948,34 @@ void att_backward(const float* x, const float* g, const float* wx, const float* 
                   float* gx, float* gg, float* gwx, float* gwg, float* gb, float* gpsi,
                   float* gbpsi, int n, int c, int cu, void* scratch, hipStream_t s) {
   AttArgs A{x, g, wx, wg, b, psi, bpsi, n, c, cu};
+  if (att_wide(c, cu)) {
+    const AttwWs w = attw_carve(reinterpret_cast<char*>(scratch), n, c, cu, true);
+    const int K = c + cu, m = n / 2;
+    const size_t Vc = (size_t)m * m * m;
+    attw_gate_fwd(A, w, nullptr, s);
+    hipLaunchKernelGGL(k_attw_gdot, dim3(wave_blocks(Vc)), dim3(256), 0, s, x, gy, w.al, n, c,
+                       w.gt);
+    hipLaunchKernelGGL(k_attw_gate_bwd, dim3(w.nbg), dim3(256), 0, s, w.a, psi, w.gt, Vc, c, w.ga,
+                       w.gp);
+    if (gpsi || gbpsi) {
+      ColOut o{{gpsi, gbpsi, nullptr, nullptr, nullptr}, {0, c, c + 1, 0, 0, 0}, 2};
+      colsum(w.gp, w.nbg, c + 1, w.tmp, o, s);
+    }
+    // gW = ga^T Z (then split into wx and wg), gb = column sums of ga
+    if (gwx || gwg || gb) {
+      pw_wgrad(w.Z, w.ga, w.pwp, w.gW, gb, Vc, K, c, s);
+      if (gwx) channel_copy(w.gW, K, 0, gwx, c, 0, c, (size_t)c, s);
+      if (gwg) channel_copy(w.gW, K, c, gwg, cu, 0, cu, (size_t)c, s);
+    }
+    if (gx || gg) {
+      pw_gemm(w.ga, w.W, nullptr, w.gZ, Vc, c, K, true, s);  // gZ = ga Wcat
+      if (gg) channel_copy(w.gZ, K, c, gg, cu, 0, cu, Vc, s);
+      if (gx)
+        hipLaunchKernelGGL(k_attw_scale_bwd, dim3(elementwise_blocks(vox3(n) * (c / 4))), dim3(256),
+                           0, s, gy, w.al, w.gZ, n, c, K, gx);
+    }
+    return;
+  }
   const int nt = att_tiles(n), nb = att_bwd_blocks(n), items = (c + 15) / 16;
   float* part = reinterpret_cast<float*>(scratch);
   const int np = att_nparams(c, cu);

@@ -252,8 +252,8 @@ d2ip_status head_check(int n, int C) {
 }
 d2ip_status att_check(int n, int c, int cu) {
   if (n < 2 || n % 2 || n > 512) return api_fail(D2IP_EINVAL, "n must be even, in [2, 512]");
-  if (c < 4 || c % 4 || c > att_max_c() || cu < 4 || cu % 4 || cu > att_max_cu())
-    return api_fail(D2IP_EINVAL, "need c % 4 == 0 <= 64 and cu % 4 == 0 <= 128");
+  if (c < 4 || c % 4 || c > att_max_c_wide() || cu < 4 || cu % 4 || cu > att_max_cu_wide())
+    return api_fail(D2IP_EINVAL, "need c % 4 == 0 <= 256 and cu % 4 == 0 <= 512");
   return D2IP_OK;
 }
 
@@ -772,14 +772,17 @@ d2ip_status d2ip_op_attention_bytes(int n, int c, int cu, size_t* out) {
 d2ip_status d2ip_op_attention_forward(const float* x, const float* g, const float* wx,
                                       const float* wg, const float* b, const float* psi,
                                       const float* bpsi, float* y, float* alpha, int n, int c,
-                                      int cu, void* hip_stream) {
+                                      int cu, void* workspace, size_t bytes, void* hip_stream) {
   d2ip_status st = att_check(n, c, cu);
   if (st != D2IP_OK) return st;
+  size_t need = 0;
+  d2ip_op_attention_bytes(n, c, cu, &need);
+  if ((st = ws_check(workspace, bytes, need)) != D2IP_OK) return st;
   if (!x || !g || !wx || !wg || !b || !psi || !bpsi || !y)
     return api_fail(D2IP_EINVAL, "null tensor");
   if (!aligned16(x) || !aligned16(g) || !aligned16(y) || !aligned16(wx) || !aligned16(wg))
     return api_fail(D2IP_EINVAL, "x, g, y, wx and wg must be 16-byte aligned");
-  att_forward(x, g, wx, wg, b, psi, bpsi, y, alpha, n, c, cu,
+  att_forward(x, g, wx, wg, b, psi, bpsi, y, alpha, n, c, cu, workspace,
               reinterpret_cast<hipStream_t>(hip_stream));
   OPCHK(hipGetLastError());
   return D2IP_OK;

@@ -616,8 +616,10 @@ def _att_fn():
             b, psi, bpsi = (t.contiguous() for t in (b, psi, bpsi))
             n, c, cu = _grid_n(x.shape[0]), x.shape[1], g.shape[1]
             y = torch.empty_like(x)
+            ws, nb = _workspace(lib.d2ip_op_attention_bytes, n, c, cu, device=x.device)
             L.check(lib.d2ip_op_attention_forward(_p(x), _p(g), _p(wx), _p(wg), _p(b), _p(psi),
-                                                  _p(bpsi), _p(y), None, n, c, cu, _stream(x)))
+                                                  _p(bpsi), _p(y), None, n, c, cu, _p(ws), nb,
+                                                  _stream(x)))
             ctx.save_for_backward(x, g, wx, wg, b, psi, bpsi)
             return y
 

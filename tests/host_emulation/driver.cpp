@@ -270,7 +270,8 @@ static int ops_case() {
     }
   // attention unit: ragged last block at 6^3 and the widest channels
   for (auto [na, ca, cua] : {std::tuple{8, 8, 16}, std::tuple{6, 4, 8}, std::tuple{8, 64, 128},
-                              std::tuple{4, 12, 4}}) {
+                              std::tuple{4, 12, 4}, std::tuple{4, 128, 256},
+                              std::tuple{6, 256, 512}}) {
     const size_t Va = (size_t)na * na * na, Vc = Va / 8;
     std::vector<float> xa(Va * ca), ga(Vc * cua), ya(Va * ca), al(Vc), gxa(Va * ca),
         gga(Vc * cua), wx((size_t)ca * ca), wg((size_t)ca * cua), ba(ca), ps(ca), bp(1),
@@ -278,7 +279,7 @@ static int ops_case() {
     CK(d2ip_op_attention_bytes(na, ca, cua, &need));
     ws = (char*)aligned_alloc(256, (need + 255) / 256 * 256);
     CK(d2ip_op_attention_forward(xa.data(), ga.data(), wx.data(), wg.data(), ba.data(), ps.data(),
-                                 bp.data(), ya.data(), al.data(), na, ca, cua, nullptr));
+                                 bp.data(), ya.data(), al.data(), na, ca, cua, ws, need, nullptr));
     CK(d2ip_op_attention_backward(xa.data(), ga.data(), wx.data(), wg.data(), ba.data(),
                                   ps.data(), bp.data(), ya.data(), gxa.data(), gga.data(),
                                   gwx.data(), gwg.data(), gba.data(), gps.data(), gbp.data(), na,

@@ -321,11 +321,14 @@ def test_network_module_operators_validate_their_arguments(L):
     assert lib.d2ip_op_head_backward(a, a, a, None, a, b2, None, None, 8, 16, 1, a, 1,
                                      None) == L.ENOMEM
     # attention
-    for args in ((7, 8, 16), (8, 68, 16), (8, 8, 132), (8, 6, 16), (0, 8, 8)):
+    for args in ((7, 8, 16), (8, 260, 16), (8, 8, 516), (8, 6, 16), (0, 8, 8)):
         assert lib.d2ip_op_attention_bytes(*args, sz) == L.EINVAL, args
     assert lib.d2ip_op_attention_bytes(16, 64, 128, sz) == L.OK and nb.value > 0
-    assert lib.d2ip_op_attention_forward(a, a, a, a, a, a, None, b2, None, 8, 8, 16,
+    assert lib.d2ip_op_attention_bytes(16, 256, 512, sz) == L.OK and nb.value > 0
+    assert lib.d2ip_op_attention_forward(a, a, a, a, a, a, None, b2, None, 8, 8, 16, a, 1 << 30,
                                          None) == L.EINVAL
+    assert lib.d2ip_op_attention_forward(a, a, a, a, a, a, a, b2, None, 8, 128, 16, a, 1,
+                                         None) == L.ENOMEM
     assert lib.d2ip_op_attention_backward(a, a, a, a, a, a, a, a, b2, None, None, None, None,
                                           None, None, 8, 8, 16, a, 1, None) == L.ENOMEM
 
@@ -417,7 +420,7 @@ def test_module_network_validates_its_description(L):
     for bad in (L.MnetDesc(16, 208, 1, 8, 0, 0, 0, 0, 0, 0), L.MnetDesc(16, 208, 3, 12, 0, 0, 0, 0, 0, 0),
                 L.MnetDesc(6, 208, 3, 8, 0, 0, 0, 0, 0, 0), L.MnetDesc(16, 0, 3, 8, 0, 0, 0, 0, 0, 0),
                 L.MnetDesc(16, 208, 3, 8, 0, -1, 0, 0, 0, 0),
-                L.MnetDesc(64, 208, 4, 32, 0, 0, 1, 0, 0, 0)):  # attention skip of 128 channels
+                L.MnetDesc(64, 208, 5, 32, 0, 0, 1, 0, 0, 0)):  # 512 channels at the bottleneck
         assert lib.d2ip_mnet_workspace_bytes(ctypes.byref(bad), ctypes.byref(sz)) == L.EINVAL
     h = ctypes.c_void_p()
     assert lib.d2ip_mnet_create(ctypes.byref(ok), ctypes.c_void_p(4096), 1024, None,

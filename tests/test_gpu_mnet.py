@@ -180,3 +180,45 @@ def test_graph_replay_equals_eager(lib, kw):
     np.testing.assert_array_equal(e.read_image(), g.read_image())
     e.close()
     g.close()
+
+
+def _kaiming_theta(p, kw, seed):
+    """Weights N(0, 2 / fan_in) per tensor of the flat layout, gains 1 + 0.1 N,
+    other vectors 0.1 N: activations stay of order one through a deep, wide
+    network (a uniform 0.3 N draw drives the sigmoid head into saturation,
+    where FP32 rounds its derivative to zero)."""
+    from paper_2507_14046_amd import ops
+    rng = np.random.default_rng(seed)
+    out = []
+    for name, shape in ops.param_shapes(p["levels"], p["base_ch"], kw.get("sep", False),
+                                        kw.get("se_ratio", 0), kw.get("att", False),
+                                        kw.get("aspp", False)):
+        k = int(np.prod(shape))
+        if len(shape) >= 2:
+            v = rng.standard_normal(k) * np.sqrt(2.0 / np.prod(shape[1:]))
+        elif name.rsplit(".", 1)[1] in ("g", "g1", "g2"):
+            v = 1.0 + 0.1 * rng.standard_normal(k)
+        else:
+            v = 0.1 * rng.standard_normal(k)
+        out.append(v)
+    return np.concatenate(out).astype(np.float32)
+
+
+def test_wide_attention_network_matches_oracle(lib):
+    """Four levels of 32 base channels (the deepest decoder stage gates 128 skip
+    channels with 256 gating channels: the attention unit's wide form) with
+    every module: one iteration's loss and gradient against the oracle."""
+    kw = dict(sep=True, se_ratio=4, att=True, tail="sigmoid", aspp=True)
+    p = problem(16, 2, 4, 32, 380)
+    th = _kaiming_theta(p, kw, 43)
+    f = _fit(lib, p, kw, th)
+    loss = f.run(1)
+    g = f.get_grad()
+    f.close()
+    L0, gref, _ = _oracle(p, kw).loss_and_grad(th.astype(np.float64),
+                                               p["dv"][0].astype(np.float64))
+    e = dict(loss=abs(loss - L0) / L0, grad=rel(g, gref), grad_elem=elementwise(g, gref, 2e-5),
+             grad_norm=float(np.linalg.norm(gref)))
+    record("mnet_wide", **e)
+    assert e["grad_norm"] > 1e-6 * L0, e  # not a saturated head
+    assert e["loss"] < 5e-6 and e["grad"] < 5e-6 and e["grad_elem"] <= 1.0, e

@@ -306,15 +306,17 @@ def test_head_operator_matches_oracle(lib, n, C, sig):
 
 @pytest.mark.parametrize("n,c,cu", [(8, 8, 16), (6, 4, 8), (16, 16, 32), (32, 32, 64),
                                     (16, 64, 128), (2, 4, 4), (4, 12, 8), (10, 20, 44),
-                                    (4, 64, 4), (6, 4, 128)])
+                                    (4, 64, 4), (6, 4, 128), (8, 128, 256), (6, 72, 136),
+                                    (4, 256, 512), (8, 32, 160)])
 def test_attention_operator_matches_oracle(lib, n, c, cu):
     """d2ip_op_attention_*: the attention unit (gate on the coarse grid from the
     pooled skip, interpolated) and its gradients against the oracle's
     att_forward / att_backward (FP64); ragged last block at 6^3 (27 coarse
     voxels), the widest channels at 16^3, a one-voxel coarse grid (2^3),
     channel counts off the 16-wide matrix-core tiles (12, 20, 44: partial row
-    and column tiles, K = c + cu padded to a multiple of 16) and the extreme
-    c / cu mixes."""
+    and column tiles, K = c + cu padded to a multiple of 16), the extreme
+    c / cu mixes, and wide channels (above 64 / 128: the composed form on the
+    pointwise GEMMs, up to 256 / 512)."""
     import torch
     from paper_2507_14046_amd import ops
     rng = np.random.default_rng(n + 10 * c + cu)
