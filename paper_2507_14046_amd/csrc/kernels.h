@@ -135,6 +135,10 @@ void up_concat_bwd(const float* gcat, int Cu, int Cs, int n, float* gu, float* g
 void pool_bwd_add(const float* gx, const float* add, int n, int C, float* gy, int batch,
                   long long istride, hipStream_t s);
 void pad_input(const float* z, size_t V, float* zp, hipStream_t s);
+// out[i] = sum over rows k of part[k][i] (FP64 partials, i < ncols), summed
+// in a fixed order in two passes (tmp holds colsum_tmp_doubles values).
+size_t colsum_tmp_doubles(int nrows, int ncols);
+void colsum_f64(const double* part, int nrows, int ncols, double* tmp, float* out, hipStream_t s);
 // ---- output head and attention unit (modules.hip) ---------------------------
 int head_max_c();
 size_t head_scratch_bytes(size_t V, int C);

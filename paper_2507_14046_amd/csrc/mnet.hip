@@ -333,7 +333,7 @@ d2ip_status scratch_need(const d2ip_mnet& N, size_t* out) {
     MNOK(conv(B.n, B.a, B.c));
     MNOK(conv(B.n, B.c, B.c));
     MNOK(take(d2ip_op_ln_relu_bytes(B.n, B.c, &b)));
-    if (B.proj) MNOK(take(d2ip_op_conv3d_bytes(B.n, B.a, B.c, 1, D2IP_PLAIN_FP32, &b)));
+    if (B.proj) MNOK(take(d2ip_op_pwconv3d_bytes(B.n, B.a, B.c, &b)));
     return D2IP_OK;
   };
   for (int l = 0; l < N.L; ++l) {
@@ -477,8 +477,7 @@ d2ip_status block_fwd(d2ip_mnet& N, const BlockP& P, BlockB& B, const float* x) 
   MNOK(conv_fwd(N, P.c2, B.a1, B.t2, B.h2, P.n, P.c, P.c));
   const float* skip = x;
   if (P.proj) {
-    MNOK(d2ip_op_conv3d_forward(x, th + P.wp, th + P.bp, B.s, P.n, P.a, P.c, 1, D2IP_PLAIN_FP32,
-                                WS));
+    MNOK(d2ip_op_pwconv3d_forward(x, th + P.wp, th + P.bp, B.s, P.n, P.a, P.c, N.stream));
     skip = B.s;
   }
   return d2ip_op_ln_relu_forward(B.h2, th + P.g2, th + P.g2 + P.c, skip, B.y, P.n, P.c, WS);
@@ -568,8 +567,8 @@ d2ip_status block_bwd(d2ip_mnet& N, const BlockP& P, const BlockB& B, const floa
   MNOK(d2ip_op_ln_relu_backward(B.h1, B.a1, th + P.g1, ga, gh, nullptr, gr + P.g1, P.n, P.c, WS));
   MNOK(conv_bwd(N, P.c1, x, B.t1, gh, gx, gt, P.n, P.a, P.c));
   if (P.proj) {
-    MNOK(d2ip_op_conv3d_backward(x, th + P.wp, gs, ga, gr + P.wp, gr + P.bp, P.n, P.a, P.c, 1,
-                                 D2IP_PLAIN_FP32, WS));
+    MNOK(d2ip_op_pwconv3d_backward(x, th + P.wp, gs, ga, gr + P.wp, gr + P.bp, P.n, P.a, P.c,
+                                   WS));
     acc(gx, ga, V * P.a, N.stream);
   } else {
     acc(gx, gs, V * P.c, N.stream);

@@ -809,6 +809,16 @@ int att_bwd_blocks(int n) { return std::max(1, std::min(att_tiles(n), 512)); }
 
 }  // namespace
 
+size_t colsum_tmp_doubles(int nrows, int ncols) {
+  return (size_t)colsum_slices(nrows) * ncols;
+}
+
+void colsum_f64(const double* part, int nrows, int ncols, double* tmp, float* out,
+                hipStream_t s) {
+  ColOut o{{out, nullptr, nullptr, nullptr, nullptr}, {0, ncols, 0, 0, 0, 0}, 1};
+  colsum(part, nrows, ncols, tmp, o, s);
+}
+
 int att_max_c() { return kAttMaxC; }
 int att_max_cu() { return kAttMaxCu; }
 int head_max_c() { return kHeadMaxC; }

@@ -215,9 +215,8 @@ d2ip_status pw_check(int n, int cin, int cout) {
 }
 
 struct LnOp {
-  double *st = nullptr, *part_c = nullptr, *part_ab = nullptr;
+  double *st = nullptr, *part_c = nullptr, *part_ab = nullptr, *ctmp = nullptr;
   float* gz = nullptr;
-  GradSeg* seg = nullptr;
   int nst = 0, nb = 0;
 };
 
@@ -229,7 +228,7 @@ void ln_plan(LnOp& l, int n, int C, Piece& w) {
   l.part_c = w.take<double>((size_t)l.nb * 2 * C);
   l.part_ab = w.take<double>(2 * (size_t)l.nb);
   l.gz = w.take<float>(V * C);
-  l.seg = w.take<GradSeg>(1);
+  l.ctmp = w.take<double>(colsum_tmp_doubles(l.nb, 2 * C));
 }
 
 // Scratch of d2ip_op_jt_noalloc: the per-slice partial sums of J^T g for up
@@ -422,17 +421,7 @@ d2ip_status d2ip_op_ln_relu_backward(const float* x, const float* y, const float
   ln_bwd(gy, LNMASK_Y, y, nullptr, nullptr, x, stat, gz, l.part_c, l.part_ab, V, C, gamma, 1, 0,
          s);
   if (gx) ln_dx(gz, x, stat, PairRef{l.part_ab, l.nb, (double)V * C}, gamma, gx, V, C, s);
-  if (dgamma_dbeta) {
-    GradSeg g;
-    std::memset(&g, 0, sizeof(g));
-    g.kind = 1;
-    g.part_off = 0;
-    g.splits = l.nb;
-    g.cout = 2 * C;
-    g.th_w = 0;
-    hipLaunchKernelGGL(k_put<GradSeg>, dim3(1), dim3(64), 0, s, l.seg, g);
-    grad_reduce(l.seg, 1, 2 * C, nullptr, nullptr, l.part_c, dgamma_dbeta, 1, 0, s);
-  }
+  if (dgamma_dbeta) colsum_f64(l.part_c, l.nb, 2 * C, l.ctmp, dgamma_dbeta, s);
   OPCHK(hipGetLastError());
   return D2IP_OK;
 }
