@@ -337,7 +337,15 @@ __global__ __launch_bounds__(256) void k_tail_bwd(const float* tpart, int nmb, i
     if (v < V) {
       const int q = inv[v];
       if (q >= 0) {
-        for (int k = 0; k < nmb; ++k) g += tpart[(size_t)k * qa_pad + q];
+        // eight row-group partials in flight, added in row-group order
+        for (int k0 = 0; k0 < nmb; k0 += 8) {
+          float t[8];
+#pragma unroll
+          for (int e = 0; e < 8; ++e)
+            t[e] = k0 + e < nmb ? tpart[(size_t)(k0 + e) * qa_pad + q] : 0.f;
+#pragma unroll
+          for (int e = 0; e < 8; ++e) g += t[e];
+        }
         if (gtv) g += gtv[v];  // the image is masked: d sigma / d out = mask
       }
     }
@@ -364,13 +372,10 @@ __global__ __launch_bounds__(256) void k_tail_bwd(const float* tpart, int nmb, i
     part[pb + tid] = a;
   }
   __syncthreads();
-  sh[tid] = gsv[tid];
-  __syncthreads();
-  if (tid == 0) {
-    double a = 0.0;
-    for (int k = 0; k < kTailVoxels; ++k) a += sh[k];
-    part[pb + C] = a;
-  }
+  // bias partial: the block's voxel gradients, summed by the fixed wave
+  // butterflies of block_sum
+  const double a = block_sum((double)gsv[tid], sh);
+  if (tid == 0) part[pb + C] = a;
 }
 
 __global__ void k_adam(float* theta, const float* g, float* m, float* v, size_t P, float lr,
