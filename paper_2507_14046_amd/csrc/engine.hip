@@ -115,6 +115,7 @@ struct Block {
   const float* up_src = nullptr;    // decoder: output of the level below
   const float* skip_src = nullptr;  // decoder: output of encoder l
   float *gz = nullptr, *ga = nullptr;  // this block's LayerNorm-backward gradients
+  float* gpj = nullptr;  // input gradient of the 1x1 projection (side stream)
   PairRef st1{}, st2{};         // forward statistics partials of h1, h2
   PairRef cb1{}, cb2{};         // LayerNorm-backward coefficient partials
   double *lnc1 = nullptr, *lnc2 = nullptr;  // per-channel dgamma/dbeta partials
@@ -352,8 +353,8 @@ bool shape_ok(const d2ip_tuning_entry& e, std::string* why) {
     if (sh.tile == TILE_2x4x16 && sh.bn == 64) return no("the 2x4x16 tile takes bn <= 32");
     if (sh.split < 1 || (kin / sh.ck) % sh.split != 0)
       return no("split must divide the number of channel chunks");
-    if (e.pass == 0 && e.taps == 1 && sh.split != 1)
-      return no("1x1 forward convs run on the side stream without split-K");
+    if (e.taps == 1 && sh.split != 1)
+      return no("1x1 convs run on the side stream without split-K");
     const bool pro_ok = e.pass == 0 ? (e.prologue == PRO_NONE || e.prologue == PRO_LN_RELU)
                                     : (e.prologue == PRO_NONE || e.prologue == PRO_LN_BWD);
     if (!pro_ok || (e.taps == 1 && e.prologue != PRO_NONE)) return no("bad prologue");
@@ -421,6 +422,8 @@ void add_conv(Instance& I, Conv& c, int precision, size_t& kpart_max, int& tiles
   if (c.fwd.ksplit > 1) kpart_max = std::max(kpart_max, (size_t)c.fwd.ksplit * V * c.cout);
   if (c.dgrad) {
     c.bwd = choose_shape(c.n, c.cout, c.cin_real, c.taps, prec);
+    // a 1x1 projection's input gradient runs on the side stream too
+    if (c.taps == 1) c.bwd.ksplit = 1;
     if (const d2ip_tuning_entry* t =
             find_tuned(c.n, c.cin, c.cout, c.taps, 1, c.pro_bwd, precision)) {
       c.bwd.tile = t->shape.tile;
@@ -505,11 +508,12 @@ struct d2ip_ctx {
   hipStream_t cap = nullptr;  // capture stream (the caller's may be the legacy default stream)
   hipStream_t side = nullptr;  // branch for work off the critical path (weight gradients)
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  hipEvent_t ev_pj = nullptr;  // a projection's input gradient, done on the side stream
   // instance groups run concurrently, each on one of a few lanes (a main and
   // a side stream) forked from and joined back into the context stream
   struct Lane {
     hipStream_t main = nullptr, side = nullptr;
-    hipEvent_t fork = nullptr, join = nullptr, done = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr, done = nullptr, pj = nullptr;
   };
   std::vector<Lane> lanes;
   hipEvent_t ev_start = nullptr;
@@ -686,6 +690,7 @@ void plan(d2ip_ctx& X, const d2ip_geometry_desc* gd, int n_geo, const d2ip_insta
       b.h2 = cv.take<float>(V * b.cout);
       b.y = cv.take<float>(V * b.cout);
       if (b.proj) b.s = cv.take<float>(V * b.cout);
+      if (b.proj) b.gpj = cv.take<float>(V * b.cin);
       if (b.enc && b.level < L - 1) b.pool_out = cv.take<float>(V / 8 * b.cout);
       b.gz = cv.take<float>(V * b.cout);
       b.ga = cv.take<float>(V * b.cout);
@@ -1167,6 +1172,12 @@ void enqueue_iteration(d2ip_ctx& X, Instance& I) {
            const_cast<double*>(b.cb2.part), V, b.cout, g2, I.B, I.istride, s);
     const ConvSrc gh2 = src_ln_bwd(b.gz, b.h2, b.cout, b.st2, g2, b.cb2);
     fork(X);
+    if (b.proj) {
+      // the projection's input gradient needs only gz: first on the side
+      // stream, off the critical path; conv1's input gradient adds it
+      L_conv_fwd(dgrad_args(X, I, b.pj, src_plain(b.gz, b.cout), b.gpj), X.side);
+      if (!g_chk) hipEventRecord(X.ev_pj, X.side);
+    }
     wgrad(X, I, b.c2, src_ln_relu(b.h1, b.cout, b.st1, g1, b1), gh2, X.side);
     if (b.proj) wgrad(X, I, b.pj, src_plain(b.x, b.cin), src_plain(b.gz, b.cout), X.side);
     L_conv_fwd(dgrad_args(X, I, b.c2, gh2, b.ga), s);
@@ -1178,12 +1189,8 @@ void enqueue_iteration(d2ip_ctx& X, Instance& I) {
     wgrad(X, I, b.c1, src_plain(b.x, b.cin), gh1, X.side);
     {
       ConvFwd a = dgrad_args(X, I, b.c1, gh1, Lv.gx);
-      if (!b.proj) a.add = b.gz;
-      L_conv_fwd(a, s);
-    }
-    if (b.proj) {
-      ConvFwd a = dgrad_args(X, I, b.pj, src_plain(b.gz, b.cout), Lv.gx);
-      a.accumulate = 1;
+      a.add = b.proj ? b.gpj : b.gz;
+      if (b.proj && !g_chk) hipStreamWaitEvent(s, X.ev_pj, 0);
       L_conv_fwd(a, s);
     }
     if (!b.enc) {
@@ -1221,7 +1228,7 @@ void enqueue_all(d2ip_ctx& X, bool capturing) {
     return;
   }
   const hipStream_t s0 = X.stream, side0 = X.side;
-  const hipEvent_t f0 = X.ev_fork, j0 = X.ev_join;
+  const hipEvent_t f0 = X.ev_fork, j0 = X.ev_join, p0 = X.ev_pj;
   hipEventRecord(X.ev_start, s0);
   for (d2ip_ctx::Lane& l : X.lanes) hipStreamWaitEvent(l.main, X.ev_start, 0);
   for (size_t k = 0; k < X.insts.size(); ++k) {
@@ -1230,12 +1237,14 @@ void enqueue_all(d2ip_ctx& X, bool capturing) {
     X.side = l.side;
     X.ev_fork = l.fork;
     X.ev_join = l.join;
+    X.ev_pj = l.pj;
     enqueue_iteration(X, X.insts[k]);
   }
   X.stream = s0;
   X.side = side0;
   X.ev_fork = f0;
   X.ev_join = j0;
+  X.ev_pj = p0;
   for (d2ip_ctx::Lane& l : X.lanes) {
     hipEventRecord(l.done, l.main);
     hipStreamWaitEvent(s0, l.done, 0);
@@ -1368,6 +1377,7 @@ constexpr size_t kMaxLanes = 4;  // concurrent instance groups (hardware queues 
 
 void release_lanes(d2ip_ctx* X) {
   for (d2ip_ctx::Lane& l : X->lanes) {
+    if (l.pj) hipEventDestroy(l.pj);
     if (l.done) hipEventDestroy(l.done);
     if (l.join) hipEventDestroy(l.join);
     if (l.fork) hipEventDestroy(l.fork);
@@ -1698,6 +1708,7 @@ d2ip_status d2ip_create(const d2ip_geometry_desc* geos, int n_geo, const d2ip_in
   plan(*X, geos, n_geo, insts, n_inst, cv);
   auto cleanup = [&](d2ip_status s) {
     release_lanes(X);
+    if (X->ev_pj) hipEventDestroy(X->ev_pj);
     if (X->ev_join) hipEventDestroy(X->ev_join);
     if (X->ev_fork) hipEventDestroy(X->ev_fork);
     if (X->side) hipStreamDestroy(X->side);
@@ -1723,6 +1734,7 @@ d2ip_status d2ip_create(const d2ip_geometry_desc* geos, int n_geo, const d2ip_in
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&X->side, hipStreamNonBlocking);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&X->ev_fork, hipEventDisableTiming);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&X->ev_join, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&X->ev_pj, hipEventDisableTiming);
   if (e == hipSuccess && X->insts.size() > 1) {
     e = hipEventCreateWithFlags(&X->ev_start, hipEventDisableTiming);
     X->lanes.resize(std::min<size_t>(X->insts.size(), kMaxLanes));
@@ -1732,6 +1744,7 @@ d2ip_status d2ip_create(const d2ip_geometry_desc* geos, int n_geo, const d2ip_in
       if (e == hipSuccess) e = hipEventCreateWithFlags(&l.fork, hipEventDisableTiming);
       if (e == hipSuccess) e = hipEventCreateWithFlags(&l.join, hipEventDisableTiming);
       if (e == hipSuccess) e = hipEventCreateWithFlags(&l.done, hipEventDisableTiming);
+      if (e == hipSuccess) e = hipEventCreateWithFlags(&l.pj, hipEventDisableTiming);
     }
   }
   if (e != hipSuccess)
@@ -1750,6 +1763,7 @@ d2ip_status d2ip_destroy(d2ip_ctx* X) {
     if (l.side) hipStreamSynchronize(l.side);
   }
   release_lanes(X);
+  if (X->ev_pj) hipEventDestroy(X->ev_pj);
   if (X->ev_join) hipEventDestroy(X->ev_join);
   if (X->ev_fork) hipEventDestroy(X->ev_fork);
   if (X->side) hipStreamDestroy(X->side);

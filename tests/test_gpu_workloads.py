@@ -152,7 +152,9 @@ def test_eight_sequences_tpp_against_stored_oracle(lib, graph):
     gradient no such oracle gradient explains to 1e-5) within 1e-5; the
     departing iteration entered with the GPU's image within 1e-5 of the
     oracle's (the state going in was the same); frames after it held only to
-    1e-3, a guard against gross errors, not a parity bound."""
+    5e-2, a guard against gross errors, not a parity bound (two trajectories
+    that part at iteration 3 of 10 measured 1.5e-2 apart at the last frame;
+    without the shadow they reach 0.25)."""
     path = os.path.join(GOLDEN, "oracle_c3_tpp.npz")
     if not os.path.exists(path):
         pytest.skip("no stored eight-sequence oracle run")
@@ -210,6 +212,6 @@ def test_eight_sequences_tpp_against_stored_oracle(lib, graph):
             if dep is None or ends[f] < dep:
                 assert sh["image_rel"][f] < 1e-5, (i, f, sh)
             else:
-                assert sh["image_rel"][f] < 1e-3, (i, f, sh)
+                assert sh["image_rel"][f] < 5e-2, (i, f, sh)
         if dep is not None:
             assert sh["entry"][dep - 1] < 1e-5, (i, sh)
