@@ -409,14 +409,16 @@ d2ip_status d2ip_op_conv3d_backward(const float* x, const float* w, const float*
 d2ip_status d2ip_op_ln_relu_bytes(int n, int C, size_t* out);
 
 /* y = relu(gamma_c * (x - mean) / sqrt(var + 1e-5) + beta_c + skip), with
- * mean and (biased) variance over all n^3 x C values of x; skip may be NULL. */
+ * mean and (biased) variance over all n^3 x C values of x; skip may be NULL.
+ * x, y and skip 16-byte aligned (D2IP_EINVAL otherwise). */
 d2ip_status d2ip_op_ln_relu_forward(const float* x, const float* gamma, const float* beta,
                                     const float* skip, float* y, int n, int C, void* workspace,
                                     size_t bytes, void* hip_stream);
 
 /* Backward of d2ip_op_ln_relu_forward given its input x, output y and
  * gy = dL/dy: gx = dL/dx, gskip = dL/dskip (the ReLU-masked gy) and
- * dgamma_dbeta = [dL/dgamma (C), dL/dbeta (C)]; outputs may be NULL. */
+ * dgamma_dbeta = [dL/dgamma (C), dL/dbeta (C)]; outputs may be NULL.
+ * x, y, gy, gx and gskip 16-byte aligned (D2IP_EINVAL otherwise). */
 d2ip_status d2ip_op_ln_relu_backward(const float* x, const float* y, const float* gamma,
                                      const float* gy, float* gx, float* gskip,
                                      float* dgamma_dbeta, int n, int C, void* workspace,
