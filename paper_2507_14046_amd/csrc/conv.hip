@@ -19,9 +19,12 @@ __device__ __forceinline__ float strided_sum(const float* x, long long stride, i
 #pragma unroll
     for (int u = 0; u < 8; ++u) a[u] += v[u];
   }
+  float r[7];  // at most 7 left: all loads issued, then added in the same order
 #pragma unroll
-  for (int u = 0; u < 7; ++u)  // at most 7 left
-    if (k + u * step < n) a[u] += x[(long long)(k + u * step) * stride];
+  for (int u = 0; u < 7; ++u) r[u] = k + u * step < n ? x[(long long)(k + u * step) * stride] : 0.f;
+#pragma unroll
+  for (int u = 0; u < 7; ++u)
+    if (k + u * step < n) a[u] += r[u];
   return ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
 }
 
@@ -42,15 +45,31 @@ __global__ void k_grad_reduce(const GradSeg* __restrict__ segs, const float* par
   }
   if (sg.kind == 1) {
     // column sums of double partials [splits][cout]: 8 columns per pass, 32
-    // row groups (rows g, g + 32, ...) combined in group order
+    // row groups (rows g, g + 32, ...) combined in group order; a group adds
+    // its rows in row order, eight loads in flight
     __shared__ double shd[32][8];
     const double* D = dpart + sg.part_off;
     const int col = threadIdx.x & 7, rg = threadIdx.x >> 3;
     for (int k0 = blockIdx.x * 8; k0 < sg.cout; k0 += gridDim.x * 8) {
       const int k = k0 + col;
       double acc = 0.0;
-      if (k < sg.cout)
-        for (int i = rg; i < sg.splits; i += 32) acc += D[(long long)i * sg.cout + k];
+      if (k < sg.cout) {
+        int i = rg;
+        for (; i + 7 * 32 < sg.splits; i += 8 * 32) {
+          double v[8];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) v[u] = D[(long long)(i + 32 * u) * sg.cout + k];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) acc += v[u];
+        }
+        double r[7];  // at most 7 rows left
+#pragma unroll
+        for (int u = 0; u < 7; ++u)
+          r[u] = i + 32 * u < sg.splits ? D[(long long)(i + 32 * u) * sg.cout + k] : 0.0;
+#pragma unroll
+        for (int u = 0; u < 7; ++u)
+          if (i + 32 * u < sg.splits) acc += r[u];
+      }
       shd[rg][col] = acc;
       __syncthreads();
       if (rg == 0 && k < sg.cout) {

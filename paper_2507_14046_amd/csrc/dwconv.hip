@@ -425,9 +425,12 @@ __global__ __launch_bounds__(256) void k_dw_wreduce(const float* __restrict__ pa
 #pragma unroll
     for (int u = 0; u < 8; ++u) a[u] += v[u];
   }
+  float r[7];  // the rest: every load issued, then added in the same order
+#pragma unroll
+  for (int u = 0; u < 7; ++u) r[u] = j + 64 * u < nP ? p[j + 64 * u] : 0.f;
 #pragma unroll
   for (int u = 0; u < 7; ++u)
-    if (j + 64 * u < nP) a[u] += p[j + 64 * u];
+    if (j + 64 * u < nP) a[u] += r[u];
   const float s = wave_sum(((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7])));
   if (lane == 0) {
     const int c = e / kDwParts, k = e - c * kDwParts;

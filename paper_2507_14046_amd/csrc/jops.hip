@@ -418,6 +418,27 @@ __device__ __forceinline__ void put_bf(uint16_t* w, long long i, long long lo_of
   if (lo_off) w[lo_off + i] = f2bf(val - bf2f(hi));
 }
 
+// p[0] + p[1] + ... + p[n-1], added in index order, with eight loads in
+// flight (one thread).
+__device__ __forceinline__ double ordered_sum(const double* p, int n) {
+  double s = 0.0;
+  int k = 0;
+  for (; k + 8 <= n; k += 8) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = p[k + u];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) s += v[u];
+  }
+  double v[7];
+#pragma unroll
+  for (int u = 0; u < 7; ++u) v[u] = k + u < n ? p[k + u] : 0.0;
+#pragma unroll
+  for (int u = 0; u < 7; ++u)
+    if (k + u < n) s += v[u];
+  return s;
+}
+
 __global__ void k_pack_weights(const ConvPack* __restrict__ packs, const float* theta,
                                float* wf32, uint16_t* wbf16, long long lo_off, IterState* it,
                                const double* rsum, int nrs, int M, const double* tvsum, int ntv,
@@ -428,11 +449,9 @@ __global__ void k_pack_weights(const ConvPack* __restrict__ packs, const float* 
     it = ishift(it, off); rsum = ishift(rsum, off); tvsum = ishift(tvsum, off);
   }
   if (it && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) {
-    double L = 0.0;
-    for (int k = 0; k < nrs; ++k) L += rsum[k];
+    double L = ordered_sum(rsum, nrs);
     L /= M;
-    double R = 0.0;
-    for (int k = 0; k < ntv; ++k) R += tvsum[k];
+    const double R = ordered_sum(tvsum, ntv);
     L += R;
     it->loss = L;
     if (!isfinite(L)) it->nonfinite = 1;

@@ -253,9 +253,12 @@ __global__ __launch_bounds__(256) void k_pw_psum(const float* __restrict__ part,
 #pragma unroll
     for (int u = 0; u < 8; ++u) a[u] += v[u];
   }
+  float r[7];  // the rest: every load issued, then added in the same order
+#pragma unroll
+  for (int u = 0; u < 7; ++u) r[u] = c + u < c1 ? part[(size_t)(c + u) * per + e] : 0.f;
 #pragma unroll
   for (int u = 0; u < 7; ++u)
-    if (c + u < c1) a[u] += part[(size_t)(c + u) * per + e];
+    if (c + u < c1) a[u] += r[u];
   out[(size_t)blockIdx.y * per + e] =
       ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
 }
@@ -275,9 +278,12 @@ __global__ __launch_bounds__(256) void k_pw_wreduce(const float* __restrict__ pa
 #pragma unroll
     for (int u = 0; u < 8; ++u) a[u] += v[u];
   }
+  float r[7];  // the rest: every load issued, then added in the same order
+#pragma unroll
+  for (int u = 0; u < 7; ++u) r[u] = c + u < nchunks ? part[(size_t)(c + u) * per + e] : 0.f;
 #pragma unroll
   for (int u = 0; u < 7; ++u)
-    if (c + u < nchunks) a[u] += part[(size_t)(c + u) * per + e];
+    if (c + u < nchunks) a[u] += r[u];
   const float s = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
   if (e < (size_t)NK) {
     if (gw) gw[e] = s;

@@ -96,9 +96,12 @@ __global__ __launch_bounds__(256) void k_se_psum(const float* __restrict__ part,
 #pragma unroll
     for (int u = 0; u < 8; ++u) a[u] += v[u];
   }
+  float r[7];  // the rest: every load issued, then added in the same order
+#pragma unroll
+  for (int u = 0; u < 7; ++u) r[u] = k + u < k1 ? part[(size_t)(k + u) * C + c] : 0.f;
 #pragma unroll
   for (int u = 0; u < 7; ++u)
-    if (k + u < k1) a[u] += part[(size_t)(k + u) * C + c];
+    if (k + u < k1) a[u] += r[u];
   gsum[(size_t)blockIdx.y * C + c] = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
 }
 
@@ -113,9 +116,12 @@ __device__ __forceinline__ double se_sum(const double* gsum, int ngroups, int C,
 #pragma unroll
     for (int u = 0; u < 8; ++u) a[u] += v[u];
   }
+  double r[7];  // the rest: every load issued, then added in the same order
+#pragma unroll
+  for (int u = 0; u < 7; ++u) r[u] = g + u < ngroups ? gsum[(size_t)(g + u) * C + c] : 0.0;
 #pragma unroll
   for (int u = 0; u < 7; ++u)
-    if (g + u < ngroups) a[u] += gsum[(size_t)(g + u) * C + c];
+    if (g + u < ngroups) a[u] += r[u];
   return ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
 }
 
