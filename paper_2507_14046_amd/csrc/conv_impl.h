@@ -886,7 +886,10 @@ __global__ __launch_bounds__(256) void k_conv_wgrad(ConvWgrad a) {
     if (t + (int)gridDim.x < ntiles) issue(t + gridDim.x);
     // ---- 3x3x3: every wave its own column tiles over all voxel k-steps;
     // 1x1x1: every wave all column tiles over k-steps ks = wave, wave + 4, ...
-#pragma unroll 2
+    // A column past the last (tap, channel) reads an in-range halo word
+    // (tap 0): column j of an MFMA product depends on column j of B alone, and
+    // those accumulators are never written out, so FP32 needs no zero select.
+#pragma unroll 8
     for (int ks = WCOLS ? 0 : wave; ks < NSTEP; ks += WCOLS ? 1 : 4) {
       FT A, Al;
       FT B[NJ], Bl[MD::SPLIT ? NJ : 1];
@@ -908,7 +911,7 @@ __global__ __launch_bounds__(256) void k_conv_wgrad(ConvWgrad a) {
         const int tz = v / (TY * TX), ty = (v / TX) % TY, tx = v % TX;
         const int vp = ((tz * HY + ty) * HX + tx) * ckp;
 #pragma unroll
-        for (int j = 0; j < NJ; ++j) B[j] = frag<MODE>(hal + vp + coff[j], cval[j]);
+        for (int j = 0; j < NJ; ++j) B[j] = frag<MODE>(hal + vp + coff[j], true);
       }
 #pragma unroll
       for (int j = 0; j < NJ; ++j) {
