@@ -176,13 +176,6 @@ __device__ __forceinline__ bool arrive_last(int* counter, int nblocks) {
   return last;
 }
 
-// Device-coherent loads of data other blocks of the same launch wrote.
-__device__ __forceinline__ float load_dev(const float* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ double load_dev(const double* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
 
 // Members of an instance group share every shape; member b's data lives
 // b * istride bytes after member 0's.  A kernel shifts its per-member pointers.

@@ -586,10 +586,14 @@ __global__ __launch_bounds__(256) void k_conv_fwd(ConvFwd a) {
       }
     }
     if (!arrive_last(a.counters + tile_id, ksplit)) return;
+    // the other splits' partials are visible after arrive_last's acquire;
+    // every element sums them in split order, and one split's loads of all
+    // this lane's elements are in flight together
+    size_t o[TPW][4];
+    bool ok[TPW][4];
 #pragma unroll
     for (int j = 0; j < TPW; ++j) {
       const int t = wave + 4 * j;
-      if (t >= NTILE) continue;
       const int mt = t / NT, nt = t - mt * NT;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
@@ -597,12 +601,23 @@ __global__ __launch_bounds__(256) void k_conv_fwd(ConvFwd a) {
         const int tz = li / (TY * TX), ty = (li / TX) % TY, tx = li % TX;
         const int gz = z0 + tz, gy = y0 + ty, gx = x0 + tx;
         const int co = co0 + nt * 16 + l16;
-        if (gz >= n || gy >= n || gx >= n || co >= a.cout) continue;
-        const size_t o = ((size_t)(gz * n + gy) * n + gx) * a.cout + co;
-        float sum = 0.f;
-        for (int k = 0; k < ksplit; ++k) sum += load_dev(a.kpart + (size_t)k * V * a.cout + o);
-        fin[j][r] = sum;
+        ok[j][r] = t < NTILE && gz < n && gy < n && gx < n && co < a.cout;
+        o[j][r] = ok[j][r] ? ((size_t)(gz * n + gy) * n + gx) * a.cout + co : 0;
+        fin[j][r] = 0.f;
       }
+    }
+    for (int k = 0; k < ksplit; ++k) {
+      const float* kp = a.kpart + (size_t)k * V * a.cout;
+      float v[TPW][4];
+#pragma unroll
+      for (int j = 0; j < TPW; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) v[j][r] = ok[j][r] ? kp[o[j][r]] : 0.f;
+#pragma unroll
+      for (int j = 0; j < TPW; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          if (ok[j][r]) fin[j][r] += v[j][r];
     }
   }
 
