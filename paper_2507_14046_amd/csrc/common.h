@@ -154,29 +154,6 @@ __device__ __forceinline__ void stat_coef_of(const PairRef& st, const PairRef& b
   c.B = (float)(s4 / bw.count);
 }
 
-// "Last block finalises": called by every thread of a block after the block
-// stored its partial results.  Returns true (uniform over the block) in the
-// block that arrives last among `nblocks` arrivals on `counter`; that block
-// resets the counter to zero, so the next launch (or graph replay) finds it
-// zeroed.  No block ever waits on another.
-__device__ __forceinline__ bool arrive_last(int* counter, int nblocks) {
-  __shared__ int s_last;
-  // release this block's partials at device scope (L2 write-back only; a
-  // seq_cst fence would also invalidate this XCD's L2 for every block)
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    const int prev = atomicAdd(counter, 1);
-    s_last = prev == nblocks - 1;
-    if (s_last) atomicExch(counter, 0);
-  }
-  __syncthreads();
-  const bool last = s_last != 0;
-  if (last) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");  // see the other blocks' partials
-  return last;
-}
-
-
 // Members of an instance group share every shape; member b's data lives
 // b * istride bytes after member 0's.  A kernel shifts its per-member pointers.
 template <class T>

@@ -132,6 +132,7 @@ void conv_fwd(const ConvFwd& a, hipStream_t s) {
     case PREC_BF16X3: conv_fwd_bf16x3(a, s); break;
     default: conv_fwd_f32(a, s); break;
   }
+  if (a.ksplit > 1) conv_detail::launch_finish(a, s);
 }
 
 int conv_wgrad_groups(int taps, int ck) {

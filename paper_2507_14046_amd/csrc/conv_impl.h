@@ -8,10 +8,10 @@
 // pending transform on the fly (LayerNorm+ReLU, or the LayerNorm backward),
 // then each wave issues 16x16 MFMAs: v_mfma_f32_16x16x4_f32 (FP32 operands)
 // or v_mfma_f32_16x16x32_bf16 (BF16 operands); accumulation is FP32.  Coarse
-// grids split the channel chunks over blocks (split-K); the last block of
-// each output tile sums the partials in a fixed order.  The epilogue adds
-// bias / residual, stores, and emits per-tile FP64 (sum, sumsq) partials; the
-// last tile turns them into the LayerNorm statistics of the output.
+// grids split the channel chunks over blocks (split-K); a second launch sums
+// each output's partials in split order.  The epilogue adds bias / residual,
+// stores, and emits per-tile FP64 (sum, sumsq) partials, which the consumer
+// reduces into the LayerNorm statistics of the output.
 //
 // Weight-gradient kernel: rows are output channels (16 per block), columns
 // (tap, channel) in groups of 128 per block, the reduction runs over voxels;
@@ -340,6 +340,54 @@ __device__ __forceinline__ typename Mode<MODE>::FT frag(const typename Mode<MODE
 
 // CK: the channel chunk, fixed at compile time for 3x3x3 (8, 16 or 32; it
 // sizes the halo prefetch), 0 for 1x1x1 (read from the arguments).
+// Epilogue of a forward tile: y = result (+ bias) (+ add) (+ y) and the
+// tile's (sum, sum of squares) of y.  fin[j] holds this lane's part of
+// accumulator tile t = wave + 4 j: rows 4 g .. 4 g + 3 of row block t / NT,
+// column l16 of column block t % NT.  Contains barriers (block_sum).
+template <int TILE, int BN, int TPW>
+__device__ __forceinline__ void fwd_epilogue(const ConvFwd& a, const f32x4 (&fin)[TPW], int x0,
+                                             int y0, int z0, int co0, int tile_id, double* red) {
+  using TD = TileDims<TILE>;
+  constexpr int TZ = TD::Z, TY = TD::Y, TX = TD::X;
+  constexpr int MT = TZ * TY * TX / 16, NT = BN / 16, NTILE = MT * NT;
+  static_assert(TPW == (NTILE + 3) / 4, "tiles per wave");
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int l16 = lane & 15, g = lane >> 4;
+  const int n = a.n;
+  double s1 = 0.0, s2 = 0.0;
+#pragma unroll
+  for (int j = 0; j < TPW; ++j) {
+    const int t = wave + 4 * j;
+    if (t >= NTILE) continue;
+    const int mt = t / NT, nt = t - mt * NT;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int li = mt * 16 + 4 * g + r;
+      const int tz = li / (TY * TX), ty = (li / TX) % TY, tx = li % TX;
+      const int gz = z0 + tz, gy = y0 + ty, gx = x0 + tx;
+      const int co = co0 + nt * 16 + l16;
+      if (gz >= n || gy >= n || gx >= n || co >= a.cout) continue;
+      const size_t o = ((size_t)(gz * n + gy) * n + gx) * a.cout + co;
+      float v = fin[j][r];
+      if (a.bias) v += a.bias[co];
+      if (a.add) v += a.add[o];
+      if (a.accumulate) v += a.y[o];
+      a.y[o] = v;
+      s1 += v;
+      s2 += (double)v * v;
+    }
+  }
+  if (a.stat_part) {
+    s1 = block_sum(s1, red);
+    s2 = block_sum(s2, red);
+    if (tid == 0) {
+      a.stat_part[2 * tile_id] = s1;
+      a.stat_part[2 * tile_id + 1] = s2;
+    }
+  }
+}
+
 template <int MODE, int TAPS, int TILE, int BN, int PRO, int CK>
 __global__ __launch_bounds__(256) void k_conv_fwd(ConvFwd a) {
   // grid z = member * ksplit + split
@@ -354,7 +402,6 @@ __global__ __launch_bounds__(256) void k_conv_fwd(ConvFwd a) {
     a.y = ishift(a.y, off);
     a.stat_part = ishift(a.stat_part, off);
     a.kpart = ishift(a.kpart, off);
-    a.counters = ishift(a.counters, off);
   }
   using MD = Mode<MODE>;
   using ST = typename MD::ST;
@@ -565,10 +612,10 @@ __global__ __launch_bounds__(256) void k_conv_fwd(ConvFwd a) {
   }
 
   const int tile_id = blockIdx.y * gridDim.x + blockIdx.x;
-  const size_t V = (size_t)n * n * n;
   if (ksplit > 1) {
-    // split-K: publish this block's partial tile; the last block of the tile
-    // sums all partials in split order and continues with the epilogue
+    // split-K: publish this block's partial tile; k_fwd_finish sums the
+    // splits in split order and runs the epilogue after this launch
+    const size_t V = (size_t)n * n * n;
     float* kp = a.kpart + (size_t)kz * V * a.cout;
 #pragma unroll
     for (int j = 0; j < TPW; ++j) {
@@ -585,47 +632,50 @@ __global__ __launch_bounds__(256) void k_conv_fwd(ConvFwd a) {
         kp[((size_t)(gz * n + gy) * n + gx) * a.cout + co] = fin[j][r];
       }
     }
-    if (!arrive_last(a.counters + tile_id, ksplit)) return;
-    // the other splits' partials are visible after arrive_last's acquire;
-    // every element sums them in split order, and one split's loads of all
-    // this lane's elements are in flight together
-    size_t o[TPW][4];
-    bool ok[TPW][4];
-#pragma unroll
-    for (int j = 0; j < TPW; ++j) {
-      const int t = wave + 4 * j;
-      const int mt = t / NT, nt = t - mt * NT;
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int li = mt * 16 + 4 * g + r;
-        const int tz = li / (TY * TX), ty = (li / TX) % TY, tx = li % TX;
-        const int gz = z0 + tz, gy = y0 + ty, gx = x0 + tx;
-        const int co = co0 + nt * 16 + l16;
-        ok[j][r] = t < NTILE && gz < n && gy < n && gx < n && co < a.cout;
-        o[j][r] = ok[j][r] ? ((size_t)(gz * n + gy) * n + gx) * a.cout + co : 0;
-        fin[j][r] = 0.f;
-      }
-    }
-    for (int k = 0; k < ksplit; ++k) {
-      const float* kp = a.kpart + (size_t)k * V * a.cout;
-      float v[TPW][4];
-#pragma unroll
-      for (int j = 0; j < TPW; ++j)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) v[j][r] = ok[j][r] ? kp[o[j][r]] : 0.f;
-#pragma unroll
-      for (int j = 0; j < TPW; ++j)
-#pragma unroll
-        for (int r = 0; r < 4; ++r)
-          if (ok[j][r]) fin[j][r] += v[j][r];
-    }
+    return;
   }
+  fwd_epilogue<TILE, BN>(a, fin, x0, y0, z0, co0, tile_id, red);
+}
 
-  double s1 = 0.0, s2 = 0.0;
+// Sum of the split-K partial tiles of a forward pass, in split order, then
+// the epilogue; same grid (x, y) as the pass, z = group member.  Partials
+// written by the previous launch are visible at the kernel boundary, so no
+// block of the pass waits on or signals another.
+template <int TILE, int BN>
+__global__ __launch_bounds__(256) void k_fwd_finish(ConvFwd a) {
+  {
+    const long long off = (long long)blockIdx.z * a.istride;
+    a.bias = ishift(a.bias, off);
+    a.add = ishift(a.add, off);
+    a.y = ishift(a.y, off);
+    a.stat_part = ishift(a.stat_part, off);
+    a.kpart = ishift(a.kpart, off);
+  }
+  using TD = TileDims<TILE>;
+  constexpr int TZ = TD::Z, TY = TD::Y, TX = TD::X;
+  constexpr int MT = TZ * TY * TX / 16, NT = BN / 16, NTILE = MT * NT, TPW = (NTILE + 3) / 4;
+  __shared__ double red[8];
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int l16 = lane & 15, g = lane >> 4;
+  const int n = a.n;
+  const int ntx = (n + TX - 1) / TX, nty = (n + TY - 1) / TY;
+  int b = blockIdx.x;
+  const int x0 = (b % ntx) * TX;
+  b /= ntx;
+  const int y0 = (b % nty) * TY;
+  b /= nty;
+  const int z0 = b * TZ;
+  const int co0 = blockIdx.y * BN;
+  const size_t V = (size_t)n * n * n;
+  // every element sums the splits in split order; one split's loads of all
+  // this lane's elements are in flight together
+  size_t o[TPW][4];
+  bool ok[TPW][4];
+  f32x4 fin[TPW];
 #pragma unroll
   for (int j = 0; j < TPW; ++j) {
     const int t = wave + 4 * j;
-    if (t >= NTILE) continue;
     const int mt = t / NT, nt = t - mt * NT;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
@@ -633,25 +683,25 @@ __global__ __launch_bounds__(256) void k_conv_fwd(ConvFwd a) {
       const int tz = li / (TY * TX), ty = (li / TX) % TY, tx = li % TX;
       const int gz = z0 + tz, gy = y0 + ty, gx = x0 + tx;
       const int co = co0 + nt * 16 + l16;
-      if (gz >= n || gy >= n || gx >= n || co >= a.cout) continue;
-      const size_t o = ((size_t)(gz * n + gy) * n + gx) * a.cout + co;
-      float v = fin[j][r];
-      if (a.bias) v += a.bias[co];
-      if (a.add) v += a.add[o];
-      if (a.accumulate) v += a.y[o];
-      a.y[o] = v;
-      s1 += v;
-      s2 += (double)v * v;
+      ok[j][r] = t < NTILE && gz < n && gy < n && gx < n && co < a.cout;
+      o[j][r] = ok[j][r] ? ((size_t)(gz * n + gy) * n + gx) * a.cout + co : 0;
+      fin[j][r] = 0.f;
     }
   }
-  if (a.stat_part) {
-    s1 = block_sum(s1, red);
-    s2 = block_sum(s2, red);
-    if (tid == 0) {
-      a.stat_part[2 * tile_id] = s1;
-      a.stat_part[2 * tile_id + 1] = s2;
-    }
+  for (int k = 0; k < a.ksplit; ++k) {
+    const float* kp = a.kpart + (size_t)k * V * a.cout;
+    float v[TPW][4];
+#pragma unroll
+    for (int j = 0; j < TPW; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) v[j][r] = ok[j][r] ? kp[o[j][r]] : 0.f;
+#pragma unroll
+    for (int j = 0; j < TPW; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        if (ok[j][r]) fin[j][r] += v[j][r];
   }
+  fwd_epilogue<TILE, BN>(a, fin, x0, y0, z0, co0, blockIdx.y * gridDim.x + blockIdx.x, red);
 }
 
 // Weight-gradient LDS (dynamic): halo, g tile and the cross-wave exchange.
@@ -1047,6 +1097,32 @@ void fwd_bn(const ConvFwd& a, hipStream_t s) {
     default:
       if constexpr (TILE != TILE_2x4x16) fwd_pro<MODE, TAPS, TILE, 64>(a, s);
       break;
+  }
+}
+
+template <int TILE, int BN>
+void launch_finish_bn(const ConvFwd& a, hipStream_t s) {
+  dim3 grid(spatial_tiles(a.n, TILE), (a.cout + BN - 1) / BN, a.batch);
+  hipLaunchKernelGGL((k_fwd_finish<TILE, BN>), grid, dim3(256), 0, s, a);
+}
+
+template <int TILE>
+void launch_finish_tile(const ConvFwd& a, hipStream_t s) {
+  switch (a.bn) {
+    case 16: launch_finish_bn<TILE, 16>(a, s); break;
+    case 32: launch_finish_bn<TILE, 32>(a, s); break;
+    default:
+      if constexpr (TILE != TILE_2x4x16) launch_finish_bn<TILE, 64>(a, s);
+      break;
+  }
+}
+
+// The split-K finishing launch of a forward pass (ksplit > 1).
+inline void launch_finish(const ConvFwd& a, hipStream_t s) {
+  switch (a.tile) {
+    case TILE_2x4x16: launch_finish_tile<TILE_2x4x16>(a, s); break;
+    case TILE_1x4x16: launch_finish_tile<TILE_1x4x16>(a, s); break;
+    default: launch_finish_tile<TILE_1x8x8>(a, s); break;
   }
 }
 

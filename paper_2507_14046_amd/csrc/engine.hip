@@ -170,7 +170,6 @@ struct Instance {
   double* tail_part = nullptr;
   double* rsum = nullptr;
   float* kpart = nullptr;   // split-K partial outputs
-  int* counters = nullptr;  // zeroed arrival counters of split-K tiles
   // 4D-TV: gradient w.r.t. the image, per-block loss partials, image history
   float *gtv = nullptr, *hist = nullptr;
   double* tvsum = nullptr;
@@ -387,7 +386,7 @@ const d2ip_tuning_entry* find_tuned(int n, int cin, int cout, int taps, int pass
 }
 
 // Launch shapes, packing table and weight-gradient partial regions of a conv.
-void add_conv(Instance& I, Conv& c, int precision, size_t& kpart_max, int& tiles_max) {
+void add_conv(Instance& I, Conv& c, int precision, size_t& kpart_max) {
   const int prec = conv_prec(precision);
   c.wf = I.wtotal;
   I.wtotal += (long long)c.cout * c.taps * c.cin;
@@ -418,7 +417,6 @@ void add_conv(Instance& I, Conv& c, int precision, size_t& kpart_max, int& tiles
     c.fwd.ck = t->shape.ck;
     c.fwd.ksplit = t->shape.split;
   }
-  tiles_max = std::max(tiles_max, conv_tiles(c.n, c.fwd.tile) * ((c.cout + c.fwd.bn - 1) / c.fwd.bn));
   if (c.fwd.ksplit > 1) kpart_max = std::max(kpart_max, (size_t)c.fwd.ksplit * V * c.cout);
   if (c.dgrad) {
     c.bwd = choose_shape(c.n, c.cout, c.cin_real, c.taps, prec);
@@ -431,8 +429,6 @@ void add_conv(Instance& I, Conv& c, int precision, size_t& kpart_max, int& tiles
       c.bwd.ck = t->shape.ck;
       c.bwd.ksplit = t->shape.split;
     }
-    tiles_max = std::max(tiles_max,
-                         conv_tiles(c.n, c.bwd.tile) * ((c.cin_real + c.bwd.bn - 1) / c.bwd.bn));
     if (c.bwd.ksplit > 1) kpart_max = std::max(kpart_max, (size_t)c.bwd.ksplit * V * c.cin_real);
   }
   // weight gradient: voxel splits sized so that about 512 blocks run
@@ -565,7 +561,6 @@ void plan(d2ip_ctx& X, const d2ip_geometry_desc* gd, int n_geo, const d2ip_insta
   const int prec = conv_prec(X.precision);
   for (size_t gi = 0; gi < X.insts.size(); ++gi) {
     size_t kpart_max = 0;
-    int tiles_max = 1;
     Instance& I = X.insts[gi];
     I.has_frame.assign(I.B, 0);
     I.has_z.assign(I.B, 0);
@@ -589,11 +584,11 @@ void plan(d2ip_ctx& X, const d2ip_geometry_desc* gd, int n_geo, const d2ip_insta
       b.c1.pro_wg = PRO_LN_BWD;
       b.c2.pro_wg = 3 * PRO_LN_RELU + PRO_LN_BWD;
     }
-    add_conv(I, I.stem, X.precision, kpart_max, tiles_max);
+    add_conv(I, I.stem, X.precision, kpart_max);
     for (Block& b : I.blocks) {
-      add_conv(I, b.c1, X.precision, kpart_max, tiles_max);
-      add_conv(I, b.c2, X.precision, kpart_max, tiles_max);
-      if (b.proj) add_conv(I, b.pj, X.precision, kpart_max, tiles_max);
+      add_conv(I, b.c1, X.precision, kpart_max);
+      add_conv(I, b.c2, X.precision, kpart_max);
+      if (b.proj) add_conv(I, b.pj, X.precision, kpart_max);
     }
     // FP64 partial arena: statistics of every LayerNorm input, LayerNorm
     // backward partials, head gradient and residual sums (offsets in doubles)
@@ -722,7 +717,6 @@ void plan(d2ip_ctx& X, const d2ip_geometry_desc* gd, int n_geo, const d2ip_insta
     I.tv_count.assign(I.B, 0);
     I.tv_head.assign(I.B, kTvHistory - 1);
     I.kpart = cv.take<float>(std::max<size_t>(kpart_max, 1));
-    I.counters = cv.take<int>((size_t)tiles_max + 64);
     // members 1.. follow member 0 at a fixed stride
     cv.off = (cv.off + 255) & ~size_t(255);
     I.istride = (long long)(cv.off - region0);
@@ -783,7 +777,6 @@ void L_conv_fwd(const ConvFwd& a, hipStream_t s) {
   c.range(a.stat_part, (size_t)tiles * 2 * sizeof(double), "stat partials", B, is);
   if (a.ksplit > 1) {
     c.range(a.kpart, (size_t)a.ksplit * V * a.cout * sizeof(float), "split-K partials", B, is);
-    c.range(a.counters, (size_t)tiles * sizeof(int), "counters", B, is);
   }
 }
 
@@ -1040,7 +1033,6 @@ ConvFwd fwd_args(const d2ip_ctx& X, const Instance& I, const Conv& c, ConvSrc sr
   a.ck = c.fwd.ck;
   a.ksplit = c.fwd.ksplit;
   a.kpart = I.kpart;
-  a.counters = I.counters;
   a.batch = I.B;
   a.istride = I.istride;
   return a;
@@ -1066,7 +1058,6 @@ ConvFwd dgrad_args(const d2ip_ctx& X, const Instance& I, const Conv& c, ConvSrc 
   a.ck = c.bwd.ck;
   a.ksplit = c.bwd.ksplit;
   a.kpart = I.kpart;
-  a.counters = I.counters;
   a.batch = I.B;
   a.istride = I.istride;
   return a;
@@ -1342,7 +1333,6 @@ struct TimeConvBufs {
   float *bias = nullptr, *kpart = nullptr, *part = nullptr, *partb = nullptr;
   void* w = nullptr;
   double *st = nullptr, *stat = nullptr;
-  int* counters = nullptr;
 };
 
 void carve_time_conv(const d2ip_tuning_entry& e, Carver& cv, TimeConvBufs& b) {
@@ -1366,7 +1356,6 @@ void carve_time_conv(const d2ip_tuning_entry& e, Carver& cv, TimeConvBufs& b) {
   const int tiles = conv_tiles(e.n, e.shape.tile) * ((kout + std::max(e.shape.bn, 16) - 1) /
                                                      std::max(e.shape.bn, 16));
   b.stat = cv.take<double>(2 * (size_t)tiles);
-  b.counters = cv.take<int>((size_t)tiles + 64);
   b.kpart = cv.take<float>(std::max<size_t>(1, (size_t)e.shape.split * V * kout));
   const size_t cout16 = (e.cout + 15) / 16 * 16;
   b.part = cv.take<float>((size_t)e.shape.split * cout16 * e.taps * e.cin);
@@ -1648,7 +1637,6 @@ d2ip_status d2ip_time_conv(const d2ip_tuning_entry* e, void* workspace, size_t b
       a.ck = e->shape.ck;
       a.ksplit = e->shape.split;
       a.kpart = b.kpart;
-      a.counters = b.counters;
       a.batch = 1;
       conv_fwd(a, s);
     }
@@ -1716,7 +1704,7 @@ d2ip_status d2ip_create(const d2ip_geometry_desc* geos, int n_geo, const d2ip_in
     delete X;
     return s;
   };
-  // zero everything once: padding of packed weights and J, state, counters
+  // zero everything once: padding of packed weights and J, state
   hipError_t e = hipMemsetAsync(workspace, 0, need, X->stream);
   if (e == hipSuccess) {
     for (Instance& I : X->insts) {

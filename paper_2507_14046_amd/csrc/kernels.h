@@ -47,8 +47,8 @@ __host__ __device__ inline ConvSrc shift_src(ConvSrc s, long long off) {
 // (+ add[v][co]); NDHWC tensors on an n^3 grid, zero padding.  Used for the
 // forward conv (Wp = forward packing) and the input gradient (Wp = flipped,
 // transposed packing).  With ksplit > 1 the channel chunks are split over
-// blocks; the last block of each output tile sums the partials in a fixed
-// order and runs the epilogue.  With stat_part set, every output tile writes
+// blocks, which store partial tiles; a second launch (conv_fwd issues it)
+// sums them in split order and runs the epilogue.  With stat_part set, every output tile writes
 // the (sum, sumsq) pair of its outputs for the following LayerNorm.
 struct ConvFwd {
   ConvSrc src;
@@ -64,8 +64,7 @@ struct ConvFwd {
   int taps;              // 27 or 1
   double* stat_part;     // per-tile (sum, sumsq) of y, or null
   int prec, tile, bn, ck, ksplit;
-  float* kpart;          // [ksplit][n^3][cout] (ksplit > 1)
-  int* counters;         // ksplit > 1: >= tiles zeroed ints (left zeroed)
+  float* kpart;          // [ksplit][n^3][cout] (ksplit > 1; a second launch sums them)
   int batch;             // group members (grid z = ksplit * batch)
   long long istride;     // bytes between members' data
 };
@@ -223,9 +222,6 @@ inline int jt_partials(int M, int qa_pad) {
 
 void gather_columns(const float* J, int M, int Q, const int* idx, int qa, int qa_pad, float* Jc,
                     hipStream_t s);
-// ppart[qb][m] = sum_{q in block qb} Jc[m][q] * sigma[idx[q]]; then, by the
-// last block: r = sum_qb ppart - dv, loss = (1/M) sum r^2 (FP64), gp = (2/M) r,
-// Adam step counter t += 1 with its bias corrections.
 // ppart[qb][m] = sum_{q in column block qb} Jc[m][q] * sigma[idx[q]]
 void jvec(const float* Jc, int M, int qa_pad, const int* idx, const float* sigma, float* ppart,
           int batch, long long istride, hipStream_t s);

@@ -68,7 +68,6 @@ struct ConvOp {
   uint16_t* wbf16 = nullptr;
   long long wtotal = 0;
   float *kpart = nullptr, *part = nullptr, *partb = nullptr, *grad = nullptr;
-  int* counters = nullptr;
 };
 
 d2ip_status conv_check(int n, int cin, int cout, int taps, int precision) {
@@ -105,9 +104,6 @@ void conv_plan(ConvOp& c, int n, int cin, int cout, int taps, int precision, Pie
     c.wbf16 = w.take<uint16_t>((c.prec == PREC_BF16X3 ? 2 : 1) * c.wtotal);
   const size_t kp = std::max((size_t)c.f_split * c.V * cout, (size_t)c.d_split * c.V * cin);
   c.kpart = w.take<float>(std::max<size_t>(1, kp));
-  const int tf = conv_tiles(n, c.f_tile) * ((cout + c.f_bn - 1) / c.f_bn);
-  const int td = conv_tiles(n, c.d_tile) * ((cin + c.d_bn - 1) / c.d_bn);
-  c.counters = w.take<int>((size_t)std::max(tf, td) + 64);
   const size_t cout16 = (cout + 15) / 16 * 16;
   c.part = w.take<float>((size_t)c.w_split * cout16 * taps * cin);
   c.partb = w.take<float>((size_t)c.w_split * cout16);
@@ -128,13 +124,10 @@ ConvPack make_pack(const ConvOp& c) {
   return p;
 }
 
-// Upload the packing table (and zero the split-K counters) once per call and
-// pack w into the forward and input-gradient layouts.
+// Upload the packing table once per call and pack w into the forward and
+// input-gradient layouts.
 d2ip_status conv_prepare(ConvOp& c, const float* w, hipStream_t s) {
   hipLaunchKernelGGL(k_put<ConvPack>, dim3(1), dim3(64), 0, s, c.pack, make_pack(c));
-  const int tf = conv_tiles(c.n, c.f_tile) * ((c.cout + c.f_bn - 1) / c.f_bn);
-  const int td = conv_tiles(c.n, c.d_tile) * ((c.cin + c.d_bn - 1) / c.d_bn);
-  zero_words(c.counters, (size_t)std::max(tf, td) + 64, s);
   pack_weights(c.pack, 1, c.cout * c.cin * c.taps, w, c.wf32, c.wbf16,
                c.prec == PREC_BF16X3 ? c.wtotal : 0, nullptr, nullptr, 0, 1, nullptr, 0, 1, 0, s);
   return D2IP_OK;
@@ -170,7 +163,6 @@ ConvFwd fwd_of(const ConvOp& c, bool dgrad, const float* src, const float* bias,
   a.ck = dgrad ? c.d_ck : c.f_ck;
   a.ksplit = dgrad ? c.d_split : c.f_split;
   a.kpart = c.kpart;
-  a.counters = c.counters;
   a.batch = 1;
   return a;
 }
