@@ -166,9 +166,17 @@ def merge(*tables):
     return out
 
 
+def update(base, new):
+    """`base` in its order with the entries of `new` in place of those with the
+    same key, then the entries of `new` that `base` lacks."""
+    by_key = {_key(e): e for e in new}
+    out = [by_key.pop(_key(e), e) for e in base]
+    return out + [e for e in new if _key(e) in by_key]
+
+
 def save(table, path):
     with open(path, "w") as f:
-        json.dump(table, f, indent=1)
+        json.dump(table, f, indent=0)
 
 
 def load_table(path):
@@ -197,14 +205,16 @@ WORKLOADS = ("c0", "c1", "c2", "c3", "c4")
 PRECISIONS = ("fp32", "bf16x3", "bf16")
 
 
-def tune_all(workloads=WORKLOADS, precisions=PRECISIONS, reps=10, log=None):
-    """One table for every conv pass of the named workloads and precisions."""
+def tune_all(workloads=WORKLOADS, precisions=PRECISIONS, reps=10, log=None, passes=(0, 1, 2)):
+    """One table for every conv pass (of the listed `passes`) of the named
+    workloads and precisions."""
     tables = []
     for w in workloads:
         geos, insts = workload(w)
         for prec in precisions:
             for k in sorted({tuple(i) for i in insts}):
-                tables.append(tune([geos[k[0]]], [(0, k[1], k[2])], prec, reps, log))
+                tables.append(tune([geos[k[0]]], [(0, k[1], k[2])], prec, reps, log,
+                                   passes=passes))
     return merge(*tables)
 
 
@@ -217,12 +227,20 @@ def main():
     ap.add_argument("--workload", default="all", help="c0..c4 or all")
     ap.add_argument("--precision", default="all")
     ap.add_argument("--reps", type=int, default=10)
+    ap.add_argument("--passes", default="0,1,2", help="conv passes to tune (0 forward, "
+                    "1 input gradient, 2 weight gradient)")
+    ap.add_argument("--base", default=None, help="table whose other entries are kept")
     ap.add_argument("--out", required=True)
     a = ap.parse_args()
     log = lambda m: print(m, file=sys.stderr, flush=True)
     ws = WORKLOADS if a.workload == "all" else (a.workload,)
     ps = PRECISIONS if a.precision == "all" else (a.precision,)
-    save(tune_all(ws, ps, a.reps, log), a.out)
+    passes = tuple(int(x) for x in a.passes.split(","))
+    table = tune_all(ws, ps, a.reps, log, passes)
+    if a.base:
+        with open(a.base) as f:
+            table = update(json.load(f), table)
+    save(table, a.out)
 
 
 if __name__ == "__main__":
