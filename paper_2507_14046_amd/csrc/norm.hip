@@ -126,6 +126,9 @@ __global__ __launch_bounds__(256) void k_ln_bwd(
 
 // y = relu(LN(h) + skip) for 2x2x2 groups of voxels, and the group mean of y
 // (the average-pooled input of the next encoder level) when `pooled` is set.
+// Thread t handles child t % 8 of coarse element t / 8 (a float4 of channels);
+// the eight threads of a group are adjacent lanes, and the child-0 lane adds
+// the group's values in child order.
 __global__ void k_ln_apply_pool(const float4* h, PairRef sr, const float* g, const float* b,
                                 const float4* skip, float4* y, float4* pooled, int n, int C4,
                                 long long istride) {
@@ -135,53 +138,63 @@ __global__ void k_ln_apply_pool(const float4* h, PairRef sr, const float* g, con
     skip = ishift(skip, off); y = ishift(y, off); pooled = ishift(pooled, off);
   }
   const int m = n / 2;
-  const size_t total = (size_t)m * m * m * C4;
+  const size_t total8 = (size_t)m * m * m * C4 * 8;
   const float4 z4 = make_float4(0.f, 0.f, 0.f, 0.f);
-  // element j of the 8 children of coarse element i
-  auto child = [&](size_t i, int k) {
+  const int lane = threadIdx.x & 63, k = lane & 7, g0 = lane & ~7;
+  // fine-grid element of child k of coarse element i
+  auto child = [&](size_t i) {
     const int c4 = (int)(i % C4);
     const size_t vc = i / C4;
     const int xx = (int)(vc % m), yy = (int)((vc / m) % m), zz = (int)(vc / ((size_t)m * m));
     const int fz = 2 * zz + (k >> 2), fy = 2 * yy + ((k >> 1) & 1), fx = 2 * xx + (k & 1);
     return ((size_t)(fz * n + fy) * n + fx) * C4 + c4;
   };
-  // the first element's 8 children are loaded while the statistics are reduced
-  const size_t i0 = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
-  float4 hv[8], sv[8];
-#pragma unroll
-  for (int k = 0; k < 8; ++k) {
-    hv[k] = z4;
-    sv[k] = z4;
-    if (i0 < total) {
-      hv[k] = h[child(i0, k)];
-      if (skip) sv[k] = skip[child(i0, k)];
-    }
+  // the first element is loaded while the statistics are reduced
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  const size_t t0 = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+  float4 hv = z4, sv = z4;
+  if (t0 < total8) {
+    const size_t j = child(t0 >> 3);
+    hv = h[j];
+    if (skip) sv = skip[j];
   }
   const LnStat st = stat_of(sr);
   const float mean = st.mean, rstd = st.rstd;
-  for (size_t i = i0; i < total; i += (size_t)gridDim.x * blockDim.x) {
+  // whole blocks iterate together (the group sums read other lanes)
+  for (size_t base = blockIdx.x * (size_t)blockDim.x; base < total8; base += stride) {
+    const size_t t = base + threadIdx.x;
+    const bool ok = t < total8;
+    const size_t i = t >> 3;
     const int c = 4 * (int)(i % C4);
-    float4 s = make_float4(0.f, 0.f, 0.f, 0.f);
-#pragma unroll
-    for (int k = 0; k < 8; ++k) {
-      const size_t j = child(i, k);
+    float4 o = z4;
+    if (ok) {
+      const size_t j = child(i);
       float4 v, sk;
-      if (i == i0) {
-        v = hv[k];
-        sk = sv[k];
+      if (t == t0) {
+        v = hv;
+        sk = sv;
       } else {
         v = h[j];
         sk = skip ? skip[j] : z4;
       }
-      float4 o;
       o.x = fmaxf(g[c + 0] * ((v.x - mean) * rstd) + b[c + 0] + sk.x, 0.f);
       o.y = fmaxf(g[c + 1] * ((v.y - mean) * rstd) + b[c + 1] + sk.y, 0.f);
       o.z = fmaxf(g[c + 2] * ((v.z - mean) * rstd) + b[c + 2] + sk.z, 0.f);
       o.w = fmaxf(g[c + 3] * ((v.w - mean) * rstd) + b[c + 3] + sk.w, 0.f);
       y[j] = o;
-      s.x += o.x; s.y += o.y; s.z += o.z; s.w += o.w;
     }
-    if (pooled) pooled[i] = make_float4(0.125f * s.x, 0.125f * s.y, 0.125f * s.z, 0.125f * s.w);
+    if (pooled) {
+      float4 s = z4;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        s.x += __shfl(o.x, g0 + q, 64);
+        s.y += __shfl(o.y, g0 + q, 64);
+        s.z += __shfl(o.z, g0 + q, 64);
+        s.w += __shfl(o.w, g0 + q, 64);
+      }
+      if (ok && k == 0)
+        pooled[i] = make_float4(0.125f * s.x, 0.125f * s.y, 0.125f * s.z, 0.125f * s.w);
+    }
   }
 }
 
@@ -388,7 +401,7 @@ void ln_bwd(const float* gy, int mask_mode, const float* my, const float* mg, co
 void ln_apply_pool(const float* h, PairRef st, const float* g, const float* b, const float* skip,
                    float* y, float* pooled, int n, int C, int batch, long long istride,
                    hipStream_t s) {
-  const size_t work = (size_t)(n / 2) * (n / 2) * (n / 2) * (C / 4);
+  const size_t work = (size_t)(n / 2) * (n / 2) * (n / 2) * (C / 4) * 8;  // thread per child
   hipLaunchKernelGGL(k_ln_apply_pool, dim3(grid_for(work), batch), dim3(256), 0, s,
                      reinterpret_cast<const float4*>(h), st, g, b,
                      reinterpret_cast<const float4*>(skip), reinterpret_cast<float4*>(y),
