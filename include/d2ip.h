@@ -381,8 +381,7 @@ d2ip_status d2ip_time_conv(const d2ip_tuning_entry* e, void* workspace, size_t b
  * 256-byte aligned, at least the matching *_bytes) is scratch owned by the
  * caller; one workspace must not be used by two calls in flight at once.
  * These calls read no host memory after they return: their small tables are
- * written by kernels from kernel arguments and their counters are cleared by
- * a kernel. */
+ * written by kernels from kernel arguments. */
 
 /* Workspace bytes of d2ip_op_conv3d_forward / _backward.  cin and cout
  * multiples of 8 in [8, 1024], taps 27 (3x3x3, zero padding) or 1. */
