@@ -209,6 +209,28 @@ def test_stored_tuning_table_plans_every_workload(L):
         at.set_tuning([])
 
 
+def test_tuning_table_update_keeps_order_and_format(tmp_path):
+    """`update` puts re-tuned entries in place of the stored ones with the same
+    pass key (the stored order kept), appends passes the table lacked, and
+    `save` writes the stored table's one-key-per-line format, so a partial
+    re-tune rewrites only the entries it changed."""
+    import json
+    from paper_2507_14046_amd import autotune as at
+    key = dict(n=16, cin=8, cout=8, taps=27, prologue=0, precision=0)
+    base = [dict(key, **{"pass": p}, shape=dict(tile=2, bn=16, ck=8, split=1), ms=0.01)
+            for p in (0, 1, 2)]
+    new = [dict(key, **{"pass": 1}, shape=dict(tile=1, bn=16, ck=8, split=4), ms=0.005),
+           dict(key, n=8, **{"pass": 0}, shape=dict(tile=2, bn=16, ck=8, split=1), ms=0.002)]
+    out = at.update(base, new)
+    assert [at._key(e) for e in out] == [at._key(e) for e in base] + [at._key(new[1])]
+    assert out[0] == base[0] and out[2] == base[2] and out[1] == new[0]
+    path = tmp_path / "t.json"
+    at.save(out, str(path))
+    text = path.read_text()
+    assert json.loads(text) == out
+    assert text.startswith('[\n{\n"n": 16,')
+
+
 @pytest.mark.parametrize("L_,C", [(2, 8), (3, 16), (4, 32)])
 @pytest.mark.parametrize("sep", [False, True])
 @pytest.mark.parametrize("r", [0, 4, 64])
