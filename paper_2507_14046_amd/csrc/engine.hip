@@ -1085,15 +1085,18 @@ void wgrad(const d2ip_ctx& X, const Instance& I, const Conv& c, ConvSrc xs, Conv
 }
 
 // Fork the side stream off the main stream at this point / join it back.
+// Event calls made while an iteration is enqueued report errors through the
+// hipGetLastError check after it (or through the end of a graph capture);
+// teardown calls ignore theirs.
 void fork(d2ip_ctx& X) {
   if (g_chk) return;
-  hipEventRecord(X.ev_fork, X.stream);
-  hipStreamWaitEvent(X.side, X.ev_fork, 0);
+  (void)hipEventRecord(X.ev_fork, X.stream);
+  (void)hipStreamWaitEvent(X.side, X.ev_fork, 0);
 }
 void join(d2ip_ctx& X) {
   if (g_chk) return;
-  hipEventRecord(X.ev_join, X.side);
-  hipStreamWaitEvent(X.stream, X.ev_join, 0);
+  (void)hipEventRecord(X.ev_join, X.side);
+  (void)hipStreamWaitEvent(X.stream, X.ev_join, 0);
 }
 
 void enqueue_forward(d2ip_ctx& X, Instance& I) {
@@ -1167,7 +1170,7 @@ void enqueue_iteration(d2ip_ctx& X, Instance& I) {
       // the projection's input gradient needs only gz: first on the side
       // stream, off the critical path; conv1's input gradient adds it
       L_conv_fwd(dgrad_args(X, I, b.pj, src_plain(b.gz, b.cout), b.gpj), X.side);
-      if (!g_chk) hipEventRecord(X.ev_pj, X.side);
+      if (!g_chk) (void)hipEventRecord(X.ev_pj, X.side);
     }
     wgrad(X, I, b.c2, src_ln_relu(b.h1, b.cout, b.st1, g1, b1), gh2, X.side);
     if (b.proj) wgrad(X, I, b.pj, src_plain(b.x, b.cin), src_plain(b.gz, b.cout), X.side);
@@ -1181,7 +1184,7 @@ void enqueue_iteration(d2ip_ctx& X, Instance& I) {
     {
       ConvFwd a = dgrad_args(X, I, b.c1, gh1, Lv.gx);
       a.add = b.proj ? b.gpj : b.gz;
-      if (b.proj && !g_chk) hipStreamWaitEvent(s, X.ev_pj, 0);
+      if (b.proj && !g_chk) (void)hipStreamWaitEvent(s, X.ev_pj, 0);
       L_conv_fwd(a, s);
     }
     if (!b.enc) {
@@ -1220,8 +1223,8 @@ void enqueue_all(d2ip_ctx& X, bool capturing) {
   }
   const hipStream_t s0 = X.stream, side0 = X.side;
   const hipEvent_t f0 = X.ev_fork, j0 = X.ev_join, p0 = X.ev_pj;
-  hipEventRecord(X.ev_start, s0);
-  for (d2ip_ctx::Lane& l : X.lanes) hipStreamWaitEvent(l.main, X.ev_start, 0);
+  (void)hipEventRecord(X.ev_start, s0);
+  for (d2ip_ctx::Lane& l : X.lanes) (void)hipStreamWaitEvent(l.main, X.ev_start, 0);
   for (size_t k = 0; k < X.insts.size(); ++k) {
     d2ip_ctx::Lane& l = X.lanes[k % X.lanes.size()];
     X.stream = l.main;
@@ -1237,8 +1240,8 @@ void enqueue_all(d2ip_ctx& X, bool capturing) {
   X.ev_join = j0;
   X.ev_pj = p0;
   for (d2ip_ctx::Lane& l : X.lanes) {
-    hipEventRecord(l.done, l.main);
-    hipStreamWaitEvent(s0, l.done, 0);
+    (void)hipEventRecord(l.done, l.main);
+    (void)hipStreamWaitEvent(s0, l.done, 0);
   }
 }
 
@@ -1366,21 +1369,21 @@ constexpr size_t kMaxLanes = 4;  // concurrent instance groups (hardware queues 
 
 void release_lanes(d2ip_ctx* X) {
   for (d2ip_ctx::Lane& l : X->lanes) {
-    if (l.pj) hipEventDestroy(l.pj);
-    if (l.done) hipEventDestroy(l.done);
-    if (l.join) hipEventDestroy(l.join);
-    if (l.fork) hipEventDestroy(l.fork);
-    if (l.side) hipStreamDestroy(l.side);
-    if (l.main) hipStreamDestroy(l.main);
+    if (l.pj) (void)hipEventDestroy(l.pj);
+    if (l.done) (void)hipEventDestroy(l.done);
+    if (l.join) (void)hipEventDestroy(l.join);
+    if (l.fork) (void)hipEventDestroy(l.fork);
+    if (l.side) (void)hipStreamDestroy(l.side);
+    if (l.main) (void)hipStreamDestroy(l.main);
   }
   X->lanes.clear();
-  if (X->ev_start) hipEventDestroy(X->ev_start);
+  if (X->ev_start) (void)hipEventDestroy(X->ev_start);
   X->ev_start = nullptr;
 }
 
 void drop_graph(d2ip_ctx* X) {
-  if (X->gexec) hipGraphExecDestroy(X->gexec);
-  if (X->graph) hipGraphDestroy(X->graph);
+  if (X->gexec) (void)hipGraphExecDestroy(X->gexec);
+  if (X->graph) (void)hipGraphDestroy(X->graph);
   X->gexec = nullptr;
   X->graph = nullptr;
 }
@@ -1651,8 +1654,8 @@ d2ip_status d2ip_time_conv(const d2ip_tuning_entry* e, void* workspace, size_t b
   HIPCHK(hipEventSynchronize(e1));
   float ms = 0.f;
   HIPCHK(hipEventElapsedTime(&ms, e0, e1));
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
   HIPCHK(hipGetLastError());
   *avg_ms = (double)ms / reps;
   return D2IP_OK;
@@ -1696,11 +1699,11 @@ d2ip_status d2ip_create(const d2ip_geometry_desc* geos, int n_geo, const d2ip_in
   plan(*X, geos, n_geo, insts, n_inst, cv);
   auto cleanup = [&](d2ip_status s) {
     release_lanes(X);
-    if (X->ev_pj) hipEventDestroy(X->ev_pj);
-    if (X->ev_join) hipEventDestroy(X->ev_join);
-    if (X->ev_fork) hipEventDestroy(X->ev_fork);
-    if (X->side) hipStreamDestroy(X->side);
-    if (X->cap) hipStreamDestroy(X->cap);
+    if (X->ev_pj) (void)hipEventDestroy(X->ev_pj);
+    if (X->ev_join) (void)hipEventDestroy(X->ev_join);
+    if (X->ev_fork) (void)hipEventDestroy(X->ev_fork);
+    if (X->side) (void)hipStreamDestroy(X->side);
+    if (X->cap) (void)hipStreamDestroy(X->cap);
     delete X;
     return s;
   };
@@ -1743,19 +1746,19 @@ d2ip_status d2ip_create(const d2ip_geometry_desc* geos, int n_geo, const d2ip_in
 
 d2ip_status d2ip_destroy(d2ip_ctx* X) {
   if (!X) return D2IP_OK;
-  hipStreamSynchronize(X->stream);
+  (void)hipStreamSynchronize(X->stream);
   drop_graph(X);
-  if (X->side) hipStreamSynchronize(X->side);
+  if (X->side) (void)hipStreamSynchronize(X->side);
   for (d2ip_ctx::Lane& l : X->lanes) {
-    if (l.main) hipStreamSynchronize(l.main);
-    if (l.side) hipStreamSynchronize(l.side);
+    if (l.main) (void)hipStreamSynchronize(l.main);
+    if (l.side) (void)hipStreamSynchronize(l.side);
   }
   release_lanes(X);
-  if (X->ev_pj) hipEventDestroy(X->ev_pj);
-  if (X->ev_join) hipEventDestroy(X->ev_join);
-  if (X->ev_fork) hipEventDestroy(X->ev_fork);
-  if (X->side) hipStreamDestroy(X->side);
-  if (X->cap) hipStreamDestroy(X->cap);
+  if (X->ev_pj) (void)hipEventDestroy(X->ev_pj);
+  if (X->ev_join) (void)hipEventDestroy(X->ev_join);
+  if (X->ev_fork) (void)hipEventDestroy(X->ev_fork);
+  if (X->side) (void)hipStreamDestroy(X->side);
+  if (X->cap) (void)hipStreamDestroy(X->cap);
   delete X;
   return D2IP_OK;
 }
@@ -2069,8 +2072,8 @@ d2ip_status d2ip_time_kernel(d2ip_ctx* X, int inst, int which, int block, int re
   HIPCHK(hipEventSynchronize(e1));
   float ms = 0.f;
   HIPCHK(hipEventElapsedTime(&ms, e0, e1));
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
   HIPCHK(hipGetLastError());
   *avg_ms = (double)ms / reps;
   return D2IP_OK;
