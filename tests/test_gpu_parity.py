@@ -340,6 +340,46 @@ def test_every_launch_shape_family_matches_oracle(lib, probs, case):
         at.set_tuning([])
 
 
+@pytest.mark.parametrize("case", ["n24_L3_C8", "n16_L3_C16_M928"])
+def test_largest_split_k_matches_oracle(lib, probs, case):
+    """Every forward and input-gradient pass forced to its largest split-K
+    (each split stores a partial tile; a second launch sums the splits in
+    order and runs the epilogue: bias, residual add, LayerNorm statistics),
+    the 3x3x3 ones on every voxel tile in turn, on a ragged and a full grid:
+    one-iteration gradient against the oracle, element by element."""
+    from paper_2507_14046_amd import autotune as at
+    p = probs[case]
+    geos, insts = [(p["n"], p["J"].shape[0])], [(0, p["levels"], p["base_ch"])]
+    table, splits = [], []
+    for j, e in enumerate(at.plan_convs(geos, insts)):
+        if e["pass"] == 2:
+            continue
+        cands = [c for c in at.candidates(e) if c["split"] > 1]
+        if not cands:
+            continue
+        top = max(c["split"] for c in cands)
+        cands = [c for c in cands if c["split"] == top]
+        table.append(dict(e, shape=cands[j % len(cands)]))
+        splits.append(top)
+    if not table:
+        pytest.skip("no pass here admits split-K")
+    pr = oracle_problem(p)
+    _, gref, _ = pr.loss_and_grad(p["theta0"].astype(np.float64), p["dv"][0].astype(np.float64))
+    try:
+        at.set_tuning(table)
+        lib.check_launches(geos, insts)
+        for graph in (False, True):
+            ctx = make_ctx(lib, [p], graph=graph)
+            ctx.run(1)
+            g = ctx.get_grad(0)
+            ctx.close()
+            _check_gradient(g, gref, p["levels"], p["base_ch"], "fp32", "largest_split_k",
+                            floor_fn=lambda: oracle_gradient_floor(p), p=p, case=case,
+                            graph=graph, passes=len(table), max_split=max(splits))
+    finally:
+        at.set_tuning([])
+
+
 @pytest.mark.parametrize("prec", precs(bf16=BF16_GRAD))
 @pytest.mark.parametrize("ck", [8, 16, 32])
 @pytest.mark.parametrize("case", ["n24_L3_C8", "n16_L3_C16_M928"])
